@@ -1,0 +1,634 @@
+/*
+ * qso.cpp -- FP64 CPU oracle for the QScatter beam-phase-space integration.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg.  Shares nothing with the HIP library.
+ *
+ * The steps follow the paper (Amaro & Vranic, arXiv 2308.09348) in its order:
+ *   1. samples of the beam phase space          -- Sec. 2 (volume elements)
+ *   2. the focused laser seen by each sample    -- eq. a0eff, Table 1 offsets
+ *   3. radiation-reaction evolution along phase -- eq. dpdtRR, eq. PWCRR
+ *   4. per-sample observables                   -- Sec. 5.2 divergence
+ *   5. deposit into spectra and moments         -- eq. dNda2dNdgf
+ * Readings of points the paper leaves open are stated where they are used.
+ */
+#include "qso.h"
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+/* ---- physical constants (CODATA 2018) -------------------------------- */
+const double kPi = 3.14159265358979323846;
+const double kAlpha = 7.2973525693e-3;            /* fine-structure constant */
+const double kLambdaBarC_um = 3.8615926796e-7;    /* reduced Compton wavelength */
+const double kC_um_per_fs = 0.299792458;          /* speed of light          */
+
+/* ---- Philox4x32-10 ----------------------------------------------------- */
+/* Counter-based generator of Salmon et al. (SC'11): ten rounds of two
+ * 32x32->64 multiplies with the key bumped by the Weyl constants between
+ * rounds. */
+void philox_round(uint32_t c[4], const uint32_t k[2]) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+}
+
+/* ---- problem-derived scalars ----------------------------------------- */
+struct Derived {
+    double omega0;   /* laser angular frequency [rad/fs]                    */
+    double aS;       /* normalised Schwinger vector potential m c^2/(hbar w0) */
+    double K;        /* drift constant: dgamma/dpsi = -K a^2 gamma^2 g(chi)  */
+    double CD;       /* diffusion constant: D = CD |a|^3 gamma^4 h(chi)      */
+    double zR;       /* Rayleigh length [um]                                */
+    double psi_max;  /* half-width of the integration window [rad]          */
+    double h;        /* phase step                                          */
+};
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+int validate(const qso_problem *p) {
+    if (!p) return -1;
+    const double vals[] = {p->a0, p->lambda_um, p->w0_um, p->tau_fs, p->x_off_um,
+                           p->y_off_um, p->delay_fs, p->gamma0, p->sigma_gamma,
+                           p->sigma_r_um, p->sigma_z_um, p->div_mrad, p->window_fwhm,
+                           p->kernel_sigma_bins, p->c_theta, p->e_lo, p->e_hi,
+                           p->th_lo_mrad, p->th_hi_mrad};
+    for (double v : vals) if (!std::isfinite(v)) return -1;
+    if (!(p->a0 >= 0) || !(p->lambda_um > 0) || !(p->w0_um >= 0) || !(p->tau_fs > 0)) return -1;
+    if (!(p->gamma0 > 1) || !finite_nonneg(p->sigma_gamma) || !finite_nonneg(p->sigma_r_um) ||
+        !finite_nonneg(p->sigma_z_um) || !finite_nonneg(p->div_mrad)) return -1;
+    if (!(p->window_fwhm > 0) || !(p->kernel_sigma_bins >= 0) || !(p->c_theta >= 0)) return -1;
+    if (p->n_samples < 0 || p->n_steps < 1) return -1;
+    if (p->n_e < 1 || p->n_th < 1 || p->n_a < 1) return -1;
+    if (!(p->e_hi > p->e_lo) || !(p->th_hi_mrad > p->th_lo_mrad)) return -1;
+    if (p->envelope != QSO_ENV_GAUSS && p->envelope != QSO_ENV_SIN2) return -1;
+    if (p->rr_model != QSO_RR_CLASSICAL && p->rr_model != QSO_RR_QUANTUM) return -1;
+    if (p->amp_mode != QSO_AMP_A0EFF && p->amp_mode != QSO_AMP_LOCAL) return -1;
+    if (p->deposit < QSO_DEP_POINT || p->deposit > QSO_DEP_GAUSS) return -1;
+    return 0;
+}
+
+Derived derive(const qso_problem *p) {
+    Derived d;
+    d.omega0 = 2.0 * kPi * kC_um_per_fs / p->lambda_um;
+    /* a_S = e E_S / (m c w0) = m c^2 / (hbar w0) = lambda / (2 pi lambdabar_C)  */
+    d.aS = p->lambda_um / (2.0 * kPi * kLambdaBarC_um);
+    /* eq. dpdtRR with chi = 2 gamma a / a_S, p = gamma m c and dpsi = 2 w0 dt
+     * (head-on: the phase advances at twice the laser frequency):
+     *   dgamma/dpsi = -g (2 alpha / 3) (c / (lambdabar_C w0)) chi^2 / 2
+     *               = -(4 alpha / (3 a_S)) a^2 gamma^2 g.                    */
+    d.K = 4.0 * kAlpha / (3.0 * d.aS);
+    /* Second moment of the LCFA photon spectrum in the classical limit:
+     *   d<dgamma^2>/dt = (55 / (24 sqrt3)) (alpha c / lambdabar_C) gamma chi^3,
+     * converted to phase units the same way (h(chi) -> 1 as chi -> 0).       */
+    d.CD = 55.0 / (6.0 * std::sqrt(3.0)) * kAlpha / (d.aS * d.aS);
+    d.zR = kPi * p->w0_um * p->w0_um / p->lambda_um;
+    if (p->envelope == QSO_ENV_GAUSS)
+        d.psi_max = p->window_fwhm * d.omega0 * p->tau_fs;
+    else
+        d.psi_max = d.omega0 * p->tau_fs;
+    d.h = 2.0 * d.psi_max / (double)p->n_steps;
+    return d;
+}
+
+/* Temporal envelope of the vector potential as a function of the phase
+ * psi = w0 (t - z/c) relative to the pulse peak.  GAUSS: intensity FWHM tau,
+ * i.e. the amplitude falls as exp(-2 ln2 (psi / (w0 tau))^2).  SIN2: the
+ * amplitude ramps from zero to peak over the rise time (the PIC set-ups of
+ * Appendix A use this shape). */
+double envelope(const qso_problem *p, const Derived &d, double psi) {
+    if (p->envelope == QSO_ENV_GAUSS) {
+        const double u = psi / (d.omega0 * p->tau_fs);
+        return std::exp(-2.0 * std::log(2.0) * u * u);
+    }
+    const double pr = d.omega0 * p->tau_fs;
+    if (std::fabs(psi) > pr) return 0.0;
+    const double s = std::sin(kPi * (psi + pr) / (2.0 * pr));
+    return s * s;
+}
+
+/* Linear polarisation along x with the carrier resolved (CEP 0). */
+double envelope_carrier(const qso_problem *p, const Derived &d, double psi) {
+    return envelope(p, d, psi) * std::cos(psi);
+}
+
+/* eq. a0eff: the focused Gaussian spatial factor a/a0 at (rho, z); the laser
+ * phase and wavefront curvature are neglected as in Sec. 2.  w0 = 0 selects a
+ * plane wave. */
+double spatial(const qso_problem *p, const Derived &d, double x, double y, double z) {
+    if (p->w0_um == 0.0) return 1.0;
+    const double zz = z / d.zR;
+    const double q = 1.0 + zz * zz;
+    const double r2 = (x * x + y * y) / (p->w0_um * p->w0_um);
+    return std::exp(-r2 / q) / std::sqrt(q);
+}
+
+/* ---- radiation functions g(chi), h(chi) -------------------------------- */
+/* The quantum-synchrotron (LCFA) emission rate per unit photon energy
+ * fraction xi, with y = 2 xi / (3 chi (1 - xi)), is proportional to
+ *   (1 - xi + 1/(1 - xi)) K_{2/3}(y) - Int_y^inf K_{1/3}.
+ * The Gaunt factor g (eq. dpdtRR) is its first xi-moment over the classical
+ * power, and h its second moment over the classical second moment:
+ *   g = sqrt3/(2 pi chi^2) Int_0^1 xi [..] dxi,
+ *   h = 24/(55 pi chi^3)   Int_0^1 xi^2 [..] dxi.
+ * The Int K_{1/3} term is integrated by parts in xi (d/dy of it is -K_{1/3},
+ * the boundary terms vanish), and xi is traded for y, which gives
+ *   Int_0^1 xi^n [..] dxi = Int_0^inf [xi^n w xi_y K_{2/3}(y)
+ *                                       - xi^{n+1}/(n+1) K_{1/3}(y)] dy
+ * with xi = 3 chi y / (2 + 3 chi y), xi_y = dxi/dy, w = 1 - xi + 1/(1 - xi).
+ * The y integral uses the exp-sinh rule y = exp(pi/2 sinh t). */
+void gh_integrals(double chi, double step, double *Ig, double *Ih) {
+    double sg = 0.0, sh = 0.0;
+    const double t_lo = std::asinh(2.0 / kPi * std::log(1e-22));
+    const double t_hi = std::asinh(2.0 / kPi * std::log(70.0));
+    const long k_lo = (long)std::floor(t_lo / step), k_hi = (long)std::ceil(t_hi / step);
+    for (long k = k_lo; k <= k_hi; ++k) {
+        const double t = k * step;
+        const double y = std::exp(0.5 * kPi * std::sinh(t));
+        const double dydt = y * 0.5 * kPi * std::cosh(t);
+        const double q = 2.0 + 3.0 * chi * y;
+        const double xi = 3.0 * chi * y / q;
+        const double one_m_xi = 2.0 / q;
+        const double w = one_m_xi + q / 2.0;
+        const double xi_y = 6.0 * chi / (q * q);
+        const double k23 = std::cyl_bessel_k(2.0 / 3.0, y);
+        const double k13 = std::cyl_bessel_k(1.0 / 3.0, y);
+        sg += (xi * w * xi_y * k23 - 0.5 * xi * xi * k13) * dydt;
+        sh += (xi * xi * w * xi_y * k23 - xi * xi * xi / 3.0 * k13) * dydt;
+    }
+    *Ig = sg * step;
+    *Ih = sh * step;
+}
+
+const double kQuadStep = 1.0 / 48.0;
+
+void gh_exact(double chi, double *g, double *h) {
+    double Ig, Ih;
+    gh_integrals(chi, kQuadStep, &Ig, &Ih);
+    *g = std::sqrt(3.0) / (2.0 * kPi * chi * chi) * Ig;
+    *h = 24.0 / (55.0 * kPi * chi * chi * chi) * Ih;
+}
+
+/* Table in u = ln chi.  Derivatives from sixth-order central differences of
+ * the quadrature values: G1 = chi g' = dg/du, G2 = chi^2 g'' = d2g/du2 - dg/du.
+ * Below chi_min the small-chi expansions hold (g: the Sokolov-Ternov series;
+ * h: its first-order term from the same Mellin moments that fix h(0) = 1). */
+struct RadTable {
+    double u0, du;
+    int n;  /* node count including padding */
+    std::vector<double> g, G1, G2, h;
+};
+
+const double kChiMin = 1e-6, kChiMax = 1e3;
+const int kPad = 6;
+const double kG1 = -55.0 * 1.7320508075688772 / 16.0;   /* -55 sqrt3 / 16  */
+const double kG2 = 48.0;
+const double kH1 = -1344.0 / (55.0 * 1.7320508075688772); /* -1344/(55 sqrt3) */
+
+RadTable *g_table = nullptr;
+std::once_flag g_table_once;
+
+void build_table() {
+    RadTable *t = new RadTable;
+    t->du = 1.0 / 256.0;
+    const double u_min = std::log(kChiMin), u_max = std::log(kChiMax);
+    const int core = (int)std::ceil((u_max - u_min) / t->du) + 1;
+    t->n = core + 2 * kPad;
+    t->u0 = u_min - kPad * t->du;
+    std::vector<double> gv(t->n), hv(t->n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < t->n; ++k) {
+        const double chi = std::exp(t->u0 + k * t->du);
+        gh_exact(chi, &gv[k], &hv[k]);
+    }
+    t->g = gv; t->h = hv;
+    t->G1.assign(t->n, 0.0);
+    t->G2.assign(t->n, 0.0);
+    for (int k = 3; k < t->n - 3; ++k) {
+        const double *f = &gv[k];
+        const double d1 = (-f[-3] + 9 * f[-2] - 45 * f[-1] + 45 * f[1] - 9 * f[2] + f[3]) /
+                          (60.0 * t->du);
+        const double d2 = (2 * f[-3] - 27 * f[-2] + 270 * f[-1] - 490 * f[0] + 270 * f[1] -
+                           27 * f[2] + 2 * f[3]) / (180.0 * t->du * t->du);
+        t->G1[k] = d1;
+        t->G2[k] = d2 - d1;
+    }
+    g_table = t;
+}
+
+const RadTable &table() {
+    std::call_once(g_table_once, build_table);
+    return *g_table;
+}
+
+/* g, chi g', chi^2 g'', h at chi >= 0 (4-point Lagrange in u). */
+void radiation(double chi, double out[4]) {
+    if (chi < kChiMin) {
+        out[0] = 1.0 + kG1 * chi + kG2 * chi * chi;
+        out[1] = kG1 * chi + 2.0 * kG2 * chi * chi;
+        out[2] = 2.0 * kG2 * chi * chi;
+        out[3] = 1.0 + kH1 * chi;
+        return;
+    }
+    if (!(chi <= kChiMax)) {
+        out[0] = out[1] = out[2] = out[3] = NAN;
+        return;
+    }
+    const RadTable &t = table();
+    const double s = (std::log(chi) - t.u0) / t.du;
+    const int i = (int)std::floor(s);
+    const double x = s - i;
+    const double w[4] = {-x * (x - 1) * (x - 2) / 6.0, (x + 1) * (x - 1) * (x - 2) / 2.0,
+                         -(x + 1) * x * (x - 2) / 2.0, (x + 1) * x * (x - 1) / 6.0};
+    const std::vector<double> *cols[4] = {&t.g, &t.G1, &t.G2, &t.h};
+    for (int c = 0; c < 4; ++c) {
+        double acc = 0.0;
+        for (int m = 0; m < 4; ++m) acc += w[m] * (*cols[c])[i - 1 + m];
+        out[c] = acc;
+    }
+}
+
+/* ---- the moment system ------------------------------------------------- */
+/* Drift A(mu) from eq. dpdtRR in phase units; the mean and variance of the
+ * energy distribution of a beamlet obey, at second order about the mean
+ * (Fokker-Planck regime of Sec. 1):
+ *   dmu/dpsi   = A(mu) + A''(mu) sig2 / 2,
+ *   dsig2/dpsi = 2 A'(mu) sig2 + D(mu),
+ * with chi = 2 mu |a| / a_S.  The classical model is g = 1, D = 0.          */
+struct Rhs { double A, A1, A2, D, dmu, dsig2; };
+
+Rhs rhs(const qso_problem *p, const Derived &d, double mu, double sig2, double a) {
+    double g = 1.0, G1 = 0.0, G2 = 0.0, hq = 0.0;
+    const double abs_a = std::fabs(a);
+    if (p->rr_model == QSO_RR_QUANTUM) {
+        double rf[4];
+        radiation(2.0 * mu * abs_a / d.aS, rf);
+        g = rf[0]; G1 = rf[1]; G2 = rf[2]; hq = rf[3];
+    }
+    Rhs r;
+    const double a2 = a * a;
+    r.A = -d.K * a2 * mu * mu * g;
+    r.A1 = -d.K * a2 * mu * (2.0 * g + G1);
+    r.A2 = -d.K * a2 * (2.0 * g + 4.0 * G1 + G2);
+    r.D = (p->rr_model == QSO_RR_QUANTUM) ? d.CD * a2 * abs_a * mu * mu * mu * mu * hq : 0.0;
+    r.dmu = r.A + 0.5 * r.A2 * sig2;
+    r.dsig2 = 2.0 * r.A1 * sig2 + r.D;
+    return r;
+}
+
+/* ---- one sample -------------------------------------------------------- */
+struct SampleIn {
+    double x, y, z, gamma0, thx, thy;  /* um, um, um, -, rad, rad */
+};
+
+void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
+    /* counter (i, shot, k, 0), key = seed; 24-bit uniforms in (0, 1) */
+    uint32_t r[8];
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t k = 0; k < 2; ++k) {
+        const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)shot, k, 0u};
+        qso_philox4x32_10(ctr, key, &r[4 * k]);
+    }
+    double u[6];
+    for (int m = 0; m < 6; ++m) u[m] = ((double)(r[m] >> 8) + 0.5) * (1.0 / 16777216.0);
+    /* Box-Muller on consecutive pairs */
+    for (int m = 0; m < 3; ++m) {
+        const double R = std::sqrt(-2.0 * std::log(u[2 * m]));
+        n[2 * m] = R * std::cos(2.0 * kPi * u[2 * m + 1]);
+        n[2 * m + 1] = R * std::sin(2.0 * kPi * u[2 * m + 1]);
+    }
+}
+
+SampleIn make_sample(const qso_problem *p, int64_t i) {
+    double n[6];
+    normals(p->seed, p->shot, i, n);
+    SampleIn s;
+    s.x = p->x_off_um + p->sigma_r_um * n[0];
+    s.y = p->y_off_um + p->sigma_r_um * n[1];
+    s.z = p->sigma_z_um * n[2];
+    s.gamma0 = p->gamma0 + p->sigma_gamma * n[3];
+    s.thx = 1e-3 * p->div_mrad * n[4];
+    s.thy = 1e-3 * p->div_mrad * n[5];
+    return s;
+}
+
+/* Ballistic geometry (Sec. 6: probe particles on ballistic trajectories).
+ * The laser moves along +z with its peak at z = c t and focus at z = 0; the
+ * beam moves along -z and its centroid meets the peak at t = delay/2, at
+ * z = c delay / 2.  Sample coordinates (x, y) are taken at that instant.
+ * A sample at longitudinal offset z meets the peak at z* = (z + c delay)/2;
+ * at phase psi it has travelled l = c psi / (2 w0) = psi lambda / (4 pi)
+ * past that point.                                                         */
+struct Geometry {
+    double zstar;  /* collision point on the axis [um]                       */
+    double S0;     /* spatial factor at the collision point                   */
+};
+
+Geometry geometry(const qso_problem *p, const Derived &d, const SampleIn &s) {
+    Geometry gmt;
+    gmt.zstar = 0.5 * (s.z + kC_um_per_fs * p->delay_fs);
+    const double xc = s.x + s.thx * 0.5 * s.z;
+    const double yc = s.y + s.thy * 0.5 * s.z;
+    gmt.S0 = spatial(p, d, xc, yc, gmt.zstar);
+    return gmt;
+}
+
+double amplitude(const qso_problem *p, const Derived &d, const SampleIn &s,
+                 const Geometry &gmt, double psi) {
+    double S;
+    if (p->amp_mode == QSO_AMP_A0EFF) {
+        /* Sec. 2: the sample is assigned the peak amplitude it meets, a0,eff */
+        S = gmt.S0;
+    } else {
+        const double l = psi * p->lambda_um / (4.0 * kPi);
+        S = spatial(p, d, s.x + s.thx * (0.5 * s.z + l), s.y + s.thy * (0.5 * s.z + l),
+                    gmt.zstar - l);
+    }
+    return p->a0 * S * envelope_carrier(p, d, psi);
+}
+
+struct SampleOut {
+    double mu, sig2, thx, thy, sigth, aeff_ratio, chimax, gamma0, x, y, z;
+};
+
+SampleOut run_sample(const qso_problem *p, const Derived &d, int64_t i) {
+    const SampleIn s = make_sample(p, i);
+    const Geometry gmt = geometry(p, d, s);
+    double mu = s.gamma0, sig2 = 0.0, chimax = 0.0;
+    const double h = d.h;
+    for (int j = 0; j < p->n_steps; ++j) {
+        /* classical fourth-order Runge-Kutta in psi on (mu, sig2) */
+        const double psi = -d.psi_max + j * h;
+        const double a1 = amplitude(p, d, s, gmt, psi);
+        const double ah = amplitude(p, d, s, gmt, psi + 0.5 * h);
+        const double a4 = amplitude(p, d, s, gmt, psi + h);
+        chimax = std::fmax(chimax, 2.0 * mu * std::fabs(a1) / d.aS);
+        const Rhs k1 = rhs(p, d, mu, sig2, a1);
+        const Rhs k2 = rhs(p, d, mu + 0.5 * h * k1.dmu, sig2 + 0.5 * h * k1.dsig2, ah);
+        const Rhs k3 = rhs(p, d, mu + 0.5 * h * k2.dmu, sig2 + 0.5 * h * k2.dsig2, ah);
+        const Rhs k4 = rhs(p, d, mu + h * k3.dmu, sig2 + h * k3.dsig2, a4);
+        mu += h / 6.0 * (k1.dmu + 2.0 * k2.dmu + 2.0 * k3.dmu + k4.dmu);
+        sig2 += h / 6.0 * (k1.dsig2 + 2.0 * k2.dsig2 + 2.0 * k3.dsig2 + k4.dsig2);
+    }
+    {
+        const double aN = amplitude(p, d, s, gmt, d.psi_max);
+        chimax = std::fmax(chimax, 2.0 * mu * std::fabs(aN) / d.aS);
+    }
+    SampleOut o;
+    o.mu = mu;
+    o.sig2 = sig2;
+    /* The photon recoil of an ultra-relativistic emitter is along its
+     * momentum (emission within 1/gamma of it, Sec. 5.1), so the direction
+     * is kept; the stochastic broadening of Sec. 5.2 is applied in the
+     * polarisation plane x: sigma_theta = c_theta sqrt(2/pi) a0eff sigma_f /
+     * gamma_f^2.                                                           */
+    o.thx = 1e3 * s.thx;
+    o.thy = 1e3 * s.thy;
+    const double sigf = std::sqrt(std::fmax(sig2, 0.0));
+    const double aeff = p->a0 * gmt.S0;
+    o.sigth = 1e3 * p->c_theta * std::sqrt(2.0 / kPi) * aeff * sigf / (mu * mu);
+    o.aeff_ratio = gmt.S0;
+    o.chimax = chimax;
+    o.gamma0 = s.gamma0;
+    o.x = s.x; o.y = s.y; o.z = s.z;
+    return o;
+}
+
+/* ---- deposit ------------------------------------------------------------ */
+double Phi(double t) { return 0.5 * std::erfc(-t / std::sqrt(2.0)); }
+double PhiC(double t) { return 0.5 * std::erfc(t / std::sqrt(2.0)); }
+double phi(double t) { return std::exp(-0.5 * t * t) / std::sqrt(2.0 * kPi); }
+
+/* The law deposited by one sample is its own energy (or angle) law -- a point
+ * at v when s = 0, else N(v, s^2) -- convolved with the deposit kernel
+ * (POINT: none, CIC: a box one bin wide, GAUSS: N(0, (k bins)^2)); each bin
+ * gets that law's mass over it, so a sample always adds exactly one unit.
+ * cdf(x) returns P(X <= x), ccdf(x) returns P(X > x).                       */
+struct Law {
+    int mode;  /* 0 step, 1 box, 2 gauss, 3 box (x) gauss */
+    double v, s, half;
+};
+
+Law make_law(double v, double s, int32_t deposit, double ksig_bins, double width) {
+    Law L;
+    L.v = v;
+    L.half = 0.5 * width;
+    if (deposit == QSO_DEP_GAUSS) {
+        const double ks = ksig_bins * width;
+        L.s = std::sqrt(s * s + ks * ks);
+        L.mode = L.s > 0 ? 2 : 0;
+    } else if (deposit == QSO_DEP_CIC) {
+        L.s = s;
+        L.mode = s > 0 ? 3 : 1;
+    } else {
+        L.s = s;
+        L.mode = s > 0 ? 2 : 0;
+    }
+    return L;
+}
+
+/* Psi(t) = Int_-inf^t Phi(u/s) du = t Phi(t/s) + s phi(t/s);
+ * PsiC(t) = Psi(t) - t = -t PhiC(t/s) + s phi(t/s).                        */
+double Psi(double t, double s) { return t * Phi(t / s) + s * phi(t / s); }
+double PsiC(double t, double s) { return -t * PhiC(t / s) + s * phi(t / s); }
+
+double law_cdf(const Law &L, double x) {
+    const double t = x - L.v;
+    switch (L.mode) {
+        case 0: return t > 0 ? 1.0 : 0.0;  /* NGP: floor((v - lo) / width) */
+        case 1: return std::fmin(1.0, std::fmax(0.0, t / (2 * L.half) + 0.5));
+        case 2: return Phi(t / L.s);
+        default: return (Psi(t + L.half, L.s) - Psi(t - L.half, L.s)) / (2 * L.half);
+    }
+}
+
+double law_ccdf(const Law &L, double x) {
+    const double t = x - L.v;
+    switch (L.mode) {
+        case 0: return t > 0 ? 0.0 : 1.0;
+        case 1: return std::fmin(1.0, std::fmax(0.0, 0.5 - t / (2 * L.half)));
+        case 2: return PhiC(t / L.s);
+        default: return (PsiC(t - L.half, L.s) - PsiC(t + L.half, L.s)) / (2 * L.half);
+    }
+}
+
+void deposit(double v, double s, int32_t dep, double ksig, double lo, double hi, int32_t n,
+             double *hist) {
+    const double width = (hi - lo) / n;
+    const Law L = make_law(v, s, dep, ksig, width);
+    hist[n] += law_cdf(L, lo);
+    hist[n + 1] += law_ccdf(L, hi);
+    for (int k = 0; k < n; ++k) {
+        const double e0 = lo + k * width, e1 = lo + (k + 1) * width;
+        /* difference of whichever tail is smaller, for relative accuracy */
+        const double m = (0.5 * (e0 + e1) <= v) ? law_cdf(L, e1) - law_cdf(L, e0)
+                                                : law_ccdf(L, e0) - law_ccdf(L, e1);
+        hist[k] += m;
+    }
+}
+
+/* Neumaier-compensated running sum. */
+struct KSum {
+    double s = 0.0, c = 0.0;
+    void add(double x) {
+        const double t = s + x;
+        if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+        s = t;
+    }
+    double value() const { return s + c; }
+};
+
+}  // namespace
+
+/* ======================================================================== */
+extern "C" {
+
+void qso_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k[0] += 0x9E3779B9u; k[1] += 0xBB67AE85u; }
+        philox_round(c, k);
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+void qso_normals(uint64_t seed, int32_t shot, int64_t i, double out[6]) {
+    normals(seed, shot, i, out);
+}
+
+void qso_gh_quadrature(double chi, double *g, double *h) { gh_exact(chi, g, h); }
+
+void qso_radiation(double chi, double out[4]) { radiation(chi, out); }
+
+int qso_derived(const qso_problem *p, double out[7]) {
+    if (validate(p)) return -1;
+    const Derived d = derive(p);
+    out[0] = d.omega0; out[1] = d.aS; out[2] = d.K; out[3] = d.CD;
+    out[4] = d.zR; out[5] = d.psi_max; out[6] = d.h;
+    return 0;
+}
+
+double qso_envelope_carrier(const qso_problem *p, double psi) {
+    const Derived d = derive(p);
+    return envelope_carrier(p, d, psi);
+}
+
+int qso_rhs(const qso_problem *p, double mu, double sig2, double a, double out[6]) {
+    if (validate(p)) return -1;
+    const Derived d = derive(p);
+    const Rhs r = rhs(p, d, mu, sig2, a);
+    out[0] = r.A; out[1] = r.A1; out[2] = r.A2; out[3] = r.D; out[4] = r.dmu; out[5] = r.dsig2;
+    return 0;
+}
+
+int qso_sample(const qso_problem *p, int64_t i, double *rec) {
+    if (validate(p)) return -1;
+    const Derived d = derive(p);
+    const SampleOut o = run_sample(p, d, i);
+    rec[QSO_S_MU] = o.mu; rec[QSO_S_SIG2] = o.sig2; rec[QSO_S_THX] = o.thx;
+    rec[QSO_S_THY] = o.thy; rec[QSO_S_SIGTH] = o.sigth; rec[QSO_S_AEFF] = p->a0 * o.aeff_ratio;
+    rec[QSO_S_CHIMAX] = o.chimax; rec[QSO_S_GAMMA0] = o.gamma0;
+    rec[QSO_S_X] = o.x; rec[QSO_S_Y] = o.y; rec[QSO_S_Z] = o.z;
+    return std::isfinite(o.mu) && std::isfinite(o.sig2) ? 0 : -2;
+}
+
+int qso_deposit(double v, double s, int32_t dep, double ksig, double lo, double hi, int32_t n,
+                double *hist) {
+    if (!(hi > lo) || n < 1 || !std::isfinite(v) || !(s >= 0)) return -1;
+    deposit(v, s, dep, ksig, lo, hi, n, hist);
+    return 0;
+}
+
+int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+                double *energy_hist, double *angle_hist, double *a0eff_hist, double *moments) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int ne = p->n_e, nt = p->n_th, na = p->n_a;
+    const int64_t total = i_end - i_begin;
+    enum { S1E, S2E, S1X, S2X, S1Y, S2Y, SAEFF, SRAD, SSIGF, NSUM };
+    std::vector<std::vector<double>> he(nthreads, std::vector<double>(ne + 2, 0.0));
+    std::vector<std::vector<double>> ht(nthreads, std::vector<double>(nt + 2, 0.0));
+    std::vector<std::vector<double>> ha(nthreads, std::vector<double>(na, 0.0));
+    std::vector<std::vector<KSum>> sums(nthreads, std::vector<KSum>(NSUM));
+    std::vector<double> chimax(nthreads, 0.0);
+    std::vector<int> bad(nthreads, 0);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        /* fixed contiguous range per thread, merged in thread order below */
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        for (int64_t i = b; i < e; ++i) {
+            const SampleOut o = run_sample(p, d, i);
+            if (!std::isfinite(o.mu) || !std::isfinite(o.sig2)) { bad[t] = 1; continue; }
+            const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
+            deposit(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+                    he[t].data());
+            deposit(o.thx, o.sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
+                    p->th_hi_mrad, nt, ht[t].data());
+            /* a0,eff histogram: NGP over a0,eff / a0 in [0, 1], top edge closed */
+            int ka = (int)std::floor(o.aeff_ratio * na);
+            if (ka > na - 1) ka = na - 1;
+            if (ka < 0) ka = 0;
+            ha[t][ka] += 1.0;
+            const double de = o.mu - p->gamma0;
+            sums[t][S1E].add(de);
+            sums[t][S2E].add(de * de + std::fmax(o.sig2, 0.0));
+            sums[t][S1X].add(o.thx);
+            sums[t][S2X].add(o.thx * o.thx + o.sigth * o.sigth);
+            sums[t][S1Y].add(o.thy);
+            sums[t][S2Y].add(o.thy * o.thy);
+            sums[t][SAEFF].add(p->a0 * o.aeff_ratio);
+            sums[t][SRAD].add(1.0 - o.mu / o.gamma0);
+            sums[t][SSIGF].add(sigf);
+            chimax[t] = std::fmax(chimax[t], o.chimax);
+        }
+    }
+    for (int t = 1; t < nthreads; ++t) {
+        for (int k = 0; k < ne + 2; ++k) he[0][k] += he[t][k];
+        for (int k = 0; k < nt + 2; ++k) ht[0][k] += ht[t][k];
+        for (int k = 0; k < na; ++k) ha[0][k] += ha[t][k];
+        for (int m = 0; m < NSUM; ++m) {
+            sums[0][m].add(sums[t][m].s);
+            sums[0][m].add(sums[t][m].c);
+        }
+        chimax[0] = std::fmax(chimax[0], chimax[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) if (bad[t]) return -2;
+    if (energy_hist) std::memcpy(energy_hist, he[0].data(), sizeof(double) * (ne + 2));
+    if (angle_hist) std::memcpy(angle_hist, ht[0].data(), sizeof(double) * (nt + 2));
+    if (a0eff_hist) std::memcpy(a0eff_hist, ha[0].data(), sizeof(double) * na);
+    if (moments) {
+        for (int m = 0; m < QSO_M_N; ++m) moments[m] = 0.0;
+        const double W = (double)total;
+        moments[QSO_M_WEIGHT] = W;
+        if (total > 0) {
+            const double m1 = sums[0][S1E].value() / W;
+            moments[QSO_M_MEAN_G] = p->gamma0 + m1;
+            moments[QSO_M_STD_G] = std::sqrt(std::fmax(sums[0][S2E].value() / W - m1 * m1, 0.0));
+            moments[QSO_M_MEAN_THX] = sums[0][S1X].value() / W;
+            moments[QSO_M_RMS_THX] = std::sqrt(sums[0][S2X].value() / W);
+            moments[QSO_M_MEAN_THY] = sums[0][S1Y].value() / W;
+            moments[QSO_M_RMS_THY] = std::sqrt(sums[0][S2Y].value() / W);
+            moments[QSO_M_MEAN_AEFF] = sums[0][SAEFF].value() / W;
+            moments[QSO_M_MAX_CHI] = chimax[0];
+            moments[QSO_M_RAD_FRAC] = sums[0][SRAD].value() / W;
+            moments[QSO_M_MEAN_SIGF] = sums[0][SSIGF].value() / W;
+        }
+    }
+    return 0;
+}
+
+}  // extern "C"

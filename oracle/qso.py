@@ -1,0 +1,194 @@
+"""ctypes loader for the FP64 CPU oracle.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  The oracle takes
+the same plain parameter dictionary as the product binding (see
+``paper_2308_09348_amd.workloads``) but converts it into its own struct.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqso.so")
+
+ENVELOPE = {"gauss": 0, "sin2": 1}
+RR_MODEL = {"classical": 0, "quantum": 1}
+AMP_MODE = {"a0eff": 0, "local": 1}
+DEPOSIT = {"point": 0, "cic": 1, "gauss": 2}
+
+# per-sample record layout (qso.h)
+S_MU, S_SIG2, S_THX, S_THY, S_SIGTH, S_AEFF, S_CHIMAX, S_GAMMA0, S_X, S_Y, S_Z, S_N = range(12)
+# moments layout
+M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, \
+    M_MEAN_AEFF, M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF = range(11)
+M_N = 16
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("a0", ctypes.c_double), ("lambda_um", ctypes.c_double), ("w0_um", ctypes.c_double),
+        ("tau_fs", ctypes.c_double), ("x_off_um", ctypes.c_double),
+        ("y_off_um", ctypes.c_double), ("delay_fs", ctypes.c_double),
+        ("gamma0", ctypes.c_double), ("sigma_gamma", ctypes.c_double),
+        ("sigma_r_um", ctypes.c_double), ("sigma_z_um", ctypes.c_double),
+        ("div_mrad", ctypes.c_double), ("window_fwhm", ctypes.c_double),
+        ("kernel_sigma_bins", ctypes.c_double), ("c_theta", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("n_samples", ctypes.c_int64),
+        ("n_steps", ctypes.c_int32), ("shot", ctypes.c_int32),
+        ("envelope", ctypes.c_int32), ("rr_model", ctypes.c_int32),
+        ("amp_mode", ctypes.c_int32), ("deposit", ctypes.c_int32),
+        ("n_e", ctypes.c_int32), ("n_th", ctypes.c_int32), ("n_a", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("e_lo", ctypes.c_double), ("e_hi", ctypes.c_double),
+        ("th_lo_mrad", ctypes.c_double), ("th_hi_mrad", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build as _b  # noqa: F401  (local build script)
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(Problem)
+        L.qso_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.qso_philox4x32_10.restype = None
+        L.qso_normals.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, dp]
+        L.qso_normals.restype = None
+        L.qso_gh_quadrature.argtypes = [ctypes.c_double, dp, dp]
+        L.qso_gh_quadrature.restype = None
+        L.qso_radiation.argtypes = [ctypes.c_double, dp]
+        L.qso_radiation.restype = None
+        L.qso_rhs.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.qso_rhs.restype = ctypes.c_int
+        L.qso_envelope_carrier.argtypes = [pp, ctypes.c_double]
+        L.qso_envelope_carrier.restype = ctypes.c_double
+        L.qso_derived.argtypes = [pp, dp]
+        L.qso_derived.restype = ctypes.c_int
+        L.qso_sample.argtypes = [pp, ctypes.c_int64, dp]
+        L.qso_sample.restype = ctypes.c_int
+        L.qso_forward.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                  dp, dp, dp, dp]
+        L.qso_forward.restype = ctypes.c_int
+        L.qso_deposit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int32, dp]
+        L.qso_deposit.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def problem(params):
+    """Convert a plain parameter dictionary into the oracle's struct."""
+    p = Problem()
+    for name, _ in Problem._fields_:
+        if name == "pad_":
+            continue
+        v = params[name]
+        if name == "envelope":
+            v = ENVELOPE[v] if isinstance(v, str) else v
+        elif name == "rr_model":
+            v = RR_MODEL[v] if isinstance(v, str) else v
+        elif name == "amp_mode":
+            v = AMP_MODE[v] if isinstance(v, str) else v
+        elif name == "deposit":
+            v = DEPOSIT[v] if isinstance(v, str) else v
+        setattr(p, name, v)
+    return p
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().qso_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def normals(seed, shot, i):
+    out = np.zeros(6)
+    lib().qso_normals(seed, shot, i, _dp(out))
+    return out
+
+
+def gh_quadrature(chi):
+    g, h = ctypes.c_double(), ctypes.c_double()
+    lib().qso_gh_quadrature(chi, ctypes.byref(g), ctypes.byref(h))
+    return g.value, h.value
+
+
+def radiation(chi):
+    out = np.zeros(4)
+    lib().qso_radiation(chi, _dp(out))
+    return out
+
+
+def rhs(params, mu, sig2, a):
+    out = np.zeros(6)
+    p = problem(params)
+    if lib().qso_rhs(ctypes.byref(p), mu, sig2, a, _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return out
+
+
+def envelope_carrier(params, psi):
+    p = problem(params)
+    return lib().qso_envelope_carrier(ctypes.byref(p), psi)
+
+
+def derived(params):
+    out = np.zeros(7)
+    p = problem(params)
+    if lib().qso_derived(ctypes.byref(p), _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return dict(zip(["omega0", "aS", "K", "CD", "zR", "psi_max", "h"], out))
+
+
+def sample(params, i):
+    rec = np.zeros(S_N)
+    p = problem(params)
+    rc = lib().qso_sample(ctypes.byref(p), i, _dp(rec))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    return rec
+
+
+def samples(params, indices):
+    return np.stack([sample(params, int(i)) for i in indices])
+
+
+def forward(params, i_begin=0, i_end=None, nthreads=0):
+    """Histograms (raw weights) and moments over samples [i_begin, i_end)."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    p = problem(params)
+    he = np.zeros(params["n_e"] + 2)
+    ht = np.zeros(params["n_th"] + 2)
+    ha = np.zeros(params["n_a"])
+    mo = np.zeros(M_N)
+    rc = lib().qso_forward(ctypes.byref(p), i_begin, i_end, nthreads,
+                           _dp(he), _dp(ht), _dp(ha), _dp(mo))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return {"energy_hist": he, "angle_hist": ht, "a0eff_hist": ha, "moments": mo}
+
+
+def deposit(v, s, dep, ksig, lo, hi, n):
+    hist = np.zeros(n + 2)
+    d = DEPOSIT[dep] if isinstance(dep, str) else dep
+    if lib().qso_deposit(v, s, d, ksig, lo, hi, n, _dp(hist)) != 0:
+        raise ValueError("invalid deposit")
+    return hist
