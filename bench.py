@@ -1,0 +1,138 @@
+"""Throughput of the beam-phase-space integration on one MI355X.
+
+One step = one full forward pass (sample generation, phase integration,
+deposit, reductions, normalisation) of the focused single-shot workload:
+a0 = 50, W0 = 3 um, 30 fs, beam 3 um x 5 um, gamma0 = 2000 +- 5 %, 1 mrad,
+2^22 samples x 1024 phase steps, quantum-corrected moments, local amplitude.
+
+Prints one JSON line.  The roofline block describes the phase-integration
+kernel (the dominant one): algorithmic FLOPs per launch over its average
+duration, timed with HIP events on the stream it runs on.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sample·phase-steps/s (fwd, fwd+adjoint), batched spectra/s; % FP32 VALU peak"
+UNIT = "sample·phase-steps/s"
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+# Algorithmic floating-point operations per sample-step of the phase loop
+# (FMA = 2, each exp / sqrt / reciprocal = 1), counted from the method's
+# arithmetic: RK4 over (mu, sig2), four evaluations of the moment right-hand
+# side, the spatial factor at the two new stage phases.  The breakdown is in
+# the design notes.
+ALG_FLOPS = {("quantum", "local"): 270, ("quantum", "a0eff"): 229,
+             ("classical", "local"): 79, ("classical", "a0eff"): 31}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--chi-fp64", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(params, target_s):
+    """The FP64 oracle on a bounded prefix of the same workload, all host
+    cores; sample-steps per second."""
+    from oracle import build as obuild, qso
+    if not os.path.exists(qso.LIB_PATH):
+        obuild.build()
+    threads = min(os.cpu_count() or 1, 64)
+    qso.forward(dict(params, n_samples=threads), 0, threads, threads)  # builds the g/h table
+    n = 4 * threads
+    while True:  # grow the prefix until it takes a tenth of the target
+        t0 = time.perf_counter()
+        qso.forward(dict(params, n_samples=n), 0, n, threads)
+        dt = time.perf_counter() - t0
+        if dt > 0.1 * target_s or n >= params["n_samples"]:
+            break
+        n = min(n * 4, params["n_samples"])
+    n = int(max(n, min(params["n_samples"], n * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    qso.forward(dict(params, n_samples=n), 0, n, threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * params["n_steps"] / dt, "unit": UNIT, "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} of {params['n_samples']} samples x {params['n_steps']} steps "
+                      f"({dt:.1f} s wall, FP64, {threads} threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2308_09348_amd as qs
+    from paper_2308_09348_amd import workloads
+
+    params = dict(workloads.focused_3d(), precision=args.precision, chi_fp64=args.chi_fp64)
+    n, N = params["n_samples"], params["n_steps"]
+    ctx = qs.Context(0)
+    dev = torch.device("cuda", 0)
+    out = ctx.forward(params)  # allocates the outputs and the context scratch
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        ctx.forward(params, out=out, check=False)
+    torch.cuda.synchronize()
+
+    # timed region: K whole forward passes, inputs resident, outputs reused
+    ctx.set_profiling(True)
+    phase_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.forward(params, out=out, stream=stream, check=False)
+        phase_ms.append(ctx.last_timings()["phase"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    st = int(out["status"].item())
+    if st != 0:
+        raise RuntimeError(f"device status {st}")
+
+    ms_per_step = 1e3 * wall / args.steps
+    value = n * N / (wall / args.steps)
+    phase_avg_ms = sum(phase_ms) / len(phase_ms)
+    flops_launch = ALG_FLOPS[(params["rr_model"], params["amp_mode"])] * n * N
+    achieved = flops_launch / (phase_avg_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "focused single shot: a0=50, W0=3um, 30fs, x_off=2um, delay=10fs, "
+                               "sigma_r=3um, sigma_z=5um, gamma0=2000+-5%, 1mrad; 2^22 samples x "
+                               "1024 steps, quantum moments, local amplitude, CIC deposit",
+                   "n_samples": n, "n_steps": N, "rr_model": params["rr_model"],
+                   "amp_mode": params["amp_mode"], "precision": args.precision,
+                   "chi_fp64": args.chi_fp64, "leg": "fwd"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "phase_kernel",
+                     "kernel_avg_ms": phase_avg_ms,
+                     "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
+                                                             params["amp_mode"])]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

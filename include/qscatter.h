@@ -1,0 +1,213 @@
+/*
+ * qscatter.h -- C ABI of the MI355X (gfx950) beam-phase-space integrator.
+ *
+ * The library predicts the asymptotic electron energy and angle distributions,
+ * the a0,eff distribution and moments after a relativistic electron beam meets
+ * a focused, possibly misaligned, laser pulse head-on (Amaro & Vranic,
+ * "QScatter", arXiv 2308.09348: abstract; Sec. 2 eq. dNda0eff and eq. a0eff;
+ * Sec. 3 eq. PWCRR and eq. dNda2dNdgf; Sec. 4 eq. dpdtRR; Sec. 5.2).
+ *
+ * Every step of the computation runs in HIP kernels on the device: sample
+ * generation, the per-sample laser amplitude, the phase integration of the
+ * radiation-reaction moment system, the deposit into spectra, the reductions
+ * and the normalisation.  The host only validates arguments and enqueues work.
+ *
+ * Conventions
+ *   - Plain C types only.  Pointers marked "device" must be device memory of
+ *     the context's GPU; pointers marked "host" are read during the call only.
+ *   - Calls are asynchronous on the given stream (0 = the null stream).  The
+ *     library retains no caller pointer after a call returns.
+ *   - Return values are qs_status codes; nothing is enqueued when a call
+ *     returns an error (no partial writes).  Errors raised inside kernels
+ *     (non-finite states, chi beyond the tabulated range) are written to the
+ *     caller's device status word and reported by qs_sync_status().
+ *   - One context may be used from one host thread at a time.  Calls that
+ *     share a context must be ordered on one stream (they share the
+ *     context's device scratch).
+ */
+#ifndef QSCATTER_H
+#define QSCATTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QS_ABI_VERSION 1
+
+typedef enum qs_status {
+    QS_OK = 0,
+    QS_EINVAL = 1,        /* an argument failed validation                     */
+    QS_ENOMEM = 2,        /* device allocation failed                          */
+    QS_EDEVICE = 3,       /* a HIP runtime call failed                         */
+    QS_ENONFINITE = 4,    /* a sample reached a non-finite state (device-side) */
+    QS_EUNSUPPORTED = 5,  /* valid but not supported by this build             */
+    QS_ERANGE = 6         /* chi left the tabulated range [0, 256) (device)    */
+} qs_status;
+
+enum { QS_ENV_GAUSS = 0, QS_ENV_SIN2 = 1 };
+enum { QS_RR_CLASSICAL = 0, QS_RR_QUANTUM = 1 };
+enum { QS_AMP_A0EFF = 0, QS_AMP_LOCAL = 1 };
+enum { QS_DEP_POINT = 0, QS_DEP_CIC = 1, QS_DEP_GAUSS = 2 };
+enum { QS_PREC_FP32 = 0, QS_PREC_FP64 = 1 };
+
+/* Laser (Sec. 2 eq. a0eff; misalignment of Table 1).  Lengths in um,
+ * times in fs.  The laser propagates along +z with its peak at z = c t and
+ * focus at z = 0; linear polarisation along x, carrier resolved, CEP 0. */
+typedef struct qs_laser {
+    double a0;         /* peak normalised vector potential, >= 0               */
+    double lambda_um;  /* central wavelength, > 0                              */
+    double w0_um;      /* spot size W0 at focus, >= 0; 0 selects a plane wave  */
+    double tau_fs;     /* GAUSS: intensity FWHM; SIN2: rise time; > 0          */
+    int32_t envelope;  /* QS_ENV_*                                             */
+    int32_t reserved0;
+    double x_off_um;   /* beam centroid offset from the laser axis (x)         */
+    double y_off_um;   /* beam centroid offset from the laser axis (y)         */
+    double delay_fs;   /* collision delay: the centroid meets the peak at
+                          z = c delay / 2                                      */
+} qs_laser;
+
+/* Electron beam (abstract: broadband beams, divergence).  The beam moves
+ * along -z; positions are per-axis Gaussian, taken when the centroid meets
+ * the laser peak. */
+typedef struct qs_beam {
+    double gamma0;       /* mean initial Lorentz factor, > 1                   */
+    double sigma_gamma;  /* rms of the initial Lorentz factor, >= 0           */
+    double sigma_r_um;   /* per-axis rms transverse size, >= 0                */
+    double sigma_z_um;   /* rms length, >= 0                                  */
+    double div_mrad;     /* per-plane rms divergence, >= 0                    */
+} qs_beam;
+
+/* Numerics of the phase-space quadrature. */
+typedef struct qs_numerics {
+    int64_t n_samples;        /* Monte-Carlo samples (beam volume elements), 1..2^32 */
+    int32_t n_steps;          /* RK4 phase steps across the window, 1..65536 */
+    int32_t shot;             /* shot index: second word of the RNG counter  */
+    double window_fwhm;       /* GAUSS: window is +-window_fwhm FWHM; > 0     */
+    uint64_t seed;            /* Philox4x32-10 key                           */
+    int32_t rr_model;         /* QS_RR_CLASSICAL (Landau-Lifshitz, g = 1) or
+                                 QS_RR_QUANTUM (Gaunt factor g(chi) and the
+                                 diffusion of the energy spread)             */
+    int32_t amp_mode;         /* QS_AMP_A0EFF: each sample sees a0,eff at its
+                                 collision point (Sec. 2); QS_AMP_LOCAL: the
+                                 local amplitude along its ballistic path    */
+    int32_t deposit;          /* QS_DEP_POINT, QS_DEP_CIC, QS_DEP_GAUSS       */
+    int32_t precision;        /* QS_PREC_FP32 (compensated) or QS_PREC_FP64   */
+    double kernel_sigma_bins; /* QS_DEP_GAUSS kernel rms, in bins, >= 0       */
+    double chi_fp64;          /* FP32 only: a wavefront runs a phase step in
+                                 FP64 when any of its samples has chi above
+                                 this at the step start; <= 0 disables        */
+    double c_theta;           /* pre-factor of the Sec. 5.2 divergence law    */
+} qs_numerics;
+
+/* Histogram windows.  Energy and angle histograms have n bins plus
+ * underflow at [n] and overflow at [n+1]; the a0,eff histogram has n_a bins
+ * over a0,eff / a0 in [0, 1] (top edge closed). */
+typedef struct qs_bins {
+    int32_t n_e;         /* energy bins, 1..4096                                */
+    int32_t n_th;        /* angle bins (x plane), 1..4096                       */
+    int32_t n_a;         /* a0,eff bins, 1..4096                                */
+    int32_t reserved0;
+    double e_lo, e_hi;   /* energy window in m c^2 (Lorentz factor), hi > lo    */
+    double th_lo_mrad, th_hi_mrad; /* angle window, hi > lo                     */
+} qs_bins;
+
+/* Moments written to qs_outputs.moments (16 doubles). */
+enum {
+    QS_M_WEIGHT = 0,    /* number of samples                                    */
+    QS_M_MEAN_G,        /* mean final Lorentz factor                            */
+    QS_M_STD_G,         /* std of the final energy law (incl. beamlet spread)   */
+    QS_M_MEAN_THX,      /* mean angle, polarisation plane [mrad]                */
+    QS_M_RMS_THX,       /* rms angle incl. the Sec. 5.2 broadening [mrad]       */
+    QS_M_MEAN_THY,      /* mean angle, other plane [mrad]                       */
+    QS_M_RMS_THY,       /* rms angle, other plane [mrad]                        */
+    QS_M_MEAN_AEFF,     /* mean a0,eff                                          */
+    QS_M_MAX_CHI,       /* largest chi met at a step start                      */
+    QS_M_RAD_FRAC,      /* mean radiated energy fraction                        */
+    QS_M_MEAN_SIGF,     /* mean beamlet energy spread sigma_f                   */
+    QS_M_N = 16
+};
+
+/* Per-sample record (QS_S_N doubles) for diagnostics and parity checks. */
+enum {
+    QS_S_MU = 0, QS_S_SIG2, QS_S_THX, QS_S_THY, QS_S_SIGTH, QS_S_AEFF, QS_S_CHIMAX,
+    QS_S_GAMMA0, QS_S_X, QS_S_Y, QS_S_Z, QS_S_N
+};
+
+/* Outputs: all device pointers, caller-allocated, fully overwritten. */
+typedef struct qs_outputs {
+    double *energy_hist;  /* [n_e + 2] weight per bin (one unit per sample)      */
+    double *angle_hist;   /* [n_th + 2]                                          */
+    double *a0eff_hist;   /* [n_a]                                               */
+    double *moments;      /* [QS_M_N]                                            */
+    int32_t *status;      /* [1] qs_status of the device-side checks             */
+    double *samples;      /* optional [n_sample_records][QS_S_N]: records of
+                             samples i = r * sample_stride; NULL for none       */
+    int64_t sample_stride;     /* >= 1 when samples != NULL                      */
+    int64_t n_sample_records;  /* records written (those with i < n_samples)     */
+} qs_outputs;
+
+typedef struct qs_ctx qs_ctx;
+
+/* Create a context on HIP device `device`: builds the radiation-function
+ * tables (g, chi g', chi^2 g'', h of the LCFA spectrum, Sec. 4 eq. dpdtRR) on
+ * the device.  *ctx receives the handle; on error it is set to NULL.
+ * Errors: QS_EINVAL (ctx NULL or no such device), QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_create(qs_ctx **ctx, int device);
+
+/* Release the context and its device memory.  Waits for the device.  NULL
+ * is accepted. */
+void qs_destroy(qs_ctx *ctx);
+
+/* One forward pass (abstract; Sec. 2-3 and 5.2): draw n_samples beam samples,
+ * integrate each sample's mean energy and energy variance along the laser
+ * phase under classical (eq. PWCRR) or quantum-corrected (eq. dpdtRR)
+ * radiation reaction, and deposit the final laws into the histograms
+ * (eq. dNda2dNdgf as a push-forward) and moments.  `stream` is a hipStream_t
+ * (void* here so the header needs no HIP include).  Results are deterministic
+ * for a given device and arguments.
+ * Errors: QS_EINVAL (any NULL struct or output pointer, a value outside its
+ * documented range, a non-finite input), QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_forward(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                     const qs_numerics *num, const qs_bins *bins,
+                     const qs_outputs *out, void *stream);
+
+/* Evaluate the device radiation-function approximation at n values of chi
+ * (device arrays): out[4*k + {0,1,2,3}] = {g, chi g', chi^2 g'', h} at
+ * chi[k], in FP32 (precision QS_PREC_FP32) or FP64.  Diagnostic entry point
+ * for parity checks of the tables against their definition (Sec. 4).
+ * Errors: QS_EINVAL, QS_EDEVICE. */
+qs_status qs_radiation_eval(qs_ctx *ctx, int32_t precision, int64_t n, const double *chi,
+                            double *out, void *stream);
+
+/* Synchronise `stream` and return the device status word of the last call
+ * that wrote `status` (device pointer) -- QS_OK, QS_ENONFINITE or QS_ERANGE. */
+qs_status qs_sync_status(qs_ctx *ctx, const int32_t *status, void *stream);
+
+/* Enable (on != 0) or disable event timing of the kernels that qs_forward
+ * enqueues on this context.  Events are recorded on the caller's stream
+ * between the launches, so they bracket each kernel.  Errors: QS_EINVAL,
+ * QS_EDEVICE. */
+qs_status qs_set_profiling(qs_ctx *ctx, int on);
+
+/* Durations in milliseconds of the kernels of the last qs_forward enqueued
+ * with profiling on: ms[0] envelope table, ms[1] accumulator clear, ms[2]
+ * phase integration, ms[3] deposit, ms[4] finalize (host array of 5).
+ * Waits for that call's last event.  Errors: QS_EINVAL (profiling off or no
+ * profiled call yet), QS_EDEVICE. */
+qs_status qs_last_timings(qs_ctx *ctx, double *ms);
+
+/* Static description of a status code. */
+const char *qs_strerror(qs_status s);
+
+/* Detail of the last error raised on this context (empty if none). */
+const char *qs_last_error(qs_ctx *ctx);
+
+/* QS_ABI_VERSION of the built library. */
+int qs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSCATTER_H */

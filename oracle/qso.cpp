@@ -232,6 +232,10 @@ const RadTable &table() {
 
 /* g, chi g', chi^2 g'', h at chi >= 0 (4-point Lagrange in u). */
 void radiation(double chi, double out[4]) {
+    if (!(chi >= 0.0)) {  /* a negative energy or amplitude: no physical chi */
+        out[0] = out[1] = out[2] = out[3] = NAN;
+        return;
+    }
     if (chi < kChiMin) {
         out[0] = 1.0 + kG1 * chi + kG2 * chi * chi;
         out[1] = kG1 * chi + 2.0 * kG2 * chi * chi;

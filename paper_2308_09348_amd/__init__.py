@@ -1,0 +1,139 @@
+"""MI355X (gfx950) beam-phase-space integrator of QScatter (arXiv 2308.09348).
+
+``forward(params)`` predicts the asymptotic electron energy / angle / a0,eff
+distributions and moments after a relativistic electron beam meets a focused,
+possibly misaligned laser pulse head-on.  All computation runs in the HIP
+kernels of ``libqscatter.so``; PyTorch only provides device memory and the
+stream.
+"""
+import ctypes
+
+from . import _lib
+
+__all__ = ["Context", "forward", "radiation_eval", "QScatterError"]
+
+QScatterError = _lib.QScatterError
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required (torch.cuda.is_available() is False)")
+    return torch
+
+
+class Context:
+    """Owns a qs_ctx (radiation tables and device scratch) on one device."""
+
+    def __init__(self, device=0):
+        self._ptr = ctypes.c_void_p()
+        self.device = int(device)
+        st = _lib.lib().qs_create(ctypes.byref(self._ptr), self.device)
+        if st != _lib.QS_OK:
+            raise QScatterError(st, "qs_create")
+
+    @property
+    def handle(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            _lib.lib().qs_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return _lib.lib().qs_last_error(self._ptr).decode()
+
+    def forward(self, params, sample_stride=0, n_sample_records=0, stream=None, out=None,
+                check=True):
+        """Enqueue one forward pass; returns a dict of device tensors.
+
+        ``out`` may hold preallocated tensors (same keys as the result) to
+        avoid allocation.  With ``check`` the stream is synchronised and the
+        device status word raised as an error."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        la, be, nu, bi = _lib.structs(params)
+        if out is None:
+            out = {
+                "energy_hist": torch.empty(params["n_e"] + 2, dtype=torch.float64, device=dev),
+                "angle_hist": torch.empty(params["n_th"] + 2, dtype=torch.float64, device=dev),
+                "a0eff_hist": torch.empty(params["n_a"], dtype=torch.float64, device=dev),
+                "moments": torch.empty(_lib.M_N, dtype=torch.float64, device=dev),
+                "status": torch.empty(1, dtype=torch.int32, device=dev),
+            }
+            if n_sample_records > 0:
+                out["samples"] = torch.empty((n_sample_records, _lib.S_N), dtype=torch.float64,
+                                             device=dev)
+        o = _lib.Outputs(
+            energy_hist=out["energy_hist"].data_ptr(), angle_hist=out["angle_hist"].data_ptr(),
+            a0eff_hist=out["a0eff_hist"].data_ptr(), moments=out["moments"].data_ptr(),
+            status=out["status"].data_ptr(),
+            samples=out["samples"].data_ptr() if "samples" in out else None,
+            sample_stride=max(int(sample_stride), 1), n_sample_records=int(n_sample_records))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        st = _lib.lib().qs_forward(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                   ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(o),
+                                   ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        if check:
+            st = _lib.lib().qs_sync_status(self._ptr, ctypes.c_void_p(out["status"].data_ptr()),
+                                           ctypes.c_void_p(stream.cuda_stream))
+            if st != _lib.QS_OK:
+                raise QScatterError(st, "device status")
+        return out
+
+    def set_profiling(self, on=True):
+        st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+
+    def last_timings(self):
+        """Kernel durations [ms] of the last profiled forward: envelope, clear,
+        phase, deposit, finalize."""
+        ms = (ctypes.c_double * 5)()
+        st = _lib.lib().qs_last_timings(self._ptr, ms)
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        return dict(zip(["envelope", "clear", "phase", "deposit", "finalize"], list(ms)))
+
+    def radiation_eval(self, chi, precision="fp32"):
+        """{g, chi g', chi^2 g'', h} of the device tables at chi (1-D float64 tensor)."""
+        torch = _torch()
+        chi = chi.to(device=torch.device("cuda", self.device), dtype=torch.float64).contiguous()
+        out = torch.empty((chi.numel(), 4), dtype=torch.float64, device=chi.device)
+        stream = torch.cuda.current_stream(chi.device)
+        st = _lib.lib().qs_radiation_eval(self._ptr, _lib.PRECISION[precision], chi.numel(),
+                                          ctypes.c_void_p(chi.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        torch.cuda.synchronize(chi.device)
+        return out
+
+
+_default = {}
+
+
+def _ctx(device=0):
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def forward(params, device=0, **kw):
+    """One forward pass on ``device`` with a cached context."""
+    return _ctx(device).forward(params, **kw)
+
+
+def radiation_eval(chi, precision="fp32", device=0):
+    return _ctx(device).radiation_eval(chi, precision)

@@ -1,0 +1,138 @@
+"""ctypes binding of libqscatter.so (the C ABI of include/qscatter.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  The library must be built (``build()`` of
+``__graft_entry__`` or ``python -m paper_2308_09348_amd.build``); there is no
+fallback when it is missing.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqscatter.so")
+
+QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_ENONFINITE, QS_EUNSUPPORTED, QS_ERANGE = range(7)
+ENVELOPE = {"gauss": 0, "sin2": 1}
+RR_MODEL = {"classical": 0, "quantum": 1}
+AMP_MODE = {"a0eff": 0, "local": 1}
+DEPOSIT = {"point": 0, "cic": 1, "gauss": 2}
+PRECISION = {"fp32": 0, "fp64": 1}
+
+M_N = 16
+S_N = 11
+(M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, M_MEAN_AEFF,
+ M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF) = range(11)
+(S_MU, S_SIG2, S_THX, S_THY, S_SIGTH, S_AEFF, S_CHIMAX, S_GAMMA0, S_X, S_Y, S_Z) = range(11)
+
+
+class Laser(ctypes.Structure):
+    _fields_ = [("a0", ctypes.c_double), ("lambda_um", ctypes.c_double),
+                ("w0_um", ctypes.c_double), ("tau_fs", ctypes.c_double),
+                ("envelope", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("x_off_um", ctypes.c_double), ("y_off_um", ctypes.c_double),
+                ("delay_fs", ctypes.c_double)]
+
+
+class Beam(ctypes.Structure):
+    _fields_ = [("gamma0", ctypes.c_double), ("sigma_gamma", ctypes.c_double),
+                ("sigma_r_um", ctypes.c_double), ("sigma_z_um", ctypes.c_double),
+                ("div_mrad", ctypes.c_double)]
+
+
+class Numerics(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("n_steps", ctypes.c_int32),
+                ("shot", ctypes.c_int32), ("window_fwhm", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("rr_model", ctypes.c_int32),
+                ("amp_mode", ctypes.c_int32), ("deposit", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("kernel_sigma_bins", ctypes.c_double),
+                ("chi_fp64", ctypes.c_double), ("c_theta", ctypes.c_double)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("n_e", ctypes.c_int32), ("n_th", ctypes.c_int32), ("n_a", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("e_lo", ctypes.c_double),
+                ("e_hi", ctypes.c_double), ("th_lo_mrad", ctypes.c_double),
+                ("th_hi_mrad", ctypes.c_double)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("energy_hist", ctypes.c_void_p), ("angle_hist", ctypes.c_void_p),
+                ("a0eff_hist", ctypes.c_void_p), ("moments", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("samples", ctypes.c_void_p),
+                ("sample_stride", ctypes.c_int64), ("n_sample_records", ctypes.c_int64)]
+
+
+EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_radiation_eval", "qs_sync_status",
+           "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
+           "qs_abi_version"]
+
+_lib = None
+
+
+class QScatterError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        msg = lib().qs_strerror(status).decode()
+        super().__init__(f"{msg} ({status})" + (f": {detail}" if detail else ""))
+
+
+def lib():
+    """Load libqscatter.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2308_09348_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.qs_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.qs_create.restype = ctypes.c_int
+        L.qs_destroy.argtypes = [vp]
+        L.qs_destroy.restype = None
+        L.qs_forward.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                                 ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+                                 ctypes.POINTER(Outputs), vp]
+        L.qs_forward.restype = ctypes.c_int
+        L.qs_radiation_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.qs_radiation_eval.restype = ctypes.c_int
+        L.qs_sync_status.argtypes = [vp, vp, vp]
+        L.qs_sync_status.restype = ctypes.c_int
+        L.qs_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.qs_set_profiling.restype = ctypes.c_int
+        L.qs_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.qs_last_timings.restype = ctypes.c_int
+        L.qs_strerror.argtypes = [ctypes.c_int]
+        L.qs_strerror.restype = ctypes.c_char_p
+        L.qs_last_error.argtypes = [vp]
+        L.qs_last_error.restype = ctypes.c_char_p
+        L.qs_abi_version.argtypes = []
+        L.qs_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _enum(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def structs(params):
+    """Plain parameter dictionary -> (Laser, Beam, Numerics, Bins)."""
+    la = Laser(a0=params["a0"], lambda_um=params["lambda_um"], w0_um=params["w0_um"],
+               tau_fs=params["tau_fs"], envelope=_enum(ENVELOPE, params["envelope"]),
+               reserved0=0, x_off_um=params["x_off_um"], y_off_um=params["y_off_um"],
+               delay_fs=params["delay_fs"])
+    be = Beam(gamma0=params["gamma0"], sigma_gamma=params["sigma_gamma"],
+              sigma_r_um=params["sigma_r_um"], sigma_z_um=params["sigma_z_um"],
+              div_mrad=params["div_mrad"])
+    nu = Numerics(n_samples=params["n_samples"], n_steps=params["n_steps"],
+                  shot=params.get("shot", 0), window_fwhm=params["window_fwhm"],
+                  seed=params["seed"], rr_model=_enum(RR_MODEL, params["rr_model"]),
+                  amp_mode=_enum(AMP_MODE, params["amp_mode"]),
+                  deposit=_enum(DEPOSIT, params["deposit"]),
+                  precision=_enum(PRECISION, params.get("precision", "fp32")),
+                  kernel_sigma_bins=params["kernel_sigma_bins"],
+                  chi_fp64=params.get("chi_fp64", 0.0), c_theta=params["c_theta"])
+    bi = Bins(n_e=params["n_e"], n_th=params["n_th"], n_a=params["n_a"], reserved0=0,
+              e_lo=params["e_lo"], e_hi=params["e_hi"], th_lo_mrad=params["th_lo_mrad"],
+              th_hi_mrad=params["th_hi_mrad"])
+    return la, be, nu, bi

@@ -1,0 +1,919 @@
+// qs_kernels.hip -- gfx950 kernels of the beam-phase-space integrator.
+//
+// Hot path (Amaro & Vranic, arXiv 2308.09348).  The phase kernel gives one
+// lane one beam sample at a time: it draws the sample (Philox4x32-10 +
+// Box-Muller), places it on its ballistic path through the focused pulse
+// (Sec. 2, eq. a0eff, Table 1 offsets) and integrates its mean energy and
+// energy variance along the phase with RK4 under the radiation-reaction drift
+// of eq. dpdtRR (classical limit: eq. PWCRR), with the state in registers and
+// the radiation-function table in LDS.  It writes the final state (56 bytes a
+// sample).  The deposit kernel turns final states into energy and angle laws
+// (eq. dNda2dNdgf as a push-forward; Sec. 5.2 divergence) deposited into
+// block-private LDS histograms in 32.32 fixed point, merged into global
+// integer histograms (order-independent), plus FP64 moment partials that a
+// finalize kernel reduces in a fixed order.  The split keeps the FP64
+// deposit arithmetic from setting the register budget of the phase loop.
+// Nothing here is a dense contraction, so no MFMA: the bound is the vector
+// ALU of the phase loop.
+#include "qs_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace qs {
+
+// ===========================================================================
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller normals
+// ===========================================================================
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Six standard normals of sample i: counter (i, shot, k, 0) for k = 0, 1,
+// 24-bit uniforms u = ((r >> 8) + 1/2) 2^-24, Box-Muller on pairs.
+__device__ __forceinline__ void sample_normals(uint32_t i, uint32_t shot, uint32_t k0, uint32_t k1,
+                                               double n[6]) {
+    uint32_t r[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 2; ++k) {
+        uint32_t c[4] = {i, shot, k, 0u};
+        philox4x32_10(c, k0, k1);
+        r[4 * k + 0] = c[0];
+        r[4 * k + 1] = c[1];
+        r[4 * k + 2] = c[2];
+        r[4 * k + 3] = c[3];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double u1 = ((double)(r[2 * m] >> 8) + 0.5) * 0x1p-24;
+        const double u2 = ((double)(r[2 * m + 1] >> 8) + 0.5) * 0x1p-24;
+        const double R = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincospi(2.0 * u2, &s, &c);
+        n[2 * m] = R * c;
+        n[2 * m + 1] = R * s;
+    }
+}
+
+// ===========================================================================
+// Radiation functions: g, chi g', chi^2 g'', h from per-cell cubics
+// ===========================================================================
+__device__ __forceinline__ void rad_eval32(const float *__restrict__ tab, float chi, float &g,
+                                           float &G1, float &G2, float &hq, int &flags) {
+    const uint32_t b = __float_as_uint(chi);
+    const int e = (int)(b >> 23) - 127;
+    const int sub = (int)((b >> (23 - kSB32)) & ((1u << kSB32) - 1));
+    const float tf = (float)(b & ((1u << (23 - kSB32)) - 1)) * (1.0f / (float)(1u << (23 - kSB32)));
+    int c = 1 + ((e - kEMin) << kSB32) + sub;
+    float t = tf;
+    if (e < kEMin) {
+        c = 0;
+        t = chi * 0x1p20f;  // chi / 2^kEMin
+    }
+    if (e > kEMax) {
+        c = kCells32 - 1;
+        t = 1.0f;
+        flags |= kFlagRange;
+    }
+    const float4 *cell = reinterpret_cast<const float4 *>(tab + c * kCellVals);
+    const float4 q0 = cell[0], q1 = cell[1], q2 = cell[2], q3 = cell[3];
+    g = fmaf(t, fmaf(t, fmaf(t, q0.w, q0.z), q0.y), q0.x);
+    G1 = fmaf(t, fmaf(t, fmaf(t, q1.w, q1.z), q1.y), q1.x);
+    G2 = fmaf(t, fmaf(t, fmaf(t, q2.w, q2.z), q2.y), q2.x);
+    hq = fmaf(t, fmaf(t, fmaf(t, q3.w, q3.z), q3.y), q3.x);
+}
+
+__device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
+                                           double &G1, double &G2, double &hq, int &flags) {
+    const uint64_t b = (uint64_t)__double_as_longlong(chi);
+    const int e = (int)(b >> 52) - 1023;
+    const int sub = (int)((b >> (52 - kSB64)) & ((1ull << kSB64) - 1));
+    const double tf = (double)(b & ((1ull << (52 - kSB64)) - 1)) * (1.0 / (double)(1ull << (52 - kSB64)));
+    int c = 1 + ((e - kEMin) << kSB64) + sub;
+    double t = tf;
+    if (e < kEMin) {
+        c = 0;
+        t = chi * 0x1p20;
+    }
+    if (e > kEMax) {
+        c = kCells64 - 1;
+        t = 1.0;
+        flags |= kFlagRange;
+    }
+    const double *q = tab + (size_t)c * kCellVals;
+    g = fma(t, fma(t, fma(t, q[3], q[2]), q[1]), q[0]);
+    G1 = fma(t, fma(t, fma(t, q[7], q[6]), q[5]), q[4]);
+    G2 = fma(t, fma(t, fma(t, q[11], q[10]), q[9]), q[8]);
+    hq = fma(t, fma(t, fma(t, q[15], q[14]), q[13]), q[12]);
+}
+
+template <class T>
+struct RadTab;
+template <>
+struct RadTab<float> {
+    const float *p;
+    __device__ __forceinline__ void eval(float chi, float &g, float &G1, float &G2, float &h,
+                                         int &f) const {
+        rad_eval32(p, chi, g, G1, G2, h, f);
+    }
+};
+template <>
+struct RadTab<double> {
+    const double *p;
+    __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2, double &h,
+                                         int &f) const {
+        rad_eval64(p, chi, g, G1, G2, h, f);
+    }
+};
+
+// ===========================================================================
+// The moment system (second-order closure of the drift-diffusion process
+// whose drift is eq. dpdtRR in phase units):
+//   dmu/dpsi   = A + A'' sig2 / 2,   dsig2/dpsi = 2 A' sig2 + D,
+//   A = -K a^2 mu^2 g,  A' = -K a^2 mu (2g + G1),  A'' = -K a^2 (2g + 4G1 + G2),
+//   D = C_D |a|^3 mu^4 h,  chi = 2 mu |a| / a_S.
+// ===========================================================================
+template <class T>
+struct Phys {
+    T K, CD, two_over_aS;
+};
+
+template <class T, bool QUANTUM>
+__device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const RadTab<T> &tab,
+                                    T &dmu, T &ds2, int &flags) {
+    const T a2 = a * a;
+    const T Ka2 = ph.K * a2;
+    if (!QUANTUM) {
+        dmu = -Ka2 * mu * mu;
+        ds2 = T(0);
+        return;
+    }
+    const T aa = fabs(a);
+    const T chi = ph.two_over_aS * mu * aa;
+    T g, G1, G2, hq;
+    tab.eval(chi, g, G1, G2, hq, flags);
+    const T two_g = T(2) * g;
+    const T A = -Ka2 * mu * mu * g;
+    const T A1 = -Ka2 * mu * (two_g + G1);
+    const T A2 = -Ka2 * (two_g + T(4) * G1 + G2);
+    const T mu2 = mu * mu;
+    const T D = ph.CD * a2 * aa * mu2 * mu2 * hq;
+    dmu = fma(T(0.5) * A2, s2, A);
+    ds2 = fma(T(2) * A1, s2, D);
+}
+
+// Spatial factor a/a0 of eq. a0eff at (x, y, z) [um].
+__device__ __forceinline__ float spatial(float x, float y, float z, float inv_w0sq, float inv_zR) {
+    const float zz = z * inv_zR;
+    const float q = fmaf(zz, zz, 1.0f);
+    const float iq = 1.0f / q;
+    const float r2 = fmaf(x, x, y * y) * inv_w0sq;
+    return expf(-r2 * iq) * sqrtf(iq);
+}
+__device__ __forceinline__ double spatial(double x, double y, double z, double inv_w0sq,
+                                          double inv_zR) {
+    const double zz = z * inv_zR;
+    const double q = fma(zz, zz, 1.0);
+    const double iq = 1.0 / q;
+    const double r2 = fma(x, x, y * y) * inv_w0sq;
+    return exp(-r2 * iq) * sqrt(iq);
+}
+
+// Geometry of one sample along its ballistic path: at phase psi it has
+// travelled l = psi lambda / (4 pi) past its collision point.
+template <class T>
+struct Path {
+    T xc, yc, thx, thy, zstar, inv_w0sq, inv_zR;
+    __device__ __forceinline__ T S(T ell) const {
+        return spatial(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell, inv_w0sq, inv_zR);
+    }
+};
+
+// One RK4 step of (mu, sig2) from psi_j with amplitudes a1 = a(psi_j),
+// ah = a(psi_j + h/2), a4 = a(psi_j + h); returns the increments.
+template <class T, bool QUANTUM>
+__device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
+                                              const Phys<T> &ph, const RadTab<T> &tab, T &dmu,
+                                              T &ds2, int &flags) {
+    const T hh = T(0.5) * h;
+    T k1m, k1s, k2m, k2s, k3m, k3s, k4m, k4s;
+    rhs<T, QUANTUM>(mu, s2, a1, ph, tab, k1m, k1s, flags);
+    rhs<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, flags);
+    rhs<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, flags);
+    rhs<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, flags);
+    const T h6 = h * T(1.0 / 6.0);
+    dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
+    ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+}
+
+// Compensated accumulation: (hi, lo) += d, renormalised (Fast2Sum, |hi| >= |d|).
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float d) {
+    const float dd = d + lo;
+    const float s = hi + dd;
+    lo = dd - (s - hi);
+    hi = s;
+}
+
+// ===========================================================================
+// Deposit of one law into block-private fixed-point histograms
+// ===========================================================================
+constexpr unsigned long long kOne = 1ull << 32;
+
+__device__ __forceinline__ double Phi(double t) { return 0.5 * erfc(-t * 0.70710678118654752440); }
+__device__ __forceinline__ double PhiC(double t) { return 0.5 * erfc(t * 0.70710678118654752440); }
+__device__ __forceinline__ double phi(double t) {
+    return exp(-0.5 * t * t) * 0.39894228040143267794;
+}
+
+__device__ __forceinline__ void ngp(double v, double lo, double w, int n,
+                                    unsigned long long *h) {
+    const double x = (v - lo) / w;
+    int k;
+    if (!(x >= 0.0))
+        k = n;  // underflow
+    else if (x >= (double)n)
+        k = n + 1;  // overflow
+    else
+        k = (int)x;
+    atomicAdd(&h[k], kOne);
+}
+
+// The deposited law is the sample's own law (a point at v if s = 0, else
+// N(v, s^2)) convolved with the deposit kernel (POINT: none; CIC: a box one
+// bin wide; GAUSS: N(0, (ksig bins)^2)).  Bin masses are differences of the
+// law's CDF at the bin edges, quantised to 2^-32 so that every sample adds
+// exactly 2^32; beyond 8 standard deviations the CDF is taken as 0 or 1.
+__device__ void deposit_law(double v, double s, int dep, double ksig, double lo, double w, int n,
+                            unsigned long long *h) {
+    const double half = 0.5 * w;
+    int mode;
+    double se = s;
+    if (dep == 2) {  // GAUSS
+        const double ks = ksig * w;
+        se = sqrt(s * s + ks * ks);
+        mode = se > 0.0 ? 2 : 0;
+    } else if (dep == 1) {  // CIC
+        mode = s > 0.0 ? 3 : 1;
+    } else {
+        mode = s > 0.0 ? 2 : 0;
+    }
+    if (mode == 0) {
+        ngp(v, lo, w, n, h);
+        return;
+    }
+    const double reach = mode == 1 ? half : (mode == 2 ? 8.0 * se : 8.0 * se + half);
+    int ka = (int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0);
+    int kb = (int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0);
+    ka = max(ka, 0);
+    kb = min(kb, n);
+    if (ka > kb) {
+        ngp(v, lo, w, n, h);  // the whole law lies inside one bin (or outside)
+        return;
+    }
+    const double inv_se = mode >= 2 ? 1.0 / se : 0.0;
+    unsigned long long qprev = 0;
+    for (int k = ka; k <= kb; ++k) {
+        const double t = fma((double)k, w, lo) - v;
+        double F;
+        bool upper = t > 0.0;
+        if (mode == 1) {
+            F = upper ? fmin(fmax(0.5 - t / w, 0.0), 1.0) : fmin(fmax(t / w + 0.5, 0.0), 1.0);
+        } else if (mode == 2) {
+            F = upper ? PhiC(t * inv_se) : Phi(t * inv_se);
+        } else {
+            const double ta = t - half, tb = t + half;
+            if (upper) {
+                const double pa = -ta * PhiC(ta * inv_se) + se * phi(ta * inv_se);
+                const double pb = -tb * PhiC(tb * inv_se) + se * phi(tb * inv_se);
+                F = (pa - pb) / w;
+            } else {
+                const double pa = ta * Phi(ta * inv_se) + se * phi(ta * inv_se);
+                const double pb = tb * Phi(tb * inv_se) + se * phi(tb * inv_se);
+                F = (pb - pa) / w;
+            }
+        }
+        F = fmin(fmax(F, 0.0), 1.0);
+        const unsigned long long qf = (unsigned long long)llrint(F * 4294967296.0);
+        unsigned long long q = upper ? kOne - qf : qf;
+        q = q < qprev ? qprev : q;
+        const int bin = k == 0 ? n : k - 1;  // mass between edge k-1 and edge k
+        if (q != qprev) atomicAdd(&h[bin], q - qprev);
+        qprev = q;
+    }
+    const int bin = kb == n ? n + 1 : kb;  // mass above the last edge in the window
+    if (qprev != kOne) atomicAdd(&h[bin], kOne - qprev);
+}
+
+// ===========================================================================
+// Phase kernel: sample -> ballistic path -> RK4 phase loop -> final state
+// ===========================================================================
+template <int PREC, bool QUANTUM, bool LOCAL>
+__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
+    constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
+    if (kTab32) {
+        const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
+        float4 *dst = reinterpret_cast<float4 *>(tab32);
+        for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
+        __syncthreads();
+    }
+    const RadTab<float> tabf{tab32};
+    const RadTab<double> tabd{P.rad64};
+    const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
+    const Phys<double> phd{P.K, P.CD, P.two_over_aS};
+    const int N = P.n_steps;
+    const bool local = LOCAL && !P.plane_wave;
+    int flags = 0;
+
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n_samples; i += stride) {
+        // ---- sample and geometry (FP64, once per sample) ----
+        double nrm[6];
+        sample_normals((uint32_t)i, (uint32_t)P.shot, P.key0, P.key1, nrm);
+        const double x = fma(P.sigma_r, nrm[0], P.x_off);
+        const double y = fma(P.sigma_r, nrm[1], P.y_off);
+        const double z = P.sigma_z * nrm[2];
+        const double g0 = fma(P.sigma_gamma, nrm[3], P.gamma0);
+        const double thx = P.div_rad * nrm[4];
+        const double thy = P.div_rad * nrm[5];
+        Path<double> pd;
+        pd.xc = fma(thx, 0.5 * z, x);
+        pd.yc = fma(thy, 0.5 * z, y);
+        pd.thx = thx;
+        pd.thy = thy;
+        pd.zstar = fma(0.5, z, P.z_delay);
+        pd.inv_w0sq = P.inv_w0sq;
+        pd.inv_zR = P.inv_zR;
+        const double S0 = P.plane_wave ? 1.0 : pd.S(0.0);
+        const double a0S0 = P.a0 * S0;
+
+        double mu_f, s2_f;
+        float cmx = 0.0f;  // largest chi at a step start for this sample
+        if (PREC == PREC_F64) {
+            double mu = g0, s2 = 0.0;
+            double aS_prev = local ? P.a0 * pd.S(-P.psi_max * P.ell_per_psi) : a0S0;
+            for (int j = 0; j < N; ++j) {
+                const double psi = fma((double)j, P.h, -P.psi_max);
+                double aSh = a0S0, aS4 = a0S0;
+                if (local) {
+                    aSh = P.a0 * pd.S(fma(0.5, P.h, psi) * P.ell_per_psi);
+                    aS4 = P.a0 * pd.S((psi + P.h) * P.ell_per_psi);
+                }
+                const double a1 = aS_prev * P.env64[2 * j];
+                const double ah = aSh * P.env64[2 * j + 1];
+                const double a4 = aS4 * P.env64[2 * j + 2];
+                cmx = fmaxf(cmx, (float)(P.two_over_aS * mu * fabs(a1)));
+                double dm, ds;
+                rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, flags);
+                mu += dm;
+                s2 += ds;
+                aS_prev = aS4;
+            }
+            mu_f = mu;
+            s2_f = s2;
+        } else {
+            Path<float> pf;
+            pf.xc = (float)pd.xc;
+            pf.yc = (float)pd.yc;
+            pf.thx = (float)thx;
+            pf.thy = (float)thy;
+            pf.zstar = (float)pd.zstar;
+            pf.inv_w0sq = P.inv_w0sqf;
+            pf.inv_zR = P.inv_zRf;
+            const float a0S0f = (float)a0S0;
+            float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
+            // the part of g0 that the FP32 pair cannot hold, restored at the end
+            const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
+            float aS_prev = local ? P.a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
+            for (int j = 0; j < N; ++j) {
+                const float psi = fmaf((float)j, P.hf, P.psi0f);
+                float aSh = a0S0f, aS4 = a0S0f;
+                if (local) {
+                    aSh = P.a0f * pf.S(fmaf(0.5f, P.hf, psi) * P.ellf);
+                    aS4 = P.a0f * pf.S((psi + P.hf) * P.ellf);
+                }
+                const float a1 = aS_prev * P.env32[2 * j];
+                const float ah = aSh * P.env32[2 * j + 1];
+                const float a4 = aS4 * P.env32[2 * j + 2];
+                const float chi1 = phf.two_over_aS * mu * fabsf(a1);
+                cmx = fmaxf(cmx, chi1);
+                bool promote = false;
+                if (PREC == PREC_F32MIX) promote = __any(chi1 > P.chi_fp64);
+                if (promote) {
+                    // the whole wavefront runs this step in FP64 (uniform branch)
+                    const double psid = fma((double)j, P.h, -P.psi_max);
+                    double A1 = a0S0, Ah = a0S0, A4 = a0S0;
+                    if (local) {
+                        A1 = P.a0 * pd.S(psid * P.ell_per_psi);
+                        Ah = P.a0 * pd.S(fma(0.5, P.h, psid) * P.ell_per_psi);
+                        A4 = P.a0 * pd.S((psid + P.h) * P.ell_per_psi);
+                    }
+                    A1 *= P.env64[2 * j];
+                    Ah *= P.env64[2 * j + 1];
+                    A4 *= P.env64[2 * j + 2];
+                    const double mud = (double)mu + (double)mu_lo;
+                    const double s2d = (double)s2 + (double)s2_lo;
+                    double dm, ds;
+                    rk4_increment<double, QUANTUM>(mud, s2d, A1, Ah, A4, P.h, phd, tabd, dm, ds,
+                                                   flags);
+                    const double mn = mud + dm, sn = s2d + ds;
+                    mu = (float)mn;
+                    mu_lo = (float)(mn - (double)mu);
+                    s2 = (float)sn;
+                    s2_lo = (float)(sn - (double)s2);
+                } else {
+                    float dm, ds;
+                    rk4_increment<float, QUANTUM>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds,
+                                                  flags);
+                    comp_add(mu, mu_lo, dm);
+                    if (QUANTUM) comp_add(s2, s2_lo, ds);
+                }
+                aS_prev = aS4;
+            }
+            mu_f = ((double)mu + (double)mu_lo) + g0_rest;
+            s2_f = (double)s2 + (double)s2_lo;
+        }
+        {
+            // chi at the end of the last step (the pulse tail)
+            const double aN = (local ? P.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * P.env64[2 * N];
+            cmx = fmaxf(cmx, (float)(P.two_over_aS * mu_f * fabs(aN)));
+        }
+        P.st.mu[i] = mu_f;
+        P.st.s2[i] = s2_f;
+        P.st.S0[i] = S0;
+        P.st.g0[i] = g0;
+        P.st.thx[i] = thx;
+        P.st.thy[i] = thy;
+        P.st.cmx[i] = cmx;
+    }
+    if (flags) atomicOr(P.flags, flags);
+}
+
+// ===========================================================================
+// Deposit kernel: final states -> observables -> histograms and moments
+// ===========================================================================
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(kDepBlock) void deposit_kernel(DepParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);
+    const int nh_e = P.n_e + 2, nh_t = P.n_th + 2, nh = nh_e + nh_t + P.n_a;
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0ull;
+    __syncthreads();
+
+    double acc[P_N];
+#pragma unroll
+    for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
+    float chimax = 0.0f;
+    int flags = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n_samples; i += stride) {
+        const double mu_f = P.st.mu[i], s2_f = P.st.s2[i], S0 = P.st.S0[i], g0 = P.st.g0[i];
+        const double thx_m = 1e3 * P.st.thx[i], thy_m = 1e3 * P.st.thy[i];
+        const float cmx = P.st.cmx[i];
+        if (!isfinite(mu_f) || !isfinite(s2_f)) {
+            flags |= kFlagNonFinite;
+            continue;
+        }
+        chimax = fmaxf(chimax, cmx);
+        // Sec. 5.2: the direction is kept, the stochastic broadening
+        // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
+        const double sigf = sqrt(fmax(s2_f, 0.0));
+        const double a_eff = P.a0 * S0;
+        const double sigth = 1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
+
+        deposit_law(mu_f, sigf, P.deposit, P.ksig_bins, P.e_lo, P.e_w, P.n_e, hist);
+        deposit_law(thx_m, sigth, P.deposit, P.ksig_bins, P.th_lo, P.th_w, P.n_th, hist + nh_e);
+        {
+            int ka = (int)floor(S0 * (double)P.n_a);
+            ka = min(max(ka, 0), P.n_a - 1);
+            atomicAdd(&hist[nh_e + nh_t + ka], kOne);
+        }
+        const double de = mu_f - P.gamma0;
+        acc[P_S1E] += de;
+        acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
+        acc[P_S1X] += thx_m;
+        acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
+        acc[P_S1Y] += thy_m;
+        acc[P_S2Y] += thy_m * thy_m;
+        acc[P_SAEFF] += a_eff;
+        acc[P_SRAD] += 1.0 - mu_f / g0;
+        acc[P_SSIGF] += sigf;
+
+        if (P.rec != nullptr && i % P.rec_stride == 0 && i / P.rec_stride < P.rec_n) {
+            double *r = P.rec + (i / P.rec_stride) * 11;
+            r[0] = mu_f;
+            r[1] = s2_f;
+            r[2] = thx_m;
+            r[3] = thy_m;
+            r[4] = sigth;
+            r[5] = a_eff;
+            r[6] = cmx;
+            r[7] = g0;
+            r[8] = 0.0;
+            r[9] = 0.0;
+            r[10] = 0.0;
+        }
+    }
+
+    // ---- block reduction of moments (fixed order) ----
+    __shared__ double red[kDepBlock / 64][P_N];
+    __shared__ float redmax[kDepBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < P_N; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wid][m] = v;
+    }
+    const float wm = wave_max(chimax);
+    if (lane == 0) redmax[wid] = wm;
+    if (flags) atomicOr(P.flags, flags);
+    __syncthreads();
+    if (threadIdx.x < P_N) {
+        double s = 0.0;
+        for (int w = 0; w < kDepBlock / 64; ++w) s += red[w][threadIdx.x];
+        P.partials[(size_t)blockIdx.x * P_N + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
+        atomicMax(P.chimax_bits, __float_as_uint(m));
+    }
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+        const unsigned long long v = hist[k];
+        if (v) atomicAdd(&P.hist[k], v);
+    }
+}
+
+// ===========================================================================
+// Finalize: fixed-order reduction of the block partials, histogram scaling
+// ===========================================================================
+__global__ __launch_bounds__(256) void finalize_kernel(FinParams F) {
+    __shared__ double sums[P_N];
+    if (threadIdx.x < P_N) {
+        double s = 0.0;
+        for (int b = 0; b < F.nblocks; ++b) s += F.partials[(size_t)b * P_N + threadIdx.x];
+        sums[threadIdx.x] = s;
+    }
+    const int nh_e = F.n_e + 2, nh_t = F.n_th + 2;
+    const double scale = 1.0 / 4294967296.0;
+    for (int k = threadIdx.x; k < nh_e; k += blockDim.x)
+        F.energy_hist[k] = (double)F.hist[k] * scale;
+    for (int k = threadIdx.x; k < nh_t; k += blockDim.x)
+        F.angle_hist[k] = (double)F.hist[nh_e + k] * scale;
+    for (int k = threadIdx.x; k < F.n_a; k += blockDim.x)
+        F.a0eff_hist[k] = (double)F.hist[nh_e + nh_t + k] * scale;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *M = F.moments;
+        for (int m = 0; m < 16; ++m) M[m] = 0.0;
+        const double W = (double)F.n_samples;
+        M[0] = W;
+        if (F.n_samples > 0) {
+            const double m1 = sums[P_S1E] / W;
+            M[1] = F.gamma0 + m1;
+            M[2] = sqrt(fmax(sums[P_S2E] / W - m1 * m1, 0.0));
+            M[3] = sums[P_S1X] / W;
+            M[4] = sqrt(sums[P_S2X] / W);
+            M[5] = sums[P_S1Y] / W;
+            M[6] = sqrt(sums[P_S2Y] / W);
+            M[7] = sums[P_SAEFF] / W;
+            M[8] = (double)__uint_as_float(*F.chimax_bits);
+            M[9] = sums[P_SRAD] / W;
+            M[10] = sums[P_SSIGF] / W;
+        }
+        const int fl = *F.flags;
+        *F.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
+    }
+}
+
+// ===========================================================================
+// Set-up kernels: envelope x carrier table, zero fill
+// ===========================================================================
+__global__ void envelope_kernel(double psi_max, double h, int n_steps, int envelope,
+                                double omega_tau, float *env32, double *env64) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > 2 * n_steps) return;
+    const double psi = fma((double)k, 0.5 * h, -psi_max);
+    double f;
+    if (envelope == 0) {
+        const double u = psi / omega_tau;
+        f = exp(-2.0 * 0.69314718055994530942 * u * u);
+    } else {
+        if (fabs(psi) > omega_tau) {
+            f = 0.0;
+        } else {
+            const double s = sinpi((psi + omega_tau) / (2.0 * omega_tau));
+            f = s * s;
+        }
+    }
+    const double e = f * cos(psi);
+    env64[k] = e;
+    env32[k] = (float)e;
+}
+
+__global__ void zero_kernel(unsigned long long *p, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x)
+        p[k] = 0ull;
+}
+
+// ===========================================================================
+// Radiation-function tables.
+//
+// The LCFA photon emission rate per unit energy fraction xi is proportional
+// to (1 - xi + 1/(1 - xi)) K_{2/3}(y) - Int_y^inf K_{1/3}, y = 2 xi / (3 chi
+// (1 - xi)).  With the integral representations K_nu(y) = Int_0^inf
+// exp(-y cosh t) cosh(nu t) dt and Int_y^inf K_{1/3} = Int_0^inf exp(-y cosh t)
+// cosh(t/3) / cosh t dt,
+//   g(chi) = sqrt3/(2 pi chi^2) I_0,   h(chi) = 24/(55 pi chi^3) J_0,
+//   I_k = Int_0^1 dxi xi Int_0^inf dt (y cosh t)^k e^{-y cosh t}
+//         [w cosh(2t/3) - cosh(t/3)/cosh t],   J_0 likewise with xi^2,
+// where chi d/dchi acting on e^{-y cosh t} brings down y cosh t, so that
+//   chi g' = C (I_1 - 2 I_0),  chi^2 g'' = C (I_2 - 6 I_1 + 6 I_0),  C = sqrt3/(2 pi chi^2).
+// The t integrals depend on y only and are tabulated once on a y = e^v
+// grid; the xi integral is taken over v with xi = 3 chi y / (2 + 3 chi y).
+// Both rules are trapezoidal on doubly-exponentially decaying integrands.
+// Each table cell stores the cubic through the values at four Chebyshev
+// points of its local coordinate.
+// ===========================================================================
+constexpr double kVLo = -32.25;  // y from ~1e-14
+constexpr double kVHi = 4.125;   // to ~62
+constexpr double kDv = 1.0 / 16.0;
+constexpr int kNY = (int)((kVHi - kVLo) / kDv) + 1;
+constexpr double kDt = 1.0 / 16.0;
+
+__global__ void rad_y_kernel(double *yf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNY) return;
+    const double y = exp(kVLo + i * kDv);
+    const double tmax = acosh(fmax(60.0 / y, 1.0)) + kDt;
+    const int nt = (int)ceil(tmax / kDt);
+    double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0;
+    for (int m = 0; m <= nt; ++m) {
+        const double t = m * kDt;
+        const double c = cosh(t);
+        const double u = y * c;
+        const double e = exp(-u) * (m == 0 ? 0.5 : 1.0);
+        const double p = e * cosh(t * (2.0 / 3.0));
+        const double q = e * cosh(t * (1.0 / 3.0)) / c;
+        P0 += p;
+        P1 += u * p;
+        P2 += u * u * p;
+        Q0 += q;
+        Q1 += u * q;
+        Q2 += u * u * q;
+    }
+    double *o = yf + 6 * i;
+    o[0] = P0 * kDt;
+    o[1] = P1 * kDt;
+    o[2] = P2 * kDt;
+    o[3] = Q0 * kDt;
+    o[4] = Q1 * kDt;
+    o[5] = Q2 * kDt;
+}
+
+__device__ __forceinline__ double cell_chi(int cell, double t, int sb) {
+    if (cell == 0) return t * 0x1p-20;
+    const int c = cell - 1;
+    const int e = kEMin + (c >> sb);
+    const int sub = c & ((1 << sb) - 1);
+    return ldexp(1.0 + ((double)sub + t) / (double)(1 << sb), e);
+}
+
+__device__ __forceinline__ double cheb_node(int m) {
+    return 0.5 * (1.0 - cospi((2.0 * m + 1.0) / 8.0));
+}
+
+// vals[node][4] at the four Chebyshev nodes of every cell, cells of the
+// FP32 table first, then those of the FP64 table.
+__global__ void rad_node_kernel(const double *yf, double *vals) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = 4 * (kCells32 + kCells64);
+    if (node >= total) return;
+    const int cell_all = node >> 2, m = node & 3;
+    const bool t32 = cell_all < kCells32;
+    const int cell = t32 ? cell_all : cell_all - kCells32;
+    const double chi = cell_chi(cell, cheb_node(m), t32 ? kSB32 : kSB64);
+    double I0 = 0, I1 = 0, I2 = 0, J0 = 0;
+    for (int i = 0; i < kNY; ++i) {
+        const double y = exp(kVLo + i * kDv);
+        const double q = 2.0 + 3.0 * chi * y;
+        const double xi = 3.0 * chi * y / q;
+        const double w = 2.0 / q + 0.5 * q;
+        const double base = xi * (6.0 * chi / (q * q)) * y;  // xi dxi/dy dy/dv
+        const double *f = yf + 6 * i;
+        const double b0 = base * (w * f[0] - f[3]);
+        I0 += b0;
+        I1 += base * (w * f[1] - f[4]);
+        I2 += base * (w * f[2] - f[5]);
+        J0 += xi * b0;
+    }
+    I0 *= kDv;
+    I1 *= kDv;
+    I2 *= kDv;
+    J0 *= kDv;
+    const double C = 1.7320508075688772935 / (2.0 * 3.14159265358979323846 * chi * chi);
+    double *o = vals + 4 * node;
+    o[0] = C * I0;
+    o[1] = C * (I1 - 2.0 * I0);
+    o[2] = C * (I2 - 6.0 * I1 + 6.0 * I0);
+    o[3] = 24.0 / (55.0 * 3.14159265358979323846 * chi * chi * chi) * J0;
+}
+
+// Cubic through the four node values of each cell, in monomials of t.
+__global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64) {
+    const int cell_all = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell_all >= kCells32 + kCells64) return;
+    double tn[4];
+    for (int m = 0; m < 4; ++m) tn[m] = cheb_node(m);
+    double coef[4][4] = {};
+    for (int m = 0; m < 4; ++m) {
+        double r[3];
+        int k = 0;
+        double den = 1.0;
+        for (int n = 0; n < 4; ++n)
+            if (n != m) {
+                r[k++] = tn[n];
+                den *= tn[m] - tn[n];
+            }
+        // (t - r0)(t - r1)(t - r2) / den
+        const double l3 = 1.0 / den;
+        const double l2 = -(r[0] + r[1] + r[2]) / den;
+        const double l1 = (r[0] * r[1] + r[0] * r[2] + r[1] * r[2]) / den;
+        const double l0 = -(r[0] * r[1] * r[2]) / den;
+        for (int f = 0; f < 4; ++f) {
+            const double v = vals[4 * (4 * cell_all + m) + f];
+            coef[f][0] += v * l0;
+            coef[f][1] += v * l1;
+            coef[f][2] += v * l2;
+            coef[f][3] += v * l3;
+        }
+    }
+    if (cell_all < kCells32) {
+        for (int f = 0; f < 4; ++f)
+            for (int c = 0; c < 4; ++c) rad32[cell_all * kCellVals + 4 * f + c] = (float)coef[f][c];
+    } else {
+        const int cell = cell_all - kCells32;
+        for (int f = 0; f < 4; ++f)
+            for (int c = 0; c < 4; ++c) rad64[(size_t)cell * kCellVals + 4 * f + c] = coef[f][c];
+    }
+}
+
+__global__ void rad_eval_kernel(const float *rad32, const double *rad64, int prec, int64_t n,
+                                const double *chi, double *out, int *flags) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int fl = 0;
+    if (prec == 0) {
+        float g, G1, G2, h;
+        rad_eval32(rad32, (float)chi[k], g, G1, G2, h, fl);
+        out[4 * k] = g;
+        out[4 * k + 1] = G1;
+        out[4 * k + 2] = G2;
+        out[4 * k + 3] = h;
+    } else {
+        double g, G1, G2, h;
+        rad_eval64(rad64, chi[k], g, G1, G2, h, fl);
+        out[4 * k] = g;
+        out[4 * k + 1] = G1;
+        out[4 * k + 2] = G2;
+        out[4 * k + 3] = h;
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+size_t radiation_work_doubles() { return (size_t)kNY * 6 + (size_t)4 * 4 * (kCells32 + kCells64); }
+
+hipError_t build_radiation_tables(float *rad32, double *rad64, double *work, size_t work_doubles,
+                                  hipStream_t s) {
+    if (work_doubles < radiation_work_doubles()) return hipErrorInvalidValue;
+    double *yf = work, *vals = work + (size_t)kNY * 6;
+    rad_y_kernel<<<(kNY + 63) / 64, 64, 0, s>>>(yf);
+    const int nodes = 4 * (kCells32 + kCells64);
+    rad_node_kernel<<<(nodes + 63) / 64, 64, 0, s>>>(yf, vals);
+    const int cells = kCells32 + kCells64;
+    rad_coef_kernel<<<(cells + 63) / 64, 64, 0, s>>>(vals, rad32, rad64);
+    return hipGetLastError();
+}
+
+hipError_t launch_envelope(double psi_max, double h, int n_steps, int envelope, double omega_tau,
+                           float *env32, double *env64, hipStream_t s) {
+    const int n = 2 * n_steps + 1;
+    envelope_kernel<<<(n + 255) / 256, 256, 0, s>>>(psi_max, h, n_steps, envelope, omega_tau,
+                                                    env32, env64);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(unsigned long long *p, size_t n64, hipStream_t s) {
+    if (n64 == 0) return hipSuccess;
+    const int grid = (int)((n64 + 255) / 256 < 1024 ? (n64 + 255) / 256 : 1024);
+    zero_kernel<<<grid, 256, 0, s>>>(p, n64);
+    return hipGetLastError();
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+static const void *phase_ptr() {
+    return reinterpret_cast<const void *>(&phase_kernel<PREC, QUANTUM, LOCAL>);
+}
+
+static const void *select_phase(int prec, int rr, int amp) {
+    const bool q = rr == 1, l = amp == 1;
+    if (prec == PREC_F32MIX && !q) prec = PREC_F32;  // no radiation table, no promotion
+#define QS_SEL(P)                                              \
+    if (prec == P) {                                           \
+        if (q && l) return phase_ptr<P, true, true>();         \
+        if (q && !l) return phase_ptr<P, true, false>();       \
+        if (!q && l) return phase_ptr<P, false, true>();       \
+        return phase_ptr<P, false, false>();                   \
+    }
+    QS_SEL(PREC_F32)
+    QS_SEL(PREC_F64)
+    if (prec == PREC_F32MIX) {
+        if (l) return phase_ptr<PREC_F32MIX, true, true>();
+        return phase_ptr<PREC_F32MIX, true, false>();
+    }
+#undef QS_SEL
+    return nullptr;
+}
+
+hipError_t launch_phase(const PhaseParams &p, int prec, int rr, int amp, hipStream_t s) {
+    const void *fn = select_phase(prec, rr, amp);
+    if (!fn) return hipErrorInvalidValue;
+    int device = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPhaseBlock, 0);
+    if (e != hipSuccess) return e;
+    // enough resident blocks to fill the chip; each lane takes samples in a grid stride
+    int64_t grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
+    const int64_t need = (p.n_samples + kPhaseBlock - 1) / kPhaseBlock;
+    if (grid > need) grid = need;
+    PhaseParams pc = p;
+    void *args[] = {&pc};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+}
+
+size_t deposit_lds_bytes(int n_e, int n_th, int n_a) { return (size_t)(n_e + 2 + n_th + 2 + n_a) * 8; }
+
+hipError_t deposit_grid(size_t lds_bytes, int device, int64_t n_samples, int *grid) {
+    const void *fn = reinterpret_cast<const void *>(&deposit_kernel);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, ncu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kDepBlock, lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    int64_t g = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
+    const int64_t need = (n_samples + kDepBlock - 1) / kDepBlock;
+    if (g > need) g = need;
+    *grid = (int)g;
+    return hipSuccess;
+}
+
+hipError_t launch_deposit(const DepParams &p, int grid, hipStream_t s) {
+    const size_t lds = deposit_lds_bytes(p.n_e, p.n_th, p.n_a);
+    deposit_kernel<<<grid, kDepBlock, lds, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinParams &p, hipStream_t s) {
+    finalize_kernel<<<1, 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int prec, int64_t n,
+                                 const double *chi, double *out, int *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    rad_eval_kernel<<<(unsigned)blocks, 256, 0, s>>>(rad32, rad64, prec, n, chi, out, flags);
+    return hipGetLastError();
+}
+
+}  // namespace qs
