@@ -72,22 +72,16 @@ __device__ __forceinline__ void sample_normals(uint32_t i, uint32_t shot, uint32
 // Radiation functions: g, chi g', chi^2 g'', h from per-cell cubics
 // ===========================================================================
 __device__ __forceinline__ void rad_eval32(const float *__restrict__ tab, float chi, float &g,
-                                           float &G1, float &G2, float &hq, int &flags) {
+                                           float &G1, float &G2, float &hq) {
+    // exponent and the top kSB32 mantissa bits give the cell directly
     const uint32_t b = __float_as_uint(chi);
-    const int e = (int)(b >> 23) - 127;
-    const int sub = (int)((b >> (23 - kSB32)) & ((1u << kSB32) - 1));
-    const float tf = (float)(b & ((1u << (23 - kSB32)) - 1)) * (1.0f / (float)(1u << (23 - kSB32)));
-    int c = 1 + ((e - kEMin) << kSB32) + sub;
-    float t = tf;
-    if (e < kEMin) {
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    float t = __uint_as_float(((b & ((1u << (23 - kSB32)) - 1)) << kSB32) | 0x3f800000u) - 1.0f;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
         c = 0;
-        t = chi * 0x1p20f;  // chi / 2^kEMin
+        t = chi * 0x1p20f;
     }
-    if (e > kEMax) {
-        c = kCells32 - 1;
-        t = 1.0f;
-        flags |= kFlagRange;
-    }
+    c = min(c, kCells32 - 1);  // chi >= 2^(kEMax+1) is reported by the caller
     const float4 *cell = reinterpret_cast<const float4 *>(tab + c * kCellVals);
     const float4 q0 = cell[0], q1 = cell[1], q2 = cell[2], q3 = cell[3];
     g = fmaf(t, fmaf(t, fmaf(t, q0.w, q0.z), q0.y), q0.x);
@@ -97,22 +91,16 @@ __device__ __forceinline__ void rad_eval32(const float *__restrict__ tab, float 
 }
 
 __device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
-                                           double &G1, double &G2, double &hq, int &flags) {
+                                           double &G1, double &G2, double &hq) {
     const uint64_t b = (uint64_t)__double_as_longlong(chi);
-    const int e = (int)(b >> 52) - 1023;
-    const int sub = (int)((b >> (52 - kSB64)) & ((1ull << kSB64) - 1));
-    const double tf = (double)(b & ((1ull << (52 - kSB64)) - 1)) * (1.0 / (double)(1ull << (52 - kSB64)));
-    int c = 1 + ((e - kEMin) << kSB64) + sub;
-    double t = tf;
-    if (e < kEMin) {
+    int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
+    double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
+                                                0x3ff0000000000000ull)) - 1.0;
+    if (c < 1) {
         c = 0;
         t = chi * 0x1p20;
     }
-    if (e > kEMax) {
-        c = kCells64 - 1;
-        t = 1.0;
-        flags |= kFlagRange;
-    }
+    c = c < kCells64 - 1 ? c : kCells64 - 1;
     const double *q = tab + (size_t)c * kCellVals;
     g = fma(t, fma(t, fma(t, q[3], q[2]), q[1]), q[0]);
     G1 = fma(t, fma(t, fma(t, q[7], q[6]), q[5]), q[4]);
@@ -125,17 +113,16 @@ struct RadTab;
 template <>
 struct RadTab<float> {
     const float *p;
-    __device__ __forceinline__ void eval(float chi, float &g, float &G1, float &G2, float &h,
-                                         int &f) const {
-        rad_eval32(p, chi, g, G1, G2, h, f);
+    __device__ __forceinline__ void eval(float chi, float &g, float &G1, float &G2, float &h) const {
+        rad_eval32(p, chi, g, G1, G2, h);
     }
 };
 template <>
 struct RadTab<double> {
     const double *p;
-    __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2, double &h,
-                                         int &f) const {
-        rad_eval64(p, chi, g, G1, G2, h, f);
+    __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2,
+                                         double &h) const {
+        rad_eval64(p, chi, g, G1, G2, h);
     }
 };
 
@@ -153,7 +140,7 @@ struct Phys {
 
 template <class T, bool QUANTUM>
 __device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const RadTab<T> &tab,
-                                    T &dmu, T &ds2, int &flags) {
+                                    T &dmu, T &ds2, T &chi_hi) {
     const T a2 = a * a;
     const T Ka2 = ph.K * a2;
     if (!QUANTUM) {
@@ -163,8 +150,9 @@ __device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const Ra
     }
     const T aa = fabs(a);
     const T chi = ph.two_over_aS * mu * aa;
+    chi_hi = fmax(chi_hi, chi);
     T g, G1, G2, hq;
-    tab.eval(chi, g, G1, G2, hq, flags);
+    tab.eval(chi, g, G1, G2, hq);
     const T two_g = T(2) * g;
     const T A = -Ka2 * mu * mu * g;
     const T A1 = -Ka2 * mu * (two_g + G1);
@@ -175,13 +163,16 @@ __device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const Ra
     ds2 = fma(T(2) * A1, s2, D);
 }
 
-// Spatial factor a/a0 of eq. a0eff at (x, y, z) [um].
+// Spatial factor a/a0 of eq. a0eff at (x, y, z) [um].  The FP32 version uses
+// the hardware reciprocal, reciprocal square root and base-2 exponential
+// (about one ulp each; the exponent's argument rounding adds |r2/q| ulps,
+// which matters only where the factor itself is small).
 __device__ __forceinline__ float spatial(float x, float y, float z, float inv_w0sq, float inv_zR) {
     const float zz = z * inv_zR;
     const float q = fmaf(zz, zz, 1.0f);
-    const float iq = 1.0f / q;
+    const float iq = __builtin_amdgcn_rcpf(q);
     const float r2 = fmaf(x, x, y * y) * inv_w0sq;
-    return expf(-r2 * iq) * sqrtf(iq);
+    return __builtin_amdgcn_exp2f(-1.4426950408889634f * r2 * iq) * __builtin_amdgcn_rsqf(q);
 }
 __device__ __forceinline__ double spatial(double x, double y, double z, double inv_w0sq,
                                           double inv_zR) {
@@ -207,13 +198,13 @@ struct Path {
 template <class T, bool QUANTUM>
 __device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
                                               const Phys<T> &ph, const RadTab<T> &tab, T &dmu,
-                                              T &ds2, int &flags) {
+                                              T &ds2, T &chi_hi) {
     const T hh = T(0.5) * h;
     T k1m, k1s, k2m, k2s, k3m, k3s, k4m, k4s;
-    rhs<T, QUANTUM>(mu, s2, a1, ph, tab, k1m, k1s, flags);
-    rhs<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, flags);
-    rhs<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, flags);
-    rhs<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, flags);
+    rhs<T, QUANTUM>(mu, s2, a1, ph, tab, k1m, k1s, chi_hi);
+    rhs<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, chi_hi);
+    rhs<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, chi_hi);
+    rhs<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, chi_hi);
     const T h6 = h * T(1.0 / 6.0);
     dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
     ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
@@ -232,11 +223,6 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float d) {
 // ===========================================================================
 constexpr unsigned long long kOne = 1ull << 32;
 
-__device__ __forceinline__ double Phi(double t) { return 0.5 * erfc(-t * 0.70710678118654752440); }
-__device__ __forceinline__ double PhiC(double t) { return 0.5 * erfc(t * 0.70710678118654752440); }
-__device__ __forceinline__ double phi(double t) {
-    return exp(-0.5 * t * t) * 0.39894228040143267794;
-}
 
 __device__ __forceinline__ void ngp(double v, double lo, double w, int n,
                                     unsigned long long *h) {
@@ -255,7 +241,29 @@ __device__ __forceinline__ void ngp(double v, double lo, double w, int n,
 // N(v, s^2)) convolved with the deposit kernel (POINT: none; CIC: a box one
 // bin wide; GAUSS: N(0, (ksig bins)^2)).  Bin masses are differences of the
 // law's CDF at the bin edges, quantised to 2^-32 so that every sample adds
-// exactly 2^32; beyond 8 standard deviations the CDF is taken as 0 or 1.
+// exactly 2^32; beyond 6 standard deviations the CDF is taken as 0 or 1 (the
+// neglected mass, 2e-9 a sample, goes to the edge bins of the window).  The
+// CDF is evaluated in FP32 on whichever side of v keeps it small (erfc of
+// the tail), so its error is a few ulps of the smaller tail mass.  For the
+// box (x) Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x
+// Phi(u/s) du at the two box ends, and consecutive edges share one end.
+struct PsiPair {
+    float P, Pc;  // Psi(x) and Psi(x) - x
+};
+__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s) {
+    const float zz = x * inv_s;
+    const float ph = s * 0.39894228040143267794f * expf(-0.5f * zz * zz);
+    PsiPair r;
+    if (zz <= 0.0f) {
+        r.P = fmaf(x, 0.5f * erfcf(-zz * 0.70710678118654752440f), ph);
+        r.Pc = r.P - x;
+    } else {
+        r.Pc = fmaf(-x, 0.5f * erfcf(zz * 0.70710678118654752440f), ph);
+        r.P = r.Pc + x;
+    }
+    return r;
+}
+
 __device__ void deposit_law(double v, double s, int dep, double ksig, double lo, double w, int n,
                             unsigned long long *h) {
     const double half = 0.5 * w;
@@ -274,7 +282,7 @@ __device__ void deposit_law(double v, double s, int dep, double ksig, double lo,
         ngp(v, lo, w, n, h);
         return;
     }
-    const double reach = mode == 1 ? half : (mode == 2 ? 8.0 * se : 8.0 * se + half);
+    const double reach = mode == 1 ? half : (mode == 2 ? 6.0 * se : 6.0 * se + half);
     int ka = (int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0);
     int kb = (int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0);
     ka = max(ka, 0);
@@ -283,30 +291,27 @@ __device__ void deposit_law(double v, double s, int dep, double ksig, double lo,
         ngp(v, lo, w, n, h);  // the whole law lies inside one bin (or outside)
         return;
     }
-    const double inv_se = mode >= 2 ? 1.0 / se : 0.0;
+    const float sf = (float)se, inv_s = mode >= 2 ? (float)(1.0 / se) : 0.0f;
+    const float wf = (float)w, inv_w = (float)(1.0 / w), hf = (float)half;
+    PsiPair lower{0.0f, 0.0f};
+    if (mode == 3) lower = psi_pair((float)(fma((double)ka, w, lo) - v) - hf, sf, inv_s);
     unsigned long long qprev = 0;
     for (int k = ka; k <= kb; ++k) {
-        const double t = fma((double)k, w, lo) - v;
-        double F;
-        bool upper = t > 0.0;
+        const float t = (float)(fma((double)k, w, lo) - v);  // edge - v
+        const bool upper = t > 0.0f;  // F is taken from the upper tail there
+        float F;
         if (mode == 1) {
-            F = upper ? fmin(fmax(0.5 - t / w, 0.0), 1.0) : fmin(fmax(t / w + 0.5, 0.0), 1.0);
+            F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
         } else if (mode == 2) {
-            F = upper ? PhiC(t * inv_se) : Phi(t * inv_se);
+            F = 0.5f * erfcf((upper ? t : -t) * inv_s * 0.70710678118654752440f);
         } else {
-            const double ta = t - half, tb = t + half;
-            if (upper) {
-                const double pa = -ta * PhiC(ta * inv_se) + se * phi(ta * inv_se);
-                const double pb = -tb * PhiC(tb * inv_se) + se * phi(tb * inv_se);
-                F = (pa - pb) / w;
-            } else {
-                const double pa = ta * Phi(ta * inv_se) + se * phi(ta * inv_se);
-                const double pb = tb * Phi(tb * inv_se) + se * phi(tb * inv_se);
-                F = (pb - pa) / w;
-            }
+            const PsiPair up = psi_pair(t + hf, sf, inv_s);
+            F = upper ? (lower.Pc - up.Pc) * inv_w : (up.P - lower.P) * inv_w;
+            lower = up;
         }
-        F = fmin(fmax(F, 0.0), 1.0);
-        const unsigned long long qf = (unsigned long long)llrint(F * 4294967296.0);
+        (void)wf;
+        F = fminf(fmaxf(F, 0.0f), 1.0f);
+        const unsigned long long qf = (unsigned long long)llrintf(F * 4294967296.0f);
         unsigned long long q = upper ? kOne - qf : qf;
         q = q < qprev ? qprev : q;
         const int bin = k == 0 ? n : k - 1;  // mass between edge k-1 and edge k
@@ -320,8 +325,13 @@ __device__ void deposit_law(double v, double s, int dep, double ksig, double lo,
 // ===========================================================================
 // Phase kernel: sample -> ballistic path -> RK4 phase loop -> final state
 // ===========================================================================
+// The envelope tables come as separate restrict-qualified arguments: the
+// kernel never writes them, so the compiler reads them with scalar loads
+// (every lane of a wavefront is at the same phase step).
 template <int PREC, bool QUANTUM, bool LOCAL>
-__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
+__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P,
+                                                            const float *__restrict__ env32,
+                                                            const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     if (kTab32) {
@@ -336,6 +346,7 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
     const Phys<double> phd{P.K, P.CD, P.two_over_aS};
     const int N = P.n_steps;
     const bool local = LOCAL && !P.plane_wave;
+    const float chi_top = (float)(1 << (kEMax + 1));  // end of the tabulated range
     int flags = 0;
 
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -361,9 +372,10 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
         const double a0S0 = P.a0 * S0;
 
         double mu_f, s2_f;
-        float cmx = 0.0f;  // largest chi at a step start for this sample
+        float cmx = 0.0f;     // largest chi at a step start for this sample
+        float chi_hi = 0.0f;  // largest chi at any stage (range check)
         if (PREC == PREC_F64) {
-            double mu = g0, s2 = 0.0;
+            double mu = g0, s2 = 0.0, chd = 0.0;
             double aS_prev = local ? P.a0 * pd.S(-P.psi_max * P.ell_per_psi) : a0S0;
             for (int j = 0; j < N; ++j) {
                 const double psi = fma((double)j, P.h, -P.psi_max);
@@ -372,18 +384,19 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
                     aSh = P.a0 * pd.S(fma(0.5, P.h, psi) * P.ell_per_psi);
                     aS4 = P.a0 * pd.S((psi + P.h) * P.ell_per_psi);
                 }
-                const double a1 = aS_prev * P.env64[2 * j];
-                const double ah = aSh * P.env64[2 * j + 1];
-                const double a4 = aS4 * P.env64[2 * j + 2];
+                const double a1 = aS_prev * env64[2 * j];
+                const double ah = aSh * env64[2 * j + 1];
+                const double a4 = aS4 * env64[2 * j + 2];
                 cmx = fmaxf(cmx, (float)(P.two_over_aS * mu * fabs(a1)));
                 double dm, ds;
-                rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, flags);
+                rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, chd);
                 mu += dm;
                 s2 += ds;
                 aS_prev = aS4;
             }
             mu_f = mu;
             s2_f = s2;
+            chi_hi = (float)chd;
         } else {
             Path<float> pf;
             pf.xc = (float)pd.xc;
@@ -397,6 +410,7 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
             float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
             // the part of g0 that the FP32 pair cannot hold, restored at the end
             const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
+            double chd = 0.0;
             float aS_prev = local ? P.a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
             for (int j = 0; j < N; ++j) {
                 const float psi = fmaf((float)j, P.hf, P.psi0f);
@@ -405,9 +419,9 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
                     aSh = P.a0f * pf.S(fmaf(0.5f, P.hf, psi) * P.ellf);
                     aS4 = P.a0f * pf.S((psi + P.hf) * P.ellf);
                 }
-                const float a1 = aS_prev * P.env32[2 * j];
-                const float ah = aSh * P.env32[2 * j + 1];
-                const float a4 = aS4 * P.env32[2 * j + 2];
+                const float a1 = aS_prev * env32[2 * j];
+                const float ah = aSh * env32[2 * j + 1];
+                const float a4 = aS4 * env32[2 * j + 2];
                 const float chi1 = phf.two_over_aS * mu * fabsf(a1);
                 cmx = fmaxf(cmx, chi1);
                 bool promote = false;
@@ -421,14 +435,14 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
                         Ah = P.a0 * pd.S(fma(0.5, P.h, psid) * P.ell_per_psi);
                         A4 = P.a0 * pd.S((psid + P.h) * P.ell_per_psi);
                     }
-                    A1 *= P.env64[2 * j];
-                    Ah *= P.env64[2 * j + 1];
-                    A4 *= P.env64[2 * j + 2];
+                    A1 *= env64[2 * j];
+                    Ah *= env64[2 * j + 1];
+                    A4 *= env64[2 * j + 2];
                     const double mud = (double)mu + (double)mu_lo;
                     const double s2d = (double)s2 + (double)s2_lo;
                     double dm, ds;
                     rk4_increment<double, QUANTUM>(mud, s2d, A1, Ah, A4, P.h, phd, tabd, dm, ds,
-                                                   flags);
+                                                   chd);
                     const double mn = mud + dm, sn = s2d + ds;
                     mu = (float)mn;
                     mu_lo = (float)(mn - (double)mu);
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
                 } else {
                     float dm, ds;
                     rk4_increment<float, QUANTUM>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds,
-                                                  flags);
+                                                  chi_hi);
                     comp_add(mu, mu_lo, dm);
                     if (QUANTUM) comp_add(s2, s2_lo, ds);
                 }
@@ -445,12 +459,15 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P) {
             }
             mu_f = ((double)mu + (double)mu_lo) + g0_rest;
             s2_f = (double)s2 + (double)s2_lo;
+            chi_hi = fmaxf(chi_hi, (float)chd);
         }
         {
             // chi at the end of the last step (the pulse tail)
-            const double aN = (local ? P.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * P.env64[2 * N];
+            const double aN = (local ? P.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * env64[2 * N];
             cmx = fmaxf(cmx, (float)(P.two_over_aS * mu_f * fabs(aN)));
         }
+        if (QUANTUM && !(chi_hi < chi_top)) flags |= kFlagRange;
+        if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) flags |= kFlagNonFinite;
         P.st.mu[i] = mu_f;
         P.st.s2[i] = s2_f;
         P.st.S0[i] = S0;
@@ -493,8 +510,8 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(DepParams P) {
         const double mu_f = P.st.mu[i], s2_f = P.st.s2[i], S0 = P.st.S0[i], g0 = P.st.g0[i];
         const double thx_m = 1e3 * P.st.thx[i], thy_m = 1e3 * P.st.thy[i];
         const float cmx = P.st.cmx[i];
-        if (!isfinite(mu_f) || !isfinite(s2_f)) {
-            flags |= kFlagNonFinite;
+        if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
+            flags |= kFlagNonFinite;  // also raised by the phase kernel
             continue;
         }
         chimax = fmaxf(chimax, cmx);
@@ -786,17 +803,17 @@ __global__ void rad_eval_kernel(const float *rad32, const double *rad64, int pre
                                 const double *chi, double *out, int *flags) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    int fl = 0;
+    const int fl = (chi[k] < (double)(1 << (kEMax + 1))) ? 0 : kFlagRange;
     if (prec == 0) {
         float g, G1, G2, h;
-        rad_eval32(rad32, (float)chi[k], g, G1, G2, h, fl);
+        rad_eval32(rad32, (float)chi[k], g, G1, G2, h);
         out[4 * k] = g;
         out[4 * k + 1] = G1;
         out[4 * k + 2] = G2;
         out[4 * k + 3] = h;
     } else {
         double g, G1, G2, h;
-        rad_eval64(rad64, chi[k], g, G1, G2, h, fl);
+        rad_eval64(rad64, chi[k], g, G1, G2, h);
         out[4 * k] = g;
         out[4 * k + 1] = G1;
         out[4 * k + 2] = G2;
@@ -875,7 +892,9 @@ hipError_t launch_phase(const PhaseParams &p, int prec, int rr, int amp, hipStre
     const int64_t need = (p.n_samples + kPhaseBlock - 1) / kPhaseBlock;
     if (grid > need) grid = need;
     PhaseParams pc = p;
-    void *args[] = {&pc};
+    const float *e32 = p.env32;
+    const double *e64 = p.env64;
+    void *args[] = {&pc, &e32, &e64};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
