@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this size (the "
+                         "reference kernel for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -128,6 +131,14 @@ def main():
                      "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
                                                              params["amp_mode"])]},
     }
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = nb
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
     print(json.dumps(line), flush=True)

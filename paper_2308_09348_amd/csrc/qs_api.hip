@@ -289,6 +289,14 @@ qs_status qs_forward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_nu
     p.n_steps = N->n_steps;
     p.shot = N->shot;
     p.plane_wave = plane_wave ? 1 : 0;
+    {
+        // the quadratic midpoint of the spatial factor is used only when one
+        // phase step moves a sample much less than the focal scales
+        const double step_um = h * p.ell_per_psi;
+        const double scale = plane_wave ? 0.0
+                                        : std::fmax(p.inv_zR, 6.0 * p.div_rad / L->w0_um);
+        p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
+    }
     p.key0 = (uint32_t)N->seed;
     p.key1 = (uint32_t)(N->seed >> 32);
     p.n_samples = n;

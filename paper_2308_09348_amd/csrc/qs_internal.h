@@ -12,7 +12,9 @@ namespace qs {
 // coordinate t in [0, 1).  Cell 0 covers chi in [0, 2^kEMin); cell
 // 1 + (e - kEMin) * 2^SB + s covers the s-th of 2^SB equal sub-intervals of
 // the octave [2^e, 2^(e+1)), e = kEMin .. kEMax.  Each cell holds 16 values:
-// four functions x four monomial coefficients (t^0 .. t^3).
+// four functions x four monomial coefficients (t^0 .. t^3).  The FP32 table is
+// function-major ([function][cell][power]), the FP64 table cell-major
+// ([cell][function][power]).
 constexpr int kEMin = -20;
 constexpr int kEMax = 7;
 constexpr int kSB32 = 4;  // FP32 table: 16 sub-cells per octave (LDS resident)
@@ -63,7 +65,8 @@ struct PhaseParams {
     double two_over_aS, K, CD, psi_max, h;
     // FP32 copies (FP32 steps)
     float a0f, inv_w0sqf, inv_zRf, ellf, two_over_aSf, Kf, CDf, psi0f, hf, chi_fp64;
-    int32_t n_steps, shot, plane_wave, pad_;
+    int32_t n_steps, shot, plane_wave;
+    int32_t mid_interp;   // stage-2/3 spatial factor by quadratic interpolation
     uint32_t key0, key1;
     int64_t n_samples;
     const float *env32;   // [2 n_steps + 1] envelope x carrier at psi_k = -psi_max + k h/2

@@ -82,12 +82,61 @@ __device__ __forceinline__ void rad_eval32(const float *__restrict__ tab, float 
         t = chi * 0x1p20f;
     }
     c = min(c, kCells32 - 1);  // chi >= 2^(kEMax+1) is reported by the caller
-    const float4 *cell = reinterpret_cast<const float4 *>(tab + c * kCellVals);
-    const float4 q0 = cell[0], q1 = cell[1], q2 = cell[2], q3 = cell[3];
+    // function-major layout: four arrays of 16-byte cubics, so that the cells
+    // read by one wavefront start on eight different 4-bank groups of LDS
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+    const float4 q0 = T[c], q1 = T[kCells32 + c], q2 = T[2 * kCells32 + c],
+                 q3 = T[3 * kCells32 + c];
     g = fmaf(t, fmaf(t, fmaf(t, q0.w, q0.z), q0.y), q0.x);
     G1 = fmaf(t, fmaf(t, fmaf(t, q1.w, q1.z), q1.y), q1.x);
     G2 = fmaf(t, fmaf(t, fmaf(t, q2.w, q2.z), q2.y), q2.x);
     hq = fmaf(t, fmaf(t, fmaf(t, q3.w, q3.z), q3.y), q3.x);
+}
+
+// One FP32 table cell held in registers.  Any chi near the cell maps to
+// its local coordinate by t = chi * tw + ts; the RK4 stages that share a
+// phase with the previous lookup (stage 3 after stage 2, the next step's
+// stage 1 after stage 4) evaluate the same cubics a hair outside [0, 1]
+// instead of reading LDS again.
+struct RadCell32 {
+    float4 q0, q1, q2, q3;
+    float tw, ts;
+};
+
+__device__ __forceinline__ void rad_lookup32(const float *__restrict__ tab, float chi,
+                                             RadCell32 &cell) {
+    const uint32_t b = __float_as_uint(chi);
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    // cell start 2^e (1 + sub/2^SB) and inverse width 2^(SB - e)
+    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
+        c = 0;
+        tw = 0x1p20f;
+        ts = 0.0f;
+    }
+    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
+        c = kCells32 - 1;
+        tw = 0.0f;
+        ts = 1.0f;
+    }
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+    cell.q0 = T[c];
+    cell.q1 = T[kCells32 + c];
+    cell.q2 = T[2 * kCells32 + c];
+    cell.q3 = T[3 * kCells32 + c];
+    cell.tw = tw;
+    cell.ts = ts;
+}
+
+__device__ __forceinline__ void rad_cell_eval(const RadCell32 &cell, float chi, float &g,
+                                              float &G1, float &G2, float &hq) {
+    // returns the four table functions of the cell (see rhs_q32)
+    const float t = fmaf(chi, cell.tw, cell.ts);
+    g = fmaf(t, fmaf(t, fmaf(t, cell.q0.w, cell.q0.z), cell.q0.y), cell.q0.x);
+    G1 = fmaf(t, fmaf(t, fmaf(t, cell.q1.w, cell.q1.z), cell.q1.y), cell.q1.x);
+    G2 = fmaf(t, fmaf(t, fmaf(t, cell.q2.w, cell.q2.z), cell.q2.y), cell.q2.x);
+    hq = fmaf(t, fmaf(t, fmaf(t, cell.q3.w, cell.q3.z), cell.q3.y), cell.q3.x);
 }
 
 __device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
@@ -170,9 +219,9 @@ __device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const Ra
 __device__ __forceinline__ float spatial(float x, float y, float z, float inv_w0sq, float inv_zR) {
     const float zz = z * inv_zR;
     const float q = fmaf(zz, zz, 1.0f);
-    const float iq = __builtin_amdgcn_rcpf(q);
+    const float rq = __builtin_amdgcn_rsqf(q);  // 1/sqrt(q); 1/q = rq^2
     const float r2 = fmaf(x, x, y * y) * inv_w0sq;
-    return __builtin_amdgcn_exp2f(-1.4426950408889634f * r2 * iq) * __builtin_amdgcn_rsqf(q);
+    return __builtin_amdgcn_exp2f(-1.4426950408889634f * r2 * (rq * rq)) * rq;
 }
 __device__ __forceinline__ double spatial(double x, double y, double z, double inv_w0sq,
                                           double inv_zR) {
@@ -208,6 +257,65 @@ __device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
     const T h6 = h * T(1.0 / 6.0);
     dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
     ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+}
+
+// Moment right-hand side (quantum model) from the FP32 table's combined
+// functions at chi = two_over_aS mu |a|:  T1 = g,  T2 = 2g + chi g',
+// T3 = g + 2 chi g' + chi^2 g''/2,  T4 = h, so that
+//   dmu/dpsi   = -K a^2 (mu^2 T1 + sig2 T3),
+//   dsig2/dpsi = -2 K a^2 mu sig2 T2 + C_D a^2 |a| mu^4 T4.
+__device__ __forceinline__ void rhs_q32(float mu, float s2, float a2, float aa, float T1, float T2,
+                                        float T3, float T4, const Phys<float> &ph, float &dmu,
+                                        float &ds2) {
+    const float u = ph.K * a2;
+    const float mu2 = mu * mu;
+    dmu = -u * fmaf(mu2, T1, s2 * T3);
+    const float D = (ph.CD * aa) * a2 * (mu2 * mu2) * T4;
+    ds2 = fmaf(-2.0f * u * mu * s2, T2, D);
+}
+
+// One FP32 RK4 step of the quantum moment system with two table reads:
+// stage 2 and stage 4 read LDS, stage 3 reuses stage 2's cell, and stage 4's
+// cell is handed to the next step's stage 1.
+__device__ __forceinline__ void rk4_q32(float mu, float s2, float a1, float ah, float a4, float h,
+                                        const Phys<float> &ph, const float *__restrict__ tab,
+                                        RadCell32 &carry, float &dmu, float &ds2,
+                                        float &chi_hi) {
+    const float hh = 0.5f * h;
+    float g, G1, G2, hq;
+    // stage 1 (cell carried from the previous stage 4)
+    const float aa1 = fabsf(a1), a21 = a1 * a1;
+    const float c1 = ph.two_over_aS * mu * aa1;
+    rad_cell_eval(carry, c1, g, G1, G2, hq);
+    float k1m, k1s;
+    rhs_q32(mu, s2, a21, aa1, g, G1, G2, hq, ph, k1m, k1s);
+    // stage 2 (table read)
+    const float aah = fabsf(ah), a2h = ah * ah;
+    const float m2 = fmaf(hh, k1m, mu), s22 = fmaf(hh, k1s, s2);
+    const float c2 = ph.two_over_aS * m2 * aah;
+    RadCell32 mid;
+    rad_lookup32(tab, c2, mid);
+    rad_cell_eval(mid, c2, g, G1, G2, hq);
+    float k2m, k2s;
+    rhs_q32(m2, s22, a2h, aah, g, G1, G2, hq, ph, k2m, k2s);
+    // stage 3 (same phase as stage 2: reuse its cell)
+    const float m3 = fmaf(hh, k2m, mu), s23 = fmaf(hh, k2s, s2);
+    const float c3 = ph.two_over_aS * m3 * aah;
+    rad_cell_eval(mid, c3, g, G1, G2, hq);
+    float k3m, k3s;
+    rhs_q32(m3, s23, a2h, aah, g, G1, G2, hq, ph, k3m, k3s);
+    // stage 4 (table read; its cell serves the next step's stage 1)
+    const float aa4 = fabsf(a4), a24 = a4 * a4;
+    const float m4 = fmaf(h, k3m, mu), s24 = fmaf(h, k3s, s2);
+    const float c4 = ph.two_over_aS * m4 * aa4;
+    rad_lookup32(tab, c4, carry);
+    rad_cell_eval(carry, c4, g, G1, G2, hq);
+    float k4m, k4s;
+    rhs_q32(m4, s24, a24, aa4, g, G1, G2, hq, ph, k4m, k4s);
+    chi_hi = fmaxf(chi_hi, fmaxf(fmaxf(c1, c2), fmaxf(c3, c4)));
+    const float h6 = h * (1.0f / 6.0f);
+    dmu = h6 * (k1m + 2.0f * (k2m + k3m) + k4m);
+    ds2 = h6 * (k1s + 2.0f * (k2s + k3s) + k4s);
 }
 
 // Compensated accumulation: (hi, lo) += d, renormalised (Fast2Sum, |hi| >= |d|).
@@ -412,10 +520,23 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P,
             const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
             double chd = 0.0;
             float aS_prev = local ? P.a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
+            RadCell32 carry;
+            if (QUANTUM) rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS_prev * env32[0]), carry);
+            // local amplitude: one spatial factor per step, at psi_{j+2}; the
+            // stage-2/3 value at psi_j + h/2 is the quadratic through psi_j,
+            // psi_{j+1} and psi_{j+2} (error of order h^3 times the third
+            // derivative of S, far below FP32 rounding)
+            float aS_next = local ? P.a0f * pf.S((P.psi0f + P.hf) * P.ellf) : a0S0f;
             for (int j = 0; j < N; ++j) {
-                const float psi = fmaf((float)j, P.hf, P.psi0f);
                 float aSh = a0S0f, aS4 = a0S0f;
-                if (local) {
+                if (local && P.mid_interp) {
+                    const float psi2 = fmaf((float)(j + 2), P.hf, P.psi0f);
+                    const float aS_far = P.a0f * pf.S(psi2 * P.ellf);
+                    aS4 = aS_next;
+                    aSh = fmaf(0.375f, aS_prev, fmaf(0.75f, aS4, -0.125f * aS_far));
+                    aS_next = aS_far;
+                } else if (local) {  // coarse steps: both points exactly
+                    const float psi = fmaf((float)j, P.hf, P.psi0f);
                     aSh = P.a0f * pf.S(fmaf(0.5f, P.hf, psi) * P.ellf);
                     aS4 = P.a0f * pf.S((psi + P.hf) * P.ellf);
                 }
@@ -448,12 +569,18 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P,
                     mu_lo = (float)(mn - (double)mu);
                     s2 = (float)sn;
                     s2_lo = (float)(sn - (double)s2);
+                    // the next FP32 stage 1 needs the cell at the new state
+                    rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS4 * env32[2 * j + 2]), carry);
+                } else if (QUANTUM) {
+                    float dm, ds;
+                    rk4_q32(mu, s2, a1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
+                    comp_add(mu, mu_lo, dm);
+                    comp_add(s2, s2_lo, ds);
                 } else {
                     float dm, ds;
-                    rk4_increment<float, QUANTUM>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds,
-                                                  chi_hi);
+                    rk4_increment<float, false>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds,
+                                                chi_hi);
                     comp_add(mu, mu_lo, dm);
-                    if (QUANTUM) comp_add(s2, s2_lo, ds);
                 }
                 aS_prev = aS4;
             }
@@ -790,8 +917,13 @@ __global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64)
         }
     }
     if (cell_all < kCells32) {
-        for (int f = 0; f < 4; ++f)
-            for (int c = 0; c < 4; ++c) rad32[cell_all * kCellVals + 4 * f + c] = (float)coef[f][c];
+        // function-major: rad32[(f * kCells32 + cell) * 4 + power], holding the
+        // drift combinations g, 2g + chi g', g + 2 chi g' + chi^2 g''/2, h
+        for (int c = 0; c < 4; ++c) {
+            const double mix[4] = {coef[0][c], 2.0 * coef[0][c] + coef[1][c],
+                                   coef[0][c] + 2.0 * coef[1][c] + 0.5 * coef[2][c], coef[3][c]};
+            for (int f = 0; f < 4; ++f) rad32[(f * kCells32 + cell_all) * 4 + c] = (float)mix[f];
+        }
     } else {
         const int cell = cell_all - kCells32;
         for (int f = 0; f < 4; ++f)
@@ -805,11 +937,12 @@ __global__ void rad_eval_kernel(const float *rad32, const double *rad64, int pre
     if (k >= n) return;
     const int fl = (chi[k] < (double)(1 << (kEMax + 1))) ? 0 : kFlagRange;
     if (prec == 0) {
-        float g, G1, G2, h;
-        rad_eval32(rad32, (float)chi[k], g, G1, G2, h);
+        float T1, T2, T3, h;
+        rad_eval32(rad32, (float)chi[k], T1, T2, T3, h);
+        const double g = T1, G1 = (double)T2 - 2.0 * T1;
         out[4 * k] = g;
         out[4 * k + 1] = G1;
-        out[4 * k + 2] = G2;
+        out[4 * k + 2] = 2.0 * ((double)T3 - g - 2.0 * G1);
         out[4 * k + 3] = h;
     } else {
         double g, G1, G2, h;
