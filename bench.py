@@ -31,6 +31,28 @@ ALG_FLOPS = {("quantum", "local"): 270, ("quantum", "a0eff"): 229,
              ("classical", "local"): 79, ("classical", "a0eff"): 31}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "phase_kernel_focused_2p22.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2308_09348_amd", "csrc", "qs_kernels.hip")
+
+
+def profiled_traffic():
+    """HBM bytes per phase-kernel launch from the committed rocprofv3 byte
+    counters, or None when the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PROFILE):
+            parts = line.split()
+            if len(parts) == 2:
+                kv[parts[0]] = parts[1]
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["phase_kernel_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,7 +148,8 @@ def main():
                    "chi_fp64": args.chi_fp64, "leg": "fwd"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "phase_kernel",
+                     "traffic": profiled_traffic() if args.precision == "fp32" else None,
+                     "kernel": "phase_kernel",
                      "kernel_avg_ms": phase_avg_ms,
                      "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
                                                              params["amp_mode"])]},
