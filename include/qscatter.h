@@ -173,6 +173,22 @@ qs_status qs_forward(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
                      const qs_numerics *num, const qs_bins *bins,
                      const qs_outputs *out, void *stream);
 
+/* Many shots in one launch (the high-repetition-rate use of the abstract and
+ * the conclusions): shot k uses lasers[k], beams[k], bins[k], outs[k] and
+ * n_samples[k] samples, and the shared numerics (num->n_samples is ignored;
+ * shot k draws its samples with RNG counter word num->shot + k).  All host
+ * arrays have n_shots entries; the outputs are device pointers as in
+ * qs_forward.  Shot k gives bit-for-bit the result of qs_forward with
+ * num->shot + k and n_samples[k].  The shots must share lambda_um, tau_fs and
+ * envelope (one phase grid serves them all): otherwise QS_EUNSUPPORTED.
+ * At most 2^20 shots and 2^36 samples in total.
+ * Errors: QS_EINVAL (as qs_forward, per shot), QS_EUNSUPPORTED, QS_ENOMEM,
+ * QS_EDEVICE. */
+qs_status qs_forward_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                             const qs_beam *beams, const int64_t *n_samples,
+                             const qs_numerics *num, const qs_bins *bins,
+                             const qs_outputs *outs, void *stream);
+
 /* Evaluate the device radiation-function approximation at n values of chi
  * (device arrays): out[4*k + {0,1,2,3}] = {g, chi g', chi^2 g'', h} at
  * chi[k], in FP32 (precision QS_PREC_FP32) or FP64.  Diagnostic entry point

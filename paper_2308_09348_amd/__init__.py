@@ -91,6 +91,55 @@ class Context:
                 raise QScatterError(st, "device status")
         return out
 
+    def forward_batched(self, shots, stream=None, check=True, out=None):
+        """One launch over a list of per-shot parameter dictionaries.  The
+        numerics (steps, seed, models, deposit, precision) come from shots[0];
+        shot k uses RNG counter word shots[0]["shot"] + k.  Returns a list of
+        per-shot result dictionaries (device tensors)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        n = len(shots)
+        if n == 0:
+            return []
+        _, _, nu, _ = _lib.structs(shots[0])
+        lasers = (_lib.Laser * n)()
+        beams = (_lib.Beam * n)()
+        bins = (_lib.Bins * n)()
+        outs = (_lib.Outputs * n)()
+        ns = (ctypes.c_int64 * n)()
+        if out is None:
+            out = []
+            for p in shots:
+                out.append({
+                    "energy_hist": torch.empty(p["n_e"] + 2, dtype=torch.float64, device=dev),
+                    "angle_hist": torch.empty(p["n_th"] + 2, dtype=torch.float64, device=dev),
+                    "a0eff_hist": torch.empty(p["n_a"], dtype=torch.float64, device=dev),
+                    "moments": torch.empty(_lib.M_N, dtype=torch.float64, device=dev),
+                    "status": torch.empty(1, dtype=torch.int32, device=dev)})
+        for k, p in enumerate(shots):
+            la, be, _, bi = _lib.structs(p)
+            lasers[k], beams[k], bins[k] = la, be, bi
+            ns[k] = int(p["n_samples"])
+            o = out[k]
+            outs[k] = _lib.Outputs(
+                energy_hist=o["energy_hist"].data_ptr(), angle_hist=o["angle_hist"].data_ptr(),
+                a0eff_hist=o["a0eff_hist"].data_ptr(), moments=o["moments"].data_ptr(),
+                status=o["status"].data_ptr(), samples=None, sample_stride=1,
+                n_sample_records=0)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        st = _lib.lib().qs_forward_batched(self._ptr, n, lasers, beams, ns, ctypes.byref(nu), bins,
+                                           outs, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        if check:
+            torch.cuda.synchronize(dev)
+            status = torch.stack([o["status"] for o in out]).cpu()
+            bad = int(status.max())
+            if bad != _lib.QS_OK:
+                raise QScatterError(bad, "device status of a shot")
+        return out
+
     def set_profiling(self, on=True):
         st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)
         if st != _lib.QS_OK:

@@ -62,7 +62,8 @@ class Outputs(ctypes.Structure):
                 ("sample_stride", ctypes.c_int64), ("n_sample_records", ctypes.c_int64)]
 
 
-EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_radiation_eval", "qs_sync_status",
+EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_radiation_eval",
+           "qs_sync_status",
            "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
            "qs_abi_version"]
 
@@ -93,6 +94,11 @@ def lib():
                                  ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                  ctypes.POINTER(Outputs), vp]
         L.qs_forward.restype = ctypes.c_int
+        L.qs_forward_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser),
+                                         ctypes.POINTER(Beam), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+                                         ctypes.POINTER(Outputs), vp]
+        L.qs_forward_batched.restype = ctypes.c_int
         L.qs_radiation_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.qs_radiation_eval.restype = ctypes.c_int
         L.qs_sync_status.argtypes = [vp, vp, vp]

@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +29,13 @@ struct qs_ctx {
     size_t part_cap = 0;
     unsigned char *states = nullptr;  // per-sample final states (SampleState arrays)
     size_t states_cap = 0;
+    // per-shot tables: pinned staging on the host, a device copy
+    unsigned char *stage = nullptr;
+    size_t stage_cap = 0;
+    unsigned char *shot_tab = nullptr;
+    size_t shot_tab_cap = 0;
+    hipEvent_t stage_done = nullptr;  // the last copy out of the staging buffer
+    bool stage_pending = false;
     int *eval_flags = nullptr;
     // kernel timing
     bool profiling = false;
@@ -71,13 +79,12 @@ class DeviceGuard {
 
 bool fin(double v) { return std::isfinite(v); }
 
-qs_status validate(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
-                   const qs_bins *H, const qs_outputs *O) {
-    if (!L || !B || !N || !H || !O) return set_err(c, "null argument"), QS_EINVAL;
+qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_bins *H,
+                        const qs_outputs *O, int64_t n_samples) {
+    if (!L || !B || !H || !O) return set_err(c, "null argument"), QS_EINVAL;
     const double vals[] = {L->a0, L->lambda_um, L->w0_um, L->tau_fs, L->x_off_um, L->y_off_um,
                            L->delay_fs, B->gamma0, B->sigma_gamma, B->sigma_r_um, B->sigma_z_um,
-                           B->div_mrad, N->window_fwhm, N->kernel_sigma_bins, N->chi_fp64,
-                           N->c_theta, H->e_lo, H->e_hi, H->th_lo_mrad, H->th_hi_mrad};
+                           B->div_mrad, H->e_lo, H->e_hi, H->th_lo_mrad, H->th_hi_mrad};
     for (double v : vals)
         if (!fin(v)) return set_err(c, "non-finite parameter"), QS_EINVAL;
     if (!(L->a0 >= 0) || !(L->lambda_um > 0) || !(L->w0_um >= 0) || !(L->tau_fs > 0))
@@ -87,8 +94,25 @@ qs_status validate(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_nume
     if (!(B->gamma0 > 1) || !(B->sigma_gamma >= 0) || !(B->sigma_r_um >= 0) ||
         !(B->sigma_z_um >= 0) || !(B->div_mrad >= 0))
         return set_err(c, "beam parameter out of range"), QS_EINVAL;
-    if (N->n_samples < 1 || N->n_samples > (int64_t)1 << 32)
+    if (n_samples < 1 || n_samples > (int64_t)1 << 32)
         return set_err(c, "n_samples must be in [1, 2^32]"), QS_EINVAL;
+    if (H->n_e < 1 || H->n_e > 4096 || H->n_th < 1 || H->n_th > 4096 || H->n_a < 1 ||
+        H->n_a > 4096)
+        return set_err(c, "bin counts must be in [1, 4096]"), QS_EINVAL;
+    if (!(H->e_hi > H->e_lo) || !(H->th_hi_mrad > H->th_lo_mrad))
+        return set_err(c, "histogram window must have hi > lo"), QS_EINVAL;
+    if (!O->energy_hist || !O->angle_hist || !O->a0eff_hist || !O->moments || !O->status)
+        return set_err(c, "null output pointer"), QS_EINVAL;
+    if (O->samples && (O->sample_stride < 1 || O->n_sample_records < 0))
+        return set_err(c, "sample records need stride >= 1"), QS_EINVAL;
+    return QS_OK;
+}
+
+qs_status validate_numerics(qs_ctx *c, const qs_numerics *N) {
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    const double vals[] = {N->window_fwhm, N->kernel_sigma_bins, N->chi_fp64, N->c_theta};
+    for (double v : vals)
+        if (!fin(v)) return set_err(c, "non-finite parameter"), QS_EINVAL;
     if (N->n_steps < 1 || N->n_steps > 65536)
         return set_err(c, "n_steps must be in [1, 65536]"), QS_EINVAL;
     if (N->shot < 0) return set_err(c, "shot must be >= 0"), QS_EINVAL;
@@ -102,15 +126,6 @@ qs_status validate(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_nume
         return set_err(c, "unknown deposit"), QS_EINVAL;
     if (N->precision != QS_PREC_FP32 && N->precision != QS_PREC_FP64)
         return set_err(c, "unknown precision"), QS_EINVAL;
-    if (H->n_e < 1 || H->n_e > 4096 || H->n_th < 1 || H->n_th > 4096 || H->n_a < 1 ||
-        H->n_a > 4096)
-        return set_err(c, "bin counts must be in [1, 4096]"), QS_EINVAL;
-    if (!(H->e_hi > H->e_lo) || !(H->th_hi_mrad > H->th_lo_mrad))
-        return set_err(c, "histogram window must have hi > lo"), QS_EINVAL;
-    if (!O->energy_hist || !O->angle_hist || !O->a0eff_hist || !O->moments || !O->status)
-        return set_err(c, "null output pointer"), QS_EINVAL;
-    if (O->samples && (O->sample_stride < 1 || O->n_sample_records < 0))
-        return set_err(c, "sample records need stride >= 1"), QS_EINVAL;
     return QS_OK;
 }
 
@@ -129,6 +144,24 @@ qs_status grow(qs_ctx *c, T **p, size_t *cap, size_t n, const char *what) {
     *cap = n;
     return QS_OK;
 }
+
+qs_status grow_pinned(qs_ctx *c, size_t n) {
+    if (c->stage_cap >= n) return QS_OK;
+    if (c->stage) {
+        if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+        (void)hipHostFree(c->stage);
+    }
+    c->stage = nullptr;
+    c->stage_cap = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->stage), n, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "pinned staging");
+    c->stage_cap = n;
+    return QS_OK;
+}
+
+qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                       const qs_outputs *O, hipStream_t s);
 
 }  // namespace
 
@@ -197,6 +230,9 @@ void qs_destroy(qs_ctx *c) {
         (void)hipFree(c->accum);
         (void)hipFree(c->partials);
         (void)hipFree(c->states);
+        (void)hipFree(c->shot_tab);
+        if (c->stage) (void)hipHostFree(c->stage);
+        if (c->stage_done) (void)hipEventDestroy(c->stage_done);
         (void)hipFree(c->eval_flags);
         for (hipEvent_t &e : c->ev)
             if (e) (void)hipEventDestroy(e);
@@ -207,168 +243,20 @@ void qs_destroy(qs_ctx *c) {
 qs_status qs_forward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
                      const qs_bins *H, const qs_outputs *O, void *stream) {
     if (!c) return QS_EINVAL;
-    qs_status st = validate(c, L, B, N, H, O);
-    if (st != QS_OK) return st;
-    DeviceGuard guard(c->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-
-    // ---- derived constants ----
-    const double omega0 = 2.0 * kPi * kC_um_per_fs / L->lambda_um;  // rad / fs
-    const double aS = L->lambda_um / (2.0 * kPi * kLambdaBarC_um);
-    const double omega_tau = omega0 * L->tau_fs;
-    const double psi_max = L->envelope == QS_ENV_GAUSS ? N->window_fwhm * omega_tau : omega_tau;
-
-    int prec = qs::PREC_F32;
-    if (N->precision == QS_PREC_FP64)
-        prec = qs::PREC_F64;
-    else if (N->rr_model == QS_RR_QUANTUM && N->chi_fp64 > 0)
-        prec = qs::PREC_F32MIX;
-    const double h = 2.0 * psi_max / (double)N->n_steps;
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
     const int64_t n = N->n_samples;
+    return forward_impl(c, 1, L, B, &n, N, H, O, reinterpret_cast<hipStream_t>(stream));
+}
 
-    // ---- scratch ----
-    const size_t nh = (size_t)(H->n_e + 2) + (H->n_th + 2) + H->n_a;
-    const size_t lds = qs::deposit_lds_bytes(H->n_e, H->n_th, H->n_a);
-    int dgrid = 0;
-    hipError_t e = qs::deposit_grid(lds, c->device, n, &dgrid);
-    if (e != hipSuccess) return hip_fail(c, e, "deposit occupancy query");
-    const size_t nenv = (size_t)2 * N->n_steps + 1;
-    // 6 doubles + 1 float per sample, each array 256-byte aligned
-    const size_t arr = ((size_t)n * 8 + 255) / 256 * 256;
-    const size_t arrf = ((size_t)n * 4 + 255) / 256 * 256;
-    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
-    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
-    if ((st = grow(c, &c->accum, &c->accum_cap, 2 + nh, "histogram accumulators")) != QS_OK)
-        return st;
-    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)dgrid * qs::P_N, "moment partials")) !=
-        QS_OK)
-        return st;
-    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf, "sample states")) != QS_OK)
-        return st;
-    qs::SampleState ss;
-    ss.mu = reinterpret_cast<double *>(c->states);
-    ss.s2 = reinterpret_cast<double *>(c->states + arr);
-    ss.S0 = reinterpret_cast<double *>(c->states + 2 * arr);
-    ss.g0 = reinterpret_cast<double *>(c->states + 3 * arr);
-    ss.thx = reinterpret_cast<double *>(c->states + 4 * arr);
-    ss.thy = reinterpret_cast<double *>(c->states + 5 * arr);
-    ss.cmx = reinterpret_cast<float *>(c->states + 6 * arr);
-    unsigned int *chimax_bits = reinterpret_cast<unsigned int *>(c->accum);
-    int *flags = reinterpret_cast<int *>(c->accum + 1);
-    unsigned long long *hist = c->accum + 2;
-
-    qs::PhaseParams p{};
-    const bool plane_wave = L->w0_um == 0.0;
-    p.a0 = L->a0;
-    p.inv_w0sq = plane_wave ? 0.0 : 1.0 / (L->w0_um * L->w0_um);
-    p.inv_zR = plane_wave ? 0.0 : L->lambda_um / (kPi * L->w0_um * L->w0_um);
-    p.x_off = L->x_off_um;
-    p.y_off = L->y_off_um;
-    p.z_delay = 0.5 * kC_um_per_fs * L->delay_fs;
-    p.ell_per_psi = L->lambda_um / (4.0 * kPi);
-    p.gamma0 = B->gamma0;
-    p.sigma_gamma = B->sigma_gamma;
-    p.sigma_r = B->sigma_r_um;
-    p.sigma_z = B->sigma_z_um;
-    p.div_rad = 1e-3 * B->div_mrad;
-    p.two_over_aS = 2.0 / aS;
-    p.K = 4.0 * kAlpha / (3.0 * aS);
-    p.CD = 55.0 / (6.0 * std::sqrt(3.0)) * kAlpha / (aS * aS);
-    p.psi_max = psi_max;
-    p.h = h;
-    p.a0f = (float)p.a0;
-    p.inv_w0sqf = (float)p.inv_w0sq;
-    p.inv_zRf = (float)p.inv_zR;
-    p.ellf = (float)p.ell_per_psi;
-    p.two_over_aSf = (float)p.two_over_aS;
-    p.Kf = (float)p.K;
-    p.CDf = (float)p.CD;
-    p.psi0f = (float)(-psi_max);
-    p.hf = (float)h;
-    p.chi_fp64 = (float)N->chi_fp64;
-    p.n_steps = N->n_steps;
-    p.shot = N->shot;
-    p.plane_wave = plane_wave ? 1 : 0;
-    {
-        // the quadratic midpoint of the spatial factor is used only when one
-        // phase step moves a sample much less than the focal scales
-        const double step_um = h * p.ell_per_psi;
-        const double scale = plane_wave ? 0.0
-                                        : std::fmax(p.inv_zR, 6.0 * p.div_rad / L->w0_um);
-        p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
-    }
-    p.key0 = (uint32_t)N->seed;
-    p.key1 = (uint32_t)(N->seed >> 32);
-    p.n_samples = n;
-    p.env32 = c->env32;
-    p.env64 = c->env64;
-    p.rad32 = c->rad32;
-    p.rad64 = c->rad64;
-    p.st = ss;
-    p.flags = flags;
-
-    qs::DepParams d{};
-    d.n_samples = n;
-    d.a0 = L->a0;
-    d.gamma0 = B->gamma0;
-    d.c_theta = N->c_theta;
-    d.deposit = N->deposit;
-    d.n_e = H->n_e;
-    d.n_th = H->n_th;
-    d.n_a = H->n_a;
-    d.ksig_bins = N->kernel_sigma_bins;
-    d.e_lo = H->e_lo;
-    d.e_w = (H->e_hi - H->e_lo) / H->n_e;
-    d.th_lo = H->th_lo_mrad;
-    d.th_w = (H->th_hi_mrad - H->th_lo_mrad) / H->n_th;
-    d.st = ss;
-    d.hist = hist;
-    d.partials = c->partials;
-    d.chimax_bits = chimax_bits;
-    d.flags = flags;
-    d.rec = O->samples;
-    d.rec_stride = O->samples ? O->sample_stride : 1;
-    d.rec_n = O->samples ? O->n_sample_records : 0;
-
-    qs::FinParams f{};
-    f.n_samples = n;
-    f.nblocks = dgrid;
-    f.n_e = H->n_e;
-    f.n_th = H->n_th;
-    f.n_a = H->n_a;
-    f.gamma0 = B->gamma0;
-    f.hist = hist;
-    f.partials = c->partials;
-    f.chimax_bits = chimax_bits;
-    f.flags = flags;
-    f.energy_hist = O->energy_hist;
-    f.angle_hist = O->angle_hist;
-    f.a0eff_hist = O->a0eff_hist;
-    f.moments = O->moments;
-    f.status = O->status;
-
-    // ---- enqueue ----
-    const bool prof = c->profiling;
-    auto mark = [&](int k) { return prof ? hipEventRecord(c->ev[k], s) : hipSuccess; };
-    if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_envelope(psi_max, h, N->n_steps, L->envelope, omega_tau, c->env32,
-                                 c->env64, s)) != hipSuccess)
-        return hip_fail(c, e, "envelope kernel");
-    if ((e = mark(1)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_zero(c->accum, 2 + nh, s)) != hipSuccess)
-        return hip_fail(c, e, "zero kernel");
-    if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_phase(p, prec, N->rr_model, N->amp_mode, s)) != hipSuccess)
-        return hip_fail(c, e, "phase kernel");
-    if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_deposit(d, dgrid, s)) != hipSuccess)
-        return hip_fail(c, e, "deposit kernel");
-    if ((e = mark(4)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_finalize(f, s)) != hipSuccess) return hip_fail(c, e, "finalize kernel");
-    if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
-    c->profiled_call = prof;
-    c->last_error[0] = 0;
-    return QS_OK;
+qs_status qs_forward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                             const qs_beam *beams, const int64_t *n_samples,
+                             const qs_numerics *num, const qs_bins *bins, const qs_outputs *outs,
+                             void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return forward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs,
+                        reinterpret_cast<hipStream_t>(stream));
 }
 
 qs_status qs_radiation_eval(qs_ctx *c, int32_t precision, int64_t n, const double *chi,
@@ -427,3 +315,203 @@ qs_status qs_sync_status(qs_ctx *c, const int32_t *status, void *stream) {
 }
 
 }  // extern "C"
+
+namespace {
+
+qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                       const qs_outputs *O, hipStream_t s) {
+    qs_status st = validate_numerics(c, N);
+    if (st != QS_OK) return st;
+    int max_nh = 0;
+    int64_t total = 0;
+    for (int k = 0; k < n_shots; ++k) {
+        if ((st = validate_shot(c, &L[k], &B[k], &H[k], &O[k], n_samples[k])) != QS_OK) return st;
+        if (L[k].lambda_um != L[0].lambda_um || L[k].tau_fs != L[0].tau_fs ||
+            L[k].envelope != L[0].envelope)
+            return set_err(c, "the shots of a batch must share wavelength, duration and envelope"),
+                   QS_EUNSUPPORTED;
+        max_nh = std::max(max_nh, H[k].n_e + 2 + H[k].n_th + 2 + H[k].n_a);
+        total += n_samples[k];
+        if (total > ((int64_t)1 << 36))
+            return set_err(c, "a batch holds at most 2^36 samples"), QS_EINVAL;
+    }
+    if (qs::deposit_lds_bytes(max_nh) > 160 * 1024)
+        return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+
+    // ---- shared constants (Sec. 2 eq. a0eff, Sec. 4 eq. dpdtRR) ----
+    const qs_laser &L0 = L[0];
+    const double omega0 = 2.0 * kPi * kC_um_per_fs / L0.lambda_um;  // rad / fs
+    const double aS = L0.lambda_um / (2.0 * kPi * kLambdaBarC_um);
+    const double omega_tau = omega0 * L0.tau_fs;
+    const double psi_max = L0.envelope == QS_ENV_GAUSS ? N->window_fwhm * omega_tau : omega_tau;
+    const double h = 2.0 * psi_max / (double)N->n_steps;
+    int prec = qs::PREC_F32;
+    if (N->precision == QS_PREC_FP64)
+        prec = qs::PREC_F64;
+    else if (N->rr_model == QS_RR_QUANTUM && N->chi_fp64 > 0)
+        prec = qs::PREC_F32MIX;
+
+    qs::BatchParams bp{};
+    bp.ell_per_psi = L0.lambda_um / (4.0 * kPi);
+    bp.two_over_aS = 2.0 / aS;
+    bp.K = 4.0 * kAlpha / (3.0 * aS);
+    bp.CD = 55.0 / (6.0 * std::sqrt(3.0)) * kAlpha / (aS * aS);
+    bp.psi_max = psi_max;
+    bp.h = h;
+    bp.ellf = (float)bp.ell_per_psi;
+    bp.two_over_aSf = (float)bp.two_over_aS;
+    bp.Kf = (float)bp.K;
+    bp.CDf = (float)bp.CD;
+    bp.psi0f = (float)(-psi_max);
+    bp.hf = (float)h;
+    bp.chi_fp64 = (float)N->chi_fp64;
+    bp.n_steps = N->n_steps;
+    bp.n_shots = n_shots;
+    bp.deposit = N->deposit;
+    bp.key0 = (uint32_t)N->seed;
+    bp.key1 = (uint32_t)(N->seed >> 32);
+    bp.ksig_bins = N->kernel_sigma_bins;
+    bp.c_theta = N->c_theta;
+
+    // ---- per-shot tables, built in pinned staging memory ----
+    const size_t tab_bytes = ((sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots + 255) /
+                             256 * 256;
+    if (c->stage_pending) {
+        hipError_t e = hipEventSynchronize(c->stage_done);  // previous copy out of staging
+        if (e != hipSuccess) return hip_fail(c, e, "staging event");
+        c->stage_pending = false;
+    }
+    if ((st = grow_pinned(c, tab_bytes)) != QS_OK) return st;
+    qs::ShotParams *sp = reinterpret_cast<qs::ShotParams *>(c->stage);
+    qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(c->stage + sizeof(qs::ShotParams) * n_shots);
+    int64_t item = 0, ditem = 0, off = 0, hoff = 0;
+    for (int k = 0; k < n_shots; ++k) {
+        const qs_laser &l = L[k];
+        const qs_beam &b = B[k];
+        const qs_bins &hb = H[k];
+        qs::ShotParams &p = sp[k];
+        p = qs::ShotParams{};
+        const bool plane_wave = l.w0_um == 0.0;
+        p.a0 = l.a0;
+        p.inv_w0sq = plane_wave ? 0.0 : 1.0 / (l.w0_um * l.w0_um);
+        p.inv_zR = plane_wave ? 0.0 : l.lambda_um / (kPi * l.w0_um * l.w0_um);
+        p.x_off = l.x_off_um;
+        p.y_off = l.y_off_um;
+        p.z_delay = 0.5 * kC_um_per_fs * l.delay_fs;
+        p.gamma0 = b.gamma0;
+        p.sigma_gamma = b.sigma_gamma;
+        p.sigma_r = b.sigma_r_um;
+        p.sigma_z = b.sigma_z_um;
+        p.div_rad = 1e-3 * b.div_mrad;
+        p.a0f = (float)p.a0;
+        p.inv_w0sqf = (float)p.inv_w0sq;
+        p.inv_zRf = (float)p.inv_zR;
+        p.plane_wave = plane_wave ? 1 : 0;
+        {
+            // the quadratic midpoint of the spatial factor is used only when one
+            // phase step moves a sample much less than the focal scales
+            const double step_um = h * bp.ell_per_psi;
+            const double scale = plane_wave ? 0.0 : std::fmax(p.inv_zR, 6.0 * p.div_rad / l.w0_um);
+            p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
+        }
+        p.shot_word = N->shot + k;
+        p.n_samples = n_samples[k];
+        p.state_off = off;
+        p.item0 = item;
+        p.ditem0 = ditem;
+        p.hist_off = hoff;
+        p.n_e = hb.n_e;
+        p.n_th = hb.n_th;
+        p.n_a = hb.n_a;
+        p.e_lo = hb.e_lo;
+        p.e_w = (hb.e_hi - hb.e_lo) / hb.n_e;
+        p.th_lo = hb.th_lo_mrad;
+        p.th_w = (hb.th_hi_mrad - hb.th_lo_mrad) / hb.n_th;
+        off += n_samples[k];
+        item += (n_samples[k] + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
+        ditem += (n_samples[k] + qs::kDepTile - 1) / qs::kDepTile;
+        hoff += hb.n_e + 2 + hb.n_th + 2 + hb.n_a;
+        const qs_outputs &o = O[k];
+        so[k].energy_hist = o.energy_hist;
+        so[k].angle_hist = o.angle_hist;
+        so[k].a0eff_hist = o.a0eff_hist;
+        so[k].moments = o.moments;
+        so[k].status = o.status;
+        so[k].samples = o.samples;
+        so[k].rec_stride = o.samples ? o.sample_stride : 1;
+        so[k].rec_n = o.samples ? o.n_sample_records : 0;
+    }
+    bp.n_items = item;
+    bp.n_ditems = ditem;
+
+    // ---- device scratch ----
+    const size_t nenv = (size_t)2 * N->n_steps + 1;
+    const size_t arr = ((size_t)total * 8 + 255) / 256 * 256;
+    const size_t arrf = ((size_t)total * 4 + 255) / 256 * 256;
+    const size_t flag_words = ((size_t)n_shots + 1) / 2;
+    const size_t accum_words = 1 + flag_words + (size_t)hoff;
+    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
+    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)ditem * qs::kPartials,
+                   "moment partials")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf, "sample states")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, tab_bytes, "shot table")) != QS_OK)
+        return st;
+    if (!c->stage_done) {
+        hipError_t e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(c, e, "event create");
+    }
+    bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
+    bp.outs = reinterpret_cast<const qs::ShotOut *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
+    bp.rad32 = c->rad32;
+    bp.rad64 = c->rad64;
+    bp.st.mu = reinterpret_cast<double *>(c->states);
+    bp.st.s2 = reinterpret_cast<double *>(c->states + arr);
+    bp.st.S0 = reinterpret_cast<double *>(c->states + 2 * arr);
+    bp.st.g0 = reinterpret_cast<double *>(c->states + 3 * arr);
+    bp.st.thx = reinterpret_cast<double *>(c->states + 4 * arr);
+    bp.st.thy = reinterpret_cast<double *>(c->states + 5 * arr);
+    bp.st.cmx = reinterpret_cast<float *>(c->states + 6 * arr);
+    bp.queue = reinterpret_cast<unsigned int *>(c->accum);
+    bp.flags = reinterpret_cast<int *>(c->accum + 1);
+    bp.hist = c->accum + 1 + flag_words;
+    bp.partials = c->partials;
+
+    // ---- enqueue ----
+    hipError_t e;
+    const bool prof = c->profiling;
+    auto mark = [&](int k) { return prof ? hipEventRecord(c->ev[k], s) : hipSuccess; };
+    if ((e = hipMemcpyAsync(c->shot_tab, c->stage, tab_bytes, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "shot table copy");
+    if ((e = hipEventRecord(c->stage_done, s)) != hipSuccess)
+        return hip_fail(c, e, "event record");
+    c->stage_pending = true;
+    if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_envelope(psi_max, h, N->n_steps, L0.envelope, omega_tau, c->env32,
+                                 c->env64, s)) != hipSuccess)
+        return hip_fail(c, e, "envelope kernel");
+    if ((e = mark(1)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
+        return hip_fail(c, e, "zero kernel");
+    if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_phase(bp, c->env32, c->env64, prec, N->rr_model, N->amp_mode, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "phase kernel");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_deposit(bp, max_nh, s)) != hipSuccess)
+        return hip_fail(c, e, "deposit kernel");
+    if ((e = mark(4)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_finalize(bp, s)) != hipSuccess) return hip_fail(c, e, "finalize kernel");
+    if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
+    c->profiled_call = prof;
+    c->last_error[0] = 0;
+    return QS_OK;
+}
+
+}  // namespace

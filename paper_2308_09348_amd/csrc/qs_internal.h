@@ -41,12 +41,15 @@ enum {
     P_N
 };
 
-constexpr int kPhaseBlock = 256;
+constexpr int kPhaseBlock = 256;  // one phase work item = kPhaseBlock samples of one shot
 constexpr int kDepBlock = 256;
+constexpr int kDepTile = 4096;    // one deposit work item = kDepTile samples of one shot
+constexpr int kPartials = P_N + 1;  // moment sums + chi max per deposit item
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
 
-// Final state of every sample (structure of arrays in device scratch).
+// Final state of every sample (structure of arrays in device scratch,
+// indexed by the shot's state offset + sample index).
 struct SampleState {
     double *mu;    // final mean Lorentz factor
     double *s2;    // final energy variance
@@ -57,52 +60,51 @@ struct SampleState {
     float *cmx;    // largest chi at a step start
 };
 
-// Phase kernel: sample -> geometry -> RK4 loop -> SampleState.
-struct PhaseParams {
-    // FP64 copies (per-sample set-up and FP64 steps)
-    double a0, inv_w0sq, inv_zR, x_off, y_off, z_delay, ell_per_psi;
+// Per-shot parameters (device table, read with scalar loads: every lane of a
+// block works on the same shot).
+struct ShotParams {
+    double a0, inv_w0sq, inv_zR, x_off, y_off, z_delay;
     double gamma0, sigma_gamma, sigma_r, sigma_z, div_rad;
-    double two_over_aS, K, CD, psi_max, h;
-    // FP32 copies (FP32 steps)
-    float a0f, inv_w0sqf, inv_zRf, ellf, two_over_aSf, Kf, CDf, psi0f, hf, chi_fp64;
-    int32_t n_steps, shot, plane_wave;
-    int32_t mid_interp;   // stage-2/3 spatial factor by quadratic interpolation
-    uint32_t key0, key1;
-    int64_t n_samples;
-    const float *env32;   // [2 n_steps + 1] envelope x carrier at psi_k = -psi_max + k h/2
-    const double *env64;
-    const float *rad32;   // [kCells32 * 16]
-    const double *rad64;  // [kCells64 * 16]
-    SampleState st;
-    int *flags;
+    float a0f, inv_w0sqf, inv_zRf, pad0;
+    int32_t plane_wave, mid_interp, shot_word, pad1;
+    int64_t n_samples;   // samples of this shot
+    int64_t state_off;   // index of its first sample state
+    int64_t item0;       // its first phase work item
+    int64_t ditem0;      // its first deposit work item
+    int64_t hist_off;    // its first histogram word in the accumulators
+    // bins
+    int32_t n_e, n_th, n_a, pad2;
+    double e_lo, e_w, th_lo, th_w;
 };
 
-// Deposit kernel: SampleState -> observables -> histograms and moments.
-struct DepParams {
-    int64_t n_samples;
-    double a0, gamma0, c_theta;
-    int32_t deposit, n_e, n_th, n_a;
-    double ksig_bins, e_lo, e_w, th_lo, th_w;
-    SampleState st;
-    unsigned long long *hist;  // [n_e + 2 | n_th + 2 | n_a] fixed point 2^-32
-    double *partials;          // [gridDim.x * P_N]
-    unsigned int *chimax_bits;
-    int *flags;
-    double *rec;               // optional per-sample records
+// Output pointers of one shot (device table).
+struct ShotOut {
+    double *energy_hist, *angle_hist, *a0eff_hist, *moments;
+    int32_t *status;
+    double *samples;
     int64_t rec_stride, rec_n;
 };
 
-struct FinParams {
-    int64_t n_samples;
-    int nblocks;
-    int n_e, n_th, n_a;
-    double gamma0;
-    const unsigned long long *hist;
-    const double *partials;
-    const unsigned int *chimax_bits;
-    const int *flags;
-    double *energy_hist, *angle_hist, *a0eff_hist, *moments;
-    int32_t *status;
+// Parameters shared by every shot of a launch.
+struct BatchParams {
+    // FP64 and FP32 copies of the shared physics constants
+    double ell_per_psi, two_over_aS, K, CD, psi_max, h;
+    float ellf, two_over_aSf, Kf, CDf, psi0f, hf, chi_fp64, pad0;
+    int32_t n_steps, n_shots, deposit, pad1;
+    uint32_t key0, key1;
+    double ksig_bins, c_theta;
+    int64_t n_items, n_ditems;
+    const ShotParams *shots;
+    const ShotOut *outs;
+    const float *rad32;   // [kCells32 * 16]
+    const double *rad64;  // [kCells64 * 16]
+    SampleState st;
+    // accumulators (device scratch, cleared before each launch)
+    unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
+    unsigned int *chimax_bits;     // [n_shots]
+    int *flags;                    // [n_shots]
+    unsigned int *queue;           // [2]: phase and deposit work counters
+    double *partials;              // [n_ditems][kPartials]
 };
 
 // ---- launchers (qs_kernels.hip) -------------------------------------------
@@ -112,11 +114,11 @@ size_t radiation_work_doubles();
 hipError_t launch_envelope(double psi_max, double h, int n_steps, int envelope, double omega_tau,
                            float *env32, double *env64, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, size_t n64, hipStream_t s);
-hipError_t launch_phase(const PhaseParams &p, int prec, int rr, int amp, hipStream_t s);
-size_t deposit_lds_bytes(int n_e, int n_th, int n_a);
-hipError_t deposit_grid(size_t lds_bytes, int device, int64_t n_samples, int *grid);
-hipError_t launch_deposit(const DepParams &p, int grid, hipStream_t s);
-hipError_t launch_finalize(const FinParams &p, hipStream_t s);
+hipError_t launch_phase(const BatchParams &p, const float *env32, const double *env64, int prec,
+                        int rr, int amp, hipStream_t s);
+size_t deposit_lds_bytes(int max_hist_words);
+hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t s);
+hipError_t launch_finalize(const BatchParams &p, hipStream_t s);
 hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int prec, int64_t n,
                                  const double *chi, double *out, int *flags, hipStream_t s);
 

@@ -431,179 +431,223 @@ __device__ void deposit_law(double v, double s, int dep, double ksig, double lo,
 }
 
 // ===========================================================================
+// Work items.  A launch covers n_shots shots; phase items are tiles of
+// kPhaseBlock consecutive samples of one shot (one sample per lane), deposit
+// items tiles of kDepTile samples.  Blocks take items from a counter; an
+// item's result does not depend on which block runs it, so the output is
+// deterministic, and a shot gives the same bits alone or in a batch.
+// ===========================================================================
+__device__ __forceinline__ int find_shot(const ShotParams *shots, int n_shots, int64_t item,
+                                         bool deposit) {
+    int lo = 0, hi = n_shots - 1;  // largest s whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t first = deposit ? shots[mid].ditem0 : shots[mid].item0;
+        if (first <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slot) {
+    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t item = *slot;
+    __syncthreads();
+    return item;
+}
+
+// ===========================================================================
 // Phase kernel: sample -> ballistic path -> RK4 phase loop -> final state
 // ===========================================================================
 // The envelope tables come as separate restrict-qualified arguments: the
 // kernel never writes them, so the compiler reads them with scalar loads
 // (every lane of a wavefront is at the same phase step).
 template <int PREC, bool QUANTUM, bool LOCAL>
-__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(PhaseParams P,
+__device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotParams &sp, int64_t i,
+                                             const float *__restrict__ env32,
+                                             const double *__restrict__ env64,
+                                             const float *tab32, int &flags) {
+    const RadTab<double> tabd{P.rad64};
+    const RadTab<float> tabf{tab32};
+    const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
+    const Phys<double> phd{P.K, P.CD, P.two_over_aS};
+    const int N = P.n_steps;
+    const bool local = LOCAL && !sp.plane_wave;
+    const float chi_top = (float)(1 << (kEMax + 1));  // end of the tabulated range
+
+    // ---- sample and geometry (FP64, once per sample) ----
+    double nrm[6];
+    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
+    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
+    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
+    const double z = sp.sigma_z * nrm[2];
+    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
+    const double thx = sp.div_rad * nrm[4];
+    const double thy = sp.div_rad * nrm[5];
+    Path<double> pd;
+    pd.xc = fma(thx, 0.5 * z, x);
+    pd.yc = fma(thy, 0.5 * z, y);
+    pd.thx = thx;
+    pd.thy = thy;
+    pd.zstar = fma(0.5, z, sp.z_delay);
+    pd.inv_w0sq = sp.inv_w0sq;
+    pd.inv_zR = sp.inv_zR;
+    const double S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
+    const double a0S0 = sp.a0 * S0;
+
+    double mu_f, s2_f;
+    float cmx = 0.0f;     // largest chi at a step start for this sample
+    float chi_hi = 0.0f;  // largest chi at any stage (range check)
+    if (PREC == PREC_F64) {
+        double mu = g0, s2 = 0.0, chd = 0.0;
+        double aS_prev = local ? sp.a0 * pd.S(-P.psi_max * P.ell_per_psi) : a0S0;
+        for (int j = 0; j < N; ++j) {
+            const double psi = fma((double)j, P.h, -P.psi_max);
+            double aSh = a0S0, aS4 = a0S0;
+            if (local) {
+                aSh = sp.a0 * pd.S(fma(0.5, P.h, psi) * P.ell_per_psi);
+                aS4 = sp.a0 * pd.S((psi + P.h) * P.ell_per_psi);
+            }
+            const double a1 = aS_prev * env64[2 * j];
+            const double ah = aSh * env64[2 * j + 1];
+            const double a4 = aS4 * env64[2 * j + 2];
+            cmx = fmaxf(cmx, (float)(P.two_over_aS * mu * fabs(a1)));
+            double dm, ds;
+            rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, chd);
+            mu += dm;
+            s2 += ds;
+            aS_prev = aS4;
+        }
+        mu_f = mu;
+        s2_f = s2;
+        chi_hi = (float)chd;
+    } else {
+        Path<float> pf;
+        pf.xc = (float)pd.xc;
+        pf.yc = (float)pd.yc;
+        pf.thx = (float)thx;
+        pf.thy = (float)thy;
+        pf.zstar = (float)pd.zstar;
+        pf.inv_w0sq = sp.inv_w0sqf;
+        pf.inv_zR = sp.inv_zRf;
+        const float a0f = sp.a0f;
+        const float a0S0f = (float)a0S0;
+        float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
+        // the part of g0 that the FP32 pair cannot hold, restored at the end
+        const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
+        double chd = 0.0;
+        float aS_prev = local ? a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
+        RadCell32 carry;
+        if (QUANTUM) rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS_prev * env32[0]), carry);
+        // local amplitude: one spatial factor per step, at psi_{j+2}; the
+        // stage-2/3 value at psi_j + h/2 is the quadratic through psi_j,
+        // psi_{j+1} and psi_{j+2} (error of order h^3 times the third
+        // derivative of S, far below FP32 rounding)
+        float aS_next = local ? a0f * pf.S((P.psi0f + P.hf) * P.ellf) : a0S0f;
+        for (int j = 0; j < N; ++j) {
+            float aSh = a0S0f, aS4 = a0S0f;
+            if (local && sp.mid_interp) {
+                const float psi2 = fmaf((float)(j + 2), P.hf, P.psi0f);
+                const float aS_far = a0f * pf.S(psi2 * P.ellf);
+                aS4 = aS_next;
+                aSh = fmaf(0.375f, aS_prev, fmaf(0.75f, aS4, -0.125f * aS_far));
+                aS_next = aS_far;
+            } else if (local) {  // coarse steps: both points exactly
+                const float psi = fmaf((float)j, P.hf, P.psi0f);
+                aSh = a0f * pf.S(fmaf(0.5f, P.hf, psi) * P.ellf);
+                aS4 = a0f * pf.S((psi + P.hf) * P.ellf);
+            }
+            const float a1 = aS_prev * env32[2 * j];
+            const float ah = aSh * env32[2 * j + 1];
+            const float a4 = aS4 * env32[2 * j + 2];
+            const float chi1 = phf.two_over_aS * mu * fabsf(a1);
+            cmx = fmaxf(cmx, chi1);
+            bool promote = false;
+            if (PREC == PREC_F32MIX) promote = __any(chi1 > P.chi_fp64);
+            if (promote) {
+                // the whole wavefront runs this step in FP64 (uniform branch)
+                const double psid = fma((double)j, P.h, -P.psi_max);
+                double A1 = a0S0, Ah = a0S0, A4 = a0S0;
+                if (local) {
+                    A1 = sp.a0 * pd.S(psid * P.ell_per_psi);
+                    Ah = sp.a0 * pd.S(fma(0.5, P.h, psid) * P.ell_per_psi);
+                    A4 = sp.a0 * pd.S((psid + P.h) * P.ell_per_psi);
+                }
+                A1 *= env64[2 * j];
+                Ah *= env64[2 * j + 1];
+                A4 *= env64[2 * j + 2];
+                const double mud = (double)mu + (double)mu_lo;
+                const double s2d = (double)s2 + (double)s2_lo;
+                double dm, ds;
+                rk4_increment<double, QUANTUM>(mud, s2d, A1, Ah, A4, P.h, phd, tabd, dm, ds, chd);
+                const double mn = mud + dm, sn = s2d + ds;
+                mu = (float)mn;
+                mu_lo = (float)(mn - (double)mu);
+                s2 = (float)sn;
+                s2_lo = (float)(sn - (double)s2);
+                // the next FP32 stage 1 needs the cell at the new state
+                rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS4 * env32[2 * j + 2]), carry);
+            } else if (QUANTUM) {
+                float dm, ds;
+                rk4_q32(mu, s2, a1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
+                comp_add(mu, mu_lo, dm);
+                comp_add(s2, s2_lo, ds);
+            } else {
+                float dm, ds;
+                rk4_increment<float, false>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds, chi_hi);
+                comp_add(mu, mu_lo, dm);
+            }
+            aS_prev = aS4;
+        }
+        mu_f = ((double)mu + (double)mu_lo) + g0_rest;
+        s2_f = (double)s2 + (double)s2_lo;
+        chi_hi = fmaxf(chi_hi, (float)chd);
+    }
+    {
+        // chi at the end of the last step (the pulse tail)
+        const double aN = (local ? sp.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * env64[2 * N];
+        cmx = fmaxf(cmx, (float)(P.two_over_aS * mu_f * fabs(aN)));
+    }
+    if (QUANTUM && !(chi_hi < chi_top)) flags |= kFlagRange;
+    if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) flags |= kFlagNonFinite;
+    const int64_t k = sp.state_off + i;
+    P.st.mu[k] = mu_f;
+    P.st.s2[k] = s2_f;
+    P.st.S0[k] = S0;
+    P.st.g0[k] = g0;
+    P.st.thx[k] = thx;
+    P.st.thy[k] = thy;
+    P.st.cmx[k] = cmx;
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
                                                             const float *__restrict__ env32,
                                                             const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
+    __shared__ int64_t slot;
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
         for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
         __syncthreads();
     }
-    const RadTab<float> tabf{tab32};
-    const RadTab<double> tabd{P.rad64};
-    const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
-    const Phys<double> phd{P.K, P.CD, P.two_over_aS};
-    const int N = P.n_steps;
-    const bool local = LOCAL && !P.plane_wave;
-    const float chi_top = (float)(1 << (kEMax + 1));  // end of the tabulated range
-    int flags = 0;
-
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n_samples; i += stride) {
-        // ---- sample and geometry (FP64, once per sample) ----
-        double nrm[6];
-        sample_normals((uint32_t)i, (uint32_t)P.shot, P.key0, P.key1, nrm);
-        const double x = fma(P.sigma_r, nrm[0], P.x_off);
-        const double y = fma(P.sigma_r, nrm[1], P.y_off);
-        const double z = P.sigma_z * nrm[2];
-        const double g0 = fma(P.sigma_gamma, nrm[3], P.gamma0);
-        const double thx = P.div_rad * nrm[4];
-        const double thy = P.div_rad * nrm[5];
-        Path<double> pd;
-        pd.xc = fma(thx, 0.5 * z, x);
-        pd.yc = fma(thy, 0.5 * z, y);
-        pd.thx = thx;
-        pd.thy = thy;
-        pd.zstar = fma(0.5, z, P.z_delay);
-        pd.inv_w0sq = P.inv_w0sq;
-        pd.inv_zR = P.inv_zR;
-        const double S0 = P.plane_wave ? 1.0 : pd.S(0.0);
-        const double a0S0 = P.a0 * S0;
-
-        double mu_f, s2_f;
-        float cmx = 0.0f;     // largest chi at a step start for this sample
-        float chi_hi = 0.0f;  // largest chi at any stage (range check)
-        if (PREC == PREC_F64) {
-            double mu = g0, s2 = 0.0, chd = 0.0;
-            double aS_prev = local ? P.a0 * pd.S(-P.psi_max * P.ell_per_psi) : a0S0;
-            for (int j = 0; j < N; ++j) {
-                const double psi = fma((double)j, P.h, -P.psi_max);
-                double aSh = a0S0, aS4 = a0S0;
-                if (local) {
-                    aSh = P.a0 * pd.S(fma(0.5, P.h, psi) * P.ell_per_psi);
-                    aS4 = P.a0 * pd.S((psi + P.h) * P.ell_per_psi);
-                }
-                const double a1 = aS_prev * env64[2 * j];
-                const double ah = aSh * env64[2 * j + 1];
-                const double a4 = aS4 * env64[2 * j + 2];
-                cmx = fmaxf(cmx, (float)(P.two_over_aS * mu * fabs(a1)));
-                double dm, ds;
-                rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, chd);
-                mu += dm;
-                s2 += ds;
-                aS_prev = aS4;
-            }
-            mu_f = mu;
-            s2_f = s2;
-            chi_hi = (float)chd;
-        } else {
-            Path<float> pf;
-            pf.xc = (float)pd.xc;
-            pf.yc = (float)pd.yc;
-            pf.thx = (float)thx;
-            pf.thy = (float)thy;
-            pf.zstar = (float)pd.zstar;
-            pf.inv_w0sq = P.inv_w0sqf;
-            pf.inv_zR = P.inv_zRf;
-            const float a0S0f = (float)a0S0;
-            float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
-            // the part of g0 that the FP32 pair cannot hold, restored at the end
-            const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
-            double chd = 0.0;
-            float aS_prev = local ? P.a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
-            RadCell32 carry;
-            if (QUANTUM) rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS_prev * env32[0]), carry);
-            // local amplitude: one spatial factor per step, at psi_{j+2}; the
-            // stage-2/3 value at psi_j + h/2 is the quadratic through psi_j,
-            // psi_{j+1} and psi_{j+2} (error of order h^3 times the third
-            // derivative of S, far below FP32 rounding)
-            float aS_next = local ? P.a0f * pf.S((P.psi0f + P.hf) * P.ellf) : a0S0f;
-            for (int j = 0; j < N; ++j) {
-                float aSh = a0S0f, aS4 = a0S0f;
-                if (local && P.mid_interp) {
-                    const float psi2 = fmaf((float)(j + 2), P.hf, P.psi0f);
-                    const float aS_far = P.a0f * pf.S(psi2 * P.ellf);
-                    aS4 = aS_next;
-                    aSh = fmaf(0.375f, aS_prev, fmaf(0.75f, aS4, -0.125f * aS_far));
-                    aS_next = aS_far;
-                } else if (local) {  // coarse steps: both points exactly
-                    const float psi = fmaf((float)j, P.hf, P.psi0f);
-                    aSh = P.a0f * pf.S(fmaf(0.5f, P.hf, psi) * P.ellf);
-                    aS4 = P.a0f * pf.S((psi + P.hf) * P.ellf);
-                }
-                const float a1 = aS_prev * env32[2 * j];
-                const float ah = aSh * env32[2 * j + 1];
-                const float a4 = aS4 * env32[2 * j + 2];
-                const float chi1 = phf.two_over_aS * mu * fabsf(a1);
-                cmx = fmaxf(cmx, chi1);
-                bool promote = false;
-                if (PREC == PREC_F32MIX) promote = __any(chi1 > P.chi_fp64);
-                if (promote) {
-                    // the whole wavefront runs this step in FP64 (uniform branch)
-                    const double psid = fma((double)j, P.h, -P.psi_max);
-                    double A1 = a0S0, Ah = a0S0, A4 = a0S0;
-                    if (local) {
-                        A1 = P.a0 * pd.S(psid * P.ell_per_psi);
-                        Ah = P.a0 * pd.S(fma(0.5, P.h, psid) * P.ell_per_psi);
-                        A4 = P.a0 * pd.S((psid + P.h) * P.ell_per_psi);
-                    }
-                    A1 *= env64[2 * j];
-                    Ah *= env64[2 * j + 1];
-                    A4 *= env64[2 * j + 2];
-                    const double mud = (double)mu + (double)mu_lo;
-                    const double s2d = (double)s2 + (double)s2_lo;
-                    double dm, ds;
-                    rk4_increment<double, QUANTUM>(mud, s2d, A1, Ah, A4, P.h, phd, tabd, dm, ds,
-                                                   chd);
-                    const double mn = mud + dm, sn = s2d + ds;
-                    mu = (float)mn;
-                    mu_lo = (float)(mn - (double)mu);
-                    s2 = (float)sn;
-                    s2_lo = (float)(sn - (double)s2);
-                    // the next FP32 stage 1 needs the cell at the new state
-                    rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS4 * env32[2 * j + 2]), carry);
-                } else if (QUANTUM) {
-                    float dm, ds;
-                    rk4_q32(mu, s2, a1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
-                    comp_add(mu, mu_lo, dm);
-                    comp_add(s2, s2_lo, ds);
-                } else {
-                    float dm, ds;
-                    rk4_increment<float, false>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds,
-                                                chi_hi);
-                    comp_add(mu, mu_lo, dm);
-                }
-                aS_prev = aS4;
-            }
-            mu_f = ((double)mu + (double)mu_lo) + g0_rest;
-            s2_f = (double)s2 + (double)s2_lo;
-            chi_hi = fmaxf(chi_hi, (float)chd);
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_items) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sp = P.shots[s];
+        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        if (i < sp.n_samples) {
+            int flags = 0;
+            phase_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, flags);
+            if (flags) atomicOr(&P.flags[s], flags);
         }
-        {
-            // chi at the end of the last step (the pulse tail)
-            const double aN = (local ? P.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * env64[2 * N];
-            cmx = fmaxf(cmx, (float)(P.two_over_aS * mu_f * fabs(aN)));
-        }
-        if (QUANTUM && !(chi_hi < chi_top)) flags |= kFlagRange;
-        if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) flags |= kFlagNonFinite;
-        P.st.mu[i] = mu_f;
-        P.st.s2[i] = s2_f;
-        P.st.S0[i] = S0;
-        P.st.g0[i] = g0;
-        P.st.thx[i] = thx;
-        P.st.thy[i] = thy;
-        P.st.cmx[i] = cmx;
     }
-    if (flags) atomicOr(P.flags, flags);
 }
 
 // ===========================================================================
@@ -620,136 +664,157 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-__global__ __launch_bounds__(kDepBlock) void deposit_kernel(DepParams P) {
+__global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);
-    const int nh_e = P.n_e + 2, nh_t = P.n_th + 2, nh = nh_e + nh_t + P.n_a;
-    for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0ull;
-    __syncthreads();
-
-    double acc[P_N];
-#pragma unroll
-    for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
-    float chimax = 0.0f;
-    int flags = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n_samples; i += stride) {
-        const double mu_f = P.st.mu[i], s2_f = P.st.s2[i], S0 = P.st.S0[i], g0 = P.st.g0[i];
-        const double thx_m = 1e3 * P.st.thx[i], thy_m = 1e3 * P.st.thy[i];
-        const float cmx = P.st.cmx[i];
-        if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
-            flags |= kFlagNonFinite;  // also raised by the phase kernel
-            continue;
-        }
-        chimax = fmaxf(chimax, cmx);
-        // Sec. 5.2: the direction is kept, the stochastic broadening
-        // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
-        const double sigf = sqrt(fmax(s2_f, 0.0));
-        const double a_eff = P.a0 * S0;
-        const double sigth = 1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
-
-        deposit_law(mu_f, sigf, P.deposit, P.ksig_bins, P.e_lo, P.e_w, P.n_e, hist);
-        deposit_law(thx_m, sigth, P.deposit, P.ksig_bins, P.th_lo, P.th_w, P.n_th, hist + nh_e);
-        {
-            int ka = (int)floor(S0 * (double)P.n_a);
-            ka = min(max(ka, 0), P.n_a - 1);
-            atomicAdd(&hist[nh_e + nh_t + ka], kOne);
-        }
-        const double de = mu_f - P.gamma0;
-        acc[P_S1E] += de;
-        acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
-        acc[P_S1X] += thx_m;
-        acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
-        acc[P_S1Y] += thy_m;
-        acc[P_S2Y] += thy_m * thy_m;
-        acc[P_SAEFF] += a_eff;
-        acc[P_SRAD] += 1.0 - mu_f / g0;
-        acc[P_SSIGF] += sigf;
-
-        if (P.rec != nullptr && i % P.rec_stride == 0 && i / P.rec_stride < P.rec_n) {
-            double *r = P.rec + (i / P.rec_stride) * 11;
-            r[0] = mu_f;
-            r[1] = s2_f;
-            r[2] = thx_m;
-            r[3] = thy_m;
-            r[4] = sigth;
-            r[5] = a_eff;
-            r[6] = cmx;
-            r[7] = g0;
-            r[8] = 0.0;
-            r[9] = 0.0;
-            r[10] = 0.0;
-        }
-    }
-
-    // ---- block reduction of moments (fixed order) ----
+    __shared__ int64_t slot;
     __shared__ double red[kDepBlock / 64][P_N];
     __shared__ float redmax[kDepBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (;;) {
+        const int64_t item = next_item(&P.queue[1], &slot);
+        if (item >= P.n_ditems) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, true));
+        const ShotParams &sp = P.shots[s];
+        const ShotOut &so = P.outs[s];
+        const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2, nh = nh_e + nh_t + sp.n_a;
+        for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0ull;
+        __syncthreads();
+
+        double acc[P_N];
 #pragma unroll
-    for (int m = 0; m < P_N; ++m) {
-        const double v = wave_sum(acc[m]);
-        if (lane == 0) red[wid][m] = v;
-    }
-    const float wm = wave_max(chimax);
-    if (lane == 0) redmax[wid] = wm;
-    if (flags) atomicOr(P.flags, flags);
-    __syncthreads();
-    if (threadIdx.x < P_N) {
-        double s = 0.0;
-        for (int w = 0; w < kDepBlock / 64; ++w) s += red[w][threadIdx.x];
-        P.partials[(size_t)blockIdx.x * P_N + threadIdx.x] = s;
-    }
-    if (threadIdx.x == 0) {
-        float m = 0.0f;
-        for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
-        atomicMax(P.chimax_bits, __float_as_uint(m));
-    }
-    for (int k = threadIdx.x; k < nh; k += blockDim.x) {
-        const unsigned long long v = hist[k];
-        if (v) atomicAdd(&P.hist[k], v);
+        for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
+        float chimax = 0.0f;
+        int flags = 0;
+        const int64_t i0 = (item - sp.ditem0) * kDepTile;
+        const int64_t i1 = i0 + kDepTile < sp.n_samples ? i0 + kDepTile : sp.n_samples;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            const int64_t k = sp.state_off + i;
+            const double mu_f = P.st.mu[k], s2_f = P.st.s2[k], S0 = P.st.S0[k], g0 = P.st.g0[k];
+            const double thx_m = 1e3 * P.st.thx[k], thy_m = 1e3 * P.st.thy[k];
+            const float cmx = P.st.cmx[k];
+            if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
+                flags |= kFlagNonFinite;  // also raised by the phase kernel
+                continue;
+            }
+            chimax = fmaxf(chimax, cmx);
+            // Sec. 5.2: the direction is kept, the stochastic broadening
+            // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
+            const double sigf = sqrt(fmax(s2_f, 0.0));
+            const double a_eff = sp.a0 * S0;
+            const double sigth =
+                1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
+
+            deposit_law(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e, hist);
+            deposit_law(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w, sp.n_th,
+                        hist + nh_e);
+            {
+                int ka = (int)floor(S0 * (double)sp.n_a);
+                ka = min(max(ka, 0), sp.n_a - 1);
+                atomicAdd(&hist[nh_e + nh_t + ka], kOne);
+            }
+            const double de = mu_f - sp.gamma0;
+            acc[P_S1E] += de;
+            acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
+            acc[P_S1X] += thx_m;
+            acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
+            acc[P_S1Y] += thy_m;
+            acc[P_S2Y] += thy_m * thy_m;
+            acc[P_SAEFF] += a_eff;
+            acc[P_SRAD] += 1.0 - mu_f / g0;
+            acc[P_SSIGF] += sigf;
+
+            if (so.samples != nullptr && i % so.rec_stride == 0 && i / so.rec_stride < so.rec_n) {
+                double *r = so.samples + (i / so.rec_stride) * 11;
+                r[0] = mu_f;
+                r[1] = s2_f;
+                r[2] = thx_m;
+                r[3] = thy_m;
+                r[4] = sigth;
+                r[5] = a_eff;
+                r[6] = cmx;
+                r[7] = g0;
+                r[8] = 0.0;
+                r[9] = 0.0;
+                r[10] = 0.0;
+            }
+        }
+
+        // ---- item reduction of moments (fixed order) ----
+#pragma unroll
+        for (int m = 0; m < P_N; ++m) {
+            const double v = wave_sum(acc[m]);
+            if (lane == 0) red[wid][m] = v;
+        }
+        const float wm = wave_max(chimax);
+        if (lane == 0) redmax[wid] = wm;
+        if (flags) atomicOr(&P.flags[s], flags);
+        __syncthreads();
+        double *part = P.partials + (size_t)item * kPartials;
+        if (threadIdx.x < P_N) {
+            double sum = 0.0;
+            for (int w = 0; w < kDepBlock / 64; ++w) sum += red[w][threadIdx.x];
+            part[threadIdx.x] = sum;
+        }
+        if (threadIdx.x == 0) {
+            float m = 0.0f;
+            for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
+            part[P_N] = m;
+        }
+        for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+            const unsigned long long v = hist[k];
+            if (v) atomicAdd(&P.hist[sp.hist_off + k], v);
+        }
+        __syncthreads();  // the next item clears the LDS histogram
     }
 }
 
 // ===========================================================================
-// Finalize: fixed-order reduction of the block partials, histogram scaling
+// Finalize: one block per shot, fixed-order reduction of its item partials
 // ===========================================================================
-__global__ __launch_bounds__(256) void finalize_kernel(FinParams F) {
-    __shared__ double sums[P_N];
-    if (threadIdx.x < P_N) {
-        double s = 0.0;
-        for (int b = 0; b < F.nblocks; ++b) s += F.partials[(size_t)b * P_N + threadIdx.x];
-        sums[threadIdx.x] = s;
+__global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
+    const int s = blockIdx.x;
+    const ShotParams &sp = P.shots[s];
+    const ShotOut &so = P.outs[s];
+    const int64_t nd = (sp.n_samples + kDepTile - 1) / kDepTile;
+    __shared__ double sums[kPartials];
+    if (threadIdx.x < kPartials) {
+        double acc = 0.0;
+        for (int64_t b = 0; b < nd; ++b) {
+            const double v = P.partials[(size_t)(sp.ditem0 + b) * kPartials + threadIdx.x];
+            acc = threadIdx.x == P_N ? fmax(acc, v) : acc + v;
+        }
+        sums[threadIdx.x] = acc;
     }
-    const int nh_e = F.n_e + 2, nh_t = F.n_th + 2;
+    const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2;
+    const unsigned long long *H = P.hist + sp.hist_off;
     const double scale = 1.0 / 4294967296.0;
-    for (int k = threadIdx.x; k < nh_e; k += blockDim.x)
-        F.energy_hist[k] = (double)F.hist[k] * scale;
+    for (int k = threadIdx.x; k < nh_e; k += blockDim.x) so.energy_hist[k] = (double)H[k] * scale;
     for (int k = threadIdx.x; k < nh_t; k += blockDim.x)
-        F.angle_hist[k] = (double)F.hist[nh_e + k] * scale;
-    for (int k = threadIdx.x; k < F.n_a; k += blockDim.x)
-        F.a0eff_hist[k] = (double)F.hist[nh_e + nh_t + k] * scale;
+        so.angle_hist[k] = (double)H[nh_e + k] * scale;
+    for (int k = threadIdx.x; k < sp.n_a; k += blockDim.x)
+        so.a0eff_hist[k] = (double)H[nh_e + nh_t + k] * scale;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double *M = F.moments;
+        double *M = so.moments;
         for (int m = 0; m < 16; ++m) M[m] = 0.0;
-        const double W = (double)F.n_samples;
+        const double W = (double)sp.n_samples;
         M[0] = W;
-        if (F.n_samples > 0) {
+        if (sp.n_samples > 0) {
             const double m1 = sums[P_S1E] / W;
-            M[1] = F.gamma0 + m1;
+            M[1] = sp.gamma0 + m1;
             M[2] = sqrt(fmax(sums[P_S2E] / W - m1 * m1, 0.0));
             M[3] = sums[P_S1X] / W;
             M[4] = sqrt(sums[P_S2X] / W);
             M[5] = sums[P_S1Y] / W;
             M[6] = sqrt(sums[P_S2Y] / W);
             M[7] = sums[P_SAEFF] / W;
-            M[8] = (double)__uint_as_float(*F.chimax_bits);
+            M[8] = sums[P_N];
             M[9] = sums[P_SRAD] / W;
             M[10] = sums[P_SSIGF] / W;
         }
-        const int fl = *F.flags;
-        *F.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
+        const int fl = P.flags[s];
+        *so.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
     }
 }
 
@@ -1012,51 +1077,48 @@ static const void *select_phase(int prec, int rr, int amp) {
     return nullptr;
 }
 
-hipError_t launch_phase(const PhaseParams &p, int prec, int rr, int amp, hipStream_t s) {
-    const void *fn = select_phase(prec, rr, amp);
-    if (!fn) return hipErrorInvalidValue;
+static hipError_t resident_grid(const void *fn, int block, size_t lds, int64_t items, int *grid) {
     int device = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPhaseBlock, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
     if (e != hipSuccess) return e;
-    // enough resident blocks to fill the chip; each lane takes samples in a grid stride
-    int64_t grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
-    const int64_t need = (p.n_samples + kPhaseBlock - 1) / kPhaseBlock;
-    if (grid > need) grid = need;
-    PhaseParams pc = p;
-    const float *e32 = p.env32;
-    const double *e64 = p.env64;
+    int64_t g = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
+    if (g > items) g = items;
+    *grid = (int)(g < 1 ? 1 : g);
+    return hipSuccess;
+}
+
+hipError_t launch_phase(const BatchParams &p, const float *env32, const double *env64, int prec,
+                        int rr, int amp, hipStream_t s) {
+    const void *fn = select_phase(prec, rr, amp);
+    if (!fn) return hipErrorInvalidValue;
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    BatchParams pc = p;
+    const float *e32 = env32;
+    const double *e64 = env64;
     void *args[] = {&pc, &e32, &e64};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
-size_t deposit_lds_bytes(int n_e, int n_th, int n_a) { return (size_t)(n_e + 2 + n_th + 2 + n_a) * 8; }
+size_t deposit_lds_bytes(int max_hist_words) { return (size_t)max_hist_words * 8; }
 
-hipError_t deposit_grid(size_t lds_bytes, int device, int64_t n_samples, int *grid) {
+hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t s) {
     const void *fn = reinterpret_cast<const void *>(&deposit_kernel);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const size_t lds = deposit_lds_bytes(max_hist_words);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    int per_cu = 0, ncu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kDepBlock, lds_bytes);
+    int grid = 0;
+    e = resident_grid(fn, kDepBlock, lds, p.n_ditems, &grid);
     if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
-    if (e != hipSuccess) return e;
-    int64_t g = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
-    const int64_t need = (n_samples + kDepBlock - 1) / kDepBlock;
-    if (g > need) g = need;
-    *grid = (int)g;
-    return hipSuccess;
-}
-
-hipError_t launch_deposit(const DepParams &p, int grid, hipStream_t s) {
-    const size_t lds = deposit_lds_bytes(p.n_e, p.n_th, p.n_a);
     deposit_kernel<<<grid, kDepBlock, lds, s>>>(p);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinParams &p, hipStream_t s) {
-    finalize_kernel<<<1, 256, 0, s>>>(p);
+hipError_t launch_finalize(const BatchParams &p, hipStream_t s) {
+    finalize_kernel<<<p.n_shots, 256, 0, s>>>(p);
     return hipGetLastError();
 }
 
