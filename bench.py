@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--chi-fp64", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2,
+                    help="timed launches of the 4096-shot batch (0 skips that leg)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -154,6 +156,29 @@ def main():
                      "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
                                                              params["amp_mode"])]},
     }
+    if args.batched_steps > 0:
+        # batched leg: 4096 shots of uneven size in one launch
+        shots = workloads.batched_shots()
+        batch = ctx.prepare_batch(shots)
+        ctx.run_batch(batch)  # scratch allocation and warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            ctx.run_batch(batch, check=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.batched_steps
+        bad = int(torch.stack([o["status"] for o in batch.out]).max().item())
+        if bad != 0:
+            raise RuntimeError(f"device status {bad} in the batched leg")
+        n_tot = sum(p["n_samples"] for p in shots)
+        line["batched"] = {
+            "workload": "4096 shots, samples log-uniform in [2^12, 2^18], a0 U[5,100], "
+                        "W0 U[2,6]um, offsets N(0,2^2)um, delay N(0,15^2)fs, gamma0 "
+                        "U[1e3,1e4], sigma_gamma 1-10%; 512 steps, quantum, local amplitude",
+            "n_shots": len(shots), "n_samples": n_tot, "n_steps": shots[0]["n_steps"],
+            "steps": args.batched_steps, "ms_per_batch": 1e3 * dt,
+            "spectra_per_s": len(shots) / dt,
+            "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt}
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)

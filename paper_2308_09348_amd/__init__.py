@@ -91,54 +91,64 @@ class Context:
                 raise QScatterError(st, "device status")
         return out
 
-    def forward_batched(self, shots, stream=None, check=True, out=None):
-        """One launch over a list of per-shot parameter dictionaries.  The
-        numerics (steps, seed, models, deposit, precision) come from shots[0];
-        shot k uses RNG counter word shots[0]["shot"] + k.  Returns a list of
-        per-shot result dictionaries (device tensors)."""
+    def prepare_batch(self, shots):
+        """Marshal a list of per-shot parameter dictionaries once (ctypes
+        arrays and output tensors); run it with run_batch().  The numerics
+        (steps, seed, models, deposit, precision) come from shots[0]; shot k
+        uses RNG counter word shots[0]["shot"] + k."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = len(shots)
         if n == 0:
-            return []
-        _, _, nu, _ = _lib.structs(shots[0])
-        lasers = (_lib.Laser * n)()
-        beams = (_lib.Beam * n)()
-        bins = (_lib.Bins * n)()
-        outs = (_lib.Outputs * n)()
-        ns = (ctypes.c_int64 * n)()
-        if out is None:
-            out = []
-            for p in shots:
-                out.append({
-                    "energy_hist": torch.empty(p["n_e"] + 2, dtype=torch.float64, device=dev),
-                    "angle_hist": torch.empty(p["n_th"] + 2, dtype=torch.float64, device=dev),
-                    "a0eff_hist": torch.empty(p["n_a"], dtype=torch.float64, device=dev),
-                    "moments": torch.empty(_lib.M_N, dtype=torch.float64, device=dev),
-                    "status": torch.empty(1, dtype=torch.int32, device=dev)})
+            raise ValueError("empty batch")
+        b = _Batch()
+        _, _, b.nu, _ = _lib.structs(shots[0])
+        b.n = n
+        b.lasers = (_lib.Laser * n)()
+        b.beams = (_lib.Beam * n)()
+        b.bins = (_lib.Bins * n)()
+        b.outs = (_lib.Outputs * n)()
+        b.ns = (ctypes.c_int64 * n)()
+        b.out = []
         for k, p in enumerate(shots):
             la, be, _, bi = _lib.structs(p)
-            lasers[k], beams[k], bins[k] = la, be, bi
-            ns[k] = int(p["n_samples"])
-            o = out[k]
-            outs[k] = _lib.Outputs(
+            b.lasers[k], b.beams[k], b.bins[k] = la, be, bi
+            b.ns[k] = int(p["n_samples"])
+            o = {"energy_hist": torch.empty(p["n_e"] + 2, dtype=torch.float64, device=dev),
+                 "angle_hist": torch.empty(p["n_th"] + 2, dtype=torch.float64, device=dev),
+                 "a0eff_hist": torch.empty(p["n_a"], dtype=torch.float64, device=dev),
+                 "moments": torch.empty(_lib.M_N, dtype=torch.float64, device=dev),
+                 "status": torch.empty(1, dtype=torch.int32, device=dev)}
+            b.out.append(o)
+            b.outs[k] = _lib.Outputs(
                 energy_hist=o["energy_hist"].data_ptr(), angle_hist=o["angle_hist"].data_ptr(),
                 a0eff_hist=o["a0eff_hist"].data_ptr(), moments=o["moments"].data_ptr(),
                 status=o["status"].data_ptr(), samples=None, sample_stride=1,
                 n_sample_records=0)
+        return b
+
+    def run_batch(self, batch, stream=None, check=True):
+        """Enqueue one launch over a prepared batch; returns its outputs."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        st = _lib.lib().qs_forward_batched(self._ptr, n, lasers, beams, ns, ctypes.byref(nu), bins,
-                                           outs, ctypes.c_void_p(stream.cuda_stream))
+        st = _lib.lib().qs_forward_batched(self._ptr, batch.n, batch.lasers, batch.beams,
+                                           batch.ns, ctypes.byref(batch.nu), batch.bins,
+                                           batch.outs, ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         if check:
             torch.cuda.synchronize(dev)
-            status = torch.stack([o["status"] for o in out]).cpu()
-            bad = int(status.max())
+            bad = int(torch.stack([o["status"] for o in batch.out]).max().item())
             if bad != _lib.QS_OK:
                 raise QScatterError(bad, "device status of a shot")
-        return out
+        return batch.out
+
+    def forward_batched(self, shots, stream=None, check=True):
+        """One launch over a list of per-shot parameter dictionaries; returns a
+        list of per-shot result dictionaries (device tensors)."""
+        return self.run_batch(self.prepare_batch(shots), stream=stream, check=check)
 
     def set_profiling(self, on=True):
         st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)
@@ -168,6 +178,10 @@ class Context:
             raise QScatterError(st, self.last_error())
         torch.cuda.synchronize(chi.device)
         return out
+
+
+class _Batch:
+    """Marshalled arguments and output tensors of a batched launch."""
 
 
 _default = {}

@@ -778,13 +778,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
     const ShotOut &so = P.outs[s];
     const int64_t nd = (sp.n_samples + kDepTile - 1) / kDepTile;
     __shared__ double sums[kPartials];
-    if (threadIdx.x < kPartials) {
+    __shared__ double tree[256];
+    // each column: thread t sums items t, t + 256, ... then a fixed tree
+    for (int m = 0; m < kPartials; ++m) {
         double acc = 0.0;
-        for (int64_t b = 0; b < nd; ++b) {
-            const double v = P.partials[(size_t)(sp.ditem0 + b) * kPartials + threadIdx.x];
-            acc = threadIdx.x == P_N ? fmax(acc, v) : acc + v;
+        for (int64_t b = threadIdx.x; b < nd; b += blockDim.x) {
+            const double v = P.partials[(size_t)(sp.ditem0 + b) * kPartials + m];
+            acc = m == P_N ? fmax(acc, v) : acc + v;
         }
-        sums[threadIdx.x] = acc;
+        tree[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                const double o = tree[threadIdx.x + w];
+                tree[threadIdx.x] = m == P_N ? fmax(tree[threadIdx.x], o) : tree[threadIdx.x] + o;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sums[m] = tree[0];
+        __syncthreads();
     }
     const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2;
     const unsigned long long *H = P.hist + sp.hist_off;
