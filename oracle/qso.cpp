@@ -28,6 +28,69 @@ const double kAlpha = 7.2973525693e-3;            /* fine-structure constant */
 const double kLambdaBarC_um = 3.8615926796e-7;    /* reduced Compton wavelength */
 const double kC_um_per_fs = 0.299792458;          /* speed of light          */
 
+/* ---- forward-mode dual numbers ----------------------------------------- */
+/* A value and its derivatives with respect to the eight differentiable
+ * parameters (a0, w0, x_off, y_off, delay, gamma0, sigma_gamma, divergence).
+ * The per-sample path below is written once for a scalar type T and
+ * instantiated with double (the forward pass) and with Dual (its exact
+ * derivative, by the chain rule applied operation by operation). */
+const int kNP = 8;
+struct Dual {
+    double v;
+    double d[kNP];
+    Dual(double x = 0.0) : v(x) { for (int k = 0; k < kNP; ++k) d[k] = 0.0; }
+};
+inline double val(double x) { return x; }
+inline double val(const Dual &x) { return x.v; }
+inline Dual operator+(const Dual &a, const Dual &b) {
+    Dual r(a.v + b.v); for (int k = 0; k < kNP; ++k) r.d[k] = a.d[k] + b.d[k]; return r;
+}
+inline Dual operator-(const Dual &a, const Dual &b) {
+    Dual r(a.v - b.v); for (int k = 0; k < kNP; ++k) r.d[k] = a.d[k] - b.d[k]; return r;
+}
+inline Dual operator-(const Dual &a) {
+    Dual r(-a.v); for (int k = 0; k < kNP; ++k) r.d[k] = -a.d[k]; return r;
+}
+inline Dual operator*(const Dual &a, const Dual &b) {
+    Dual r(a.v * b.v); for (int k = 0; k < kNP; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r;
+}
+inline Dual operator/(const Dual &a, const Dual &b) {
+    Dual r(a.v / b.v);
+    for (int k = 0; k < kNP; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+inline Dual operator+(const Dual &a, double b) { Dual r = a; r.v += b; return r; }
+inline Dual operator+(double a, const Dual &b) { return b + a; }
+inline Dual operator-(const Dual &a, double b) { Dual r = a; r.v -= b; return r; }
+inline Dual operator-(double a, const Dual &b) { return -b + a; }
+inline Dual operator*(const Dual &a, double b) {
+    Dual r(a.v * b); for (int k = 0; k < kNP; ++k) r.d[k] = a.d[k] * b; return r;
+}
+inline Dual operator*(double a, const Dual &b) { return b * a; }
+inline Dual operator/(const Dual &a, double b) {
+    Dual r(a.v / b); for (int k = 0; k < kNP; ++k) r.d[k] = a.d[k] / b; return r;
+}
+inline Dual operator/(double a, const Dual &b) { return Dual(a) / b; }
+inline Dual &operator+=(Dual &a, const Dual &b) { a = a + b; return a; }
+inline Dual chain(const Dual &a, double f, double df) {
+    Dual r(f); for (int k = 0; k < kNP; ++k) r.d[k] = df * a.d[k]; return r;
+}
+inline Dual exp(const Dual &a) { const double e = std::exp(a.v); return chain(a, e, e); }
+inline Dual log(const Dual &a) { return chain(a, std::log(a.v), 1.0 / a.v); }
+inline Dual sqrt(const Dual &a) {
+    if (a.v == 0.0) return Dual(0.0);  /* sqrt(max(sig2, 0)) at sig2 = 0: flat */
+    const double s = std::sqrt(a.v);
+    return chain(a, s, 0.5 / s);
+}
+inline Dual fabs(const Dual &a) { return a.v < 0 ? -a : a; }
+inline Dual erfc(const Dual &a) {
+    return chain(a, std::erfc(a.v), -2.0 / std::sqrt(kPi) * std::exp(-a.v * a.v));
+}
+inline Dual fmax(const Dual &a, const Dual &b) { return a.v >= b.v ? a : b; }
+inline Dual fmin(const Dual &a, const Dual &b) { return a.v <= b.v ? a : b; }
+using std::exp; using std::log; using std::sqrt; using std::fabs; using std::erfc;
+using std::fmax; using std::fmin;
+
 /* ---- Philox4x32-10 ----------------------------------------------------- */
 /* Counter-based generator of Salmon et al. (SC'11): ten rounds of two
  * 32x32->64 multiplies with the key bumped by the Weyl constants between
@@ -124,12 +187,13 @@ double envelope_carrier(const qso_problem *p, const Derived &d, double psi) {
 /* eq. a0eff: the focused Gaussian spatial factor a/a0 at (rho, z); the laser
  * phase and wavefront curvature are neglected as in Sec. 2.  w0 = 0 selects a
  * plane wave. */
-double spatial(const qso_problem *p, const Derived &d, double x, double y, double z) {
-    if (p->w0_um == 0.0) return 1.0;
-    const double zz = z / d.zR;
-    const double q = 1.0 + zz * zz;
-    const double r2 = (x * x + y * y) / (p->w0_um * p->w0_um);
-    return std::exp(-r2 / q) / std::sqrt(q);
+template <class T>
+T spatial(const T &w0, const T &zR, const T &x, const T &y, const T &z) {
+    if (val(w0) == 0.0) return T(1.0);
+    const T zz = z / zR;
+    const T q = 1.0 + zz * zz;
+    const T r2 = (x * x + y * y) / (w0 * w0);
+    return exp(-r2 / q) / sqrt(q);
 }
 
 /* ---- radiation functions g(chi), h(chi) -------------------------------- */
@@ -231,31 +295,32 @@ const RadTable &table() {
 }
 
 /* g, chi g', chi^2 g'', h at chi >= 0 (4-point Lagrange in u). */
-void radiation(double chi, double out[4]) {
-    if (!(chi >= 0.0)) {  /* a negative energy or amplitude: no physical chi */
-        out[0] = out[1] = out[2] = out[3] = NAN;
+template <class T>
+void radiation(const T &chi, T out[4]) {
+    if (!(val(chi) >= 0.0)) {  /* a negative energy or amplitude: no physical chi */
+        out[0] = out[1] = out[2] = out[3] = T(NAN);
         return;
     }
-    if (chi < kChiMin) {
+    if (val(chi) < kChiMin) {
         out[0] = 1.0 + kG1 * chi + kG2 * chi * chi;
         out[1] = kG1 * chi + 2.0 * kG2 * chi * chi;
         out[2] = 2.0 * kG2 * chi * chi;
         out[3] = 1.0 + kH1 * chi;
         return;
     }
-    if (!(chi <= kChiMax)) {
-        out[0] = out[1] = out[2] = out[3] = NAN;
+    if (!(val(chi) <= kChiMax)) {
+        out[0] = out[1] = out[2] = out[3] = T(NAN);
         return;
     }
     const RadTable &t = table();
-    const double s = (std::log(chi) - t.u0) / t.du;
-    const int i = (int)std::floor(s);
-    const double x = s - i;
-    const double w[4] = {-x * (x - 1) * (x - 2) / 6.0, (x + 1) * (x - 1) * (x - 2) / 2.0,
-                         -(x + 1) * x * (x - 2) / 2.0, (x + 1) * x * (x - 1) / 6.0};
+    const T s = (log(chi) - t.u0) / t.du;
+    const int i = (int)std::floor(val(s));
+    const T x = s - (double)i;
+    const T w[4] = {-x * (x - 1.0) * (x - 2.0) / 6.0, (x + 1.0) * (x - 1.0) * (x - 2.0) / 2.0,
+                    -(x + 1.0) * x * (x - 2.0) / 2.0, (x + 1.0) * x * (x - 1.0) / 6.0};
     const std::vector<double> *cols[4] = {&t.g, &t.G1, &t.G2, &t.h};
     for (int c = 0; c < 4; ++c) {
-        double acc = 0.0;
+        T acc(0.0);
         for (int m = 0; m < 4; ++m) acc += w[m] * (*cols[c])[i - 1 + m];
         out[c] = acc;
     }
@@ -268,30 +333,54 @@ void radiation(double chi, double out[4]) {
  *   dmu/dpsi   = A(mu) + A''(mu) sig2 / 2,
  *   dsig2/dpsi = 2 A'(mu) sig2 + D(mu),
  * with chi = 2 mu |a| / a_S.  The classical model is g = 1, D = 0.          */
-struct Rhs { double A, A1, A2, D, dmu, dsig2; };
+template <class T>
+struct Rhs { T A, A1, A2, D, dmu, dsig2; };
 
-Rhs rhs(const qso_problem *p, const Derived &d, double mu, double sig2, double a) {
-    double g = 1.0, G1 = 0.0, G2 = 0.0, hq = 0.0;
-    const double abs_a = std::fabs(a);
+template <class T>
+Rhs<T> rhs(const qso_problem *p, const Derived &d, const T &mu, const T &sig2, const T &a) {
+    T g(1.0), G1(0.0), G2(0.0), hq(0.0);
+    const T abs_a = fabs(a);
     if (p->rr_model == QSO_RR_QUANTUM) {
-        double rf[4];
-        radiation(2.0 * mu * abs_a / d.aS, rf);
+        T rf[4];
+        radiation<T>(2.0 * mu * abs_a / d.aS, rf);
         g = rf[0]; G1 = rf[1]; G2 = rf[2]; hq = rf[3];
     }
-    Rhs r;
-    const double a2 = a * a;
+    Rhs<T> r;
+    const T a2 = a * a;
     r.A = -d.K * a2 * mu * mu * g;
     r.A1 = -d.K * a2 * mu * (2.0 * g + G1);
     r.A2 = -d.K * a2 * (2.0 * g + 4.0 * G1 + G2);
-    r.D = (p->rr_model == QSO_RR_QUANTUM) ? d.CD * a2 * abs_a * mu * mu * mu * mu * hq : 0.0;
+    r.D = (p->rr_model == QSO_RR_QUANTUM) ? d.CD * a2 * abs_a * mu * mu * mu * mu * hq : T(0.0);
     r.dmu = r.A + 0.5 * r.A2 * sig2;
     r.dsig2 = 2.0 * r.A1 * sig2 + r.D;
     return r;
 }
 
 /* ---- one sample -------------------------------------------------------- */
+/* The eight parameters a derivative can be taken with respect to. */
+template <class T>
+struct Params {
+    T a0, w0, x_off, y_off, delay, gamma0, sigma_gamma, div_mrad;
+    T zR;  /* Rayleigh length pi w0^2 / lambda */
+};
+
+template <class T>
+Params<T> params(const qso_problem *p) {
+    Params<T> P;
+    P.a0 = p->a0; P.w0 = p->w0_um; P.x_off = p->x_off_um; P.y_off = p->y_off_um;
+    P.delay = p->delay_fs; P.gamma0 = p->gamma0; P.sigma_gamma = p->sigma_gamma;
+    P.div_mrad = p->div_mrad;
+    return P;
+}
+
+template <class T>
+void finish_params(const qso_problem *p, Params<T> &P) {
+    P.zR = kPi * P.w0 * P.w0 / p->lambda_um;
+}
+
+template <class T>
 struct SampleIn {
-    double x, y, z, gamma0, thx, thy;  /* um, um, um, -, rad, rad */
+    T x, y, z, gamma0, thx, thy;  /* um, um, um, -, rad, rad */
 };
 
 void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
@@ -312,82 +401,92 @@ void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
     }
 }
 
-SampleIn make_sample(const qso_problem *p, int64_t i) {
+template <class T>
+SampleIn<T> make_sample(const qso_problem *p, const Params<T> &P, int64_t i) {
     double n[6];
     normals(p->seed, p->shot, i, n);
-    SampleIn s;
-    s.x = p->x_off_um + p->sigma_r_um * n[0];
-    s.y = p->y_off_um + p->sigma_r_um * n[1];
-    s.z = p->sigma_z_um * n[2];
-    s.gamma0 = p->gamma0 + p->sigma_gamma * n[3];
-    s.thx = 1e-3 * p->div_mrad * n[4];
-    s.thy = 1e-3 * p->div_mrad * n[5];
+    SampleIn<T> s;
+    s.x = P.x_off + p->sigma_r_um * n[0];
+    s.y = P.y_off + p->sigma_r_um * n[1];
+    s.z = T(p->sigma_z_um * n[2]);
+    s.gamma0 = P.gamma0 + P.sigma_gamma * n[3];
+    s.thx = 1e-3 * P.div_mrad * n[4];
+    s.thy = 1e-3 * P.div_mrad * n[5];
     return s;
 }
 
-/* Ballistic geometry (Sec. 6: probe particles on ballistic trajectories).
- * The laser moves along +z with its peak at z = c t and focus at z = 0; the
- * beam moves along -z and its centroid meets the peak at t = delay/2, at
- * z = c delay / 2.  Sample coordinates (x, y) are taken at that instant.
- * A sample at longitudinal offset z meets the peak at z* = (z + c delay)/2;
- * at phase psi it has travelled l = c psi / (2 w0) = psi lambda / (4 pi)
- * past that point.                                                         */
+/* Ballistic geometry (probe particles on ballistic trajectories, as the
+ * conclusions restate).  The laser moves along +z with its peak at z = c t
+ * and focus at z = 0; the beam moves along -z and its centroid meets the
+ * peak at t = delay/2, at z = c delay / 2.  Sample coordinates (x, y) are
+ * taken at that instant.  A sample at longitudinal offset z meets the peak at
+ * z* = (z + c delay)/2; at phase psi it has travelled l = c psi / (2 w0) =
+ * psi lambda / (4 pi) past that point.                                     */
+template <class T>
 struct Geometry {
-    double zstar;  /* collision point on the axis [um]                       */
-    double S0;     /* spatial factor at the collision point                   */
+    T zstar;  /* collision point on the axis [um]                            */
+    T S0;     /* spatial factor at the collision point                        */
 };
 
-Geometry geometry(const qso_problem *p, const Derived &d, const SampleIn &s) {
-    Geometry gmt;
-    gmt.zstar = 0.5 * (s.z + kC_um_per_fs * p->delay_fs);
-    const double xc = s.x + s.thx * 0.5 * s.z;
-    const double yc = s.y + s.thy * 0.5 * s.z;
-    gmt.S0 = spatial(p, d, xc, yc, gmt.zstar);
+template <class T>
+Geometry<T> geometry(const qso_problem *p, const Params<T> &P, const SampleIn<T> &s) {
+    Geometry<T> gmt;
+    gmt.zstar = 0.5 * (s.z + kC_um_per_fs * P.delay);
+    const T xc = s.x + s.thx * 0.5 * s.z;
+    const T yc = s.y + s.thy * 0.5 * s.z;
+    gmt.S0 = spatial<T>(P.w0, P.zR, xc, yc, gmt.zstar);
+    (void)p;
     return gmt;
 }
 
-double amplitude(const qso_problem *p, const Derived &d, const SampleIn &s,
-                 const Geometry &gmt, double psi) {
-    double S;
+template <class T>
+T amplitude(const qso_problem *p, const Derived &d, const Params<T> &P, const SampleIn<T> &s,
+            const Geometry<T> &gmt, double psi) {
+    T S;
     if (p->amp_mode == QSO_AMP_A0EFF) {
         /* Sec. 2: the sample is assigned the peak amplitude it meets, a0,eff */
         S = gmt.S0;
     } else {
         const double l = psi * p->lambda_um / (4.0 * kPi);
-        S = spatial(p, d, s.x + s.thx * (0.5 * s.z + l), s.y + s.thy * (0.5 * s.z + l),
-                    gmt.zstar - l);
+        S = spatial<T>(P.w0, P.zR, s.x + s.thx * (0.5 * s.z + l), s.y + s.thy * (0.5 * s.z + l),
+                       gmt.zstar - l);
     }
-    return p->a0 * S * envelope_carrier(p, d, psi);
+    return P.a0 * S * envelope_carrier(p, d, psi);
 }
 
+template <class T>
 struct SampleOut {
-    double mu, sig2, thx, thy, sigth, aeff_ratio, chimax, gamma0, x, y, z;
+    T mu, sig2, thx, thy, sigth, aeff_ratio;
+    double chimax;
+    T gamma0, x, y, z;
 };
 
-SampleOut run_sample(const qso_problem *p, const Derived &d, int64_t i) {
-    const SampleIn s = make_sample(p, i);
-    const Geometry gmt = geometry(p, d, s);
-    double mu = s.gamma0, sig2 = 0.0, chimax = 0.0;
+template <class T>
+SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i) {
+    const SampleIn<T> s = make_sample<T>(p, P, i);
+    const Geometry<T> gmt = geometry<T>(p, P, s);
+    T mu = s.gamma0, sig2(0.0);
+    double chimax = 0.0;
     const double h = d.h;
     for (int j = 0; j < p->n_steps; ++j) {
         /* classical fourth-order Runge-Kutta in psi on (mu, sig2) */
         const double psi = -d.psi_max + j * h;
-        const double a1 = amplitude(p, d, s, gmt, psi);
-        const double ah = amplitude(p, d, s, gmt, psi + 0.5 * h);
-        const double a4 = amplitude(p, d, s, gmt, psi + h);
-        chimax = std::fmax(chimax, 2.0 * mu * std::fabs(a1) / d.aS);
-        const Rhs k1 = rhs(p, d, mu, sig2, a1);
-        const Rhs k2 = rhs(p, d, mu + 0.5 * h * k1.dmu, sig2 + 0.5 * h * k1.dsig2, ah);
-        const Rhs k3 = rhs(p, d, mu + 0.5 * h * k2.dmu, sig2 + 0.5 * h * k2.dsig2, ah);
-        const Rhs k4 = rhs(p, d, mu + h * k3.dmu, sig2 + h * k3.dsig2, a4);
+        const T a1 = amplitude<T>(p, d, P, s, gmt, psi);
+        const T ah = amplitude<T>(p, d, P, s, gmt, psi + 0.5 * h);
+        const T a4 = amplitude<T>(p, d, P, s, gmt, psi + h);
+        chimax = std::fmax(chimax, 2.0 * val(mu) * std::fabs(val(a1)) / d.aS);
+        const Rhs<T> k1 = rhs<T>(p, d, mu, sig2, a1);
+        const Rhs<T> k2 = rhs<T>(p, d, mu + 0.5 * h * k1.dmu, sig2 + 0.5 * h * k1.dsig2, ah);
+        const Rhs<T> k3 = rhs<T>(p, d, mu + 0.5 * h * k2.dmu, sig2 + 0.5 * h * k2.dsig2, ah);
+        const Rhs<T> k4 = rhs<T>(p, d, mu + h * k3.dmu, sig2 + h * k3.dsig2, a4);
         mu += h / 6.0 * (k1.dmu + 2.0 * k2.dmu + 2.0 * k3.dmu + k4.dmu);
         sig2 += h / 6.0 * (k1.dsig2 + 2.0 * k2.dsig2 + 2.0 * k3.dsig2 + k4.dsig2);
     }
     {
-        const double aN = amplitude(p, d, s, gmt, d.psi_max);
-        chimax = std::fmax(chimax, 2.0 * mu * std::fabs(aN) / d.aS);
+        const T aN = amplitude<T>(p, d, P, s, gmt, d.psi_max);
+        chimax = std::fmax(chimax, 2.0 * val(mu) * std::fabs(val(aN)) / d.aS);
     }
-    SampleOut o;
+    SampleOut<T> o;
     o.mu = mu;
     o.sig2 = sig2;
     /* The photon recoil of an ultra-relativistic emitter is along its
@@ -397,8 +496,8 @@ SampleOut run_sample(const qso_problem *p, const Derived &d, int64_t i) {
      * gamma_f^2.                                                           */
     o.thx = 1e3 * s.thx;
     o.thy = 1e3 * s.thy;
-    const double sigf = std::sqrt(std::fmax(sig2, 0.0));
-    const double aeff = p->a0 * gmt.S0;
+    const T sigf = sqrt(fmax(sig2, T(0.0)));
+    const T aeff = P.a0 * gmt.S0;
     o.sigth = 1e3 * p->c_theta * std::sqrt(2.0 / kPi) * aeff * sigf / (mu * mu);
     o.aeff_ratio = gmt.S0;
     o.chimax = chimax;
@@ -407,75 +506,89 @@ SampleOut run_sample(const qso_problem *p, const Derived &d, int64_t i) {
     return o;
 }
 
+SampleOut<double> run_sample(const qso_problem *p, const Derived &d, int64_t i) {
+    Params<double> P = params<double>(p);
+    finish_params(p, P);
+    return run_sample<double>(p, d, P, i);
+}
+
 /* ---- deposit ------------------------------------------------------------ */
-double Phi(double t) { return 0.5 * std::erfc(-t / std::sqrt(2.0)); }
-double PhiC(double t) { return 0.5 * std::erfc(t / std::sqrt(2.0)); }
-double phi(double t) { return std::exp(-0.5 * t * t) / std::sqrt(2.0 * kPi); }
+template <class T> T Phi(const T &t) { return 0.5 * erfc(-t / std::sqrt(2.0)); }
+template <class T> T PhiC(const T &t) { return 0.5 * erfc(t / std::sqrt(2.0)); }
+template <class T> T phi(const T &t) { return exp(-0.5 * t * t) / std::sqrt(2.0 * kPi); }
 
 /* The law deposited by one sample is its own energy (or angle) law -- a point
  * at v when s = 0, else N(v, s^2) -- convolved with the deposit kernel
  * (POINT: none, CIC: a box one bin wide, GAUSS: N(0, (k bins)^2)); each bin
  * gets that law's mass over it, so a sample always adds exactly one unit.
  * cdf(x) returns P(X <= x), ccdf(x) returns P(X > x).                       */
+template <class T>
 struct Law {
     int mode;  /* 0 step, 1 box, 2 gauss, 3 box (x) gauss */
-    double v, s, half;
+    T v, s;
+    double half;
 };
 
-Law make_law(double v, double s, int32_t deposit, double ksig_bins, double width) {
-    Law L;
+template <class T>
+Law<T> make_law(const T &v, const T &s, int32_t deposit, double ksig_bins, double width) {
+    Law<T> L;
     L.v = v;
     L.half = 0.5 * width;
     if (deposit == QSO_DEP_GAUSS) {
         const double ks = ksig_bins * width;
-        L.s = std::sqrt(s * s + ks * ks);
-        L.mode = L.s > 0 ? 2 : 0;
+        L.s = sqrt(s * s + ks * ks);
+        L.mode = val(L.s) > 0 ? 2 : 0;
     } else if (deposit == QSO_DEP_CIC) {
         L.s = s;
-        L.mode = s > 0 ? 3 : 1;
+        L.mode = val(s) > 0 ? 3 : 1;
     } else {
         L.s = s;
-        L.mode = s > 0 ? 2 : 0;
+        L.mode = val(s) > 0 ? 2 : 0;
     }
     return L;
 }
 
 /* Psi(t) = Int_-inf^t Phi(u/s) du = t Phi(t/s) + s phi(t/s);
  * PsiC(t) = Psi(t) - t = -t PhiC(t/s) + s phi(t/s).                        */
-double Psi(double t, double s) { return t * Phi(t / s) + s * phi(t / s); }
-double PsiC(double t, double s) { return -t * PhiC(t / s) + s * phi(t / s); }
+template <class T> T Psi(const T &t, const T &s) { return t * Phi<T>(t / s) + s * phi<T>(t / s); }
+template <class T> T PsiC(const T &t, const T &s) {
+    return -t * PhiC<T>(t / s) + s * phi<T>(t / s);
+}
 
-double law_cdf(const Law &L, double x) {
-    const double t = x - L.v;
+template <class T>
+T law_cdf(const Law<T> &L, double x) {
+    const T t = x - L.v;
     switch (L.mode) {
-        case 0: return t > 0 ? 1.0 : 0.0;  /* NGP: floor((v - lo) / width) */
-        case 1: return std::fmin(1.0, std::fmax(0.0, t / (2 * L.half) + 0.5));
-        case 2: return Phi(t / L.s);
-        default: return (Psi(t + L.half, L.s) - Psi(t - L.half, L.s)) / (2 * L.half);
+        case 0: return T(val(t) > 0 ? 1.0 : 0.0);  /* NGP: floor((v - lo) / width) */
+        case 1: return fmin(T(1.0), fmax(T(0.0), t / (2 * L.half) + 0.5));
+        case 2: return Phi<T>(t / L.s);
+        default: return (Psi<T>(t + L.half, L.s) - Psi<T>(t - L.half, L.s)) / (2 * L.half);
     }
 }
 
-double law_ccdf(const Law &L, double x) {
-    const double t = x - L.v;
+template <class T>
+T law_ccdf(const Law<T> &L, double x) {
+    const T t = x - L.v;
     switch (L.mode) {
-        case 0: return t > 0 ? 0.0 : 1.0;
-        case 1: return std::fmin(1.0, std::fmax(0.0, 0.5 - t / (2 * L.half)));
-        case 2: return PhiC(t / L.s);
-        default: return (PsiC(t - L.half, L.s) - PsiC(t + L.half, L.s)) / (2 * L.half);
+        case 0: return T(val(t) > 0 ? 0.0 : 1.0);
+        case 1: return fmin(T(1.0), fmax(T(0.0), 0.5 - t / (2 * L.half)));
+        case 2: return PhiC<T>(t / L.s);
+        default: return (PsiC<T>(t - L.half, L.s) - PsiC<T>(t + L.half, L.s)) / (2 * L.half);
     }
 }
 
-void deposit(double v, double s, int32_t dep, double ksig, double lo, double hi, int32_t n,
-             double *hist) {
+template <class T>
+void deposit(const T &v, const T &s, int32_t dep, double ksig, double lo, double hi, int32_t n,
+             T *hist) {
     const double width = (hi - lo) / n;
-    const Law L = make_law(v, s, dep, ksig, width);
-    hist[n] += law_cdf(L, lo);
-    hist[n + 1] += law_ccdf(L, hi);
+    const Law<T> L = make_law<T>(v, s, dep, ksig, width);
+    hist[n] += law_cdf<T>(L, lo);
+    hist[n + 1] += law_ccdf<T>(L, hi);
     for (int k = 0; k < n; ++k) {
         const double e0 = lo + k * width, e1 = lo + (k + 1) * width;
         /* difference of whichever tail is smaller, for relative accuracy */
-        const double m = (0.5 * (e0 + e1) <= v) ? law_cdf(L, e1) - law_cdf(L, e0)
-                                                : law_ccdf(L, e0) - law_ccdf(L, e1);
+        const T m = (0.5 * (e0 + e1) <= val(v)) ? law_cdf<T>(L, e1) - law_cdf<T>(L, e0)
+                                                 : law_ccdf<T>(L, e0) - law_ccdf<T>(L, e1);
         hist[k] += m;
     }
 }
@@ -538,7 +651,7 @@ int qso_rhs(const qso_problem *p, double mu, double sig2, double a, double out[6
 int qso_sample(const qso_problem *p, int64_t i, double *rec) {
     if (validate(p)) return -1;
     const Derived d = derive(p);
-    const SampleOut o = run_sample(p, d, i);
+    const SampleOut<double> o = run_sample(p, d, i);
     rec[QSO_S_MU] = o.mu; rec[QSO_S_SIG2] = o.sig2; rec[QSO_S_THX] = o.thx;
     rec[QSO_S_THY] = o.thy; rec[QSO_S_SIGTH] = o.sigth; rec[QSO_S_AEFF] = p->a0 * o.aeff_ratio;
     rec[QSO_S_CHIMAX] = o.chimax; rec[QSO_S_GAMMA0] = o.gamma0;
@@ -549,7 +662,7 @@ int qso_sample(const qso_problem *p, int64_t i, double *rec) {
 int qso_deposit(double v, double s, int32_t dep, double ksig, double lo, double hi, int32_t n,
                 double *hist) {
     if (!(hi > lo) || n < 1 || !std::isfinite(v) || !(s >= 0)) return -1;
-    deposit(v, s, dep, ksig, lo, hi, n, hist);
+    deposit<double>(v, s, dep, ksig, lo, hi, n, hist);
     return 0;
 }
 
@@ -575,13 +688,13 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
         /* fixed contiguous range per thread, merged in thread order below */
         const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
         for (int64_t i = b; i < e; ++i) {
-            const SampleOut o = run_sample(p, d, i);
+            const SampleOut<double> o = run_sample(p, d, i);
             if (!std::isfinite(o.mu) || !std::isfinite(o.sig2)) { bad[t] = 1; continue; }
             const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
-            deposit(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
-                    he[t].data());
-            deposit(o.thx, o.sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
-                    p->th_hi_mrad, nt, ht[t].data());
+            deposit<double>(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+                            he[t].data());
+            deposit<double>(o.thx, o.sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
+                            p->th_hi_mrad, nt, ht[t].data());
             /* a0,eff histogram: NGP over a0,eff / a0 in [0, 1], top edge closed */
             int ka = (int)std::floor(o.aeff_ratio * na);
             if (ka > na - 1) ka = na - 1;
@@ -631,6 +744,70 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
             moments[QSO_M_RAD_FRAC] = sums[0][SRAD].value() / W;
             moments[QSO_M_MEAN_SIGF] = sums[0][SSIGF].value() / W;
         }
+    }
+    return 0;
+}
+
+/* ---- derivatives ---------------------------------------------------------- */
+static Params<Dual> seeded_params(const qso_problem *p) {
+    Params<Dual> P = params<Dual>(p);
+    P.a0.d[0] = 1.0;
+    P.w0.d[1] = 1.0;
+    P.x_off.d[2] = 1.0;
+    P.y_off.d[3] = 1.0;
+    P.delay.d[4] = 1.0;
+    P.gamma0.d[5] = 1.0;
+    P.sigma_gamma.d[6] = 1.0;
+    P.div_mrad.d[7] = 1.0;
+    finish_params(p, P);
+    return P;
+}
+
+int qso_sample_grad(const qso_problem *p, int64_t i, double *out) {
+    if (validate(p)) return -1;
+    const Derived d = derive(p);
+    const Params<Dual> P = seeded_params(p);
+    const SampleOut<Dual> o = run_sample<Dual>(p, d, P, i);
+    out[0] = o.mu.v;
+    out[9] = o.sig2.v;
+    for (int k = 0; k < kNP; ++k) {
+        out[1 + k] = o.mu.d[k];
+        out[10 + k] = o.sig2.d[k];
+    }
+    return std::isfinite(o.mu.v) && std::isfinite(o.sig2.v) ? 0 : -2;
+}
+
+int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads, double *hist,
+             double *jac) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int ne = p->n_e;
+    const int64_t total = i_end - i_begin;
+    const Params<Dual> P = seeded_params(p);
+    std::vector<std::vector<Dual>> he(nthreads, std::vector<Dual>(ne + 2, Dual(0.0)));
+    std::vector<int> bad(nthreads, 0);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        for (int64_t i = b; i < e; ++i) {
+            const SampleOut<Dual> o = run_sample<Dual>(p, d, P, i);
+            if (!std::isfinite(o.mu.v) || !std::isfinite(o.sig2.v)) { bad[t] = 1; continue; }
+            const Dual sigf = sqrt(fmax(o.sig2, Dual(0.0)));
+            deposit<Dual>(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+                          he[t].data());
+        }
+    }
+    for (int t = 1; t < nthreads; ++t)
+        for (int k = 0; k < ne + 2; ++k) he[0][k] += he[t][k];
+    for (int t = 0; t < nthreads; ++t) if (bad[t]) return -2;
+    for (int k = 0; k < ne + 2; ++k) {
+        if (hist) hist[k] = he[0][k].v;
+        if (jac)
+            for (int m = 0; m < kNP; ++m) jac[k * kNP + m] = he[0][k].d[m];
     }
     return 0;
 }

@@ -119,6 +119,17 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
                 double *energy_hist, double *angle_hist, double *a0eff_hist,
                 double *moments);
 
+/* Derivatives with respect to the eight parameters, in this order:
+ * (a0, w0_um, x_off_um, y_off_um, delay_fs, gamma0, sigma_gamma, div_mrad).
+ * qso_sample_grad: out[0] = mu_f, out[1..8] = d mu_f / d p, out[9] = sig2_f,
+ * out[10..17] = d sig2_f / d p for sample i.
+ * qso_grad: energy histogram hist[n_e + 2] (as qso_forward) and its Jacobian
+ * jac[(n_e + 2) * 8] (row = bin) over samples [i_begin, i_end).  Forward-mode
+ * derivatives (dual numbers) of exactly the arithmetic qso_forward does. */
+int qso_sample_grad(const qso_problem *p, int64_t i, double *out);
+int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+             double *hist, double *jac);
+
 /* Deposit one law into a histogram (exposed for the pins). */
 int qso_deposit(double v, double s, int32_t deposit, double kernel_sigma_bins,
                 double lo, double hi, int32_t n, double *hist);

@@ -77,6 +77,10 @@ def lib():
         L.qso_forward.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                   dp, dp, dp, dp]
         L.qso_forward.restype = ctypes.c_int
+        L.qso_sample_grad.argtypes = [pp, ctypes.c_int64, dp]
+        L.qso_sample_grad.restype = ctypes.c_int
+        L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
+        L.qso_grad.restype = ctypes.c_int
         L.qso_deposit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int32, dp]
@@ -184,6 +188,36 @@ def forward(params, i_begin=0, i_end=None, nthreads=0):
     if rc == -2:
         raise FloatingPointError("non-finite state")
     return {"energy_hist": he, "angle_hist": ht, "a0eff_hist": ha, "moments": mo}
+
+
+PARAM_NAMES = ["a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
+               "div_mrad"]
+
+
+def sample_grad(params, i):
+    """(mu_f, d mu_f/dp[8]), (sig2_f, d sig2_f/dp[8]) for sample i."""
+    out = np.zeros(18)
+    p = problem(params)
+    rc = lib().qso_sample_grad(ctypes.byref(p), i, _dp(out))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    return out[:9], out[9:]
+
+
+def grad(params, i_begin=0, i_end=None, nthreads=0):
+    """Energy histogram [n_e + 2] and its Jacobian [n_e + 2, 8] with respect to
+    PARAM_NAMES."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    p = problem(params)
+    h = np.zeros(params["n_e"] + 2)
+    j = np.zeros((params["n_e"] + 2, 8))
+    rc = lib().qso_grad(ctypes.byref(p), i_begin, i_end, nthreads, _dp(h), _dp(j))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return h, j
 
 
 def deposit(v, s, dep, ksig, lo, hi, n):
