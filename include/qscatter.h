@@ -197,6 +197,66 @@ qs_status qs_forward_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *laser
 qs_status qs_radiation_eval(qs_ctx *ctx, int32_t precision, int64_t n, const double *chi,
                             double *out, void *stream);
 
+/* Parameters the adjoint differentiates with respect to: index into
+ * qs_grad_outputs.grad.  Units as in qs_laser / qs_beam (um, fs, mrad). */
+enum {
+    QS_P_A0 = 0,       /* qs_laser.a0          */
+    QS_P_W0,           /* qs_laser.w0_um       */
+    QS_P_X_OFF,        /* qs_laser.x_off_um    */
+    QS_P_Y_OFF,        /* qs_laser.y_off_um    */
+    QS_P_DELAY,        /* qs_laser.delay_fs    */
+    QS_P_GAMMA0,       /* qs_beam.gamma0       */
+    QS_P_SIGMA_GAMMA,  /* qs_beam.sigma_gamma  */
+    QS_P_DIV,          /* qs_beam.div_mrad     */
+    QS_P_N
+};
+
+/* Adjoint inputs and outputs of one shot: device pointers, caller-allocated. */
+typedef struct qs_grad_outputs {
+    const double *d_energy_hist; /* in: [n_e + 2] dL/dH for the energy histogram of
+                                    qs_forward (bins, underflow, overflow)        */
+    double *grad;                /* out: [QS_P_N] dL/dp                           */
+    int32_t *status;             /* out: [1] qs_status of the device-side checks,
+                                    or NULL                                       */
+} qs_grad_outputs;
+
+/* Adjoint of the energy histogram (the parameter-reconstruction use the
+ * abstract and the conclusions give for the method's speed): for
+ * L = sum_k w_k H_k with w = d_energy_hist and H the energy histogram that
+ * qs_forward returns for the same arguments, write dL/dp for the QS_P_*
+ * parameters.  Each sample's trajectory (Sec. 2-4, as in qs_forward) is
+ * integrated again together with its forward-mode tangents, i.e. the exact
+ * derivatives of the discrete RK4 map, and contracted with the derivative of
+ * the sample's deposited law at the bin edges (the smooth law, without the
+ * forward pass's 2^-32 quantisation and 6-sigma cut).  The quantum model
+ * needs chi^3 g''' and chi h', tabulated on the device like g and h.
+ * precision QS_PREC_FP64 integrates in FP64; QS_PREC_FP32 (and chi_fp64 > 0)
+ * in compensated FP32 with FP32 tangents.  num->deposit may be any of the
+ * three kernels; n_samples and the RNG stream as in qs_forward, so the
+ * derivative is that of the same Monte-Carlo estimate.
+ * Errors: QS_EINVAL (as qs_forward; NULL d_energy_hist or grad),
+ * QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_backward(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                      const qs_numerics *num, const qs_bins *bins, const qs_grad_outputs *out,
+                      void *stream);
+
+/* The adjoint of qs_forward_batched: shot k as qs_backward with outs[k], RNG
+ * counter word num->shot + k and n_samples[k] samples; same batch rules
+ * (shared lambda_um, tau_fs and envelope, else QS_EUNSUPPORTED).  Shot k gives
+ * bit-for-bit the result of qs_backward with num->shot + k.
+ * Errors: QS_EINVAL, QS_EUNSUPPORTED, QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_backward_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                              const qs_beam *beams, const int64_t *n_samples,
+                              const qs_numerics *num, const qs_bins *bins,
+                              const qs_grad_outputs *outs, void *stream);
+
+/* Evaluate the derivative tables that the adjoint uses at n values of chi
+ * (device arrays): out[6*k + {0..5}] = {g, chi g', chi^2 g'', h, chi^3 g''',
+ * chi h'} at chi[k], FP32 or FP64 (Sec. 4 eq. dpdtRR; diagnostic entry point).
+ * Errors: QS_EINVAL, QS_EDEVICE. */
+qs_status qs_radiation_derivs(qs_ctx *ctx, int32_t precision, int64_t n, const double *chi,
+                              double *out, void *stream);
+
 /* Synchronise `stream` and return the device status word of the last call
  * that wrote `status` (device pointer) -- QS_OK, QS_ENONFINITE or QS_ERANGE. */
 qs_status qs_sync_status(qs_ctx *ctx, const int32_t *status, void *stream);

@@ -2,17 +2,21 @@
 
 ``forward(params)`` predicts the asymptotic electron energy / angle / a0,eff
 distributions and moments after a relativistic electron beam meets a focused,
-possibly misaligned laser pulse head-on.  All computation runs in the HIP
-kernels of ``libqscatter.so``; PyTorch only provides device memory and the
-stream.
+possibly misaligned laser pulse head-on; ``energy_histogram(theta, params)``
+is the same energy histogram as a differentiable function of the eight shot
+parameters ``PARAM_NAMES`` (adjoint on the device).  All computation runs in
+the HIP kernels of ``libqscatter.so``; PyTorch only provides device memory and
+the stream.
 """
 import ctypes
 
 from . import _lib
 
-__all__ = ["Context", "forward", "radiation_eval", "QScatterError"]
+__all__ = ["Context", "forward", "energy_histogram", "radiation_eval", "QScatterError",
+           "PARAM_NAMES"]
 
 QScatterError = _lib.QScatterError
+PARAM_NAMES = _lib.PARAM_NAMES
 
 
 def _torch():
@@ -150,6 +154,76 @@ class Context:
         list of per-shot result dictionaries (device tensors)."""
         return self.run_batch(self.prepare_batch(shots), stream=stream, check=check)
 
+    def backward(self, params, d_energy, stream=None, check=True):
+        """Derivatives of L = sum_k d_energy[k] H_k (H: the energy histogram of
+        forward(params), n_e + 2 entries) with respect to PARAM_NAMES; returns
+        a float64 device tensor of 8."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        la, be, nu, bi = _lib.structs(params)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        d = d_energy.to(device=dev, dtype=torch.float64).contiguous()
+        if d.numel() != params["n_e"] + 2:
+            raise ValueError("d_energy needs n_e + 2 entries")
+        if d.data_ptr() != d_energy.data_ptr():
+            d.record_stream(stream)
+        grad = torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev)
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+        g = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grad.data_ptr(),
+                             status=status.data_ptr())
+        st = _lib.lib().qs_backward(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                    ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(g),
+                                    ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        if check:
+            st = _lib.lib().qs_sync_status(self._ptr, ctypes.c_void_p(status.data_ptr()),
+                                           ctypes.c_void_p(stream.cuda_stream))
+            if st != _lib.QS_OK:
+                raise QScatterError(st, "device status")
+        return grad
+
+    def backward_batched(self, shots, d_energy, stream=None, check=True):
+        """Adjoint of forward_batched(shots): d_energy is a list of per-shot
+        upstream weights (n_e + 2 each); returns a list of gradient tensors."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        n = len(shots)
+        if n == 0 or len(d_energy) != n:
+            raise ValueError("one upstream weight vector per shot")
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _, _, nu, _ = _lib.structs(shots[0])
+        lasers, beams, bins = (_lib.Laser * n)(), (_lib.Beam * n)(), (_lib.Bins * n)()
+        outs, ns = (_lib.GradOutputs * n)(), (ctypes.c_int64 * n)()
+        keep, grads = [], []
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+        for k, p in enumerate(shots):
+            la, be, _, bi = _lib.structs(p)
+            lasers[k], beams[k], bins[k] = la, be, bi
+            ns[k] = int(p["n_samples"])
+            d = d_energy[k].to(device=dev, dtype=torch.float64).contiguous()
+            if d.numel() != p["n_e"] + 2:
+                raise ValueError("d_energy needs n_e + 2 entries per shot")
+            keep.append(d)
+            grads.append(torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev))
+            outs[k] = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grads[k].data_ptr(),
+                                       status=status[k:].data_ptr())
+        st = _lib.lib().qs_backward_batched(self._ptr, n, lasers, beams, ns, ctypes.byref(nu),
+                                            bins, outs, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        for d, src in zip(keep, d_energy):
+            if d.data_ptr() != src.data_ptr():
+                d.record_stream(stream)
+        if check:
+            torch.cuda.synchronize(dev)
+            bad = int(status.max().item())
+            if bad != _lib.QS_OK:
+                raise QScatterError(bad, "device status of a shot")
+        return grads
+
     def set_profiling(self, on=True):
         st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)
         if st != _lib.QS_OK:
@@ -179,6 +253,22 @@ class Context:
         torch.cuda.synchronize(chi.device)
         return out
 
+    def radiation_derivs(self, chi, precision="fp32"):
+        """The adjoint's device tables at chi (1-D float64 tensor): columns g,
+        chi g', chi^2 g'', h, chi^3 d3g/dchi3, chi h'."""
+        torch = _torch()
+        chi = chi.to(device=torch.device("cuda", self.device), dtype=torch.float64).contiguous()
+        out = torch.empty((chi.numel(), 6), dtype=torch.float64, device=chi.device)
+        stream = torch.cuda.current_stream(chi.device)
+        st = _lib.lib().qs_radiation_derivs(self._ptr, _lib.PRECISION[precision], chi.numel(),
+                                            ctypes.c_void_p(chi.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        torch.cuda.synchronize(chi.device)
+        return out
+
 
 class _Batch:
     """Marshalled arguments and output tensors of a batched launch."""
@@ -200,3 +290,45 @@ def forward(params, device=0, **kw):
 
 def radiation_eval(chi, precision="fp32", device=0):
     return _ctx(device).radiation_eval(chi, precision)
+
+
+def _with_theta(params, theta):
+    p = dict(params)
+    for name, v in zip(PARAM_NAMES, theta.detach().to("cpu", dtype=_torch().float64).tolist()):
+        p[name] = v
+    return p
+
+
+def _energy_hist_fn():
+    torch = _torch()
+
+    class EnergyHistogram(torch.autograd.Function):
+        """H(theta): the energy histogram (n_e + 2 raw weights) of one shot as a
+        function of theta = the PARAM_NAMES values; the backward runs the
+        device adjoint."""
+
+        @staticmethod
+        def forward(fctx, theta, qctx, params):
+            p = _with_theta(params, theta)
+            fctx.qctx, fctx.p = qctx, p
+            fctx.theta_meta = (theta.dtype, theta.device)
+            return qctx.forward(p)["energy_hist"]
+
+        @staticmethod
+        def backward(fctx, grad_h):
+            g = fctx.qctx.backward(fctx.p, grad_h)
+            dtype, device = fctx.theta_meta
+            return g.to(device=device, dtype=dtype), None, None
+
+    return EnergyHistogram
+
+
+_fn_cache = []
+
+
+def energy_histogram(theta, params, context=None, device=0):
+    """Differentiable energy histogram: theta (8 values, PARAM_NAMES order)
+    overrides those entries of ``params``."""
+    if not _fn_cache:
+        _fn_cache.append(_energy_hist_fn())
+    return _fn_cache[0].apply(theta, context or _ctx(device), params)

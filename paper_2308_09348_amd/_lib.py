@@ -62,8 +62,17 @@ class Outputs(ctypes.Structure):
                 ("sample_stride", ctypes.c_int64), ("n_sample_records", ctypes.c_int64)]
 
 
-EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_radiation_eval",
-           "qs_sync_status",
+class GradOutputs(ctypes.Structure):
+    _fields_ = [("d_energy_hist", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+# parameters of the adjoint, in the order of the QS_P_* enum
+PARAM_NAMES = ("a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
+               "div_mrad")
+
+EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_backward",
+           "qs_backward_batched", "qs_radiation_eval", "qs_radiation_derivs", "qs_sync_status",
            "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
            "qs_abi_version"]
 
@@ -99,8 +108,19 @@ def lib():
                                          ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                          ctypes.POINTER(Outputs), vp]
         L.qs_forward_batched.restype = ctypes.c_int
+        L.qs_backward.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                                  ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+                                  ctypes.POINTER(GradOutputs), vp]
+        L.qs_backward.restype = ctypes.c_int
+        L.qs_backward_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser),
+                                          ctypes.POINTER(Beam), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+                                          ctypes.POINTER(GradOutputs), vp]
+        L.qs_backward_batched.restype = ctypes.c_int
         L.qs_radiation_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.qs_radiation_eval.restype = ctypes.c_int
+        L.qs_radiation_derivs.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.qs_radiation_derivs.restype = ctypes.c_int
         L.qs_sync_status.argtypes = [vp, vp, vp]
         L.qs_sync_status.restype = ctypes.c_int
         L.qs_set_profiling.argtypes = [vp, ctypes.c_int]

@@ -19,6 +19,8 @@ struct qs_ctx {
     int device = -1;
     float *rad32 = nullptr;
     double *rad64 = nullptr;
+    float *rad32d = nullptr;   // derivative tables (adjoint)
+    double *rad64d = nullptr;
     // per-call device scratch (grow-only)
     float *env32 = nullptr;
     double *env64 = nullptr;
@@ -80,8 +82,8 @@ class DeviceGuard {
 bool fin(double v) { return std::isfinite(v); }
 
 qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_bins *H,
-                        const qs_outputs *O, int64_t n_samples) {
-    if (!L || !B || !H || !O) return set_err(c, "null argument"), QS_EINVAL;
+                        int64_t n_samples) {
+    if (!L || !B || !H) return set_err(c, "null argument"), QS_EINVAL;
     const double vals[] = {L->a0, L->lambda_um, L->w0_um, L->tau_fs, L->x_off_um, L->y_off_um,
                            L->delay_fs, B->gamma0, B->sigma_gamma, B->sigma_r_um, B->sigma_z_um,
                            B->div_mrad, H->e_lo, H->e_hi, H->th_lo_mrad, H->th_hi_mrad};
@@ -101,10 +103,21 @@ qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs
         return set_err(c, "bin counts must be in [1, 4096]"), QS_EINVAL;
     if (!(H->e_hi > H->e_lo) || !(H->th_hi_mrad > H->th_lo_mrad))
         return set_err(c, "histogram window must have hi > lo"), QS_EINVAL;
+    return QS_OK;
+}
+
+qs_status validate_outputs(qs_ctx *c, const qs_outputs *O) {
+    if (!O) return set_err(c, "null argument"), QS_EINVAL;
     if (!O->energy_hist || !O->angle_hist || !O->a0eff_hist || !O->moments || !O->status)
         return set_err(c, "null output pointer"), QS_EINVAL;
     if (O->samples && (O->sample_stride < 1 || O->n_sample_records < 0))
         return set_err(c, "sample records need stride >= 1"), QS_EINVAL;
+    return QS_OK;
+}
+
+qs_status validate_outputs(qs_ctx *c, const qs_grad_outputs *O) {
+    if (!O) return set_err(c, "null argument"), QS_EINVAL;
+    if (!O->d_energy_hist || !O->grad) return set_err(c, "null gradient pointer"), QS_EINVAL;
     return QS_OK;
 }
 
@@ -162,6 +175,9 @@ qs_status grow_pinned(qs_ctx *c, size_t n) {
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                        const qs_outputs *O, hipStream_t s);
+qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                        const qs_grad_outputs *O, hipStream_t s);
 
 }  // namespace
 
@@ -198,6 +214,10 @@ qs_status qs_create(qs_ctx **out, int device) {
     const size_t wd = qs::radiation_work_doubles();
     if ((e = hipMalloc(&c->rad32, sizeof(float) * qs::kCells32 * qs::kCellVals)) != hipSuccess ||
         (e = hipMalloc(&c->rad64, sizeof(double) * qs::kCells64 * qs::kCellVals)) != hipSuccess ||
+        (e = hipMalloc(&c->rad32d, sizeof(float) * qs::kCells32 * 4 * qs::kDerivFuncs)) !=
+            hipSuccess ||
+        (e = hipMalloc(&c->rad64d, sizeof(double) * qs::kCells64 * 4 * qs::kDerivFuncs)) !=
+            hipSuccess ||
         (e = hipMalloc(&c->eval_flags, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&work, sizeof(double) * wd)) != hipSuccess ||
         (e = hipMemset(c->eval_flags, 0, sizeof(int))) != hipSuccess) {
@@ -206,7 +226,7 @@ qs_status qs_create(qs_ctx **out, int device) {
         qs_destroy(c);
         return st;
     }
-    e = qs::build_radiation_tables(c->rad32, c->rad64, work, wd, nullptr);
+    e = qs::build_radiation_tables(c->rad32, c->rad64, c->rad32d, c->rad64d, work, wd, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipFree(work);
     if (e != hipSuccess) {
@@ -225,6 +245,8 @@ void qs_destroy(qs_ctx *c) {
         (void)hipDeviceSynchronize();
         (void)hipFree(c->rad32);
         (void)hipFree(c->rad64);
+        (void)hipFree(c->rad32d);
+        (void)hipFree(c->rad64d);
         (void)hipFree(c->env32);
         (void)hipFree(c->env64);
         (void)hipFree(c->accum);
@@ -269,6 +291,39 @@ qs_status qs_radiation_eval(qs_ctx *c, int32_t precision, int64_t n, const doubl
     hipError_t e = qs::launch_radiation_eval(c->rad32, c->rad64, precision, n, chi, out,
                                              c->eval_flags, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(c, e, "radiation_eval kernel");
+    return QS_OK;
+}
+
+qs_status qs_backward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
+                      const qs_bins *H, const qs_grad_outputs *O, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    const int64_t n = N->n_samples;
+    return backward_impl(c, 1, L, B, &n, N, H, O, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_backward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                              const qs_beam *beams, const int64_t *n_samples,
+                              const qs_numerics *num, const qs_bins *bins,
+                              const qs_grad_outputs *outs, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return backward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_radiation_derivs(qs_ctx *c, int32_t precision, int64_t n, const double *chi,
+                              double *out, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n < 0 || (n > 0 && (!chi || !out)) ||
+        (precision != QS_PREC_FP32 && precision != QS_PREC_FP64))
+        return set_err(c, "invalid radiation_derivs arguments"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+    hipError_t e = qs::launch_radiation_derivs(c->rad32d, c->rad64d, precision, n, chi, out,
+                                               c->eval_flags,
+                                               reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(c, e, "radiation_derivs kernel");
     return QS_OK;
 }
 
@@ -318,54 +373,63 @@ qs_status qs_sync_status(qs_ctx *c, const int32_t *status, void *stream) {
 
 namespace {
 
-qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
-                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                       const qs_outputs *O, hipStream_t s) {
+// Shared set-up of a batch: validation of the shots, the constants of the
+// shared phase grid (Sec. 2 eq. a0eff, Sec. 4 eq. dpdtRR) and the per-shot
+// table, built in pinned staging memory as [ShotParams x n][OutT x n].
+struct Batch {
+    qs::BatchParams bp{};
+    double psi_max = 0, h = 0, omega_tau = 0;
+    int prec = qs::PREC_F32;
+    int max_nh = 0;       // largest histogram word count of a shot
+    int64_t total = 0;    // samples over all shots
+    int64_t hist_words = 0;
+    size_t tab_bytes = 0;
+    qs::ShotParams *sp = nullptr;  // in the staging buffer
+    unsigned char *outs = nullptr;  // in the staging buffer, after the ShotParams
+};
+
+qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                        size_t out_size, Batch &b) {
     qs_status st = validate_numerics(c, N);
     if (st != QS_OK) return st;
-    int max_nh = 0;
-    int64_t total = 0;
     for (int k = 0; k < n_shots; ++k) {
-        if ((st = validate_shot(c, &L[k], &B[k], &H[k], &O[k], n_samples[k])) != QS_OK) return st;
+        if ((st = validate_shot(c, &L[k], &B[k], &H[k], n_samples[k])) != QS_OK) return st;
         if (L[k].lambda_um != L[0].lambda_um || L[k].tau_fs != L[0].tau_fs ||
             L[k].envelope != L[0].envelope)
             return set_err(c, "the shots of a batch must share wavelength, duration and envelope"),
                    QS_EUNSUPPORTED;
-        max_nh = std::max(max_nh, H[k].n_e + 2 + H[k].n_th + 2 + H[k].n_a);
-        total += n_samples[k];
-        if (total > ((int64_t)1 << 36))
+        b.max_nh = std::max(b.max_nh, H[k].n_e + 2 + H[k].n_th + 2 + H[k].n_a);
+        b.total += n_samples[k];
+        if (b.total > ((int64_t)1 << 36))
             return set_err(c, "a batch holds at most 2^36 samples"), QS_EINVAL;
     }
-    if (qs::deposit_lds_bytes(max_nh) > 160 * 1024)
-        return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
-    DeviceGuard guard(c->device);
 
-    // ---- shared constants (Sec. 2 eq. a0eff, Sec. 4 eq. dpdtRR) ----
+    // ---- shared constants ----
     const qs_laser &L0 = L[0];
     const double omega0 = 2.0 * kPi * kC_um_per_fs / L0.lambda_um;  // rad / fs
     const double aS = L0.lambda_um / (2.0 * kPi * kLambdaBarC_um);
-    const double omega_tau = omega0 * L0.tau_fs;
-    const double psi_max = L0.envelope == QS_ENV_GAUSS ? N->window_fwhm * omega_tau : omega_tau;
-    const double h = 2.0 * psi_max / (double)N->n_steps;
-    int prec = qs::PREC_F32;
+    b.omega_tau = omega0 * L0.tau_fs;
+    b.psi_max = L0.envelope == QS_ENV_GAUSS ? N->window_fwhm * b.omega_tau : b.omega_tau;
+    b.h = 2.0 * b.psi_max / (double)N->n_steps;
     if (N->precision == QS_PREC_FP64)
-        prec = qs::PREC_F64;
+        b.prec = qs::PREC_F64;
     else if (N->rr_model == QS_RR_QUANTUM && N->chi_fp64 > 0)
-        prec = qs::PREC_F32MIX;
+        b.prec = qs::PREC_F32MIX;
 
-    qs::BatchParams bp{};
+    qs::BatchParams &bp = b.bp;
     bp.ell_per_psi = L0.lambda_um / (4.0 * kPi);
     bp.two_over_aS = 2.0 / aS;
     bp.K = 4.0 * kAlpha / (3.0 * aS);
     bp.CD = 55.0 / (6.0 * std::sqrt(3.0)) * kAlpha / (aS * aS);
-    bp.psi_max = psi_max;
-    bp.h = h;
+    bp.psi_max = b.psi_max;
+    bp.h = b.h;
     bp.ellf = (float)bp.ell_per_psi;
     bp.two_over_aSf = (float)bp.two_over_aS;
     bp.Kf = (float)bp.K;
     bp.CDf = (float)bp.CD;
-    bp.psi0f = (float)(-psi_max);
-    bp.hf = (float)h;
+    bp.psi0f = (float)(-b.psi_max);
+    bp.hf = (float)b.h;
     bp.chi_fp64 = (float)N->chi_fp64;
     bp.n_steps = N->n_steps;
     bp.n_shots = n_shots;
@@ -375,23 +439,22 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     bp.ksig_bins = N->kernel_sigma_bins;
     bp.c_theta = N->c_theta;
 
-    // ---- per-shot tables, built in pinned staging memory ----
-    const size_t tab_bytes = ((sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots + 255) /
-                             256 * 256;
+    // ---- per-shot table in pinned staging memory ----
+    b.tab_bytes = ((sizeof(qs::ShotParams) + out_size) * n_shots + 255) / 256 * 256;
     if (c->stage_pending) {
         hipError_t e = hipEventSynchronize(c->stage_done);  // previous copy out of staging
         if (e != hipSuccess) return hip_fail(c, e, "staging event");
         c->stage_pending = false;
     }
-    if ((st = grow_pinned(c, tab_bytes)) != QS_OK) return st;
-    qs::ShotParams *sp = reinterpret_cast<qs::ShotParams *>(c->stage);
-    qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(c->stage + sizeof(qs::ShotParams) * n_shots);
+    if ((st = grow_pinned(c, b.tab_bytes)) != QS_OK) return st;
+    b.sp = reinterpret_cast<qs::ShotParams *>(c->stage);
+    b.outs = c->stage + sizeof(qs::ShotParams) * n_shots;
     int64_t item = 0, ditem = 0, off = 0, hoff = 0;
     for (int k = 0; k < n_shots; ++k) {
         const qs_laser &l = L[k];
-        const qs_beam &b = B[k];
+        const qs_beam &bm = B[k];
         const qs_bins &hb = H[k];
-        qs::ShotParams &p = sp[k];
+        qs::ShotParams &p = b.sp[k];
         p = qs::ShotParams{};
         const bool plane_wave = l.w0_um == 0.0;
         p.a0 = l.a0;
@@ -400,11 +463,11 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         p.x_off = l.x_off_um;
         p.y_off = l.y_off_um;
         p.z_delay = 0.5 * kC_um_per_fs * l.delay_fs;
-        p.gamma0 = b.gamma0;
-        p.sigma_gamma = b.sigma_gamma;
-        p.sigma_r = b.sigma_r_um;
-        p.sigma_z = b.sigma_z_um;
-        p.div_rad = 1e-3 * b.div_mrad;
+        p.gamma0 = bm.gamma0;
+        p.sigma_gamma = bm.sigma_gamma;
+        p.sigma_r = bm.sigma_r_um;
+        p.sigma_z = bm.sigma_z_um;
+        p.div_rad = 1e-3 * bm.div_mrad;
         p.a0f = (float)p.a0;
         p.inv_w0sqf = (float)p.inv_w0sq;
         p.inv_zRf = (float)p.inv_zR;
@@ -412,7 +475,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         {
             // the quadratic midpoint of the spatial factor is used only when one
             // phase step moves a sample much less than the focal scales
-            const double step_um = h * bp.ell_per_psi;
+            const double step_um = b.h * bp.ell_per_psi;
             const double scale = plane_wave ? 0.0 : std::fmax(p.inv_zR, 6.0 * p.div_rad / l.w0_um);
             p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
         }
@@ -433,6 +496,41 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         item += (n_samples[k] + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
         ditem += (n_samples[k] + qs::kDepTile - 1) / qs::kDepTile;
         hoff += hb.n_e + 2 + hb.n_th + 2 + hb.n_a;
+    }
+    bp.n_items = item;
+    bp.n_ditems = ditem;
+    b.hist_words = hoff;
+    return QS_OK;
+}
+
+// Copy the staged shot table to the device and record the staging event.
+qs_status upload_batch(qs_ctx *c, const Batch &b, hipStream_t s) {
+    if (!c->stage_done) {
+        hipError_t e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(c, e, "event create");
+    }
+    hipError_t e = hipMemcpyAsync(c->shot_tab, c->stage, b.tab_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "shot table copy");
+    if ((e = hipEventRecord(c->stage_done, s)) != hipSuccess) return hip_fail(c, e, "event record");
+    c->stage_pending = true;
+    return QS_OK;
+}
+
+qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                       const qs_outputs *O, hipStream_t s) {
+    qs_status st;
+    for (int k = 0; k < n_shots; ++k)
+        if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
+    Batch b;
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotOut), b)) != QS_OK)
+        return st;
+    if (qs::deposit_lds_bytes(b.max_nh) > 160 * 1024)
+        return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+    qs::BatchParams &bp = b.bp;
+    qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(b.outs);
+    for (int k = 0; k < n_shots; ++k) {
         const qs_outputs &o = O[k];
         so[k].energy_hist = o.energy_hist;
         so[k].angle_hist = o.angle_hist;
@@ -443,33 +541,29 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         so[k].rec_stride = o.samples ? o.sample_stride : 1;
         so[k].rec_n = o.samples ? o.n_sample_records : 0;
     }
-    bp.n_items = item;
-    bp.n_ditems = ditem;
 
     // ---- device scratch ----
     const size_t nenv = (size_t)2 * N->n_steps + 1;
-    const size_t arr = ((size_t)total * 8 + 255) / 256 * 256;
-    const size_t arrf = ((size_t)total * 4 + 255) / 256 * 256;
+    const size_t arr = ((size_t)b.total * 8 + 255) / 256 * 256;
+    const size_t arrf = ((size_t)b.total * 4 + 255) / 256 * 256;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;
-    const size_t accum_words = 1 + flag_words + (size_t)hoff;
+    const size_t accum_words = 1 + flag_words + (size_t)b.hist_words;
     if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
-    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)ditem * qs::kPartials,
+    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_ditems * qs::kPartials,
                    "moment partials")) != QS_OK)
         return st;
     if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf, "sample states")) != QS_OK)
         return st;
-    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, tab_bytes, "shot table")) != QS_OK)
+    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
         return st;
-    if (!c->stage_done) {
-        hipError_t e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(c, e, "event create");
-    }
     bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
     bp.outs = reinterpret_cast<const qs::ShotOut *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
     bp.rad32 = c->rad32;
     bp.rad64 = c->rad64;
+    bp.rad32d = c->rad32d;
+    bp.rad64d = c->rad64d;
     bp.st.mu = reinterpret_cast<double *>(c->states);
     bp.st.s2 = reinterpret_cast<double *>(c->states + arr);
     bp.st.S0 = reinterpret_cast<double *>(c->states + 2 * arr);
@@ -486,30 +580,80 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     hipError_t e;
     const bool prof = c->profiling;
     auto mark = [&](int k) { return prof ? hipEventRecord(c->ev[k], s) : hipSuccess; };
-    if ((e = hipMemcpyAsync(c->shot_tab, c->stage, tab_bytes, hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-        return hip_fail(c, e, "shot table copy");
-    if ((e = hipEventRecord(c->stage_done, s)) != hipSuccess)
-        return hip_fail(c, e, "event record");
-    c->stage_pending = true;
+    if ((st = upload_batch(c, b, s)) != QS_OK) return st;
     if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_envelope(psi_max, h, N->n_steps, L0.envelope, omega_tau, c->env32,
+    if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau, c->env32,
                                  c->env64, s)) != hipSuccess)
         return hip_fail(c, e, "envelope kernel");
     if ((e = mark(1)) != hipSuccess) return hip_fail(c, e, "event record");
     if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
         return hip_fail(c, e, "zero kernel");
     if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_phase(bp, c->env32, c->env64, prec, N->rr_model, N->amp_mode, s)) !=
+    if ((e = qs::launch_phase(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, s)) !=
         hipSuccess)
         return hip_fail(c, e, "phase kernel");
     if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_deposit(bp, max_nh, s)) != hipSuccess)
+    if ((e = qs::launch_deposit(bp, b.max_nh, s)) != hipSuccess)
         return hip_fail(c, e, "deposit kernel");
     if ((e = mark(4)) != hipSuccess) return hip_fail(c, e, "event record");
     if ((e = qs::launch_finalize(bp, s)) != hipSuccess) return hip_fail(c, e, "finalize kernel");
     if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
     c->profiled_call = prof;
+    c->last_error[0] = 0;
+    return QS_OK;
+}
+
+qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                        const qs_grad_outputs *O, hipStream_t s) {
+    qs_status st;
+    for (int k = 0; k < n_shots; ++k)
+        if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
+    Batch b;
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotGrad), b)) != QS_OK)
+        return st;
+    DeviceGuard guard(c->device);
+    qs::BatchParams &bp = b.bp;
+    qs::ShotGrad *so = reinterpret_cast<qs::ShotGrad *>(b.outs);
+    for (int k = 0; k < n_shots; ++k) {
+        so[k].d_energy = O[k].d_energy_hist;
+        so[k].grad = O[k].grad;
+        so[k].status = O[k].status;
+    }
+    const size_t nenv = (size_t)2 * N->n_steps + 1;
+    const size_t flag_words = ((size_t)n_shots + 1) / 2;
+    const size_t accum_words = 1 + flag_words;
+    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
+    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_items * qs::kGradParams,
+                   "gradient partials")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
+        return st;
+    bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
+    bp.gouts =
+        reinterpret_cast<const qs::ShotGrad *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
+    bp.rad32 = c->rad32;
+    bp.rad64 = c->rad64;
+    bp.rad32d = c->rad32d;
+    bp.rad64d = c->rad64d;
+    bp.queue = reinterpret_cast<unsigned int *>(c->accum);
+    bp.flags = reinterpret_cast<int *>(c->accum + 1);
+    bp.partials = c->partials;
+
+    hipError_t e;
+    if ((st = upload_batch(c, b, s)) != QS_OK) return st;
+    if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau, c->env32,
+                                 c->env64, s)) != hipSuccess)
+        return hip_fail(c, e, "envelope kernel");
+    if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
+        return hip_fail(c, e, "zero kernel");
+    if ((e = qs::launch_adjoint(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "adjoint kernel");
+    if ((e = qs::launch_grad_finalize(bp, s)) != hipSuccess)
+        return hip_fail(c, e, "gradient finalize kernel");
     c->last_error[0] = 0;
     return QS_OK;
 }

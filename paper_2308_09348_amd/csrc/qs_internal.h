@@ -22,6 +22,10 @@ constexpr int kSB64 = 6;  // FP64 table: 64 sub-cells per octave (global)
 constexpr int kCells32 = 1 + (kEMax - kEMin + 1) * (1 << kSB32);
 constexpr int kCells64 = 1 + (kEMax - kEMin + 1) * (1 << kSB64);
 constexpr int kCellVals = 16;
+// Derivative tables (adjoint): six functions per cell, in the order g,
+// chi g', chi^2 g'', h, chi^3 g''', chi h'; FP32 function-major
+// ([function][cell][power]), FP64 cell-major ([cell][function][power]).
+constexpr int kDerivFuncs = 6;
 
 // ---- device status bits ---------------------------------------------------
 constexpr int kFlagNonFinite = 1;
@@ -85,6 +89,15 @@ struct ShotOut {
     int64_t rec_stride, rec_n;
 };
 
+// Adjoint in/out pointers of one shot (device table).
+struct ShotGrad {
+    const double *d_energy;  // upstream weights dL/dH over the n_e + 2 energy bins
+    double *grad;            // 8 derivatives (order of the qs_grad_param enum)
+    int32_t *status;         // optional
+};
+
+constexpr int kGradParams = 8;
+
 // Parameters shared by every shot of a launch.
 struct BatchParams {
     // FP64 and FP32 copies of the shared physics constants
@@ -98,18 +111,21 @@ struct BatchParams {
     const ShotOut *outs;
     const float *rad32;   // [kCells32 * 16]
     const double *rad64;  // [kCells64 * 16]
+    const float *rad32d;  // [kCells32 * 4 * kDerivFuncs]
+    const double *rad64d; // [kCells64 * 4 * kDerivFuncs]
+    const ShotGrad *gouts;  // adjoint launches only
     SampleState st;
     // accumulators (device scratch, cleared before each launch)
     unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
     unsigned int *chimax_bits;     // [n_shots]
     int *flags;                    // [n_shots]
     unsigned int *queue;           // [2]: phase and deposit work counters
-    double *partials;              // [n_ditems][kPartials]
+    double *partials;              // [n_ditems][kPartials]; adjoint: [n_items][kGradParams]
 };
 
 // ---- launchers (qs_kernels.hip) -------------------------------------------
-hipError_t build_radiation_tables(float *rad32, double *rad64, double *work, size_t work_doubles,
-                                  hipStream_t s);
+hipError_t build_radiation_tables(float *rad32, double *rad64, float *rad32d, double *rad64d,
+                                  double *work, size_t work_doubles, hipStream_t s);
 size_t radiation_work_doubles();
 hipError_t launch_envelope(double psi_max, double h, int n_steps, int envelope, double omega_tau,
                            float *env32, double *env64, hipStream_t s);
@@ -121,5 +137,10 @@ hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t 
 hipError_t launch_finalize(const BatchParams &p, hipStream_t s);
 hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int prec, int64_t n,
                                  const double *chi, double *out, int *flags, hipStream_t s);
+hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, int prec, int64_t n,
+                                   const double *chi, double *out, int *flags, hipStream_t s);
+hipError_t launch_adjoint(const BatchParams &p, const float *env32, const double *env64, int prec,
+                          int rr, int amp, hipStream_t s);
+hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s);
 
 }  // namespace qs

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 namespace qs {
 
 // ===========================================================================
@@ -885,6 +887,8 @@ constexpr double kVHi = 4.125;   // to ~62
 constexpr double kDv = 1.0 / 16.0;
 constexpr int kNY = (int)((kVHi - kVLo) / kDv) + 1;
 constexpr double kDt = 1.0 / 16.0;
+constexpr int kYVals = 8;     // per y node: P_0..P_2, Q_0..Q_2, P_3, Q_3
+constexpr int kNodeVals = 6;  // per chi node: g, chi g', chi^2 g'', h, chi^3 g''', chi h'
 
 __global__ void rad_y_kernel(double *yf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -892,7 +896,7 @@ __global__ void rad_y_kernel(double *yf) {
     const double y = exp(kVLo + i * kDv);
     const double tmax = acosh(fmax(60.0 / y, 1.0)) + kDt;
     const int nt = (int)ceil(tmax / kDt);
-    double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0;
+    double P0 = 0, P1 = 0, P2 = 0, P3 = 0, Q0 = 0, Q1 = 0, Q2 = 0, Q3 = 0;
     for (int m = 0; m <= nt; ++m) {
         const double t = m * kDt;
         const double c = cosh(t);
@@ -903,17 +907,21 @@ __global__ void rad_y_kernel(double *yf) {
         P0 += p;
         P1 += u * p;
         P2 += u * u * p;
+        P3 += u * u * u * p;
         Q0 += q;
         Q1 += u * q;
         Q2 += u * u * q;
+        Q3 += u * u * u * q;
     }
-    double *o = yf + 6 * i;
+    double *o = yf + kYVals * i;
     o[0] = P0 * kDt;
     o[1] = P1 * kDt;
     o[2] = P2 * kDt;
     o[3] = Q0 * kDt;
     o[4] = Q1 * kDt;
     o[5] = Q2 * kDt;
+    o[6] = P3 * kDt;
+    o[7] = Q3 * kDt;
 }
 
 __device__ __forceinline__ double cell_chi(int cell, double t, int sb) {
@@ -928,8 +936,13 @@ __device__ __forceinline__ double cheb_node(int m) {
     return 0.5 * (1.0 - cospi((2.0 * m + 1.0) / 8.0));
 }
 
-// vals[node][4] at the four Chebyshev nodes of every cell, cells of the
-// FP32 table first, then those of the FP64 table.
+// vals[node][6] at the four Chebyshev nodes of every cell, cells of the
+// FP32 table first, then those of the FP64 table.  The chi dependence of the
+// moments I_k (weight (y cosh t)^k) and J_k sits in y cosh t, which scales
+// as 1/chi at fixed chi y, so chi d/dchi maps I_k to I_{k+1} - k I_k; with
+// g = C I_0 (C ~ chi^-2) and h = C' J_0 (C' ~ chi^-3) that gives
+//   chi g' = C (I_1 - 2 I_0),       chi^2 g'' = C (I_2 - 6 I_1 + 6 I_0),
+//   chi^3 g''' = C (I_3 - 12 I_2 + 36 I_1 - 24 I_0),   chi h' = C' (J_1 - 3 J_0).
 __global__ void rad_node_kernel(const double *yf, double *vals) {
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     const int total = 4 * (kCells32 + kCells64);
@@ -938,39 +951,50 @@ __global__ void rad_node_kernel(const double *yf, double *vals) {
     const bool t32 = cell_all < kCells32;
     const int cell = t32 ? cell_all : cell_all - kCells32;
     const double chi = cell_chi(cell, cheb_node(m), t32 ? kSB32 : kSB64);
-    double I0 = 0, I1 = 0, I2 = 0, J0 = 0;
+    double I0 = 0, I1 = 0, I2 = 0, I3 = 0, J0 = 0, J1 = 0;
     for (int i = 0; i < kNY; ++i) {
         const double y = exp(kVLo + i * kDv);
         const double q = 2.0 + 3.0 * chi * y;
         const double xi = 3.0 * chi * y / q;
         const double w = 2.0 / q + 0.5 * q;
         const double base = xi * (6.0 * chi / (q * q)) * y;  // xi dxi/dy dy/dv
-        const double *f = yf + 6 * i;
+        const double *f = yf + kYVals * i;
         const double b0 = base * (w * f[0] - f[3]);
+        const double b1 = base * (w * f[1] - f[4]);
         I0 += b0;
-        I1 += base * (w * f[1] - f[4]);
+        I1 += b1;
         I2 += base * (w * f[2] - f[5]);
+        I3 += base * (w * f[6] - f[7]);
         J0 += xi * b0;
+        J1 += xi * b1;
     }
     I0 *= kDv;
     I1 *= kDv;
     I2 *= kDv;
+    I3 *= kDv;
     J0 *= kDv;
+    J1 *= kDv;
     const double C = 1.7320508075688772935 / (2.0 * 3.14159265358979323846 * chi * chi);
-    double *o = vals + 4 * node;
+    const double Cp = 24.0 / (55.0 * 3.14159265358979323846 * chi * chi * chi);
+    double *o = vals + kNodeVals * node;
     o[0] = C * I0;
     o[1] = C * (I1 - 2.0 * I0);
     o[2] = C * (I2 - 6.0 * I1 + 6.0 * I0);
-    o[3] = 24.0 / (55.0 * 3.14159265358979323846 * chi * chi * chi) * J0;
+    o[3] = Cp * J0;
+    o[4] = C * (I3 - 12.0 * I2 + 36.0 * I1 - 24.0 * I0);
+    o[5] = Cp * (J1 - 3.0 * J0);
 }
 
-// Cubic through the four node values of each cell, in monomials of t.
-__global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64) {
+// Cubic through the four node values of each cell, in monomials of t.  The
+// forward tables take g, chi g', chi^2 g'', h; the derivative tables all six
+// functions (same order as the node values).
+__global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64, float *rad32d,
+                                double *rad64d) {
     const int cell_all = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell_all >= kCells32 + kCells64) return;
     double tn[4];
     for (int m = 0; m < 4; ++m) tn[m] = cheb_node(m);
-    double coef[4][4] = {};
+    double coef[kNodeVals][4] = {};
     for (int m = 0; m < 4; ++m) {
         double r[3];
         int k = 0;
@@ -985,8 +1009,8 @@ __global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64)
         const double l2 = -(r[0] + r[1] + r[2]) / den;
         const double l1 = (r[0] * r[1] + r[0] * r[2] + r[1] * r[2]) / den;
         const double l0 = -(r[0] * r[1] * r[2]) / den;
-        for (int f = 0; f < 4; ++f) {
-            const double v = vals[4 * (4 * cell_all + m) + f];
+        for (int f = 0; f < kNodeVals; ++f) {
+            const double v = vals[kNodeVals * (4 * cell_all + m) + f];
             coef[f][0] += v * l0;
             coef[f][1] += v * l1;
             coef[f][2] += v * l2;
@@ -1000,11 +1024,16 @@ __global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64)
             const double mix[4] = {coef[0][c], 2.0 * coef[0][c] + coef[1][c],
                                    coef[0][c] + 2.0 * coef[1][c] + 0.5 * coef[2][c], coef[3][c]};
             for (int f = 0; f < 4; ++f) rad32[(f * kCells32 + cell_all) * 4 + c] = (float)mix[f];
+            for (int f = 0; f < kDerivFuncs; ++f)
+                rad32d[(f * kCells32 + cell_all) * 4 + c] = (float)coef[f][c];
         }
     } else {
         const int cell = cell_all - kCells32;
         for (int f = 0; f < 4; ++f)
             for (int c = 0; c < 4; ++c) rad64[(size_t)cell * kCellVals + 4 * f + c] = coef[f][c];
+        for (int f = 0; f < kDerivFuncs; ++f)
+            for (int c = 0; c < 4; ++c)
+                rad64d[(size_t)cell * (4 * kDerivFuncs) + 4 * f + c] = coef[f][c];
     }
 }
 
@@ -1033,19 +1062,600 @@ __global__ void rad_eval_kernel(const float *rad32, const double *rad64, int pre
 }
 
 // ===========================================================================
+// Adjoint: derivatives of a weighted sum of the energy histogram,
+//   L = sum_k w_k H_k   (w = dL/dH from the caller),
+// with respect to the eight shot parameters (a0, W0, x and y offsets, delay,
+// gamma0, sigma_gamma, divergence).  Every sample's trajectory is integrated
+// again together with its tangents: forward-mode derivatives of the discrete
+// RK4 map itself, so no trajectory is stored.  The final tangents are
+// contracted with the sample's sensitivities dL/dmu_f and dL/dsig2_f, taken
+// from its deposited law; the sums over samples are reduced per work item and
+// per shot in a fixed order.
+//
+// Tangent directions.  The sample state depends on the parameters through
+// the amplitude a(psi) = a0 S(x_e, y_e, z_e) f(psi) cos psi along the path
+// (Sec. 2, eq. a0eff) and through the initial energy.  gamma0 and
+// sigma_gamma only enter the initial energy (mu_0 = gamma0 + sigma_gamma n3),
+// so the sigma_gamma tangent is n3 times the gamma0 tangent.  With the
+// amplitude frozen at a0,eff every amplitude direction forces the system
+// with a multiple of S0 f cos psi, so one tangent serves a0 and the four
+// geometric parameters.
+// ===========================================================================
+template <class T>
+struct Rad6 {
+    T g, G1, G2, h, G3, H1;
+};
+
+__device__ __forceinline__ Rad6<float> rad6_eval32(const float *__restrict__ tab, float chi) {
+    const uint32_t b = __float_as_uint(chi);
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    float t = __uint_as_float(((b & ((1u << (23 - kSB32)) - 1)) << kSB32) | 0x3f800000u) - 1.0f;
+    if (c < 1) {
+        c = 0;
+        t = chi * 0x1p20f;
+    }
+    c = min(c, kCells32 - 1);  // beyond the table: reported by the caller
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+    float v[kDerivFuncs];
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f) {
+        const float4 q = T[f * kCells32 + c];
+        v[f] = fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+    }
+    return Rad6<float>{v[0], v[1], v[2], v[3], v[4], v[5]};
+}
+
+__device__ __forceinline__ Rad6<double> rad6_eval64(const double *__restrict__ tab, double chi) {
+    const uint64_t b = (uint64_t)__double_as_longlong(chi);
+    int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
+    double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
+                                                0x3ff0000000000000ull)) - 1.0;
+    if (c < 1) {
+        c = 0;
+        t = chi * 0x1p20;
+    }
+    c = c < kCells64 - 1 ? c : kCells64 - 1;
+    const double *q = tab + (size_t)c * (4 * kDerivFuncs);
+    double v[kDerivFuncs];
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f)
+        v[f] = fma(t, fma(t, fma(t, q[4 * f + 3], q[4 * f + 2]), q[4 * f + 1]), q[4 * f]);
+    return Rad6<double>{v[0], v[1], v[2], v[3], v[4], v[5]};
+}
+
+__device__ __forceinline__ Rad6<float> rad6_eval(const float *tab, float chi) {
+    return rad6_eval32(tab, chi);
+}
+__device__ __forceinline__ Rad6<double> rad6_eval(const double *tab, double chi) {
+    return rad6_eval64(tab, chi);
+}
+
+// Right-hand side f = (dmu/dpsi, dsig2/dpsi) of the moment system and its
+// partial derivatives with respect to mu, sig2 and the amplitude a.  With
+// chi d/dchi written D (D g = G1, D G1 = G1 + G2, D G2 = 2 G2 + G3,
+// D h = H1), E1 = 2g + G1, E2 = 2g + 4 G1 + G2, u = K a^2:
+//   f_mu  = -u (mu^2 g + sig2 E2 / 2),      f_s2 = -2 u mu sig2 E1 + C_D |a|^3 mu^4 h,
+//   d f_mu / d mu   = -u (mu E1 + sig2 (6 G1 + 6 G2 + G3) / (2 mu)),
+//   d f_mu / d sig2 = -u E2 / 2,
+//   d f_s2 / d mu   = -2 u sig2 E2 + C_D |a|^3 mu^3 (4 h + H1),
+//   d f_s2 / d sig2 = -2 u mu E1,
+//   d f_mu / d a    = -K a (mu^2 E1 + sig2 (2g + 7 G1 + 4 G2 + G3 / 2)),
+//   d f_s2 / d a    = -2 K a mu sig2 (4g + 5 G1 + G2) + C_D a |a| mu^4 (3 h + H1).
+// Classical model (g = 1, no diffusion; sig2 stays 0): f_mu = -u mu^2.
+template <class T>
+struct Jac {
+    T fm, fs, mm, ms, sm, ss, ma, sa;
+};
+
+template <class T, bool QUANTUM>
+__device__ __forceinline__ Jac<T> rhs_jac(T mu, T s2, T a, const Phys<T> &ph, const T *tab,
+                                          T &chi_hi) {
+    Jac<T> J;
+    const T Ka = ph.K * a;
+    const T u = Ka * a;
+    if (!QUANTUM) {
+        J.fm = -u * mu * mu;
+        J.mm = T(-2) * u * mu;
+        J.ma = T(-2) * Ka * mu * mu;
+        J.fs = J.ms = J.sm = J.ss = J.sa = T(0);
+        return J;
+    }
+    const T aa = fabs(a);
+    const T chi = ph.two_over_aS * mu * aa;
+    chi_hi = fmax(chi_hi, chi);
+    const Rad6<T> r = rad6_eval(tab, chi);
+    const T E1 = fma(T(2), r.g, r.G1);
+    const T E2 = fma(T(4), r.G1, fma(T(2), r.g, r.G2));
+    const T E3 = fma(T(6), r.G1 + r.G2, r.G3);
+    const T mu2 = mu * mu;
+    const T c3 = ph.CD * aa * a * mu2;  // C_D a |a| mu^2
+    const T hs = T(0.5) * s2;
+    J.fm = -u * fma(mu2, r.g, hs * E2);
+    J.fs = fma(T(-2) * u * mu * s2, E1, c3 * mu2 * a * r.h);
+    J.mm = -u * fma(mu, E1, hs * E3 / mu);
+    J.ms = T(-0.5) * u * E2;
+    J.sm = fma(T(-2) * u * s2, E2, c3 * mu * a * fma(T(4), r.h, r.H1));
+    J.ss = T(-2) * u * mu * E1;
+    const T F = fma(T(7), r.G1, fma(T(4), r.G2, fma(T(0.5), r.G3, T(2) * r.g)));
+    J.ma = -Ka * fma(mu2, E1, s2 * F);
+    J.sa = fma(T(-2) * Ka * mu * s2, fma(T(4), r.g, fma(T(5), r.G1, r.G2)),
+               c3 * mu2 * fma(T(3), r.h, r.H1));
+    return J;
+}
+
+// Spatial factor of eq. a0eff and its logarithmic derivatives with respect to
+// the sample position (x, y, z) and the spot size W0:
+//   ln S = -p - ln(q)/2,  p = (x^2 + y^2) / (W0^2 q),  q = 1 + (z / zR)^2,
+//   d/dx = -2 x / (W0^2 q),  d/dz = 2 (z / zR^2) (p - 1/2) / q,
+//   d/dW0 = (2 / W0) (p - 2 (z/zR)^2 (p - 1/2) / q)   (zR = pi W0^2 / lambda).
+template <class T>
+struct SpD {
+    T S, Lx, Ly, Lz, Lw;
+};
+
+__device__ __forceinline__ SpD<float> spatial_d(float x, float y, float z, float inv_w0sq,
+                                                float inv_zR, float inv_w0) {
+    const float zz = z * inv_zR;
+    const float q = fmaf(zz, zz, 1.0f);
+    const float rq = __builtin_amdgcn_rsqf(q);
+    const float iq = rq * rq;
+    const float p = fmaf(x, x, y * y) * inv_w0sq * iq;
+    SpD<float> r;
+    r.S = __builtin_amdgcn_exp2f(-1.4426950408889634f * p) * rq;
+    const float m = -2.0f * inv_w0sq * iq;
+    r.Lx = m * x;
+    r.Ly = m * y;
+    const float B = iq * (p - 0.5f);
+    r.Lz = 2.0f * zz * inv_zR * B;
+    r.Lw = 2.0f * inv_w0 * fmaf(-2.0f * zz * zz, B, p);
+    return r;
+}
+
+__device__ __forceinline__ SpD<double> spatial_d(double x, double y, double z, double inv_w0sq,
+                                                 double inv_zR, double inv_w0) {
+    const double zz = z * inv_zR;
+    const double q = fma(zz, zz, 1.0);
+    const double iq = 1.0 / q;
+    const double p = fma(x, x, y * y) * inv_w0sq * iq;
+    SpD<double> r;
+    r.S = exp(-p) * sqrt(iq);
+    const double m = -2.0 * inv_w0sq * iq;
+    r.Lx = m * x;
+    r.Ly = m * y;
+    const double B = iq * (p - 0.5);
+    r.Lz = 2.0 * zz * inv_zR * B;
+    r.Lw = 2.0 * inv_w0 * fma(-2.0 * zz * zz, B, p);
+    return r;
+}
+
+// Directions of the local-amplitude tangents: a0, W0, x offset, y offset,
+// delay, gamma0, divergence.
+constexpr int kDirLocal = 7;
+constexpr int kDirA0eff = 2;  // a0 (all amplitude directions), gamma0
+
+// Geometry of one sample in the adjoint's precision.
+template <class T>
+struct AdjPath {
+    T xc, yc, thx, thy, zstar, hz;     // hz = z / 2
+    T dthx, dthy;                      // d theta / d div_mrad = 1e-3 n4, 1e-3 n5
+    T inv_w0sq, inv_zR, inv_w0, a0, zfac;  // zfac = d z* / d delay = c / 2
+    // amplitude without the carrier and its derivative in each direction
+    __device__ __forceinline__ void amp(T ell, T fc, T &a, T *da) const {
+        const SpD<T> d = spatial_d(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell, inv_w0sq,
+                                   inv_zR, inv_w0);
+        const T Sf = d.S * fc;
+        a = a0 * Sf;
+        da[0] = Sf;
+        da[1] = a * d.Lw;
+        da[2] = a * d.Lx;
+        da[3] = a * d.Ly;
+        da[4] = a * zfac * d.Lz;
+        da[5] = T(0);
+        da[6] = a * (hz + ell) * fma(dthx, d.Lx, dthy * d.Ly);
+    }
+};
+
+// One RK4 step of the state and of its tangents (vm, vs: d mu / d dir,
+// d sig2 / d dir).  da1, dah, da4: amplitude derivatives at the three phases.
+template <class T, int ND, bool QUANTUM>
+__device__ __forceinline__ void rk4_tangent(T mu, T s2, T a1, T ah, T a4, const T *da1,
+                                            const T *dah, const T *da4, T h, const Phys<T> &ph,
+                                            const T *tab, T *vm, T *vs, T &dmu, T &ds2,
+                                            T &chi_hi) {
+    const T hh = T(0.5) * h;
+    T am[ND], as[ND], wm[ND], ws[ND];
+    // stage 1
+    Jac<T> J = rhs_jac<T, QUANTUM>(mu, s2, a1, ph, tab, chi_hi);
+    const T k1m = J.fm, k1s = J.fs;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        T km = fma(J.mm, vm[d], J.ma * da1[d]);
+        T ks = T(0);
+        if (QUANTUM) {
+            km = fma(J.ms, vs[d], km);
+            ks = fma(J.sm, vm[d], fma(J.ss, vs[d], J.sa * da1[d]));
+        }
+        am[d] = km;
+        as[d] = ks;
+        wm[d] = fma(hh, km, vm[d]);
+        ws[d] = fma(hh, ks, vs[d]);
+    }
+    // stage 2
+    J = rhs_jac<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, chi_hi);
+    const T k2m = J.fm, k2s = J.fs;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        T km = fma(J.mm, wm[d], J.ma * dah[d]);
+        T ks = T(0);
+        if (QUANTUM) {
+            km = fma(J.ms, ws[d], km);
+            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * dah[d]));
+        }
+        am[d] = fma(T(2), km, am[d]);
+        as[d] = fma(T(2), ks, as[d]);
+        wm[d] = fma(hh, km, vm[d]);
+        ws[d] = fma(hh, ks, vs[d]);
+    }
+    // stage 3
+    J = rhs_jac<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, chi_hi);
+    const T k3m = J.fm, k3s = J.fs;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        T km = fma(J.mm, wm[d], J.ma * dah[d]);
+        T ks = T(0);
+        if (QUANTUM) {
+            km = fma(J.ms, ws[d], km);
+            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * dah[d]));
+        }
+        am[d] = fma(T(2), km, am[d]);
+        as[d] = fma(T(2), ks, as[d]);
+        wm[d] = fma(h, km, vm[d]);
+        ws[d] = fma(h, ks, vs[d]);
+    }
+    // stage 4
+    J = rhs_jac<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, chi_hi);
+    const T k4m = J.fm, k4s = J.fs;
+    const T h6 = h * T(1.0 / 6.0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        T km = fma(J.mm, wm[d], J.ma * da4[d]);
+        T ks = T(0);
+        if (QUANTUM) {
+            km = fma(J.ms, ws[d], km);
+            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * da4[d]));
+        }
+        vm[d] = fma(h6, am[d] + km, vm[d]);
+        if (QUANTUM) vs[d] = fma(h6, as[d] + ks, vs[d]);
+    }
+    dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
+    ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+}
+
+// Sensitivities of one sample's share of L = sum_k w_k H_k to the centre v
+// and the variance sig2 of its energy law.  Writing F for the law's CDF and
+// e_j = lo + j width (j = 0..n) for the bin edges, the sample adds F(e_0) to
+// the underflow, F(e_{k+1}) - F(e_k) to bin k and 1 - F(e_n) to the overflow,
+// so its share is sum_j c_j F(e_j) + w_over with c_j = w_{j-1} - w_j
+// (w_{-1} = w_under, w_n = w_over).  For the three laws (with t = e_j - v):
+//   Gaussian N(v, s^2):  dF/dv = -phi(t/s)/s,          dF/ds = -(t/s) phi(t/s)/s;
+//   box of width b:      dF/dv = -1/b for |t| < b/2,   no s;
+//   box (x) N(0, s^2):   dF/dv = -(Phi((t + b/2)/s) - Phi((t - b/2)/s)) / b,
+//                        dF/ds = (phi((t + b/2)/s) - phi((t - b/2)/s)) / b.
+// Edges beyond 9 standard deviations add nothing at FP64 precision.
+__device__ __forceinline__ double phi_pdf(double z) {
+    return 0.39894228040143267794 * exp(-0.5 * z * z);
+}
+
+__device__ __forceinline__ double phi_diff(double zp, double zm) {  // Phi(zp) - Phi(zm), zp > zm
+    const double r = 0.70710678118654752440;
+    if (zm > 0.0) return 0.5 * (erfc(zm * r) - erfc(zp * r));
+    if (zp < 0.0) return 0.5 * (erfc(-zp * r) - erfc(-zm * r));
+    return 1.0 - 0.5 * (erfc(zp * r) + erfc(-zm * r));
+}
+
+__device__ void law_sensitivity(double v, double s2, int dep, double ksig, double lo, double wb,
+                                int n, const double *__restrict__ W, double &lv, double &ls2) {
+    lv = 0.0;
+    ls2 = 0.0;
+    const double s = sqrt(fmax(s2, 0.0));
+    const double half = 0.5 * wb;
+    int mode;
+    double se = s, dse = 0.0;  // law width and d se / d sig2
+    if (dep == 2) {            // GAUSS
+        const double ks = ksig * wb;
+        se = sqrt(s * s + ks * ks);
+        mode = se > 0.0 ? 2 : 0;
+        if (s2 > 0.0) dse = 0.5 / se;
+    } else if (dep == 1) {  // CIC
+        mode = s > 0.0 ? 3 : 1;
+        if (s > 0.0) dse = 0.5 / s;
+    } else {
+        mode = s > 0.0 ? 2 : 0;
+        if (s > 0.0) dse = 0.5 / s;
+    }
+    if (mode == 0) return;
+    const double reach = mode == 1 ? half : (mode == 2 ? 9.0 * se : 9.0 * se + half);
+    const int ja = (int)fmin(fmax(ceil((v - reach - lo) / wb), 0.0), (double)n + 1.0);
+    const int jb = (int)fmin(fmax(floor((v + reach - lo) / wb), -1.0), (double)n);
+    const double inv_se = mode >= 2 ? 1.0 / se : 0.0;
+    double sv = 0.0, ss = 0.0;
+    for (int j = ja; j <= jb; ++j) {
+        const double wl = j == 0 ? W[n] : W[j - 1];
+        const double wr = j == n ? W[n + 1] : W[j];
+        const double c = wl - wr;
+        if (c == 0.0) continue;
+        const double t = fma((double)j, wb, lo) - v;
+        double p, q = 0.0;
+        if (mode == 1) {
+            p = fabs(t) < half ? 1.0 / wb : 0.0;
+        } else if (mode == 2) {
+            const double z = t * inv_se;
+            const double f = phi_pdf(z) * inv_se;
+            p = f;
+            q = -z * f;
+        } else {
+            const double zp = (t + half) * inv_se, zm = (t - half) * inv_se;
+            p = phi_diff(zp, zm) / wb;
+            q = (phi_pdf(zp) - phi_pdf(zm)) / wb;
+        }
+        sv = fma(c, p, sv);
+        ss = fma(c, q, ss);
+    }
+    lv = -sv;
+    ls2 = ss * dse;
+}
+
+// One sample of the adjoint: returns its eight derivative terms in g.
+template <int PREC, bool QUANTUM, bool LOCAL>
+__device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotParams &sp,
+                                               const ShotGrad &so, int64_t i,
+                                               const float *__restrict__ env32,
+                                               const double *__restrict__ env64,
+                                               const float *tab32, double *g, int &flags) {
+    using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    constexpr int ND = LOCAL ? kDirLocal : kDirA0eff;
+    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
+    const int N = P.n_steps;
+    const T *tab;
+    if constexpr (PREC == PREC_F64)
+        tab = P.rad64d;
+    else
+        tab = tab32;
+    const T *env;
+    if constexpr (PREC == PREC_F64)
+        env = env64;
+    else
+        env = env32;
+    Phys<T> ph;
+    ph.K = (T)P.K;
+    ph.CD = (T)P.CD;
+    ph.two_over_aS = (T)P.two_over_aS;
+    const float chi_top = (float)(1 << (kEMax + 1));
+
+    // ---- sample and geometry (FP64) ----
+    double nrm[6];
+    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
+    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
+    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
+    const double z = sp.sigma_z * nrm[2];
+    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
+    const double thx = sp.div_rad * nrm[4];
+    const double thy = sp.div_rad * nrm[5];
+    const double inv_w0 = sqrt(sp.inv_w0sq);
+    const double xc = fma(thx, 0.5 * z, x), yc = fma(thy, 0.5 * z, y);
+    const double zstar = fma(0.5, z, sp.z_delay);
+    const SpD<double> d0 = spatial_d(xc, yc, zstar, sp.inv_w0sq, sp.inv_zR, inv_w0);
+
+    AdjPath<T> pth;
+    pth.xc = (T)xc;
+    pth.yc = (T)yc;
+    pth.thx = (T)thx;
+    pth.thy = (T)thy;
+    pth.zstar = (T)zstar;
+    pth.hz = (T)(0.5 * z);
+    pth.dthx = (T)(1e-3 * nrm[4]);
+    pth.dthy = (T)(1e-3 * nrm[5]);
+    pth.inv_w0sq = (T)sp.inv_w0sq;
+    pth.inv_zR = (T)sp.inv_zR;
+    pth.inv_w0 = (T)inv_w0;
+    pth.a0 = (T)sp.a0;
+    pth.zfac = (T)kHalfC;
+    const T S0 = (T)d0.S;
+    const T ell_per_psi = (T)P.ell_per_psi;
+    const T h = (T)P.h;
+    const T psi0 = (T)(-P.psi_max);
+
+    T vm[ND], vs[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) vm[d] = vs[d] = T(0);
+    vm[LOCAL ? 5 : 1] = T(1);  // d mu_0 / d gamma0
+
+    T mu = (T)g0, mu_lo = T(0), s2 = T(0), s2_lo = T(0);
+    double g0_rest = 0.0;
+    if constexpr (PREC != PREC_F64) {
+        mu_lo = (T)(g0 - (double)mu);
+        g0_rest = (g0 - (double)mu) - (double)mu_lo;
+    }
+    T chi_hi = T(0);
+    T a1, da1[ND];
+    if (LOCAL) {
+        pth.amp(psi0 * ell_per_psi, env[0], a1, da1);
+    } else {
+        const T Sf = S0 * env[0];
+        a1 = pth.a0 * Sf;
+        da1[0] = Sf;
+        da1[1] = T(0);
+    }
+    for (int j = 0; j < N; ++j) {
+        const T psi = fma((T)j, h, psi0);
+        T ah, a4, dah[ND], da4[ND];
+        if (LOCAL) {
+            pth.amp(fma(T(0.5), h, psi) * ell_per_psi, env[2 * j + 1], ah, dah);
+            pth.amp((psi + h) * ell_per_psi, env[2 * j + 2], a4, da4);
+        } else {
+            const T Sh = S0 * env[2 * j + 1], S4 = S0 * env[2 * j + 2];
+            ah = pth.a0 * Sh;
+            a4 = pth.a0 * S4;
+            dah[0] = Sh;
+            da4[0] = S4;
+            dah[1] = da4[1] = T(0);
+        }
+        T dm, ds;
+        rk4_tangent<T, ND, QUANTUM>(mu, s2, a1, ah, a4, da1, dah, da4, h, ph, tab, vm, vs, dm, ds,
+                                    chi_hi);
+        if constexpr (PREC == PREC_F64) {
+            mu += dm;
+            s2 += ds;
+        } else {
+            comp_add(mu, mu_lo, dm);
+            comp_add(s2, s2_lo, ds);
+        }
+        a1 = a4;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) da1[d] = da4[d];
+    }
+    const double mu_f = ((double)mu + (double)mu_lo) + g0_rest;
+    const double s2_f = (double)s2 + (double)s2_lo;
+    if (QUANTUM && !((float)chi_hi < chi_top)) flags |= kFlagRange;
+#pragma unroll
+    for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
+    if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
+        flags |= kFlagNonFinite;
+        return;
+    }
+    double lv, ls;
+    law_sensitivity(mu_f, s2_f, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e, so.d_energy, lv,
+                    ls);
+    double t[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) t[d] = fma(lv, (double)vm[d], QUANTUM ? ls * (double)vs[d] : 0.0);
+    if (LOCAL) {
+        g[0] = t[0];
+        g[1] = t[1];
+        g[2] = t[2];
+        g[3] = t[3];
+        g[4] = t[4];
+        g[5] = t[5];
+        g[6] = nrm[3] * t[5];
+        g[7] = t[6];
+    } else {
+        const double b = sp.a0 * t[0];
+        g[0] = t[0];
+        g[1] = b * d0.Lw;
+        g[2] = b * d0.Lx;
+        g[3] = b * d0.Ly;
+        g[4] = b * kHalfC * d0.Lz;
+        g[5] = t[1];
+        g[6] = nrm[3] * t[1];
+        g[7] = b * (0.5 * z) * fma(1e-3 * nrm[4], d0.Lx, 1e-3 * nrm[5] * d0.Ly);
+    }
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+__global__ __launch_bounds__(kPhaseBlock) void adjoint_kernel(BatchParams P,
+                                                              const float *__restrict__ env32,
+                                                              const double *__restrict__ env64) {
+    constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    __shared__ __align__(16) float tab32[kTab32 ? kCells32 * 4 * kDerivFuncs : 4];
+    __shared__ int64_t slot;
+    __shared__ double red[kPhaseBlock / 64][kGradParams];
+    if (kTab32) {
+        const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
+        float4 *dst = reinterpret_cast<float4 *>(tab32);
+        for (int k = threadIdx.x; k < kCells32 * kDerivFuncs; k += blockDim.x) dst[k] = src[k];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_items) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sp = P.shots[s];
+        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        double g[kGradParams];
+#pragma unroll
+        for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
+        if (i < sp.n_samples) {
+            int flags = 0;
+            adjoint_sample<PREC, QUANTUM, LOCAL>(P, sp, P.gouts[s], i, env32, env64, tab32, g,
+                                                 flags);
+            if (flags) atomicOr(&P.flags[s], flags);
+        }
+        // fixed-order item reduction
+#pragma unroll
+        for (int p = 0; p < kGradParams; ++p) {
+            const double v = wave_sum(g[p]);
+            if (lane == 0) red[wid][p] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kGradParams) {
+            double sum = 0.0;
+            for (int w = 0; w < kPhaseBlock / 64; ++w) sum += red[w][threadIdx.x];
+            P.partials[(size_t)item * kGradParams + threadIdx.x] = sum;
+        }
+        // red is rewritten only after the next item's barriers
+    }
+}
+
+// One block per shot: fixed-order sum of the shot's item partials.
+__global__ __launch_bounds__(256) void grad_finalize_kernel(BatchParams P) {
+    const int s = blockIdx.x;
+    const ShotParams &sp = P.shots[s];
+    const ShotGrad &so = P.gouts[s];
+    const int64_t ni = (sp.n_samples + kPhaseBlock - 1) / kPhaseBlock;
+    __shared__ double tree[256];
+    for (int p = 0; p < kGradParams; ++p) {
+        double acc = 0.0;
+        for (int64_t b = threadIdx.x; b < ni; b += blockDim.x)
+            acc += P.partials[(size_t)(sp.item0 + b) * kGradParams + p];
+        tree[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) so.grad[p] = tree[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && so.status) {
+        const int fl = P.flags[s];
+        *so.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
+    }
+}
+
+__global__ void rad_derivs_kernel(const float *rad32d, const double *rad64d, int prec, int64_t n,
+                                  const double *chi, double *out, int *flags) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int fl = (chi[k] < (double)(1 << (kEMax + 1))) ? 0 : kFlagRange;
+    double v[kDerivFuncs];
+    if (prec == 0) {
+        const Rad6<float> r = rad6_eval32(rad32d, (float)chi[k]);
+        v[0] = r.g; v[1] = r.G1; v[2] = r.G2; v[3] = r.h; v[4] = r.G3; v[5] = r.H1;
+    } else {
+        const Rad6<double> r = rad6_eval64(rad64d, chi[k]);
+        v[0] = r.g; v[1] = r.G1; v[2] = r.G2; v[3] = r.h; v[4] = r.G3; v[5] = r.H1;
+    }
+    for (int f = 0; f < kDerivFuncs; ++f) out[kDerivFuncs * k + f] = v[f];
+    if (fl) atomicOr(flags, fl);
+}
+
+// ===========================================================================
 // Launchers
 // ===========================================================================
-size_t radiation_work_doubles() { return (size_t)kNY * 6 + (size_t)4 * 4 * (kCells32 + kCells64); }
+size_t radiation_work_doubles() {
+    return (size_t)kNY * kYVals + (size_t)4 * kNodeVals * (kCells32 + kCells64);
+}
 
-hipError_t build_radiation_tables(float *rad32, double *rad64, double *work, size_t work_doubles,
-                                  hipStream_t s) {
+hipError_t build_radiation_tables(float *rad32, double *rad64, float *rad32d, double *rad64d,
+                                  double *work, size_t work_doubles, hipStream_t s) {
     if (work_doubles < radiation_work_doubles()) return hipErrorInvalidValue;
-    double *yf = work, *vals = work + (size_t)kNY * 6;
+    double *yf = work, *vals = work + (size_t)kNY * kYVals;
     rad_y_kernel<<<(kNY + 63) / 64, 64, 0, s>>>(yf);
     const int nodes = 4 * (kCells32 + kCells64);
     rad_node_kernel<<<(nodes + 63) / 64, 64, 0, s>>>(yf, vals);
     const int cells = kCells32 + kCells64;
-    rad_coef_kernel<<<(cells + 63) / 64, 64, 0, s>>>(vals, rad32, rad64);
+    rad_coef_kernel<<<(cells + 63) / 64, 64, 0, s>>>(vals, rad32, rad64, rad32d, rad64d);
     return hipGetLastError();
 }
 
@@ -1139,6 +1749,44 @@ hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int pr
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     rad_eval_kernel<<<(unsigned)blocks, 256, 0, s>>>(rad32, rad64, prec, n, chi, out, flags);
+    return hipGetLastError();
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+static const void *adjoint_ptr() {
+    return reinterpret_cast<const void *>(&adjoint_kernel<PREC, QUANTUM, LOCAL>);
+}
+
+hipError_t launch_adjoint(const BatchParams &p, const float *env32, const double *env64, int prec,
+                          int rr, int amp, hipStream_t s) {
+    const bool q = rr == 1, l = amp == 1;
+    const void *fn;
+    if (prec == PREC_F64)
+        fn = q ? (l ? adjoint_ptr<PREC_F64, true, true>() : adjoint_ptr<PREC_F64, true, false>())
+               : (l ? adjoint_ptr<PREC_F64, false, true>() : adjoint_ptr<PREC_F64, false, false>());
+    else
+        fn = q ? (l ? adjoint_ptr<PREC_F32, true, true>() : adjoint_ptr<PREC_F32, true, false>())
+               : (l ? adjoint_ptr<PREC_F32, false, true>() : adjoint_ptr<PREC_F32, false, false>());
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    BatchParams pc = p;
+    const float *e32 = env32;
+    const double *e64 = env64;
+    void *args[] = {&pc, &e32, &e64};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+}
+
+hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {
+    grad_finalize_kernel<<<p.n_shots, 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, int prec, int64_t n,
+                                   const double *chi, double *out, int *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    rad_derivs_kernel<<<(unsigned)blocks, 256, 0, s>>>(rad32d, rad64d, prec, n, chi, out, flags);
     return hipGetLastError();
 }
 
