@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2,
                     help="timed launches of the 4096-shot batch (0 skips that leg)")
+    ap.add_argument("--adjoint-steps", type=int, default=3,
+                    help="timed forward+adjoint steps on the differentiation workload (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -95,6 +99,61 @@ def cpu_baseline(params, target_s):
             "kind": "oracle",
             "sample": f"first {n} of {params['n_samples']} samples x {params['n_steps']} steps "
                       f"({dt:.1f} s wall, FP64, {threads} threads)"}
+
+
+def adjoint_leg(ctx, qs, workloads, torch, steps):
+    """Forward + adjoint on the differentiation workload: a Neyman chi^2 loss
+    against a Poisson target drawn from the histogram at the reference
+    parameters, evaluated at perturbed parameters; one step = forward, loss,
+    upstream weights, adjoint (all on the device)."""
+    ref = workloads.differentiation()
+    p = workloads.differentiation_eval()
+    n, N = p["n_samples"], p["n_steps"]
+    n_tot = 1e6
+    h_ref = ctx.forward(ref)["energy_hist"].cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(4))
+    target = torch.tensor(rng.poisson(n_tot * h_ref / n).astype(np.float64), device="cuda")
+    denom = torch.clamp(target, min=1.0)
+
+    def step():
+        h = ctx.forward(p, check=False)["energy_hist"]
+        r = n_tot * h / n - target
+        loss = (r * r / denom).sum()
+        w = 2.0 * r / denom * (n_tot / n)
+        g = ctx.backward(p, w, check=False)
+        return loss, g
+
+    loss, g = step()  # warm-up and scratch allocation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss, g = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the two halves on their own
+    out = ctx.forward(p)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.forward(p, out=out, check=False)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    w = torch.ones(p["n_e"] + 2, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.backward(p, w, check=False)
+    torch.cuda.synchronize()
+    t_bwd = (time.perf_counter() - t0) / steps
+    g = g.cpu().numpy()
+    if not np.all(np.isfinite(g)):
+        raise RuntimeError("non-finite gradient in the adjoint leg")
+    return {"workload": "differentiation: focused-shot physics, GAUSS deposit (1 bin), 2^20 "
+                        "samples x 1024 steps, quantum, local amplitude; Neyman chi^2 loss vs a "
+                        "Poisson target (1e6 counts) at parameters perturbed by 5%",
+            "n_samples": n, "n_steps": N, "steps": steps, "ms_per_step": 1e3 * dt,
+            "fwd_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_bwd,
+            "step_over_fwd": dt / t_fwd,
+            "sample_steps_per_s": n * N / dt, "loss": float(loss),
+            "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
 
 def main():
@@ -179,6 +238,8 @@ def main():
             "steps": args.batched_steps, "ms_per_batch": 1e3 * dt,
             "spectra_per_s": len(shots) / dt,
             "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt}
+    if args.adjoint_steps > 0:
+        line["adjoint"] = adjoint_leg(ctx, qs, workloads, torch, args.adjoint_steps)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)

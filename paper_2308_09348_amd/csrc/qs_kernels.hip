@@ -1024,8 +1024,13 @@ __global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64,
             const double mix[4] = {coef[0][c], 2.0 * coef[0][c] + coef[1][c],
                                    coef[0][c] + 2.0 * coef[1][c] + 0.5 * coef[2][c], coef[3][c]};
             for (int f = 0; f < 4; ++f) rad32[(f * kCells32 + cell_all) * 4 + c] = (float)mix[f];
+            // g, E1 = 2g + G1, E2 = 2g + 4 G1 + G2, E3 = 6 G1 + 6 G2 + G3, h, H1
+            const double jm[kDerivFuncs] = {
+                coef[0][c], 2.0 * coef[0][c] + coef[1][c],
+                2.0 * coef[0][c] + 4.0 * coef[1][c] + coef[2][c],
+                6.0 * (coef[1][c] + coef[2][c]) + coef[4][c], coef[3][c], coef[5][c]};
             for (int f = 0; f < kDerivFuncs; ++f)
-                rad32d[(f * kCells32 + cell_all) * 4 + c] = (float)coef[f][c];
+                rad32d[(f * kCells32 + cell_all) * 4 + c] = (float)jm[f];
         }
     } else {
         const int cell = cell_all - kCells32;
@@ -1081,31 +1086,60 @@ __global__ void rad_eval_kernel(const float *rad32, const double *rad64, int pre
 // with a multiple of S0 f cos psi, so one tangent serves a0 and the four
 // geometric parameters.
 // ===========================================================================
+// Radiation functions in the combinations the Jacobian uses:
+//   g,  E1 = 2g + G1,  E2 = 2g + 4 G1 + G2,  E3 = 6 G1 + 6 G2 + G3,  h,  H1
+// (G1 = chi g', G2 = chi^2 g'', G3 = chi^3 g''', H1 = chi h').  The FP32
+// derivative table stores these combinations; the FP64 one the plain
+// functions.
 template <class T>
-struct Rad6 {
-    T g, G1, G2, h, G3, H1;
+struct RadJ {
+    T g, E1, E2, E3, h, H1;
 };
 
-__device__ __forceinline__ Rad6<float> rad6_eval32(const float *__restrict__ tab, float chi) {
+// One FP32 derivative-table cell in registers (see RadCell32).
+struct RadCell6 {
+    float4 q[kDerivFuncs];
+    float tw, ts;
+};
+
+__device__ __forceinline__ void rad6_lookup32(const float *__restrict__ tab, float chi,
+                                              RadCell6 &cell) {
     const uint32_t b = __float_as_uint(chi);
     int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
-    float t = __uint_as_float(((b & ((1u << (23 - kSB32)) - 1)) << kSB32) | 0x3f800000u) - 1.0f;
-    if (c < 1) {
+    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
         c = 0;
-        t = chi * 0x1p20f;
+        tw = 0x1p20f;
+        ts = 0.0f;
     }
-    c = min(c, kCells32 - 1);  // beyond the table: reported by the caller
+    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
+        c = kCells32 - 1;
+        tw = 0.0f;
+        ts = 1.0f;
+    }
     const float4 *T = reinterpret_cast<const float4 *>(tab);
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f) cell.q[f] = T[f * kCells32 + c];
+    cell.tw = tw;
+    cell.ts = ts;
+}
+
+__device__ __forceinline__ RadJ<float> rad6_cell_eval(const RadCell6 &cell, float chi) {
+    const float t = fmaf(chi, cell.tw, cell.ts);
     float v[kDerivFuncs];
 #pragma unroll
     for (int f = 0; f < kDerivFuncs; ++f) {
-        const float4 q = T[f * kCells32 + c];
+        const float4 &q = cell.q[f];
         v[f] = fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
     }
-    return Rad6<float>{v[0], v[1], v[2], v[3], v[4], v[5]};
+    return RadJ<float>{v[0], v[1], v[2], v[3], v[4], v[5]};
 }
 
-__device__ __forceinline__ Rad6<double> rad6_eval64(const double *__restrict__ tab, double chi) {
+// FP64 table, cell-major [cell][g, G1, G2, h, G3, H1][power]: the plain
+// functions, combined here.
+__device__ __forceinline__ void rad6_plain64(const double *__restrict__ tab, double chi,
+                                             double v[kDerivFuncs]) {
     const uint64_t b = (uint64_t)__double_as_longlong(chi);
     int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
     double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
@@ -1116,71 +1150,240 @@ __device__ __forceinline__ Rad6<double> rad6_eval64(const double *__restrict__ t
     }
     c = c < kCells64 - 1 ? c : kCells64 - 1;
     const double *q = tab + (size_t)c * (4 * kDerivFuncs);
-    double v[kDerivFuncs];
 #pragma unroll
     for (int f = 0; f < kDerivFuncs; ++f)
         v[f] = fma(t, fma(t, fma(t, q[4 * f + 3], q[4 * f + 2]), q[4 * f + 1]), q[4 * f]);
-    return Rad6<double>{v[0], v[1], v[2], v[3], v[4], v[5]};
 }
 
-__device__ __forceinline__ Rad6<float> rad6_eval(const float *tab, float chi) {
-    return rad6_eval32(tab, chi);
+__device__ __forceinline__ RadJ<double> radj_eval64(const double *__restrict__ tab, double chi) {
+    double v[kDerivFuncs];
+    rad6_plain64(tab, chi, v);
+    const double g = v[0], G1 = v[1], G2 = v[2], h = v[3], G3 = v[4], H1 = v[5];
+    return RadJ<double>{g, fma(2.0, g, G1), fma(4.0, G1, fma(2.0, g, G2)), fma(6.0, G1 + G2, G3),
+                        h, H1};
 }
-__device__ __forceinline__ Rad6<double> rad6_eval(const double *tab, double chi) {
-    return rad6_eval64(tab, chi);
-}
+
+// Where a stage takes its radiation functions from.  FP32: the LDS table,
+// read at stages 2 and 4 only -- stage 3 reuses stage 2's cell and the next
+// step's stage 1 reuses stage 4's (as in the forward phase loop).  FP64: the
+// global table at every stage.
+template <class T>
+struct RadSrc;
+template <>
+struct RadSrc<float> {
+    const float *tab;
+    RadCell6 carry, mid;
+    __device__ __forceinline__ void init(float chi) { rad6_lookup32(tab, chi, carry); }
+    __device__ __forceinline__ RadJ<float> s1(float chi) { return rad6_cell_eval(carry, chi); }
+    __device__ __forceinline__ RadJ<float> s2(float chi) {
+        rad6_lookup32(tab, chi, mid);
+        return rad6_cell_eval(mid, chi);
+    }
+    __device__ __forceinline__ RadJ<float> s3(float chi) { return rad6_cell_eval(mid, chi); }
+    __device__ __forceinline__ RadJ<float> s4(float chi) {
+        rad6_lookup32(tab, chi, carry);
+        return rad6_cell_eval(carry, chi);
+    }
+};
+template <>
+struct RadSrc<double> {
+    const double *tab;
+    __device__ __forceinline__ void init(double) {}
+    __device__ __forceinline__ RadJ<double> s1(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s2(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s3(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s4(double chi) { return radj_eval64(tab, chi); }
+};
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Right-hand side f = (dmu/dpsi, dsig2/dpsi) of the moment system and its
 // partial derivatives with respect to mu, sig2 and the amplitude a.  With
 // chi d/dchi written D (D g = G1, D G1 = G1 + G2, D G2 = 2 G2 + G3,
-// D h = H1), E1 = 2g + G1, E2 = 2g + 4 G1 + G2, u = K a^2:
+// D h = H1) and u = K a^2:
 //   f_mu  = -u (mu^2 g + sig2 E2 / 2),      f_s2 = -2 u mu sig2 E1 + C_D |a|^3 mu^4 h,
-//   d f_mu / d mu   = -u (mu E1 + sig2 (6 G1 + 6 G2 + G3) / (2 mu)),
+//   d f_mu / d mu   = -u (mu E1 + sig2 E3 / (2 mu)),
 //   d f_mu / d sig2 = -u E2 / 2,
 //   d f_s2 / d mu   = -2 u sig2 E2 + C_D |a|^3 mu^3 (4 h + H1),
 //   d f_s2 / d sig2 = -2 u mu E1,
-//   d f_mu / d a    = -K a (mu^2 E1 + sig2 (2g + 7 G1 + 4 G2 + G3 / 2)),
-//   d f_s2 / d a    = -2 K a mu sig2 (4g + 5 G1 + G2) + C_D a |a| mu^4 (3 h + H1).
+//   d f_mu / d a    = -K a (mu^2 E1 + sig2 (E2 + E3 / 2)),
+//   d f_s2 / d a    = -2 K a mu sig2 (E1 + E2) + C_D a |a| mu^4 (3 h + H1).
 // Classical model (g = 1, no diffusion; sig2 stays 0): f_mu = -u mu^2.
 template <class T>
 struct Jac {
-    T fm, fs, mm, ms, sm, ss, ma, sa;
+    T fm, fs;  // f
+    T mm, ms, sm, ss;  // d f / d (mu, sig2)
+    T ma, sa;  // d f / d a
 };
 
-template <class T, bool QUANTUM>
-__device__ __forceinline__ Jac<T> rhs_jac(T mu, T s2, T a, const Phys<T> &ph, const T *tab,
-                                          T &chi_hi) {
+// Per-stage amplitude constants: a, K a, C_D a |a|, 2 |a| / a_S.
+template <class T>
+struct StageAmp {
+    T a, Ka, cda, chi_per_mu;
+    __device__ __forceinline__ StageAmp(T a_, const Phys<T> &ph)
+        : a(a_), Ka(ph.K * a_), cda(ph.CD * a_ * fabs(a_)), chi_per_mu(ph.two_over_aS * fabs(a_)) {}
+};
+
+template <class T>
+__device__ __forceinline__ Jac<T> jac_quantum(T mu, T s2, const StageAmp<T> &A, const RadJ<T> &r) {
     Jac<T> J;
-    const T Ka = ph.K * a;
-    const T u = Ka * a;
-    if (!QUANTUM) {
-        J.fm = -u * mu * mu;
-        J.mm = T(-2) * u * mu;
-        J.ma = T(-2) * Ka * mu * mu;
-        J.fs = J.ms = J.sm = J.ss = J.sa = T(0);
-        return J;
-    }
-    const T aa = fabs(a);
-    const T chi = ph.two_over_aS * mu * aa;
-    chi_hi = fmax(chi_hi, chi);
-    const Rad6<T> r = rad6_eval(tab, chi);
-    const T E1 = fma(T(2), r.g, r.G1);
-    const T E2 = fma(T(4), r.G1, fma(T(2), r.g, r.G2));
-    const T E3 = fma(T(6), r.G1 + r.G2, r.G3);
+    const T u = A.Ka * A.a;
     const T mu2 = mu * mu;
-    const T c3 = ph.CD * aa * a * mu2;  // C_D a |a| mu^2
     const T hs = T(0.5) * s2;
-    J.fm = -u * fma(mu2, r.g, hs * E2);
-    J.fs = fma(T(-2) * u * mu * s2, E1, c3 * mu2 * a * r.h);
-    J.mm = -u * fma(mu, E1, hs * E3 / mu);
-    J.ms = T(-0.5) * u * E2;
-    J.sm = fma(T(-2) * u * s2, E2, c3 * mu * a * fma(T(4), r.h, r.H1));
-    J.ss = T(-2) * u * mu * E1;
-    const T F = fma(T(7), r.G1, fma(T(4), r.G2, fma(T(0.5), r.G3, T(2) * r.g)));
-    J.ma = -Ka * fma(mu2, E1, s2 * F);
-    J.sa = fma(T(-2) * Ka * mu * s2, fma(T(4), r.g, fma(T(5), r.G1, r.G2)),
-               c3 * mu2 * fma(T(3), r.h, r.H1));
+    const T c3 = A.cda * mu2;        // C_D a |a| mu^2
+    const T c3a = c3 * mu * A.a;     // C_D |a|^3 mu^3
+    const T u2 = T(-2) * u;
+    J.fm = -u * fma(mu2, r.g, hs * r.E2);
+    J.fs = fma(u2 * mu * s2, r.E1, c3a * mu * r.h);
+    J.mm = -u * fma(mu, r.E1, hs * r.E3 * recip(mu));
+    J.ms = T(-0.5) * u * r.E2;
+    J.sm = fma(u2 * s2, r.E2, c3a * fma(T(4), r.h, r.H1));
+    J.ss = u2 * mu * r.E1;
+    J.ma = -A.Ka * fma(mu2, r.E1, s2 * fma(T(0.5), r.E3, r.E2));
+    J.sa = fma(T(-2) * A.Ka * mu * s2, r.E1 + r.E2, c3 * mu2 * fma(T(3), r.h, r.H1));
     return J;
+}
+
+template <class T>
+__device__ __forceinline__ Jac<T> jac_classical(T mu, const StageAmp<T> &A) {
+    Jac<T> J;
+    const T u = A.Ka * A.a;
+    J.fm = -u * mu * mu;
+    J.mm = T(-2) * u * mu;
+    J.ma = T(-2) * A.Ka * mu * mu;
+    J.fs = J.ms = J.sm = J.ss = J.sa = T(0);
+    return J;
+}
+
+// 2x2 matrices [[a, b], [c, d]] and 2-vectors acting on (mu, sig2); in the
+// classical model only the mu entries are used.
+template <class T>
+struct Mat2 {
+    T a, b, c, d;
+};
+template <class T>
+struct Vec2 {
+    T x, y;
+};
+
+// K (I + s M) = K + s K M
+template <class T, bool Q>
+__device__ __forceinline__ Mat2<T> kism(const Jac<T> &K, T s, const Mat2<T> &M) {
+    Mat2<T> R;
+    if (Q) {
+        R.a = fma(s, fma(K.mm, M.a, K.ms * M.c), K.mm);
+        R.b = fma(s, fma(K.mm, M.b, K.ms * M.d), K.ms);
+        R.c = fma(s, fma(K.sm, M.a, K.ss * M.c), K.sm);
+        R.d = fma(s, fma(K.sm, M.b, K.ss * M.d), K.ss);
+    } else {
+        R.a = fma(s, K.mm * M.a, K.mm);
+        R.b = R.c = R.d = T(0);
+    }
+    return R;
+}
+
+// s K v
+template <class T, bool Q>
+__device__ __forceinline__ Vec2<T> skv(const Jac<T> &K, T s, const Vec2<T> &v) {
+    Vec2<T> r;
+    if (Q) {
+        r.x = s * fma(K.mm, v.x, K.ms * v.y);
+        r.y = s * fma(K.sm, v.x, K.ss * v.y);
+    } else {
+        r.x = s * K.mm * v.x;
+        r.y = T(0);
+    }
+    return r;
+}
+
+// One RK4 step of (mu, sig2), linearised.  The tangent of any direction obeys
+//   dk1 = K1 V + g1 d1,            dk2 = K2 (V + h/2 dk1) + g2 dh,
+//   dk3 = K3 (V + h/2 dk2) + g3 dh, dk4 = K4 (V + h dk3) + g4 d4,
+//   V' = V + h/6 (dk1 + 2 dk2 + 2 dk3 + dk4),
+// with K_s = d f / d(mu, sig2) and g_s = d f / d a at stage s, and d1, dh, d4
+// the direction's amplitude derivatives at psi_j, psi_j + h/2, psi_j + h.
+// That map is linear, V' = A V + P1 d1 + Ph dh + P4 d4, and A, P1, Ph, P4 are
+// shared by all directions, so they are formed once per step.
+template <class T, bool Q>
+struct StepLin {
+    Mat2<T> A;
+    Vec2<T> P1, Ph, P4;
+    T dmu, ds2;  // the state increment
+};
+
+template <class T, bool Q>
+__device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T> &A1,
+                                                    const StageAmp<T> &Ah, const StageAmp<T> &A4,
+                                                    T h, RadSrc<T> &rad, T &chi_hi) {
+    const T hh = T(0.5) * h, h6 = h * T(1.0 / 6.0);
+    StepLin<T, Q> L;
+    // stage 1
+    Jac<T> K1;
+    if (Q) {
+        const T chi = A1.chi_per_mu * mu;
+        chi_hi = fmax(chi_hi, chi);
+        K1 = jac_quantum(mu, s2, A1, rad.s1(chi));
+    } else {
+        K1 = jac_classical(mu, A1);
+    }
+    const Vec2<T> g1{K1.ma, K1.sa};
+    // stage 2
+    const T m2 = fma(hh, K1.fm, mu), s22 = fma(hh, K1.fs, s2);
+    Jac<T> K2;
+    if (Q) {
+        const T chi = Ah.chi_per_mu * m2;
+        chi_hi = fmax(chi_hi, chi);
+        K2 = jac_quantum(m2, s22, Ah, rad.s2(chi));
+    } else {
+        K2 = jac_classical(m2, Ah);
+    }
+    const Mat2<T> M1{K1.mm, K1.ms, K1.sm, K1.ss};
+    const Mat2<T> M2 = kism<T, Q>(K2, hh, M1);
+    const Vec2<T> e21 = skv<T, Q>(K2, hh, g1);
+    const Vec2<T> g2{K2.ma, K2.sa};
+    // stage 3
+    const T m3 = fma(hh, K2.fm, mu), s23 = fma(hh, K2.fs, s2);
+    Jac<T> K3;
+    if (Q) {
+        const T chi = Ah.chi_per_mu * m3;
+        chi_hi = fmax(chi_hi, chi);
+        K3 = jac_quantum(m3, s23, Ah, rad.s3(chi));
+    } else {
+        K3 = jac_classical(m3, Ah);
+    }
+    const Mat2<T> M3 = kism<T, Q>(K3, hh, M2);
+    const Vec2<T> e31 = skv<T, Q>(K3, hh, e21);
+    Vec2<T> e3h = skv<T, Q>(K3, hh, g2);
+    e3h.x += K3.ma;
+    e3h.y += K3.sa;
+    // stage 4
+    const T m4 = fma(h, K3.fm, mu), s24 = fma(h, K3.fs, s2);
+    Jac<T> K4;
+    if (Q) {
+        const T chi = A4.chi_per_mu * m4;
+        chi_hi = fmax(chi_hi, chi);
+        K4 = jac_quantum(m4, s24, A4, rad.s4(chi));
+    } else {
+        K4 = jac_classical(m4, A4);
+    }
+    const Mat2<T> M4 = kism<T, Q>(K4, h, M3);
+    const Vec2<T> e41 = skv<T, Q>(K4, h, e31);
+    const Vec2<T> e4h = skv<T, Q>(K4, h, e3h);
+    // assemble
+    L.A.a = fma(h6, M1.a + T(2) * (M2.a + M3.a) + M4.a, T(1));
+    L.A.b = h6 * (M1.b + T(2) * (M2.b + M3.b) + M4.b);
+    L.A.c = h6 * (M1.c + T(2) * (M2.c + M3.c) + M4.c);
+    L.A.d = fma(h6, M1.d + T(2) * (M2.d + M3.d) + M4.d, T(1));
+    L.P1.x = h6 * (g1.x + T(2) * (e21.x + e31.x) + e41.x);
+    L.P1.y = h6 * (g1.y + T(2) * (e21.y + e31.y) + e41.y);
+    L.Ph.x = h6 * (T(2) * (g2.x + e3h.x) + e4h.x);
+    L.Ph.y = h6 * (T(2) * (g2.y + e3h.y) + e4h.y);
+    L.P4.x = h6 * K4.ma;
+    L.P4.y = h6 * K4.sa;
+    L.dmu = h6 * (K1.fm + T(2) * (K2.fm + K3.fm) + K4.fm);
+    L.ds2 = h6 * (K1.fs + T(2) * (K2.fs + K3.fs) + K4.fs);
+    return L;
 }
 
 // Spatial factor of eq. a0eff and its logarithmic derivatives with respect to
@@ -1254,82 +1457,6 @@ struct AdjPath {
         da[6] = a * (hz + ell) * fma(dthx, d.Lx, dthy * d.Ly);
     }
 };
-
-// One RK4 step of the state and of its tangents (vm, vs: d mu / d dir,
-// d sig2 / d dir).  da1, dah, da4: amplitude derivatives at the three phases.
-template <class T, int ND, bool QUANTUM>
-__device__ __forceinline__ void rk4_tangent(T mu, T s2, T a1, T ah, T a4, const T *da1,
-                                            const T *dah, const T *da4, T h, const Phys<T> &ph,
-                                            const T *tab, T *vm, T *vs, T &dmu, T &ds2,
-                                            T &chi_hi) {
-    const T hh = T(0.5) * h;
-    T am[ND], as[ND], wm[ND], ws[ND];
-    // stage 1
-    Jac<T> J = rhs_jac<T, QUANTUM>(mu, s2, a1, ph, tab, chi_hi);
-    const T k1m = J.fm, k1s = J.fs;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        T km = fma(J.mm, vm[d], J.ma * da1[d]);
-        T ks = T(0);
-        if (QUANTUM) {
-            km = fma(J.ms, vs[d], km);
-            ks = fma(J.sm, vm[d], fma(J.ss, vs[d], J.sa * da1[d]));
-        }
-        am[d] = km;
-        as[d] = ks;
-        wm[d] = fma(hh, km, vm[d]);
-        ws[d] = fma(hh, ks, vs[d]);
-    }
-    // stage 2
-    J = rhs_jac<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, chi_hi);
-    const T k2m = J.fm, k2s = J.fs;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        T km = fma(J.mm, wm[d], J.ma * dah[d]);
-        T ks = T(0);
-        if (QUANTUM) {
-            km = fma(J.ms, ws[d], km);
-            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * dah[d]));
-        }
-        am[d] = fma(T(2), km, am[d]);
-        as[d] = fma(T(2), ks, as[d]);
-        wm[d] = fma(hh, km, vm[d]);
-        ws[d] = fma(hh, ks, vs[d]);
-    }
-    // stage 3
-    J = rhs_jac<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, chi_hi);
-    const T k3m = J.fm, k3s = J.fs;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        T km = fma(J.mm, wm[d], J.ma * dah[d]);
-        T ks = T(0);
-        if (QUANTUM) {
-            km = fma(J.ms, ws[d], km);
-            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * dah[d]));
-        }
-        am[d] = fma(T(2), km, am[d]);
-        as[d] = fma(T(2), ks, as[d]);
-        wm[d] = fma(h, km, vm[d]);
-        ws[d] = fma(h, ks, vs[d]);
-    }
-    // stage 4
-    J = rhs_jac<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, chi_hi);
-    const T k4m = J.fm, k4s = J.fs;
-    const T h6 = h * T(1.0 / 6.0);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        T km = fma(J.mm, wm[d], J.ma * da4[d]);
-        T ks = T(0);
-        if (QUANTUM) {
-            km = fma(J.ms, ws[d], km);
-            ks = fma(J.sm, wm[d], fma(J.ss, ws[d], J.sa * da4[d]));
-        }
-        vm[d] = fma(h6, am[d] + km, vm[d]);
-        if (QUANTUM) vs[d] = fma(h6, as[d] + ks, vs[d]);
-    }
-    dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
-    ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
-}
 
 // Sensitivities of one sample's share of L = sum_k w_k H_k to the centre v
 // and the variance sig2 of its energy law.  Writing F for the law's CDF and
@@ -1416,11 +1543,11 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
     constexpr int ND = LOCAL ? kDirLocal : kDirA0eff;
     constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
     const int N = P.n_steps;
-    const T *tab;
+    RadSrc<T> rad;
     if constexpr (PREC == PREC_F64)
-        tab = P.rad64d;
+        rad.tab = P.rad64d;
     else
-        tab = tab32;
+        rad.tab = tab32;
     const T *env;
     if constexpr (PREC == PREC_F64)
         env = env64;
@@ -1477,6 +1604,7 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
         g0_rest = (g0 - (double)mu) - (double)mu_lo;
     }
     T chi_hi = T(0);
+    constexpr int GD = LOCAL ? 5 : 1;  // the gamma0 direction: no amplitude forcing
     T a1, da1[ND];
     if (LOCAL) {
         pth.amp(psi0 * ell_per_psi, env[0], a1, da1);
@@ -1486,6 +1614,8 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
         da1[0] = Sf;
         da1[1] = T(0);
     }
+    StageAmp<T> A1(a1, ph);
+    if (QUANTUM) rad.init(A1.chi_per_mu * mu);
     for (int j = 0; j < N; ++j) {
         const T psi = fma((T)j, h, psi0);
         T ah, a4, dah[ND], da4[ND];
@@ -1500,17 +1630,32 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
             da4[0] = S4;
             dah[1] = da4[1] = T(0);
         }
-        T dm, ds;
-        rk4_tangent<T, ND, QUANTUM>(mu, s2, a1, ah, a4, da1, dah, da4, h, ph, tab, vm, vs, dm, ds,
-                                    chi_hi);
-        if constexpr (PREC == PREC_F64) {
-            mu += dm;
-            s2 += ds;
-        } else {
-            comp_add(mu, mu_lo, dm);
-            comp_add(s2, s2_lo, ds);
+        const StageAmp<T> Ah(ah, ph), A4(a4, ph);
+        const StepLin<T, QUANTUM> L = rk4_linear<T, QUANTUM>(mu, s2, A1, Ah, A4, h, rad, chi_hi);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            T fm = T(0), fs = T(0);
+            if (d != GD) {
+                fm = fma(L.P1.x, da1[d], fma(L.Ph.x, dah[d], L.P4.x * da4[d]));
+                fs = fma(L.P1.y, da1[d], fma(L.Ph.y, dah[d], L.P4.y * da4[d]));
+            }
+            const T m0 = vm[d];
+            if (QUANTUM) {
+                const T s0 = vs[d];
+                vm[d] = fma(L.A.a, m0, fma(L.A.b, s0, fm));
+                vs[d] = fma(L.A.c, m0, fma(L.A.d, s0, fs));
+            } else {
+                vm[d] = fma(L.A.a, m0, fm);
+            }
         }
-        a1 = a4;
+        if constexpr (PREC == PREC_F64) {
+            mu += L.dmu;
+            s2 += L.ds2;
+        } else {
+            comp_add(mu, mu_lo, L.dmu);
+            comp_add(s2, s2_lo, L.ds2);
+        }
+        A1 = A4;
 #pragma unroll
         for (int d = 0; d < ND; ++d) da1[d] = da4[d];
     }
@@ -1630,11 +1775,20 @@ __global__ void rad_derivs_kernel(const float *rad32d, const double *rad64d, int
     const int fl = (chi[k] < (double)(1 << (kEMax + 1))) ? 0 : kFlagRange;
     double v[kDerivFuncs];
     if (prec == 0) {
-        const Rad6<float> r = rad6_eval32(rad32d, (float)chi[k]);
-        v[0] = r.g; v[1] = r.G1; v[2] = r.G2; v[3] = r.h; v[4] = r.G3; v[5] = r.H1;
+        // the FP32 table holds combinations: undo them
+        RadCell6 cell;
+        rad6_lookup32(rad32d, (float)chi[k], cell);
+        const RadJ<float> r = rad6_cell_eval(cell, (float)chi[k]);
+        const double g = r.g, G1 = (double)r.E1 - 2.0 * g;
+        const double G2 = (double)r.E2 - 2.0 * g - 4.0 * G1;
+        v[0] = g;
+        v[1] = G1;
+        v[2] = G2;
+        v[3] = r.h;
+        v[4] = (double)r.E3 - 6.0 * (G1 + G2);
+        v[5] = r.H1;
     } else {
-        const Rad6<double> r = rad6_eval64(rad64d, chi[k]);
-        v[0] = r.g; v[1] = r.G1; v[2] = r.G2; v[3] = r.h; v[4] = r.G3; v[5] = r.H1;
+        rad6_plain64(rad64d, chi[k], v);
     }
     for (int f = 0; f < kDerivFuncs; ++f) out[kDerivFuncs * k + f] = v[f];
     if (fl) atomicOr(flags, fl);

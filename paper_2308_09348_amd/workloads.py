@@ -55,6 +55,21 @@ def differentiation():
     return p
 
 
+GRAD_PARAMS = ("a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
+               "div_mrad")
+
+
+def differentiation_eval(seed=40):
+    """The point where the differentiation workload's loss is evaluated: each
+    of the eight differentiable parameters of differentiation() scaled by
+    (1 + 0.05 eps), eps ~ N(0, 1) drawn by PCG64(seed)."""
+    p = differentiation()
+    eps = np.random.Generator(np.random.PCG64(seed)).normal(size=len(GRAD_PARAMS))
+    for name, e in zip(GRAD_PARAMS, eps):
+        p[name] = float(p[name] * (1.0 + 0.05 * e))
+    return p
+
+
 def batched_shots(n_shots=4096, seed=3):
     """Per-shot parameter draws for the batched workload: samples log-uniform
     in [2^12, 2^18], a0 ~ U[5, 100], w0 ~ U[2, 6] um, offsets ~ N(0, 2^2) um,
