@@ -104,8 +104,10 @@ def cpu_baseline(params, target_s):
 def adjoint_leg(ctx, qs, workloads, torch, steps):
     """Forward + adjoint on the differentiation workload: a Neyman chi^2 loss
     against a Poisson target drawn from the histogram at the reference
-    parameters, evaluated at perturbed parameters; one step = forward, loss,
-    upstream weights, adjoint (all on the device)."""
+    parameters, evaluated at perturbed parameters.  One step = forward pass
+    recording the derivative tape, loss, upstream weights, adjoint from the
+    tape (all on the device).  The parts are also timed alone, with the
+    adjoint that integrates the trajectories again instead of reading a tape."""
     ref = workloads.differentiation()
     p = workloads.differentiation_eval()
     n, N = p["n_samples"], p["n_steps"]
@@ -114,45 +116,47 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
     rng = np.random.Generator(np.random.PCG64(4))
     target = torch.tensor(rng.poisson(n_tot * h_ref / n).astype(np.float64), device="cuda")
     denom = torch.clamp(target, min=1.0)
+    tape = ctx.new_tape(n)
+    out = ctx.forward(p, tape=tape)
 
     def step():
-        h = ctx.forward(p, check=False)["energy_hist"]
+        h = ctx.forward(p, out=out, tape=tape, check=False)["energy_hist"]
         r = n_tot * h / n - target
         loss = (r * r / denom).sum()
         w = 2.0 * r / denom * (n_tot / n)
-        g = ctx.backward(p, w, check=False)
-        return loss, g
+        g = ctx.backward(p, w, tape=tape, check=False)
+        return loss, g, w
 
-    loss, g = step()  # warm-up and scratch allocation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        loss, g = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    # the two halves on their own
-    out = ctx.forward(p)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.forward(p, out=out, check=False)
-    torch.cuda.synchronize()
-    t_fwd = (time.perf_counter() - t0) / steps
-    w = torch.ones(p["n_e"] + 2, dtype=torch.float64, device="cuda")
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.backward(p, w, check=False)
-    torch.cuda.synchronize()
-    t_bwd = (time.perf_counter() - t0) / steps
-    g = g.cpu().numpy()
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    res = {}
+    dt = timed(lambda: res.update(zip(("loss", "g", "w"), step())))
+    if int(out["status"].item()) != 0:
+        raise RuntimeError("device status in the adjoint leg")
+    w = res["w"]
+    t_fwd = timed(lambda: ctx.forward(p, out=out, check=False))
+    t_tape = timed(lambda: ctx.forward(p, out=out, tape=tape, check=False))
+    t_contract = timed(lambda: ctx.backward(p, w, tape=tape, check=False))
+    t_recompute = timed(lambda: ctx.backward(p, w, check=False))
+    g = res["g"].cpu().numpy()
     if not np.all(np.isfinite(g)):
         raise RuntimeError("non-finite gradient in the adjoint leg")
     return {"workload": "differentiation: focused-shot physics, GAUSS deposit (1 bin), 2^20 "
                         "samples x 1024 steps, quantum, local amplitude; Neyman chi^2 loss vs a "
                         "Poisson target (1e6 counts) at parameters perturbed by 5%",
             "n_samples": n, "n_steps": N, "steps": steps, "ms_per_step": 1e3 * dt,
-            "fwd_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_bwd,
+            "fwd_ms": 1e3 * t_fwd, "fwd_tape_ms": 1e3 * t_tape,
+            "adjoint_from_tape_ms": 1e3 * t_contract,
+            "adjoint_recompute_ms": 1e3 * t_recompute,
             "step_over_fwd": dt / t_fwd,
-            "sample_steps_per_s": n * N / dt, "loss": float(loss),
+            "sample_steps_per_s": n * N / dt, "loss": float(res["loss"]),
             "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
 

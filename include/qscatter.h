@@ -250,6 +250,48 @@ qs_status qs_backward_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lase
                               const qs_numerics *num, const qs_bins *bins,
                               const qs_grad_outputs *outs, void *stream);
 
+/* Fields of a derivative tape (doubles, structure of arrays): field f of
+ * sample i of shot k is at tape[f * n_total + off_k + i], with n_total the
+ * samples of the whole call and off_k those of the shots before k.
+ * Fields: QS_T_MU final mean energy mu_f, QS_T_SIG2 final variance sig2_f,
+ * QS_T_DMU + p = d mu_f / d p, QS_T_DSIG2 + p = d sig2_f / d p (p a QS_P_*). */
+enum { QS_T_MU = 0, QS_T_SIG2 = 1, QS_T_DMU = 2, QS_T_DSIG2 = 2 + QS_P_N,
+       QS_TAPE_FIELDS = 2 + 2 * QS_P_N };
+
+/* qs_forward that also records the derivative tape (device, caller-allocated,
+ * QS_TAPE_FIELDS * n_samples doubles, overwritten): each sample's trajectory
+ * is integrated together with its tangents (as qs_backward does), its final
+ * state goes to the deposit as in qs_forward, and mu_f, sig2_f and their
+ * derivatives go to the tape.  The histograms and moments agree with
+ * qs_forward's to the parity tolerances (not bit for bit: the FP32 step
+ * arithmetic differs), and qs_backward_tape on the tape then costs one read
+ * of it instead of a second integration.  Errors: as qs_forward; QS_EINVAL
+ * for a NULL tape. */
+qs_status qs_forward_tape(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                          const qs_numerics *num, const qs_bins *bins, const qs_outputs *out,
+                          double *tape, void *stream);
+
+/* qs_forward_batched with a tape over all shots (n_total = sum of n_samples). */
+qs_status qs_forward_tape_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                                  const qs_beam *beams, const int64_t *n_samples,
+                                  const qs_numerics *num, const qs_bins *bins,
+                                  const qs_outputs *outs, double *tape, void *stream);
+
+/* qs_backward from a tape recorded by qs_forward_tape with the same
+ * arguments: dL/dp = sum_i (dL/dmu_i d mu_i/dp + dL/dsig2_i d sig2_i/dp) with
+ * the law sensitivities of qs_backward (read-only tape).  Errors: as
+ * qs_backward; QS_EINVAL for a NULL tape. */
+qs_status qs_backward_tape(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                           const qs_numerics *num, const qs_bins *bins,
+                           const qs_grad_outputs *out, const double *tape, void *stream);
+
+/* qs_backward_batched from a batched tape. */
+qs_status qs_backward_tape_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                                   const qs_beam *beams, const int64_t *n_samples,
+                                   const qs_numerics *num, const qs_bins *bins,
+                                   const qs_grad_outputs *outs, const double *tape,
+                                   void *stream);
+
 /* Evaluate the derivative tables that the adjoint uses at n values of chi
  * (device arrays): out[6*k + {0..5}] = {g, chi g', chi^2 g'', h, chi^3 g''',
  * chi h'} at chi[k], FP32 or FP64 (Sec. 4 eq. dpdtRR; diagnostic entry point).

@@ -54,13 +54,22 @@ class Context:
     def last_error(self):
         return _lib.lib().qs_last_error(self._ptr).decode()
 
+    def new_tape(self, n_samples):
+        """A device tensor for a derivative tape of n_samples samples:
+        [TAPE_FIELDS, n_samples] float64 (fields T_MU, T_SIG2, T_DMU + p,
+        T_DSIG2 + p)."""
+        torch = _torch()
+        return torch.empty((_lib.TAPE_FIELDS, int(n_samples)), dtype=torch.float64,
+                           device=torch.device("cuda", self.device))
+
     def forward(self, params, sample_stride=0, n_sample_records=0, stream=None, out=None,
-                check=True):
+                check=True, tape=None):
         """Enqueue one forward pass; returns a dict of device tensors.
 
         ``out`` may hold preallocated tensors (same keys as the result) to
         avoid allocation.  With ``check`` the stream is synchronised and the
-        device status word raised as an error."""
+        device status word raised as an error.  With ``tape`` (from new_tape)
+        the pass also records the per-sample parameter derivatives there."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         la, be, nu, bi = _lib.structs(params)
@@ -83,9 +92,16 @@ class Context:
             sample_stride=max(int(sample_stride), 1), n_sample_records=int(n_sample_records))
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        st = _lib.lib().qs_forward(self._ptr, ctypes.byref(la), ctypes.byref(be),
-                                   ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(o),
-                                   ctypes.c_void_p(stream.cuda_stream))
+        if tape is not None:
+            _check_tape(tape, params["n_samples"])
+            st = _lib.lib().qs_forward_tape(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                            ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(o),
+                                            ctypes.c_void_p(tape.data_ptr()),
+                                            ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_forward(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                       ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(o),
+                                       ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         if check:
@@ -131,15 +147,24 @@ class Context:
                 n_sample_records=0)
         return b
 
-    def run_batch(self, batch, stream=None, check=True):
-        """Enqueue one launch over a prepared batch; returns its outputs."""
+    def run_batch(self, batch, stream=None, check=True, tape=None):
+        """Enqueue one launch over a prepared batch; returns its outputs.  With
+        ``tape`` ([TAPE_FIELDS, total samples]) the launch records the
+        per-sample parameter derivatives of every shot."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        st = _lib.lib().qs_forward_batched(self._ptr, batch.n, batch.lasers, batch.beams,
-                                           batch.ns, ctypes.byref(batch.nu), batch.bins,
-                                           batch.outs, ctypes.c_void_p(stream.cuda_stream))
+        if tape is not None:
+            _check_tape(tape, sum(batch.ns))
+            st = _lib.lib().qs_forward_tape_batched(
+                self._ptr, batch.n, batch.lasers, batch.beams, batch.ns, ctypes.byref(batch.nu),
+                batch.bins, batch.outs, ctypes.c_void_p(tape.data_ptr()),
+                ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_forward_batched(self._ptr, batch.n, batch.lasers, batch.beams,
+                                               batch.ns, ctypes.byref(batch.nu), batch.bins,
+                                               batch.outs, ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         if check:
@@ -149,15 +174,17 @@ class Context:
                 raise QScatterError(bad, "device status of a shot")
         return batch.out
 
-    def forward_batched(self, shots, stream=None, check=True):
+    def forward_batched(self, shots, stream=None, check=True, tape=None):
         """One launch over a list of per-shot parameter dictionaries; returns a
         list of per-shot result dictionaries (device tensors)."""
-        return self.run_batch(self.prepare_batch(shots), stream=stream, check=check)
+        return self.run_batch(self.prepare_batch(shots), stream=stream, check=check, tape=tape)
 
-    def backward(self, params, d_energy, stream=None, check=True):
+    def backward(self, params, d_energy, stream=None, check=True, tape=None):
         """Derivatives of L = sum_k d_energy[k] H_k (H: the energy histogram of
         forward(params), n_e + 2 entries) with respect to PARAM_NAMES; returns
-        a float64 device tensor of 8."""
+        a float64 device tensor of 8.  With ``tape`` (recorded by
+        forward(params, tape=...)) the derivatives are read from it instead of
+        integrating the trajectories again."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         la, be, nu, bi = _lib.structs(params)
@@ -172,9 +199,16 @@ class Context:
         status = torch.empty(1, dtype=torch.int32, device=dev)
         g = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grad.data_ptr(),
                              status=status.data_ptr())
-        st = _lib.lib().qs_backward(self._ptr, ctypes.byref(la), ctypes.byref(be),
-                                    ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(g),
-                                    ctypes.c_void_p(stream.cuda_stream))
+        if tape is not None:
+            _check_tape(tape, params["n_samples"])
+            st = _lib.lib().qs_backward_tape(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                             ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(g),
+                                             ctypes.c_void_p(tape.data_ptr()),
+                                             ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_backward(self._ptr, ctypes.byref(la), ctypes.byref(be),
+                                        ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(g),
+                                        ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         if check:
@@ -184,9 +218,10 @@ class Context:
                 raise QScatterError(st, "device status")
         return grad
 
-    def backward_batched(self, shots, d_energy, stream=None, check=True):
+    def backward_batched(self, shots, d_energy, stream=None, check=True, tape=None):
         """Adjoint of forward_batched(shots): d_energy is a list of per-shot
-        upstream weights (n_e + 2 each); returns a list of gradient tensors."""
+        upstream weights (n_e + 2 each); returns a list of gradient tensors.
+        ``tape``: as recorded by forward_batched(shots, tape=...)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = len(shots)
@@ -210,8 +245,16 @@ class Context:
             grads.append(torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev))
             outs[k] = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grads[k].data_ptr(),
                                        status=status[k:].data_ptr())
-        st = _lib.lib().qs_backward_batched(self._ptr, n, lasers, beams, ns, ctypes.byref(nu),
-                                            bins, outs, ctypes.c_void_p(stream.cuda_stream))
+        if tape is not None:
+            _check_tape(tape, sum(ns))
+            st = _lib.lib().qs_backward_tape_batched(self._ptr, n, lasers, beams, ns,
+                                                     ctypes.byref(nu), bins, outs,
+                                                     ctypes.c_void_p(tape.data_ptr()),
+                                                     ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_backward_batched(self._ptr, n, lasers, beams, ns,
+                                                ctypes.byref(nu), bins, outs,
+                                                ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         for d, src in zip(keep, d_energy):
@@ -274,6 +317,14 @@ class _Batch:
     """Marshalled arguments and output tensors of a batched launch."""
 
 
+def _check_tape(tape, n_samples):
+    import torch
+    if (tape.dtype != torch.float64 or not tape.is_cuda or not tape.is_contiguous()
+            or tape.numel() != _lib.TAPE_FIELDS * int(n_samples)):
+        raise ValueError("tape must be a contiguous float64 device tensor of "
+                         "TAPE_FIELDS x n_samples")
+
+
 _default = {}
 
 
@@ -304,19 +355,20 @@ def _energy_hist_fn():
 
     class EnergyHistogram(torch.autograd.Function):
         """H(theta): the energy histogram (n_e + 2 raw weights) of one shot as a
-        function of theta = the PARAM_NAMES values; the backward runs the
-        device adjoint."""
+        function of theta = the PARAM_NAMES values.  The forward records the
+        derivative tape; the backward contracts it with dL/dH on the device."""
 
         @staticmethod
         def forward(fctx, theta, qctx, params):
             p = _with_theta(params, theta)
-            fctx.qctx, fctx.p = qctx, p
+            tape = qctx.new_tape(p["n_samples"])
+            fctx.qctx, fctx.p, fctx.tape = qctx, p, tape
             fctx.theta_meta = (theta.dtype, theta.device)
-            return qctx.forward(p)["energy_hist"]
+            return qctx.forward(p, tape=tape)["energy_hist"]
 
         @staticmethod
         def backward(fctx, grad_h):
-            g = fctx.qctx.backward(fctx.p, grad_h)
+            g = fctx.qctx.backward(fctx.p, grad_h, tape=fctx.tape)
             dtype, device = fctx.theta_meta
             return g.to(device=device, dtype=dtype), None, None
 

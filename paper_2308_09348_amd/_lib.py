@@ -71,8 +71,13 @@ class GradOutputs(ctypes.Structure):
 PARAM_NAMES = ("a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
                "div_mrad")
 
+TAPE_FIELDS = 2 + 2 * len(PARAM_NAMES)  # mu, sig2, d mu / dp, d sig2 / dp
+T_MU, T_SIG2, T_DMU, T_DSIG2 = 0, 1, 2, 2 + len(PARAM_NAMES)
+
 EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_backward",
-           "qs_backward_batched", "qs_radiation_eval", "qs_radiation_derivs", "qs_sync_status",
+           "qs_backward_batched", "qs_forward_tape", "qs_forward_tape_batched",
+           "qs_backward_tape", "qs_backward_tape_batched", "qs_radiation_eval",
+           "qs_radiation_derivs", "qs_sync_status",
            "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
            "qs_abi_version"]
 
@@ -117,6 +122,14 @@ def lib():
                                           ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                           ctypes.POINTER(GradOutputs), vp]
         L.qs_backward_batched.restype = ctypes.c_int
+        L.qs_forward_tape.argtypes = L.qs_forward.argtypes[:6] + [vp, vp]
+        L.qs_forward_tape.restype = ctypes.c_int
+        L.qs_forward_tape_batched.argtypes = L.qs_forward_batched.argtypes[:8] + [vp, vp]
+        L.qs_forward_tape_batched.restype = ctypes.c_int
+        L.qs_backward_tape.argtypes = L.qs_backward.argtypes[:6] + [vp, vp]
+        L.qs_backward_tape.restype = ctypes.c_int
+        L.qs_backward_tape_batched.argtypes = L.qs_backward_batched.argtypes[:8] + [vp, vp]
+        L.qs_backward_tape_batched.restype = ctypes.c_int
         L.qs_radiation_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.qs_radiation_eval.restype = ctypes.c_int
         L.qs_radiation_derivs.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]

@@ -174,10 +174,10 @@ qs_status grow_pinned(qs_ctx *c, size_t n) {
 
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                       const qs_outputs *O, hipStream_t s);
+                       const qs_outputs *O, double *tape, hipStream_t s);
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        const qs_grad_outputs *O, hipStream_t s);
+                        const qs_grad_outputs *O, const double *tape, hipStream_t s);
 
 }  // namespace
 
@@ -267,7 +267,7 @@ qs_status qs_forward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_nu
     if (!c) return QS_EINVAL;
     if (!N) return set_err(c, "null argument"), QS_EINVAL;
     const int64_t n = N->n_samples;
-    return forward_impl(c, 1, L, B, &n, N, H, O, reinterpret_cast<hipStream_t>(stream));
+    return forward_impl(c, 1, L, B, &n, N, H, O, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 
 qs_status qs_forward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
@@ -277,7 +277,7 @@ qs_status qs_forward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
     if (!c) return QS_EINVAL;
     if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs)
         return set_err(c, "invalid batch arguments"), QS_EINVAL;
-    return forward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs,
+    return forward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, nullptr,
                         reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -299,7 +299,7 @@ qs_status qs_backward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_n
     if (!c) return QS_EINVAL;
     if (!N) return set_err(c, "null argument"), QS_EINVAL;
     const int64_t n = N->n_samples;
-    return backward_impl(c, 1, L, B, &n, N, H, O, reinterpret_cast<hipStream_t>(stream));
+    return backward_impl(c, 1, L, B, &n, N, H, O, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 
 qs_status qs_backward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
@@ -309,7 +309,49 @@ qs_status qs_backward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers
     if (!c) return QS_EINVAL;
     if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs)
         return set_err(c, "invalid batch arguments"), QS_EINVAL;
-    return backward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs,
+    return backward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, nullptr,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_forward_tape(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
+                          const qs_bins *H, const qs_outputs *O, double *tape, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N || !tape) return set_err(c, "null argument"), QS_EINVAL;
+    const int64_t n = N->n_samples;
+    return forward_impl(c, 1, L, B, &n, N, H, O, tape, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_forward_tape_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                                  const qs_beam *beams, const int64_t *n_samples,
+                                  const qs_numerics *num, const qs_bins *bins,
+                                  const qs_outputs *outs, double *tape, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs ||
+        !tape)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return forward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, tape,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_backward_tape(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
+                           const qs_bins *H, const qs_grad_outputs *O, const double *tape,
+                           void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N || !tape) return set_err(c, "null argument"), QS_EINVAL;
+    const int64_t n = N->n_samples;
+    return backward_impl(c, 1, L, B, &n, N, H, O, tape, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_backward_tape_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                                   const qs_beam *beams, const int64_t *n_samples,
+                                   const qs_numerics *num, const qs_bins *bins,
+                                   const qs_grad_outputs *outs, const double *tape,
+                                   void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs ||
+        !tape)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return backward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, tape,
                          reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -518,7 +560,7 @@ qs_status upload_batch(qs_ctx *c, const Batch &b, hipStream_t s) {
 
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                       const qs_outputs *O, hipStream_t s) {
+                       const qs_outputs *O, double *tape, hipStream_t s) {
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
@@ -575,6 +617,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     bp.flags = reinterpret_cast<int *>(c->accum + 1);
     bp.hist = c->accum + 1 + flag_words;
     bp.partials = c->partials;
+    bp.tape = tape;
+    bp.tape_n = b.total;
 
     // ---- enqueue ----
     hipError_t e;
@@ -589,9 +633,15 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
         return hip_fail(c, e, "zero kernel");
     if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
-    if ((e = qs::launch_phase(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, s)) !=
-        hipSuccess)
+    if (tape) {
+        // the forward pass that also records the parameter derivatives
+        if ((e = qs::launch_tangent(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, true,
+                                    s)) != hipSuccess)
+            return hip_fail(c, e, "tangent kernel");
+    } else if ((e = qs::launch_phase(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode,
+                                     s)) != hipSuccess) {
         return hip_fail(c, e, "phase kernel");
+    }
     if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
     if ((e = qs::launch_deposit(bp, b.max_nh, s)) != hipSuccess)
         return hip_fail(c, e, "deposit kernel");
@@ -605,7 +655,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
 
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        const qs_grad_outputs *O, hipStream_t s) {
+                        const qs_grad_outputs *O, const double *tape, hipStream_t s) {
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
@@ -641,6 +691,8 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     bp.queue = reinterpret_cast<unsigned int *>(c->accum);
     bp.flags = reinterpret_cast<int *>(c->accum + 1);
     bp.partials = c->partials;
+    bp.tape = const_cast<double *>(tape);  // read only by the contraction kernel
+    bp.tape_n = b.total;
 
     hipError_t e;
     if ((st = upload_batch(c, b, s)) != QS_OK) return st;
@@ -649,9 +701,13 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         return hip_fail(c, e, "envelope kernel");
     if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
         return hip_fail(c, e, "zero kernel");
-    if ((e = qs::launch_adjoint(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, s)) !=
-        hipSuccess)
+    if (tape) {
+        if ((e = qs::launch_contract(bp, s)) != hipSuccess)
+            return hip_fail(c, e, "contraction kernel");
+    } else if ((e = qs::launch_tangent(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode,
+                                       false, s)) != hipSuccess) {
         return hip_fail(c, e, "adjoint kernel");
+    }
     if ((e = qs::launch_grad_finalize(bp, s)) != hipSuccess)
         return hip_fail(c, e, "gradient finalize kernel");
     c->last_error[0] = 0;

@@ -97,6 +97,7 @@ struct ShotGrad {
 };
 
 constexpr int kGradParams = 8;
+constexpr int kTapeFields = 2 + 2 * kGradParams;  // mu, sig2, d mu / dp, d sig2 / dp
 
 // Parameters shared by every shot of a launch.
 struct BatchParams {
@@ -114,6 +115,8 @@ struct BatchParams {
     const float *rad32d;  // [kCells32 * 4 * kDerivFuncs]
     const double *rad64d; // [kCells64 * 4 * kDerivFuncs]
     const ShotGrad *gouts;  // adjoint launches only
+    double *tape;           // derivative tape: [2 + 2 kGradParams][tape_n]
+    int64_t tape_n;         // samples over the batch (tape field stride)
     SampleState st;
     // accumulators (device scratch, cleared before each launch)
     unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
@@ -139,8 +142,9 @@ hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int pr
                                  const double *chi, double *out, int *flags, hipStream_t s);
 hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, int prec, int64_t n,
                                    const double *chi, double *out, int *flags, hipStream_t s);
-hipError_t launch_adjoint(const BatchParams &p, const float *env32, const double *env64, int prec,
-                          int rr, int amp, hipStream_t s);
+hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
+                          int rr, int amp, bool tape, hipStream_t s);
+hipError_t launch_contract(const BatchParams &p, hipStream_t s);
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s);
 
 }  // namespace qs

@@ -1532,15 +1532,26 @@ __device__ void law_sensitivity(double v, double s2, int dep, double ksig, doubl
     ls2 = ss * dse;
 }
 
-// One sample of the adjoint: returns its eight derivative terms in g.
+// Final state of one sample and its derivatives along the eight parameters
+// (order of the grad outputs: a0, W0, x offset, y offset, delay, gamma0,
+// sigma_gamma, divergence).
+struct SampleTangent {
+    double mu, s2;
+    double dmu[kGradParams], ds2[kGradParams];
+    double S0, g0, thx, thy;
+    float cmx;
+};
+
+// One sample: trajectory, tangents, and the chain to the eight parameters.
 template <int PREC, bool QUANTUM, bool LOCAL>
-__device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotParams &sp,
-                                               const ShotGrad &so, int64_t i,
-                                               const float *__restrict__ env32,
+__device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotParams &sp,
+                                               int64_t i, const float *__restrict__ env32,
                                                const double *__restrict__ env64,
-                                               const float *tab32, double *g, int &flags) {
+                                               const float *tab32, SampleTangent &o,
+                                               int &flags) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
     constexpr int ND = LOCAL ? kDirLocal : kDirA0eff;
+    constexpr int GD = LOCAL ? 5 : 1;  // the gamma0 direction: no amplitude forcing
     constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
     const int N = P.n_steps;
     RadSrc<T> rad;
@@ -1595,7 +1606,7 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
     T vm[ND], vs[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) vm[d] = vs[d] = T(0);
-    vm[LOCAL ? 5 : 1] = T(1);  // d mu_0 / d gamma0
+    vm[GD] = T(1);  // d mu_0 / d gamma0
 
     T mu = (T)g0, mu_lo = T(0), s2 = T(0), s2_lo = T(0);
     double g0_rest = 0.0;
@@ -1604,7 +1615,7 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
         g0_rest = (g0 - (double)mu) - (double)mu_lo;
     }
     T chi_hi = T(0);
-    constexpr int GD = LOCAL ? 5 : 1;  // the gamma0 direction: no amplitude forcing
+    float cmx = 0.0f;  // largest chi at a step start
     T a1, da1[ND];
     if (LOCAL) {
         pth.amp(psi0 * ell_per_psi, env[0], a1, da1);
@@ -1618,6 +1629,7 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
     if (QUANTUM) rad.init(A1.chi_per_mu * mu);
     for (int j = 0; j < N; ++j) {
         const T psi = fma((T)j, h, psi0);
+        cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));
         T ah, a4, dah[ND], da4[ND];
         if (LOCAL) {
             pth.amp(fma(T(0.5), h, psi) * ell_per_psi, env[2 * j + 1], ah, dah);
@@ -1659,45 +1671,75 @@ __device__ __forceinline__ void adjoint_sample(const BatchParams &P, const ShotP
 #pragma unroll
         for (int d = 0; d < ND; ++d) da1[d] = da4[d];
     }
-    const double mu_f = ((double)mu + (double)mu_lo) + g0_rest;
-    const double s2_f = (double)s2 + (double)s2_lo;
+    o.mu = ((double)mu + (double)mu_lo) + g0_rest;
+    o.s2 = (double)s2 + (double)s2_lo;
+    o.cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));  // the end of the last step
+    o.S0 = d0.S;
+    o.g0 = g0;
+    o.thx = thx;
+    o.thy = thy;
     if (QUANTUM && !((float)chi_hi < chi_top)) flags |= kFlagRange;
+    if (!(o.mu > 0.0) || !isfinite(o.mu) || !isfinite(o.s2)) flags |= kFlagNonFinite;
+
+    // ---- chain to the eight parameters ----
+    const double dthx_dd = 1e-3 * nrm[4], dthy_dd = 1e-3 * nrm[5];
 #pragma unroll
-    for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
-    if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
-        flags |= kFlagNonFinite;
-        return;
-    }
-    double lv, ls;
-    law_sensitivity(mu_f, s2_f, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e, so.d_energy, lv,
-                    ls);
-    double t[ND];
+    for (int c = 0; c < 2; ++c) {
+        const T *v = c == 0 ? vm : vs;
+        double *d = c == 0 ? o.dmu : o.ds2;
+        if (c == 1 && !QUANTUM) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) t[d] = fma(lv, (double)vm[d], QUANTUM ? ls * (double)vs[d] : 0.0);
-    if (LOCAL) {
-        g[0] = t[0];
-        g[1] = t[1];
-        g[2] = t[2];
-        g[3] = t[3];
-        g[4] = t[4];
-        g[5] = t[5];
-        g[6] = nrm[3] * t[5];
-        g[7] = t[6];
-    } else {
-        const double b = sp.a0 * t[0];
-        g[0] = t[0];
-        g[1] = b * d0.Lw;
-        g[2] = b * d0.Lx;
-        g[3] = b * d0.Ly;
-        g[4] = b * kHalfC * d0.Lz;
-        g[5] = t[1];
-        g[6] = nrm[3] * t[1];
-        g[7] = b * (0.5 * z) * fma(1e-3 * nrm[4], d0.Lx, 1e-3 * nrm[5] * d0.Ly);
+            for (int p = 0; p < kGradParams; ++p) d[p] = 0.0;
+            continue;
+        }
+        if (LOCAL) {
+            d[0] = v[0];
+            d[1] = v[1];
+            d[2] = v[2];
+            d[3] = v[3];
+            d[4] = v[4];
+            d[5] = v[5];
+            d[6] = nrm[3] * (double)v[5];
+            d[7] = v[6];
+        } else {
+            // every amplitude direction is a multiple of the a0 tangent
+            const double b = sp.a0 * (double)v[0];
+            d[0] = v[0];
+            d[1] = b * d0.Lw;
+            d[2] = b * d0.Lx;
+            d[3] = b * d0.Ly;
+            d[4] = b * kHalfC * d0.Lz;
+            d[5] = v[1];
+            d[6] = nrm[3] * (double)v[1];
+            d[7] = b * (0.5 * z) * fma(dthx_dd, d0.Lx, dthy_dd * d0.Ly);
+        }
     }
 }
 
-template <int PREC, bool QUANTUM, bool LOCAL>
-__global__ __launch_bounds__(kPhaseBlock) void adjoint_kernel(BatchParams P,
+// Fixed-order reduction of the block's eight sums into the item's partials.
+__device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t item,
+                                                 const double *g, double (*red)[kGradParams]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < kGradParams; ++p) {
+        const double v = wave_sum(g[p]);
+        if (lane == 0) red[wid][p] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGradParams) {
+        double sum = 0.0;
+        for (int w = 0; w < kPhaseBlock / 64; ++w) sum += red[w][threadIdx.x];
+        P.partials[(size_t)item * kGradParams + threadIdx.x] = sum;
+    }
+    // red is rewritten only after the next item's barriers
+}
+
+// TAPE = false: the adjoint -- each sample's derivatives contracted at once
+// with its law sensitivities, summed per item.  TAPE = true: the forward pass
+// that also records the derivatives: final states for the deposit kernel and
+// the tape (mu, sig2 and their eight derivatives, structure of arrays).
+template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
+__global__ __launch_bounds__(kPhaseBlock) void tangent_kernel(BatchParams P,
                                                               const float *__restrict__ env32,
                                                               const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
@@ -1710,7 +1752,6 @@ __global__ __launch_bounds__(kPhaseBlock) void adjoint_kernel(BatchParams P,
         for (int k = threadIdx.x; k < kCells32 * kDerivFuncs; k += blockDim.x) dst[k] = src[k];
         __syncthreads();
     }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
         if (item >= P.n_items) break;
@@ -1722,23 +1763,69 @@ __global__ __launch_bounds__(kPhaseBlock) void adjoint_kernel(BatchParams P,
         for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
         if (i < sp.n_samples) {
             int flags = 0;
-            adjoint_sample<PREC, QUANTUM, LOCAL>(P, sp, P.gouts[s], i, env32, env64, tab32, g,
-                                                 flags);
+            SampleTangent o;
+            tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, o, flags);
+            if (TAPE) {
+                const int64_t k = sp.state_off + i;
+                P.st.mu[k] = o.mu;
+                P.st.s2[k] = o.s2;
+                P.st.S0[k] = o.S0;
+                P.st.g0[k] = o.g0;
+                P.st.thx[k] = o.thx;
+                P.st.thy[k] = o.thy;
+                P.st.cmx[k] = o.cmx;
+                double *t = P.tape + k;
+                const int64_t n = P.tape_n;
+                t[0] = o.mu;
+                t[n] = o.s2;
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) {
+                    t[(2 + p) * n] = o.dmu[p];
+                    t[(2 + kGradParams + p) * n] = o.ds2[p];
+                }
+            } else if (!(flags & kFlagNonFinite)) {
+                double lv, ls;
+                law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                P.gouts[s].d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
+            }
             if (flags) atomicOr(&P.flags[s], flags);
         }
-        // fixed-order item reduction
+        if (!TAPE) grad_item_reduce(P, item, g, red);
+    }
+}
+
+// The adjoint from a tape: contraction of the recorded derivatives with the
+// law sensitivities (memory-bound: 144 bytes a sample).
+__global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
+    __shared__ int64_t slot;
+    __shared__ double red[kPhaseBlock / 64][kGradParams];
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_items) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sp = P.shots[s];
+        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        double g[kGradParams];
 #pragma unroll
-        for (int p = 0; p < kGradParams; ++p) {
-            const double v = wave_sum(g[p]);
-            if (lane == 0) red[wid][p] = v;
+        for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
+        if (i < sp.n_samples) {
+            const int64_t n = P.tape_n;
+            const double *t = P.tape + sp.state_off + i;
+            const double mu = t[0], s2 = t[n];
+            if (mu > 0.0 && isfinite(mu) && isfinite(s2)) {
+                double lv, ls;
+                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                P.gouts[s].d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p)
+                    g[p] = fma(lv, t[(2 + p) * n], ls * t[(2 + kGradParams + p) * n]);
+            } else {
+                atomicOr(&P.flags[s], kFlagNonFinite);
+            }
         }
-        __syncthreads();
-        if (threadIdx.x < kGradParams) {
-            double sum = 0.0;
-            for (int w = 0; w < kPhaseBlock / 64; ++w) sum += red[w][threadIdx.x];
-            P.partials[(size_t)item * kGradParams + threadIdx.x] = sum;
-        }
-        // red is rewritten only after the next item's barriers
+        grad_item_reduce(P, item, g, red);
     }
 }
 
@@ -1906,21 +1993,28 @@ hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int pr
     return hipGetLastError();
 }
 
-template <int PREC, bool QUANTUM, bool LOCAL>
-static const void *adjoint_ptr() {
-    return reinterpret_cast<const void *>(&adjoint_kernel<PREC, QUANTUM, LOCAL>);
+template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
+static const void *tangent_ptr() {
+    return reinterpret_cast<const void *>(&tangent_kernel<PREC, QUANTUM, LOCAL, TAPE>);
 }
 
-hipError_t launch_adjoint(const BatchParams &p, const float *env32, const double *env64, int prec,
-                          int rr, int amp, hipStream_t s) {
+template <bool TAPE>
+static const void *select_tangent(int prec, int rr, int amp) {
     const bool q = rr == 1, l = amp == 1;
-    const void *fn;
     if (prec == PREC_F64)
-        fn = q ? (l ? adjoint_ptr<PREC_F64, true, true>() : adjoint_ptr<PREC_F64, true, false>())
-               : (l ? adjoint_ptr<PREC_F64, false, true>() : adjoint_ptr<PREC_F64, false, false>());
-    else
-        fn = q ? (l ? adjoint_ptr<PREC_F32, true, true>() : adjoint_ptr<PREC_F32, true, false>())
-               : (l ? adjoint_ptr<PREC_F32, false, true>() : adjoint_ptr<PREC_F32, false, false>());
+        return q ? (l ? tangent_ptr<PREC_F64, true, true, TAPE>()
+                      : tangent_ptr<PREC_F64, true, false, TAPE>())
+                 : (l ? tangent_ptr<PREC_F64, false, true, TAPE>()
+                      : tangent_ptr<PREC_F64, false, false, TAPE>());
+    return q ? (l ? tangent_ptr<PREC_F32, true, true, TAPE>()
+                  : tangent_ptr<PREC_F32, true, false, TAPE>())
+             : (l ? tangent_ptr<PREC_F32, false, true, TAPE>()
+                  : tangent_ptr<PREC_F32, false, false, TAPE>());
+}
+
+hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
+                          int rr, int amp, bool tape, hipStream_t s) {
+    const void *fn = tape ? select_tangent<true>(prec, rr, amp) : select_tangent<false>(prec, rr, amp);
     int grid = 0;
     hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
     if (e != hipSuccess) return e;
@@ -1929,6 +2023,15 @@ hipError_t launch_adjoint(const BatchParams &p, const float *env32, const double
     const double *e64 = env64;
     void *args[] = {&pc, &e32, &e64};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+}
+
+hipError_t launch_contract(const BatchParams &p, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&contract_kernel);
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    contract_kernel<<<grid, kPhaseBlock, 0, s>>>(p);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {

@@ -160,7 +160,7 @@ def test_autograd_function(gpu):
     p = _case("quantum-local-gauss", n_samples=2000)
     theta = torch.tensor([p[n] for n in NAMES], dtype=torch.float64, requires_grad=True)
     h = qs.energy_histogram(theta, p, context=gpu)
-    ref = gpu.forward(p)["energy_hist"]
+    ref = gpu.forward(p, tape=gpu.new_tape(p["n_samples"]))["energy_hist"]
     assert torch.equal(h.detach(), ref)
     w = torch.tensor(_weights(p["n_e"]), dtype=torch.float64, device="cuda")
     (h * w).sum().backward()
