@@ -461,8 +461,18 @@ struct SampleOut {
     T gamma0, x, y, z;
 };
 
-template <class T>
-SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i) {
+/* No-op stage visitor (see run_sample). */
+struct NoVisit {
+    template <class T>
+    void operator()(double, const T &, const T &, const Rhs<T> &) const {}
+};
+
+/* One sample's trajectory.  visit(w, mu_s, a_s, k_s) is called at every RK4
+ * stage with its quadrature weight w (h/6, h/3, h/3, h/6), the stage state
+ * and amplitude, and the stage's right-hand side. */
+template <class T, class Visit>
+SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i,
+                        Visit &visit) {
     const SampleIn<T> s = make_sample<T>(p, P, i);
     const Geometry<T> gmt = geometry<T>(p, P, s);
     T mu = s.gamma0, sig2(0.0);
@@ -476,9 +486,16 @@ SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> 
         const T a4 = amplitude<T>(p, d, P, s, gmt, psi + h);
         chimax = std::fmax(chimax, 2.0 * val(mu) * std::fabs(val(a1)) / d.aS);
         const Rhs<T> k1 = rhs<T>(p, d, mu, sig2, a1);
-        const Rhs<T> k2 = rhs<T>(p, d, mu + 0.5 * h * k1.dmu, sig2 + 0.5 * h * k1.dsig2, ah);
-        const Rhs<T> k3 = rhs<T>(p, d, mu + 0.5 * h * k2.dmu, sig2 + 0.5 * h * k2.dsig2, ah);
-        const Rhs<T> k4 = rhs<T>(p, d, mu + h * k3.dmu, sig2 + h * k3.dsig2, a4);
+        const T m2 = mu + 0.5 * h * k1.dmu;
+        const Rhs<T> k2 = rhs<T>(p, d, m2, sig2 + 0.5 * h * k1.dsig2, ah);
+        const T m3 = mu + 0.5 * h * k2.dmu;
+        const Rhs<T> k3 = rhs<T>(p, d, m3, sig2 + 0.5 * h * k2.dsig2, ah);
+        const T m4 = mu + h * k3.dmu;
+        const Rhs<T> k4 = rhs<T>(p, d, m4, sig2 + h * k3.dsig2, a4);
+        visit(h / 6.0, mu, a1, k1);
+        visit(h / 3.0, m2, ah, k2);
+        visit(h / 3.0, m3, ah, k3);
+        visit(h / 6.0, m4, a4, k4);
         mu += h / 6.0 * (k1.dmu + 2.0 * k2.dmu + 2.0 * k3.dmu + k4.dmu);
         sig2 += h / 6.0 * (k1.dsig2 + 2.0 * k2.dsig2 + 2.0 * k3.dsig2 + k4.dsig2);
     }
@@ -504,6 +521,12 @@ SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> 
     o.gamma0 = s.gamma0;
     o.x = s.x; o.y = s.y; o.z = s.z;
     return o;
+}
+
+template <class T>
+SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i) {
+    NoVisit none;
+    return run_sample<T>(p, d, P, i, none);
 }
 
 SampleOut<double> run_sample(const qso_problem *p, const Derived &d, int64_t i) {
@@ -591,6 +614,164 @@ void deposit(const T &v, const T &s, int32_t dep, double ksig, double lo, double
                                                  : law_ccdf<T>(L, e0) - law_ccdf<T>(L, e1);
         hist[k] += m;
     }
+}
+
+/* ---- photon emission (Sec. 4) ------------------------------------------- */
+/* The approximate photon spectrum of Sec. 4: at each phase the electron of
+ * mean energy gamma meets the instantaneous amplitude a and emits the LCFA
+ * quantum-synchrotron spectrum of chi = 2 gamma |a| / a_S; the spectra are
+ * integrated over the phase.  Per unit phase (dpsi = 2 omega0 dt) and unit
+ * photon energy fraction xi the expected photon number is
+ *   d2N / (dpsi dxi) = C_ph F(xi, chi) / gamma,   C_ph = alpha a_S / (2 sqrt3 pi),
+ *   F = (1 - xi + 1/(1 - xi)) K_{2/3}(y) - Int_y^inf K_{1/3},  y = 2 xi / (3 chi (1 - xi)),
+ * the emission rate of the radiation functions above over dpsi/dt; its first
+ * xi-moment is (2 pi chi^2 / sqrt3) g, i.e. the drift of eq. dpdtRR.
+ * Reading: the phase integral uses the RK4 stages of each step with their
+ * weights (h/6, h/3, h/3, h/6) at the stage states, so that in the classical
+ * model the emitted photon energy equals the electron's energy loss exactly.
+ *
+ * The number CDF Phi(xi; chi) = Int_0^xi F dxi' is tabulated over
+ * u = ln chi and z = y^(1/3) (Phi grows like z near 0), divided by chi (in
+ * the classical limit Phi = chi H(y)).  Per row the Int K_{1/3} term is
+ * integrated by parts:
+ *   Phi = Int_0^y [w K_{2/3}(y') xi_y(y') - xi(y') K_{1/3}(y')] dy' - xi Int_y^inf K_{1/3},
+ * with 5-point Gauss-Legendre on every z interval, and Int_y^inf K_{1/3}
+ * accumulated downwards from y_max = 80 (both tails there are below 1e-34). */
+struct PhotonTable {
+    double u0, du, dz;
+    int nu, nz;
+    std::vector<double> v;  /* [nu][nz + 1]: Phi / chi at z_j = j dz */
+};
+
+const double kPhotonYMax = 80.0;
+PhotonTable *g_photon = nullptr;
+std::once_flag g_photon_once;
+
+void build_photon_table() {
+    PhotonTable *T = new PhotonTable;
+    T->du = 1.0 / 32.0;
+    T->u0 = std::log(1e-6);
+    T->nu = (int)std::ceil((std::log(1e3) - T->u0) / T->du) + 1;
+    T->nz = 512;
+    T->dz = std::cbrt(kPhotonYMax) / T->nz;
+    T->v.assign((size_t)T->nu * (T->nz + 1), 0.0);
+    const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
+                          0.9061798459386640};
+    const double gw[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                          0.4786286704993665, 0.2369268850561891};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int r = 0; r < T->nu; ++r) {
+        const double chi = std::exp(T->u0 + r * T->du);
+        const int nz = T->nz;
+        const double dz = T->dz;
+        std::vector<double> I13(nz + 1, 0.0), A(nz + 1, 0.0);
+        for (int j = nz - 1; j >= 0; --j) {  /* Int_y^inf K_{1/3}, downwards */
+            double s = 0.0;
+            for (int g = 0; g < 5; ++g) {
+                const double z = dz * (j + 0.5 + 0.5 * gx[g]);
+                const double y = z * z * z;
+                s += gw[g] * std::cyl_bessel_k(1.0 / 3.0, y) * 3.0 * z * z;
+            }
+            I13[j] = I13[j + 1] + 0.5 * dz * s;
+        }
+        for (int j = 0; j < nz; ++j) {  /* the other two terms, upwards */
+            double s = 0.0;
+            for (int g = 0; g < 5; ++g) {
+                const double z = dz * (j + 0.5 + 0.5 * gx[g]);
+                const double y = z * z * z;
+                const double q = 2.0 + 3.0 * chi * y;
+                const double xi = 3.0 * chi * y / q;
+                const double w = 2.0 / q + 0.5 * q;  /* 1 - xi + 1/(1 - xi) */
+                const double xi_y = 6.0 * chi / (q * q);
+                const double f = w * std::cyl_bessel_k(2.0 / 3.0, y) * xi_y -
+                                 xi * std::cyl_bessel_k(1.0 / 3.0, y);
+                s += gw[g] * f * 3.0 * z * z;
+            }
+            A[j + 1] = A[j] + 0.5 * dz * s;
+        }
+        double *row = &T->v[(size_t)r * (nz + 1)];
+        for (int j = 0; j <= nz; ++j) {
+            const double y = std::pow(dz * j, 3.0);
+            const double xi = 3.0 * chi * y / (2.0 + 3.0 * chi * y);
+            row[j] = (A[j] - xi * I13[j]) / chi;
+        }
+    }
+    g_photon = T;
+}
+
+const PhotonTable &photon_table() {
+    std::call_once(g_photon_once, build_photon_table);
+    return *g_photon;
+}
+
+/* 4-point Lagrange weights at x in [0, 3] for nodes 0..3. */
+void lagrange4(double x, double w[4]) {
+    w[0] = -(x - 1.0) * (x - 2.0) * (x - 3.0) / 6.0;
+    w[1] = x * (x - 2.0) * (x - 3.0) / 2.0;
+    w[2] = -x * (x - 1.0) * (x - 3.0) / 2.0;
+    w[3] = x * (x - 1.0) * (x - 2.0) / 6.0;
+}
+
+/* Interpolation in u fixed for one chi: Phi(xi; chi) at many xi.  Below the
+ * table's first row the classical scaling Phi = chi H(y) is used (row 0 at the
+ * sample's own y); above its last row the value is NaN. */
+struct PhotonRow {
+    const PhotonTable *T;
+    double chi, wu[4];
+    int r0;
+    bool ok;
+    explicit PhotonRow(double chi_) : T(&photon_table()), chi(chi_) {
+        const double s = (std::log(chi) - T->u0) / T->du;
+        ok = chi > 0.0 && s <= T->nu - 1;
+        if (s < 0.0) {
+            r0 = 0;
+            wu[0] = 1.0; wu[1] = wu[2] = wu[3] = 0.0;
+            return;
+        }
+        int i = (int)std::floor(s) - 1;
+        if (i < 0) i = 0;
+        if (i > T->nu - 4) i = T->nu - 4;
+        r0 = i;
+        lagrange4(s - i, wu);
+    }
+    double at_z(double z) const {  /* Phi / chi at z (clamped to the table) */
+        double t = z / T->dz;
+        if (t > T->nz) t = T->nz;
+        int j = (int)std::floor(t) - 1;
+        if (j < 0) j = 0;
+        if (j > T->nz - 3) j = T->nz - 3;
+        double wz[4];
+        lagrange4(t - j, wz);
+        double acc = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const double *row = &T->v[(size_t)(r0 + a) * (T->nz + 1) + j];
+            acc += wu[a] * (wz[0] * row[0] + wz[1] * row[1] + wz[2] * row[2] + wz[3] * row[3]);
+        }
+        return acc;
+    }
+    double total() const { return ok ? chi * at_z(T->nz * T->dz) : NAN; }
+    double cdf(double xi) const {
+        if (!ok) return NAN;
+        if (!(xi > 0.0)) return 0.0;
+        if (xi >= 1.0) return total();
+        const double y = 2.0 * xi / (3.0 * chi * (1.0 - xi));
+        return chi * at_z(std::cbrt(y));
+    }
+};
+
+/* Photon bins of one emission: weight C_ph w / gamma times the CDF
+ * differences at the bin edges (underflow [n], overflow [n + 1]). */
+void photon_deposit(double weight, double gamma, const PhotonRow &R, int32_t n, double lo,
+                    double width, double *hist) {
+    const double N = R.total();
+    double prev = R.cdf(lo / gamma);
+    hist[n] += weight * prev;
+    for (int k = 0; k < n; ++k) {
+        const double next = R.cdf((lo + (k + 1) * width) / gamma);
+        hist[k] += weight * (next - prev);
+        prev = next;
+    }
+    hist[n + 1] += weight * (N - prev);
 }
 
 /* Neumaier-compensated running sum. */
@@ -812,4 +993,63 @@ int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
     return 0;
 }
 
+int qso_photon_cdf(double xi, double chi, double *phi, double *total) {
+    if (!(chi > 0.0) || !(chi <= 1e3)) return -1;
+    const PhotonRow R(chi);
+    if (phi) *phi = R.cdf(xi);
+    if (total) *total = R.total();
+    return 0;
+}
+
+int qso_photons(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads, int32_t n_ph,
+                double ph_lo, double ph_hi, double *hist, double *energy) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
+    if (n_ph < 1 || !(ph_lo >= 0.0) || !(ph_hi > ph_lo) || !std::isfinite(ph_hi)) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    photon_table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int64_t total = i_end - i_begin;
+    const double width = (ph_hi - ph_lo) / n_ph;
+    const double c_ph = kAlpha * d.aS / (2.0 * std::sqrt(3.0) * kPi);
+    std::vector<std::vector<double>> H(nthreads, std::vector<double>(n_ph + 2, 0.0));
+    std::vector<KSum> eph(nthreads), eel(nthreads);
+    std::vector<int> bad(nthreads, 0);
+    Params<double> P = params<double>(p);
+    finish_params(p, P);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        double *h = H[t].data();
+        KSum &ep = eph[t];
+        auto visit = [&](double w, const double &mu, const double &a, const Rhs<double> &k) {
+            const double chi = 2.0 * mu * std::fabs(a) / d.aS;
+            if (!(chi > 0.0)) return;
+            ep.add(-w * k.A);  /* photon energy = the drift's energy loss */
+            const PhotonRow R(chi);
+            photon_deposit(c_ph * w / mu, mu, R, n_ph, ph_lo, width, h);
+        };
+        for (int64_t i = b; i < e; ++i) {
+            const SampleOut<double> o = run_sample<double>(p, d, P, i, visit);
+            if (!std::isfinite(o.mu) || !std::isfinite(o.sig2)) { bad[t] = 1; continue; }
+            eel[t].add(o.gamma0 - o.mu);
+        }
+    }
+    for (int t = 1; t < nthreads; ++t) {
+        for (int k = 0; k < n_ph + 2; ++k) H[0][k] += H[t][k];
+        eph[0].add(eph[t].s); eph[0].add(eph[t].c);
+        eel[0].add(eel[t].s); eel[0].add(eel[t].c);
+    }
+    for (int t = 0; t < nthreads; ++t) if (bad[t]) return -2;
+    if (hist) std::memcpy(hist, H[0].data(), sizeof(double) * (n_ph + 2));
+    if (energy) {
+        energy[0] = eph[0].value();
+        energy[1] = eel[0].value();
+    }
+    return 0;
+}
+
 }  // extern "C"
+

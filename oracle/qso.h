@@ -130,6 +130,19 @@ int qso_sample_grad(const qso_problem *p, int64_t i, double *out);
 int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
              double *hist, double *jac);
 
+/* Photon emission (Sec. 4): at every RK4 stage the electron's mean energy
+ * and the instantaneous amplitude give the LCFA photon spectrum of
+ * chi = 2 gamma |a| / a_S, integrated over the phase with the stage weights.
+ * hist[n_ph + 2]: expected photon number per bin of photon energy over
+ * [ph_lo, ph_hi) in m c^2 units (underflow [n_ph], overflow [n_ph + 1]),
+ * summed over samples [i_begin, i_end); energy[0] = emitted photon energy,
+ * energy[1] = sum of the electrons' energy loss gamma0_i - mu_f (m c^2). */
+int qso_photons(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads, int32_t n_ph,
+                double ph_lo, double ph_hi, double *hist, double *energy);
+/* Number CDF Phi(xi; chi) = Int_0^xi F(xi', chi) dxi' of the LCFA spectrum
+ * (F as in qso_photons' notes) and its total Phi(1; chi). */
+int qso_photon_cdf(double xi, double chi, double *phi, double *total);
+
 /* Deposit one law into a histogram (exposed for the pins). */
 int qso_deposit(double v, double s, int32_t deposit, double kernel_sigma_bins,
                 double lo, double hi, int32_t n, double *hist);

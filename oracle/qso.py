@@ -81,6 +81,11 @@ def lib():
         L.qso_sample_grad.restype = ctypes.c_int
         L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
         L.qso_grad.restype = ctypes.c_int
+        L.qso_photons.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_double, dp, dp]
+        L.qso_photons.restype = ctypes.c_int
+        L.qso_photon_cdf.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.qso_photon_cdf.restype = ctypes.c_int
         L.qso_deposit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int32, dp]
@@ -218,6 +223,32 @@ def grad(params, i_begin=0, i_end=None, nthreads=0):
     if rc == -2:
         raise FloatingPointError("non-finite state")
     return h, j
+
+
+def photons(params, n_ph, ph_lo, ph_hi, i_begin=0, i_end=None, nthreads=0):
+    """Expected photon number per photon-energy bin (n_ph + 2 with underflow,
+    overflow) over samples [i_begin, i_end), and (emitted photon energy,
+    electron energy loss), both in m c^2."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    p = problem(params)
+    h = np.zeros(n_ph + 2)
+    e = np.zeros(2)
+    rc = lib().qso_photons(ctypes.byref(p), i_begin, i_end, nthreads, n_ph, ph_lo, ph_hi,
+                           _dp(h), _dp(e))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return h, e
+
+
+def photon_cdf(xi, chi):
+    """(Phi(xi; chi), Phi(1; chi)) of the LCFA photon number spectrum."""
+    phi, tot = ctypes.c_double(), ctypes.c_double()
+    if lib().qso_photon_cdf(xi, chi, ctypes.byref(phi), ctypes.byref(tot)) != 0:
+        raise ValueError("chi out of range")
+    return phi.value, tot.value
 
 
 def deposit(v, s, dep, ksig, lo, hi, n):
