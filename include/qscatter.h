@@ -292,6 +292,52 @@ qs_status qs_backward_tape_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser 
                                    const qs_grad_outputs *outs, const double *tape,
                                    void *stream);
 
+/* Photon-energy bins: n_ph bins over [ph_lo, ph_hi) in m c^2 units, plus
+ * underflow [n_ph] and overflow [n_ph + 1]. */
+typedef struct qs_photon_bins {
+    int32_t n_ph;        /* 1..4096                                            */
+    int32_t reserved0;
+    double ph_lo, ph_hi; /* 0 <= ph_lo < ph_hi                                 */
+} qs_photon_bins;
+
+/* Photon outputs of one shot: device pointers, caller-allocated. */
+typedef struct qs_photon_outputs {
+    double *photon_hist; /* [n_ph + 2] expected photon number per bin, summed
+                            over the samples (one electron each)              */
+    double *energy;      /* [2]: emitted photon energy, and the electrons'
+                            energy loss sum(gamma0_i - mu_f), m c^2 units      */
+    int32_t *status;     /* [1] qs_status of the device-side checks, or NULL   */
+} qs_photon_outputs;
+
+/* The approximate photon spectrum of Sec. 4: along each sample's trajectory
+ * (integrated as in qs_forward) every phase pairs the mean energy with the
+ * instantaneous amplitude and emits the LCFA quantum-synchrotron spectrum of
+ * chi = 2 gamma |a| / a_S; the spectra are integrated over the phase with the
+ * RK4 stage weights.  On the device each stage deposits its emission weight
+ * into an emission grid over (ln chi, ln mu) (bilinear, 0.2 in ln chi, at
+ * most 64 columns over the shot's energy range), which is contracted with
+ * the tabulated LCFA number spectrum: about 1e-3 of the spectrum in L1.  The
+ * emitted photon energy (energy[0]) is summed exactly per stage; in the
+ * classical model it equals the electrons' energy loss (energy[1]).
+ * Errors: QS_EINVAL (as qs_forward; photon bins out of range; NULL outputs),
+ * QS_ENOMEM, QS_EDEVICE.  Device status QS_ERANGE: a stage left the grid. */
+qs_status qs_photons(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                     const qs_numerics *num, const qs_photon_bins *bins,
+                     const qs_photon_outputs *out, void *stream);
+
+/* qs_photons over many shots in one launch (rules of qs_forward_batched;
+ * shot k uses RNG counter word num->shot + k). */
+qs_status qs_photons_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                             const qs_beam *beams, const int64_t *n_samples,
+                             const qs_numerics *num, const qs_photon_bins *bins,
+                             const qs_photon_outputs *outs, void *stream);
+
+/* The device's LCFA number CDF Phi(xi; chi) = Int_0^xi F(xi', chi) dxi' at n
+ * points (device arrays; diagnostic entry point for parity checks).
+ * Errors: QS_EINVAL, QS_EDEVICE. */
+qs_status qs_photon_cdf(qs_ctx *ctx, int64_t n, const double *chi, const double *xi,
+                        double *out, void *stream);
+
 /* Evaluate the derivative tables that the adjoint uses at n values of chi
  * (device arrays): out[6*k + {0..5}] = {g, chi g', chi^2 g'', h, chi^3 g''',
  * chi h'} at chi[k], FP32 or FP64 (Sec. 4 eq. dpdtRR; diagnostic entry point).

@@ -631,8 +631,8 @@ void deposit(const T &v, const T &s, int32_t dep, double ksig, double lo, double
  * model the emitted photon energy equals the electron's energy loss exactly.
  *
  * The number CDF Phi(xi; chi) = Int_0^xi F dxi' is tabulated over
- * u = ln chi and z = y^(1/3) (Phi grows like z near 0), divided by chi (in
- * the classical limit Phi = chi H(y)).  Per row the Int K_{1/3} term is
+ * u = ln chi and z = y^(1/3), as Phi / (chi z): Phi grows like z near 0 and
+ * in the classical limit Phi = chi H(y).  Per row the Int K_{1/3} term is
  * integrated by parts:
  *   Phi = Int_0^y [w K_{2/3}(y') xi_y(y') - xi(y') K_{1/3}(y')] dy' - xi Int_y^inf K_{1/3},
  * with 5-point Gauss-Legendre on every z interval, and Int_y^inf K_{1/3}
@@ -640,7 +640,7 @@ void deposit(const T &v, const T &s, int32_t dep, double ksig, double lo, double
 struct PhotonTable {
     double u0, du, dz;
     int nu, nz;
-    std::vector<double> v;  /* [nu][nz + 1]: Phi / chi at z_j = j dz */
+    std::vector<double> v;  /* [nu][nz + 1]: Phi / (chi z) at z_j = j dz */
 };
 
 const double kPhotonYMax = 80.0;
@@ -652,7 +652,7 @@ void build_photon_table() {
     T->du = 1.0 / 32.0;
     T->u0 = std::log(1e-6);
     T->nu = (int)std::ceil((std::log(1e3) - T->u0) / T->du) + 1;
-    T->nz = 512;
+    T->nz = 2048;
     T->dz = std::cbrt(kPhotonYMax) / T->nz;
     T->v.assign((size_t)T->nu * (T->nz + 1), 0.0);
     const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
@@ -690,10 +690,13 @@ void build_photon_table() {
             A[j + 1] = A[j] + 0.5 * dz * s;
         }
         double *row = &T->v[(size_t)r * (nz + 1)];
-        for (int j = 0; j <= nz; ++j) {
-            const double y = std::pow(dz * j, 3.0);
+        /* stored: Phi / (chi z), smooth at z = 0, where it tends to
+         * 9 2^(-1/3) Gamma(2/3) (from K_{2/3}(y) ~ Gamma(2/3)/2 (y/2)^(-2/3)) */
+        row[0] = 9.0 * std::pow(2.0, -1.0 / 3.0) * std::tgamma(2.0 / 3.0);
+        for (int j = 1; j <= nz; ++j) {
+            const double z = dz * j, y = z * z * z;
             const double xi = 3.0 * chi * y / (2.0 + 3.0 * chi * y);
-            row[j] = (A[j] - xi * I13[j]) / chi;
+            row[j] = (A[j] - xi * I13[j]) / (chi * z);
         }
     }
     g_photon = T;
@@ -735,8 +738,8 @@ struct PhotonRow {
         lagrange4(s - i, wu);
     }
     double at_z(double z) const {  /* Phi / chi at z (clamped to the table) */
+        if (z > T->nz * T->dz) z = T->nz * T->dz;
         double t = z / T->dz;
-        if (t > T->nz) t = T->nz;
         int j = (int)std::floor(t) - 1;
         if (j < 0) j = 0;
         if (j > T->nz - 3) j = T->nz - 3;
@@ -747,7 +750,7 @@ struct PhotonRow {
             const double *row = &T->v[(size_t)(r0 + a) * (T->nz + 1) + j];
             acc += wu[a] * (wz[0] * row[0] + wz[1] * row[1] + wz[2] * row[2] + wz[3] * row[3]);
         }
-        return acc;
+        return acc * z;
     }
     double total() const { return ok ? chi * at_z(T->nz * T->dz) : NAN; }
     double cdf(double xi) const {

@@ -267,6 +267,71 @@ class Context:
                 raise QScatterError(bad, "device status of a shot")
         return grads
 
+    def photons(self, params, stream=None, check=True):
+        """Photon spectrum of one shot (Sec. 4): returns {"photon_hist": [n_ph + 2]
+        expected photon number per bin, "energy": [emitted photon energy,
+        electron energy loss], "status"}; bins from photon_bins(params)."""
+        return self.photons_batched([params], stream=stream, check=check, single=True)[0]
+
+    def photons_batched(self, shots, stream=None, check=True, single=False):
+        """Photon spectra of many shots in one launch (shot k uses RNG counter
+        word shots[0]["shot"] + k)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        n = len(shots)
+        if n == 0:
+            raise ValueError("empty batch")
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _, _, nu, _ = _lib.structs(shots[0])
+        lasers, beams = (_lib.Laser * n)(), (_lib.Beam * n)()
+        pbins, pouts, ns = (_lib.PhotonBins * n)(), (_lib.PhotonOutputs * n)(), (ctypes.c_int64 * n)()
+        outs = []
+        for k, p in enumerate(shots):
+            la, be, _, _ = _lib.structs(p)
+            lasers[k], beams[k] = la, be
+            pbins[k] = _lib.photon_bins(p)
+            ns[k] = int(p["n_samples"])
+            o = {"photon_hist": torch.empty(pbins[k].n_ph + 2, dtype=torch.float64, device=dev),
+                 "energy": torch.empty(2, dtype=torch.float64, device=dev),
+                 "status": torch.empty(1, dtype=torch.int32, device=dev)}
+            outs.append(o)
+            pouts[k] = _lib.PhotonOutputs(photon_hist=o["photon_hist"].data_ptr(),
+                                          energy=o["energy"].data_ptr(),
+                                          status=o["status"].data_ptr())
+        if single:
+            st = _lib.lib().qs_photons(self._ptr, ctypes.byref(lasers[0]), ctypes.byref(beams[0]),
+                                       ctypes.byref(nu), ctypes.byref(pbins[0]),
+                                       ctypes.byref(pouts[0]), ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_photons_batched(self._ptr, n, lasers, beams, ns, ctypes.byref(nu),
+                                               pbins, pouts, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        if check:
+            torch.cuda.synchronize(dev)
+            bad = int(torch.stack([o["status"] for o in outs]).max().item())
+            if bad != _lib.QS_OK:
+                raise QScatterError(bad, "device status of a shot")
+        return outs
+
+    def photon_cdf(self, chi, xi):
+        """The device's LCFA number CDF Phi(xi; chi) (1-D float64 tensors)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        chi = chi.to(device=dev, dtype=torch.float64).contiguous()
+        xi = xi.to(device=dev, dtype=torch.float64).contiguous()
+        out = torch.empty_like(chi)
+        stream = torch.cuda.current_stream(dev)
+        st = _lib.lib().qs_photon_cdf(self._ptr, chi.numel(), ctypes.c_void_p(chi.data_ptr()),
+                                      ctypes.c_void_p(xi.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        torch.cuda.synchronize(dev)
+        return out
+
     def set_profiling(self, on=True):
         st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)
         if st != _lib.QS_OK:

@@ -62,6 +62,16 @@ class Outputs(ctypes.Structure):
                 ("sample_stride", ctypes.c_int64), ("n_sample_records", ctypes.c_int64)]
 
 
+class PhotonBins(ctypes.Structure):
+    _fields_ = [("n_ph", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("ph_lo", ctypes.c_double), ("ph_hi", ctypes.c_double)]
+
+
+class PhotonOutputs(ctypes.Structure):
+    _fields_ = [("photon_hist", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
 class GradOutputs(ctypes.Structure):
     _fields_ = [("d_energy_hist", ctypes.c_void_p), ("grad", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
@@ -76,7 +86,8 @@ T_MU, T_SIG2, T_DMU, T_DSIG2 = 0, 1, 2, 2 + len(PARAM_NAMES)
 
 EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_backward",
            "qs_backward_batched", "qs_forward_tape", "qs_forward_tape_batched",
-           "qs_backward_tape", "qs_backward_tape_batched", "qs_radiation_eval",
+           "qs_backward_tape", "qs_backward_tape_batched", "qs_photons", "qs_photons_batched",
+           "qs_photon_cdf", "qs_radiation_eval",
            "qs_radiation_derivs", "qs_sync_status",
            "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
            "qs_abi_version"]
@@ -130,6 +141,17 @@ def lib():
         L.qs_backward_tape.restype = ctypes.c_int
         L.qs_backward_tape_batched.argtypes = L.qs_backward_batched.argtypes[:8] + [vp, vp]
         L.qs_backward_tape_batched.restype = ctypes.c_int
+        L.qs_photons.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                                 ctypes.POINTER(Numerics), ctypes.POINTER(PhotonBins),
+                                 ctypes.POINTER(PhotonOutputs), vp]
+        L.qs_photons.restype = ctypes.c_int
+        L.qs_photons_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser),
+                                         ctypes.POINTER(Beam), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(Numerics), ctypes.POINTER(PhotonBins),
+                                         ctypes.POINTER(PhotonOutputs), vp]
+        L.qs_photons_batched.restype = ctypes.c_int
+        L.qs_photon_cdf.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.qs_photon_cdf.restype = ctypes.c_int
         L.qs_radiation_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.qs_radiation_eval.restype = ctypes.c_int
         L.qs_radiation_derivs.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
@@ -152,6 +174,14 @@ def lib():
 
 def _enum(table, v):
     return table[v] if isinstance(v, str) else int(v)
+
+
+def photon_bins(params):
+    """Photon-energy bins of a parameter dictionary (m c^2 units): n_ph
+    (default 256) over [ph_lo, ph_hi) (default [0, e_hi))."""
+    return PhotonBins(n_ph=int(params.get("n_ph", 256)), reserved0=0,
+                      ph_lo=float(params.get("ph_lo", 0.0)),
+                      ph_hi=float(params.get("ph_hi", params["e_hi"])))
 
 
 def structs(params):

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "qs_internal.h"
 
@@ -21,6 +22,7 @@ struct qs_ctx {
     double *rad64 = nullptr;
     float *rad32d = nullptr;   // derivative tables (adjoint)
     double *rad64d = nullptr;
+    double *phtab = nullptr;   // LCFA photon number CDF
     // per-call device scratch (grow-only)
     float *env32 = nullptr;
     double *env64 = nullptr;
@@ -178,6 +180,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                         const qs_grad_outputs *O, const double *tape, hipStream_t s);
+qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                       const int64_t *n_samples, const qs_numerics *N, const qs_photon_bins *PB,
+                       const qs_photon_outputs *PO, hipStream_t s);
 
 }  // namespace
 
@@ -211,12 +216,14 @@ qs_status qs_create(qs_ctx **out, int device) {
     DeviceGuard g(device);
     hipError_t e;
     double *work = nullptr;
-    const size_t wd = qs::radiation_work_doubles();
+    const size_t wd = std::max(qs::radiation_work_doubles(), qs::photon_work_doubles());
     if ((e = hipMalloc(&c->rad32, sizeof(float) * qs::kCells32 * qs::kCellVals)) != hipSuccess ||
         (e = hipMalloc(&c->rad64, sizeof(double) * qs::kCells64 * qs::kCellVals)) != hipSuccess ||
         (e = hipMalloc(&c->rad32d, sizeof(float) * qs::kCells32 * 4 * qs::kDerivFuncs)) !=
             hipSuccess ||
         (e = hipMalloc(&c->rad64d, sizeof(double) * qs::kCells64 * 4 * qs::kDerivFuncs)) !=
+            hipSuccess ||
+        (e = hipMalloc(&c->phtab, sizeof(double) * qs::kPhRows * (qs::kPhNZ + 1))) !=
             hipSuccess ||
         (e = hipMalloc(&c->eval_flags, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&work, sizeof(double) * wd)) != hipSuccess ||
@@ -227,6 +234,8 @@ qs_status qs_create(qs_ctx **out, int device) {
         return st;
     }
     e = qs::build_radiation_tables(c->rad32, c->rad64, c->rad32d, c->rad64d, work, wd, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = qs::build_photon_table(c->phtab, work, wd, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipFree(work);
     if (e != hipSuccess) {
@@ -247,6 +256,7 @@ void qs_destroy(qs_ctx *c) {
         (void)hipFree(c->rad64);
         (void)hipFree(c->rad32d);
         (void)hipFree(c->rad64d);
+        (void)hipFree(c->phtab);
         (void)hipFree(c->env32);
         (void)hipFree(c->env64);
         (void)hipFree(c->accum);
@@ -353,6 +363,37 @@ qs_status qs_backward_tape_batched(qs_ctx *c, int32_t n_shots, const qs_laser *l
         return set_err(c, "invalid batch arguments"), QS_EINVAL;
     return backward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, tape,
                          reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_photons(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
+                     const qs_photon_bins *PB, const qs_photon_outputs *PO, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    const int64_t n = N->n_samples;
+    return photons_impl(c, 1, L, B, &n, N, PB, PO, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_photons_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                             const qs_beam *beams, const int64_t *n_samples,
+                             const qs_numerics *num, const qs_photon_bins *bins,
+                             const qs_photon_outputs *outs, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins || !outs)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return photons_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_photon_cdf(qs_ctx *c, int64_t n, const double *chi, const double *xi, double *out,
+                        void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n < 0 || (n > 0 && (!chi || !xi || !out)))
+        return set_err(c, "invalid photon_cdf arguments"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+    hipError_t e = qs::launch_photon_cdf(c->phtab, n, chi, xi, out,
+                                         reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(c, e, "photon_cdf kernel");
+    return QS_OK;
 }
 
 qs_status qs_radiation_derivs(qs_ctx *c, int32_t precision, int64_t n, const double *chi,
@@ -714,4 +755,116 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     return QS_OK;
 }
 
+qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                       const int64_t *n_samples, const qs_numerics *N, const qs_photon_bins *PB,
+                       const qs_photon_outputs *PO, hipStream_t s) {
+    for (int k = 0; k < n_shots; ++k) {
+        const qs_photon_bins &b = PB[k];
+        if (b.n_ph < 1 || b.n_ph > 4096 || !fin(b.ph_lo) || !fin(b.ph_hi) || !(b.ph_lo >= 0.0) ||
+            !(b.ph_hi > b.ph_lo))
+            return set_err(c, "photon bins out of range"), QS_EINVAL;
+        if (!PO[k].photon_hist || !PO[k].energy)
+            return set_err(c, "null photon output pointer"), QS_EINVAL;
+    }
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    for (int k = 0; k < n_shots; ++k)
+        if ((double)n_samples[k] * (double)N->n_steps > 1099511627776.0)  // 2^40
+            return set_err(c, "photon grids hold at most 2^40 sample-steps a shot"), QS_EINVAL;
+    // the electron histograms are not used: placeholder windows
+    std::vector<qs_bins> H(n_shots);
+    for (qs_bins &h : H) h = qs_bins{1, 1, 1, 0, 0.0, 1.0, 0.0, 1.0};
+    Batch b;
+    qs_status st;
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H.data(), sizeof(qs::ShotPhot), b)) !=
+        QS_OK)
+        return st;
+    DeviceGuard guard(c->device);
+    qs::BatchParams &bp = b.bp;
+    qs::ShotPhot *sph = reinterpret_cast<qs::ShotPhot *>(b.outs);
+    const double aS = 2.0 / bp.two_over_aS;
+    // envelope integral of f^2 over the window (an upper bound of the
+    // cos^2-weighted one), for the classical-loss bound of the energy range
+    const double I2 = L[0].envelope == QS_ENV_GAUSS ? b.omega_tau * std::sqrt(kPi / (4.0 * std::log(2.0)))
+                                                    : 0.75 * b.omega_tau;
+    int64_t pitem = 0;
+    for (int k = 0; k < n_shots; ++k) {
+        qs::ShotPhot &p = sph[k];
+        p = qs::ShotPhot{};
+        const double g0 = B[k].gamma0, sg = B[k].sigma_gamma, a0 = L[k].a0;
+        // energy range: the samples' spread above, half the classical
+        // (Landau-Lifshitz, peak amplitude) bound of the loss below
+        const double mu_max = g0 + 6.5 * sg;
+        const double mu_lo = std::max(g0 - 6.5 * sg, 1.01);
+        const double mu_min = std::max(0.5 * mu_lo / (1.0 + bp.K * mu_lo * a0 * a0 * I2), 1.0);
+        p.nv = qs::kPhNV;
+        p.v_lo = std::log(mu_min) - 0.01;
+        p.dv = (std::log(mu_max) + 0.01 - p.v_lo) / (p.nv - 1);
+        // chi range: the largest chi possible above; below, stages whose
+        // photons all fall in the lowest bin (y > 27 beyond 40 chi mu)
+        const double width = (PB[k].ph_hi - PB[k].ph_lo) / PB[k].n_ph;
+        int r_hi = 1, r_lo = 0;
+        if (a0 > 0.0) {
+            const double chi_max = 2.0 * mu_max * a0 / aS * 1.02;
+            const double chi_floor = std::max(PB[k].ph_lo, width) / (40.0 * mu_max);
+            r_hi = (int)std::ceil((std::log(chi_max) - qs::kPhU0) / qs::kPhDu) + 1;
+            r_hi = std::min(std::max(r_hi, 1), qs::kPhRows - 1);
+            r_lo = (int)std::floor((std::log(chi_floor) - qs::kPhU0) / qs::kPhDu);
+            r_lo = std::max(r_lo, 0);
+            if (r_hi - r_lo + 1 > qs::kPhNU) r_lo = r_hi - qs::kPhNU + 1;
+            if (r_lo > r_hi - 1) r_lo = r_hi - 1;
+        }
+        p.r_lo = r_lo;
+        p.nu = r_hi - r_lo + 1;
+        p.n_ph = PB[k].n_ph;
+        p.ph_lo = PB[k].ph_lo;
+        p.ph_w = width;
+        p.hist = PO[k].photon_hist;
+        p.energy = PO[k].energy;
+        p.status = PO[k].status;
+        p.pitem0 = pitem;
+        p.grid_off = (int64_t)k * qs::kPhNodes;
+        pitem += (n_samples[k] + qs::kPhotTile - 1) / qs::kPhotTile;
+    }
+    bp.n_pitems = pitem;
+
+    const size_t nenv = (size_t)2 * N->n_steps + 1;
+    const size_t flag_words = ((size_t)n_shots + 1) / 2;
+    const size_t accum_words = 1 + flag_words + (size_t)n_shots * qs::kPhNodes;
+    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
+    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)pitem * qs::kPhotPartials,
+                   "photon partials")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
+        return st;
+    bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
+    bp.phot =
+        reinterpret_cast<const qs::ShotPhot *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
+    bp.rad32 = c->rad32;
+    bp.rad64 = c->rad64;
+    bp.phtab = c->phtab;
+    bp.queue = reinterpret_cast<unsigned int *>(c->accum);
+    bp.flags = reinterpret_cast<int *>(c->accum + 1);
+    bp.pgrid = c->accum + 1 + flag_words;
+    bp.partials = c->partials;
+
+    hipError_t e;
+    if ((st = upload_batch(c, b, s)) != QS_OK) return st;
+    if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau, c->env32,
+                                 c->env64, s)) != hipSuccess)
+        return hip_fail(c, e, "envelope kernel");
+    if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
+        return hip_fail(c, e, "zero kernel");
+    if ((e = qs::launch_photon(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "photon kernel");
+    const double c_ph = kAlpha * aS / (2.0 * std::sqrt(3.0) * kPi);
+    if ((e = qs::launch_photon_finalize(bp, c_ph, s)) != hipSuccess)
+        return hip_fail(c, e, "photon finalize kernel");
+    c->last_error[0] = 0;
+    return QS_OK;
+}
+
 }  // namespace
+

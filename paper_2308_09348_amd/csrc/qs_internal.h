@@ -89,6 +89,33 @@ struct ShotOut {
     int64_t rec_stride, rec_n;
 };
 
+// ---- photon spectrum (Sec. 4) ---------------------------------------------
+// Number CDF of the LCFA photon spectrum, stored as Phi(xi; chi) / (chi z) on
+// global rows u_r = kPhU0 + r kPhDu (u = ln chi) and nodes z_j = j kPhDz
+// (z = y^(1/3), y = 2 xi / (3 chi (1 - xi))), FP64, [kPhRows][kPhNZ + 1].
+constexpr double kPhDu = 0.2;
+constexpr double kPhU0 = kEMin * 0.69314718055994530942;
+constexpr int kPhRows = 100;  // u up to kPhU0 + 99 kPhDu: chi beyond 2^(kEMax+1)
+constexpr int kPhNZ = 1024;
+constexpr double kPhYMax = 80.0;
+// Emission grid of one shot: at most kPhNU rows (ln chi, global rows
+// r_lo .. r_lo + nu - 1) x kPhNV columns (ln mu), weights in fixed point.
+constexpr int kPhNU = 64, kPhNV = 64, kPhNodes = kPhNU * kPhNV;
+constexpr int kPhotTile = 2048;          // one photon work item = kPhotTile samples
+constexpr int kPhotPartials = 3;         // photon energy, electron loss, soft weight
+constexpr double kPhScale = 16777216.0;  // 2^24: unit of the grid weights
+
+struct ShotPhot {
+    int32_t r_lo, nu, nv, n_ph;  // first global row, rows, columns, photon bins
+    double v_lo, dv;             // ln mu at column 0, column width
+    double ph_lo, ph_w;          // photon-energy bins [m c^2]
+    double *hist;                // [n_ph + 2]
+    double *energy;              // [2]: photon energy, electron energy loss
+    int32_t *status;             // optional
+    int64_t pitem0;              // first photon work item
+    int64_t grid_off;            // its grid in the accumulators (kPhNodes words)
+};
+
 // Adjoint in/out pointers of one shot (device table).
 struct ShotGrad {
     const double *d_energy;  // upstream weights dL/dH over the n_e + 2 energy bins
@@ -115,6 +142,10 @@ struct BatchParams {
     const float *rad32d;  // [kCells32 * 4 * kDerivFuncs]
     const double *rad64d; // [kCells64 * 4 * kDerivFuncs]
     const ShotGrad *gouts;  // adjoint launches only
+    const ShotPhot *phot;   // photon launches only
+    const double *phtab;    // photon CDF table
+    unsigned long long *pgrid;  // per-shot emission grids
+    int64_t n_pitems;
     double *tape;           // derivative tape: [2 + 2 kGradParams][tape_n]
     int64_t tape_n;         // samples over the batch (tape field stride)
     SampleState st;
@@ -145,6 +176,13 @@ hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, in
 hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
                           int rr, int amp, bool tape, hipStream_t s);
 hipError_t launch_contract(const BatchParams &p, hipStream_t s);
+size_t photon_work_doubles();
+hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, hipStream_t s);
+hipError_t launch_photon(const BatchParams &p, const float *env32, const double *env64, int prec,
+                         int rr, int amp, hipStream_t s);
+hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t s);
+hipError_t launch_photon_cdf(const double *phtab, int64_t n, const double *chi, const double *xi,
+                             double *out, hipStream_t s);
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s);
 
 }  // namespace qs
