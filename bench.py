@@ -34,21 +34,29 @@ ALG_FLOPS = {("quantum", "local"): 270, ("quantum", "a0eff"): 229,
 
 
 PROFILE = os.path.join(ROOT, "profiles", "phase_kernel_focused_2p22.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2308_09348_amd", "csrc", "qs_kernels.hip")
+# the forward kernels and the device helpers they use
+KERNEL_SRC = [os.path.join(ROOT, "paper_2308_09348_amd", "csrc", f)
+              for f in ("qs_kernels.hip", "qs_device.h")]
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def profiled_traffic():
     """HBM bytes per phase-kernel launch from the committed rocprofv3 byte
     counters, or None when the kernel source changed since they were taken."""
-    import hashlib
     try:
         kv = {}
         for line in open(PROFILE):
             parts = line.split()
             if len(parts) == 2:
                 kv[parts[0]] = parts[1]
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
+        if kv.get("kernel_source_sha256") != kernel_source_sha256():
             return None
         return float(kv["phase_kernel_traffic_bytes"])
     except (OSError, KeyError, ValueError):
@@ -67,6 +75,9 @@ def parse():
                     help="timed launches of the 4096-shot batch (0 skips that leg)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="timed forward+adjoint steps on the differentiation workload (0: skip)")
+    ap.add_argument("--quantum-batch-steps", type=int, default=1,
+                    help="timed steps of the quantum batch with gradients and photon spectra "
+                         "(0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -160,6 +171,67 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
             "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
 
+def quantum_batch_leg(ctx, workloads, torch, steps):
+    """256 shots of 2^18 samples x 2048 steps, quantum (FP64 steps where
+    chi > 0.1): per step the electron spectra, the derivative tape and per-shot
+    gradients of a Neyman chi^2 loss against per-shot Poisson targets, and the
+    photon spectra -- all shots in one launch per stage."""
+    shots = workloads.quantum_batch()
+    total = sum(p["n_samples"] for p in shots)
+    N = shots[0]["n_steps"]
+    batch = ctx.prepare_batch(shots)
+    tape = ctx.new_tape(total)
+    n_tot = 1e6
+    ref = ctx.run_batch(batch)
+    rng = np.random.Generator(np.random.PCG64(5))
+    targets = [torch.tensor(rng.poisson(n_tot * o["energy_hist"].cpu().numpy() / p["n_samples"])
+                            .astype(np.float64), device="cuda") for o, p in zip(ref, shots)]
+    parts = {}
+
+    def step():
+        t = [time.perf_counter()]
+        outs = ctx.run_batch(batch, check=False)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        tout = ctx.run_batch(batch, check=False, tape=tape)
+        ws = []
+        for o, p, tg in zip(tout, shots, targets):
+            r = n_tot * o["energy_hist"] / p["n_samples"] - tg
+            ws.append(2.0 * r / torch.clamp(tg, min=1.0) * (n_tot / p["n_samples"]))
+        grads = ctx.backward_batched(shots, ws, check=False, tape=tape)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        phot = ctx.photons_batched(shots, check=False)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        for k, name in enumerate(("spectra", "gradients", "photons")):
+            parts[name] = parts.get(name, 0.0) + t[k + 1] - t[k]
+        return outs, grads, phot
+
+    step()  # warm-up
+    parts.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs, grads, phot = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    bad = int(torch.stack([o["status"] for o in outs] + [o["status"] for o in phot]).max().item())
+    if bad != 0:
+        raise RuntimeError(f"device status {bad} in the quantum batch leg")
+    g = torch.stack(grads).cpu().numpy()
+    if not np.all(np.isfinite(g)):
+        raise RuntimeError("non-finite gradient in the quantum batch leg")
+    return {"workload": "256 shots: gamma0 N(2e4, 600^2), a0 U[50,150], W0 2um, no offsets, "
+                        "2^18 samples x 2048 steps, quantum with FP64 steps where chi > 0.1, "
+                        "local amplitude; electron spectra, per-shot gradients (tape), "
+                        "256-bin photon spectra",
+            "n_shots": len(shots), "n_samples": total, "n_steps": N, "steps": steps,
+            "ms_per_step": 1e3 * dt,
+            "ms_parts": {k: 1e3 * v / steps for k, v in parts.items()},
+            "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -244,6 +316,8 @@ def main():
             "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt}
     if args.adjoint_steps > 0:
         line["adjoint"] = adjoint_leg(ctx, qs, workloads, torch, args.adjoint_steps)
+    if args.quantum_batch_steps > 0:
+        line["quantum_batch"] = quantum_batch_leg(ctx, workloads, torch, args.quantum_batch_steps)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)

@@ -1,0 +1,880 @@
+// qs_adjoint.hip -- derivatives of the energy histogram with respect to the
+// eight shot parameters: the tangent kernel (adjoint, or forward pass with a
+// derivative tape), the tape contraction and the per-shot reduction.
+#include "qs_device.h"
+
+namespace qs {
+
+// ===========================================================================
+// Adjoint: derivatives of a weighted sum of the energy histogram,
+//   L = sum_k w_k H_k   (w = dL/dH from the caller),
+// with respect to the eight shot parameters (a0, W0, x and y offsets, delay,
+// gamma0, sigma_gamma, divergence).  Every sample's trajectory is integrated
+// again together with its tangents: forward-mode derivatives of the discrete
+// RK4 map itself, so no trajectory is stored.  The final tangents are
+// contracted with the sample's sensitivities dL/dmu_f and dL/dsig2_f, taken
+// from its deposited law; the sums over samples are reduced per work item and
+// per shot in a fixed order.
+//
+// Tangent directions.  The sample state depends on the parameters through
+// the amplitude a(psi) = a0 S(x_e, y_e, z_e) f(psi) cos psi along the path
+// (Sec. 2, eq. a0eff) and through the initial energy.  gamma0 and
+// sigma_gamma only enter the initial energy (mu_0 = gamma0 + sigma_gamma n3),
+// so the sigma_gamma tangent is n3 times the gamma0 tangent.  With the
+// amplitude frozen at a0,eff every amplitude direction forces the system
+// with a multiple of S0 f cos psi, so one tangent serves a0 and the four
+// geometric parameters.
+// ===========================================================================
+// Radiation functions in the combinations the Jacobian uses:
+//   g,  E1 = 2g + G1,  E2 = 2g + 4 G1 + G2,  E3 = 6 G1 + 6 G2 + G3,  h,  H1
+// (G1 = chi g', G2 = chi^2 g'', G3 = chi^3 g''', H1 = chi h').  The FP32
+// derivative table stores these combinations; the FP64 one the plain
+// functions.
+template <class T>
+struct RadJ {
+    T g, E1, E2, E3, h, H1;
+};
+
+// One FP32 derivative-table cell in registers (see RadCell32).
+struct RadCell6 {
+    float4 q[kDerivFuncs];
+    float tw, ts;
+};
+
+__device__ __forceinline__ void rad6_lookup32(const float *__restrict__ tab, float chi,
+                                              RadCell6 &cell) {
+    const uint32_t b = __float_as_uint(chi);
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
+        c = 0;
+        tw = 0x1p20f;
+        ts = 0.0f;
+    }
+    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
+        c = kCells32 - 1;
+        tw = 0.0f;
+        ts = 1.0f;
+    }
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f) cell.q[f] = T[f * kCells32 + c];
+    cell.tw = tw;
+    cell.ts = ts;
+}
+
+__device__ __forceinline__ RadJ<float> rad6_cell_eval(const RadCell6 &cell, float chi) {
+    const float t = fmaf(chi, cell.tw, cell.ts);
+    float v[kDerivFuncs];
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f) {
+        const float4 &q = cell.q[f];
+        v[f] = fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+    }
+    return RadJ<float>{v[0], v[1], v[2], v[3], v[4], v[5]};
+}
+
+// FP64 table, cell-major [cell][g, G1, G2, h, G3, H1][power]: the plain
+// functions, combined here.
+__device__ __forceinline__ void rad6_plain64(const double *__restrict__ tab, double chi,
+                                             double v[kDerivFuncs]) {
+    const uint64_t b = (uint64_t)__double_as_longlong(chi);
+    int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
+    double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
+                                                0x3ff0000000000000ull)) - 1.0;
+    if (c < 1) {
+        c = 0;
+        t = chi * 0x1p20;
+    }
+    c = c < kCells64 - 1 ? c : kCells64 - 1;
+    const double *q = tab + (size_t)c * (4 * kDerivFuncs);
+#pragma unroll
+    for (int f = 0; f < kDerivFuncs; ++f)
+        v[f] = fma(t, fma(t, fma(t, q[4 * f + 3], q[4 * f + 2]), q[4 * f + 1]), q[4 * f]);
+}
+
+__device__ __forceinline__ RadJ<double> radj_eval64(const double *__restrict__ tab, double chi) {
+    double v[kDerivFuncs];
+    rad6_plain64(tab, chi, v);
+    const double g = v[0], G1 = v[1], G2 = v[2], h = v[3], G3 = v[4], H1 = v[5];
+    return RadJ<double>{g, fma(2.0, g, G1), fma(4.0, G1, fma(2.0, g, G2)), fma(6.0, G1 + G2, G3),
+                        h, H1};
+}
+
+// Where a stage takes its radiation functions from.  FP32: the LDS table,
+// read at stages 2 and 4 only -- stage 3 reuses stage 2's cell and the next
+// step's stage 1 reuses stage 4's (as in the forward phase loop).  FP64: the
+// global table at every stage.
+template <class T>
+struct RadSrc;
+template <>
+struct RadSrc<float> {
+    const float *tab;
+    RadCell6 carry, mid;
+    __device__ __forceinline__ void init(float chi) { rad6_lookup32(tab, chi, carry); }
+    __device__ __forceinline__ RadJ<float> s1(float chi) { return rad6_cell_eval(carry, chi); }
+    __device__ __forceinline__ RadJ<float> s2(float chi) {
+        rad6_lookup32(tab, chi, mid);
+        return rad6_cell_eval(mid, chi);
+    }
+    __device__ __forceinline__ RadJ<float> s3(float chi) { return rad6_cell_eval(mid, chi); }
+    __device__ __forceinline__ RadJ<float> s4(float chi) {
+        rad6_lookup32(tab, chi, carry);
+        return rad6_cell_eval(carry, chi);
+    }
+};
+template <>
+struct RadSrc<double> {
+    const double *tab;
+    __device__ __forceinline__ void init(double) {}
+    __device__ __forceinline__ RadJ<double> s1(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s2(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s3(double chi) { return radj_eval64(tab, chi); }
+    __device__ __forceinline__ RadJ<double> s4(double chi) { return radj_eval64(tab, chi); }
+};
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Right-hand side f = (dmu/dpsi, dsig2/dpsi) of the moment system and its
+// partial derivatives with respect to mu, sig2 and the amplitude a.  With
+// chi d/dchi written D (D g = G1, D G1 = G1 + G2, D G2 = 2 G2 + G3,
+// D h = H1) and u = K a^2:
+//   f_mu  = -u (mu^2 g + sig2 E2 / 2),      f_s2 = -2 u mu sig2 E1 + C_D |a|^3 mu^4 h,
+//   d f_mu / d mu   = -u (mu E1 + sig2 E3 / (2 mu)),
+//   d f_mu / d sig2 = -u E2 / 2,
+//   d f_s2 / d mu   = -2 u sig2 E2 + C_D |a|^3 mu^3 (4 h + H1),
+//   d f_s2 / d sig2 = -2 u mu E1,
+//   d f_mu / d a    = -K a (mu^2 E1 + sig2 (E2 + E3 / 2)),
+//   d f_s2 / d a    = -2 K a mu sig2 (E1 + E2) + C_D a |a| mu^4 (3 h + H1).
+// Classical model (g = 1, no diffusion; sig2 stays 0): f_mu = -u mu^2.
+template <class T>
+struct Jac {
+    T fm, fs;  // f
+    T mm, ms, sm, ss;  // d f / d (mu, sig2)
+    T ma, sa;  // d f / d a
+};
+
+// Per-stage amplitude constants: a, K a, C_D a |a|, 2 |a| / a_S.
+template <class T>
+struct StageAmp {
+    T a, Ka, cda, chi_per_mu;
+    __device__ __forceinline__ StageAmp(T a_, const Phys<T> &ph)
+        : a(a_), Ka(ph.K * a_), cda(ph.CD * a_ * fabs(a_)), chi_per_mu(ph.two_over_aS * fabs(a_)) {}
+};
+
+template <class T>
+__device__ __forceinline__ Jac<T> jac_quantum(T mu, T s2, const StageAmp<T> &A, const RadJ<T> &r) {
+    Jac<T> J;
+    const T u = A.Ka * A.a;
+    const T mu2 = mu * mu;
+    const T hs = T(0.5) * s2;
+    const T c3 = A.cda * mu2;        // C_D a |a| mu^2
+    const T c3a = c3 * mu * A.a;     // C_D |a|^3 mu^3
+    const T u2 = T(-2) * u;
+    J.fm = -u * fma(mu2, r.g, hs * r.E2);
+    J.fs = fma(u2 * mu * s2, r.E1, c3a * mu * r.h);
+    J.mm = -u * fma(mu, r.E1, hs * r.E3 * recip(mu));
+    J.ms = T(-0.5) * u * r.E2;
+    J.sm = fma(u2 * s2, r.E2, c3a * fma(T(4), r.h, r.H1));
+    J.ss = u2 * mu * r.E1;
+    J.ma = -A.Ka * fma(mu2, r.E1, s2 * fma(T(0.5), r.E3, r.E2));
+    J.sa = fma(T(-2) * A.Ka * mu * s2, r.E1 + r.E2, c3 * mu2 * fma(T(3), r.h, r.H1));
+    return J;
+}
+
+template <class T>
+__device__ __forceinline__ Jac<T> jac_classical(T mu, const StageAmp<T> &A) {
+    Jac<T> J;
+    const T u = A.Ka * A.a;
+    J.fm = -u * mu * mu;
+    J.mm = T(-2) * u * mu;
+    J.ma = T(-2) * A.Ka * mu * mu;
+    J.fs = J.ms = J.sm = J.ss = J.sa = T(0);
+    return J;
+}
+
+// 2x2 matrices [[a, b], [c, d]] and 2-vectors acting on (mu, sig2); in the
+// classical model only the mu entries are used.
+template <class T>
+struct Mat2 {
+    T a, b, c, d;
+};
+template <class T>
+struct Vec2 {
+    T x, y;
+};
+
+// K (I + s M) = K + s K M
+template <class T, bool Q>
+__device__ __forceinline__ Mat2<T> kism(const Jac<T> &K, T s, const Mat2<T> &M) {
+    Mat2<T> R;
+    if (Q) {
+        R.a = fma(s, fma(K.mm, M.a, K.ms * M.c), K.mm);
+        R.b = fma(s, fma(K.mm, M.b, K.ms * M.d), K.ms);
+        R.c = fma(s, fma(K.sm, M.a, K.ss * M.c), K.sm);
+        R.d = fma(s, fma(K.sm, M.b, K.ss * M.d), K.ss);
+    } else {
+        R.a = fma(s, K.mm * M.a, K.mm);
+        R.b = R.c = R.d = T(0);
+    }
+    return R;
+}
+
+// s K v
+template <class T, bool Q>
+__device__ __forceinline__ Vec2<T> skv(const Jac<T> &K, T s, const Vec2<T> &v) {
+    Vec2<T> r;
+    if (Q) {
+        r.x = s * fma(K.mm, v.x, K.ms * v.y);
+        r.y = s * fma(K.sm, v.x, K.ss * v.y);
+    } else {
+        r.x = s * K.mm * v.x;
+        r.y = T(0);
+    }
+    return r;
+}
+
+// One RK4 step of (mu, sig2), linearised.  The tangent of any direction obeys
+//   dk1 = K1 V + g1 d1,            dk2 = K2 (V + h/2 dk1) + g2 dh,
+//   dk3 = K3 (V + h/2 dk2) + g3 dh, dk4 = K4 (V + h dk3) + g4 d4,
+//   V' = V + h/6 (dk1 + 2 dk2 + 2 dk3 + dk4),
+// with K_s = d f / d(mu, sig2) and g_s = d f / d a at stage s, and d1, dh, d4
+// the direction's amplitude derivatives at psi_j, psi_j + h/2, psi_j + h.
+// That map is linear, V' = A V + P1 d1 + Ph dh + P4 d4, and A, P1, Ph, P4 are
+// shared by all directions, so they are formed once per step.
+template <class T, bool Q>
+struct StepLin {
+    Mat2<T> A;
+    Vec2<T> P1, Ph, P4;
+    T dmu, ds2;  // the state increment
+};
+
+template <class T, bool Q>
+__device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T> &A1,
+                                                    const StageAmp<T> &Ah, const StageAmp<T> &A4,
+                                                    T h, RadSrc<T> &rad, T &chi_hi) {
+    const T hh = T(0.5) * h, h6 = h * T(1.0 / 6.0);
+    StepLin<T, Q> L;
+    // stage 1
+    Jac<T> K1;
+    if (Q) {
+        const T chi = A1.chi_per_mu * mu;
+        chi_hi = fmax(chi_hi, chi);
+        K1 = jac_quantum(mu, s2, A1, rad.s1(chi));
+    } else {
+        K1 = jac_classical(mu, A1);
+    }
+    const Vec2<T> g1{K1.ma, K1.sa};
+    // stage 2
+    const T m2 = fma(hh, K1.fm, mu), s22 = fma(hh, K1.fs, s2);
+    Jac<T> K2;
+    if (Q) {
+        const T chi = Ah.chi_per_mu * m2;
+        chi_hi = fmax(chi_hi, chi);
+        K2 = jac_quantum(m2, s22, Ah, rad.s2(chi));
+    } else {
+        K2 = jac_classical(m2, Ah);
+    }
+    const Mat2<T> M1{K1.mm, K1.ms, K1.sm, K1.ss};
+    const Mat2<T> M2 = kism<T, Q>(K2, hh, M1);
+    const Vec2<T> e21 = skv<T, Q>(K2, hh, g1);
+    const Vec2<T> g2{K2.ma, K2.sa};
+    // stage 3
+    const T m3 = fma(hh, K2.fm, mu), s23 = fma(hh, K2.fs, s2);
+    Jac<T> K3;
+    if (Q) {
+        const T chi = Ah.chi_per_mu * m3;
+        chi_hi = fmax(chi_hi, chi);
+        K3 = jac_quantum(m3, s23, Ah, rad.s3(chi));
+    } else {
+        K3 = jac_classical(m3, Ah);
+    }
+    const Mat2<T> M3 = kism<T, Q>(K3, hh, M2);
+    const Vec2<T> e31 = skv<T, Q>(K3, hh, e21);
+    Vec2<T> e3h = skv<T, Q>(K3, hh, g2);
+    e3h.x += K3.ma;
+    e3h.y += K3.sa;
+    // stage 4
+    const T m4 = fma(h, K3.fm, mu), s24 = fma(h, K3.fs, s2);
+    Jac<T> K4;
+    if (Q) {
+        const T chi = A4.chi_per_mu * m4;
+        chi_hi = fmax(chi_hi, chi);
+        K4 = jac_quantum(m4, s24, A4, rad.s4(chi));
+    } else {
+        K4 = jac_classical(m4, A4);
+    }
+    const Mat2<T> M4 = kism<T, Q>(K4, h, M3);
+    const Vec2<T> e41 = skv<T, Q>(K4, h, e31);
+    const Vec2<T> e4h = skv<T, Q>(K4, h, e3h);
+    // assemble
+    L.A.a = fma(h6, M1.a + T(2) * (M2.a + M3.a) + M4.a, T(1));
+    L.A.b = h6 * (M1.b + T(2) * (M2.b + M3.b) + M4.b);
+    L.A.c = h6 * (M1.c + T(2) * (M2.c + M3.c) + M4.c);
+    L.A.d = fma(h6, M1.d + T(2) * (M2.d + M3.d) + M4.d, T(1));
+    L.P1.x = h6 * (g1.x + T(2) * (e21.x + e31.x) + e41.x);
+    L.P1.y = h6 * (g1.y + T(2) * (e21.y + e31.y) + e41.y);
+    L.Ph.x = h6 * (T(2) * (g2.x + e3h.x) + e4h.x);
+    L.Ph.y = h6 * (T(2) * (g2.y + e3h.y) + e4h.y);
+    L.P4.x = h6 * K4.ma;
+    L.P4.y = h6 * K4.sa;
+    L.dmu = h6 * (K1.fm + T(2) * (K2.fm + K3.fm) + K4.fm);
+    L.ds2 = h6 * (K1.fs + T(2) * (K2.fs + K3.fs) + K4.fs);
+    return L;
+}
+
+// Spatial factor of eq. a0eff and its logarithmic derivatives with respect to
+// the sample position (x, y, z) and the spot size W0:
+//   ln S = -p - ln(q)/2,  p = (x^2 + y^2) / (W0^2 q),  q = 1 + (z / zR)^2,
+//   d/dx = -2 x / (W0^2 q),  d/dz = 2 (z / zR^2) (p - 1/2) / q,
+//   d/dW0 = (2 / W0) (p - 2 (z/zR)^2 (p - 1/2) / q)   (zR = pi W0^2 / lambda).
+template <class T>
+struct SpD {
+    T S, Lx, Ly, Lz, Lw;
+};
+
+__device__ __forceinline__ SpD<float> spatial_d(float x, float y, float z, float inv_w0sq,
+                                                float inv_zR, float inv_w0) {
+    const float zz = z * inv_zR;
+    const float q = fmaf(zz, zz, 1.0f);
+    const float rq = __builtin_amdgcn_rsqf(q);
+    const float iq = rq * rq;
+    const float p = fmaf(x, x, y * y) * inv_w0sq * iq;
+    SpD<float> r;
+    r.S = __builtin_amdgcn_exp2f(-1.4426950408889634f * p) * rq;
+    const float m = -2.0f * inv_w0sq * iq;
+    r.Lx = m * x;
+    r.Ly = m * y;
+    const float B = iq * (p - 0.5f);
+    r.Lz = 2.0f * zz * inv_zR * B;
+    r.Lw = 2.0f * inv_w0 * fmaf(-2.0f * zz * zz, B, p);
+    return r;
+}
+
+__device__ __forceinline__ SpD<double> spatial_d(double x, double y, double z, double inv_w0sq,
+                                                 double inv_zR, double inv_w0) {
+    const double zz = z * inv_zR;
+    const double q = fma(zz, zz, 1.0);
+    const double iq = 1.0 / q;
+    const double p = fma(x, x, y * y) * inv_w0sq * iq;
+    SpD<double> r;
+    r.S = exp(-p) * sqrt(iq);
+    const double m = -2.0 * inv_w0sq * iq;
+    r.Lx = m * x;
+    r.Ly = m * y;
+    const double B = iq * (p - 0.5);
+    r.Lz = 2.0 * zz * inv_zR * B;
+    r.Lw = 2.0 * inv_w0 * fma(-2.0 * zz * zz, B, p);
+    return r;
+}
+
+// Directions of the local-amplitude tangents: a0, W0, x offset, y offset,
+// delay, gamma0, divergence.
+constexpr int kDirLocal = 7;
+constexpr int kDirA0eff = 2;  // a0 (all amplitude directions), gamma0
+
+// Geometry of one sample in the adjoint's precision.
+template <class T>
+struct AdjPath {
+    T xc, yc, thx, thy, zstar, hz;     // hz = z / 2
+    T dthx, dthy;                      // d theta / d div_mrad = 1e-3 n4, 1e-3 n5
+    T inv_w0sq, inv_zR, inv_w0, a0, zfac;  // zfac = d z* / d delay = c / 2
+    // amplitude without the carrier and its derivative in each direction
+    __device__ __forceinline__ void amp(T ell, T fc, T &a, T *da) const {
+        const SpD<T> d = spatial_d(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell, inv_w0sq,
+                                   inv_zR, inv_w0);
+        const T Sf = d.S * fc;
+        a = a0 * Sf;
+        da[0] = Sf;
+        da[1] = a * d.Lw;
+        da[2] = a * d.Lx;
+        da[3] = a * d.Ly;
+        da[4] = a * zfac * d.Lz;
+        da[5] = T(0);
+        da[6] = a * (hz + ell) * fma(dthx, d.Lx, dthy * d.Ly);
+    }
+};
+
+// Sensitivities of one sample's share of L = sum_k w_k H_k to the centre v
+// and the variance sig2 of its energy law.  Writing F for the law's CDF and
+// e_j = lo + j width (j = 0..n) for the bin edges, the sample adds F(e_0) to
+// the underflow, F(e_{k+1}) - F(e_k) to bin k and 1 - F(e_n) to the overflow,
+// so its share is sum_j c_j F(e_j) + w_over with c_j = w_{j-1} - w_j
+// (w_{-1} = w_under, w_n = w_over).  For the three laws (with t = e_j - v):
+//   Gaussian N(v, s^2):  dF/dv = -phi(t/s)/s,          dF/ds = -(t/s) phi(t/s)/s;
+//   box of width b:      dF/dv = -1/b for |t| < b/2,   no s;
+//   box (x) N(0, s^2):   dF/dv = -(Phi((t + b/2)/s) - Phi((t - b/2)/s)) / b,
+//                        dF/ds = (phi((t + b/2)/s) - phi((t - b/2)/s)) / b.
+// Edges beyond 9 standard deviations add nothing at FP64 precision.
+__device__ __forceinline__ double phi_pdf(double z) {
+    return 0.39894228040143267794 * exp(-0.5 * z * z);
+}
+
+__device__ __forceinline__ double phi_diff(double zp, double zm) {  // Phi(zp) - Phi(zm), zp > zm
+    const double r = 0.70710678118654752440;
+    if (zm > 0.0) return 0.5 * (erfc(zm * r) - erfc(zp * r));
+    if (zp < 0.0) return 0.5 * (erfc(-zp * r) - erfc(-zm * r));
+    return 1.0 - 0.5 * (erfc(zp * r) + erfc(-zm * r));
+}
+
+__device__ void law_sensitivity(double v, double s2, int dep, double ksig, double lo, double wb,
+                                int n, const double *__restrict__ W, double &lv, double &ls2) {
+    lv = 0.0;
+    ls2 = 0.0;
+    const double s = sqrt(fmax(s2, 0.0));
+    const double half = 0.5 * wb;
+    int mode;
+    double se = s, dse = 0.0;  // law width and d se / d sig2
+    if (dep == 2) {            // GAUSS
+        const double ks = ksig * wb;
+        se = sqrt(s * s + ks * ks);
+        mode = se > 0.0 ? 2 : 0;
+        if (s2 > 0.0) dse = 0.5 / se;
+    } else if (dep == 1) {  // CIC
+        mode = s > 0.0 ? 3 : 1;
+        if (s > 0.0) dse = 0.5 / s;
+    } else {
+        mode = s > 0.0 ? 2 : 0;
+        if (s > 0.0) dse = 0.5 / s;
+    }
+    if (mode == 0) return;
+    const double reach = mode == 1 ? half : (mode == 2 ? 9.0 * se : 9.0 * se + half);
+    const int ja = (int)fmin(fmax(ceil((v - reach - lo) / wb), 0.0), (double)n + 1.0);
+    const int jb = (int)fmin(fmax(floor((v + reach - lo) / wb), -1.0), (double)n);
+    const double inv_se = mode >= 2 ? 1.0 / se : 0.0;
+    double sv = 0.0, ss = 0.0;
+    for (int j = ja; j <= jb; ++j) {
+        const double wl = j == 0 ? W[n] : W[j - 1];
+        const double wr = j == n ? W[n + 1] : W[j];
+        const double c = wl - wr;
+        if (c == 0.0) continue;
+        const double t = fma((double)j, wb, lo) - v;
+        double p, q = 0.0;
+        if (mode == 1) {
+            p = fabs(t) < half ? 1.0 / wb : 0.0;
+        } else if (mode == 2) {
+            const double z = t * inv_se;
+            const double f = phi_pdf(z) * inv_se;
+            p = f;
+            q = -z * f;
+        } else {
+            const double zp = (t + half) * inv_se, zm = (t - half) * inv_se;
+            p = phi_diff(zp, zm) / wb;
+            q = (phi_pdf(zp) - phi_pdf(zm)) / wb;
+        }
+        sv = fma(c, p, sv);
+        ss = fma(c, q, ss);
+    }
+    lv = -sv;
+    ls2 = ss * dse;
+}
+
+// Final state of one sample and its derivatives along the eight parameters
+// (order of the grad outputs: a0, W0, x offset, y offset, delay, gamma0,
+// sigma_gamma, divergence).
+struct SampleTangent {
+    double mu, s2;
+    double dmu[kGradParams], ds2[kGradParams];
+    double S0, g0, thx, thy;
+    float cmx;
+};
+
+// One sample: trajectory, tangents, and the chain to the eight parameters.
+template <int PREC, bool QUANTUM, bool LOCAL>
+__device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotParams &sp,
+                                               int64_t i, const float *__restrict__ env32,
+                                               const double *__restrict__ env64,
+                                               const float *tab32, SampleTangent &o,
+                                               int &flags) {
+    using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    constexpr int ND = LOCAL ? kDirLocal : kDirA0eff;
+    constexpr int GD = LOCAL ? 5 : 1;  // the gamma0 direction: no amplitude forcing
+    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
+    const int N = P.n_steps;
+    RadSrc<T> rad;
+    if constexpr (PREC == PREC_F64)
+        rad.tab = P.rad64d;
+    else
+        rad.tab = tab32;
+    const T *env;
+    if constexpr (PREC == PREC_F64)
+        env = env64;
+    else
+        env = env32;
+    Phys<T> ph;
+    ph.K = (T)P.K;
+    ph.CD = (T)P.CD;
+    ph.two_over_aS = (T)P.two_over_aS;
+    const float chi_top = (float)(1 << (kEMax + 1));
+
+    // ---- sample and geometry (FP64) ----
+    double nrm[6];
+    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
+    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
+    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
+    const double z = sp.sigma_z * nrm[2];
+    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
+    const double thx = sp.div_rad * nrm[4];
+    const double thy = sp.div_rad * nrm[5];
+    const double inv_w0 = sqrt(sp.inv_w0sq);
+    const double xc = fma(thx, 0.5 * z, x), yc = fma(thy, 0.5 * z, y);
+    const double zstar = fma(0.5, z, sp.z_delay);
+    const SpD<double> d0 = spatial_d(xc, yc, zstar, sp.inv_w0sq, sp.inv_zR, inv_w0);
+
+    AdjPath<T> pth;
+    pth.xc = (T)xc;
+    pth.yc = (T)yc;
+    pth.thx = (T)thx;
+    pth.thy = (T)thy;
+    pth.zstar = (T)zstar;
+    pth.hz = (T)(0.5 * z);
+    pth.dthx = (T)(1e-3 * nrm[4]);
+    pth.dthy = (T)(1e-3 * nrm[5]);
+    pth.inv_w0sq = (T)sp.inv_w0sq;
+    pth.inv_zR = (T)sp.inv_zR;
+    pth.inv_w0 = (T)inv_w0;
+    pth.a0 = (T)sp.a0;
+    pth.zfac = (T)kHalfC;
+    const T S0 = (T)d0.S;
+    const T ell_per_psi = (T)P.ell_per_psi;
+    const T h = (T)P.h;
+    const T psi0 = (T)(-P.psi_max);
+
+    T vm[ND], vs[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) vm[d] = vs[d] = T(0);
+    vm[GD] = T(1);  // d mu_0 / d gamma0
+
+    T mu = (T)g0, mu_lo = T(0), s2 = T(0), s2_lo = T(0);
+    double g0_rest = 0.0;
+    if constexpr (PREC != PREC_F64) {
+        mu_lo = (T)(g0 - (double)mu);
+        g0_rest = (g0 - (double)mu) - (double)mu_lo;
+    }
+    T chi_hi = T(0);
+    float cmx = 0.0f;  // largest chi at a step start
+    T a1, da1[ND];
+    if (LOCAL) {
+        pth.amp(psi0 * ell_per_psi, env[0], a1, da1);
+    } else {
+        const T Sf = S0 * env[0];
+        a1 = pth.a0 * Sf;
+        da1[0] = Sf;
+        da1[1] = T(0);
+    }
+    StageAmp<T> A1(a1, ph);
+    if (QUANTUM) rad.init(A1.chi_per_mu * mu);
+    for (int j = 0; j < N; ++j) {
+        const T psi = fma((T)j, h, psi0);
+        cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));
+        T ah, a4, dah[ND], da4[ND];
+        if (LOCAL) {
+            pth.amp(fma(T(0.5), h, psi) * ell_per_psi, env[2 * j + 1], ah, dah);
+            pth.amp((psi + h) * ell_per_psi, env[2 * j + 2], a4, da4);
+        } else {
+            const T Sh = S0 * env[2 * j + 1], S4 = S0 * env[2 * j + 2];
+            ah = pth.a0 * Sh;
+            a4 = pth.a0 * S4;
+            dah[0] = Sh;
+            da4[0] = S4;
+            dah[1] = da4[1] = T(0);
+        }
+        const StageAmp<T> Ah(ah, ph), A4(a4, ph);
+        const StepLin<T, QUANTUM> L = rk4_linear<T, QUANTUM>(mu, s2, A1, Ah, A4, h, rad, chi_hi);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            T fm = T(0), fs = T(0);
+            if (d != GD) {
+                fm = fma(L.P1.x, da1[d], fma(L.Ph.x, dah[d], L.P4.x * da4[d]));
+                fs = fma(L.P1.y, da1[d], fma(L.Ph.y, dah[d], L.P4.y * da4[d]));
+            }
+            const T m0 = vm[d];
+            if (QUANTUM) {
+                const T s0 = vs[d];
+                vm[d] = fma(L.A.a, m0, fma(L.A.b, s0, fm));
+                vs[d] = fma(L.A.c, m0, fma(L.A.d, s0, fs));
+            } else {
+                vm[d] = fma(L.A.a, m0, fm);
+            }
+        }
+        if constexpr (PREC == PREC_F64) {
+            mu += L.dmu;
+            s2 += L.ds2;
+        } else {
+            comp_add(mu, mu_lo, L.dmu);
+            comp_add(s2, s2_lo, L.ds2);
+        }
+        A1 = A4;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) da1[d] = da4[d];
+    }
+    o.mu = ((double)mu + (double)mu_lo) + g0_rest;
+    o.s2 = (double)s2 + (double)s2_lo;
+    o.cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));  // the end of the last step
+    o.S0 = d0.S;
+    o.g0 = g0;
+    o.thx = thx;
+    o.thy = thy;
+    if (QUANTUM && !((float)chi_hi < chi_top)) flags |= kFlagRange;
+    if (!(o.mu > 0.0) || !isfinite(o.mu) || !isfinite(o.s2)) flags |= kFlagNonFinite;
+
+    // ---- chain to the eight parameters ----
+    const double dthx_dd = 1e-3 * nrm[4], dthy_dd = 1e-3 * nrm[5];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T *v = c == 0 ? vm : vs;
+        double *d = c == 0 ? o.dmu : o.ds2;
+        if (c == 1 && !QUANTUM) {
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) d[p] = 0.0;
+            continue;
+        }
+        if (LOCAL) {
+            d[0] = v[0];
+            d[1] = v[1];
+            d[2] = v[2];
+            d[3] = v[3];
+            d[4] = v[4];
+            d[5] = v[5];
+            d[6] = nrm[3] * (double)v[5];
+            d[7] = v[6];
+        } else {
+            // every amplitude direction is a multiple of the a0 tangent
+            const double b = sp.a0 * (double)v[0];
+            d[0] = v[0];
+            d[1] = b * d0.Lw;
+            d[2] = b * d0.Lx;
+            d[3] = b * d0.Ly;
+            d[4] = b * kHalfC * d0.Lz;
+            d[5] = v[1];
+            d[6] = nrm[3] * (double)v[1];
+            d[7] = b * (0.5 * z) * fma(dthx_dd, d0.Lx, dthy_dd * d0.Ly);
+        }
+    }
+}
+
+// Fixed-order reduction of the block's eight sums into the item's partials.
+__device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t item,
+                                                 const double *g, double (*red)[kGradParams]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < kGradParams; ++p) {
+        const double v = wave_sum(g[p]);
+        if (lane == 0) red[wid][p] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGradParams) {
+        double sum = 0.0;
+        for (int w = 0; w < kPhaseBlock / 64; ++w) sum += red[w][threadIdx.x];
+        P.partials[(size_t)item * kGradParams + threadIdx.x] = sum;
+    }
+    // red is rewritten only after the next item's barriers
+}
+
+// TAPE = false: the adjoint -- each sample's derivatives contracted at once
+// with its law sensitivities, summed per item.  TAPE = true: the forward pass
+// that also records the derivatives: final states for the deposit kernel and
+// the tape (mu, sig2 and their eight derivatives, structure of arrays).
+template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
+__global__ __launch_bounds__(kPhaseBlock) void tangent_kernel(BatchParams P,
+                                                              const float *__restrict__ env32,
+                                                              const double *__restrict__ env64) {
+    constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    __shared__ __align__(16) float tab32[kTab32 ? kCells32 * 4 * kDerivFuncs : 4];
+    __shared__ int64_t slot;
+    __shared__ double red[kPhaseBlock / 64][kGradParams];
+    if (kTab32) {
+        const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
+        float4 *dst = reinterpret_cast<float4 *>(tab32);
+        for (int k = threadIdx.x; k < kCells32 * kDerivFuncs; k += blockDim.x) dst[k] = src[k];
+        __syncthreads();
+    }
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_items) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sp = P.shots[s];
+        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        double g[kGradParams];
+#pragma unroll
+        for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
+        if (i < sp.n_samples) {
+            int flags = 0;
+            SampleTangent o;
+            tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, o, flags);
+            if (TAPE) {
+                const int64_t k = sp.state_off + i;
+                P.st.mu[k] = o.mu;
+                P.st.s2[k] = o.s2;
+                P.st.S0[k] = o.S0;
+                P.st.g0[k] = o.g0;
+                P.st.thx[k] = o.thx;
+                P.st.thy[k] = o.thy;
+                P.st.cmx[k] = o.cmx;
+                double *t = P.tape + k;
+                const int64_t n = P.tape_n;
+                t[0] = o.mu;
+                t[n] = o.s2;
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) {
+                    t[(2 + p) * n] = o.dmu[p];
+                    t[(2 + kGradParams + p) * n] = o.ds2[p];
+                }
+            } else if (!(flags & kFlagNonFinite)) {
+                double lv, ls;
+                law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                P.gouts[s].d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
+            }
+            if (flags) atomicOr(&P.flags[s], flags);
+        }
+        if (!TAPE) grad_item_reduce(P, item, g, red);
+    }
+}
+
+// The adjoint from a tape: contraction of the recorded derivatives with the
+// law sensitivities (memory-bound: 144 bytes a sample).
+__global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
+    __shared__ int64_t slot;
+    __shared__ double red[kPhaseBlock / 64][kGradParams];
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_items) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sp = P.shots[s];
+        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        double g[kGradParams];
+#pragma unroll
+        for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
+        if (i < sp.n_samples) {
+            const int64_t n = P.tape_n;
+            const double *t = P.tape + sp.state_off + i;
+            const double mu = t[0], s2 = t[n];
+            if (mu > 0.0 && isfinite(mu) && isfinite(s2)) {
+                double lv, ls;
+                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                P.gouts[s].d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p)
+                    g[p] = fma(lv, t[(2 + p) * n], ls * t[(2 + kGradParams + p) * n]);
+            } else {
+                atomicOr(&P.flags[s], kFlagNonFinite);
+            }
+        }
+        grad_item_reduce(P, item, g, red);
+    }
+}
+
+// One block per shot: fixed-order sum of the shot's item partials.
+__global__ __launch_bounds__(256) void grad_finalize_kernel(BatchParams P) {
+    const int s = blockIdx.x;
+    const ShotParams &sp = P.shots[s];
+    const ShotGrad &so = P.gouts[s];
+    const int64_t ni = (sp.n_samples + kPhaseBlock - 1) / kPhaseBlock;
+    __shared__ double tree[256];
+    for (int p = 0; p < kGradParams; ++p) {
+        double acc = 0.0;
+        for (int64_t b = threadIdx.x; b < ni; b += blockDim.x)
+            acc += P.partials[(size_t)(sp.item0 + b) * kGradParams + p];
+        tree[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) so.grad[p] = tree[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && so.status) {
+        const int fl = P.flags[s];
+        *so.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
+    }
+}
+
+__global__ void rad_derivs_kernel(const float *rad32d, const double *rad64d, int prec, int64_t n,
+                                  const double *chi, double *out, int *flags) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int fl = (chi[k] < (double)(1 << (kEMax + 1))) ? 0 : kFlagRange;
+    double v[kDerivFuncs];
+    if (prec == 0) {
+        // the FP32 table holds combinations: undo them
+        RadCell6 cell;
+        rad6_lookup32(rad32d, (float)chi[k], cell);
+        const RadJ<float> r = rad6_cell_eval(cell, (float)chi[k]);
+        const double g = r.g, G1 = (double)r.E1 - 2.0 * g;
+        const double G2 = (double)r.E2 - 2.0 * g - 4.0 * G1;
+        v[0] = g;
+        v[1] = G1;
+        v[2] = G2;
+        v[3] = r.h;
+        v[4] = (double)r.E3 - 6.0 * (G1 + G2);
+        v[5] = r.H1;
+    } else {
+        rad6_plain64(rad64d, chi[k], v);
+    }
+    for (int f = 0; f < kDerivFuncs; ++f) out[kDerivFuncs * k + f] = v[f];
+    if (fl) atomicOr(flags, fl);
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
+static const void *tangent_ptr() {
+    return reinterpret_cast<const void *>(&tangent_kernel<PREC, QUANTUM, LOCAL, TAPE>);
+}
+
+template <bool TAPE>
+static const void *select_tangent(int prec, int rr, int amp) {
+    const bool q = rr == 1, l = amp == 1;
+    if (prec == PREC_F64)
+        return q ? (l ? tangent_ptr<PREC_F64, true, true, TAPE>()
+                      : tangent_ptr<PREC_F64, true, false, TAPE>())
+                 : (l ? tangent_ptr<PREC_F64, false, true, TAPE>()
+                      : tangent_ptr<PREC_F64, false, false, TAPE>());
+    return q ? (l ? tangent_ptr<PREC_F32, true, true, TAPE>()
+                  : tangent_ptr<PREC_F32, true, false, TAPE>())
+             : (l ? tangent_ptr<PREC_F32, false, true, TAPE>()
+                  : tangent_ptr<PREC_F32, false, false, TAPE>());
+}
+
+hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
+                          int rr, int amp, bool tape, hipStream_t s) {
+    const void *fn = tape ? select_tangent<true>(prec, rr, amp) : select_tangent<false>(prec, rr, amp);
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    BatchParams pc = p;
+    const float *e32 = env32;
+    const double *e64 = env64;
+    void *args[] = {&pc, &e32, &e64};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+}
+
+hipError_t launch_contract(const BatchParams &p, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&contract_kernel);
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    contract_kernel<<<grid, kPhaseBlock, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {
+    grad_finalize_kernel<<<p.n_shots, 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, int prec, int64_t n,
+                                   const double *chi, double *out, int *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    rad_derivs_kernel<<<(unsigned)blocks, 256, 0, s>>>(rad32d, rad64d, prec, n, chi, out, flags);
+    return hipGetLastError();
+}
+
+}  // namespace qs

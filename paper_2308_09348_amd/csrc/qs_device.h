@@ -1,0 +1,377 @@
+// qs_device.h -- device helpers shared by the kernels of the library: the
+// sample generator, the radiation-function table lookups, the moment system,
+// the spatial factor and ballistic path, RK4 steps, compensated sums, work
+// items and wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <type_traits>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+// ===========================================================================
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller normals
+// ===========================================================================
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Six standard normals of sample i: counter (i, shot, k, 0) for k = 0, 1,
+// 24-bit uniforms u = ((r >> 8) + 1/2) 2^-24, Box-Muller on pairs.
+__device__ __forceinline__ void sample_normals(uint32_t i, uint32_t shot, uint32_t k0, uint32_t k1,
+                                               double n[6]) {
+    uint32_t r[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 2; ++k) {
+        uint32_t c[4] = {i, shot, k, 0u};
+        philox4x32_10(c, k0, k1);
+        r[4 * k + 0] = c[0];
+        r[4 * k + 1] = c[1];
+        r[4 * k + 2] = c[2];
+        r[4 * k + 3] = c[3];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double u1 = ((double)(r[2 * m] >> 8) + 0.5) * 0x1p-24;
+        const double u2 = ((double)(r[2 * m + 1] >> 8) + 0.5) * 0x1p-24;
+        const double R = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincospi(2.0 * u2, &s, &c);
+        n[2 * m] = R * c;
+        n[2 * m + 1] = R * s;
+    }
+}
+
+// ===========================================================================
+// Radiation functions: g, chi g', chi^2 g'', h from per-cell cubics
+// ===========================================================================
+__device__ __forceinline__ void rad_eval32(const float *__restrict__ tab, float chi, float &g,
+                                           float &G1, float &G2, float &hq) {
+    // exponent and the top kSB32 mantissa bits give the cell directly
+    const uint32_t b = __float_as_uint(chi);
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    float t = __uint_as_float(((b & ((1u << (23 - kSB32)) - 1)) << kSB32) | 0x3f800000u) - 1.0f;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
+        c = 0;
+        t = chi * 0x1p20f;
+    }
+    c = min(c, kCells32 - 1);  // chi >= 2^(kEMax+1) is reported by the caller
+    // function-major layout: four arrays of 16-byte cubics, so that the cells
+    // read by one wavefront start on eight different 4-bank groups of LDS
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+    const float4 q0 = T[c], q1 = T[kCells32 + c], q2 = T[2 * kCells32 + c],
+                 q3 = T[3 * kCells32 + c];
+    g = fmaf(t, fmaf(t, fmaf(t, q0.w, q0.z), q0.y), q0.x);
+    G1 = fmaf(t, fmaf(t, fmaf(t, q1.w, q1.z), q1.y), q1.x);
+    G2 = fmaf(t, fmaf(t, fmaf(t, q2.w, q2.z), q2.y), q2.x);
+    hq = fmaf(t, fmaf(t, fmaf(t, q3.w, q3.z), q3.y), q3.x);
+}
+
+// One FP32 table cell held in registers.  Any chi near the cell maps to
+// its local coordinate by t = chi * tw + ts; the RK4 stages that share a
+// phase with the previous lookup (stage 3 after stage 2, the next step's
+// stage 1 after stage 4) evaluate the same cubics a hair outside [0, 1]
+// instead of reading LDS again.
+struct RadCell32 {
+    float4 q0, q1, q2, q3;
+    float tw, ts;
+};
+
+__device__ __forceinline__ void rad_lookup32(const float *__restrict__ tab, float chi,
+                                             RadCell32 &cell) {
+    const uint32_t b = __float_as_uint(chi);
+    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    // cell start 2^e (1 + sub/2^SB) and inverse width 2^(SB - e)
+    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
+    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
+        c = 0;
+        tw = 0x1p20f;
+        ts = 0.0f;
+    }
+    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
+        c = kCells32 - 1;
+        tw = 0.0f;
+        ts = 1.0f;
+    }
+    const float4 *T = reinterpret_cast<const float4 *>(tab);
+    cell.q0 = T[c];
+    cell.q1 = T[kCells32 + c];
+    cell.q2 = T[2 * kCells32 + c];
+    cell.q3 = T[3 * kCells32 + c];
+    cell.tw = tw;
+    cell.ts = ts;
+}
+
+__device__ __forceinline__ void rad_cell_eval(const RadCell32 &cell, float chi, float &g,
+                                              float &G1, float &G2, float &hq) {
+    // returns the four table functions of the cell (see rhs_q32)
+    const float t = fmaf(chi, cell.tw, cell.ts);
+    g = fmaf(t, fmaf(t, fmaf(t, cell.q0.w, cell.q0.z), cell.q0.y), cell.q0.x);
+    G1 = fmaf(t, fmaf(t, fmaf(t, cell.q1.w, cell.q1.z), cell.q1.y), cell.q1.x);
+    G2 = fmaf(t, fmaf(t, fmaf(t, cell.q2.w, cell.q2.z), cell.q2.y), cell.q2.x);
+    hq = fmaf(t, fmaf(t, fmaf(t, cell.q3.w, cell.q3.z), cell.q3.y), cell.q3.x);
+}
+
+__device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
+                                           double &G1, double &G2, double &hq) {
+    const uint64_t b = (uint64_t)__double_as_longlong(chi);
+    int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
+    double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
+                                                0x3ff0000000000000ull)) - 1.0;
+    if (c < 1) {
+        c = 0;
+        t = chi * 0x1p20;
+    }
+    c = c < kCells64 - 1 ? c : kCells64 - 1;
+    const double *q = tab + (size_t)c * kCellVals;
+    g = fma(t, fma(t, fma(t, q[3], q[2]), q[1]), q[0]);
+    G1 = fma(t, fma(t, fma(t, q[7], q[6]), q[5]), q[4]);
+    G2 = fma(t, fma(t, fma(t, q[11], q[10]), q[9]), q[8]);
+    hq = fma(t, fma(t, fma(t, q[15], q[14]), q[13]), q[12]);
+}
+
+template <class T>
+struct RadTab;
+template <>
+struct RadTab<float> {
+    const float *p;
+    __device__ __forceinline__ void eval(float chi, float &g, float &G1, float &G2, float &h) const {
+        rad_eval32(p, chi, g, G1, G2, h);
+    }
+};
+template <>
+struct RadTab<double> {
+    const double *p;
+    __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2,
+                                         double &h) const {
+        rad_eval64(p, chi, g, G1, G2, h);
+    }
+};
+
+// ===========================================================================
+// The moment system (second-order closure of the drift-diffusion process
+// whose drift is eq. dpdtRR in phase units):
+//   dmu/dpsi   = A + A'' sig2 / 2,   dsig2/dpsi = 2 A' sig2 + D,
+//   A = -K a^2 mu^2 g,  A' = -K a^2 mu (2g + G1),  A'' = -K a^2 (2g + 4G1 + G2),
+//   D = C_D |a|^3 mu^4 h,  chi = 2 mu |a| / a_S.
+// ===========================================================================
+template <class T>
+struct Phys {
+    T K, CD, two_over_aS;
+};
+
+template <class T, bool QUANTUM>
+__device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const RadTab<T> &tab,
+                                    T &dmu, T &ds2, T &chi_hi) {
+    const T a2 = a * a;
+    const T Ka2 = ph.K * a2;
+    if (!QUANTUM) {
+        dmu = -Ka2 * mu * mu;
+        ds2 = T(0);
+        return;
+    }
+    const T aa = fabs(a);
+    const T chi = ph.two_over_aS * mu * aa;
+    chi_hi = fmax(chi_hi, chi);
+    T g, G1, G2, hq;
+    tab.eval(chi, g, G1, G2, hq);
+    const T two_g = T(2) * g;
+    const T A = -Ka2 * mu * mu * g;
+    const T A1 = -Ka2 * mu * (two_g + G1);
+    const T A2 = -Ka2 * (two_g + T(4) * G1 + G2);
+    const T mu2 = mu * mu;
+    const T D = ph.CD * a2 * aa * mu2 * mu2 * hq;
+    dmu = fma(T(0.5) * A2, s2, A);
+    ds2 = fma(T(2) * A1, s2, D);
+}
+
+// Spatial factor a/a0 of eq. a0eff at (x, y, z) [um].  The FP32 version uses
+// the hardware reciprocal, reciprocal square root and base-2 exponential
+// (about one ulp each; the exponent's argument rounding adds |r2/q| ulps,
+// which matters only where the factor itself is small).
+__device__ __forceinline__ float spatial(float x, float y, float z, float inv_w0sq, float inv_zR) {
+    const float zz = z * inv_zR;
+    const float q = fmaf(zz, zz, 1.0f);
+    const float rq = __builtin_amdgcn_rsqf(q);  // 1/sqrt(q); 1/q = rq^2
+    const float r2 = fmaf(x, x, y * y) * inv_w0sq;
+    return __builtin_amdgcn_exp2f(-1.4426950408889634f * r2 * (rq * rq)) * rq;
+}
+__device__ __forceinline__ double spatial(double x, double y, double z, double inv_w0sq,
+                                          double inv_zR) {
+    const double zz = z * inv_zR;
+    const double q = fma(zz, zz, 1.0);
+    const double iq = 1.0 / q;
+    const double r2 = fma(x, x, y * y) * inv_w0sq;
+    return exp(-r2 * iq) * sqrt(iq);
+}
+
+// Geometry of one sample along its ballistic path: at phase psi it has
+// travelled l = psi lambda / (4 pi) past its collision point.
+template <class T>
+struct Path {
+    T xc, yc, thx, thy, zstar, inv_w0sq, inv_zR;
+    __device__ __forceinline__ T S(T ell) const {
+        return spatial(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell, inv_w0sq, inv_zR);
+    }
+};
+
+// One RK4 step of (mu, sig2) from psi_j with amplitudes a1 = a(psi_j),
+// ah = a(psi_j + h/2), a4 = a(psi_j + h); returns the increments.
+template <class T, bool QUANTUM>
+__device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
+                                              const Phys<T> &ph, const RadTab<T> &tab, T &dmu,
+                                              T &ds2, T &chi_hi) {
+    const T hh = T(0.5) * h;
+    T k1m, k1s, k2m, k2s, k3m, k3s, k4m, k4s;
+    rhs<T, QUANTUM>(mu, s2, a1, ph, tab, k1m, k1s, chi_hi);
+    rhs<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, chi_hi);
+    rhs<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, chi_hi);
+    rhs<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, chi_hi);
+    const T h6 = h * T(1.0 / 6.0);
+    dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
+    ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+}
+
+// Moment right-hand side (quantum model) from the FP32 table's combined
+// functions at chi = two_over_aS mu |a|:  T1 = g,  T2 = 2g + chi g',
+// T3 = g + 2 chi g' + chi^2 g''/2,  T4 = h, so that
+//   dmu/dpsi   = -K a^2 (mu^2 T1 + sig2 T3),
+//   dsig2/dpsi = -2 K a^2 mu sig2 T2 + C_D a^2 |a| mu^4 T4.
+__device__ __forceinline__ void rhs_q32(float mu, float s2, float a2, float aa, float T1, float T2,
+                                        float T3, float T4, const Phys<float> &ph, float &dmu,
+                                        float &ds2) {
+    const float u = ph.K * a2;
+    const float mu2 = mu * mu;
+    dmu = -u * fmaf(mu2, T1, s2 * T3);
+    const float D = (ph.CD * aa) * a2 * (mu2 * mu2) * T4;
+    ds2 = fmaf(-2.0f * u * mu * s2, T2, D);
+}
+
+// One FP32 RK4 step of the quantum moment system with two table reads:
+// stage 2 and stage 4 read LDS, stage 3 reuses stage 2's cell, and stage 4's
+// cell is handed to the next step's stage 1.
+__device__ __forceinline__ void rk4_q32(float mu, float s2, float a1, float ah, float a4, float h,
+                                        const Phys<float> &ph, const float *__restrict__ tab,
+                                        RadCell32 &carry, float &dmu, float &ds2,
+                                        float &chi_hi) {
+    const float hh = 0.5f * h;
+    float g, G1, G2, hq;
+    // stage 1 (cell carried from the previous stage 4)
+    const float aa1 = fabsf(a1), a21 = a1 * a1;
+    const float c1 = ph.two_over_aS * mu * aa1;
+    rad_cell_eval(carry, c1, g, G1, G2, hq);
+    float k1m, k1s;
+    rhs_q32(mu, s2, a21, aa1, g, G1, G2, hq, ph, k1m, k1s);
+    // stage 2 (table read)
+    const float aah = fabsf(ah), a2h = ah * ah;
+    const float m2 = fmaf(hh, k1m, mu), s22 = fmaf(hh, k1s, s2);
+    const float c2 = ph.two_over_aS * m2 * aah;
+    RadCell32 mid;
+    rad_lookup32(tab, c2, mid);
+    rad_cell_eval(mid, c2, g, G1, G2, hq);
+    float k2m, k2s;
+    rhs_q32(m2, s22, a2h, aah, g, G1, G2, hq, ph, k2m, k2s);
+    // stage 3 (same phase as stage 2: reuse its cell)
+    const float m3 = fmaf(hh, k2m, mu), s23 = fmaf(hh, k2s, s2);
+    const float c3 = ph.two_over_aS * m3 * aah;
+    rad_cell_eval(mid, c3, g, G1, G2, hq);
+    float k3m, k3s;
+    rhs_q32(m3, s23, a2h, aah, g, G1, G2, hq, ph, k3m, k3s);
+    // stage 4 (table read; its cell serves the next step's stage 1)
+    const float aa4 = fabsf(a4), a24 = a4 * a4;
+    const float m4 = fmaf(h, k3m, mu), s24 = fmaf(h, k3s, s2);
+    const float c4 = ph.two_over_aS * m4 * aa4;
+    rad_lookup32(tab, c4, carry);
+    rad_cell_eval(carry, c4, g, G1, G2, hq);
+    float k4m, k4s;
+    rhs_q32(m4, s24, a24, aa4, g, G1, G2, hq, ph, k4m, k4s);
+    chi_hi = fmaxf(chi_hi, fmaxf(fmaxf(c1, c2), fmaxf(c3, c4)));
+    const float h6 = h * (1.0f / 6.0f);
+    dmu = h6 * (k1m + 2.0f * (k2m + k3m) + k4m);
+    ds2 = h6 * (k1s + 2.0f * (k2s + k3s) + k4s);
+}
+
+// Compensated accumulation: (hi, lo) += d, renormalised (Fast2Sum, |hi| >= |d|).
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float d) {
+    const float dd = d + lo;
+    const float s = hi + dd;
+    lo = dd - (s - hi);
+    hi = s;
+}
+
+// ===========================================================================
+// Work items.  A launch covers n_shots shots; phase items are tiles of
+// kPhaseBlock consecutive samples of one shot (one sample per lane), deposit
+// items tiles of kDepTile samples.  Blocks take items from a counter; an
+// item's result does not depend on which block runs it, so the output is
+// deterministic, and a shot gives the same bits alone or in a batch.
+// ===========================================================================
+__device__ __forceinline__ int find_shot(const ShotParams *shots, int n_shots, int64_t item,
+                                         bool deposit) {
+    int lo = 0, hi = n_shots - 1;  // largest s whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t first = deposit ? shots[mid].ditem0 : shots[mid].item0;
+        if (first <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slot) {
+    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t item = *slot;
+    __syncthreads();
+    return item;
+}
+
+// ===========================================================================
+// Wavefront reductions
+// ===========================================================================
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Grid of resident blocks for a persistent work-queue kernel (never more
+// blocks than items).
+inline hipError_t resident_grid(const void *fn, int block, size_t lds, int64_t items, int *grid) {
+    int device = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
+    if (e != hipSuccess) return e;
+    int64_t g = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
+    if (g > items) g = items;
+    *grid = (int)(g < 1 ? 1 : g);
+    return hipSuccess;
+}
+
+}  // namespace qs

@@ -1,0 +1,617 @@
+// qs_photon.hip -- the approximate photon spectrum of Sec. 4: the LCFA number
+// CDF table, the emission kernel and the per-shot contraction.
+#include "qs_device.h"
+
+namespace qs {
+
+// ===========================================================================
+// Photon spectrum (Sec. 4).  Along each sample's trajectory every RK4 stage
+// (weights h/6, h/3, h/3, h/6) emits the LCFA spectrum of its state:
+//   d2N / (dpsi dxi) = C_ph F(xi, chi) / mu,   C_ph = alpha a_S / (2 sqrt3 pi),
+// so that a stage adds c h C_ph (chi / mu) [Phi(e_{k+1}/mu; chi) -
+// Phi(e_k/mu; chi)] / chi to photon-energy bin k, Phi(xi; chi) = Int_0^xi F.
+// Evaluating Phi at every bin edge for every stage would cost the bin count
+// per stage, so each stage instead deposits its weight c (chi / mu) =
+// c 2|a| / a_S, bilinearly, into an emission grid over (ln chi, ln mu) kept
+// in LDS in fixed point (order-independent sums); a finalize kernel then
+// evaluates Phi / chi once per grid node and bin edge.  The grid spacing
+// (0.2 in ln chi, at most ~0.05 in ln mu for the shot's energy range) sets the
+// accuracy, about 1e-3 of the spectrum in L1.  Stages whose chi lies below
+// the grid emit photons below the first bin (the host sizes the grid so): they
+// add only their photon number, (5 pi / 2) chi (1 - 8 chi / (5 sqrt3)) per
+// unit C_ph c / mu, to the lowest bin.  The emitted photon energy itself,
+// c h (-A) summed over the stages (A: the drift), is accumulated exactly.
+// ===========================================================================
+__device__ __forceinline__ double ph_dz() { return cbrt(kPhYMax) / kPhNZ; }
+__device__ __forceinline__ float ph_ln(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994530942f;
+}
+__device__ __forceinline__ float ph_ln(double x) { return (float)log(x); }
+
+// K_{2/3} and K_{1/3} at the 5 Gauss-Legendre nodes of every z interval.
+__constant__ double kGLx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0,
+                               0.5384693101056831, 0.9061798459386640};
+__constant__ double kGLw[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                               0.4786286704993665, 0.2369268850561891};
+
+__device__ __forceinline__ double ph_node_z(int g) {
+    return ph_dz() * ((g / 5) + 0.5 + 0.5 * kGLx[g % 5]);
+}
+
+__global__ void ph_bessel_kernel(double *k23, double *k13) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 5 * kPhNZ) return;
+    const double z = ph_node_z(g);
+    const double y = z * z * z;
+    // K_nu(y) = Int_0^inf exp(-y cosh t) cosh(nu t) dt (trapezoid, doubly
+    // exponential decay)
+    const double dt = 1.0 / 32.0;
+    const double tmax = acosh(fmax(60.0 / y, 1.0)) + dt;
+    const int nt = (int)ceil(tmax / dt);
+    double s23 = 0.0, s13 = 0.0;
+    for (int m = 0; m <= nt; ++m) {
+        const double t = m * dt;
+        const double e = exp(-y * cosh(t)) * (m == 0 ? 0.5 : 1.0);
+        s23 += e * cosh(t * (2.0 / 3.0));
+        s13 += e * cosh(t * (1.0 / 3.0));
+    }
+    k23[g] = s23 * dt;
+    k13[g] = s13 * dt;
+}
+
+// Int_{y(z_j)}^inf K_{1/3}, accumulated downwards (y beyond kPhYMax: < 1e-34).
+__global__ void ph_i13_kernel(const double *k13, double *i13) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const double dz = ph_dz();
+    i13[kPhNZ] = 0.0;
+    for (int j = kPhNZ - 1; j >= 0; --j) {
+        double s = 0.0;
+        for (int q = 0; q < 5; ++q) {
+            const double z = ph_node_z(5 * j + q);
+            s += kGLw[q] * k13[5 * j + q] * 3.0 * z * z;
+        }
+        i13[j] = i13[j + 1] + 0.5 * dz * s;
+    }
+}
+
+// One row per thread: Phi / chi at the z nodes,
+//   Phi = Int_0^y [w K_{2/3} xi_y - xi K_{1/3}] dy' - xi Int_y^inf K_{1/3}
+// (the Int K_{1/3} term of F integrated by parts).
+__global__ void ph_row_kernel(const double *k23, const double *k13, const double *i13,
+                              double *phtab) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= kPhRows) return;
+    const double chi = exp(kPhU0 + r * kPhDu);
+    const double dz = ph_dz();
+    double *row = phtab + (size_t)r * (kPhNZ + 1);
+    double A = 0.0;
+    // stored: Phi / (chi z), smooth at z = 0 where it tends to
+    // 9 2^(-1/3) Gamma(2/3) (K_{2/3}(y) ~ Gamma(2/3)/2 (y/2)^(-2/3))
+    row[0] = 9.0 * 0.79370052598409973738 * 1.3541179394264004169;
+    for (int j = 0; j < kPhNZ; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < 5; ++q) {
+            const int g = 5 * j + q;
+            const double z = ph_node_z(g);
+            const double y = z * z * z;
+            const double qq = 2.0 + 3.0 * chi * y;
+            const double xi = 3.0 * chi * y / qq;
+            const double w = 2.0 / qq + 0.5 * qq;
+            const double xi_y = 6.0 * chi / (qq * qq);
+            s += kGLw[q] * (w * k23[g] * xi_y - xi * k13[g]) * 3.0 * z * z;
+        }
+        A += 0.5 * dz * s;
+        const double z1 = (j + 1) * dz, y1 = z1 * z1 * z1;
+        const double xi1 = 3.0 * chi * y1 / (2.0 + 3.0 * chi * y1);
+        row[j + 1] = (A - xi1 * i13[j + 1]) / (chi * z1);
+    }
+}
+
+// Phi / chi on global row r at xi: the stored Phi / (chi z) interpolated by a
+// cubic in z, times z (xi >= 1 and y >= kPhYMax give the row's total).
+__device__ __forceinline__ double ph_cdf_row(const double *__restrict__ phtab, int r, double chi,
+                                             double xi) {
+    if (!(xi > 0.0)) return 0.0;
+    const double *row = phtab + (size_t)r * (kPhNZ + 1);
+    const double zmax = kPhNZ * ph_dz();
+    if (xi >= 1.0) return row[kPhNZ] * zmax;
+    const double y = 2.0 * xi / (3.0 * chi * (1.0 - xi));
+    if (!(y < kPhYMax)) return row[kPhNZ] * zmax;
+    const double z = cbrt(y);
+    const double t = z / ph_dz();
+    int j = (int)t - 1;
+    j = j < 0 ? 0 : (j > kPhNZ - 3 ? kPhNZ - 3 : j);
+    const double x = t - j;
+    const double w0 = -(x - 1.0) * (x - 2.0) * (x - 3.0) * (1.0 / 6.0);
+    const double w1 = x * (x - 2.0) * (x - 3.0) * 0.5;
+    const double w2 = -x * (x - 1.0) * (x - 3.0) * 0.5;
+    const double w3 = x * (x - 1.0) * (x - 2.0) * (1.0 / 6.0);
+    return (w0 * row[j] + w1 * row[j + 1] + w2 * row[j + 2] + w3 * row[j + 3]) * z;
+}
+
+// Diagnostic: Phi(xi; chi) with cubic interpolation across rows as well.
+__global__ void ph_cdf_kernel(const double *phtab, int64_t n, const double *chi,
+                              const double *xi, double *out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double c = chi[k];
+    const double s = (log(c) - kPhU0) / kPhDu;
+    if (!(c > 0.0) || !(s >= 0.0) || !(s <= kPhRows - 1)) {
+        out[k] = nan("");
+        return;
+    }
+    int r = (int)s - 1;
+    r = r < 0 ? 0 : (r > kPhRows - 4 ? kPhRows - 4 : r);
+    const double x = s - r;
+    const double wr[4] = {-(x - 1.0) * (x - 2.0) * (x - 3.0) / 6.0, x * (x - 2.0) * (x - 3.0) / 2.0,
+                          -x * (x - 1.0) * (x - 3.0) / 2.0, x * (x - 1.0) * (x - 2.0) / 6.0};
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a) acc += wr[a] * ph_cdf_row(phtab, r + a, c, xi[k]);
+    out[k] = acc * c;
+}
+
+// Deposit of emission weight D (in units of 2 a0 / a_S per unit h) at
+// v = ln mu, u = ln chi = la + v (la = ln(2 |a| / a_S)), bilinear in (u, v);
+// below the grid only the photon number is kept.
+struct PhotAcc {
+    double e_ph, soft;
+    int flags;
+};
+
+__device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi,
+                                           const ShotPhot &sp, unsigned long long *grid,
+                                           PhotAcc &acc) {
+    const float ru = (la + v - (float)(kPhU0 + sp.r_lo * kPhDu)) * (float)(1.0 / kPhDu);
+    if (ru < 0.0f) {  // below the grid: photon number only
+        acc.soft += (double)D * (1.0 - 0.92376043070340122 * (double)chi);
+        return;
+    }
+    float fu = ru, fv = (v - (float)sp.v_lo) / (float)sp.dv;
+    if (!(fu <= (float)(sp.nu - 1)) || !(fv >= 0.0f) || !(fv <= (float)(sp.nv - 1))) {
+        acc.flags |= kFlagRange;
+        fu = fminf(fmaxf(fu, 0.0f), (float)(sp.nu - 1));
+        fv = fminf(fmaxf(fv, 0.0f), (float)(sp.nv - 1));
+    }
+    const int n = min((int)fu, sp.nu - 2), m = min((int)fv, sp.nv - 2);
+    const float du = fu - (float)n, dv = fv - (float)m;
+    const double q = (double)D * kPhScale;
+    unsigned long long *g = grid + n * sp.nv + m;
+    const unsigned long long q00 = (unsigned long long)llrint(q * (double)((1.0f - du) * (1.0f - dv)));
+    const unsigned long long q01 = (unsigned long long)llrint(q * (double)((1.0f - du) * dv));
+    const unsigned long long q10 = (unsigned long long)llrint(q * (double)(du * (1.0f - dv)));
+    const unsigned long long q11 = (unsigned long long)llrint(q * (double)(du * dv));
+    if (q00) atomicAdd(g, q00);
+    if (q01) atomicAdd(g + 1, q01);
+    if (q10) atomicAdd(g + sp.nv, q10);
+    if (q11) atomicAdd(g + sp.nv + 1, q11);
+}
+
+// Radiation functions per stage in the forward table's combinations
+// T1 = g, T2 = 2g + chi g', T3 = g + 2 chi g' + chi^2 g''/2, T4 = h.  FP32:
+// the LDS table read at stages 2 and 4 only, stage 3 and the next stage 1
+// reusing those cells; FP64: the global table at every stage.
+template <class T>
+struct FwdRad;
+template <>
+struct FwdRad<float> {
+    const float *tab;
+    RadCell32 carry, mid;
+    __device__ __forceinline__ void init(float chi) { rad_lookup32(tab, chi, carry); }
+    __device__ __forceinline__ void s1(float chi, float *t) {
+        rad_cell_eval(carry, chi, t[0], t[1], t[2], t[3]);
+    }
+    __device__ __forceinline__ void s2(float chi, float *t) {
+        rad_lookup32(tab, chi, mid);
+        rad_cell_eval(mid, chi, t[0], t[1], t[2], t[3]);
+    }
+    __device__ __forceinline__ void s3(float chi, float *t) {
+        rad_cell_eval(mid, chi, t[0], t[1], t[2], t[3]);
+    }
+    __device__ __forceinline__ void s4(float chi, float *t) {
+        rad_lookup32(tab, chi, carry);
+        rad_cell_eval(carry, chi, t[0], t[1], t[2], t[3]);
+    }
+};
+template <>
+struct FwdRad<double> {
+    const double *tab;
+    __device__ __forceinline__ void init(double) {}
+    __device__ __forceinline__ void ev(double chi, double *t) {
+        double g, G1, G2, hq;
+        rad_eval64(tab, chi, g, G1, G2, hq);
+        t[0] = g;
+        t[1] = fma(2.0, g, G1);
+        t[2] = fma(0.5, G2, fma(2.0, G1, g));
+        t[3] = hq;
+    }
+    __device__ __forceinline__ void s1(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s2(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s3(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s4(double chi, double *t) { ev(chi, t); }
+};
+
+// One stage: slopes and the drift A (the photon energy per unit phase is -A).
+template <class T, bool QUANTUM, int S>
+__device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph, FwdRad<T> &rad,
+                                             T &dmu, T &ds2, T &A, T &chi_hi) {
+    const T a2 = a * a;
+    const T u = ph.K * a2;
+    const T mu2 = mu * mu;
+    if (!QUANTUM) {
+        A = -u * mu2;
+        dmu = A;
+        ds2 = T(0);
+        return;
+    }
+    const T aa = fabs(a);
+    const T chi = ph.two_over_aS * mu * aa;
+    chi_hi = fmax(chi_hi, chi);
+    T t[4];
+    if (S == 1) rad.s1(chi, t);
+    if (S == 2) rad.s2(chi, t);
+    if (S == 3) rad.s3(chi, t);
+    if (S == 4) rad.s4(chi, t);
+    A = -u * mu2 * t[0];
+    dmu = -u * fma(mu2, t[0], s2 * t[2]);
+    ds2 = fma(T(-2) * u * mu * s2, t[1], ph.CD * aa * a2 * mu2 * mu2 * t[3]);
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+__device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotParams &sp,
+                                              const ShotPhot &pp, int64_t i,
+                                              const float *__restrict__ env32,
+                                              const double *__restrict__ env64,
+                                              const float *tab32, unsigned long long *grid,
+                                              PhotAcc &acc, double &loss) {
+    using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    const T *env;
+    FwdRad<T> rad;
+    if constexpr (PREC == PREC_F64) {
+        env = env64;
+        rad.tab = P.rad64;
+    } else {
+        env = env32;
+        rad.tab = tab32;
+    }
+    Phys<T> ph;
+    ph.K = (T)P.K;
+    ph.CD = (T)P.CD;
+    ph.two_over_aS = (T)P.two_over_aS;
+    const int N = P.n_steps;
+    const bool local = LOCAL && !sp.plane_wave;
+
+    double nrm[6];
+    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
+    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
+    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
+    const double z = sp.sigma_z * nrm[2];
+    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
+    const double thx = sp.div_rad * nrm[4];
+    const double thy = sp.div_rad * nrm[5];
+    Path<double> pd;
+    pd.xc = fma(thx, 0.5 * z, x);
+    pd.yc = fma(thy, 0.5 * z, y);
+    pd.thx = thx;
+    pd.thy = thy;
+    pd.zstar = fma(0.5, z, sp.z_delay);
+    pd.inv_w0sq = sp.inv_w0sq;
+    pd.inv_zR = sp.inv_zR;
+    const double S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
+    Path<T> pt;
+    pt.xc = (T)pd.xc;
+    pt.yc = (T)pd.yc;
+    pt.thx = (T)thx;
+    pt.thy = (T)thy;
+    pt.zstar = (T)pd.zstar;
+    pt.inv_w0sq = (T)sp.inv_w0sq;
+    pt.inv_zR = (T)sp.inv_zR;
+
+    const T a0 = (T)sp.a0, a0S0 = (T)(sp.a0 * S0);
+    const float inv_a0 = sp.a0 > 0.0 ? (float)(1.0 / sp.a0) : 0.0f;
+    const float tas = (float)P.two_over_aS;
+    const T h = (T)P.h, hh = T(0.5) * h, psi0 = (T)(-P.psi_max), ell = (T)P.ell_per_psi;
+    const T c16 = T(1.0 / 6.0), c13 = T(1.0 / 3.0);
+    T mu = (T)g0, mu_lo = T(0), s2 = T(0), s2_lo = T(0);
+    double g0_rest = 0.0;
+    if constexpr (PREC != PREC_F64) {
+        mu_lo = (T)(g0 - (double)mu);
+        g0_rest = (g0 - (double)mu) - (double)mu_lo;
+    }
+    T chi_hi = T(0);
+    T aS_prev = local ? a0 * pt.S(psi0 * ell) : a0S0;
+    if (QUANTUM) rad.init(ph.two_over_aS * mu * fabs(aS_prev * env[0]));
+    // the first stage of the first step deposits alone
+    {
+        const float aa = fabsf((float)(aS_prev * env[0]));
+        if (aa > 0.0f)
+            ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)mu), ph_ln(tas * aa),
+                       tas * (float)mu * aa, pp, grid, acc);
+    }
+    T m4_prev = T(0);  // the previous step's stage-4 state, deposited with this step's stage 1
+    for (int j = 0; j < N; ++j) {
+        const T psi = fma((T)j, h, psi0);
+        T aSh = a0S0, aS4 = a0S0;
+        if (local) {
+            aSh = a0 * pt.S(fma(T(0.5), h, psi) * ell);
+            aS4 = a0 * pt.S((psi + h) * ell);
+        }
+        const T a1 = aS_prev * env[2 * j], ah = aSh * env[2 * j + 1], a4 = aS4 * env[2 * j + 2];
+        // stage 4 of the previous step with stage 1 of this one (same
+        // amplitude): one deposit at the geometric mean of the two energies
+        if (j > 0) {
+            const float aa = fabsf((float)a1);
+            if (aa > 0.0f) {
+                const float v = 0.5f * ph_ln((float)m4_prev * (float)mu);
+                ph_deposit((float)c13 * aa * inv_a0, v, ph_ln(tas * aa), tas * (float)mu * aa, pp,
+                           grid, acc);
+            }
+        }
+        T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
+        photon_stage<T, QUANTUM, 1>(mu, s2, a1, ph, rad, k1m, k1s, A1, chi_hi);
+        const T m2 = fma(hh, k1m, mu);
+        photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, ph, rad, k2m, k2s, A2, chi_hi);
+        const T m3 = fma(hh, k2m, mu);
+        photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, ph, rad, k3m, k3s, A3, chi_hi);
+        const T m4 = fma(h, k3m, mu);
+        photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, ph, rad, k4m, k4s, A4, chi_hi);
+        acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
+        {  // stages 2 and 3 (same amplitude)
+            const float aa = fabsf((float)ah);
+            if (aa > 0.0f) {
+                const float v = 0.5f * ph_ln((float)m2 * (float)m3);
+                ph_deposit(2.0f * (float)c13 * aa * inv_a0, v, ph_ln(tas * aa),
+                           tas * (float)m2 * aa, pp, grid, acc);
+            }
+        }
+        const T h6 = h * c16;
+        const T dm = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
+        const T ds = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+        if constexpr (PREC == PREC_F64) {
+            mu += dm;
+            s2 += ds;
+        } else {
+            comp_add(mu, mu_lo, dm);
+            comp_add(s2, s2_lo, ds);
+        }
+        m4_prev = m4;
+        aS_prev = aS4;
+    }
+    {  // the last stage 4 deposits alone
+        const float aa = fabsf((float)(aS_prev * env[2 * N]));
+        if (aa > 0.0f)
+            ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)m4_prev), ph_ln(tas * aa),
+                       tas * (float)m4_prev * aa, pp, grid, acc);
+    }
+    const double mu_f = ((double)mu + (double)mu_lo) + g0_rest;
+    if (QUANTUM && !((float)chi_hi < (float)(1 << (kEMax + 1)))) acc.flags |= kFlagRange;
+    if (!(mu_f > 0.0) || !isfinite(mu_f)) {
+        acc.flags |= kFlagNonFinite;
+        return;
+    }
+    loss += g0 - mu_f;
+}
+
+__device__ __forceinline__ int find_phot(const ShotPhot *ph, int n_shots, int64_t item) {
+    int lo = 0, hi = n_shots - 1;  // largest s whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ph[mid].pitem0 <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+__global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
+                                                           const float *__restrict__ env32,
+                                                           const double *__restrict__ env64) {
+    constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
+    __shared__ unsigned long long grid[kPhNodes];
+    __shared__ int64_t slot;
+    __shared__ double red[kDepBlock / 64][kPhotPartials];
+    if (kTab32) {
+        const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
+        float4 *dst = reinterpret_cast<float4 *>(tab32);
+        for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (;;) {
+        const int64_t item = next_item(&P.queue[0], &slot);
+        if (item >= P.n_pitems) break;
+        const int s = __builtin_amdgcn_readfirstlane(find_phot(P.phot, P.n_shots, item));
+        const ShotParams &sp = P.shots[s];
+        const ShotPhot &pp = P.phot[s];
+        const int nodes = pp.nu * pp.nv;
+        for (int k = threadIdx.x; k < nodes; k += blockDim.x) grid[k] = 0ull;
+        __syncthreads();
+        PhotAcc acc{0.0, 0.0, 0};
+        double loss = 0.0;
+        const int64_t i0 = (item - pp.pitem0) * kPhotTile;
+        const int64_t i1 = i0 + kPhotTile < sp.n_samples ? i0 + kPhotTile : sp.n_samples;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+            photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, acc,
+                                                loss);
+        if (acc.flags) atomicOr(&P.flags[s], acc.flags);
+        const double v[kPhotPartials] = {acc.e_ph, loss, acc.soft};
+#pragma unroll
+        for (int m = 0; m < kPhotPartials; ++m) {
+            const double w = wave_sum(v[m]);
+            if (lane == 0) red[wid][m] = w;
+        }
+        __syncthreads();
+        if (threadIdx.x < kPhotPartials) {
+            double sum = 0.0;
+            for (int w = 0; w < kDepBlock / 64; ++w) sum += red[w][threadIdx.x];
+            P.partials[(size_t)item * kPhotPartials + threadIdx.x] = sum;
+        }
+        for (int k = threadIdx.x; k < nodes; k += blockDim.x) {
+            const unsigned long long w = grid[k];
+            if (w) atomicAdd(&P.pgrid[pp.grid_off + k], w);
+        }
+        __syncthreads();  // the next item clears the grid
+    }
+}
+
+// One block per shot: the item sums in a fixed order, then the spectrum.
+// With S_k = sum over grid nodes of W_node Phi(e_k / mu_node; chi_node) / chi_node
+// (nodes in index order), bin k holds C (S_{k+1} - S_k), the underflow C S_0
+// and the overflow C (S_total - S_n), C = 2^-24 (2 a0 / a_S) h C_ph.
+constexpr int kPhMaxEdgesPerThread = (4096 + 2 + 255) / 256;
+
+__global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, double c_ph) {
+    const int s = blockIdx.x;
+    const ShotParams &sp = P.shots[s];
+    const ShotPhot &pp = P.phot[s];
+    __shared__ double tree[256];
+    __shared__ double sums[kPhotPartials];
+    __shared__ double nzw[kPhNodes + 2];   // weights of the non-zero nodes, then S_k
+    __shared__ unsigned short nzi[kPhNodes];
+    __shared__ int cnt[257];
+    const int tid = threadIdx.x;
+    const int64_t ni = (sp.n_samples + kPhotTile - 1) / kPhotTile;
+    for (int m = 0; m < kPhotPartials; ++m) {
+        double a = 0.0;
+        for (int64_t b = tid; b < ni; b += blockDim.x)
+            a += P.partials[(size_t)(pp.pitem0 + b) * kPhotPartials + m];
+        tree[tid] = a;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) tree[tid] += tree[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) sums[m] = tree[0];
+        __syncthreads();
+    }
+    // compact the non-zero nodes in index order
+    const int nodes = pp.nu * pp.nv;
+    const unsigned long long *G = P.pgrid + pp.grid_off;
+    constexpr int kPer = kPhNodes / 256;
+    int mine = 0;
+    for (int q = 0; q < kPer; ++q) {
+        const int k = tid * kPer + q;
+        if (k < nodes && G[k]) ++mine;
+    }
+    cnt[tid + 1] = mine;
+    if (tid == 0) cnt[0] = 0;
+    __syncthreads();
+    if (tid == 0)
+        for (int t = 1; t <= 256; ++t) cnt[t] += cnt[t - 1];
+    __syncthreads();
+    int pos = cnt[tid];
+    for (int q = 0; q < kPer; ++q) {
+        const int k = tid * kPer + q;
+        if (k < nodes && G[k]) {
+            nzi[pos] = (unsigned short)k;
+            nzw[pos] = (double)G[k];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const int nnz = cnt[256];
+    // edge sums: thread tid owns edges tid, tid + 256, ...; index n_ph + 1
+    // stands for the total
+    const int n_edges = pp.n_ph + 2;
+    double S[kPhMaxEdgesPerThread];
+    for (int q = 0; q < kPhMaxEdgesPerThread; ++q) S[q] = 0.0;
+    for (int z = 0; z < nnz; ++z) {
+        const int k = nzi[z];
+        const int n = k / pp.nv, m = k - n * pp.nv;
+        const int r = pp.r_lo + n;
+        const double chi = exp(kPhU0 + r * kPhDu);
+        const double inv_mu = exp(-(pp.v_lo + m * pp.dv));
+        const double w = nzw[z];
+        for (int q = 0; q < kPhMaxEdgesPerThread; ++q) {
+            const int e = tid + 256 * q;
+            if (e >= n_edges) break;
+            const double xi = e == pp.n_ph + 1 ? 2.0 : (pp.ph_lo + e * pp.ph_w) * inv_mu;
+            S[q] = fma(w, ph_cdf_row(P.phtab, r, chi, xi), S[q]);
+        }
+    }
+    __syncthreads();  // nzw is reused for S
+    for (int q = 0; q < kPhMaxEdgesPerThread; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n_edges) nzw[e] = S[q];
+    }
+    __syncthreads();
+    const double C = (1.0 / kPhScale) * (2.0 * sp.a0 * P.two_over_aS * 0.5) * P.h * c_ph;
+    // C = 2^-24 (2 a0 / a_S) h C_ph  (two_over_aS / 2 = 1 / a_S)
+    const double soft = sums[2] * (2.0 * sp.a0 * P.two_over_aS * 0.5) * P.h * c_ph *
+                        (5.0 * 3.14159265358979323846 / 2.0);
+    const int n = pp.n_ph;
+    for (int k = tid; k < n + 2; k += blockDim.x) {
+        double v;
+        if (k < n)
+            v = C * (nzw[k + 1] - nzw[k]);
+        else if (k == n)
+            v = C * nzw[0];
+        else
+            v = C * (nzw[n + 1] - nzw[n]);
+        if (pp.ph_lo > 0.0 ? k == n : k == 0) v += soft;
+        pp.hist[k] = v;
+    }
+    if (tid == 0) {
+        pp.energy[0] = sums[0];
+        pp.energy[1] = sums[1];
+        if (pp.status) {
+            const int fl = P.flags[s];
+            *pp.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
+        }
+    }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+size_t photon_work_doubles() { return (size_t)2 * 5 * kPhNZ + (kPhNZ + 1); }
+
+hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, hipStream_t s) {
+    if (work_doubles < photon_work_doubles()) return hipErrorInvalidValue;
+    double *k23 = work, *k13 = work + 5 * kPhNZ, *i13 = work + 10 * kPhNZ;
+    ph_bessel_kernel<<<(5 * kPhNZ + 63) / 64, 64, 0, s>>>(k23, k13);
+    ph_i13_kernel<<<1, 1, 0, s>>>(k13, i13);
+    ph_row_kernel<<<(kPhRows + 63) / 64, 64, 0, s>>>(k23, k13, i13, phtab);
+    return hipGetLastError();
+}
+
+template <int PREC, bool QUANTUM, bool LOCAL>
+static const void *photon_ptr() {
+    return reinterpret_cast<const void *>(&photon_kernel<PREC, QUANTUM, LOCAL>);
+}
+
+hipError_t launch_photon(const BatchParams &p, const float *env32, const double *env64, int prec,
+                         int rr, int amp, hipStream_t s) {
+    const bool q = rr == 1, l = amp == 1;
+    const void *fn;
+    if (prec == PREC_F64)
+        fn = q ? (l ? photon_ptr<PREC_F64, true, true>() : photon_ptr<PREC_F64, true, false>())
+               : (l ? photon_ptr<PREC_F64, false, true>() : photon_ptr<PREC_F64, false, false>());
+    else
+        fn = q ? (l ? photon_ptr<PREC_F32, true, true>() : photon_ptr<PREC_F32, true, false>())
+               : (l ? photon_ptr<PREC_F32, false, true>() : photon_ptr<PREC_F32, false, false>());
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kDepBlock, 0, p.n_pitems, &grid);
+    if (e != hipSuccess) return e;
+    BatchParams pc = p;
+    const float *e32 = env32;
+    const double *e64 = env64;
+    void *args[] = {&pc, &e32, &e64};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kDepBlock), args, 0, s);
+}
+
+hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t s) {
+    photon_finalize_kernel<<<p.n_shots, 256, 0, s>>>(p, c_ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_photon_cdf(const double *phtab, int64_t n, const double *chi, const double *xi,
+                             double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    ph_cdf_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(phtab, n, chi, xi, out);
+    return hipGetLastError();
+}
+
+}  // namespace qs

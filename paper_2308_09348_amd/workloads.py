@@ -98,6 +98,30 @@ def batched_shots(n_shots=4096, seed=3):
     return shots
 
 
+def quantum_batch(n_shots=256, seed=5, n_samples=1 << 18):
+    """Quantum batch with gradients and photon spectra: gamma0 ~ N(2e4, 600^2),
+    a0 ~ U[50, 150] drawn per shot by PCG64(seed); W0 = 2 um, no offsets or
+    delay, 30 fs, beam 3 um x 5 um, 1 mrad, 5 % energy spread; 2^18 samples,
+    2048 steps, quantum moments with FP64 steps where chi > 0.1, local
+    amplitude, Gaussian-kernel deposit; 256 energy bins over [0, 1.5 gamma0)
+    and 256 photon bins over [0, 1.2 gamma0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g0 = rng.normal(2e4, 600.0, n_shots)
+    a0 = rng.uniform(50.0, 150.0, n_shots)
+    shots = []
+    for s in range(n_shots):
+        p = copy.deepcopy(BASE)
+        p.update(a0=float(a0[s]), w0_um=2.0, tau_fs=30.0, x_off_um=0.0, y_off_um=0.0,
+                 delay_fs=0.0, gamma0=float(g0[s]), sigma_gamma=0.05 * float(g0[s]),
+                 sigma_r_um=3.0, sigma_z_um=5.0, div_mrad=1.0, n_samples=int(n_samples),
+                 n_steps=2048, seed=seed, shot=s, rr_model="quantum", amp_mode="local",
+                 deposit="gauss", kernel_sigma_bins=1.0, chi_fp64=0.1, n_e=256, e_lo=0.0,
+                 e_hi=1.5 * float(g0[s]), n_th=128, n_a=256, n_ph=256, ph_lo=0.0,
+                 ph_hi=1.2 * float(g0[s]))
+        shots.append(p)
+    return shots
+
+
 def scaled(params, n_samples=None, n_steps=None, **kw):
     """A copy with fewer samples / steps (parity-test sizes)."""
     p = copy.deepcopy(params)
