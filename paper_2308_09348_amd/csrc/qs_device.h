@@ -94,23 +94,20 @@ struct RadCell32 {
     float tw, ts;
 };
 
+// The index comes from chi clamped to the octave cells [2^kEMin, 2^(kEMax+1)).
+// Below 2^kEMin the first octave cell's cubic is extrapolated down to chi = 0
+// (t >= -2^kSB32): there g, chi g', chi^2 g'' and h are linear in chi to
+// 1e-12, and so is the cell's cubic.  Above the table the result is not used
+// (the caller reports the range error).
 __device__ __forceinline__ void rad_lookup32(const float *__restrict__ tab, float chi,
                                              RadCell32 &cell) {
-    const uint32_t b = __float_as_uint(chi);
-    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
+    const float xc = fminf(fmaxf(chi, 0x1p-20f), 0x1.fffffep7f);
+    const uint32_t b = __float_as_uint(xc);
+    // cell 1 + (b - bits(2^kEMin)) >> (23 - SB): non-negative by the clamp
+    const uint32_t c = ((b - ((uint32_t)(127 + kEMin) << 23)) >> (23 - kSB32)) + 1u;
     // cell start 2^e (1 + sub/2^SB) and inverse width 2^(SB - e)
-    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
-    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
-    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
-        c = 0;
-        tw = 0x1p20f;
-        ts = 0.0f;
-    }
-    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
-        c = kCells32 - 1;
-        tw = 0.0f;
-        ts = 1.0f;
-    }
+    const float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    const float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
     const float4 *T = reinterpret_cast<const float4 *>(tab);
     cell.q0 = T[c];
     cell.q1 = T[kCells32 + c];
@@ -255,54 +252,67 @@ __device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
 // T3 = g + 2 chi g' + chi^2 g''/2,  T4 = h, so that
 //   dmu/dpsi   = -K a^2 (mu^2 T1 + sig2 T3),
 //   dsig2/dpsi = -2 K a^2 mu sig2 T2 + C_D a^2 |a| mu^4 T4.
-__device__ __forceinline__ void rhs_q32(float mu, float s2, float a2, float aa, float T1, float T2,
-                                        float T3, float T4, const Phys<float> &ph, float &dmu,
-                                        float &ds2) {
-    const float u = ph.K * a2;
+// The factors that depend on the amplitude only are formed once per phase
+// point (stages 2 and 3 share one, stage 4 hands its to the next stage 1).
+struct AmpQ {
+    float nu;   // -K a^2
+    float nu2;  // -2 K a^2
+    float cd;   // C_D a^2 |a|
+    float cpm;  // chi per unit mu: 2 |a| / a_S
+    __device__ __forceinline__ AmpQ() {}
+    __device__ __forceinline__ AmpQ(float a, const Phys<float> &ph) {
+        const float aa = fabsf(a), a2 = a * a;
+        nu = -ph.K * a2;
+        nu2 = 2.0f * nu;
+        cd = ph.CD * aa * a2;
+        cpm = ph.two_over_aS * aa;
+    }
+};
+
+__device__ __forceinline__ void rhs_q32(float mu, float s2, const AmpQ &A, float T1, float T2,
+                                        float T3, float T4, float &dmu, float &ds2) {
     const float mu2 = mu * mu;
-    dmu = -u * fmaf(mu2, T1, s2 * T3);
-    const float D = (ph.CD * aa) * a2 * (mu2 * mu2) * T4;
-    ds2 = fmaf(-2.0f * u * mu * s2, T2, D);
+    dmu = A.nu * fmaf(mu2, T1, s2 * T3);
+    ds2 = fmaf(A.nu2 * mu * s2, T2, A.cd * (mu2 * mu2) * T4);
 }
 
 // One FP32 RK4 step of the quantum moment system with two table reads:
 // stage 2 and stage 4 read LDS, stage 3 reuses stage 2's cell, and stage 4's
-// cell is handed to the next step's stage 1.
-__device__ __forceinline__ void rk4_q32(float mu, float s2, float a1, float ah, float a4, float h,
+// cell is handed to the next step's stage 1 (with its amplitude factors).
+__device__ __forceinline__ void rk4_q32(float mu, float s2, AmpQ &A1, float ah, float a4, float h,
                                         const Phys<float> &ph, const float *__restrict__ tab,
                                         RadCell32 &carry, float &dmu, float &ds2,
                                         float &chi_hi) {
     const float hh = 0.5f * h;
     float g, G1, G2, hq;
-    // stage 1 (cell carried from the previous stage 4)
-    const float aa1 = fabsf(a1), a21 = a1 * a1;
-    const float c1 = ph.two_over_aS * mu * aa1;
+    // stage 1 (cell and amplitude factors carried from the previous stage 4)
+    const float c1 = A1.cpm * mu;
     rad_cell_eval(carry, c1, g, G1, G2, hq);
     float k1m, k1s;
-    rhs_q32(mu, s2, a21, aa1, g, G1, G2, hq, ph, k1m, k1s);
+    rhs_q32(mu, s2, A1, g, G1, G2, hq, k1m, k1s);
     // stage 2 (table read)
-    const float aah = fabsf(ah), a2h = ah * ah;
+    const AmpQ Ah(ah, ph);
     const float m2 = fmaf(hh, k1m, mu), s22 = fmaf(hh, k1s, s2);
-    const float c2 = ph.two_over_aS * m2 * aah;
+    const float c2 = Ah.cpm * m2;
     RadCell32 mid;
     rad_lookup32(tab, c2, mid);
     rad_cell_eval(mid, c2, g, G1, G2, hq);
     float k2m, k2s;
-    rhs_q32(m2, s22, a2h, aah, g, G1, G2, hq, ph, k2m, k2s);
+    rhs_q32(m2, s22, Ah, g, G1, G2, hq, k2m, k2s);
     // stage 3 (same phase as stage 2: reuse its cell)
     const float m3 = fmaf(hh, k2m, mu), s23 = fmaf(hh, k2s, s2);
-    const float c3 = ph.two_over_aS * m3 * aah;
+    const float c3 = Ah.cpm * m3;
     rad_cell_eval(mid, c3, g, G1, G2, hq);
     float k3m, k3s;
-    rhs_q32(m3, s23, a2h, aah, g, G1, G2, hq, ph, k3m, k3s);
+    rhs_q32(m3, s23, Ah, g, G1, G2, hq, k3m, k3s);
     // stage 4 (table read; its cell serves the next step's stage 1)
-    const float aa4 = fabsf(a4), a24 = a4 * a4;
+    A1 = AmpQ(a4, ph);
     const float m4 = fmaf(h, k3m, mu), s24 = fmaf(h, k3s, s2);
-    const float c4 = ph.two_over_aS * m4 * aa4;
+    const float c4 = A1.cpm * m4;
     rad_lookup32(tab, c4, carry);
     rad_cell_eval(carry, c4, g, G1, G2, hq);
     float k4m, k4s;
-    rhs_q32(m4, s24, a24, aa4, g, G1, G2, hq, ph, k4m, k4s);
+    rhs_q32(m4, s24, A1, g, G1, G2, hq, k4m, k4s);
     chi_hi = fmaxf(chi_hi, fmaxf(fmaxf(c1, c2), fmaxf(c3, c4)));
     const float h6 = h * (1.0f / 6.0f);
     dmu = h6 * (k1m + 2.0f * (k2m + k3m) + k4m);

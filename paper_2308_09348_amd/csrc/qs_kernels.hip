@@ -205,7 +205,11 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         double chd = 0.0;
         float aS_prev = local ? a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
         RadCell32 carry;
-        if (QUANTUM) rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS_prev * env32[0]), carry);
+        AmpQ amp1;  // amplitude factors of the next stage 1
+        if (QUANTUM) {
+            amp1 = AmpQ(aS_prev * env32[0], phf);
+            rad_lookup32(tab32, amp1.cpm * mu, carry);
+        }
         // local amplitude: one spatial factor per step, at psi_{j+2}; the
         // stage-2/3 value at psi_j + h/2 is the quadratic through psi_j,
         // psi_{j+1} and psi_{j+2} (error of order h^3 times the third
@@ -227,7 +231,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             const float a1 = aS_prev * env32[2 * j];
             const float ah = aSh * env32[2 * j + 1];
             const float a4 = aS4 * env32[2 * j + 2];
-            const float chi1 = phf.two_over_aS * mu * fabsf(a1);
+            const float chi1 = QUANTUM ? amp1.cpm * mu : phf.two_over_aS * mu * fabsf(a1);
             cmx = fmaxf(cmx, chi1);
             bool promote = false;
             if (PREC == PREC_F32MIX) promote = __any(chi1 > P.chi_fp64);
@@ -253,10 +257,11 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
                 s2 = (float)sn;
                 s2_lo = (float)(sn - (double)s2);
                 // the next FP32 stage 1 needs the cell at the new state
-                rad_lookup32(tab32, phf.two_over_aS * mu * fabsf(aS4 * env32[2 * j + 2]), carry);
+                amp1 = AmpQ(a4, phf);
+                rad_lookup32(tab32, amp1.cpm * mu, carry);
             } else if (QUANTUM) {
                 float dm, ds;
-                rk4_q32(mu, s2, a1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
+                rk4_q32(mu, s2, amp1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
                 comp_add(mu, mu_lo, dm);
                 comp_add(s2, s2_lo, ds);
             } else {
