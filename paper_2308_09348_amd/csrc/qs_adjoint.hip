@@ -41,22 +41,15 @@ struct RadCell6 {
     float tw, ts;
 };
 
+// Index from chi clamped to the octave cells, as rad_lookup32 (the first
+// octave cell extrapolates linearly down to chi = 0).
 __device__ __forceinline__ void rad6_lookup32(const float *__restrict__ tab, float chi,
                                               RadCell6 &cell) {
-    const uint32_t b = __float_as_uint(chi);
-    int c = (int)(b >> (23 - kSB32)) - ((127 + kEMin) << kSB32) + 1;
-    float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
-    float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
-    if (c < 1) {  // chi < 2^kEMin: the first cell, linear in chi
-        c = 0;
-        tw = 0x1p20f;
-        ts = 0.0f;
-    }
-    if (c > kCells32 - 1) {  // beyond the table (reported by the caller)
-        c = kCells32 - 1;
-        tw = 0.0f;
-        ts = 1.0f;
-    }
+    const float xc = fminf(fmaxf(chi, 0x1p-20f), 0x1.fffffep7f);
+    const uint32_t b = __float_as_uint(xc);
+    const uint32_t c = ((b - ((uint32_t)(127 + kEMin) << 23)) >> (23 - kSB32)) + 1u;
+    const float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    const float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
     const float4 *T = reinterpret_cast<const float4 *>(tab);
 #pragma unroll
     for (int f = 0; f < kDerivFuncs; ++f) cell.q[f] = T[f * kCells32 + c];
