@@ -467,14 +467,13 @@ struct NoVisit {
     void operator()(double, const T &, const T &, const Rhs<T> &) const {}
 };
 
-/* One sample's trajectory.  visit(w, mu_s, a_s, k_s) is called at every RK4
- * stage with its quadrature weight w (h/6, h/3, h/3, h/6), the stage state
- * and amplitude, and the stage's right-hand side. */
+/* The trajectory of a sample with initial state s and geometry gmt.
+ * visit(w, mu_s, a_s, k_s) is called at every RK4 stage with its quadrature
+ * weight w (h/6, h/3, h/3, h/6), the stage state and amplitude, and the
+ * stage's right-hand side. */
 template <class T, class Visit>
-SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i,
-                        Visit &visit) {
-    const SampleIn<T> s = make_sample<T>(p, P, i);
-    const Geometry<T> gmt = geometry<T>(p, P, s);
+SampleOut<T> evolve(const qso_problem *p, const Derived &d, const Params<T> &P,
+                    const SampleIn<T> &s, const Geometry<T> &gmt, Visit &visit) {
     T mu = s.gamma0, sig2(0.0);
     double chimax = 0.0;
     const double h = d.h;
@@ -521,6 +520,15 @@ SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> 
     o.gamma0 = s.gamma0;
     o.x = s.x; o.y = s.y; o.z = s.z;
     return o;
+}
+
+/* One sample's trajectory (its draw, its geometry, its evolution). */
+template <class T, class Visit>
+SampleOut<T> run_sample(const qso_problem *p, const Derived &d, const Params<T> &P, int64_t i,
+                        Visit &visit) {
+    const SampleIn<T> s = make_sample<T>(p, P, i);
+    const Geometry<T> gmt = geometry<T>(p, P, s);
+    return evolve<T>(p, d, P, s, gmt, visit);
 }
 
 template <class T>
@@ -927,6 +935,189 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
             moments[QSO_M_MAX_CHI] = chimax[0];
             moments[QSO_M_RAD_FRAC] = sums[0][SRAD].value() / W;
             moments[QSO_M_MEAN_SIGF] = sums[0][SSIGF].value() / W;
+        }
+    }
+    return 0;
+}
+
+/* ---- plane-wave reconstruction (Sec. 3.2, Sec. 3.3) --------------------- */
+/* The paper rebuilds the 3D spectrum as a sum, over a uniform discrete set of
+ * a0,eff values, of plane-wave spectra weighted by dN_b/da0,eff.  In A0EFF
+ * mode a sample's trajectory depends only on its a0,eff and its initial
+ * Lorentz factor, so the plane-wave runs are made on the nodes
+ *   a_k     = a0 k / (K - 1),                          k = 0 .. K-1,
+ *   gamma_m = gamma0 + 6 sigma_gamma (2 m / (M - 1) - 1), m = 0 .. M-1
+ * (M = 1, gamma_0 = gamma0, when sigma_gamma = 0; six standard deviations
+ * hold every Box-Muller normal drawn from 24-bit uniforms, |n| <= 5.89).
+ * Steps, in the paper's order:
+ *   1. the plane-wave runs: the moment system at every node (a_k, gamma_m);
+ *   2. the weights: each sample spreads its unit weight over the four nodes
+ *      around (a0,eff, gamma0_i) with bilinear weights, giving the node
+ *      weights H_n, the discrete joint distribution of (a0,eff, gamma0);
+ *   3. the sum: energy spectrum = sum_n H_n x (law of node n deposited).
+ * The angle law of a sample keeps its own direction; its Sec. 5.2 width is
+ * the bilinear interpolation of the nodes' widths.  The a0,eff histogram and
+ * the angle and a0,eff moments are those of the samples; the energy moments
+ * and the radiated fraction are H-weighted node values, and the largest chi is
+ * that of the nodes with weight.                                            */
+int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int64_t i_begin,
+                   int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
+                   double *a0eff_hist, double *moments, double *node_states,
+                   double *node_weights) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
+    if (p->amp_mode != QSO_AMP_A0EFF || n_anodes < 2) return -1;
+    if (p->sigma_gamma > 0.0 ? n_gnodes < 2 : n_gnodes != 1) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int K = n_anodes, M = n_gnodes, NN = K * M;
+    const double g_lo = p->gamma0 - 6.0 * p->sigma_gamma;
+    const double g_step = M > 1 ? 12.0 * p->sigma_gamma / (M - 1) : 0.0;
+    const Params<double> P = [&] {
+        Params<double> q = params<double>(p);
+        finish_params(p, q);
+        return q;
+    }();
+
+    /* 1. plane-wave runs on the nodes (node n = k M + m) */
+    std::vector<SampleOut<double>> node(NN);
+    std::vector<double> node_sigth(NN);
+    int bad_node = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : bad_node)
+    for (int n = 0; n < NN; ++n) {
+        const int k = n / M, m = n % M;
+        SampleIn<double> s{};
+        s.gamma0 = M > 1 ? g_lo + m * g_step : p->gamma0;
+        Geometry<double> gmt{};
+        gmt.S0 = (double)k / (K - 1);
+        NoVisit none;
+        node[n] = evolve<double>(p, d, P, s, gmt, none);
+        node_sigth[n] = node[n].sigth;
+        if (!std::isfinite(node[n].mu) || !std::isfinite(node[n].sig2)) bad_node = 1;
+    }
+    if (bad_node) return -2;
+
+    /* 2. node weights and the per-sample observables */
+    const int nt = p->n_th, na = p->n_a, ne = p->n_e;
+    const int64_t total = i_end - i_begin;
+    enum { S1X, S2X, S1Y, S2Y, SAEFF, NSUM };
+    std::vector<std::vector<double>> hw(nthreads, std::vector<double>(NN, 0.0));
+    std::vector<std::vector<double>> ht(nthreads, std::vector<double>(nt + 2, 0.0));
+    std::vector<std::vector<double>> ha(nthreads, std::vector<double>(na, 0.0));
+    std::vector<std::vector<KSum>> sums(nthreads, std::vector<KSum>(NSUM));
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        for (int64_t i = b; i < e; ++i) {
+            const SampleIn<double> s = make_sample<double>(p, P, i);
+            const Geometry<double> gmt = geometry<double>(p, P, s);
+            /* bilinear weights of the sample on the node grid */
+            const double ta = gmt.S0 * (K - 1);
+            int k = (int)std::floor(ta);
+            if (k > K - 2) k = K - 2;
+            if (k < 0) k = 0;
+            const double fa = ta - k;
+            int m = 0;
+            double fg = 0.0;
+            if (M > 1) {
+                double tg = (s.gamma0 - g_lo) / g_step;
+                if (tg < 0.0) tg = 0.0;
+                if (tg > M - 1) tg = M - 1;
+                m = (int)std::floor(tg);
+                if (m > M - 2) m = M - 2;
+                fg = tg - m;
+            }
+            const int n00 = k * M + m;
+            const int n10 = n00 + M;
+            double w[4] = {(1.0 - fa) * (1.0 - fg), fa * (1.0 - fg), 0.0, 0.0};
+            int idx[4] = {n00, n10, n00, n10};
+            if (M > 1) {
+                w[2] = (1.0 - fa) * fg;
+                w[3] = fa * fg;
+                idx[2] = n00 + 1;
+                idx[3] = n10 + 1;
+            }
+            double sigth = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                hw[t][idx[q]] += w[q];
+                sigth += w[q] * node_sigth[idx[q]];
+            }
+            const double thx = 1e3 * s.thx, thy = 1e3 * s.thy;
+            deposit<double>(thx, sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
+                            p->th_hi_mrad, nt, ht[t].data());
+            int ka = (int)std::floor(gmt.S0 * na);
+            if (ka > na - 1) ka = na - 1;
+            if (ka < 0) ka = 0;
+            ha[t][ka] += 1.0;
+            sums[t][S1X].add(thx);
+            sums[t][S2X].add(thx * thx + sigth * sigth);
+            sums[t][S1Y].add(thy);
+            sums[t][S2Y].add(thy * thy);
+            sums[t][SAEFF].add(p->a0 * gmt.S0);
+        }
+    }
+    for (int t = 1; t < nthreads; ++t) {
+        for (int n = 0; n < NN; ++n) hw[0][n] += hw[t][n];
+        for (int k = 0; k < nt + 2; ++k) ht[0][k] += ht[t][k];
+        for (int k = 0; k < na; ++k) ha[0][k] += ha[t][k];
+        for (int q = 0; q < NSUM; ++q) {
+            sums[0][q].add(sums[t][q].s);
+            sums[0][q].add(sums[t][q].c);
+        }
+    }
+    const std::vector<double> &H = hw[0];
+
+    /* 3. the sum over nodes of H_n times node n's deposited energy law */
+    std::vector<double> he(ne + 2, 0.0), law(ne + 2);
+    KSum s1e, s2e, srad, ssigf;
+    double chimax = 0.0;
+    for (int n = 0; n < NN; ++n) {
+        if (H[n] == 0.0) continue;
+        const SampleOut<double> &o = node[n];
+        const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
+        std::fill(law.begin(), law.end(), 0.0);
+        deposit<double>(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+                        law.data());
+        for (int b = 0; b < ne + 2; ++b) he[b] += H[n] * law[b];
+        const double de = o.mu - p->gamma0;
+        s1e.add(H[n] * de);
+        s2e.add(H[n] * (de * de + std::fmax(o.sig2, 0.0)));
+        srad.add(H[n] * (1.0 - o.mu / o.gamma0));
+        ssigf.add(H[n] * sigf);
+        chimax = std::fmax(chimax, o.chimax);
+    }
+    if (energy_hist) std::memcpy(energy_hist, he.data(), sizeof(double) * (ne + 2));
+    if (angle_hist) std::memcpy(angle_hist, ht[0].data(), sizeof(double) * (nt + 2));
+    if (a0eff_hist) std::memcpy(a0eff_hist, ha[0].data(), sizeof(double) * na);
+    if (node_weights) std::memcpy(node_weights, H.data(), sizeof(double) * NN);
+    if (node_states) {
+        for (int n = 0; n < NN; ++n) {
+            double *r = node_states + (size_t)n * QSO_N_N;
+            r[QSO_N_A] = p->a0 * ((double)(n / M) / (K - 1));
+            r[QSO_N_GAMMA0] = node[n].gamma0;
+            r[QSO_N_MU] = node[n].mu;
+            r[QSO_N_SIG2] = node[n].sig2;
+            r[QSO_N_CHIMAX] = node[n].chimax;
+        }
+    }
+    if (moments) {
+        for (int q = 0; q < QSO_M_N; ++q) moments[q] = 0.0;
+        const double W = (double)total;
+        moments[QSO_M_WEIGHT] = W;
+        if (total > 0) {
+            const double m1 = s1e.value() / W;
+            moments[QSO_M_MEAN_G] = p->gamma0 + m1;
+            moments[QSO_M_STD_G] = std::sqrt(std::fmax(s2e.value() / W - m1 * m1, 0.0));
+            moments[QSO_M_MEAN_THX] = sums[0][S1X].value() / W;
+            moments[QSO_M_RMS_THX] = std::sqrt(sums[0][S2X].value() / W);
+            moments[QSO_M_MEAN_THY] = sums[0][S1Y].value() / W;
+            moments[QSO_M_RMS_THY] = std::sqrt(sums[0][S2Y].value() / W);
+            moments[QSO_M_MEAN_AEFF] = sums[0][SAEFF].value() / W;
+            moments[QSO_M_MAX_CHI] = chimax;
+            moments[QSO_M_RAD_FRAC] = srad.value() / W;
+            moments[QSO_M_MEAN_SIGF] = ssigf.value() / W;
         }
     }
     return 0;

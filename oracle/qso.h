@@ -119,6 +119,29 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
                 double *energy_hist, double *angle_hist, double *a0eff_hist,
                 double *moments);
 
+/* Node record of the plane-wave reconstruction (index order of the doubles). */
+enum {
+    QSO_N_A = 0,      /* the node's a0,eff                                   */
+    QSO_N_GAMMA0,     /* its initial Lorentz factor                          */
+    QSO_N_MU,         /* final mean Lorentz factor                           */
+    QSO_N_SIG2,       /* final energy variance                               */
+    QSO_N_CHIMAX,     /* max chi at the step starts                          */
+    QSO_N_N
+};
+
+/* Plane-wave reconstruction of the A0EFF forward pass (Sec. 3.2, 3.3): the
+ * moment system runs on n_anodes x n_gnodes nodes (a0,eff uniform over
+ * [0, a0]; gamma0 uniform over gamma0 +- 6 sigma_gamma, one node when
+ * sigma_gamma = 0), samples [i_begin, i_end) give the bilinear node weights,
+ * and the energy histogram is the weighted sum of the nodes' deposited laws.
+ * node_states ([nodes][QSO_N_N]) and node_weights ([nodes], node = k
+ * n_gnodes + m) are optional.  Returns 0, -1 on invalid input (also when
+ * amp_mode is not A0EFF), -2 on a non-finite node state. */
+int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int64_t i_begin,
+                   int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
+                   double *a0eff_hist, double *moments, double *node_states,
+                   double *node_weights);
+
 /* Derivatives with respect to the eight parameters, in this order:
  * (a0, w0_um, x_off_um, y_off_um, delay_fs, gamma0, sigma_gamma, div_mrad).
  * qso_sample_grad: out[0] = mu_f, out[1..8] = d mu_f / d p, out[9] = sig2_f,

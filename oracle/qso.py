@@ -24,6 +24,8 @@ S_MU, S_SIG2, S_THX, S_THY, S_SIGTH, S_AEFF, S_CHIMAX, S_GAMMA0, S_X, S_Y, S_Z, 
 M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, \
     M_MEAN_AEFF, M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF = range(11)
 M_N = 16
+# node record of the plane-wave reconstruction
+N_A, N_GAMMA0, N_MU, N_SIG2, N_CHIMAX, N_N = range(6)
 
 
 class Problem(ctypes.Structure):
@@ -90,6 +92,9 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int32, dp]
         L.qso_deposit.restype = ctypes.c_int
+        L.qso_factorised.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        L.qso_factorised.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -193,6 +198,29 @@ def forward(params, i_begin=0, i_end=None, nthreads=0):
     if rc == -2:
         raise FloatingPointError("non-finite state")
     return {"energy_hist": he, "angle_hist": ht, "a0eff_hist": ha, "moments": mo}
+
+
+def factorised(params, n_anodes, n_gnodes, i_begin=0, i_end=None, nthreads=0):
+    """Plane-wave reconstruction of the A0EFF forward pass on an n_anodes x
+    n_gnodes node grid: histograms, moments, node records [nodes, N_N] and
+    node weights [nodes] (node = k n_gnodes + m)."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    p = problem(params)
+    he = np.zeros(params["n_e"] + 2)
+    ht = np.zeros(params["n_th"] + 2)
+    ha = np.zeros(params["n_a"])
+    mo = np.zeros(M_N)
+    ns = np.zeros((n_anodes * n_gnodes, N_N))
+    nw = np.zeros(n_anodes * n_gnodes)
+    rc = lib().qso_factorised(ctypes.byref(p), n_anodes, n_gnodes, i_begin, i_end, nthreads,
+                              _dp(he), _dp(ht), _dp(ha), _dp(mo), _dp(ns), _dp(nw))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return {"energy_hist": he, "angle_hist": ht, "a0eff_hist": ha, "moments": mo,
+            "node_states": ns, "node_weights": nw}
 
 
 PARAM_NAMES = ["a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
