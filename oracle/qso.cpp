@@ -941,25 +941,26 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
 }
 
 /* ---- plane-wave reconstruction (Sec. 3.2, Sec. 3.3) --------------------- */
-/* The paper rebuilds the 3D spectrum as a sum, over a uniform discrete set of
- * a0,eff values, of plane-wave spectra weighted by dN_b/da0,eff.  In A0EFF
- * mode a sample's trajectory depends only on its a0,eff and its initial
- * Lorentz factor, so the plane-wave runs are made on the nodes
+/* The paper rebuilds the 3D spectrum from plane-wave runs over a uniform
+ * discrete set of a0,eff values weighted by dN_b/da0,eff: every volume element
+ * takes the plane-wave result at its a0,eff.  In A0EFF mode a sample's
+ * trajectory depends only on its a0,eff and its initial Lorentz factor, so the
+ * plane-wave runs are made on the nodes
  *   a_k     = a0 k / (K - 1),                          k = 0 .. K-1,
  *   gamma_m = gamma0 + 6 sigma_gamma (2 m / (M - 1) - 1), m = 0 .. M-1
  * (M = 1, gamma_0 = gamma0, when sigma_gamma = 0; six standard deviations
  * hold every Box-Muller normal drawn from 24-bit uniforms, |n| <= 5.89).
- * Steps, in the paper's order:
+ * Steps:
  *   1. the plane-wave runs: the moment system at every node (a_k, gamma_m);
- *   2. the weights: each sample spreads its unit weight over the four nodes
- *      around (a0,eff, gamma0_i) with bilinear weights, giving the node
- *      weights H_n, the discrete joint distribution of (a0,eff, gamma0);
- *   3. the sum: energy spectrum = sum_n H_n x (law of node n deposited).
- * The angle law of a sample keeps its own direction; its Sec. 5.2 width is
- * the bilinear interpolation of the nodes' widths.  The a0,eff histogram and
- * the angle and a0,eff moments are those of the samples; the energy moments
- * and the radiated fraction are H-weighted node values, and the largest chi is
- * that of the nodes with weight.                                            */
+ *   2. each sample takes the bilinear interpolant, at (a0,eff, gamma0_i), of
+ *      the nodes' final mean, variance and largest chi; the bilinear weights
+ *      summed over the samples are the node weights H_n (the discrete joint
+ *      distribution of a0,eff and gamma0);
+ *   3. the sample is deposited as in the direct pass, with its own direction
+ *      and a0,eff (Sec. 5.2 width from its interpolated state).
+ * (Reading: the weighted sum of the paper is taken with the weights carried
+ * by the samples rather than by bins of a0,eff, so that node laws narrower
+ * than the node spacing are not mixed into a comb.)                        */
 int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int64_t i_begin,
                    int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
                    double *a0eff_hist, double *moments, double *node_states,
@@ -981,7 +982,6 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
 
     /* 1. plane-wave runs on the nodes (node n = k M + m) */
     std::vector<SampleOut<double>> node(NN);
-    std::vector<double> node_sigth(NN);
     int bad_node = 0;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : bad_node)
     for (int n = 0; n < NN; ++n) {
@@ -992,19 +992,20 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
         gmt.S0 = (double)k / (K - 1);
         NoVisit none;
         node[n] = evolve<double>(p, d, P, s, gmt, none);
-        node_sigth[n] = node[n].sigth;
         if (!std::isfinite(node[n].mu) || !std::isfinite(node[n].sig2)) bad_node = 1;
     }
     if (bad_node) return -2;
 
-    /* 2. node weights and the per-sample observables */
-    const int nt = p->n_th, na = p->n_a, ne = p->n_e;
+    /* 2-3. samples: interpolated plane-wave state, deposit, node weights */
+    const int ne = p->n_e, nt = p->n_th, na = p->n_a;
     const int64_t total = i_end - i_begin;
-    enum { S1X, S2X, S1Y, S2Y, SAEFF, NSUM };
+    enum { S1E, S2E, S1X, S2X, S1Y, S2Y, SAEFF, SRAD, SSIGF, NSUM };
     std::vector<std::vector<double>> hw(nthreads, std::vector<double>(NN, 0.0));
+    std::vector<std::vector<double>> he(nthreads, std::vector<double>(ne + 2, 0.0));
     std::vector<std::vector<double>> ht(nthreads, std::vector<double>(nt + 2, 0.0));
     std::vector<std::vector<double>> ha(nthreads, std::vector<double>(na, 0.0));
     std::vector<std::vector<KSum>> sums(nthreads, std::vector<KSum>(NSUM));
+    std::vector<double> chimax(nthreads, 0.0);
 #pragma omp parallel num_threads(nthreads)
     {
         const int t = omp_get_thread_num();
@@ -1039,59 +1040,53 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
                 idx[2] = n00 + 1;
                 idx[3] = n10 + 1;
             }
-            double sigth = 0.0;
+            double mu = 0.0, sig2 = 0.0, cmx = 0.0;
             for (int q = 0; q < 4; ++q) {
                 hw[t][idx[q]] += w[q];
-                sigth += w[q] * node_sigth[idx[q]];
+                mu += w[q] * node[idx[q]].mu;
+                sig2 += w[q] * node[idx[q]].sig2;
+                cmx += w[q] * node[idx[q]].chimax;
             }
+            const double sigf = std::sqrt(std::fmax(sig2, 0.0));
+            const double aeff = p->a0 * gmt.S0;
             const double thx = 1e3 * s.thx, thy = 1e3 * s.thy;
+            const double sigth = 1e3 * p->c_theta * std::sqrt(2.0 / kPi) * aeff * sigf / (mu * mu);
+            deposit<double>(mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+                            he[t].data());
             deposit<double>(thx, sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
                             p->th_hi_mrad, nt, ht[t].data());
             int ka = (int)std::floor(gmt.S0 * na);
             if (ka > na - 1) ka = na - 1;
             if (ka < 0) ka = 0;
             ha[t][ka] += 1.0;
+            const double de = mu - p->gamma0;
+            sums[t][S1E].add(de);
+            sums[t][S2E].add(de * de + std::fmax(sig2, 0.0));
             sums[t][S1X].add(thx);
             sums[t][S2X].add(thx * thx + sigth * sigth);
             sums[t][S1Y].add(thy);
             sums[t][S2Y].add(thy * thy);
-            sums[t][SAEFF].add(p->a0 * gmt.S0);
+            sums[t][SAEFF].add(aeff);
+            sums[t][SRAD].add(1.0 - mu / s.gamma0);
+            sums[t][SSIGF].add(sigf);
+            chimax[t] = std::fmax(chimax[t], cmx);
         }
     }
     for (int t = 1; t < nthreads; ++t) {
         for (int n = 0; n < NN; ++n) hw[0][n] += hw[t][n];
+        for (int k = 0; k < ne + 2; ++k) he[0][k] += he[t][k];
         for (int k = 0; k < nt + 2; ++k) ht[0][k] += ht[t][k];
         for (int k = 0; k < na; ++k) ha[0][k] += ha[t][k];
         for (int q = 0; q < NSUM; ++q) {
             sums[0][q].add(sums[t][q].s);
             sums[0][q].add(sums[t][q].c);
         }
+        chimax[0] = std::fmax(chimax[0], chimax[t]);
     }
-    const std::vector<double> &H = hw[0];
-
-    /* 3. the sum over nodes of H_n times node n's deposited energy law */
-    std::vector<double> he(ne + 2, 0.0), law(ne + 2);
-    KSum s1e, s2e, srad, ssigf;
-    double chimax = 0.0;
-    for (int n = 0; n < NN; ++n) {
-        if (H[n] == 0.0) continue;
-        const SampleOut<double> &o = node[n];
-        const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
-        std::fill(law.begin(), law.end(), 0.0);
-        deposit<double>(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
-                        law.data());
-        for (int b = 0; b < ne + 2; ++b) he[b] += H[n] * law[b];
-        const double de = o.mu - p->gamma0;
-        s1e.add(H[n] * de);
-        s2e.add(H[n] * (de * de + std::fmax(o.sig2, 0.0)));
-        srad.add(H[n] * (1.0 - o.mu / o.gamma0));
-        ssigf.add(H[n] * sigf);
-        chimax = std::fmax(chimax, o.chimax);
-    }
-    if (energy_hist) std::memcpy(energy_hist, he.data(), sizeof(double) * (ne + 2));
+    if (energy_hist) std::memcpy(energy_hist, he[0].data(), sizeof(double) * (ne + 2));
     if (angle_hist) std::memcpy(angle_hist, ht[0].data(), sizeof(double) * (nt + 2));
     if (a0eff_hist) std::memcpy(a0eff_hist, ha[0].data(), sizeof(double) * na);
-    if (node_weights) std::memcpy(node_weights, H.data(), sizeof(double) * NN);
+    if (node_weights) std::memcpy(node_weights, hw[0].data(), sizeof(double) * NN);
     if (node_states) {
         for (int n = 0; n < NN; ++n) {
             double *r = node_states + (size_t)n * QSO_N_N;
@@ -1107,17 +1102,17 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
         const double W = (double)total;
         moments[QSO_M_WEIGHT] = W;
         if (total > 0) {
-            const double m1 = s1e.value() / W;
+            const double m1 = sums[0][S1E].value() / W;
             moments[QSO_M_MEAN_G] = p->gamma0 + m1;
-            moments[QSO_M_STD_G] = std::sqrt(std::fmax(s2e.value() / W - m1 * m1, 0.0));
+            moments[QSO_M_STD_G] = std::sqrt(std::fmax(sums[0][S2E].value() / W - m1 * m1, 0.0));
             moments[QSO_M_MEAN_THX] = sums[0][S1X].value() / W;
             moments[QSO_M_RMS_THX] = std::sqrt(sums[0][S2X].value() / W);
             moments[QSO_M_MEAN_THY] = sums[0][S1Y].value() / W;
             moments[QSO_M_RMS_THY] = std::sqrt(sums[0][S2Y].value() / W);
             moments[QSO_M_MEAN_AEFF] = sums[0][SAEFF].value() / W;
-            moments[QSO_M_MAX_CHI] = chimax;
-            moments[QSO_M_RAD_FRAC] = srad.value() / W;
-            moments[QSO_M_MEAN_SIGF] = ssigf.value() / W;
+            moments[QSO_M_MAX_CHI] = chimax[0];
+            moments[QSO_M_RAD_FRAC] = sums[0][SRAD].value() / W;
+            moments[QSO_M_MEAN_SIGF] = sums[0][SSIGF].value() / W;
         }
     }
     return 0;

@@ -132,11 +132,12 @@ enum {
 /* Plane-wave reconstruction of the A0EFF forward pass (Sec. 3.2, 3.3): the
  * moment system runs on n_anodes x n_gnodes nodes (a0,eff uniform over
  * [0, a0]; gamma0 uniform over gamma0 +- 6 sigma_gamma, one node when
- * sigma_gamma = 0), samples [i_begin, i_end) give the bilinear node weights,
- * and the energy histogram is the weighted sum of the nodes' deposited laws.
- * node_states ([nodes][QSO_N_N]) and node_weights ([nodes], node = k
- * n_gnodes + m) are optional.  Returns 0, -1 on invalid input (also when
- * amp_mode is not A0EFF), -2 on a non-finite node state. */
+ * sigma_gamma = 0); each of the samples [i_begin, i_end) takes the bilinear
+ * interpolant of the node states at its (a0,eff, gamma0) and is deposited as
+ * in qso_forward.  node_states ([nodes][QSO_N_N]) and node_weights ([nodes],
+ * the samples' bilinear weights summed; node = k n_gnodes + m) are optional.
+ * Returns 0, -1 on invalid input (also when amp_mode is not A0EFF), -2 on a
+ * non-finite node state. */
 int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int64_t i_begin,
                    int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
                    double *a0eff_hist, double *moments, double *node_states,

@@ -1,16 +1,17 @@
 """Pins of the oracle's plane-wave reconstruction (Sec. 3.2, Sec. 3.3): the
-3D spectrum as a dN_b/da0,eff-weighted sum of plane-wave runs, made on an
-(a0,eff, gamma0) node grid.
+3D spectrum from plane-wave runs made on an (a0,eff, gamma0) node grid, each
+sample taking the plane-wave result interpolated at its own a0,eff and
+gamma0 (the samples carry the dN_b/da0,eff weights).
 
 What fixes it other than itself:
   - the node runs are plane-wave runs: classically they follow eq. PWCRR with
     a0 replaced by the node's a0,eff, and a node without field keeps gamma0;
-  - when every sample sits on a node (plane wave, no energy spread) the sum
-    reduces to the direct Monte-Carlo pass exactly;
-  - the mixture of node values is a bilinear interpolant, so its mean
-    departs from the exact classical mean by at most (da^2/8) max|mu_aa| +
-    (dg^2/8) max|mu_gg| a sample (closed-form second derivatives of eq.
-    PWCRR);
+  - when every sample sits on a node (plane wave, no energy spread) the
+    reconstruction reduces to the direct Monte-Carlo pass exactly;
+  - a sample's final mean is the bilinear interpolant of the node means, so
+    the mean departs from the exact classical mean by at most (da^2/8)
+    max|mu_aa| + (dg^2/8) max|mu_gg| a sample (closed-form second
+    derivatives of eq. PWCRR);
   - on a grid refined by two the error against the direct pass falls by
     about four (second order), and the weights conserve every sample.
 Nothing here calls the HIP library.
@@ -117,8 +118,8 @@ def test_interpolation_error_within_the_bilinear_bound(oracle):
         mean = f["moments"][oracle.M_MEAN_G]
         err = abs(mean - exact)
         assert err <= bound + 1e-8 * exact, (K, M, err, bound)
-        # the interpolant lies above a concave-in-a map: the error is real
-        # and of the bound's order, so the bound is not vacuous
+        # the error is real and of the bound's order, so the bound is not
+        # vacuous
         assert err >= 0.05 * bound, (K, M, err, bound)
 
 
