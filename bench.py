@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--quantum-batch-steps", type=int, default=1,
                     help="timed steps of the quantum batch with gradients and photon spectra "
                          "(0: skip)")
+    ap.add_argument("--factorised-steps", type=int, default=10,
+                    help="steps of the plane-wave reconstruction leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -232,6 +234,49 @@ def quantum_batch_leg(ctx, workloads, torch, steps):
             "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt}
 
 
+def factorised_leg(ctx, workloads, torch, steps):
+    """The focused workload in A0EFF mode (2^22 samples x 1024 steps, quantum,
+    FP32): the direct pass against the plane-wave reconstruction on a 61 x 64
+    (a0,eff, gamma0) node grid, both timed over whole passes."""
+    p = dict(workloads.focused_3d(), amp_mode="a0eff")
+    n, N = p["n_samples"], p["n_steps"]
+    K, M = 61, 64
+    out = ctx.forward(p)
+    batch = ctx.prepare_factorised([p], K, M)
+    fact = ctx.run_factorised(batch, single=True)[0]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_direct = timed(lambda: ctx.forward(p, out=out, check=False))
+    t_fact = timed(lambda: ctx.run_factorised(batch, check=False, single=True))
+    ctx.set_profiling(True)
+    ctx.run_factorised(batch, check=False, single=True)
+    parts = ctx.last_timings()
+    ctx.set_profiling(False)
+    for o in (out, fact):
+        if int(o["status"].item()) != 0:
+            raise RuntimeError("device status in the reconstruction leg")
+    hd, hf = out["energy_hist"].cpu().numpy(), fact["energy_hist"].cpu().numpy()
+    md, mf = out["moments"].cpu().numpy(), fact["moments"].cpu().numpy()
+    return {"workload": "focused single shot in A0EFF mode (2^22 samples x 1024 steps, quantum, "
+                        "FP32, CIC); plane-wave reconstruction on 61 a0,eff x 64 gamma0 nodes",
+            "n_samples": n, "n_steps": N, "nodes": K * M, "steps": steps,
+            "direct_ms": 1e3 * t_direct, "factorised_ms": 1e3 * t_fact,
+            "speedup": t_direct / t_fact,
+            "ms_parts": {"node_runs": parts["phase"], "weights": parts["deposit"],
+                         "contraction_finalize": parts["finalize"]},
+            "equivalent_sample_steps_per_s": n * N / t_fact,
+            "l1_vs_direct": float(np.abs(hf - hd).sum() / n),
+            "mean_gamma_rel_diff": float(abs(mf[1] - md[1]) / md[1])}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -314,6 +359,8 @@ def main():
             "steps": args.batched_steps, "ms_per_batch": 1e3 * dt,
             "spectra_per_s": len(shots) / dt,
             "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt}
+    if args.factorised_steps > 0:
+        line["factorised"] = factorised_leg(ctx, workloads, torch, args.factorised_steps)
     if args.adjoint_steps > 0:
         line["adjoint"] = adjoint_leg(ctx, qs, workloads, torch, args.adjoint_steps)
     if args.quantum_batch_steps > 0:

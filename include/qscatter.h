@@ -345,6 +345,48 @@ qs_status qs_photon_cdf(qs_ctx *ctx, int64_t n, const double *chi, const double 
 qs_status qs_radiation_derivs(qs_ctx *ctx, int32_t precision, int64_t n, const double *chi,
                               double *out, void *stream);
 
+/* Node grid of the plane-wave reconstruction of one shot.  a0,eff nodes
+ * a_k = a0 k / (n_a - 1), k = 0 .. n_a - 1; gamma0 nodes gamma_m = gamma0 +
+ * 6 sigma_gamma (2 m / (n_g - 1) - 1), m = 0 .. n_g - 1 (six standard
+ * deviations hold every drawn sample); node index k n_g + m. */
+typedef struct qs_node_grid {
+    int32_t n_a;          /* >= 2                                                */
+    int32_t n_g;          /* >= 2 when sigma_gamma > 0, exactly 1 when it is 0   */
+    double *node_states;  /* optional device [n_a n_g][5]: a0,eff, gamma0, mu_f,
+                             sig2_f, largest chi at a step start; NULL for none */
+    double *node_weights; /* optional device [n_a n_g]: the samples' bilinear
+                             weights summed per node (they add up to
+                             n_samples); NULL for none                         */
+} qs_node_grid;
+
+/* The A0EFF forward pass by the paper's plane-wave reconstruction (Sec. 3.2:
+ * the 3D spectrum from plane-wave runs over a uniform a0,eff set weighted by
+ * dN_b/da0,eff; Sec. 3.3 for the quantum case).  The moment system runs once
+ * per node of `grid` (the plane-wave runs); each sample, drawn as in
+ * qs_forward, takes the bilinear interpolant of the nodes' final mean,
+ * variance and largest chi at its (a0,eff, gamma0_i) and is deposited as in
+ * qs_forward (histograms, moments, Sec. 5.2 width from its interpolated state
+ * and its own a0,eff).  The result converges to qs_forward's at second order
+ * in the node spacing.  num->amp_mode must be QS_AMP_A0EFF; num->precision
+ * and chi_fp64 apply to the node runs; sample records (out->samples) hold the
+ * interpolated state, with QS_S_X .. QS_S_Z zero as in qs_forward.  When
+ * grid->node_weights is requested, n_a n_g 8-byte words must fit the 160 KiB
+ * LDS of a CU (20480 nodes); at most 2^20 nodes otherwise.
+ * Errors: QS_EINVAL (as qs_forward; grid NULL or out of range; amp_mode not
+ * A0EFF), QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_forward_factorised(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                                const qs_numerics *num, const qs_bins *bins,
+                                const qs_node_grid *grid, const qs_outputs *out, void *stream);
+
+/* qs_forward_factorised over many shots in one launch (rules of
+ * qs_forward_batched; shot k uses grids[k] and RNG counter word num->shot + k,
+ * and gives bit-for-bit the single-shot result with num->shot + k). */
+qs_status qs_forward_factorised_batched(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers,
+                                        const qs_beam *beams, const int64_t *n_samples,
+                                        const qs_numerics *num, const qs_bins *bins,
+                                        const qs_node_grid *grids, const qs_outputs *outs,
+                                        void *stream);
+
 /* Synchronise `stream` and return the device status word of the last call
  * that wrote `status` (device pointer) -- QS_OK, QS_ENONFINITE or QS_ERANGE. */
 qs_status qs_sync_status(qs_ctx *ctx, const int32_t *status, void *stream);
@@ -357,7 +399,9 @@ qs_status qs_set_profiling(qs_ctx *ctx, int on);
 
 /* Durations in milliseconds of the kernels of the last qs_forward enqueued
  * with profiling on: ms[0] envelope table, ms[1] accumulator clear, ms[2]
- * phase integration, ms[3] deposit, ms[4] finalize (host array of 5).
+ * phase integration, ms[3] deposit, ms[4] finalize (host array of 5).  After
+ * qs_forward_factorised: ms[2] node runs, ms[3] interpolation pass, ms[4]
+ * deposit and finalize.
  * Waits for that call's last event.  Errors: QS_EINVAL (profiling off or no
  * profiled call yet), QS_EDEVICE. */
 qs_status qs_last_timings(qs_ctx *ctx, double *ms);

@@ -179,6 +179,77 @@ class Context:
         list of per-shot result dictionaries (device tensors)."""
         return self.run_batch(self.prepare_batch(shots), stream=stream, check=check, tape=tape)
 
+    def forward_factorised(self, params, n_anodes=61, n_gnodes=None, nodes=False, stream=None,
+                           check=True, sample_stride=0, n_sample_records=0):
+        """The A0EFF forward pass by plane-wave reconstruction on an n_anodes x
+        n_gnodes node grid (n_gnodes defaults to 64, or 1 without an energy
+        spread); returns a dict of device tensors, with "node_states"
+        [nodes, NODE_FIELDS] and "node_weights" [nodes] when ``nodes``, and
+        "samples" [n_sample_records, S_N] (every sample_stride-th sample)."""
+        torch = _torch()
+        b = self.prepare_factorised([params], n_anodes, n_gnodes, nodes)
+        if n_sample_records > 0:
+            o = b.out[0]
+            o["samples"] = torch.empty((n_sample_records, _lib.S_N), dtype=torch.float64,
+                                       device=torch.device("cuda", self.device))
+            b.outs[0].samples = o["samples"].data_ptr()
+            b.outs[0].sample_stride = max(int(sample_stride), 1)
+            b.outs[0].n_sample_records = int(n_sample_records)
+        return self.run_factorised(b, stream=stream, check=check, single=True)[0]
+
+    def forward_factorised_batched(self, shots, n_anodes=61, n_gnodes=None, nodes=False,
+                                   stream=None, check=True, single=False):
+        """forward_factorised over a list of shots in one launch (numerics from
+        shots[0], shot k with RNG counter word shots[0]["shot"] + k); with
+        ``single`` the one-shot entry point is called instead."""
+        batch = self.prepare_factorised(shots, n_anodes, n_gnodes, nodes)
+        return self.run_factorised(batch, stream=stream, check=check, single=single)
+
+    def prepare_factorised(self, shots, n_anodes=61, n_gnodes=None, nodes=False):
+        """Marshal a reconstruction launch once (see prepare_batch); run it
+        with run_factorised()."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        b = self.prepare_batch(shots)
+        b.grids = (_lib.NodeGrid * b.n)()
+        for k, p in enumerate(shots):
+            ng = n_gnodes if n_gnodes is not None else (64 if p["sigma_gamma"] > 0 else 1)
+            b.grids[k] = _lib.NodeGrid(n_a=int(n_anodes), n_g=int(ng))
+            if nodes:
+                o = b.out[k]
+                o["node_states"] = torch.empty((n_anodes * ng, _lib.NODE_FIELDS),
+                                               dtype=torch.float64, device=dev)
+                o["node_weights"] = torch.empty(n_anodes * ng, dtype=torch.float64, device=dev)
+                b.grids[k].node_states = o["node_states"].data_ptr()
+                b.grids[k].node_weights = o["node_weights"].data_ptr()
+        return b
+
+    def run_factorised(self, b, stream=None, check=True, single=False):
+        """Enqueue one reconstruction launch over a prepared batch."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        if single:
+            if b.n != 1:
+                raise ValueError("single needs one shot")
+            st = _lib.lib().qs_forward_factorised(
+                self._ptr, ctypes.byref(b.lasers[0]), ctypes.byref(b.beams[0]),
+                ctypes.byref(b.nu), ctypes.byref(b.bins[0]), ctypes.byref(b.grids[0]),
+                ctypes.byref(b.outs[0]), ctypes.c_void_p(stream.cuda_stream))
+        else:
+            st = _lib.lib().qs_forward_factorised_batched(
+                self._ptr, b.n, b.lasers, b.beams, b.ns, ctypes.byref(b.nu), b.bins, b.grids,
+                b.outs, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        if check:
+            torch.cuda.synchronize(dev)
+            bad = int(torch.stack([o["status"] for o in b.out]).max().item())
+            if bad != _lib.QS_OK:
+                raise QScatterError(bad, "device status of a shot")
+        return b.out
+
     def backward(self, params, d_energy, stream=None, check=True, tape=None):
         """Derivatives of L = sum_k d_energy[k] H_k (H: the energy histogram of
         forward(params), n_e + 2 entries) with respect to PARAM_NAMES; returns

@@ -62,6 +62,15 @@ class Outputs(ctypes.Structure):
                 ("sample_stride", ctypes.c_int64), ("n_sample_records", ctypes.c_int64)]
 
 
+class NodeGrid(ctypes.Structure):
+    _fields_ = [("n_a", ctypes.c_int32), ("n_g", ctypes.c_int32),
+                ("node_states", ctypes.c_void_p), ("node_weights", ctypes.c_void_p)]
+
+
+NODE_FIELDS = 5  # a0,eff, gamma0, mu_f, sig2_f, chi max
+N_A, N_GAMMA0, N_MU, N_SIG2, N_CHIMAX = range(NODE_FIELDS)
+
+
 class PhotonBins(ctypes.Structure):
     _fields_ = [("n_ph", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("ph_lo", ctypes.c_double), ("ph_hi", ctypes.c_double)]
@@ -84,7 +93,8 @@ PARAM_NAMES = ("a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sig
 TAPE_FIELDS = 2 + 2 * len(PARAM_NAMES)  # mu, sig2, d mu / dp, d sig2 / dp
 T_MU, T_SIG2, T_DMU, T_DSIG2 = 0, 1, 2, 2 + len(PARAM_NAMES)
 
-EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched", "qs_backward",
+EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched",
+           "qs_forward_factorised", "qs_forward_factorised_batched", "qs_backward",
            "qs_backward_batched", "qs_forward_tape", "qs_forward_tape_batched",
            "qs_backward_tape", "qs_backward_tape_batched", "qs_photons", "qs_photons_batched",
            "qs_photon_cdf", "qs_radiation_eval",
@@ -124,6 +134,15 @@ def lib():
                                          ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                          ctypes.POINTER(Outputs), vp]
         L.qs_forward_batched.restype = ctypes.c_int
+        L.qs_forward_factorised.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                                            ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+                                            ctypes.POINTER(NodeGrid), ctypes.POINTER(Outputs), vp]
+        L.qs_forward_factorised.restype = ctypes.c_int
+        L.qs_forward_factorised_batched.argtypes = [
+            vp, ctypes.c_int32, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
+            ctypes.POINTER(NodeGrid), ctypes.POINTER(Outputs), vp]
+        L.qs_forward_factorised_batched.restype = ctypes.c_int
         L.qs_backward.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
                                   ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                   ctypes.POINTER(GradOutputs), vp]

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libqscatter.so")
 SOURCES = ["csrc/qs_kernels.hip", "csrc/qs_tables.hip", "csrc/qs_adjoint.hip", "csrc/qs_photon.hip",
-           "csrc/qs_api.hip"]
+           "csrc/qs_factor.hip", "csrc/qs_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -183,6 +183,9 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
 qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_photon_bins *PB,
                        const qs_photon_outputs *PO, hipStream_t s);
+qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                      const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                      const qs_node_grid *G, const qs_outputs *O, hipStream_t s);
 
 }  // namespace
 
@@ -289,6 +292,28 @@ qs_status qs_forward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
         return set_err(c, "invalid batch arguments"), QS_EINVAL;
     return forward_impl(c, n_shots, lasers, beams, n_samples, num, bins, outs, nullptr,
                         reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_forward_factorised(qs_ctx *c, const qs_laser *L, const qs_beam *B,
+                                const qs_numerics *N, const qs_bins *H, const qs_node_grid *G,
+                                const qs_outputs *O, void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    const int64_t n = N->n_samples;
+    return factor_impl(c, 1, L, B, &n, N, H, G, O, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_forward_factorised_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
+                                        const qs_beam *beams, const int64_t *n_samples,
+                                        const qs_numerics *num, const qs_bins *bins,
+                                        const qs_node_grid *grids, const qs_outputs *outs,
+                                        void *stream) {
+    if (!c) return QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20) || !lasers || !beams || !n_samples || !bins ||
+        !grids || !outs)
+        return set_err(c, "invalid batch arguments"), QS_EINVAL;
+    return factor_impl(c, n_shots, lasers, beams, n_samples, num, bins, grids, outs,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 qs_status qs_radiation_eval(qs_ctx *c, int32_t precision, int64_t n, const double *chi,
@@ -615,6 +640,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(b.outs);
     for (int k = 0; k < n_shots; ++k) {
         const qs_outputs &o = O[k];
+        so[k] = qs::ShotOut{};
         so[k].energy_hist = o.energy_hist;
         so[k].angle_hist = o.angle_hist;
         so[k].a0eff_hist = o.a0eff_hist;
@@ -866,5 +892,152 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     return QS_OK;
 }
 
-}  // namespace
+// Plane-wave reconstruction (Sec. 3.2, 3.3): node runs, interpolation,
+// deposit, finalize.  The staging buffer holds the sample view of the shot
+// table, the outputs, then the node view (node count and node offset in the
+// sample-count and state-offset fields) that the node pass reads.
+qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                      const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                      const qs_node_grid *G, const qs_outputs *O, hipStream_t s) {
+    qs_status st;
+    if (!G) return set_err(c, "null node grid"), QS_EINVAL;
+    if (!B || !H) return set_err(c, "null argument"), QS_EINVAL;
+    for (int k = 0; k < n_shots; ++k) {
+        if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
+        const qs_node_grid &g = G[k];
+        if (g.n_a < 2 || g.n_a > 4096) return set_err(c, "node grid: n_a in [2, 4096]"), QS_EINVAL;
+        if (B[k].sigma_gamma > 0 ? (g.n_g < 2 || g.n_g > 4096) : g.n_g != 1)
+            return set_err(c, "node grid: n_g in [2, 4096] with an energy spread, else 1"),
+                   QS_EINVAL;
+        if ((int64_t)g.n_a * g.n_g > (1 << 20))
+            return set_err(c, "node grid: at most 2^20 nodes"), QS_EINVAL;
+    }
+    if (N && N->amp_mode != QS_AMP_A0EFF)
+        return set_err(c, "the plane-wave reconstruction needs amp_mode A0EFF"), QS_EINVAL;
+    Batch b;
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H,
+                            sizeof(qs::ShotOut) + sizeof(qs::ShotParams), b)) != QS_OK)
+        return st;
+    if (qs::deposit_lds_bytes(b.max_nh) > 160 * 1024)
+        return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+    qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(b.outs);
+    qs::ShotParams *nv = reinterpret_cast<qs::ShotParams *>(b.outs + sizeof(qs::ShotOut) * n_shots);
+    int64_t node_off = 0, node_items = 0, hoff = 0;
+    int weight_words = 0;
+    for (int k = 0; k < n_shots; ++k) {
+        qs::ShotParams &p = b.sp[k];
+        const int na = G[k].n_a, ng = G[k].n_g, nn = na * ng;
+        p.n_anode = na;
+        p.n_gnode = ng;
+        p.node_off = node_off;
+        p.g_node_lo = B[k].gamma0 - 6.0 * B[k].sigma_gamma;
+        p.g_node_step = ng > 1 ? 12.0 * B[k].sigma_gamma / (ng - 1) : 0.0;
+        p.hist_off = hoff;  // [energy | angle | a0,eff | node weights]
+        hoff += H[k].n_e + 2 + H[k].n_th + 2 + H[k].n_a + nn;
+        if (G[k].node_weights) weight_words = std::max(weight_words, nn);
+        nv[k] = p;
+        nv[k].n_samples = nn;
+        nv[k].state_off = node_off;
+        nv[k].item0 = node_items;
+        node_off += nn;
+        node_items += (nn + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
+        const qs_outputs &o = O[k];
+        so[k] = qs::ShotOut{};
+        so[k].energy_hist = o.energy_hist;
+        so[k].angle_hist = o.angle_hist;
+        so[k].a0eff_hist = o.a0eff_hist;
+        so[k].moments = o.moments;
+        so[k].status = o.status;
+        so[k].samples = o.samples;
+        so[k].rec_stride = o.samples ? o.sample_stride : 1;
+        so[k].rec_n = o.samples ? o.n_sample_records : 0;
+        so[k].node_states = G[k].node_states;
+        so[k].node_weights = G[k].node_weights;
+    }
+    if ((size_t)weight_words * 8 > 160 * 1024)
+        return set_err(c, "node weights exceed the LDS budget (at most 20480 nodes when "
+                          "node_weights is requested)"),
+               QS_EINVAL;
+    b.hist_words = hoff;
 
+    // ---- device scratch: sample and node states, accumulators, partials ----
+    qs::BatchParams &bp = b.bp;
+    const size_t nenv = (size_t)2 * N->n_steps + 1;
+    const size_t arr = ((size_t)b.total * 8 + 255) / 256 * 256;
+    const size_t arrf = ((size_t)b.total * 4 + 255) / 256 * 256;
+    const size_t narr = ((size_t)node_off * 8 + 255) / 256 * 256;
+    const size_t narrf = ((size_t)node_off * 4 + 255) / 256 * 256;
+    const size_t flag_words = ((size_t)n_shots + 1) / 2;
+    const size_t accum_words = 1 + flag_words + (size_t)b.hist_words;
+    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
+    if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
+    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_ditems * qs::kPartials,
+                   "moment partials")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf + 6 * narr + narrf,
+                   "sample and node states")) != QS_OK)
+        return st;
+    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
+        return st;
+    bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
+    bp.outs = reinterpret_cast<const qs::ShotOut *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
+    bp.rad32 = c->rad32;
+    bp.rad64 = c->rad64;
+    auto states_at = [&](unsigned char *base, size_t a8, size_t a4) {
+        qs::SampleState x;
+        x.mu = reinterpret_cast<double *>(base);
+        x.s2 = reinterpret_cast<double *>(base + a8);
+        x.S0 = reinterpret_cast<double *>(base + 2 * a8);
+        x.g0 = reinterpret_cast<double *>(base + 3 * a8);
+        x.thx = reinterpret_cast<double *>(base + 4 * a8);
+        x.thy = reinterpret_cast<double *>(base + 5 * a8);
+        x.cmx = reinterpret_cast<float *>(base + 6 * a8);
+        (void)a4;
+        return x;
+    };
+    bp.st = states_at(c->states, arr, arrf);
+    bp.nst = states_at(c->states + 6 * arr + arrf, narr, narrf);
+    bp.queue = reinterpret_cast<unsigned int *>(c->accum);
+    bp.flags = reinterpret_cast<int *>(c->accum + 1);
+    bp.hist = c->accum + 1 + flag_words;
+    bp.partials = c->partials;
+    qs::BatchParams bn = bp;  // the node pass: node view, writes the node states
+    bn.shots = reinterpret_cast<const qs::ShotParams *>(
+        c->shot_tab + (sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots);
+    bn.n_items = node_items;
+    bn.st = bp.nst;
+
+    // ---- enqueue ----
+    hipError_t e;
+    const bool prof = c->profiling;
+    auto mark = [&](int k) { return prof ? hipEventRecord(c->ev[k], s) : hipSuccess; };
+    if ((st = upload_batch(c, b, s)) != QS_OK) return st;
+    if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau, c->env32,
+                                 c->env64, s)) != hipSuccess)
+        return hip_fail(c, e, "envelope kernel");
+    if ((e = mark(1)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
+        return hip_fail(c, e, "zero kernel");
+    if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_phase_nodes(bn, c->env32, c->env64, b.prec, N->rr_model, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "node kernel");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_interp(bp, weight_words, s)) != hipSuccess)
+        return hip_fail(c, e, "interpolation kernel");
+    if ((e = mark(4)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = qs::launch_deposit(bp, b.max_nh, s)) != hipSuccess)
+        return hip_fail(c, e, "deposit kernel");
+    if ((e = qs::launch_finalize(bp, s)) != hipSuccess) return hip_fail(c, e, "finalize kernel");
+    if ((e = qs::launch_node_outputs(bp, s)) != hipSuccess)
+        return hip_fail(c, e, "node output kernel");
+    if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
+    c->profiled_call = prof;
+    c->last_error[0] = 0;
+    return QS_OK;
+}
+
+}  // namespace

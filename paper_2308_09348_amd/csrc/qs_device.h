@@ -230,6 +230,29 @@ struct Path {
     }
 };
 
+// Sample i of a shot (Sec. 2 volume element): its initial Lorentz factor and
+// angles, its ballistic path and the spatial factor at its collision point.
+__device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0, uint32_t key1,
+                                            int64_t i, double &g0, double &thx, double &thy,
+                                            Path<double> &pd, double &S0) {
+    double nrm[6];
+    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, key0, key1, nrm);
+    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
+    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
+    const double z = sp.sigma_z * nrm[2];
+    g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
+    thx = sp.div_rad * nrm[4];
+    thy = sp.div_rad * nrm[5];
+    pd.xc = fma(thx, 0.5 * z, x);
+    pd.yc = fma(thy, 0.5 * z, y);
+    pd.thx = thx;
+    pd.thy = thy;
+    pd.zstar = fma(0.5, z, sp.z_delay);
+    pd.inv_w0sq = sp.inv_w0sq;
+    pd.inv_zR = sp.inv_zR;
+    S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
+}
+
 // One RK4 step of (mu, sig2) from psi_j with amplitudes a1 = a(psi_j),
 // ah = a(psi_j + h/2), a4 = a(psi_j + h); returns the increments.
 template <class T, bool QUANTUM>
@@ -354,6 +377,112 @@ __device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slo
     const int64_t item = *slot;
     __syncthreads();
     return item;
+}
+
+// ===========================================================================
+// Deposit of one law into block-private fixed-point histograms (forward
+// deposit and the angle law of the plane-wave reconstruction)
+// ===========================================================================
+constexpr unsigned long long kOne = 1ull << 32;
+
+
+__device__ __forceinline__ void ngp(double v, double lo, double w, int n,
+                                    unsigned long long *h) {
+    const double x = (v - lo) / w;
+    int k;
+    if (!(x >= 0.0))
+        k = n;  // underflow
+    else if (x >= (double)n)
+        k = n + 1;  // overflow
+    else
+        k = (int)x;
+    atomicAdd(&h[k], kOne);
+}
+
+// The deposited law is the sample's own law (a point at v if s = 0, else
+// N(v, s^2)) convolved with the deposit kernel (POINT: none; CIC: a box one
+// bin wide; GAUSS: N(0, (ksig bins)^2)).  Bin masses are differences of the
+// law's CDF at the bin edges, quantised to 2^-32 so that every sample adds
+// exactly 2^32; beyond 6 standard deviations the CDF is taken as 0 or 1 (the
+// neglected mass, 2e-9 a sample, goes to the edge bins of the window).  The
+// CDF is evaluated in FP32 on whichever side of v keeps it small (erfc of
+// the tail), so its error is a few ulps of the smaller tail mass.  For the
+// box (x) Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x
+// Phi(u/s) du at the two box ends, and consecutive edges share one end.
+struct PsiPair {
+    float P, Pc;  // Psi(x) and Psi(x) - x
+};
+__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s) {
+    const float zz = x * inv_s;
+    const float ph = s * 0.39894228040143267794f * expf(-0.5f * zz * zz);
+    PsiPair r;
+    if (zz <= 0.0f) {
+        r.P = fmaf(x, 0.5f * erfcf(-zz * 0.70710678118654752440f), ph);
+        r.Pc = r.P - x;
+    } else {
+        r.Pc = fmaf(-x, 0.5f * erfcf(zz * 0.70710678118654752440f), ph);
+        r.P = r.Pc + x;
+    }
+    return r;
+}
+
+__attribute__((unused)) static __device__ void deposit_law(double v, double s, int dep,
+                                                         double ksig, double lo, double w, int n,
+                                                         unsigned long long *h) {
+    const double half = 0.5 * w;
+    int mode;
+    double se = s;
+    if (dep == 2) {  // GAUSS
+        const double ks = ksig * w;
+        se = sqrt(s * s + ks * ks);
+        mode = se > 0.0 ? 2 : 0;
+    } else if (dep == 1) {  // CIC
+        mode = s > 0.0 ? 3 : 1;
+    } else {
+        mode = s > 0.0 ? 2 : 0;
+    }
+    if (mode == 0) {
+        ngp(v, lo, w, n, h);
+        return;
+    }
+    const double reach = mode == 1 ? half : (mode == 2 ? 6.0 * se : 6.0 * se + half);
+    int ka = (int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0);
+    int kb = (int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0);
+    ka = max(ka, 0);
+    kb = min(kb, n);
+    if (ka > kb) {
+        ngp(v, lo, w, n, h);  // the whole law lies inside one bin (or outside)
+        return;
+    }
+    const float sf = (float)se, inv_s = mode >= 2 ? (float)(1.0 / se) : 0.0f;
+    const float wf = (float)w, inv_w = (float)(1.0 / w), hf = (float)half;
+    PsiPair lower{0.0f, 0.0f};
+    if (mode == 3) lower = psi_pair((float)(fma((double)ka, w, lo) - v) - hf, sf, inv_s);
+    unsigned long long qprev = 0;
+    for (int k = ka; k <= kb; ++k) {
+        const float t = (float)(fma((double)k, w, lo) - v);  // edge - v
+        const bool upper = t > 0.0f;  // F is taken from the upper tail there
+        float F;
+        if (mode == 1) {
+            F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
+        } else if (mode == 2) {
+            F = 0.5f * erfcf((upper ? t : -t) * inv_s * 0.70710678118654752440f);
+        } else {
+            const PsiPair up = psi_pair(t + hf, sf, inv_s);
+            F = upper ? (lower.Pc - up.Pc) * inv_w : (up.P - lower.P) * inv_w;
+            lower = up;
+        }
+        (void)wf;
+        F = fminf(fmaxf(F, 0.0f), 1.0f);
+        const unsigned long long qf = (unsigned long long)llrintf(F * 4294967296.0f);
+        unsigned long long q = upper ? kOne - qf : qf;
+        q = q < qprev ? qprev : q;
+        const int bin = k == 0 ? n : k - 1;  // mass between edge k-1 and edge k
+        if (q != qprev) atomicAdd(&h[bin], q - qprev);
+        qprev = q;
+    }
+    const int bin = kb == n ? n + 1 : kb;  // mass above the last edge in the window
+    if (qprev != kOne) atomicAdd(&h[bin], kOne - qprev);
 }
 
 // ===========================================================================

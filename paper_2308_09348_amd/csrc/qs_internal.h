@@ -79,6 +79,10 @@ struct ShotParams {
     // bins
     int32_t n_e, n_th, n_a, pad2;
     double e_lo, e_w, th_lo, th_w;
+    // plane-wave reconstruction: the shot's node grid (node = k n_gnode + m)
+    int32_t n_anode, n_gnode;
+    int64_t node_off;             // index of its first node state
+    double g_node_lo, g_node_step;  // gamma0 of node m: g_node_lo + m g_node_step
 };
 
 // Output pointers of one shot (device table).
@@ -87,7 +91,13 @@ struct ShotOut {
     int32_t *status;
     double *samples;
     int64_t rec_stride, rec_n;
+    double *node_states;   // plane-wave reconstruction (optional): [nodes][kNodeFields]
+    double *node_weights;  // [nodes]
 };
+
+// Node record of the plane-wave reconstruction: a0,eff, gamma0, mu_f, sig2_f,
+// chi max.
+constexpr int kNodeFields = 5;
 
 // ---- photon spectrum (Sec. 4) ---------------------------------------------
 // Number CDF of the LCFA photon spectrum, stored as Phi(xi; chi) / (chi z) on
@@ -149,6 +159,7 @@ struct BatchParams {
     double *tape;           // derivative tape: [2 + 2 kGradParams][tape_n]
     int64_t tape_n;         // samples over the batch (tape field stride)
     SampleState st;
+    SampleState nst;        // plane-wave reconstruction: final states of the nodes
     // accumulators (device scratch, cleared before each launch)
     unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
     unsigned int *chimax_bits;     // [n_shots]
@@ -184,5 +195,12 @@ hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t
 hipError_t launch_photon_cdf(const double *phtab, int64_t n, const double *chi, const double *xi,
                              double *out, hipStream_t s);
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s);
+// plane-wave reconstruction (qs_factor.hip): the node pass is the phase
+// kernel in node mode on the node view of the shot table; the interpolation
+// pass writes sample states for the deposit and finalize kernels
+hipError_t launch_phase_nodes(const BatchParams &p, const float *env32, const double *env64,
+                              int prec, int rr, hipStream_t s);
+hipError_t launch_interp(const BatchParams &p, int weight_words, hipStream_t s);
+hipError_t launch_node_outputs(const BatchParams &p, hipStream_t s);
 
 }  // namespace qs

@@ -20,116 +20,16 @@
 namespace qs {
 
 // ===========================================================================
-// Deposit of one law into block-private fixed-point histograms
-// ===========================================================================
-constexpr unsigned long long kOne = 1ull << 32;
-
-
-__device__ __forceinline__ void ngp(double v, double lo, double w, int n,
-                                    unsigned long long *h) {
-    const double x = (v - lo) / w;
-    int k;
-    if (!(x >= 0.0))
-        k = n;  // underflow
-    else if (x >= (double)n)
-        k = n + 1;  // overflow
-    else
-        k = (int)x;
-    atomicAdd(&h[k], kOne);
-}
-
-// The deposited law is the sample's own law (a point at v if s = 0, else
-// N(v, s^2)) convolved with the deposit kernel (POINT: none; CIC: a box one
-// bin wide; GAUSS: N(0, (ksig bins)^2)).  Bin masses are differences of the
-// law's CDF at the bin edges, quantised to 2^-32 so that every sample adds
-// exactly 2^32; beyond 6 standard deviations the CDF is taken as 0 or 1 (the
-// neglected mass, 2e-9 a sample, goes to the edge bins of the window).  The
-// CDF is evaluated in FP32 on whichever side of v keeps it small (erfc of
-// the tail), so its error is a few ulps of the smaller tail mass.  For the
-// box (x) Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x
-// Phi(u/s) du at the two box ends, and consecutive edges share one end.
-struct PsiPair {
-    float P, Pc;  // Psi(x) and Psi(x) - x
-};
-__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s) {
-    const float zz = x * inv_s;
-    const float ph = s * 0.39894228040143267794f * expf(-0.5f * zz * zz);
-    PsiPair r;
-    if (zz <= 0.0f) {
-        r.P = fmaf(x, 0.5f * erfcf(-zz * 0.70710678118654752440f), ph);
-        r.Pc = r.P - x;
-    } else {
-        r.Pc = fmaf(-x, 0.5f * erfcf(zz * 0.70710678118654752440f), ph);
-        r.P = r.Pc + x;
-    }
-    return r;
-}
-
-__device__ void deposit_law(double v, double s, int dep, double ksig, double lo, double w, int n,
-                            unsigned long long *h) {
-    const double half = 0.5 * w;
-    int mode;
-    double se = s;
-    if (dep == 2) {  // GAUSS
-        const double ks = ksig * w;
-        se = sqrt(s * s + ks * ks);
-        mode = se > 0.0 ? 2 : 0;
-    } else if (dep == 1) {  // CIC
-        mode = s > 0.0 ? 3 : 1;
-    } else {
-        mode = s > 0.0 ? 2 : 0;
-    }
-    if (mode == 0) {
-        ngp(v, lo, w, n, h);
-        return;
-    }
-    const double reach = mode == 1 ? half : (mode == 2 ? 6.0 * se : 6.0 * se + half);
-    int ka = (int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0);
-    int kb = (int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0);
-    ka = max(ka, 0);
-    kb = min(kb, n);
-    if (ka > kb) {
-        ngp(v, lo, w, n, h);  // the whole law lies inside one bin (or outside)
-        return;
-    }
-    const float sf = (float)se, inv_s = mode >= 2 ? (float)(1.0 / se) : 0.0f;
-    const float wf = (float)w, inv_w = (float)(1.0 / w), hf = (float)half;
-    PsiPair lower{0.0f, 0.0f};
-    if (mode == 3) lower = psi_pair((float)(fma((double)ka, w, lo) - v) - hf, sf, inv_s);
-    unsigned long long qprev = 0;
-    for (int k = ka; k <= kb; ++k) {
-        const float t = (float)(fma((double)k, w, lo) - v);  // edge - v
-        const bool upper = t > 0.0f;  // F is taken from the upper tail there
-        float F;
-        if (mode == 1) {
-            F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
-        } else if (mode == 2) {
-            F = 0.5f * erfcf((upper ? t : -t) * inv_s * 0.70710678118654752440f);
-        } else {
-            const PsiPair up = psi_pair(t + hf, sf, inv_s);
-            F = upper ? (lower.Pc - up.Pc) * inv_w : (up.P - lower.P) * inv_w;
-            lower = up;
-        }
-        (void)wf;
-        F = fminf(fmaxf(F, 0.0f), 1.0f);
-        const unsigned long long qf = (unsigned long long)llrintf(F * 4294967296.0f);
-        unsigned long long q = upper ? kOne - qf : qf;
-        q = q < qprev ? qprev : q;
-        const int bin = k == 0 ? n : k - 1;  // mass between edge k-1 and edge k
-        if (q != qprev) atomicAdd(&h[bin], q - qprev);
-        qprev = q;
-    }
-    const int bin = kb == n ? n + 1 : kb;  // mass above the last edge in the window
-    if (qprev != kOne) atomicAdd(&h[bin], kOne - qprev);
-}
-
-// ===========================================================================
 // Phase kernel: sample -> ballistic path -> RK4 phase loop -> final state
 // ===========================================================================
 // The envelope tables come as separate restrict-qualified arguments: the
 // kernel never writes them, so the compiler reads them with scalar loads
 // (every lane of a wavefront is at the same phase step).
-template <int PREC, bool QUANTUM, bool LOCAL>
+// NODES: the lane runs node i = k n_gnode + m of the shot's plane-wave
+// reconstruction grid (a0,eff = a0 k / (n_anode - 1), gamma0 of node m, no
+// angles) instead of drawing sample i; the caller passes the node view of the
+// shot table (its node count and node offset as samples and state offset).
+template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false>
 __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotParams &sp, int64_t i,
                                              const float *__restrict__ env32,
                                              const double *__restrict__ env64,
@@ -143,23 +43,21 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
     const float chi_top = (float)(1 << (kEMax + 1));  // end of the tabulated range
 
     // ---- sample and geometry (FP64, once per sample) ----
-    double nrm[6];
-    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
-    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
-    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
-    const double z = sp.sigma_z * nrm[2];
-    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
-    const double thx = sp.div_rad * nrm[4];
-    const double thy = sp.div_rad * nrm[5];
-    Path<double> pd;
-    pd.xc = fma(thx, 0.5 * z, x);
-    pd.yc = fma(thy, 0.5 * z, y);
-    pd.thx = thx;
-    pd.thy = thy;
-    pd.zstar = fma(0.5, z, sp.z_delay);
-    pd.inv_w0sq = sp.inv_w0sq;
-    pd.inv_zR = sp.inv_zR;
-    const double S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
+    double g0, thx = 0.0, thy = 0.0, S0;
+    Path<double> pd{};
+    if (NODES) {
+        static_assert(!NODES || !LOCAL, "nodes carry a fixed amplitude");
+        const int k = (int)(i / sp.n_gnode);
+        const int m = (int)(i - (int64_t)k * sp.n_gnode);
+        S0 = (double)k / (double)(sp.n_anode - 1);
+        g0 = sp.gamma0;
+        if (sp.n_gnode > 1) {
+#pragma clang fp contract(off)
+            g0 = sp.g_node_lo + (double)m * sp.g_node_step;  // rounded twice, as defined
+        }
+    } else {
+        draw_sample(sp, P.key0, P.key1, i, g0, thx, thy, pd, S0);
+    }
     const double a0S0 = sp.a0 * S0;
 
     double mu_f, s2_f;
@@ -292,7 +190,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
     P.st.cmx[k] = cmx;
 }
 
-template <int PREC, bool QUANTUM, bool LOCAL>
+template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false>
 __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
                                                             const float *__restrict__ env32,
                                                             const double *__restrict__ env64) {
@@ -313,7 +211,7 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
         const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
         if (i < sp.n_samples) {
             int flags = 0;
-            phase_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, flags);
+            phase_sample<PREC, QUANTUM, LOCAL, NODES>(P, sp, i, env32, env64, tab32, flags);
             if (flags) atomicOr(&P.flags[s], flags);
         }
     }
@@ -565,6 +463,30 @@ static const void *select_phase(int prec, int rr, int amp) {
 hipError_t launch_phase(const BatchParams &p, const float *env32, const double *env64, int prec,
                         int rr, int amp, hipStream_t s) {
     const void *fn = select_phase(prec, rr, amp);
+    if (!fn) return hipErrorInvalidValue;
+    int grid = 0;
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    if (e != hipSuccess) return e;
+    BatchParams pc = p;
+    const float *e32 = env32;
+    const double *e64 = env64;
+    void *args[] = {&pc, &e32, &e64};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+}
+
+template <int PREC, bool QUANTUM>
+static const void *node_ptr() {
+    return reinterpret_cast<const void *>(&phase_kernel<PREC, QUANTUM, false, true>);
+}
+
+hipError_t launch_phase_nodes(const BatchParams &p, const float *env32, const double *env64,
+                              int prec, int rr, hipStream_t s) {
+    const bool q = rr == 1;
+    if (prec == PREC_F32MIX && !q) prec = PREC_F32;
+    const void *fn = nullptr;
+    if (prec == PREC_F32) fn = q ? node_ptr<PREC_F32, true>() : node_ptr<PREC_F32, false>();
+    if (prec == PREC_F64) fn = q ? node_ptr<PREC_F64, true>() : node_ptr<PREC_F64, false>();
+    if (prec == PREC_F32MIX) fn = node_ptr<PREC_F32MIX, true>();
     if (!fn) return hipErrorInvalidValue;
     int grid = 0;
     hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);

@@ -60,11 +60,14 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Numerics) == 8 + 4 * 2 + 8 * 2 + 4 * 4 + 8 * 3
     assert ctypes.sizeof(_lib.Bins) == 4 * 4 + 8 * 4
     assert ctypes.sizeof(_lib.Outputs) == 8 * 8
+    assert ctypes.sizeof(_lib.NodeGrid) == 4 * 2 + 8 * 2
 
 
 def test_null_context_is_rejected_without_a_device():
     from paper_2308_09348_amd import _lib
     L = _lib.lib()
     assert L.qs_forward(None, None, None, None, None, None, None) == _lib.QS_EINVAL
+    assert L.qs_forward_factorised(None, None, None, None, None, None, None,
+                                   None) == _lib.QS_EINVAL
     assert L.qs_create(None, 0) == _lib.QS_EINVAL
     L.qs_destroy(None)
