@@ -961,40 +961,110 @@ int qso_forward(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthrea
  * (Reading: the weighted sum of the paper is taken with the weights carried
  * by the samples rather than by bins of a0,eff, so that node laws narrower
  * than the node spacing are not mixed into a comb.)                        */
+/* The node grid, its plane-wave runs, and the interpolated state of a sample. */
+struct NodeGrid {
+    int K = 0, M = 0;
+    double g_lo = 0.0, g_step = 0.0;
+    std::vector<SampleOut<double>> node;  /* node n = k M + m */
+
+    /* 1. the plane-wave runs; returns -2 on a non-finite node state */
+    int run(const qso_problem *p, const Derived &d, const Params<double> &P, int K_, int M_,
+            int nthreads) {
+        K = K_;
+        M = M_;
+        g_lo = p->gamma0 - 6.0 * p->sigma_gamma;
+        g_step = M > 1 ? 12.0 * p->sigma_gamma / (M - 1) : 0.0;
+        node.assign((size_t)K * M, SampleOut<double>{});
+        int bad = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : bad)
+        for (int n = 0; n < K * M; ++n) {
+            const int k = n / M, m = n % M;
+            SampleIn<double> s{};
+            s.gamma0 = M > 1 ? g_lo + m * g_step : p->gamma0;
+            Geometry<double> gmt{};
+            gmt.S0 = (double)k / (K - 1);
+            NoVisit none;
+            node[n] = evolve<double>(p, d, P, s, gmt, none);
+            if (!std::isfinite(node[n].mu) || !std::isfinite(node[n].sig2)) bad = 1;
+        }
+        return bad ? -2 : 0;
+    }
+
+    /* 2. bilinear weights w[4] on nodes idx[4] at (S0 = a0,eff / a0, gamma0) */
+    void weights(double S0, double gamma0, double w[4], int idx[4]) const {
+        const double ta = S0 * (K - 1);
+        int k = (int)std::floor(ta);
+        if (k > K - 2) k = K - 2;
+        if (k < 0) k = 0;
+        const double fa = ta - k;
+        int m = 0;
+        double fg = 0.0;
+        if (M > 1) {
+            double tg = (gamma0 - g_lo) / g_step;
+            if (tg < 0.0) tg = 0.0;
+            if (tg > M - 1) tg = M - 1;
+            m = (int)std::floor(tg);
+            if (m > M - 2) m = M - 2;
+            fg = tg - m;
+        }
+        const int n00 = k * M + m, n10 = n00 + M;
+        w[0] = (1.0 - fa) * (1.0 - fg);
+        w[1] = fa * (1.0 - fg);
+        w[2] = M > 1 ? (1.0 - fa) * fg : 0.0;
+        w[3] = M > 1 ? fa * fg : 0.0;
+        idx[0] = n00;
+        idx[1] = n10;
+        idx[2] = M > 1 ? n00 + 1 : n00;
+        idx[3] = M > 1 ? n10 + 1 : n10;
+    }
+
+    /* the sample's interpolated final state and observables (its own draw,
+     * direction and a0,eff) */
+    SampleOut<double> sample(const qso_problem *p, const Params<double> &P, int64_t i, double w[4],
+                             int idx[4]) const {
+        const SampleIn<double> s = make_sample<double>(p, P, i);
+        const Geometry<double> gmt = geometry<double>(p, P, s);
+        weights(gmt.S0, s.gamma0, w, idx);
+        SampleOut<double> o{};
+        o.mu = 0.0;
+        o.sig2 = 0.0;
+        o.chimax = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            o.mu += w[q] * node[idx[q]].mu;
+            o.sig2 += w[q] * node[idx[q]].sig2;
+            o.chimax += w[q] * node[idx[q]].chimax;
+        }
+        const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
+        const double aeff = P.a0 * gmt.S0;
+        o.thx = 1e3 * s.thx;
+        o.thy = 1e3 * s.thy;
+        o.sigth = 1e3 * p->c_theta * std::sqrt(2.0 / kPi) * aeff * sigf / (o.mu * o.mu);
+        o.aeff_ratio = gmt.S0;
+        o.gamma0 = s.gamma0;
+        o.x = s.x; o.y = s.y; o.z = s.z;
+        return o;
+    }
+};
+
+bool valid_grid(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes) {
+    if (p->amp_mode != QSO_AMP_A0EFF || n_anodes < 2) return false;
+    return p->sigma_gamma > 0.0 ? n_gnodes >= 2 : n_gnodes == 1;
+}
+
 int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int64_t i_begin,
                    int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
                    double *a0eff_hist, double *moments, double *node_states,
                    double *node_weights) {
     if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
-    if (p->amp_mode != QSO_AMP_A0EFF || n_anodes < 2) return -1;
-    if (p->sigma_gamma > 0.0 ? n_gnodes < 2 : n_gnodes != 1) return -1;
+    if (!valid_grid(p, n_anodes, n_gnodes)) return -1;
     const Derived d = derive(p);
     if (p->rr_model == QSO_RR_QUANTUM) table();
     if (nthreads < 1) nthreads = omp_get_max_threads();
-    const int K = n_anodes, M = n_gnodes, NN = K * M;
-    const double g_lo = p->gamma0 - 6.0 * p->sigma_gamma;
-    const double g_step = M > 1 ? 12.0 * p->sigma_gamma / (M - 1) : 0.0;
-    const Params<double> P = [&] {
-        Params<double> q = params<double>(p);
-        finish_params(p, q);
-        return q;
-    }();
-
-    /* 1. plane-wave runs on the nodes (node n = k M + m) */
-    std::vector<SampleOut<double>> node(NN);
-    int bad_node = 0;
-#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : bad_node)
-    for (int n = 0; n < NN; ++n) {
-        const int k = n / M, m = n % M;
-        SampleIn<double> s{};
-        s.gamma0 = M > 1 ? g_lo + m * g_step : p->gamma0;
-        Geometry<double> gmt{};
-        gmt.S0 = (double)k / (K - 1);
-        NoVisit none;
-        node[n] = evolve<double>(p, d, P, s, gmt, none);
-        if (!std::isfinite(node[n].mu) || !std::isfinite(node[n].sig2)) bad_node = 1;
-    }
-    if (bad_node) return -2;
+    Params<double> P = params<double>(p);
+    finish_params(p, P);
+    NodeGrid grid;
+    if (grid.run(p, d, P, n_anodes, n_gnodes, nthreads)) return -2;
+    const int NN = n_anodes * n_gnodes;
 
     /* 2-3. samples: interpolated plane-wave state, deposit, node weights */
     const int ne = p->n_e, nt = p->n_th, na = p->n_a;
@@ -1012,64 +1082,30 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
         const int nth = omp_get_num_threads();
         const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
         for (int64_t i = b; i < e; ++i) {
-            const SampleIn<double> s = make_sample<double>(p, P, i);
-            const Geometry<double> gmt = geometry<double>(p, P, s);
-            /* bilinear weights of the sample on the node grid */
-            const double ta = gmt.S0 * (K - 1);
-            int k = (int)std::floor(ta);
-            if (k > K - 2) k = K - 2;
-            if (k < 0) k = 0;
-            const double fa = ta - k;
-            int m = 0;
-            double fg = 0.0;
-            if (M > 1) {
-                double tg = (s.gamma0 - g_lo) / g_step;
-                if (tg < 0.0) tg = 0.0;
-                if (tg > M - 1) tg = M - 1;
-                m = (int)std::floor(tg);
-                if (m > M - 2) m = M - 2;
-                fg = tg - m;
-            }
-            const int n00 = k * M + m;
-            const int n10 = n00 + M;
-            double w[4] = {(1.0 - fa) * (1.0 - fg), fa * (1.0 - fg), 0.0, 0.0};
-            int idx[4] = {n00, n10, n00, n10};
-            if (M > 1) {
-                w[2] = (1.0 - fa) * fg;
-                w[3] = fa * fg;
-                idx[2] = n00 + 1;
-                idx[3] = n10 + 1;
-            }
-            double mu = 0.0, sig2 = 0.0, cmx = 0.0;
-            for (int q = 0; q < 4; ++q) {
-                hw[t][idx[q]] += w[q];
-                mu += w[q] * node[idx[q]].mu;
-                sig2 += w[q] * node[idx[q]].sig2;
-                cmx += w[q] * node[idx[q]].chimax;
-            }
-            const double sigf = std::sqrt(std::fmax(sig2, 0.0));
-            const double aeff = p->a0 * gmt.S0;
-            const double thx = 1e3 * s.thx, thy = 1e3 * s.thy;
-            const double sigth = 1e3 * p->c_theta * std::sqrt(2.0 / kPi) * aeff * sigf / (mu * mu);
-            deposit<double>(mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
+            double w[4];
+            int idx[4];
+            const SampleOut<double> o = grid.sample(p, P, i, w, idx);
+            for (int q = 0; q < 4; ++q) hw[t][idx[q]] += w[q];
+            const double sigf = std::sqrt(std::fmax(o.sig2, 0.0));
+            deposit<double>(o.mu, sigf, p->deposit, p->kernel_sigma_bins, p->e_lo, p->e_hi, ne,
                             he[t].data());
-            deposit<double>(thx, sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
+            deposit<double>(o.thx, o.sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
                             p->th_hi_mrad, nt, ht[t].data());
-            int ka = (int)std::floor(gmt.S0 * na);
+            int ka = (int)std::floor(o.aeff_ratio * na);
             if (ka > na - 1) ka = na - 1;
             if (ka < 0) ka = 0;
             ha[t][ka] += 1.0;
-            const double de = mu - p->gamma0;
+            const double de = o.mu - p->gamma0;
             sums[t][S1E].add(de);
-            sums[t][S2E].add(de * de + std::fmax(sig2, 0.0));
-            sums[t][S1X].add(thx);
-            sums[t][S2X].add(thx * thx + sigth * sigth);
-            sums[t][S1Y].add(thy);
-            sums[t][S2Y].add(thy * thy);
-            sums[t][SAEFF].add(aeff);
-            sums[t][SRAD].add(1.0 - mu / s.gamma0);
+            sums[t][S2E].add(de * de + std::fmax(o.sig2, 0.0));
+            sums[t][S1X].add(o.thx);
+            sums[t][S2X].add(o.thx * o.thx + o.sigth * o.sigth);
+            sums[t][S1Y].add(o.thy);
+            sums[t][S2Y].add(o.thy * o.thy);
+            sums[t][SAEFF].add(p->a0 * o.aeff_ratio);
+            sums[t][SRAD].add(1.0 - o.mu / o.gamma0);
             sums[t][SSIGF].add(sigf);
-            chimax[t] = std::fmax(chimax[t], cmx);
+            chimax[t] = std::fmax(chimax[t], o.chimax);
         }
     }
     for (int t = 1; t < nthreads; ++t) {
@@ -1090,11 +1126,11 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
     if (node_states) {
         for (int n = 0; n < NN; ++n) {
             double *r = node_states + (size_t)n * QSO_N_N;
-            r[QSO_N_A] = p->a0 * ((double)(n / M) / (K - 1));
-            r[QSO_N_GAMMA0] = node[n].gamma0;
-            r[QSO_N_MU] = node[n].mu;
-            r[QSO_N_SIG2] = node[n].sig2;
-            r[QSO_N_CHIMAX] = node[n].chimax;
+            r[QSO_N_A] = p->a0 * ((double)(n / n_gnodes) / (n_anodes - 1));
+            r[QSO_N_GAMMA0] = grid.node[n].gamma0;
+            r[QSO_N_MU] = grid.node[n].mu;
+            r[QSO_N_SIG2] = grid.node[n].sig2;
+            r[QSO_N_CHIMAX] = grid.node[n].chimax;
         }
     }
     if (moments) {
@@ -1114,6 +1150,31 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
             moments[QSO_M_RAD_FRAC] = sums[0][SRAD].value() / W;
             moments[QSO_M_MEAN_SIGF] = sums[0][SSIGF].value() / W;
         }
+    }
+    return 0;
+}
+
+int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes,
+                           int64_t n_idx, const int64_t *idx, int nthreads, double *recs) {
+    if (validate(p) || !valid_grid(p, n_anodes, n_gnodes) || n_idx < 0) return -1;
+    for (int64_t r = 0; r < n_idx; ++r)
+        if (idx[r] < 0 || idx[r] >= p->n_samples) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    Params<double> P = params<double>(p);
+    finish_params(p, P);
+    NodeGrid grid;
+    if (grid.run(p, d, P, n_anodes, n_gnodes, nthreads)) return -2;
+    for (int64_t r = 0; r < n_idx; ++r) {
+        double w[4];
+        int ix[4];
+        const SampleOut<double> o = grid.sample(p, P, idx[r], w, ix);
+        double *rec = recs + (size_t)r * QSO_S_N;
+        rec[QSO_S_MU] = o.mu; rec[QSO_S_SIG2] = o.sig2; rec[QSO_S_THX] = o.thx;
+        rec[QSO_S_THY] = o.thy; rec[QSO_S_SIGTH] = o.sigth; rec[QSO_S_AEFF] = p->a0 * o.aeff_ratio;
+        rec[QSO_S_CHIMAX] = o.chimax; rec[QSO_S_GAMMA0] = o.gamma0;
+        rec[QSO_S_X] = o.x; rec[QSO_S_Y] = o.y; rec[QSO_S_Z] = o.z;
     }
     return 0;
 }

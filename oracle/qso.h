@@ -142,6 +142,10 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
                    int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
                    double *a0eff_hist, double *moments, double *node_states,
                    double *node_weights);
+/* Records (QSO_S_N doubles) of samples idx[0 .. n_idx) as the reconstruction
+ * deposits them: the interpolated final state and the sample's observables. */
+int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes,
+                           int64_t n_idx, const int64_t *idx, int nthreads, double *recs);
 
 /* Derivatives with respect to the eight parameters, in this order:
  * (a0, w0_um, x_off_um, y_off_um, delay_fs, gamma0, sigma_gamma, div_mrad).

@@ -95,6 +95,9 @@ def lib():
         L.qso_factorised.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         L.qso_factorised.restype = ctypes.c_int
+        L.qso_factorised_samples.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp]
+        L.qso_factorised_samples.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -221,6 +224,22 @@ def factorised(params, n_anodes, n_gnodes, i_begin=0, i_end=None, nthreads=0):
         raise FloatingPointError("non-finite state")
     return {"energy_hist": he, "angle_hist": ht, "a0eff_hist": ha, "moments": mo,
             "node_states": ns, "node_weights": nw}
+
+
+def factorised_samples(params, n_anodes, n_gnodes, indices, nthreads=0):
+    """Records [len(indices), S_N] of the given samples as the reconstruction
+    deposits them (interpolated final state, own observables)."""
+    idx = np.ascontiguousarray(np.asarray(list(indices), dtype=np.int64))
+    recs = np.zeros((len(idx), S_N))
+    p = problem(params)
+    rc = lib().qso_factorised_samples(ctypes.byref(p), n_anodes, n_gnodes, len(idx),
+                                      idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      nthreads, _dp(recs))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return recs
 
 
 PARAM_NAMES = ["a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
