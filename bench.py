@@ -270,8 +270,8 @@ def factorised_leg(ctx, workloads, torch, steps):
             "n_samples": n, "n_steps": N, "nodes": K * M, "steps": steps,
             "direct_ms": 1e3 * t_direct, "factorised_ms": 1e3 * t_fact,
             "speedup": t_direct / t_fact,
-            "ms_parts": {"node_runs": parts["phase"], "weights": parts["deposit"],
-                         "contraction_finalize": parts["finalize"]},
+            "ms_parts": {"node_runs": parts["phase"], "interpolation": parts["deposit"],
+                         "deposit_finalize": parts["finalize"]},
             "equivalent_sample_steps_per_s": n * N / t_fact,
             "l1_vs_direct": float(np.abs(hf - hd).sum() / n),
             "mean_gamma_rel_diff": float(abs(mf[1] - md[1]) / md[1])}

@@ -380,109 +380,176 @@ __device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slo
 }
 
 // ===========================================================================
-// Deposit of one law into block-private fixed-point histograms (forward
-// deposit and the angle law of the plane-wave reconstruction)
+// Deposit of sample laws into fixed-point histograms
 // ===========================================================================
-constexpr unsigned long long kOne = 1ull << 32;
-
-
-__device__ __forceinline__ void ngp(double v, double lo, double w, int n,
-                                    unsigned long long *h) {
-    const double x = (v - lo) / w;
-    int k;
-    if (!(x >= 0.0))
-        k = n;  // underflow
-    else if (x >= (double)n)
-        k = n + 1;  // overflow
-    else
-        k = (int)x;
-    atomicAdd(&h[k], kOne);
-}
-
-// The deposited law is the sample's own law (a point at v if s = 0, else
+// The deposited law of a sample is its own law (a point at v if s = 0, else
 // N(v, s^2)) convolved with the deposit kernel (POINT: none; CIC: a box one
 // bin wide; GAUSS: N(0, (ksig bins)^2)).  Bin masses are differences of the
 // law's CDF at the bin edges, quantised to 2^-32 so that every sample adds
 // exactly 2^32; beyond 6 standard deviations the CDF is taken as 0 or 1 (the
 // neglected mass, 2e-9 a sample, goes to the edge bins of the window).  The
-// CDF is evaluated in FP32 on whichever side of v keeps it small (erfc of
-// the tail), so its error is a few ulps of the smaller tail mass.  For the
-// box (x) Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x
-// Phi(u/s) du at the two box ends, and consecutive edges share one end.
+// CDF is evaluated in FP32 on whichever side of v keeps it small (the tail),
+// so its error is a few ulps of the smaller tail mass.  For the box (x)
+// Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x Phi(u/s) du at
+// the two box ends, and consecutive edges share one end.
+constexpr unsigned long long kOne = 1ull << 32;
+
+// erfc(a) for a >= 0 without branches, given ea2 = exp(-a^2): the
+// Chebyshev-fitted form erfc(a) = t exp(-a^2 + P(t)), t = 1 / (1 + a/2), of
+// Press, Teukolsky, Vetterling and Flannery, Numerical Recipes (2nd ed.,
+// Sec. 6.2), fractional error below 1.2e-7 for every a >= 0.  The library
+// erfcf branches on the argument range, which costs a wavefront every branch
+// its lanes take.
+__device__ __forceinline__ float erfc_pos(float a, float ea2) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, a, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return t * ea2 * __expf(p);
+}
+
+// 0.5 erfc(|z| / sqrt2): the Gaussian tail beyond |z| standard deviations.
+__device__ __forceinline__ float gauss_tail(float z) {
+    const float a = fabsf(z) * 0.70710678118654752440f;
+    return 0.5f * erfc_pos(a, __expf(-a * a));
+}
+
 struct PsiPair {
     float P, Pc;  // Psi(x) and Psi(x) - x
 };
+// Psi(x) = x Phi(x/s) + s phi(x/s) and Psi(x) - x = -x Phi(-x/s) + s phi(x/s),
+// each formed from the tail on its own side (no cancellation), without
+// branches: one exponential serves phi and the tail.
 __device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s) {
     const float zz = x * inv_s;
-    const float ph = s * 0.39894228040143267794f * expf(-0.5f * zz * zz);
+    const float e2 = __expf(-0.5f * zz * zz);  // relative error below 2e-6 out to 6 sigma
+    const float ph = s * 0.39894228040143267794f * e2;
+    const float tail = 0.5f * erfc_pos(fabsf(zz) * 0.70710678118654752440f, e2);
+    const float lo = fmaf(x, tail, ph);   // Psi(x) when x <= 0
+    const float hi = fmaf(-x, tail, ph);  // Psi(x) - x when x > 0
     PsiPair r;
-    if (zz <= 0.0f) {
-        r.P = fmaf(x, 0.5f * erfcf(-zz * 0.70710678118654752440f), ph);
-        r.Pc = r.P - x;
-    } else {
-        r.Pc = fmaf(-x, 0.5f * erfcf(zz * 0.70710678118654752440f), ph);
-        r.P = r.Pc + x;
-    }
+    r.P = zz <= 0.0f ? lo : hi + x;
+    r.Pc = zz <= 0.0f ? lo - x : hi;
     return r;
 }
 
-__attribute__((unused)) static __device__ void deposit_law(double v, double s, int dep,
-                                                         double ksig, double lo, double w, int n,
-                                                         unsigned long long *h) {
+// One law of a lane, ready for the wavefront deposit: kind 1 box, 2 Gaussian,
+// 3 box (x) Gaussian over edges ka .. kb (t0 = edge ka - v); kind 0 when the
+// sample deposits as a point (NGP bin in `ngp`: 0 underflow, k + 1 for bin k,
+// n + 1 overflow), -1 when the lane has no sample.
+struct LawLane {
+    int kind, ka, kb, ngp;
+    float t0, sf, inv_s;
+};
+
+__device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double ksig, double lo,
+                                             double w, int n) {
+    LawLane L{0, 0, -1, 0, 0.0f, 0.0f, 0.0f};
     const double half = 0.5 * w;
-    int mode;
     double se = s;
     if (dep == 2) {  // GAUSS
         const double ks = ksig * w;
         se = sqrt(s * s + ks * ks);
-        mode = se > 0.0 ? 2 : 0;
+        L.kind = se > 0.0 ? 2 : 0;
     } else if (dep == 1) {  // CIC
-        mode = s > 0.0 ? 3 : 1;
+        L.kind = s > 0.0 ? 3 : 1;
     } else {
-        mode = s > 0.0 ? 2 : 0;
+        L.kind = s > 0.0 ? 2 : 0;
     }
-    if (mode == 0) {
-        ngp(v, lo, w, n, h);
-        return;
-    }
-    const double reach = mode == 1 ? half : (mode == 2 ? 6.0 * se : 6.0 * se + half);
-    int ka = (int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0);
-    int kb = (int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0);
-    ka = max(ka, 0);
-    kb = min(kb, n);
-    if (ka > kb) {
-        ngp(v, lo, w, n, h);  // the whole law lies inside one bin (or outside)
-        return;
-    }
-    const float sf = (float)se, inv_s = mode >= 2 ? (float)(1.0 / se) : 0.0f;
-    const float wf = (float)w, inv_w = (float)(1.0 / w), hf = (float)half;
-    PsiPair lower{0.0f, 0.0f};
-    if (mode == 3) lower = psi_pair((float)(fma((double)ka, w, lo) - v) - hf, sf, inv_s);
-    unsigned long long qprev = 0;
-    for (int k = ka; k <= kb; ++k) {
-        const float t = (float)(fma((double)k, w, lo) - v);  // edge - v
-        const bool upper = t > 0.0f;  // F is taken from the upper tail there
-        float F;
-        if (mode == 1) {
-            F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
-        } else if (mode == 2) {
-            F = 0.5f * erfcf((upper ? t : -t) * inv_s * 0.70710678118654752440f);
+    if (L.kind != 0) {
+        const double reach =
+            L.kind == 1 ? half : (L.kind == 2 ? 6.0 * se : 6.0 * se + half);
+        const int ka = max((int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0), 0);
+        const int kb = min((int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0), n);
+        if (ka > kb) {
+            L.kind = 0;  // the whole law lies inside one bin (or outside)
         } else {
-            const PsiPair up = psi_pair(t + hf, sf, inv_s);
-            F = upper ? (lower.Pc - up.Pc) * inv_w : (up.P - lower.P) * inv_w;
-            lower = up;
+            L.ka = ka;
+            L.kb = kb;
+            L.t0 = (float)(fma((double)ka, w, lo) - v);
+            L.sf = (float)se;
+            L.inv_s = L.kind >= 2 ? (float)(1.0 / se) : 0.0f;
         }
-        (void)wf;
-        F = fminf(fmaxf(F, 0.0f), 1.0f);
-        const unsigned long long qf = (unsigned long long)llrintf(F * 4294967296.0f);
-        unsigned long long q = upper ? kOne - qf : qf;
-        q = q < qprev ? qprev : q;
-        const int bin = k == 0 ? n : k - 1;  // mass between edge k-1 and edge k
-        if (q != qprev) atomicAdd(&h[bin], q - qprev);
-        qprev = q;
     }
-    const int bin = kb == n ? n + 1 : kb;  // mass above the last edge in the window
-    if (qprev != kOne) atomicAdd(&h[bin], kOne - qprev);
+    if (L.kind == 0) {
+        const double x = (v - lo) / w;  // bin floor(x); v on an edge goes up
+        L.ngp = !(x >= 0.0) ? 0 : (x >= (double)n ? n + 1 : (int)x + 1);
+    }
+    return L;
+}
+
+// The laws of the 64 lanes of a wavefront, deposited together.  A law spans
+// anywhere from one bin to the whole window, so one lane per law would leave
+// most lanes idle behind the widest: instead the edges of all 64 laws are laid
+// end to end (law s takes edges ka - 1 .. kb, the first only to supply the
+// lower box end of edge ka) and the lanes take 64 consecutive positions at a
+// time, each finding its law by a binary search over the laws' offsets.
+// Q[e] (u64) accumulates the quantised weight at or below edge e of the laws
+// that cover e; cnt[c] (u32) counts the samples whose weight is all at or
+// below edge c - 1 (a point in bin c - 1, or a law ending at edge c - 1), so
+// that edge e carries Q[e] + 2^32 sum_(c <= e) cnt[c] in total.
+__device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
+                                             unsigned long long *Q, unsigned int *cnt) {
+    const int lane = threadIdx.x & 63;
+    if (L.kind == 0) atomicAdd(&cnt[L.ngp], 1u);
+    if (L.kind > 0) atomicAdd(&cnt[L.kb + 1], 1u);
+    const int np = L.kind > 0 ? L.kb - L.ka + 2 : 0;
+    int incl = np;  // inclusive scan of the position counts over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const int off = incl - np;
+    const int total = __shfl(incl, 63, 64);
+    const float wf = (float)w, inv_w = (float)(1.0 / w);
+    float cP = 0.0f, cPc = 0.0f;  // box ends of the previous block's last position
+    for (int base = 0; base < total; base += 64) {
+        const int p = base + lane;
+        int own = 0;  // the last lane whose offset is <= p
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(off, own + step, 64) <= p) own += step;
+        const int kind = __shfl(L.kind, own, 64);
+        const int ka = __shfl(L.ka, own, 64);
+        const int rel = p - __shfl(off, own, 64) - 1;  // edge - ka
+        const float t0 = __shfl(L.t0, own, 64), sf = __shfl(L.sf, own, 64);
+        const float inv_s = __shfl(L.inv_s, own, 64);
+        const bool live = p < total && rel >= 0;
+        const float t = fmaf((float)rel, wf, t0);
+        const bool upper = t > 0.0f;
+        PsiPair up{0.0f, 0.0f};
+        if (kind == 3) up = psi_pair(t + hf, sf, inv_s);
+        float lP = __shfl_up(up.P, 1, 64), lPc = __shfl_up(up.Pc, 1, 64);
+        if (lane == 0) {
+            lP = cP;
+            lPc = cPc;
+        }
+        cP = __shfl(up.P, 63, 64);
+        cPc = __shfl(up.Pc, 63, 64);
+        if (live) {
+            float F;
+            if (kind == 3)
+                F = upper ? (lPc - up.Pc) * inv_w : (up.P - lP) * inv_w;
+            else if (kind == 2)
+                F = gauss_tail(t * inv_s);
+            else
+                F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
+            F = fminf(fmaxf(F, 0.0f), 1.0f);
+            // below 1, 2^32 F rounds to at most 2^32 - 256: 32 bits
+            const unsigned long long qf =
+                F >= 1.0f ? kOne : (unsigned long long)(uint32_t)rintf(F * 4294967296.0f);
+            const unsigned long long q = upper ? kOne - qf : qf;
+            if (q) atomicAdd(&Q[ka + rel], q);
+        }
+    }
 }
 
 // ===========================================================================

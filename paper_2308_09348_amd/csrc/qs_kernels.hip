@@ -220,12 +220,64 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
 // ===========================================================================
 // Deposit kernel: final states -> observables -> histograms and moments
 // ===========================================================================
+// Exclusive prefix sum over the block of one value a thread (256 threads);
+// *total receives the sum.
+__device__ __forceinline__ unsigned int block_scan(unsigned int v, unsigned int *wsum,
+                                                   unsigned int *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    unsigned int before = 0, all = 0;
+    for (int w = 0; w < kDepBlock / 64; ++w) {
+        if (w < wid) before += wsum[w];
+        all += wsum[w];
+    }
+    __syncthreads();  // wsum is reused by the next scan
+    *total = all;
+    return before + x - v;
+}
+
+// Bin masses of one histogram of n bins from the edge accumulators of a tile
+// (see wave_deposit): edge e carries T(e) = Q[e] + 2^32 C(e), C(e) =
+// sum_(c <= e) cnt[c]; bin b gets T(b+1) - T(b), the underflow T(0), the
+// overflow 2^32 S - T(n) with S = sum of all cnt (every sample counts once).
+// Added to the global words G[0 .. n+1] (bins, underflow, overflow).
+__device__ void flush_edges(const unsigned long long *Q, const unsigned int *cnt, int n,
+                            unsigned long long *G, unsigned int *wsum) {
+    const int m = (n + 2 + kDepBlock - 1) / kDepBlock;  // cnt entries a thread
+    const int c0 = threadIdx.x * m, c1 = min(c0 + m, n + 2);
+    unsigned int local = 0;
+    for (int c = c0; c < c1; ++c) local += cnt[c];
+    unsigned int S;
+    unsigned int C = block_scan(local, wsum, &S);
+    const unsigned long long one = kOne;
+    unsigned long long prev = c0 >= 1 && c0 <= n + 1 ? Q[c0 - 1] + one * C : 0ull;
+    for (int e = c0; e < c1 && e <= n; ++e) {
+        C += cnt[e];
+        const unsigned long long T = Q[e] + one * C;
+        const long long mass = (long long)(e == 0 ? T : T - prev);
+        const int bin = e == 0 ? n : e - 1;
+        if (mass > 0) atomicAdd(&G[bin], (unsigned long long)mass);
+        if (e == n) {
+            const long long over = (long long)(one * S - T);
+            if (over > 0) atomicAdd(&G[n + 1], (unsigned long long)over);
+        }
+        prev = T;
+    }
+}
+
 __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);
     __shared__ int64_t slot;
     __shared__ double red[kDepBlock / 64][P_N];
     __shared__ float redmax[kDepBlock / 64];
+    __shared__ unsigned int wsum[kDepBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (;;) {
         const int64_t item = next_item(&P.queue[1], &slot);
@@ -233,8 +285,17 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
         const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, true));
         const ShotParams &sp = P.shots[s];
         const ShotOut &so = P.outs[s];
-        const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2, nh = nh_e + nh_t + sp.n_a;
-        for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0ull;
+        const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2;
+        // LDS: edge weights Qe [n_e + 1], Qt [n_th + 1] (u64); counters
+        // ce [n_e + 2], ct [n_th + 2], ca [n_a] (u32)
+        unsigned long long *Qe = reinterpret_cast<unsigned long long *>(smem);
+        unsigned long long *Qt = Qe + sp.n_e + 1;
+        unsigned int *ce = reinterpret_cast<unsigned int *>(Qt + sp.n_th + 1);
+        unsigned int *ct = ce + nh_e;
+        unsigned int *ca = ct + nh_t;
+        const int nq = sp.n_e + 1 + sp.n_th + 1, nc = nh_e + nh_t + sp.n_a;
+        for (int k = threadIdx.x; k < nq; k += blockDim.x) Qe[k] = 0ull;
+        for (int k = threadIdx.x; k < nc; k += blockDim.x) ce[k] = 0u;
         __syncthreads();
 
         double acc[P_N];
@@ -244,56 +305,65 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
         int flags = 0;
         const int64_t i0 = (item - sp.ditem0) * kDepTile;
         const int64_t i1 = i0 + kDepTile < sp.n_samples ? i0 + kDepTile : sp.n_samples;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            const int64_t k = sp.state_off + i;
-            const double mu_f = P.st.mu[k], s2_f = P.st.s2[k], S0 = P.st.S0[k], g0 = P.st.g0[k];
-            const double thx_m = 1e3 * P.st.thx[k], thy_m = 1e3 * P.st.thy[k];
-            const float cmx = P.st.cmx[k];
-            if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
-                flags |= kFlagNonFinite;  // also raised by the phase kernel
-                continue;
-            }
-            chimax = fmaxf(chimax, cmx);
-            // Sec. 5.2: the direction is kept, the stochastic broadening
-            // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
-            const double sigf = sqrt(fmax(s2_f, 0.0));
-            const double a_eff = sp.a0 * S0;
-            const double sigth =
-                1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
+        const float hfe = (float)(0.5 * sp.e_w), hft = (float)(0.5 * sp.th_w);
+        // every lane runs every round (the wavefront deposit needs them all)
+        for (int64_t base = i0; base < i1; base += blockDim.x) {
+            const int64_t i = base + threadIdx.x;
+            LawLane le{-1, 0, -1, 0, 0.0f, 0.0f, 0.0f}, lt = le;
+            if (i < i1) {
+                const int64_t k = sp.state_off + i;
+                const double mu_f = P.st.mu[k], s2_f = P.st.s2[k], S0 = P.st.S0[k];
+                const double g0 = P.st.g0[k];
+                const double thx_m = 1e3 * P.st.thx[k], thy_m = 1e3 * P.st.thy[k];
+                const float cmx = P.st.cmx[k];
+                if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
+                    flags |= kFlagNonFinite;  // also raised by the phase kernel
+                } else {
+                    chimax = fmaxf(chimax, cmx);
+                    // Sec. 5.2: the direction is kept, the stochastic broadening
+                    // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
+                    const double sigf = sqrt(fmax(s2_f, 0.0));
+                    const double a_eff = sp.a0 * S0;
+                    const double sigth =
+                        1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
+                    le = law_setup(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e);
+                    lt = law_setup(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w,
+                                   sp.n_th);
+                    {
+                        int ka = (int)floor(S0 * (double)sp.n_a);
+                        ka = min(max(ka, 0), sp.n_a - 1);
+                        atomicAdd(&ca[ka], 1u);
+                    }
+                    const double de = mu_f - sp.gamma0;
+                    acc[P_S1E] += de;
+                    acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
+                    acc[P_S1X] += thx_m;
+                    acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
+                    acc[P_S1Y] += thy_m;
+                    acc[P_S2Y] += thy_m * thy_m;
+                    acc[P_SAEFF] += a_eff;
+                    acc[P_SRAD] += 1.0 - mu_f / g0;
+                    acc[P_SSIGF] += sigf;
 
-            deposit_law(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e, hist);
-            deposit_law(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w, sp.n_th,
-                        hist + nh_e);
-            {
-                int ka = (int)floor(S0 * (double)sp.n_a);
-                ka = min(max(ka, 0), sp.n_a - 1);
-                atomicAdd(&hist[nh_e + nh_t + ka], kOne);
+                    if (so.samples != nullptr && i % so.rec_stride == 0 &&
+                        i / so.rec_stride < so.rec_n) {
+                        double *r = so.samples + (i / so.rec_stride) * 11;
+                        r[0] = mu_f;
+                        r[1] = s2_f;
+                        r[2] = thx_m;
+                        r[3] = thy_m;
+                        r[4] = sigth;
+                        r[5] = a_eff;
+                        r[6] = cmx;
+                        r[7] = g0;
+                        r[8] = 0.0;
+                        r[9] = 0.0;
+                        r[10] = 0.0;
+                    }
+                }
             }
-            const double de = mu_f - sp.gamma0;
-            acc[P_S1E] += de;
-            acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
-            acc[P_S1X] += thx_m;
-            acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
-            acc[P_S1Y] += thy_m;
-            acc[P_S2Y] += thy_m * thy_m;
-            acc[P_SAEFF] += a_eff;
-            acc[P_SRAD] += 1.0 - mu_f / g0;
-            acc[P_SSIGF] += sigf;
-
-            if (so.samples != nullptr && i % so.rec_stride == 0 && i / so.rec_stride < so.rec_n) {
-                double *r = so.samples + (i / so.rec_stride) * 11;
-                r[0] = mu_f;
-                r[1] = s2_f;
-                r[2] = thx_m;
-                r[3] = thy_m;
-                r[4] = sigth;
-                r[5] = a_eff;
-                r[6] = cmx;
-                r[7] = g0;
-                r[8] = 0.0;
-                r[9] = 0.0;
-                r[10] = 0.0;
-            }
+            wave_deposit(le, sp.e_w, hfe, Qe, ce);
+            wave_deposit(lt, sp.th_w, hft, Qt, ct);
         }
 
         // ---- item reduction of moments (fixed order) ----
@@ -317,11 +387,12 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
             for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
             part[P_N] = m;
         }
-        for (int k = threadIdx.x; k < nh; k += blockDim.x) {
-            const unsigned long long v = hist[k];
-            if (v) atomicAdd(&P.hist[sp.hist_off + k], v);
-        }
-        __syncthreads();  // the next item clears the LDS histogram
+        unsigned long long *G = P.hist + sp.hist_off;
+        flush_edges(Qe, ce, sp.n_e, G, wsum);
+        flush_edges(Qt, ct, sp.n_th, G + nh_e, wsum);
+        for (int k = threadIdx.x; k < sp.n_a; k += blockDim.x)
+            if (ca[k]) atomicAdd(&G[nh_e + nh_t + k], kOne * ca[k]);
+        __syncthreads();  // the next item clears the LDS words
     }
 }
 
@@ -498,7 +569,9 @@ hipError_t launch_phase_nodes(const BatchParams &p, const float *env32, const do
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
-size_t deposit_lds_bytes(int max_hist_words) { return (size_t)max_hist_words * 8; }
+// edge weights (u64, one per edge) and counters (u32, one per bin and two
+// more) of the deposit kernel: at most 12 bytes a histogram word
+size_t deposit_lds_bytes(int max_hist_words) { return (size_t)max_hist_words * 12; }
 
 hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t s) {
     const void *fn = reinterpret_cast<const void *>(&deposit_kernel);
