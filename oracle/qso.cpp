@@ -134,6 +134,9 @@ int validate(const qso_problem *p) {
     if (p->n_e < 1 || p->n_th < 1 || p->n_a < 1) return -1;
     if (!(p->e_hi > p->e_lo) || !(p->th_hi_mrad > p->th_lo_mrad)) return -1;
     if (p->envelope != QSO_ENV_GAUSS && p->envelope != QSO_ENV_SIN2) return -1;
+    if ((p->transverse != QSO_PROFILE_GAUSS && p->transverse != QSO_PROFILE_FLAT) ||
+        (p->longitudinal != QSO_PROFILE_GAUSS && p->longitudinal != QSO_PROFILE_FLAT))
+        return -1;
     if (p->rr_model != QSO_RR_CLASSICAL && p->rr_model != QSO_RR_QUANTUM) return -1;
     if (p->amp_mode != QSO_AMP_A0EFF && p->amp_mode != QSO_AMP_LOCAL) return -1;
     if (p->deposit < QSO_DEP_POINT || p->deposit > QSO_DEP_GAUSS) return -1;
@@ -383,16 +386,21 @@ struct SampleIn {
     T x, y, z, gamma0, thx, thy;  /* um, um, um, -, rad, rad */
 };
 
-void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
-    /* counter (i, shot, k, 0), key = seed; 24-bit uniforms in (0, 1) */
+/* The six 24-bit uniforms in (0, 1) of sample i: counter (i, shot, k, 0),
+ * key = seed. */
+void uniforms(uint64_t seed, int32_t shot, int64_t i, double u[6]) {
     uint32_t r[8];
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (uint32_t k = 0; k < 2; ++k) {
         const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)shot, k, 0u};
         qso_philox4x32_10(ctr, key, &r[4 * k]);
     }
-    double u[6];
     for (int m = 0; m < 6; ++m) u[m] = ((double)(r[m] >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+
+void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
+    double u[6];
+    uniforms(seed, shot, i, u);
     /* Box-Muller on consecutive pairs */
     for (int m = 0; m < 3; ++m) {
         const double R = std::sqrt(-2.0 * std::log(u[2 * m]));
@@ -401,14 +409,27 @@ void normals(uint64_t seed, int32_t shot, int64_t i, double n[6]) {
     }
 }
 
+/* A sample of the beam (Sec. 2 volume element).  Gaussian profiles use the
+ * Box-Muller normals; the flat-top beams of Table 1 (Wide, Thin) use the
+ * same uniforms directly: a uniform disk of radius sigma_r, r = sigma_r
+ * sqrt(u0) at the Box-Muller angle 2 pi u1, and a uniform length sigma_z,
+ * z = sigma_z (u2 - 1/2). */
 template <class T>
 SampleIn<T> make_sample(const qso_problem *p, const Params<T> &P, int64_t i) {
-    double n[6];
+    double n[6], u[6];
     normals(p->seed, p->shot, i, n);
+    uniforms(p->seed, p->shot, i, u);
     SampleIn<T> s;
-    s.x = P.x_off + p->sigma_r_um * n[0];
-    s.y = P.y_off + p->sigma_r_um * n[1];
-    s.z = T(p->sigma_z_um * n[2]);
+    if (p->transverse == QSO_PROFILE_FLAT) {
+        const double r = p->sigma_r_um * std::sqrt(u[0]);
+        s.x = P.x_off + r * std::cos(2.0 * kPi * u[1]);
+        s.y = P.y_off + r * std::sin(2.0 * kPi * u[1]);
+    } else {
+        s.x = P.x_off + p->sigma_r_um * n[0];
+        s.y = P.y_off + p->sigma_r_um * n[1];
+    }
+    s.z = T(p->longitudinal == QSO_PROFILE_FLAT ? p->sigma_z_um * (u[2] - 0.5)
+                                                : p->sigma_z_um * n[2]);
     s.gamma0 = P.gamma0 + P.sigma_gamma * n[3];
     s.thx = 1e-3 * P.div_mrad * n[4];
     s.thy = 1e-3 * P.div_mrad * n[5];

@@ -34,6 +34,7 @@ enum { QSO_ENV_GAUSS = 0, QSO_ENV_SIN2 = 1 };
 enum { QSO_RR_CLASSICAL = 0, QSO_RR_QUANTUM = 1 };
 enum { QSO_AMP_A0EFF = 0, QSO_AMP_LOCAL = 1 };
 enum { QSO_DEP_POINT = 0, QSO_DEP_CIC = 1, QSO_DEP_GAUSS = 2 };
+enum { QSO_PROFILE_GAUSS = 0, QSO_PROFILE_FLAT = 1 };
 
 /* One scattering problem.  Lengths in micrometres, times in femtoseconds,
  * angles in milliradians, energies in units of m c^2. */
@@ -65,7 +66,12 @@ typedef struct qso_problem {
     int32_t amp_mode;
     int32_t deposit;
     /* bins */
-    int32_t n_e, n_th, n_a, pad_;
+    int32_t n_e, n_th, n_a;
+    int32_t transverse;   /* QSO_PROFILE_GAUSS: rms sigma_r_um per axis;
+                             QSO_PROFILE_FLAT: uniform disk of radius sigma_r_um */
+    int32_t longitudinal; /* QSO_PROFILE_GAUSS: rms sigma_z_um;
+                             QSO_PROFILE_FLAT: uniform over a length sigma_z_um */
+    int32_t pad_;
     double e_lo, e_hi;          /* energy window, units of m c^2          */
     double th_lo_mrad, th_hi_mrad;
 } qso_problem;

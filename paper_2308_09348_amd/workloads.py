@@ -18,6 +18,7 @@ BASE = dict(
     x_off_um=0.0, y_off_um=0.0, delay_fs=0.0,
     # beam
     gamma0=2000.0, sigma_gamma=100.0, sigma_r_um=0.0, sigma_z_um=0.0, div_mrad=0.0,
+    transverse="gauss", longitudinal="gauss",
     # numerics
     n_samples=10_000, n_steps=512, window_fwhm=2.5, seed=1, shot=0,
     rr_model="classical", amp_mode="a0eff", deposit="point",
