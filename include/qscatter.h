@@ -51,6 +51,7 @@ enum { QS_RR_CLASSICAL = 0, QS_RR_QUANTUM = 1 };
 enum { QS_AMP_A0EFF = 0, QS_AMP_LOCAL = 1 };
 enum { QS_DEP_POINT = 0, QS_DEP_CIC = 1, QS_DEP_GAUSS = 2 };
 enum { QS_PREC_FP32 = 0, QS_PREC_FP64 = 1 };
+enum { QS_PROFILE_GAUSS = 0, QS_PROFILE_FLAT = 1 };
 
 /* Laser (Sec. 2 eq. a0eff; misalignment of Table 1).  Lengths in um,
  * times in fs.  The laser propagates along +z with its peak at z = c t and
@@ -69,14 +70,18 @@ typedef struct qs_laser {
 } qs_laser;
 
 /* Electron beam (abstract: broadband beams, divergence).  The beam moves
- * along -z; positions are per-axis Gaussian, taken when the centroid meets
- * the laser peak. */
+ * along -z; positions are taken when the centroid meets the laser peak.  The
+ * density profiles are Gaussian, or flat-top as the Wide and Thin beams of
+ * Sec. 2 (Table 1): a uniform disk of radius sigma_r_um and a uniform length
+ * sigma_z_um. */
 typedef struct qs_beam {
     double gamma0;       /* mean initial Lorentz factor, > 1                   */
     double sigma_gamma;  /* rms of the initial Lorentz factor, >= 0           */
-    double sigma_r_um;   /* per-axis rms transverse size, >= 0                */
-    double sigma_z_um;   /* rms length, >= 0                                  */
+    double sigma_r_um;   /* GAUSS: per-axis rms transverse size; FLAT: radius  */
+    double sigma_z_um;   /* GAUSS: rms length; FLAT: full length, >= 0        */
     double div_mrad;     /* per-plane rms divergence, >= 0                    */
+    int32_t transverse;  /* QS_PROFILE_*                                      */
+    int32_t longitudinal; /* QS_PROFILE_*                                     */
 } qs_beam;
 
 /* Numerics of the phase-space quadrature. */

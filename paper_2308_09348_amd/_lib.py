@@ -17,6 +17,7 @@ RR_MODEL = {"classical": 0, "quantum": 1}
 AMP_MODE = {"a0eff": 0, "local": 1}
 DEPOSIT = {"point": 0, "cic": 1, "gauss": 2}
 PRECISION = {"fp32": 0, "fp64": 1}
+PROFILE = {"gauss": 0, "flat": 1}
 
 M_N = 16
 S_N = 11
@@ -36,7 +37,8 @@ class Laser(ctypes.Structure):
 class Beam(ctypes.Structure):
     _fields_ = [("gamma0", ctypes.c_double), ("sigma_gamma", ctypes.c_double),
                 ("sigma_r_um", ctypes.c_double), ("sigma_z_um", ctypes.c_double),
-                ("div_mrad", ctypes.c_double)]
+                ("div_mrad", ctypes.c_double), ("transverse", ctypes.c_int32),
+                ("longitudinal", ctypes.c_int32)]
 
 
 class Numerics(ctypes.Structure):
@@ -211,7 +213,9 @@ def structs(params):
                delay_fs=params["delay_fs"])
     be = Beam(gamma0=params["gamma0"], sigma_gamma=params["sigma_gamma"],
               sigma_r_um=params["sigma_r_um"], sigma_z_um=params["sigma_z_um"],
-              div_mrad=params["div_mrad"])
+              div_mrad=params["div_mrad"],
+              transverse=_enum(PROFILE, params.get("transverse", "gauss")),
+              longitudinal=_enum(PROFILE, params.get("longitudinal", "gauss")))
     nu = Numerics(n_samples=params["n_samples"], n_steps=params["n_steps"],
                   shot=params.get("shot", 0), window_fwhm=params["window_fwhm"],
                   seed=params["seed"], rr_model=_enum(RR_MODEL, params["rr_model"]),

@@ -503,14 +503,13 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
     const float chi_top = (float)(1 << (kEMax + 1));
 
     // ---- sample and geometry (FP64) ----
-    double nrm[6];
-    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
-    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
-    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
-    const double z = sp.sigma_z * nrm[2];
-    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
-    const double thx = sp.div_rad * nrm[4];
-    const double thy = sp.div_rad * nrm[5];
+    SampleCoords sc;
+    sample_coords(sp, P.key0, P.key1, i, sc);
+    const double *nrm = sc.n;
+    const double x = sc.x, y = sc.y, z = sc.z;
+    const double g0 = sc.g0;
+    const double thx = sc.thx;
+    const double thy = sc.thy;
     const double inv_w0 = sqrt(sp.inv_w0sq);
     const double xc = fma(thx, 0.5 * z, x), yc = fma(thy, 0.5 * z, y);
     const double zstar = fma(0.5, z, sp.z_delay);

@@ -98,6 +98,9 @@ qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs
     if (!(B->gamma0 > 1) || !(B->sigma_gamma >= 0) || !(B->sigma_r_um >= 0) ||
         !(B->sigma_z_um >= 0) || !(B->div_mrad >= 0))
         return set_err(c, "beam parameter out of range"), QS_EINVAL;
+    if ((B->transverse != QS_PROFILE_GAUSS && B->transverse != QS_PROFILE_FLAT) ||
+        (B->longitudinal != QS_PROFILE_GAUSS && B->longitudinal != QS_PROFILE_FLAT))
+        return set_err(c, "unknown beam profile"), QS_EINVAL;
     if (n_samples < 1 || n_samples > (int64_t)1 << 32)
         return set_err(c, "n_samples must be in [1, 2^32]"), QS_EINVAL;
     if (H->n_e < 1 || H->n_e > 4096 || H->n_th < 1 || H->n_th > 4096 || H->n_a < 1 ||
@@ -575,6 +578,8 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         p.sigma_gamma = bm.sigma_gamma;
         p.sigma_r = bm.sigma_r_um;
         p.sigma_z = bm.sigma_z_um;
+        p.profile = (bm.transverse == QS_PROFILE_FLAT ? qs::kFlatR : 0) |
+                    (bm.longitudinal == QS_PROFILE_FLAT ? qs::kFlatZ : 0);
         p.div_rad = 1e-3 * bm.div_mrad;
         p.a0f = (float)p.a0;
         p.inv_w0sqf = (float)p.inv_w0sq;

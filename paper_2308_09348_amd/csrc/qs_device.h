@@ -33,30 +33,58 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
-// Six standard normals of sample i: counter (i, shot, k, 0) for k = 0, 1,
-// 24-bit uniforms u = ((r >> 8) + 1/2) 2^-24, Box-Muller on pairs.
-__device__ __forceinline__ void sample_normals(uint32_t i, uint32_t shot, uint32_t k0, uint32_t k1,
-                                               double n[6]) {
+// The beam coordinates of sample i of a shot (a volume element of Sec. 2):
+// counter (i, shot, k, 0) for k = 0, 1 gives eight words, the first six make
+// 24-bit uniforms u = ((r >> 8) + 1/2) 2^-24, and Box-Muller on the pairs
+// (u0, u1), (u2, u3), (u4, u5) gives six standard normals n.  Transverse
+// position: x_off + sigma_r (n0, n1), or for a flat-top beam the uniform disk
+// x_off + sigma_r sqrt(u0) (cos 2 pi u1, sin 2 pi u1); longitudinal offset
+// sigma_z n2, or sigma_z (u2 - 1/2) for a flat-top beam of length sigma_z;
+// gamma0 + sigma_gamma n3; angles div (n4, n5).
+struct SampleCoords {
+    double x, y, z, g0, thx, thy;
+    double n[6];
+};
+
+__device__ __forceinline__ void sample_coords(const ShotParams &sp, uint32_t k0, uint32_t k1,
+                                              int64_t i, SampleCoords &sc) {
     uint32_t r[8];
 #pragma unroll
     for (uint32_t k = 0; k < 2; ++k) {
-        uint32_t c[4] = {i, shot, k, 0u};
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)sp.shot_word, k, 0u};
         philox4x32_10(c, k0, k1);
         r[4 * k + 0] = c[0];
         r[4 * k + 1] = c[1];
         r[4 * k + 2] = c[2];
         r[4 * k + 3] = c[3];
     }
+    double u[6], cs0 = 0.0, sn0 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) u[m] = ((double)(r[m] >> 8) + 0.5) * 0x1p-24;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const double u1 = ((double)(r[2 * m] >> 8) + 0.5) * 0x1p-24;
-        const double u2 = ((double)(r[2 * m + 1] >> 8) + 0.5) * 0x1p-24;
-        const double R = sqrt(-2.0 * log(u1));
+        const double R = sqrt(-2.0 * log(u[2 * m]));
         double s, c;
-        sincospi(2.0 * u2, &s, &c);
-        n[2 * m] = R * c;
-        n[2 * m + 1] = R * s;
+        sincospi(2.0 * u[2 * m + 1], &s, &c);
+        sc.n[2 * m] = R * c;
+        sc.n[2 * m + 1] = R * s;
+        if (m == 0) {
+            cs0 = c;
+            sn0 = s;
+        }
     }
+    if (sp.profile & kFlatR) {
+        const double rad = sp.sigma_r * sqrt(u[0]);
+        sc.x = fma(rad, cs0, sp.x_off);
+        sc.y = fma(rad, sn0, sp.y_off);
+    } else {
+        sc.x = fma(sp.sigma_r, sc.n[0], sp.x_off);
+        sc.y = fma(sp.sigma_r, sc.n[1], sp.y_off);
+    }
+    sc.z = (sp.profile & kFlatZ) ? sp.sigma_z * (u[2] - 0.5) : sp.sigma_z * sc.n[2];
+    sc.g0 = fma(sp.sigma_gamma, sc.n[3], sp.gamma0);
+    sc.thx = sp.div_rad * sc.n[4];
+    sc.thy = sp.div_rad * sc.n[5];
 }
 
 // ===========================================================================
@@ -235,14 +263,12 @@ struct Path {
 __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0, uint32_t key1,
                                             int64_t i, double &g0, double &thx, double &thy,
                                             Path<double> &pd, double &S0) {
-    double nrm[6];
-    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, key0, key1, nrm);
-    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
-    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
-    const double z = sp.sigma_z * nrm[2];
-    g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
-    thx = sp.div_rad * nrm[4];
-    thy = sp.div_rad * nrm[5];
+    SampleCoords sc;
+    sample_coords(sp, key0, key1, i, sc);
+    const double x = sc.x, y = sc.y, z = sc.z;
+    g0 = sc.g0;
+    thx = sc.thx;
+    thy = sc.thy;
     pd.xc = fma(thx, 0.5 * z, x);
     pd.yc = fma(thy, 0.5 * z, y);
     pd.thx = thx;

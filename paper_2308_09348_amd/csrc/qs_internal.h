@@ -70,7 +70,8 @@ struct ShotParams {
     double a0, inv_w0sq, inv_zR, x_off, y_off, z_delay;
     double gamma0, sigma_gamma, sigma_r, sigma_z, div_rad;
     float a0f, inv_w0sqf, inv_zRf, pad0;
-    int32_t plane_wave, mid_interp, shot_word, pad1;
+    int32_t plane_wave, mid_interp, shot_word;
+    int32_t profile;     // kFlatR | kFlatZ: flat-top beam profiles
     int64_t n_samples;   // samples of this shot
     int64_t state_off;   // index of its first sample state
     int64_t item0;       // its first phase work item
@@ -84,6 +85,12 @@ struct ShotParams {
     int64_t node_off;             // index of its first node state
     double g_node_lo, g_node_step;  // gamma0 of node m: g_node_lo + m g_node_step
 };
+
+// Beam profile bits of ShotParams::profile: a uniform disk of radius sigma_r
+// (else Gaussian of rms sigma_r per axis), a uniform length sigma_z (else
+// Gaussian of rms sigma_z).
+constexpr int kFlatR = 1;
+constexpr int kFlatZ = 2;
 
 // Output pointers of one shot (device table).
 struct ShotOut {

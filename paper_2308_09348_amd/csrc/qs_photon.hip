@@ -280,14 +280,12 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     const int N = P.n_steps;
     const bool local = LOCAL && !sp.plane_wave;
 
-    double nrm[6];
-    sample_normals((uint32_t)i, (uint32_t)sp.shot_word, P.key0, P.key1, nrm);
-    const double x = fma(sp.sigma_r, nrm[0], sp.x_off);
-    const double y = fma(sp.sigma_r, nrm[1], sp.y_off);
-    const double z = sp.sigma_z * nrm[2];
-    const double g0 = fma(sp.sigma_gamma, nrm[3], sp.gamma0);
-    const double thx = sp.div_rad * nrm[4];
-    const double thy = sp.div_rad * nrm[5];
+    SampleCoords sc;
+    sample_coords(sp, P.key0, P.key1, i, sc);
+    const double x = sc.x, y = sc.y, z = sc.z;
+    const double g0 = sc.g0;
+    const double thx = sc.thx;
+    const double thy = sc.thy;
     Path<double> pd;
     pd.xc = fma(thx, 0.5 * z, x);
     pd.yc = fma(thy, 0.5 * z, y);

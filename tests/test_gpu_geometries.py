@@ -1,0 +1,165 @@
+"""Flat-top beams (the Wide and Thin beams of Table 1) on the GPU path: the
+printed Table 1 and Table 2 laws checked on the GPU's own histograms, and
+parity with the oracle for the forward pass, the adjoint, the photon
+spectrum and the plane-wave reconstruction with flat-top profiles (the same
+tolerances as the Gaussian-beam parity tests).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import paper_tables as T
+from paper_2308_09348_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09348_amd as qs
+    ctx = qs.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def _chi2_ok(obs, exp, min_exp=5.0, p_min=1e-4):
+    obs = np.asarray(obs, float)
+    exp = np.asarray(exp, float)
+    keep = exp >= min_exp
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    if e[-1] < min_exp:
+        o[-2] += o[-1]
+        e[-2] += e[-1]
+        o, e = o[:-1], e[:-1]
+    x2 = float(np.sum((o - e) ** 2 / e))
+    return stats.chi2.sf(x2, len(e) - 1) > p_min, x2, len(e) - 1
+
+
+LAMBDA, W0, L = 1.0, 2.0, 100.0
+ZR = math.pi * W0 ** 2 / LAMBDA
+
+
+def _geometry(kind, n, d_par=0.0, **kw):
+    p = workloads.scaled(workloads.plane_wave_1d(), n_samples=n, n_steps=8,
+                         lambda_um=LAMBDA, w0_um=W0, sigma_r_um=0.0 if kind == "thin" else 30.0,
+                         sigma_z_um=L, transverse="flat", longitudinal="flat",
+                         delay_fs=2.0 * d_par / 0.299792458, div_mrad=0.0, sigma_gamma=0.0,
+                         a0=10.0, amp_mode="a0eff", rr_model="classical", n_a=40, seed=31)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("d_par", [0.0, 10.0, 40.0])
+def test_table1_thin_beam_on_gpu(gpu, d_par):
+    n = 200000
+    p = _geometry("thin", n, d_par)
+    h = gpu.forward(p)["a0eff_hist"].cpu().numpy()
+    edges = np.linspace(0, 1, p["n_a"] + 1)
+    breaks = (T.a_of(d_par + L / 4, ZR), T.a_of(d_par - L / 4, ZR))
+    exp = T.expected_counts(lambda a: T.thin_density(a, ZR, L, d_par), edges, n, breaks)
+    ok, x2, dof = _chi2_ok(h, exp)
+    assert ok, (x2, dof)
+
+
+@pytest.mark.parametrize("d_par", [0.0, 40.0])
+def test_table1_wide_beam_on_gpu(gpu, d_par):
+    n = 1 << 21
+    p = _geometry("wide", n, d_par)
+    h = gpu.forward(p)["a0eff_hist"].cpu().numpy()
+    edges = np.linspace(0, 1, p["n_a"] + 1)
+    breaks = (T.a_of(d_par + L / 4, ZR), T.a_of(d_par - L / 4, ZR))
+    exp = T.expected_counts(lambda a: T.wide_density(a, ZR, L, d_par, W0, 30.0), edges[2:], n,
+                            breaks)
+    ok, x2, dof = _chi2_ok(h[2:], exp)
+    assert ok, (x2, dof)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_table2_thin_beam_on_gpu(gpu, precision):
+    n = 200000
+    p = _geometry("thin", n, 0.0, lambda_um=0.8, gamma0=5000.0, a0=12.0, n_steps=512,
+                  deposit="point", n_e=300, e_lo=0.0, e_hi=5000.0, precision=precision)
+    zR = math.pi * W0 ** 2 / 0.8
+    h = gpu.forward(p)["energy_hist"].cpu().numpy()
+    c = T.c_rr_gauss(0.8, p["tau_fs"])
+    g0, a0 = 5000.0, 12.0
+    g_min = g0 / (1 + c * g0 * a0 ** 2)
+    g_z = g0 / (1 + c * g0 * (a0 * T.a_of(L / 4, zR)) ** 2)
+    edges = np.linspace(p["e_lo"], p["e_hi"], p["n_e"] + 1)
+    exp = T.expected_counts(lambda g: T.thin_energy_density(g, g0, a0, c, zR, L), edges, n,
+                            (g_min, g_z))
+    ok, x2, dof = _chi2_ok(h[:-2], exp, min_exp=8.0)
+    assert ok, (x2, dof)
+
+
+# ---- parity with the oracle, flat-top beams ---------------------------------
+
+def _flat_focused(**kw):
+    """Focused-workload physics with a flat-top beam: disk of radius 4 um,
+    length 12 um."""
+    p = workloads.scaled(workloads.focused_3d(), n_samples=3037, n_steps=256,
+                         transverse="flat", longitudinal="flat", sigma_r_um=4.0,
+                         sigma_z_um=12.0)
+    p.update(kw)
+    return p
+
+
+def _check_bins(gh, oh, rel=1e-4, floor=1e-7):
+    tol = rel * np.abs(oh) + floor * oh.sum()
+    bad = np.abs(gh - oh) > tol
+    assert not bad.any(), (np.nonzero(bad)[0][:10], gh[bad][:5], oh[bad][:5])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_flat_beam_forward_parity(gpu, oracle, precision):
+    p = _flat_focused(precision=precision, deposit="cic")
+    n = p["n_samples"]
+    g = _np(gpu.forward(p, sample_stride=7, n_sample_records=n // 7 + 1))
+    o = oracle.forward(p)
+    ref = oracle.samples(p, range(0, n, 7))
+    tol = 2e-9 if precision == "fp64" else 3e-6
+    assert np.allclose(g["samples"][:, 0], ref[:, oracle.S_MU], rtol=tol, atol=0)
+    assert np.allclose(g["samples"][:, 5], ref[:, oracle.S_AEFF], rtol=1e-13, atol=0)
+    for key in ("energy_hist", "angle_hist"):
+        _check_bins(g[key], o[key])
+    for k in (1, 2, 4, 7, 9, 10):
+        assert abs(g["moments"][k] - o["moments"][k]) <= 1e-5 * abs(o["moments"][k]), k
+
+
+def test_flat_beam_adjoint_parity(gpu, oracle):
+    import torch
+    p = _flat_focused(n_samples=400, precision="fp64", deposit="gauss")
+    w = np.random.Generator(np.random.PCG64(17)).normal(size=p["n_e"] + 2)
+    go = gpu.backward(p, torch.tensor(w, dtype=torch.float64, device="cuda")).cpu().numpy()
+    _, jac = oracle.grad(p)
+    og, scale = w @ jac, np.abs(w) @ np.abs(jac)
+    assert np.all(np.abs(go - og) <= 1e-9 * scale + 1e-300), (go, og)
+
+
+def test_flat_beam_photon_parity(gpu, oracle):
+    p = _flat_focused(n_samples=200, precision="fp64", n_ph=64, ph_lo=0.0, ph_hi=2400.0)
+    g = _np(gpu.photons(p))
+    oh, oe = oracle.photons(p, p["n_ph"], p["ph_lo"], p["ph_hi"])
+    assert np.all(np.abs(g["energy"] - oe) <= 1e-10 * np.abs(oe))
+    assert np.abs(g["photon_hist"] - oh).sum() <= 2e-3 * oh.sum()
+
+
+def test_flat_beam_reconstruction_parity(gpu, oracle):
+    p = _flat_focused(amp_mode="a0eff", deposit="gauss", precision="fp64")
+    n = p["n_samples"]
+    g = _np(gpu.forward_factorised(p, 21, 17, nodes=True, sample_stride=1, n_sample_records=n))
+    o = oracle.factorised(p, 21, 17)
+    orec = oracle.factorised_samples(p, 21, 17, range(n))
+    assert np.allclose(g["samples"][:, 0], orec[:, oracle.S_MU], rtol=2e-9, atol=0)
+    assert np.all(np.abs(g["node_weights"] - o["node_weights"]) <= 1e-9 * n)
+    _check_bins(g["energy_hist"], o["energy_hist"])
