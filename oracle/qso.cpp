@@ -1200,6 +1200,80 @@ int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gno
     return 0;
 }
 
+/* ---- photon angular distribution (Sec. 5.1) --------------------------------- */
+/* Photons leave along the electron's direction within a cone of about 1/gamma.
+ * In a linearly polarised plane wave the transverse momentum in the
+ * polarisation plane is the vector potential, so at a stage with amplitude a
+ * and mean energy mu the emission angle in x is theta_x + a / mu (theta_x the
+ * sample's own direction) and in y is theta_y; the cone adds 1 / mu^2 to the
+ * mean square in each plane (reading: rms 1/gamma per plane).  The paper's
+ * photon-number weighting (theta^2 averaged with N_gamma / N_e over the
+ * a0,eff distribution) is taken per stage: each RK4 stage emits
+ *   dN = C_ph (w / mu) Phi(1; chi)   photons (the LCFA number over all
+ *                                     photon energies, Sec. 4),
+ *   dE = -w A                         in photon energy (the drift),
+ * with the stage weights w of the phase quadrature.  out[6] = {total number,
+ * rms theta_x and theta_y weighted by number [mrad], emitted energy, rms
+ * theta_x and theta_y weighted by energy [mrad]}. */
+int qso_photon_angles(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+                      double *out) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples || !out) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    photon_table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int64_t total = i_end - i_begin;
+    const double c_ph = kAlpha * d.aS / (2.0 * std::sqrt(3.0) * kPi);
+    enum { N, NX, NY, E, EX, EY, NS };
+    std::vector<std::vector<KSum>> S(nthreads, std::vector<KSum>(NS));
+    std::vector<int> bad(nthreads, 0);
+    Params<double> P = params<double>(p);
+    finish_params(p, P);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        std::vector<KSum> &acc = S[t];
+        double thx = 0.0, thy = 0.0;
+        auto visit = [&](double w, const double &mu, const double &a, const Rhs<double> &k) {
+            const double chi = 2.0 * mu * std::fabs(a) / d.aS;
+            if (!(chi > 0.0)) return;
+            const double dN = c_ph * w / mu * PhotonRow(chi).total();
+            const double dE = -w * k.A;
+            const double tx = thx + a / mu, cone = 1.0 / (mu * mu);
+            const double x2 = tx * tx + cone, y2 = thy * thy + cone;
+            acc[N].add(dN);
+            acc[NX].add(dN * x2);
+            acc[NY].add(dN * y2);
+            acc[E].add(dE);
+            acc[EX].add(dE * x2);
+            acc[EY].add(dE * y2);
+        };
+        for (int64_t i = b; i < e; ++i) {
+            const SampleIn<double> s = make_sample<double>(p, P, i);
+            thx = s.thx;
+            thy = s.thy;
+            const SampleOut<double> o = run_sample<double>(p, d, P, i, visit);
+            if (!std::isfinite(o.mu) || !std::isfinite(o.sig2)) bad[t] = 1;
+        }
+    }
+    for (int t = 1; t < nthreads; ++t)
+        for (int m = 0; m < NS; ++m) {
+            S[0][m].add(S[t][m].s);
+            S[0][m].add(S[t][m].c);
+        }
+    for (int t = 0; t < nthreads; ++t) if (bad[t]) return -2;
+    const double n = S[0][N].value(), en = S[0][E].value();
+    out[0] = n;
+    out[1] = n > 0.0 ? 1e3 * std::sqrt(S[0][NX].value() / n) : 0.0;
+    out[2] = n > 0.0 ? 1e3 * std::sqrt(S[0][NY].value() / n) : 0.0;
+    out[3] = en;
+    out[4] = en > 0.0 ? 1e3 * std::sqrt(S[0][EX].value() / en) : 0.0;
+    out[5] = en > 0.0 ? 1e3 * std::sqrt(S[0][EY].value() / en) : 0.0;
+    return 0;
+}
+
 /* ---- derivatives ---------------------------------------------------------- */
 static Params<Dual> seeded_params(const qso_problem *p) {
     Params<Dual> P = params<Dual>(p);

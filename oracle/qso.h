@@ -148,6 +148,13 @@ int qso_factorised(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes, int
                    int64_t i_end, int nthreads, double *energy_hist, double *angle_hist,
                    double *a0eff_hist, double *moments, double *node_states,
                    double *node_weights);
+/* Photon angular moments (Sec. 5.1) over samples [i_begin, i_end): out[6] =
+ * {photon number, number-weighted rms theta_x, theta_y [mrad], emitted
+ * energy, energy-weighted rms theta_x, theta_y [mrad]}; per RK4 stage the
+ * emission angle is (theta_x + a/mu, theta_y) with a 1/mu cone per plane. */
+int qso_photon_angles(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+                      double *out);
+
 /* Records (QSO_S_N doubles) of samples idx[0 .. n_idx) as the reconstruction
  * deposits them: the interpolated final state and the sample's observables. */
 int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes,

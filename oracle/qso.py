@@ -100,6 +100,8 @@ def lib():
         L.qso_factorised_samples.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp]
         L.qso_factorised_samples.restype = ctypes.c_int
+        L.qso_photon_angles.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
+        L.qso_photon_angles.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -294,6 +296,21 @@ def photons(params, n_ph, ph_lo, ph_hi, i_begin=0, i_end=None, nthreads=0):
     if rc == -2:
         raise FloatingPointError("non-finite state")
     return h, e
+
+
+def photon_angles(params, i_begin=0, i_end=None, nthreads=0):
+    """[photon number, rms theta_x, rms theta_y (number-weighted, mrad),
+    emitted energy, rms theta_x, rms theta_y (energy-weighted, mrad)]."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    out = np.zeros(6)
+    p = problem(params)
+    rc = lib().qso_photon_angles(ctypes.byref(p), i_begin, i_end, nthreads, _dp(out))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return out
 
 
 def photon_cdf(xi, chi):

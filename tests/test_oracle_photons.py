@@ -126,3 +126,61 @@ def test_no_field_no_photons(oracle):
     p = _photon_case("quantum", "local", a0=0.0)
     h, e = oracle.photons(p, 32, 0.0, 3000.0)
     assert np.all(h == 0.0) and e[0] == 0.0 and e[1] == 0.0
+
+
+# ---- Sec. 5.1: photon angular moments ---------------------------------------
+
+def test_photon_angles_plane_wave_closed_form(oracle):
+    """Classical plane wave, one energy: 1/mu(psi) = 1/gamma0 + K Int a^2 (the
+    exact Landau-Lifshitz solution), photon number rate C_ph (5 pi / 2) (2|a|/a_S)
+    (1 - 8 chi/(5 sqrt3)) (the small-chi number, chi ~ 2e-3 here), energy rate
+    K a^2 mu^2; angles (a/mu, 0) with a 1/mu cone.  Fine Simpson quadrature in
+    psi against the oracle's RK4 stage sums."""
+    import math
+    from scipy import integrate
+    p = workloads.scaled(workloads.plane_wave_1d(), n_samples=4, n_steps=2048, sigma_gamma=0.0,
+                         a0=2.0, gamma0=200.0)
+    d = oracle.derived(p)
+    aS, K, psim = d["aS"], d["K"], d["psi_max"]
+    otau = d["omega0"] * p["tau_fs"]
+    c_ph = 7.2973525693e-3 * aS / (2 * math.sqrt(3) * math.pi)
+    psi = np.linspace(-psim, psim, 2_000_001)
+    a = p["a0"] * np.exp(-2 * math.log(2) * (psi / otau) ** 2) * np.cos(psi)
+    mu = 1.0 / (1.0 / p["gamma0"] + K * integrate.cumulative_trapezoid(a * a, psi, initial=0))
+    chi = 2 * mu * np.abs(a) / aS
+    dN = c_ph / mu * (5 * math.pi / 2) * chi * (1 - 8 * chi / (5 * math.sqrt(3)))
+    dE = K * a * a * mu * mu
+    x2, y2 = (a / mu) ** 2 + 1 / mu ** 2, 1 / mu ** 2
+    N, E = integrate.simpson(dN, x=psi), integrate.simpson(dE, x=psi)
+    ref = np.array([N, 1e3 * math.sqrt(integrate.simpson(dN * x2, x=psi) / N),
+                    1e3 * math.sqrt(integrate.simpson(dN * y2, x=psi) / N), E,
+                    1e3 * math.sqrt(integrate.simpson(dE * x2, x=psi) / E),
+                    1e3 * math.sqrt(integrate.simpson(dE * y2, x=psi) / E)])
+    o = oracle.photon_angles(p) / np.array([4, 1, 1, 4, 1, 1])  # per electron
+    rel = np.abs(o - ref) / ref
+    assert np.all(rel <= [3e-5, 1e-5, 1e-9, 1e-9, 1e-9, 1e-9]), rel
+    # energy weighting: the emitted energy is the electron's loss
+    r = oracle.sample(p, 0)
+    assert abs(o[3] - (p["gamma0"] - r[oracle.S_MU])) <= 1e-10 * o[3]
+
+
+def test_photon_angles_add_the_beam_direction(oracle):
+    """Plane wave, one energy, 1 mrad divergence: every sample runs the same
+    trajectory, so the y second moment is the samples' own mean theta_y^2 plus
+    the cone of the divergence-free run exactly, and in x also up to the
+    cross term 2 <theta_x> <a/mu>."""
+    import math
+    base = workloads.scaled(workloads.plane_wave_1d(), n_samples=400, n_steps=512,
+                            sigma_gamma=0.0, a0=5.0, gamma0=1000.0)
+    o0 = oracle.photon_angles(base)
+    p = dict(base, div_mrad=1.0)
+    o = oracle.photon_angles(p)
+    rec = oracle.samples(dict(p, n_steps=1), range(p["n_samples"]))
+    tx, ty = rec[:, oracle.S_THX], rec[:, oracle.S_THY]   # mrad
+    for w in (0, 3):   # number-weighted, energy-weighted
+        assert abs(o[w] - o0[w]) <= 1e-12 * o0[w]
+        assert abs(o[w + 2] ** 2 - (np.mean(ty ** 2) + o0[w + 2] ** 2)) <= 1e-9 * o[w + 2] ** 2
+        cross = 2 * abs(np.mean(tx)) * o0[w + 1]
+        assert abs(o[w + 1] ** 2 - (np.mean(tx ** 2) + o0[w + 1] ** 2)) <= cross + 1e-9
+        assert cross < 0.1 * o[w + 1] ** 2  # the check is not empty
+    assert math.isfinite(o[1]) and o[1] > o0[1]
