@@ -203,7 +203,7 @@ def quantum_batch_leg(ctx, workloads, torch, steps):
         grads = ctx.backward_batched(shots, ws, check=False, tape=tape)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        phot = ctx.photons_batched(shots, check=False)
+        phot = ctx.photons_batched(shots, check=False, angles=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
         for k, name in enumerate(("spectra", "gradients", "photons")):
@@ -227,7 +227,7 @@ def quantum_batch_leg(ctx, workloads, torch, steps):
     return {"workload": "256 shots: gamma0 N(2e4, 600^2), a0 U[50,150], W0 2um, no offsets, "
                         "2^18 samples x 2048 steps, quantum with FP64 steps where chi > 0.1, "
                         "local amplitude; electron spectra, per-shot gradients (tape), "
-                        "256-bin photon spectra",
+                        "256-bin photon spectra with photon angular moments",
             "n_shots": len(shots), "n_samples": total, "n_steps": N, "steps": steps,
             "ms_per_step": 1e3 * dt,
             "ms_parts": {k: 1e3 * v / steps for k, v in parts.items()},

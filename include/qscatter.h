@@ -312,6 +312,15 @@ typedef struct qs_photon_outputs {
     double *energy;      /* [2]: emitted photon energy, and the electrons'
                             energy loss sum(gamma0_i - mu_f), m c^2 units      */
     int32_t *status;     /* [1] qs_status of the device-side checks, or NULL   */
+    double *angles;      /* optional [6] (NULL: not computed), Sec. 5.1: the
+                            emitted photon number (all energies), its rms
+                            angles theta_x, theta_y [mrad]; the emitted photon
+                            energy, its rms theta_x, theta_y [mrad].  A stage
+                            emits along (theta_x + a/mu, theta_y), the sample's
+                            direction plus the quiver angle in the polarisation
+                            plane, within a 1/mu cone per plane; each stage's
+                            photons weigh by their number (the paper's
+                            N_gamma/N_e weighting) or by their energy        */
 } qs_photon_outputs;
 
 /* The approximate photon spectrum of Sec. 4: along each sample's trajectory

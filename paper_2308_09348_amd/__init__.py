@@ -338,13 +338,16 @@ class Context:
                 raise QScatterError(bad, "device status of a shot")
         return grads
 
-    def photons(self, params, stream=None, check=True):
+    def photons(self, params, stream=None, check=True, angles=False):
         """Photon spectrum of one shot (Sec. 4): returns {"photon_hist": [n_ph + 2]
         expected photon number per bin, "energy": [emitted photon energy,
-        electron energy loss], "status"}; bins from photon_bins(params)."""
-        return self.photons_batched([params], stream=stream, check=check, single=True)[0]
+        electron energy loss], "status"}; bins from photon_bins(params).  With
+        ``angles`` also "angles" [6]: photon number and its rms theta_x,
+        theta_y (mrad), photon energy and its rms theta_x, theta_y (Sec. 5.1)."""
+        return self.photons_batched([params], stream=stream, check=check, single=True,
+                                    angles=angles)[0]
 
-    def photons_batched(self, shots, stream=None, check=True, single=False):
+    def photons_batched(self, shots, stream=None, check=True, single=False, angles=False):
         """Photon spectra of many shots in one launch (shot k uses RNG counter
         word shots[0]["shot"] + k)."""
         torch = _torch()
@@ -366,10 +369,13 @@ class Context:
             o = {"photon_hist": torch.empty(pbins[k].n_ph + 2, dtype=torch.float64, device=dev),
                  "energy": torch.empty(2, dtype=torch.float64, device=dev),
                  "status": torch.empty(1, dtype=torch.int32, device=dev)}
+            if angles:
+                o["angles"] = torch.empty(6, dtype=torch.float64, device=dev)
             outs.append(o)
             pouts[k] = _lib.PhotonOutputs(photon_hist=o["photon_hist"].data_ptr(),
                                           energy=o["energy"].data_ptr(),
-                                          status=o["status"].data_ptr())
+                                          status=o["status"].data_ptr(),
+                                          angles=o["angles"].data_ptr() if angles else None)
         if single:
             st = _lib.lib().qs_photons(self._ptr, ctypes.byref(lasers[0]), ctypes.byref(beams[0]),
                                        ctypes.byref(nu), ctypes.byref(pbins[0]),

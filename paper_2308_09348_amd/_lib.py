@@ -80,7 +80,7 @@ class PhotonBins(ctypes.Structure):
 
 class PhotonOutputs(ctypes.Structure):
     _fields_ = [("photon_hist", ctypes.c_void_p), ("energy", ctypes.c_void_p),
-                ("status", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("angles", ctypes.c_void_p)]
 
 
 class GradOutputs(ctypes.Structure):

@@ -852,6 +852,7 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         p.hist = PO[k].photon_hist;
         p.energy = PO[k].energy;
         p.status = PO[k].status;
+        p.angles = PO[k].angles;
         p.pitem0 = pitem;
         p.grid_off = (int64_t)k * qs::kPhNodes;
         pitem += (n_samples[k] + qs::kPhotTile - 1) / qs::kPhotTile;

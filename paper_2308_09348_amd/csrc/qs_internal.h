@@ -119,7 +119,10 @@ constexpr double kPhYMax = 80.0;
 // r_lo .. r_lo + nu - 1) x kPhNV columns (ln mu), weights in fixed point.
 constexpr int kPhNU = 64, kPhNV = 64, kPhNodes = kPhNU * kPhNV;
 constexpr int kPhotTile = 2048;          // one photon work item = kPhotTile samples
-constexpr int kPhotPartials = 3;         // photon energy, electron loss, soft weight
+// photon energy, electron loss, soft weight; then the Sec. 5.1 angular sums:
+// number, number x theta_x^2, number x theta_y^2, energy, energy x theta_x^2,
+// energy x theta_y^2
+constexpr int kPhotPartials = 9;
 constexpr double kPhScale = 16777216.0;  // 2^24: unit of the grid weights
 
 struct ShotPhot {
@@ -129,6 +132,7 @@ struct ShotPhot {
     double *hist;                // [n_ph + 2]
     double *energy;              // [2]: photon energy, electron energy loss
     int32_t *status;             // optional
+    double *angles;              // optional [6]: Sec. 5.1 photon angular moments
     int64_t pitem0;              // first photon work item
     int64_t grid_off;            // its grid in the accumulators (kPhNodes words)
 };

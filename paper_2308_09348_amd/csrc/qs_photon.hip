@@ -156,6 +156,49 @@ __global__ void ph_cdf_kernel(const double *phtab, int64_t n, const double *chi,
 struct PhotAcc {
     double e_ph, soft;
     int flags;
+    // Sec. 5.1 angular sums (in units that the finalize kernel scales):
+    // sum c |a| Phi(1; chi)/chi (photon number), the same times theta_x^2 and
+    // theta_y^2; sum c (-A) (energy), the same times theta_x^2, theta_y^2
+    double nn, nx, ny, ee, ex, ey;
+};
+
+// Phi(1; chi) / chi, the LCFA photon number over all energies per unit chi,
+// from the number CDF table's last node on each row (z_max Phi/(chi z) at
+// y = kPhYMax, beyond which the spectrum is below 1e-34), cubic in ln chi; below
+// the first row the small-chi series (5 pi / 2)(1 - 8 chi / (5 sqrt3)).
+__device__ __forceinline__ float ph_total(const float *tot, float chi) {
+    const float s = (__logf(chi) - (float)kPhU0) * (float)(1.0 / kPhDu);
+    if (!(s > 0.0f)) return 7.85398163397448310f * fmaf(-0.92376043070340122f, chi, 1.0f);
+    const int i = min(max((int)s - 1, 0), kPhRows - 4);
+    const float t = s - (float)i;
+    const float w0 = -(t - 1.0f) * (t - 2.0f) * (t - 3.0f) * (1.0f / 6.0f);
+    const float w1 = t * (t - 2.0f) * (t - 3.0f) * 0.5f;
+    const float w2 = -t * (t - 1.0f) * (t - 3.0f) * 0.5f;
+    const float w3 = t * (t - 1.0f) * (t - 2.0f) * (1.0f / 6.0f);
+    return fmaf(w0, tot[i], fmaf(w1, tot[i + 1], fmaf(w2, tot[i + 2], w3 * tot[i + 3])));
+}
+
+// One stage's share of the angular sums: weight c (the stage's quadrature
+// weight over h), amplitude a, mean energy mu, drift A; the emission angle is
+// theta_x + a/mu in x and theta_y in y, plus a 1/mu cone in each plane.
+template <class T>
+struct AngStep {
+    T n, nx, ny, e, ex, ey;
+    __device__ __forceinline__ void add(T c, T a, T mu, T A, T thx, T thy, float tas,
+                                        const float *tot) {
+        const T aa = fabs(a);
+        const T imu = T(1) / mu;
+        const T tx = fma(a, imu, thx), cone = imu * imu;
+        const T x2 = fma(tx, tx, cone), y2 = fma(thy, thy, cone);
+        const T dn = aa > T(0) ? c * aa * (T)ph_total(tot, tas * (float)mu * (float)aa) : T(0);
+        const T de = -c * A;
+        n += dn;
+        nx = fma(dn, x2, nx);
+        ny = fma(dn, y2, ny);
+        e += de;
+        ex = fma(de, x2, ex);
+        ey = fma(de, y2, ey);
+    }
 };
 
 __device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi,
@@ -262,7 +305,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                                               const float *__restrict__ env32,
                                               const double *__restrict__ env64,
                                               const float *tab32, unsigned long long *grid,
-                                              PhotAcc &acc, double &loss) {
+                                              const float *tot, PhotAcc &acc, double &loss) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
     const T *env;
     FwdRad<T> rad;
@@ -325,6 +368,8 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
             ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)mu), ph_ln(tas * aa),
                        tas * (float)mu * aa, pp, grid, acc);
     }
+    const bool angles = pp.angles != nullptr;
+    const T tthx = (T)thx, tthy = (T)thy;
     T m4_prev = T(0);  // the previous step's stage-4 state, deposited with this step's stage 1
     for (int j = 0; j < N; ++j) {
         const T psi = fma((T)j, h, psi0);
@@ -353,6 +398,19 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
         const T m4 = fma(h, k3m, mu);
         photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, ph, rad, k4m, k4s, A4, chi_hi);
         acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
+        if (angles) {
+            AngStep<T> st{T(0), T(0), T(0), T(0), T(0), T(0)};
+            st.add(c16, a1, mu, A1, tthx, tthy, tas, tot);
+            st.add(c13, ah, m2, A2, tthx, tthy, tas, tot);
+            st.add(c13, ah, m3, A3, tthx, tthy, tas, tot);
+            st.add(c16, a4, m4, A4, tthx, tthy, tas, tot);
+            acc.nn += st.n;
+            acc.nx += st.nx;
+            acc.ny += st.ny;
+            acc.ee += st.e;
+            acc.ex += st.ex;
+            acc.ey += st.ey;
+        }
         {  // stages 2 and 3 (same amplitude)
             const float aa = fabsf((float)ah);
             if (aa > 0.0f) {
@@ -408,14 +466,17 @@ __global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     __shared__ unsigned long long grid[kPhNodes];
+    __shared__ float tot[kPhRows];  // Phi(1; chi) / chi on the table rows
     __shared__ int64_t slot;
     __shared__ double red[kDepBlock / 64][kPhotPartials];
+    for (int r = threadIdx.x; r < kPhRows; r += blockDim.x)
+        tot[r] = (float)(cbrt(kPhYMax) * P.phtab[(size_t)r * (kPhNZ + 1) + kPhNZ]);
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
         for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
-        __syncthreads();
     }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
@@ -426,15 +487,16 @@ __global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
         const int nodes = pp.nu * pp.nv;
         for (int k = threadIdx.x; k < nodes; k += blockDim.x) grid[k] = 0ull;
         __syncthreads();
-        PhotAcc acc{0.0, 0.0, 0};
+        PhotAcc acc{0.0, 0.0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double loss = 0.0;
         const int64_t i0 = (item - pp.pitem0) * kPhotTile;
         const int64_t i1 = i0 + kPhotTile < sp.n_samples ? i0 + kPhotTile : sp.n_samples;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-            photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, acc,
-                                                loss);
+            photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, tot,
+                                                acc, loss);
         if (acc.flags) atomicOr(&P.flags[s], acc.flags);
-        const double v[kPhotPartials] = {acc.e_ph, loss, acc.soft};
+        const double v[kPhotPartials] = {acc.e_ph, loss, acc.soft, acc.nn, acc.nx,
+                                         acc.ny, acc.ee, acc.ex, acc.ey};
 #pragma unroll
         for (int m = 0; m < kPhotPartials; ++m) {
             const double w = wave_sum(v[m]);
@@ -554,6 +616,17 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
     if (tid == 0) {
         pp.energy[0] = sums[0];
         pp.energy[1] = sums[1];
+        if (pp.angles) {
+            // number: C_ph (2 / a_S) h sum c |a| Phi(1; chi)/chi; energy: h sum c (-A)
+            double *o = pp.angles;
+            const double nn = sums[3], ee = sums[6];
+            o[0] = c_ph * P.two_over_aS * P.h * nn;
+            o[1] = nn > 0.0 ? 1e3 * sqrt(sums[4] / nn) : 0.0;
+            o[2] = nn > 0.0 ? 1e3 * sqrt(sums[5] / nn) : 0.0;
+            o[3] = P.h * ee;
+            o[4] = ee > 0.0 ? 1e3 * sqrt(sums[7] / ee) : 0.0;
+            o[5] = ee > 0.0 ? 1e3 * sqrt(sums[8] / ee) : 0.0;
+        }
         if (pp.status) {
             const int fl = P.flags[s];
             *pp.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);

@@ -133,3 +133,31 @@ def test_batched_equals_single_and_repeats(gpu):
         for key in ("photon_hist", "energy", "status"):
             assert np.array_equal(batch[k][key], single[key]), (k, key)
             assert np.array_equal(batch[k][key], again[k][key]), (k, key)
+
+
+# ---- Sec. 5.1: photon angular moments -----------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp32", (2e-5, 2e-5)), ("fp64", (2e-6, 1e-9))])
+@pytest.mark.parametrize("name", list(CASES))
+def test_photon_angles_vs_oracle(gpu, oracle, name, precision, tol):
+    """Number-weighted moments: the device tabulates Phi(1; chi)/chi on rows
+    0.2 apart in ln chi (cubic, < 1e-6) against the oracle's 1/32; energy-
+    weighted moments: the same stage sums on both sides."""
+    p = _case(name, precision, div_mrad=1.0)
+    g = gpu.photons(p, angles=True)["angles"].cpu().numpy()
+    o = oracle.photon_angles(p)
+    tn, te = tol
+    assert np.all(np.abs(g[:3] - o[:3]) <= tn * np.abs(o[:3])), (name, g, o)
+    assert np.all(np.abs(g[3:] - o[3:]) <= max(te, 2e-5 if precision == "fp32" else 0) *
+                  np.abs(o[3:])), (name, g, o)
+
+
+def test_photon_angles_batched_and_empty(gpu):
+    p = _case("quantum-local", div_mrad=1.0)
+    single = gpu.photons(p, angles=True)["angles"].cpu().numpy()
+    batch = gpu.photons_batched([p, dict(p, a0=0.0)], angles=True)
+    assert np.array_equal(batch[0]["angles"].cpu().numpy(), single)
+    assert not batch[1]["angles"].cpu().numpy().any()
+    # asking for the moments leaves the spectrum unchanged
+    h = gpu.photons(p)["photon_hist"].cpu().numpy()
+    assert np.array_equal(h, gpu.photons(p, angles=True)["photon_hist"].cpu().numpy())
