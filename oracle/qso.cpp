@@ -15,6 +15,7 @@
 #include "qso.h"
 
 #include <cmath>
+#include <functional>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -137,6 +138,11 @@ int validate(const qso_problem *p) {
     if ((p->transverse != QSO_PROFILE_GAUSS && p->transverse != QSO_PROFILE_FLAT) ||
         (p->longitudinal != QSO_PROFILE_GAUSS && p->longitudinal != QSO_PROFILE_FLAT))
         return -1;
+    if (p->mode != QSO_MODE_GAUSS && p->mode != QSO_MODE_HG && p->mode != QSO_MODE_LG) return -1;
+    if (p->mode != QSO_MODE_GAUSS &&
+        (p->mode_m < 0 || p->mode_m > 8 || std::abs(p->mode_n) > 8 ||
+         (p->mode == QSO_MODE_HG && p->mode_n < 0)))
+        return -1;
     if (p->rr_model != QSO_RR_CLASSICAL && p->rr_model != QSO_RR_QUANTUM) return -1;
     if (p->amp_mode != QSO_AMP_A0EFF && p->amp_mode != QSO_AMP_LOCAL) return -1;
     if (p->deposit < QSO_DEP_POINT || p->deposit > QSO_DEP_GAUSS) return -1;
@@ -190,13 +196,125 @@ double envelope_carrier(const qso_problem *p, const Derived &d, double psi) {
 /* eq. a0eff: the focused Gaussian spatial factor a/a0 at (rho, z); the laser
  * phase and wavefront curvature are neglected as in Sec. 2.  w0 = 0 selects a
  * plane wave. */
+/* ---- transverse laser modes (conclusions) ------------------------------- */
+/* Hermite and generalised Laguerre polynomials by their three-term
+ * recurrences. */
 template <class T>
-T spatial(const T &w0, const T &zR, const T &x, const T &y, const T &z) {
+T hermite_poly(int m, const T &s) {
+    T h0(1.0), h1 = 2.0 * s;
+    if (m == 0) return h0;
+    for (int k = 1; k < m; ++k) {
+        const T h2 = 2.0 * s * h1 - (2.0 * k) * h0;
+        h0 = h1;
+        h1 = h2;
+    }
+    return h1;
+}
+
+template <class T>
+T laguerre_poly(int p, int l, const T &t) {
+    if (p < 0) return T(0.0);
+    T L0(1.0), L1 = (1.0 + l) - t;
+    if (p == 0) return L0;
+    for (int k = 1; k < p; ++k) {
+        const T L2 = ((2.0 * k + 1.0 + l - t) * L1 - (double)(k + l) * L0) / (double)(k + 1);
+        L0 = L1;
+        L1 = L2;
+    }
+    return L1;
+}
+
+/* Focal-plane peak of a mode's amplitude.  HG m: the extrema of |H_m(s)|
+ * e^(-s^2/2) are where s H_m(s) = H_(m+1)(s) (the derivative with H_m' =
+ * 2m H_(m-1)); LG p, l: those of t^(l/2) |L_p^l(t)| e^(-t/2) where
+ * (l - t) L_p^l(t) = 2t L_(p-1)^(l+1)(t) (with dL_p^l/dt = -L_(p-1)^(l+1)).
+ * Sign changes on a fine grid, bisection, the largest value. */
+double extremum_max(const std::function<double(double)> &cond,
+                    const std::function<double(double)> &val, double hi) {
+    double best = std::fmax(val(0.0), val(hi));
+    const int n = 20000;
+    double a = 0.0, fa = cond(0.0);
+    for (int k = 1; k <= n; ++k) {
+        const double b = hi * k / n, fb = cond(b);
+        if ((fa < 0.0) != (fb < 0.0)) {
+            double lo = a, up = b, flo = fa;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (lo + up), fm = cond(mid);
+                if ((fm < 0.0) == (flo < 0.0)) lo = mid, flo = fm;
+                else up = mid;
+            }
+            best = std::fmax(best, val(0.5 * (lo + up)));
+        }
+        a = b;
+        fa = fb;
+    }
+    return best;
+}
+
+double mode_peak(int mode, int m, int n) {
+    if (mode == QSO_MODE_HG) {
+        auto one = [](int k) {
+            return extremum_max(
+                [k](double s) { return s * hermite_poly<double>(k, s) - hermite_poly<double>(k + 1, s); },
+                [k](double s) { return std::fabs(hermite_poly<double>(k, s)) * std::exp(-0.5 * s * s); },
+                std::sqrt(2.0 * k + 1.0) + 5.0);
+        };
+        return one(m) * one(n);
+    }
+    if (mode == QSO_MODE_LG) {
+        const int l = std::abs(n), p = m;
+        return extremum_max(
+            [p, l](double t) {
+                return (l - t) * laguerre_poly<double>(p, l, t) -
+                       2.0 * t * laguerre_poly<double>(p - 1, l + 1, t);
+            },
+            [p, l](double t) {
+                return std::pow(t, 0.5 * l) * std::fabs(laguerre_poly<double>(p, l, t)) *
+                       std::exp(-0.5 * t);
+            },
+            4.0 * p + 2.0 * l + 40.0);
+    }
+    return 1.0;
+}
+
+double mode_inv_peak(const qso_problem *p) {
+    thread_local int key[3] = {-1, -1, -1};
+    thread_local double v = 1.0;
+    if (key[0] != p->mode || key[1] != p->mode_m || key[2] != p->mode_n) {
+        v = 1.0 / mode_peak(p->mode, p->mode_m, p->mode_n);
+        key[0] = p->mode;
+        key[1] = p->mode_m;
+        key[2] = p->mode_n;
+    }
+    return v;
+}
+
+/* eq. a0eff: the focused Gaussian spatial factor a/a0 at (rho, z); a higher
+ * mode (the conclusions' Laguerre- or Hermite-Gauss extension) replaces the
+ * transverse profile, amplitude only, scaled to a focal-plane peak of 1:
+ *   HG: |H_m(sqrt2 x/W) H_n(sqrt2 y/W)| e^(-rho^2/W^2) (W0/W) / C,
+ *   LG: (2 rho^2/W^2)^(|l|/2) |L_p^|l|(2 rho^2/W^2)| e^(-rho^2/W^2) (W0/W) / C. */
+template <class T>
+T spatial(const qso_problem *p, const T &w0, const T &zR, const T &x, const T &y, const T &z) {
     if (val(w0) == 0.0) return T(1.0);
     const T zz = z / zR;
     const T q = 1.0 + zz * zz;
     const T r2 = (x * x + y * y) / (w0 * w0);
-    return exp(-r2 / q) / sqrt(q);
+    const T g = exp(-r2 / q) / sqrt(q);
+    if (p->mode == QSO_MODE_HG) {
+        const T sc = sqrt(2.0 / q) / w0;
+        return fabs(hermite_poly<T>(p->mode_m, x * sc) * hermite_poly<T>(p->mode_n, y * sc)) * g *
+               mode_inv_peak(p);
+    }
+    if (p->mode == QSO_MODE_LG) {
+        const int l = std::abs(p->mode_n);
+        const T t = 2.0 * r2 / q;
+        T tp(1.0);
+        for (int k = 0; k < l / 2; ++k) tp = tp * t;
+        if (l & 1) tp = tp * sqrt(t);
+        return tp * fabs(laguerre_poly<T>(p->mode_m, l, t)) * g * mode_inv_peak(p);
+    }
+    return g;
 }
 
 /* ---- radiation functions g(chi), h(chi) -------------------------------- */
@@ -455,7 +573,7 @@ Geometry<T> geometry(const qso_problem *p, const Params<T> &P, const SampleIn<T>
     gmt.zstar = 0.5 * (s.z + kC_um_per_fs * P.delay);
     const T xc = s.x + s.thx * 0.5 * s.z;
     const T yc = s.y + s.thy * 0.5 * s.z;
-    gmt.S0 = spatial<T>(P.w0, P.zR, xc, yc, gmt.zstar);
+    gmt.S0 = spatial<T>(p, P.w0, P.zR, xc, yc, gmt.zstar);
     (void)p;
     return gmt;
 }
@@ -469,8 +587,8 @@ T amplitude(const qso_problem *p, const Derived &d, const Params<T> &P, const Sa
         S = gmt.S0;
     } else {
         const double l = psi * p->lambda_um / (4.0 * kPi);
-        S = spatial<T>(P.w0, P.zR, s.x + s.thx * (0.5 * s.z + l), s.y + s.thy * (0.5 * s.z + l),
-                       gmt.zstar - l);
+        S = spatial<T>(p, P.w0, P.zR, s.x + s.thx * (0.5 * s.z + l),
+                       s.y + s.thy * (0.5 * s.z + l), gmt.zstar - l);
     }
     return P.a0 * S * envelope_carrier(p, d, psi);
 }

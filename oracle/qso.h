@@ -35,6 +35,7 @@ enum { QSO_RR_CLASSICAL = 0, QSO_RR_QUANTUM = 1 };
 enum { QSO_AMP_A0EFF = 0, QSO_AMP_LOCAL = 1 };
 enum { QSO_DEP_POINT = 0, QSO_DEP_CIC = 1, QSO_DEP_GAUSS = 2 };
 enum { QSO_PROFILE_GAUSS = 0, QSO_PROFILE_FLAT = 1 };
+enum { QSO_MODE_GAUSS = 0, QSO_MODE_HG = 1, QSO_MODE_LG = 2 };
 
 /* One scattering problem.  Lengths in micrometres, times in femtoseconds,
  * angles in milliradians, energies in units of m c^2. */
@@ -71,7 +72,9 @@ typedef struct qso_problem {
                              QSO_PROFILE_FLAT: uniform disk of radius sigma_r_um */
     int32_t longitudinal; /* QSO_PROFILE_GAUSS: rms sigma_z_um;
                              QSO_PROFILE_FLAT: uniform over a length sigma_z_um */
-    int32_t pad_;
+    int32_t mode;         /* QSO_MODE_GAUSS, QSO_MODE_HG (orders mode_m in x,
+                             mode_n in y), QSO_MODE_LG (p = mode_m, l = mode_n) */
+    int32_t mode_m, mode_n;
     double e_lo, e_hi;          /* energy window, units of m c^2          */
     double th_lo_mrad, th_hi_mrad;
 } qso_problem;

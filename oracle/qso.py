@@ -18,6 +18,7 @@ RR_MODEL = {"classical": 0, "quantum": 1}
 AMP_MODE = {"a0eff": 0, "local": 1}
 DEPOSIT = {"point": 0, "cic": 1, "gauss": 2}
 PROFILE = {"gauss": 0, "flat": 1}
+MODE = {"gauss": 0, "hg": 1, "lg": 2}
 
 # per-sample record layout (qso.h)
 S_MU, S_SIG2, S_THX, S_THY, S_SIGTH, S_AEFF, S_CHIMAX, S_GAMMA0, S_X, S_Y, S_Z, S_N = range(12)
@@ -44,7 +45,7 @@ class Problem(ctypes.Structure):
         ("amp_mode", ctypes.c_int32), ("deposit", ctypes.c_int32),
         ("n_e", ctypes.c_int32), ("n_th", ctypes.c_int32), ("n_a", ctypes.c_int32),
         ("transverse", ctypes.c_int32), ("longitudinal", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("mode", ctypes.c_int32), ("mode_m", ctypes.c_int32), ("mode_n", ctypes.c_int32),
         ("e_lo", ctypes.c_double), ("e_hi", ctypes.c_double),
         ("th_lo_mrad", ctypes.c_double), ("th_hi_mrad", ctypes.c_double),
     ]
@@ -119,6 +120,13 @@ def problem(params):
         if name in ("transverse", "longitudinal"):
             v = params.get(name, "gauss")
             setattr(p, name, PROFILE[v] if isinstance(v, str) else v)
+            continue
+        if name == "mode":
+            v = params.get("mode", "gauss")
+            setattr(p, name, MODE[v] if isinstance(v, str) else v)
+            continue
+        if name in ("mode_m", "mode_n"):
+            setattr(p, name, int(params.get(name, 0)))
             continue
         v = params[name]
         if name == "envelope":

@@ -55,7 +55,7 @@ def test_abi_version_and_strerror():
 def test_struct_layouts_match_header():
     from paper_2308_09348_amd import _lib
     # sizes follow from the header's field lists (8-byte aligned doubles)
-    assert ctypes.sizeof(_lib.Laser) == 8 * 4 + 4 * 2 + 8 * 3
+    assert ctypes.sizeof(_lib.Laser) == 8 * 4 + 4 * 2 + 8 * 3 + 4 * 2
     assert ctypes.sizeof(_lib.Beam) == 8 * 5 + 4 * 2
     assert ctypes.sizeof(_lib.Numerics) == 8 + 4 * 2 + 8 * 2 + 4 * 4 + 8 * 3
     assert ctypes.sizeof(_lib.Bins) == 4 * 4 + 8 * 4
