@@ -52,6 +52,16 @@ enum { QS_AMP_A0EFF = 0, QS_AMP_LOCAL = 1 };
 enum { QS_DEP_POINT = 0, QS_DEP_CIC = 1, QS_DEP_GAUSS = 2 };
 enum { QS_PREC_FP32 = 0, QS_PREC_FP64 = 1 };
 enum { QS_PROFILE_GAUSS = 0, QS_PROFILE_FLAT = 1 };
+/* Transverse laser modes, amplitude only (the wave's phase, Gouy phase and
+ * curvature neglected as for eq. a0eff), scaled to a peak of 1 in the focal
+ * plane so that a0 stays the peak amplitude; with u = x/W, v = y/W,
+ * W = W0 sqrt(1 + z^2/zR^2):
+ *   GAUSS: (W0/W) exp(-(u^2 + v^2));
+ *   HG:    (W0/W) |H_m(sqrt2 u) H_n(sqrt2 v)| exp(-(u^2 + v^2)) / C_mn;
+ *   LG:    (W0/W) (2(u^2 + v^2))^(|l|/2) |L_p^|l|(2(u^2 + v^2))|
+ *          exp(-(u^2 + v^2)) / C_pl,
+ * H the physicists' Hermite and L the generalised Laguerre polynomials. */
+enum { QS_MODE_GAUSS = 0, QS_MODE_HG = 1, QS_MODE_LG = 2 };
 
 /* Laser (Sec. 2 eq. a0eff; misalignment of Table 1).  Lengths in um,
  * times in fs.  The laser propagates along +z with its peak at z = c t and
@@ -62,11 +72,14 @@ typedef struct qs_laser {
     double w0_um;      /* spot size W0 at focus, >= 0; 0 selects a plane wave  */
     double tau_fs;     /* GAUSS: intensity FWHM; SIN2: rise time; > 0          */
     int32_t envelope;  /* QS_ENV_*                                             */
-    int32_t reserved0;
+    int32_t mode;      /* transverse mode, QS_MODE_* (conclusions: Laguerre- or
+                          Hermite-Gauss in place of the Gaussian focus)        */
     double x_off_um;   /* beam centroid offset from the laser axis (x)         */
     double y_off_um;   /* beam centroid offset from the laser axis (y)         */
     double delay_fs;   /* collision delay: the centroid meets the peak at
                           z = c delay / 2                                      */
+    int32_t mode_m;    /* HG: order in x, 0..8; LG: radial index p, 0..8       */
+    int32_t mode_n;    /* HG: order in y, 0..8; LG: azimuthal index l, -8..8   */
 } qs_laser;
 
 /* Electron beam (abstract: broadband beams, divergence).  The beam moves

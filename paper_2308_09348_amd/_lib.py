@@ -18,6 +18,7 @@ AMP_MODE = {"a0eff": 0, "local": 1}
 DEPOSIT = {"point": 0, "cic": 1, "gauss": 2}
 PRECISION = {"fp32": 0, "fp64": 1}
 PROFILE = {"gauss": 0, "flat": 1}
+MODE = {"gauss": 0, "hg": 1, "lg": 2}
 
 M_N = 16
 S_N = 11
@@ -29,9 +30,10 @@ S_N = 11
 class Laser(ctypes.Structure):
     _fields_ = [("a0", ctypes.c_double), ("lambda_um", ctypes.c_double),
                 ("w0_um", ctypes.c_double), ("tau_fs", ctypes.c_double),
-                ("envelope", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("envelope", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("x_off_um", ctypes.c_double), ("y_off_um", ctypes.c_double),
-                ("delay_fs", ctypes.c_double)]
+                ("delay_fs", ctypes.c_double), ("mode_m", ctypes.c_int32),
+                ("mode_n", ctypes.c_int32)]
 
 
 class Beam(ctypes.Structure):
@@ -209,8 +211,9 @@ def structs(params):
     """Plain parameter dictionary -> (Laser, Beam, Numerics, Bins)."""
     la = Laser(a0=params["a0"], lambda_um=params["lambda_um"], w0_um=params["w0_um"],
                tau_fs=params["tau_fs"], envelope=_enum(ENVELOPE, params["envelope"]),
-               reserved0=0, x_off_um=params["x_off_um"], y_off_um=params["y_off_um"],
-               delay_fs=params["delay_fs"])
+               mode=_enum(MODE, params.get("mode", "gauss")), x_off_um=params["x_off_um"],
+               y_off_um=params["y_off_um"], delay_fs=params["delay_fs"],
+               mode_m=int(params.get("mode_m", 0)), mode_n=int(params.get("mode_n", 0)))
     be = Beam(gamma0=params["gamma0"], sigma_gamma=params["sigma_gamma"],
               sigma_r_um=params["sigma_r_um"], sigma_z_um=params["sigma_z_um"],
               div_mrad=params["div_mrad"],

@@ -83,6 +83,68 @@ class DeviceGuard {
 
 bool fin(double v) { return std::isfinite(v); }
 
+// Peak over the focal plane of a transverse mode's amplitude (QS_MODE_*):
+// HG m, n: max_s |H_m(s)| e^(-s^2/2) times the same for n (separable, s =
+// sqrt2 x / W0); LG p, l: max_t t^(|l|/2) |L_p^|l|(t)| e^(-t/2), t = 2 rho^2 / W0^2.
+// A scan at 1/4096 of the lobe scale, then golden-section search on the
+// best bracket.
+double hermite_fn(int m, double s) {
+    double h0 = 1.0, h1 = 2.0 * s;
+    if (m == 0) return std::exp(-0.5 * s * s);
+    for (int k = 1; k < m; ++k) {
+        const double h2 = 2.0 * s * h1 - 2.0 * k * h0;
+        h0 = h1;
+        h1 = h2;
+    }
+    return std::fabs(h1) * std::exp(-0.5 * s * s);
+}
+
+double laguerre_fn(int p, int l, double t) {
+    double L0 = 1.0, L1 = 1.0 + l - t, Lp = p >= 1 ? L1 : L0;
+    for (int k = 1; k < p; ++k) {
+        const double L2 = ((2.0 * k + 1 + l - t) * L1 - (k + l) * L0) / (k + 1);
+        L0 = L1;
+        L1 = L2;
+        Lp = L2;
+    }
+    return std::pow(t, 0.5 * l) * std::fabs(Lp) * std::exp(-0.5 * t);
+}
+
+template <class F>
+double scan_max(F f, double hi) {
+    const int n = 1 << 16;
+    int best = 0;
+    double fb = f(0.0);
+    for (int k = 1; k <= n; ++k) {
+        const double v = f(hi * k / n);
+        if (v > fb) fb = v, best = k;
+    }
+    double a = hi * std::max(best - 1, 0) / n, b = hi * std::min(best + 1, n) / n;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 100; ++it) {
+        const double c = b - g * (b - a), d = a + g * (b - a);
+        if (f(c) > f(d))
+            b = d;
+        else
+            a = c;
+    }
+    return std::max(fb, f(0.5 * (a + b)));
+}
+
+double mode_peak(int mode, int m, int n) {
+    if (mode == QS_MODE_HG) {
+        auto peak1 = [](int k) {
+            return scan_max([k](double s) { return hermite_fn(k, s); }, std::sqrt(2.0 * k + 1) + 4);
+        };
+        return peak1(m) * peak1(n);
+    }
+    if (mode == QS_MODE_LG) {
+        const int l = std::abs(n);
+        return scan_max([m, l](double t) { return laguerre_fn(m, l, t); }, 4.0 * m + 2.0 * l + 30);
+    }
+    return 1.0;
+}
+
 qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_bins *H,
                         int64_t n_samples) {
     if (!L || !B || !H) return set_err(c, "null argument"), QS_EINVAL;
@@ -95,6 +157,12 @@ qs_status validate_shot(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs
         return set_err(c, "laser parameter out of range"), QS_EINVAL;
     if (L->envelope != QS_ENV_GAUSS && L->envelope != QS_ENV_SIN2)
         return set_err(c, "unknown envelope"), QS_EINVAL;
+    if (L->mode != QS_MODE_GAUSS && L->mode != QS_MODE_HG && L->mode != QS_MODE_LG)
+        return set_err(c, "unknown transverse mode"), QS_EINVAL;
+    if (L->mode == QS_MODE_HG && (L->mode_m < 0 || L->mode_m > 8 || L->mode_n < 0 || L->mode_n > 8))
+        return set_err(c, "Hermite-Gauss orders must be in [0, 8]"), QS_EINVAL;
+    if (L->mode == QS_MODE_LG && (L->mode_m < 0 || L->mode_m > 8 || L->mode_n < -8 || L->mode_n > 8))
+        return set_err(c, "Laguerre-Gauss indices: p in [0, 8], l in [-8, 8]"), QS_EINVAL;
     if (!(B->gamma0 > 1) || !(B->sigma_gamma >= 0) || !(B->sigma_r_um >= 0) ||
         !(B->sigma_z_um >= 0) || !(B->div_mrad >= 0))
         return set_err(c, "beam parameter out of range"), QS_EINVAL;
@@ -589,9 +657,21 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
             // the quadratic midpoint of the spatial factor is used only when one
             // phase step moves a sample much less than the focal scales
             const double step_um = b.h * bp.ell_per_psi;
-            const double scale = plane_wave ? 0.0 : std::fmax(p.inv_zR, 6.0 * p.div_rad / l.w0_um);
+            // (a mode of order k varies on W0 / sqrt(1 + k))
+            const int order = l.mode == QS_MODE_HG   ? std::max(l.mode_m, l.mode_n)
+                              : l.mode == QS_MODE_LG ? 2 * l.mode_m + std::abs(l.mode_n)
+                                                     : 0;
+            const double scale = plane_wave ? 0.0
+                                            : std::fmax(p.inv_zR, 6.0 * p.div_rad / l.w0_um) *
+                                                  std::sqrt(1.0 + order);
             p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
         }
+        p.mode = plane_wave ? QS_MODE_GAUSS : l.mode;
+        p.mode_m = l.mode_m;
+        p.mode_n = l.mode_n;
+        p.mode_inv_norm = p.mode == QS_MODE_GAUSS ? 1.0 : 1.0 / mode_peak(l.mode, l.mode_m, l.mode_n);
+        p.mode_inv_normf = (float)p.mode_inv_norm;
+        if (p.mode != QS_MODE_GAUSS) bp.any_mode = 1;
         p.shot_word = N->shot + k;
         p.n_samples = n_samples[k];
         p.state_off = off;
@@ -635,6 +715,10 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
+    if (tape && L)
+        for (int k = 0; k < n_shots; ++k)
+            if (L[k].mode != QS_MODE_GAUSS)
+                return set_err(c, "derivatives are for the Gaussian mode only"), QS_EUNSUPPORTED;
     Batch b;
     if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotOut), b)) != QS_OK)
         return st;
@@ -731,6 +815,10 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
+    if (L)
+        for (int k = 0; k < n_shots; ++k)
+            if (L[k].mode != QS_MODE_GAUSS)
+                return set_err(c, "derivatives are for the Gaussian mode only"), QS_EUNSUPPORTED;
     Batch b;
     if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotGrad), b)) != QS_OK)
         return st;

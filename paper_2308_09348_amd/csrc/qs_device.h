@@ -248,21 +248,78 @@ __device__ __forceinline__ double spatial(double x, double y, double z, double i
     return exp(-r2 * iq) * sqrt(iq);
 }
 
-// Geometry of one sample along its ballistic path: at phase psi it has
-// travelled l = psi lambda / (4 pi) past its collision point.
+// Higher transverse modes (amplitude only, peak 1 in the focal plane): with
+// u = x/W, v = y/W, W = W0 sqrt(q), q = 1 + z^2/zR^2,
+//   Hermite-Gauss m, n:  |H_m(sqrt2 u) H_n(sqrt2 v)| exp(-(u^2 + v^2)) / sqrt(q),
+//   Laguerre-Gauss p, l: t^(|l|/2) |L_p^|l|(t)| exp(-t/2) / sqrt(q), t = 2(u^2 + v^2),
+// divided by the mode's focal-plane peak; H and L by their three-term
+// recurrences (H_(k+1) = 2s H_k - 2k H_(k-1); (k+1) L_(k+1) =
+// (2k + 1 + l - t) L_k - (k + l) L_(k-1)).
 template <class T>
+__device__ __forceinline__ T hermite(int m, T s) {
+    T h0 = T(1), h1 = T(2) * s;
+    if (m == 0) return h0;
+    for (int k = 1; k < m; ++k) {
+        const T h2 = fma(T(2) * s, h1, T(-2 * k) * h0);
+        h0 = h1;
+        h1 = h2;
+    }
+    return h1;
+}
+template <class T>
+__device__ __forceinline__ T spatial_mode(T x, T y, T z, T inv_w0sq, T inv_zR, int mode, int mm,
+                                          int mn, T inv_norm) {
+    const T zz = z * inv_zR;
+    const T q = fma(zz, zz, T(1));
+    const T iq = T(1) / q;
+    const T u2 = x * x * inv_w0sq * iq, v2 = y * y * inv_w0sq * iq;
+    const T g = exp(-(u2 + v2)) * sqrt(iq) * inv_norm;
+    if (mode == 1) {  // Hermite-Gauss
+        const T r2 = sqrt(T(2) * inv_w0sq * iq);
+        return fabs(hermite<T>(mm, x * r2) * hermite<T>(mn, y * r2)) * g;
+    }
+    const int l = abs(mn);  // Laguerre-Gauss, p = mm
+    const T t = T(2) * (u2 + v2);
+    T L0 = T(1), L1 = T(1 + l) - t, Lp = L0;
+    if (mm >= 1) Lp = L1;
+    for (int k = 1; k < mm; ++k) {
+        const T L2 = (fma(T(2 * k + 1 + l) - t, L1, T(-(k + l)) * L0)) / T(k + 1);
+        L0 = L1;
+        L1 = L2;
+        Lp = L2;
+    }
+    T tp = T(1);
+    for (int k = 0; k < l / 2; ++k) tp *= t;
+    if (l & 1) tp *= sqrt(t);
+    return tp * fabs(Lp) * g;
+}
+
+// Geometry of one sample along its ballistic path: at phase psi it has
+// travelled l = psi lambda / (4 pi) past its collision point.  mode != 0
+// selects a higher transverse mode (QS_MODE_HG 1, QS_MODE_LG 2).
+// MODES = false compiles the Gaussian focus alone (the hot loop's register
+// budget does not carry the mode recurrences).
+template <class T, bool MODES = true>
 struct Path {
     T xc, yc, thx, thy, zstar, inv_w0sq, inv_zR;
+    int mode, mm, mn;
+    T inv_norm;
     __device__ __forceinline__ T S(T ell) const {
+        if constexpr (MODES) {
+            if (mode != 0)
+                return spatial_mode<T>(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell,
+                                       inv_w0sq, inv_zR, mode, mm, mn, inv_norm);
+        }
         return spatial(fma(thx, ell, xc), fma(thy, ell, yc), zstar - ell, inv_w0sq, inv_zR);
     }
 };
 
 // Sample i of a shot (Sec. 2 volume element): its initial Lorentz factor and
 // angles, its ballistic path and the spatial factor at its collision point.
+template <bool MODES = true>
 __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0, uint32_t key1,
                                             int64_t i, double &g0, double &thx, double &thy,
-                                            Path<double> &pd, double &S0) {
+                                            Path<double, MODES> &pd, double &S0) {
     SampleCoords sc;
     sample_coords(sp, key0, key1, i, sc);
     const double x = sc.x, y = sc.y, z = sc.z;
@@ -276,6 +333,10 @@ __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0,
     pd.zstar = fma(0.5, z, sp.z_delay);
     pd.inv_w0sq = sp.inv_w0sq;
     pd.inv_zR = sp.inv_zR;
+    pd.mode = sp.mode;
+    pd.mm = sp.mode_m;
+    pd.mn = sp.mode_n;
+    pd.inv_norm = sp.mode_inv_norm;
     S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
 }
 

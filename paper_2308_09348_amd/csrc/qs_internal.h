@@ -72,6 +72,9 @@ struct ShotParams {
     float a0f, inv_w0sqf, inv_zRf, pad0;
     int32_t plane_wave, mid_interp, shot_word;
     int32_t profile;     // kFlatR | kFlatZ: flat-top beam profiles
+    int32_t mode, mode_m, mode_n;  // transverse laser mode (QS_MODE_*), its indices
+    float mode_inv_normf;          // 1 / the mode's peak in the focal plane
+    double mode_inv_norm;
     int64_t n_samples;   // samples of this shot
     int64_t state_off;   // index of its first sample state
     int64_t item0;       // its first phase work item
@@ -152,7 +155,8 @@ struct BatchParams {
     // FP64 and FP32 copies of the shared physics constants
     double ell_per_psi, two_over_aS, K, CD, psi_max, h;
     float ellf, two_over_aSf, Kf, CDf, psi0f, hf, chi_fp64, pad0;
-    int32_t n_steps, n_shots, deposit, pad1;
+    int32_t n_steps, n_shots, deposit;
+    int32_t any_mode;  // some shot uses a higher transverse mode
     uint32_t key0, key1;
     double ksig_bins, c_theta;
     int64_t n_items, n_ditems;

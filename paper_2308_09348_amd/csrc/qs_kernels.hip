@@ -29,7 +29,7 @@ namespace qs {
 // reconstruction grid (a0,eff = a0 k / (n_anode - 1), gamma0 of node m, no
 // angles) instead of drawing sample i; the caller passes the node view of the
 // shot table (its node count and node offset as samples and state offset).
-template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false>
+template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false, bool MODES = false>
 __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotParams &sp, int64_t i,
                                              const float *__restrict__ env32,
                                              const double *__restrict__ env64,
@@ -44,7 +44,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
 
     // ---- sample and geometry (FP64, once per sample) ----
     double g0, thx = 0.0, thy = 0.0, S0;
-    Path<double> pd{};
+    Path<double, MODES> pd{};
     if (NODES) {
         static_assert(!NODES || !LOCAL, "nodes carry a fixed amplitude");
         const int k = (int)(i / sp.n_gnode);
@@ -56,7 +56,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             g0 = sp.g_node_lo + (double)m * sp.g_node_step;  // rounded twice, as defined
         }
     } else {
-        draw_sample(sp, P.key0, P.key1, i, g0, thx, thy, pd, S0);
+        draw_sample<MODES>(sp, P.key0, P.key1, i, g0, thx, thy, pd, S0);
     }
     const double a0S0 = sp.a0 * S0;
 
@@ -87,7 +87,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         s2_f = s2;
         chi_hi = (float)chd;
     } else {
-        Path<float> pf;
+        Path<float, MODES> pf;
         pf.xc = (float)pd.xc;
         pf.yc = (float)pd.yc;
         pf.thx = (float)thx;
@@ -95,6 +95,10 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         pf.zstar = (float)pd.zstar;
         pf.inv_w0sq = sp.inv_w0sqf;
         pf.inv_zR = sp.inv_zRf;
+        pf.mode = sp.mode;
+        pf.mm = sp.mode_m;
+        pf.mn = sp.mode_n;
+        pf.inv_norm = sp.mode_inv_normf;
         const float a0f = sp.a0f;
         const float a0S0f = (float)a0S0;
         float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
@@ -190,7 +194,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
     P.st.cmx[k] = cmx;
 }
 
-template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false>
+template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false, bool MODES = false>
 __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
                                                             const float *__restrict__ env32,
                                                             const double *__restrict__ env64) {
@@ -211,7 +215,8 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
         const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
         if (i < sp.n_samples) {
             int flags = 0;
-            phase_sample<PREC, QUANTUM, LOCAL, NODES>(P, sp, i, env32, env64, tab32, flags);
+            phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(P, sp, i, env32, env64, tab32,
+                                                             flags);
             if (flags) atomicOr(&P.flags[s], flags);
         }
     }
@@ -507,25 +512,27 @@ hipError_t launch_zero(unsigned long long *p, size_t n64, hipStream_t s) {
 }
 
 template <int PREC, bool QUANTUM, bool LOCAL>
-static const void *phase_ptr() {
+static const void *phase_ptr(bool modes) {
+    if (modes) return reinterpret_cast<const void *>(&phase_kernel<PREC, QUANTUM, LOCAL, false, true>);
     return reinterpret_cast<const void *>(&phase_kernel<PREC, QUANTUM, LOCAL>);
 }
 
-static const void *select_phase(int prec, int rr, int amp) {
+// modes: some shot of the launch uses a higher transverse mode
+static const void *select_phase(int prec, int rr, int amp, bool modes) {
     const bool q = rr == 1, l = amp == 1;
     if (prec == PREC_F32MIX && !q) prec = PREC_F32;  // no radiation table, no promotion
 #define QS_SEL(P)                                              \
     if (prec == P) {                                           \
-        if (q && l) return phase_ptr<P, true, true>();         \
-        if (q && !l) return phase_ptr<P, true, false>();       \
-        if (!q && l) return phase_ptr<P, false, true>();       \
-        return phase_ptr<P, false, false>();                   \
+        if (q && l) return phase_ptr<P, true, true>(modes);    \
+        if (q && !l) return phase_ptr<P, true, false>(modes);  \
+        if (!q && l) return phase_ptr<P, false, true>(modes);  \
+        return phase_ptr<P, false, false>(modes);              \
     }
     QS_SEL(PREC_F32)
     QS_SEL(PREC_F64)
     if (prec == PREC_F32MIX) {
-        if (l) return phase_ptr<PREC_F32MIX, true, true>();
-        return phase_ptr<PREC_F32MIX, true, false>();
+        if (l) return phase_ptr<PREC_F32MIX, true, true>(modes);
+        return phase_ptr<PREC_F32MIX, true, false>(modes);
     }
 #undef QS_SEL
     return nullptr;
@@ -533,7 +540,7 @@ static const void *select_phase(int prec, int rr, int amp) {
 
 hipError_t launch_phase(const BatchParams &p, const float *env32, const double *env64, int prec,
                         int rr, int amp, hipStream_t s) {
-    const void *fn = select_phase(prec, rr, amp);
+    const void *fn = select_phase(prec, rr, amp, p.any_mode != 0);
     if (!fn) return hipErrorInvalidValue;
     int grid = 0;
     hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);

@@ -337,6 +337,10 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     pd.zstar = fma(0.5, z, sp.z_delay);
     pd.inv_w0sq = sp.inv_w0sq;
     pd.inv_zR = sp.inv_zR;
+    pd.mode = sp.mode;
+    pd.mm = sp.mode_m;
+    pd.mn = sp.mode_n;
+    pd.inv_norm = sp.mode_inv_norm;
     const double S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
     Path<T> pt;
     pt.xc = (T)pd.xc;
@@ -346,6 +350,10 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     pt.zstar = (T)pd.zstar;
     pt.inv_w0sq = (T)sp.inv_w0sq;
     pt.inv_zR = (T)sp.inv_zR;
+    pt.mode = sp.mode;
+    pt.mm = sp.mode_m;
+    pt.mn = sp.mode_n;
+    pt.inv_norm = (T)sp.mode_inv_norm;
 
     const T a0 = (T)sp.a0, a0S0 = (T)(sp.a0 * S0);
     const float inv_a0 = sp.a0 > 0.0 ? (float)(1.0 / sp.a0) : 0.0f;
