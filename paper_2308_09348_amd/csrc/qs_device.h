@@ -73,15 +73,13 @@ __device__ __forceinline__ void sample_coords(const ShotParams &sp, uint32_t k0,
             sn0 = s;
         }
     }
-    if (sp.profile & kFlatR) {
-        const double rad = sp.sigma_r * sqrt(u[0]);
-        sc.x = fma(rad, cs0, sp.x_off);
-        sc.y = fma(rad, sn0, sp.y_off);
-    } else {
-        sc.x = fma(sp.sigma_r, sc.n[0], sp.x_off);
-        sc.y = fma(sp.sigma_r, sc.n[1], sp.y_off);
-    }
-    sc.z = (sp.profile & kFlatZ) ? sp.sigma_z * (u[2] - 0.5) : sp.sigma_z * sc.n[2];
+    // selects rather than branches: the hot loops that follow keep their
+    // register budget
+    const bool flat_r = (sp.profile & kFlatR) != 0;
+    const double rad = sp.sigma_r * sqrt(u[0]);
+    sc.x = fma(flat_r ? rad : sp.sigma_r, flat_r ? cs0 : sc.n[0], sp.x_off);
+    sc.y = fma(flat_r ? rad : sp.sigma_r, flat_r ? sn0 : sc.n[1], sp.y_off);
+    sc.z = sp.sigma_z * ((sp.profile & kFlatZ) ? u[2] - 0.5 : sc.n[2]);
     sc.g0 = fma(sp.sigma_gamma, sc.n[3], sp.gamma0);
     sc.thx = sp.div_rad * sc.n[4];
     sc.thy = sp.div_rad * sc.n[5];
@@ -155,22 +153,79 @@ __device__ __forceinline__ void rad_cell_eval(const RadCell32 &cell, float chi, 
     hq = fmaf(t, fmaf(t, fmaf(t, cell.q3.w, cell.q3.z), cell.q3.y), cell.q3.x);
 }
 
-__device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
-                                           double &G1, double &G2, double &hq) {
+// FP64 cell of chi and the coordinate t in the cell (cell 0 is linear in chi
+// below 2^kEMin; chi beyond the table is clamped to the last cell and
+// reported by the caller).
+__device__ __forceinline__ int rad_index64(double chi, double &t) {
     const uint64_t b = (uint64_t)__double_as_longlong(chi);
     int64_t c = (int64_t)(b >> (52 - kSB64)) - ((int64_t)(1023 + kEMin) << kSB64) + 1;
-    double t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
-                                                0x3ff0000000000000ull)) - 1.0;
+    t = __longlong_as_double((long long)(((b & ((1ull << (52 - kSB64)) - 1)) << kSB64) |
+                                         0x3ff0000000000000ull)) - 1.0;
     if (c < 1) {
         c = 0;
         t = chi * 0x1p20;
     }
-    c = c < kCells64 - 1 ? c : kCells64 - 1;
-    const double *q = tab + (size_t)c * kCellVals;
+    return (int)(c < kCells64 - 1 ? c : kCells64 - 1);
+}
+
+__device__ __forceinline__ void rad_cell_eval64(const double *q, double t, double &g, double &G1,
+                                                double &G2, double &hq) {
     g = fma(t, fma(t, fma(t, q[3], q[2]), q[1]), q[0]);
     G1 = fma(t, fma(t, fma(t, q[7], q[6]), q[5]), q[4]);
     G2 = fma(t, fma(t, fma(t, q[11], q[10]), q[9]), q[8]);
     hq = fma(t, fma(t, fma(t, q[15], q[14]), q[13]), q[12]);
+}
+
+__device__ __forceinline__ void rad_eval64(const double *__restrict__ tab, double chi, double &g,
+                                           double &G1, double &G2, double &hq) {
+    double t;
+    const int c = rad_index64(chi, t);
+    rad_cell_eval64(tab + (size_t)c * kCellVals, t, g, G1, G2, hq);
+}
+
+// The FP64 cells of all 64 lanes of a wavefront, fetched together.  A cell
+// is 128 bytes, one cache line; read lane by lane, every load instruction
+// would touch 64 lines.  Here four lanes read 64 bytes of one cell, so every
+// load instruction touches 16 lines and uses each fully for its half, and
+// the cells reach their lanes through a per-wavefront LDS staging area: one
+// row a lane holding half a cell (first the lower, then the upper 64 bytes),
+// rows padded to 80 bytes so that the row reads of eight lanes fall on
+// distinct banks.  Every lane of the wavefront must be active; the values
+// are those rad_eval64 reads.
+constexpr int kStageStride = 5;                  // 16-byte chunks a row
+constexpr int kStageChunks = 64 * kStageStride;  // per wavefront
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void coop_cell64(const double *__restrict__ tab, int c,
+                                            double2 *__restrict__ stage, double q[16]) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int k = lane & 3;
+    const double2 *cell[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int cr = __shfl(c, 16 * r + (lane >> 2), 64);
+        cell[r] = reinterpret_cast<const double2 *>(tab + (size_t)cr * kCellVals) + k;
+    }
+    const double2 *row = stage + lane * kStageStride;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            stage[(16 * r + (lane >> 2)) * kStageStride + k] = cell[r][4 * half];
+        wave_sync_lds();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double2 v = row[m];
+            q[8 * half + 2 * m] = v.x;
+            q[8 * half + 2 * m + 1] = v.y;
+        }
+        wave_sync_lds();  // the upper halves overwrite the rows
+    }
 }
 
 template <class T>
@@ -190,6 +245,17 @@ struct RadTab<double> {
         rad_eval64(p, chi, g, G1, G2, h);
     }
 };
+// FP64 table read cooperatively by the whole wavefront (see coop_cell64).
+struct RadTabWave {
+    const double *p;
+    double2 *stage;
+    __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2,
+                                         double &h) const {
+        double t, q[16];
+        coop_cell64(p, rad_index64(chi, t), stage, q);
+        rad_cell_eval64(q, t, g, G1, G2, h);
+    }
+};
 
 // ===========================================================================
 // The moment system (second-order closure of the drift-diffusion process
@@ -203,8 +269,8 @@ struct Phys {
     T K, CD, two_over_aS;
 };
 
-template <class T, bool QUANTUM>
-__device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const RadTab<T> &tab,
+template <class T, bool QUANTUM, class Tab = RadTab<T>>
+__device__ __forceinline__ void rhs(T mu, T s2, T a, const Phys<T> &ph, const Tab &tab,
                                     T &dmu, T &ds2, T &chi_hi) {
     const T a2 = a * a;
     const T Ka2 = ph.K * a2;
@@ -342,16 +408,16 @@ __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0,
 
 // One RK4 step of (mu, sig2) from psi_j with amplitudes a1 = a(psi_j),
 // ah = a(psi_j + h/2), a4 = a(psi_j + h); returns the increments.
-template <class T, bool QUANTUM>
+template <class T, bool QUANTUM, class Tab = RadTab<T>>
 __device__ __forceinline__ void rk4_increment(T mu, T s2, T a1, T ah, T a4, T h,
-                                              const Phys<T> &ph, const RadTab<T> &tab, T &dmu,
+                                              const Phys<T> &ph, const Tab &tab, T &dmu,
                                               T &ds2, T &chi_hi) {
     const T hh = T(0.5) * h;
     T k1m, k1s, k2m, k2s, k3m, k3s, k4m, k4s;
-    rhs<T, QUANTUM>(mu, s2, a1, ph, tab, k1m, k1s, chi_hi);
-    rhs<T, QUANTUM>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, chi_hi);
-    rhs<T, QUANTUM>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, chi_hi);
-    rhs<T, QUANTUM>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, chi_hi);
+    rhs<T, QUANTUM, Tab>(mu, s2, a1, ph, tab, k1m, k1s, chi_hi);
+    rhs<T, QUANTUM, Tab>(fma(hh, k1m, mu), fma(hh, k1s, s2), ah, ph, tab, k2m, k2s, chi_hi);
+    rhs<T, QUANTUM, Tab>(fma(hh, k2m, mu), fma(hh, k2s, s2), ah, ph, tab, k3m, k3s, chi_hi);
+    rhs<T, QUANTUM, Tab>(fma(h, k3m, mu), fma(h, k3s, s2), a4, ph, tab, k4m, k4s, chi_hi);
     const T h6 = h * T(1.0 / 6.0);
     dmu = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
     ds2 = h6 * (k1s + T(2) * (k2s + k3s) + k4s);

@@ -29,12 +29,54 @@ namespace qs {
 // reconstruction grid (a0,eff = a0 k / (n_anode - 1), gamma0 of node m, no
 // angles) instead of drawing sample i; the caller passes the node view of the
 // shot table (its node count and node offset as samples and state offset).
+// FP64 steps of the mixed-precision loop from step j on, for as long as some
+// lane of the wavefront has chi above the threshold at the step start: the
+// amplitude's spatial factor is carried from one step's end to the next
+// step's start, as in the FP64 loop.  Returns the first step not taken.
+template <bool QUANTUM, bool MODES>
+__device__ __forceinline__ int fp64_segment(const BatchParams &P, const ShotParams &sp,
+                                            const Path<double, MODES> &pd, bool local,
+                                            double a0S0, const double *__restrict__ env64, int j,
+                                            double2 *stage, double &mu, double &s2, float &cmx,
+                                            double &chd) {
+    const RadTabWave tabd{P.rad64, stage};
+    const Phys<double> phd{P.K, P.CD, P.two_over_aS};
+    const int N = P.n_steps;
+    double aS1 = local ? sp.a0 * pd.S(fma((double)j, P.h, -P.psi_max) * P.ell_per_psi) : a0S0;
+    bool more = true;
+    while (more) {
+        const double psi = fma((double)j, P.h, -P.psi_max);
+        double aSh = a0S0, aS4 = a0S0;
+        if (local) {
+            aSh = sp.a0 * pd.S(fma(0.5, P.h, psi) * P.ell_per_psi);
+            aS4 = sp.a0 * pd.S((psi + P.h) * P.ell_per_psi);
+        }
+        double dm, ds;
+        rk4_increment<double, QUANTUM, RadTabWave>(mu, s2, aS1 * env64[2 * j],
+                                                   aSh * env64[2 * j + 1], aS4 * env64[2 * j + 2],
+                                                   P.h, phd, tabd, dm, ds, chd);
+        mu += dm;
+        s2 += ds;
+        aS1 = aS4;
+        ++j;
+        if (j >= N) break;
+        const double chi = P.two_over_aS * mu * fabs(aS1 * env64[2 * j]);
+        cmx = fmaxf(cmx, (float)chi);
+        more = __any(chi > (double)P.chi_fp64);
+    }
+    return j;
+}
+
 template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false, bool MODES = false>
+// stage: this wavefront's staging rows for the FP64 table (quantum passes
+// with FP64 steps; every lane of the wavefront runs, live says whether the
+// lane's sample is real and its state is stored).
 __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotParams &sp, int64_t i,
                                              const float *__restrict__ env32,
                                              const double *__restrict__ env64,
-                                             const float *tab32, int &flags) {
-    const RadTab<double> tabd{P.rad64};
+                                             const float *tab32, double2 *stage, bool live,
+                                             int &flags) {
+    const RadTabWave tabd{P.rad64, stage};
     const RadTab<float> tabf{tab32};
     const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
     const Phys<double> phd{P.K, P.CD, P.two_over_aS};
@@ -78,7 +120,8 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             const double a4 = aS4 * env64[2 * j + 2];
             cmx = fmaxf(cmx, (float)(P.two_over_aS * mu * fabs(a1)));
             double dm, ds;
-            rk4_increment<double, QUANTUM>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds, chd);
+            rk4_increment<double, QUANTUM, RadTabWave>(mu, s2, a1, ah, a4, P.h, phd, tabd, dm, ds,
+                                                       chd);
             mu += dm;
             s2 += ds;
             aS_prev = aS4;
@@ -117,7 +160,34 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         // psi_{j+1} and psi_{j+2} (error of order h^3 times the third
         // derivative of S, far below FP32 rounding)
         float aS_next = local ? a0f * pf.S((P.psi0f + P.hf) * P.ellf) : a0S0f;
-        for (int j = 0; j < N; ++j) {
+        int j = 0;
+        while (j < N) {
+            if (PREC == PREC_F32MIX) {
+                const float chi1 = amp1.cpm * mu;
+                cmx = fmaxf(cmx, chi1);
+                if (__any(chi1 > P.chi_fp64)) {
+                    // FP64 steps while any lane of the wavefront has chi above
+                    // the threshold at the step start (uniform loop); the FP32
+                    // state, amplitudes and cell are rebuilt at the exit step
+                    double mud = (double)mu + (double)mu_lo;
+                    double s2d = (double)s2 + (double)s2_lo;
+                    j = fp64_segment<QUANTUM>(P, sp, pd, local, a0S0, env64, j, stage, mud, s2d,
+                                              cmx, chd);
+                    mu = (float)mud;
+                    mu_lo = (float)(mud - (double)mu);
+                    s2 = (float)s2d;
+                    s2_lo = (float)(s2d - (double)s2);
+                    if (local) {
+                        aS_prev = a0f * pf.S(fmaf((float)j, P.hf, P.psi0f) * P.ellf);
+                        aS_next = a0f * pf.S(fmaf((float)(j + 1), P.hf, P.psi0f) * P.ellf);
+                    }
+                    if (j < N) {
+                        amp1 = AmpQ(aS_prev * env32[2 * j], phf);
+                        rad_lookup32(tab32, amp1.cpm * mu, carry);
+                    }
+                    continue;
+                }
+            }
             float aSh = a0S0f, aS4 = a0S0f;
             if (local && sp.mid_interp) {
                 const float psi2 = fmaf((float)(j + 2), P.hf, P.psi0f);
@@ -133,45 +203,20 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             const float a1 = aS_prev * env32[2 * j];
             const float ah = aSh * env32[2 * j + 1];
             const float a4 = aS4 * env32[2 * j + 2];
-            const float chi1 = QUANTUM ? amp1.cpm * mu : phf.two_over_aS * mu * fabsf(a1);
-            cmx = fmaxf(cmx, chi1);
-            bool promote = false;
-            if (PREC == PREC_F32MIX) promote = __any(chi1 > P.chi_fp64);
-            if (promote) {
-                // the whole wavefront runs this step in FP64 (uniform branch)
-                const double psid = fma((double)j, P.h, -P.psi_max);
-                double A1 = a0S0, Ah = a0S0, A4 = a0S0;
-                if (local) {
-                    A1 = sp.a0 * pd.S(psid * P.ell_per_psi);
-                    Ah = sp.a0 * pd.S(fma(0.5, P.h, psid) * P.ell_per_psi);
-                    A4 = sp.a0 * pd.S((psid + P.h) * P.ell_per_psi);
-                }
-                A1 *= env64[2 * j];
-                Ah *= env64[2 * j + 1];
-                A4 *= env64[2 * j + 2];
-                const double mud = (double)mu + (double)mu_lo;
-                const double s2d = (double)s2 + (double)s2_lo;
-                double dm, ds;
-                rk4_increment<double, QUANTUM>(mud, s2d, A1, Ah, A4, P.h, phd, tabd, dm, ds, chd);
-                const double mn = mud + dm, sn = s2d + ds;
-                mu = (float)mn;
-                mu_lo = (float)(mn - (double)mu);
-                s2 = (float)sn;
-                s2_lo = (float)(sn - (double)s2);
-                // the next FP32 stage 1 needs the cell at the new state
-                amp1 = AmpQ(a4, phf);
-                rad_lookup32(tab32, amp1.cpm * mu, carry);
-            } else if (QUANTUM) {
+            if (QUANTUM) {
+                if (PREC != PREC_F32MIX) cmx = fmaxf(cmx, amp1.cpm * mu);
                 float dm, ds;
                 rk4_q32(mu, s2, amp1, ah, a4, P.hf, phf, tab32, carry, dm, ds, chi_hi);
                 comp_add(mu, mu_lo, dm);
                 comp_add(s2, s2_lo, ds);
             } else {
+                cmx = fmaxf(cmx, phf.two_over_aS * mu * fabsf(a1));
                 float dm, ds;
                 rk4_increment<float, false>(mu, s2, a1, ah, a4, P.hf, phf, tabf, dm, ds, chi_hi);
                 comp_add(mu, mu_lo, dm);
             }
             aS_prev = aS4;
+            ++j;
         }
         mu_f = ((double)mu + (double)mu_lo) + g0_rest;
         s2_f = (double)s2 + (double)s2_lo;
@@ -182,6 +227,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         const double aN = (local ? sp.a0 * pd.S(P.psi_max * P.ell_per_psi) : a0S0) * env64[2 * N];
         cmx = fmaxf(cmx, (float)(P.two_over_aS * mu_f * fabs(aN)));
     }
+    if (!live) return;
     if (QUANTUM && !(chi_hi < chi_top)) flags |= kFlagRange;
     if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) flags |= kFlagNonFinite;
     const int64_t k = sp.state_off + i;
@@ -199,7 +245,12 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
                                                             const float *__restrict__ env32,
                                                             const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    // FP64 table staging (quantum passes with FP64 steps): every lane of a
+    // wavefront takes part in the table reads, so lanes past the end of the
+    // shot run its last sample again without storing it
+    constexpr bool kWave64 = QUANTUM && PREC != PREC_F32;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
+    __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
@@ -207,16 +258,18 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
         for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
         __syncthreads();
     }
+    double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
         if (item >= P.n_items) break;
         const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
         const ShotParams &sp = P.shots[s];
         const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
-        if (i < sp.n_samples) {
+        const bool live = i < sp.n_samples;
+        if (kWave64 || live) {
             int flags = 0;
-            phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(P, sp, i, env32, env64, tab32,
-                                                             flags);
+            phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(
+                P, sp, live ? i : sp.n_samples - 1, env32, env64, tab32, wstage, live, flags);
             if (flags) atomicOr(&P.flags[s], flags);
         }
     }

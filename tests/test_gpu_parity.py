@@ -164,6 +164,41 @@ def test_focused_parity(gpu, oracle, rr, amp, dep, prec, chi64):
     assert np.allclose(recs[:, 7], ref[:, oracle.S_GAMMA0], rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("amp", ["local", "a0eff"])
+def test_promotion_everywhere_is_the_fp64_pass(gpu, amp):
+    """A threshold below every chi promotes every step of every wavefront: the
+    mixed-precision pass then integrates in FP64 from start to end (one FP64
+    segment) and differs from the FP64 pass only by the FP32 pair that holds
+    the state on return (2^-48 relative)."""
+    p = workloads.scaled(workloads.focused_3d(), n_samples=3037, n_steps=384,
+                         amp_mode=amp, deposit="gauss")
+    n = p["n_samples"]
+    g = _run(gpu, dict(p, precision="fp32", chi_fp64=1e-30), sample_stride=1,
+             n_sample_records=n)
+    d = _run(gpu, dict(p, precision="fp64"), sample_stride=1, n_sample_records=n)
+    assert np.allclose(g["samples"][:, 0], d["samples"][:, 0], rtol=1e-13, atol=0)
+    assert np.allclose(g["samples"][:, 1], d["samples"][:, 1], rtol=1e-12,
+                       atol=1e-12 * d["samples"][:, 1].max())
+    _check_bins(g["energy_hist"], d["energy_hist"], rel=1e-9, floor=1e-12)
+
+
+def test_promotion_at_high_chi(gpu, oracle):
+    """Quantum-batch physics (gamma0 = 2e4, a0 = 120, W0 = 2 um: chi up to
+    several): FP64 steps where chi > 0.1, FP32 elsewhere, against the oracle;
+    segments of FP64 steps start and end inside the pulse."""
+    shot = workloads.quantum_batch(n_shots=4)[1]
+    p = dict(shot, a0=120.0, n_samples=2037, n_steps=1024)
+    g = _run(gpu, p, sample_stride=13, n_sample_records=p["n_samples"] // 13 + 1)
+    o = oracle.forward(p)
+    _check_moments(g, o, p)
+    _check_bins(g["energy_hist"], o["energy_hist"])
+    ref = oracle.samples(p, range(0, p["n_samples"], 13))
+    assert np.allclose(g["samples"][:, 0], ref[:, oracle.S_MU], rtol=3e-6, atol=0)
+    assert np.allclose(g["samples"][:, 1], ref[:, oracle.S_SIG2], rtol=3e-5,
+                       atol=3e-5 * ref[:, oracle.S_SIG2].max())
+    assert g["moments"][8] > 1.0  # the promoted steps were taken
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
 def test_small_and_ragged_sizes(gpu, oracle, n):
     p = workloads.scaled(workloads.focused_3d(), n_samples=n, n_steps=64)
