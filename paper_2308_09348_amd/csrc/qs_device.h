@@ -246,13 +246,23 @@ struct RadTab<double> {
     }
 };
 // FP64 table read cooperatively by the whole wavefront (see coop_cell64).
+// The last cells read stay in registers: a stage whose lanes all fall in the
+// cells they already hold (the third RK4 stage mostly, and the first stage
+// after the fourth at the same amplitude) reads nothing.
 struct RadTabWave {
     const double *p;
     double2 *stage;
+    mutable double q[16];
+    mutable int c = -1;
+    __device__ __forceinline__ RadTabWave(const double *tab, double2 *st) : p(tab), stage(st) {}
     __device__ __forceinline__ void eval(double chi, double &g, double &G1, double &G2,
                                          double &h) const {
-        double t, q[16];
-        coop_cell64(p, rad_index64(chi, t), stage, q);
+        double t;
+        const int cn = rad_index64(chi, t);
+        if (__any(cn != c)) {
+            coop_cell64(p, cn, stage, q);
+            c = cn;
+        }
         rad_cell_eval64(q, t, g, G1, G2, h);
     }
 };

@@ -39,7 +39,7 @@ __device__ __forceinline__ int fp64_segment(const BatchParams &P, const ShotPara
                                             double a0S0, const double *__restrict__ env64, int j,
                                             double2 *stage, double &mu, double &s2, float &cmx,
                                             double &chd) {
-    const RadTabWave tabd{P.rad64, stage};
+    const RadTabWave tabd(P.rad64, stage);
     const Phys<double> phd{P.K, P.CD, P.two_over_aS};
     const int N = P.n_steps;
     double aS1 = local ? sp.a0 * pd.S(fma((double)j, P.h, -P.psi_max) * P.ell_per_psi) : a0S0;
@@ -76,7 +76,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
                                              const double *__restrict__ env64,
                                              const float *tab32, double2 *stage, bool live,
                                              int &flags) {
-    const RadTabWave tabd{P.rad64, stage};
+    const RadTabWave tabd(P.rad64, stage);
     const RadTab<float> tabf{tab32};
     const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
     const Phys<double> phd{P.K, P.CD, P.two_over_aS};
