@@ -918,6 +918,8 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         p.nv = qs::kPhNV;
         p.v_lo = std::log(mu_min) - 0.01;
         p.dv = (std::log(mu_max) + 0.01 - p.v_lo) / (p.nv - 1);
+        p.v_lof = (float)p.v_lo;
+        p.inv_dv = (float)(1.0 / p.dv);
         // chi range: the largest chi possible above; below, stages whose
         // photons all fall in the lowest bin (y > 27 beyond 40 chi mu)
         const double width = (PB[k].ph_hi - PB[k].ph_lo) / PB[k].n_ph;

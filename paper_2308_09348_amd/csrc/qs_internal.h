@@ -131,6 +131,7 @@ constexpr double kPhScale = 16777216.0;  // 2^24: unit of the grid weights
 struct ShotPhot {
     int32_t r_lo, nu, nv, n_ph;  // first global row, rows, columns, photon bins
     double v_lo, dv;             // ln mu at column 0, column width
+    float v_lof, inv_dv;         // the same for the FP32 deposit: v_lo, 1 / dv
     double ph_lo, ph_w;          // photon-energy bins [m c^2]
     double *hist;                // [n_ph + 2]
     double *energy;              // [2]: photon energy, electron energy loss

@@ -187,7 +187,11 @@ struct AngStep {
     __device__ __forceinline__ void add(T c, T a, T mu, T A, T thx, T thy, float tas,
                                         const float *tot) {
         const T aa = fabs(a);
-        const T imu = T(1) / mu;
+        T imu;
+        if constexpr (sizeof(T) == 4)
+            imu = __builtin_amdgcn_rcpf(mu);  // about one ulp
+        else
+            imu = T(1) / mu;
         const T tx = fma(a, imu, thx), cone = imu * imu;
         const T x2 = fma(tx, tx, cone), y2 = fma(thy, thy, cone);
         const T dn = aa > T(0) ? c * aa * (T)ph_total(tot, tas * (float)mu * (float)aa) : T(0);
@@ -201,6 +205,9 @@ struct AngStep {
     }
 };
 
+// Weights in units of 2^-24 (kPhScale): D <= 2/3, so every node weight is
+// below 2^24 and its FP32 product is within half a unit of the exact one
+// before rounding to an integer; the grid words sum them in any order alike.
 __device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi,
                                            const ShotPhot &sp, unsigned long long *grid,
                                            PhotAcc &acc) {
@@ -209,7 +216,7 @@ __device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi
         acc.soft += (double)D * (1.0 - 0.92376043070340122 * (double)chi);
         return;
     }
-    float fu = ru, fv = (v - (float)sp.v_lo) / (float)sp.dv;
+    float fu = ru, fv = (v - sp.v_lof) * sp.inv_dv;
     if (!(fu <= (float)(sp.nu - 1)) || !(fv >= 0.0f) || !(fv <= (float)(sp.nv - 1))) {
         acc.flags |= kFlagRange;
         fu = fminf(fmaxf(fu, 0.0f), (float)(sp.nu - 1));
@@ -217,16 +224,13 @@ __device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi
     }
     const int n = min((int)fu, sp.nu - 2), m = min((int)fv, sp.nv - 2);
     const float du = fu - (float)n, dv = fv - (float)m;
-    const double q = (double)D * kPhScale;
+    const float q = D * (float)kPhScale;
+    const float qu = q * du, ql = q - qu;  // the two rows' shares
     unsigned long long *g = grid + n * sp.nv + m;
-    const unsigned long long q00 = (unsigned long long)llrint(q * (double)((1.0f - du) * (1.0f - dv)));
-    const unsigned long long q01 = (unsigned long long)llrint(q * (double)((1.0f - du) * dv));
-    const unsigned long long q10 = (unsigned long long)llrint(q * (double)(du * (1.0f - dv)));
-    const unsigned long long q11 = (unsigned long long)llrint(q * (double)(du * dv));
-    if (q00) atomicAdd(g, q00);
-    if (q01) atomicAdd(g + 1, q01);
-    if (q10) atomicAdd(g + sp.nv, q10);
-    if (q11) atomicAdd(g + sp.nv + 1, q11);
+    atomicAdd(g, (unsigned long long)(unsigned int)rintf(ql - ql * dv));
+    atomicAdd(g + 1, (unsigned long long)(unsigned int)rintf(ql * dv));
+    atomicAdd(g + sp.nv, (unsigned long long)(unsigned int)rintf(qu - qu * dv));
+    atomicAdd(g + sp.nv + 1, (unsigned long long)(unsigned int)rintf(qu * dv));
 }
 
 // Radiation functions per stage in the forward table's combinations
@@ -368,6 +372,10 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     }
     T chi_hi = T(0);
     T aS_prev = local ? a0 * pt.S(psi0 * ell) : a0S0;
+    // FP32 with fine steps: one spatial factor a step, the midpoint from the
+    // quadratic through three step points (as in the phase kernel)
+    const bool mid = PREC != PREC_F64 && local && sp.mid_interp;
+    T aS_next = mid ? a0 * pt.S((psi0 + h) * ell) : a0S0;
     if (QUANTUM) rad.init(ph.two_over_aS * mu * fabs(aS_prev * env[0]));
     // the first stage of the first step deposits alone
     {
@@ -382,7 +390,12 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     for (int j = 0; j < N; ++j) {
         const T psi = fma((T)j, h, psi0);
         T aSh = a0S0, aS4 = a0S0;
-        if (local) {
+        if (mid) {
+            const T aS_far = a0 * pt.S(fma((T)(j + 2), h, psi0) * ell);
+            aS4 = aS_next;
+            aSh = fma(T(0.375), aS_prev, fma(T(0.75), aS4, T(-0.125) * aS_far));
+            aS_next = aS_far;
+        } else if (local) {
             aSh = a0 * pt.S(fma(T(0.5), h, psi) * ell);
             aS4 = a0 * pt.S((psi + h) * ell);
         }
