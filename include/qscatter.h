@@ -433,6 +433,53 @@ qs_status qs_set_profiling(qs_ctx *ctx, int on);
  * profiled call yet), QS_EDEVICE. */
 qs_status qs_last_timings(qs_ctx *ctx, double *ms);
 
+/* Launch choices for a class of forward launches (qs_tune).  None of them
+ * changes a result bit: moment partial sums are kept per tile of 1024
+ * samples whatever the deposit tile. */
+typedef struct qs_tuning {
+    int32_t dep_tile;    /* samples of one deposit work item: 1024 .. 8192      */
+    int32_t phase_cap;   /* resident phase blocks per compute unit at most; 0 =
+                            as many as fit                                    */
+    int32_t dep_cap;     /* the same for the deposit kernel                     */
+    int32_t from_cache;  /* 1: read from the cache file, nothing was timed      */
+    double phase_ms;     /* phase kernel time of the choice (from the cache if
+                            from_cache)                                       */
+    double deposit_ms;   /* deposit kernel time of the choice                   */
+} qs_tuning;
+
+/* Tune the forward launches of one class (batching of the high-repetition-
+ * rate use in the abstract and the conclusions: many shots, each launch
+ * sized to the machine).  The class is (n_steps, rr_model, amp_mode,
+ * deposit, precision with its FP64 steps, histogram words n_e + n_th + n_a
+ * + 4, floor(log2 n_samples), floor(log2 shots)); it is taken from num,
+ * bins and one shot (laser, beam, num->n_samples).  The call times forward
+ * passes of that shot on `stream` under each candidate (phase blocks per CU
+ * in {all, 3, 2}, then deposit tile in {1024, 2048, 4096, 8192} x deposit
+ * blocks per CU in {all, 4, 2}), keeps the fastest for later launches of the
+ * class on this context and, when cache_path is not NULL, appends it to that
+ * text file as one line keyed by the device (architecture and compute-unit
+ * count) and the class.  A cache line for this device and class is used
+ * instead of timing.  `out` (host, optional) receives the choice.  Blocks
+ * until the trial passes end; allocates its own trial outputs.  Launches of
+ * other classes keep the defaults (deposit tile 4096, all resident blocks).
+ * Errors: QS_EINVAL (as qs_forward; a cache file that cannot be appended
+ * to), QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_tune(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                  const qs_numerics *num, const qs_bins *bins, const char *cache_path,
+                  qs_tuning *out, void *stream);
+
+/* Enable (on != 0) or disable HIP graphs for qs_forward and
+ * qs_forward_batched on this context: the device work of a launch after the
+ * shot-table copy (envelope table, accumulator clear, phase, deposit,
+ * finalize kernels) is captured once into a graph and replayed by later
+ * launches whose kernel arguments are byte-identical (same shapes, sample
+ * counts, numerics and scratch buffers; the per-shot parameters and output
+ * pointers travel in the shot table, which is copied before every replay).
+ * Up to 8 graphs are kept.  Results are the same bits as without graphs.
+ * Profiled launches and derivative-tape launches are not captured.
+ * Errors: QS_EINVAL (ctx NULL). */
+qs_status qs_set_graphs(qs_ctx *ctx, int on);
+
 /* Static description of a status code. */
 const char *qs_strerror(qs_status s);
 

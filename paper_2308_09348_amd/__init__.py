@@ -9,6 +9,7 @@ the HIP kernels of ``libqscatter.so``; PyTorch only provides device memory and
 the stream.
 """
 import ctypes
+import os
 
 from . import _lib
 
@@ -408,6 +409,32 @@ class Context:
             raise QScatterError(st, self.last_error())
         torch.cuda.synchronize(dev)
         return out
+
+    def tune(self, params, cache_path=None, stream=None):
+        """Time the launch choices for the class of `params` (qs_tune) and keep
+        the fastest for later launches of that class on this context; with
+        cache_path, read the choice from / append it to that text file.
+        Returns the choice as a dict."""
+        torch = _torch()
+        la, be, nu, bi = _lib.structs(params)
+        stream = stream or torch.cuda.current_stream(torch.device("cuda", self.device))
+        t = _lib.Tuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        st = _lib.lib().qs_tune(self._ptr, ctypes.byref(la), ctypes.byref(be), ctypes.byref(nu),
+                                ctypes.byref(bi), path, ctypes.byref(t),
+                                ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        return {"dep_tile": t.dep_tile, "phase_cap": t.phase_cap, "dep_cap": t.dep_cap,
+                "from_cache": bool(t.from_cache), "phase_ms": t.phase_ms,
+                "deposit_ms": t.deposit_ms}
+
+    def set_graphs(self, on=True):
+        """Capture forward launches into HIP graphs and replay them for
+        launches with identical kernel arguments (qs_set_graphs)."""
+        st = _lib.lib().qs_set_graphs(self._ptr, 1 if on else 0)
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
 
     def set_profiling(self, on=True):
         st = _lib.lib().qs_set_profiling(self._ptr, 1 if on else 0)

@@ -71,6 +71,12 @@ class NodeGrid(ctypes.Structure):
                 ("node_states", ctypes.c_void_p), ("node_weights", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("dep_tile", ctypes.c_int32), ("phase_cap", ctypes.c_int32),
+                ("dep_cap", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("phase_ms", ctypes.c_double), ("deposit_ms", ctypes.c_double)]
+
+
 NODE_FIELDS = 5  # a0,eff, gamma0, mu_f, sig2_f, chi max
 N_A, N_GAMMA0, N_MU, N_SIG2, N_CHIMAX = range(NODE_FIELDS)
 
@@ -103,8 +109,8 @@ EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched",
            "qs_backward_tape", "qs_backward_tape_batched", "qs_photons", "qs_photons_batched",
            "qs_photon_cdf", "qs_radiation_eval",
            "qs_radiation_derivs", "qs_sync_status",
-           "qs_set_profiling", "qs_last_timings", "qs_strerror", "qs_last_error",
-           "qs_abi_version"]
+           "qs_set_profiling", "qs_last_timings", "qs_tune", "qs_set_graphs", "qs_strerror",
+           "qs_last_error", "qs_abi_version"]
 
 _lib = None
 
@@ -185,6 +191,12 @@ def lib():
         L.qs_set_profiling.restype = ctypes.c_int
         L.qs_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.qs_last_timings.restype = ctypes.c_int
+        L.qs_tune.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                              ctypes.POINTER(Numerics), ctypes.POINTER(Bins), ctypes.c_char_p,
+                              ctypes.POINTER(Tuning), vp]
+        L.qs_tune.restype = ctypes.c_int
+        L.qs_set_graphs.argtypes = [vp, ctypes.c_int]
+        L.qs_set_graphs.restype = ctypes.c_int
         L.qs_strerror.argtypes = [ctypes.c_int]
         L.qs_strerror.restype = ctypes.c_char_p
         L.qs_last_error.argtypes = [vp]

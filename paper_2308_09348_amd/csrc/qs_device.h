@@ -516,8 +516,9 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float d) {
 // ===========================================================================
 // Work items.  A launch covers n_shots shots; phase items are tiles of
 // kPhaseBlock consecutive samples of one shot (one sample per lane), deposit
-// items tiles of kDepTile samples.  Blocks take items from a counter; an
-// item's result does not depend on which block runs it, so the output is
+// items tiles of dep_tile samples (a multiple of kMomTile, the tile of the
+// moment partial sums).  Blocks take items from a counter; an item's result
+// does not depend on which block runs it, nor on dep_tile, so the output is
 // deterministic, and a shot gives the same bits alone or in a batch.
 // ===========================================================================
 __device__ __forceinline__ int find_shot(const ShotParams *shots, int n_shots, int64_t item,
@@ -730,13 +731,15 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Grid of resident blocks for a persistent work-queue kernel (never more
-// blocks than items).
-inline hipError_t resident_grid(const void *fn, int block, size_t lds, int64_t items, int *grid) {
+// blocks than items; at most cap blocks a CU when cap > 0).
+inline hipError_t resident_grid(const void *fn, int block, size_t lds, int64_t items, int *grid,
+                                int cap = 0) {
     int device = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
     if (e != hipSuccess) return e;
+    if (cap > 0 && per_cu > cap) per_cu = cap;
     int64_t g = (int64_t)(per_cu < 1 ? 1 : per_cu) * ncu;
     if (g > items) g = items;
     *grid = (int)(g < 1 ? 1 : g);

@@ -24,7 +24,7 @@
 
 namespace qs {
 
-// One block per deposit tile (kDepTile samples of one shot).  Dynamic LDS:
+// One block per deposit tile (dep_tile samples of one shot).  Dynamic LDS:
 // the node weights of the tile's shot, when that shot asks for them.
 __global__ __launch_bounds__(kDepBlock) void interp_kernel(BatchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kDepBlock) void interp_kernel(BatchParams P) {
         __syncthreads();
     }
     const SampleState &nd = P.nst;
-    const int64_t i0 = (item - sp.ditem0) * kDepTile;
-    const int64_t i1 = i0 + kDepTile < sp.n_samples ? i0 + kDepTile : sp.n_samples;
+    const int64_t i0 = (item - sp.ditem0) * P.dep_tile;
+    const int64_t i1 = i0 + P.dep_tile < sp.n_samples ? i0 + P.dep_tile : sp.n_samples;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double g0, thx, thy, S0;
         Path<double> pd;

@@ -47,7 +47,10 @@ enum {
 
 constexpr int kPhaseBlock = 256;  // one phase work item = kPhaseBlock samples of one shot
 constexpr int kDepBlock = 256;
-constexpr int kDepTile = 4096;    // one deposit work item = kDepTile samples of one shot
+constexpr int kDepTile = 4096;    // default deposit work item: kDepTile samples of one shot
+// Moment partial sums are kept per tile of kMomTile samples whatever the
+// deposit work item (a multiple of it), so the moments do not depend on it.
+constexpr int kMomTile = 1024;
 constexpr int kPartials = P_N + 1;  // moment sums + chi max per deposit item
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
@@ -79,6 +82,7 @@ struct ShotParams {
     int64_t state_off;   // index of its first sample state
     int64_t item0;       // its first phase work item
     int64_t ditem0;      // its first deposit work item
+    int64_t mtile0;      // its first moment tile (kMomTile samples each)
     int64_t hist_off;    // its first histogram word in the accumulators
     // bins
     int32_t n_e, n_th, n_a, pad2;
@@ -158,9 +162,13 @@ struct BatchParams {
     float ellf, two_over_aSf, Kf, CDf, psi0f, hf, chi_fp64, pad0;
     int32_t n_steps, n_shots, deposit;
     int32_t any_mode;  // some shot uses a higher transverse mode
+    int32_t dep_tile;   // samples of one deposit work item (a tuning choice)
+    int32_t phase_cap;  // resident phase blocks per CU at most (0: all that fit)
+    int32_t dep_cap;    // resident deposit blocks per CU at most (0: all that fit)
+    int32_t pad1;
     uint32_t key0, key1;
     double ksig_bins, c_theta;
-    int64_t n_items, n_ditems;
+    int64_t n_items, n_ditems, n_mtiles;
     const ShotParams *shots;
     const ShotOut *outs;
     const float *rad32;   // [kCells32 * 16]
@@ -181,7 +189,7 @@ struct BatchParams {
     unsigned int *chimax_bits;     // [n_shots]
     int *flags;                    // [n_shots]
     unsigned int *queue;           // [2]: phase and deposit work counters
-    double *partials;              // [n_ditems][kPartials]; adjoint: [n_items][kGradParams]
+    double *partials;              // [n_mtiles][kPartials]; adjoint: [n_items][kGradParams]
 };
 
 // ---- launchers (qs_kernels.hip) -------------------------------------------

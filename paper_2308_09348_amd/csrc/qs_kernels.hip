@@ -356,95 +356,99 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
         for (int k = threadIdx.x; k < nc; k += blockDim.x) ce[k] = 0u;
         __syncthreads();
 
-        double acc[P_N];
-#pragma unroll
-        for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
-        float chimax = 0.0f;
         int flags = 0;
-        const int64_t i0 = (item - sp.ditem0) * kDepTile;
-        const int64_t i1 = i0 + kDepTile < sp.n_samples ? i0 + kDepTile : sp.n_samples;
+        const int64_t i0 = (item - sp.ditem0) * P.dep_tile;
+        const int64_t i1 = i0 + P.dep_tile < sp.n_samples ? i0 + P.dep_tile : sp.n_samples;
         const float hfe = (float)(0.5 * sp.e_w), hft = (float)(0.5 * sp.th_w);
-        // every lane runs every round (the wavefront deposit needs them all)
-        for (int64_t base = i0; base < i1; base += blockDim.x) {
-            const int64_t i = base + threadIdx.x;
-            LawLane le{-1, 0, -1, 0, 0.0f, 0.0f, 0.0f}, lt = le;
-            if (i < i1) {
-                const int64_t k = sp.state_off + i;
-                const double mu_f = P.st.mu[k], s2_f = P.st.s2[k], S0 = P.st.S0[k];
-                const double g0 = P.st.g0[k];
-                const double thx_m = 1e3 * P.st.thx[k], thy_m = 1e3 * P.st.thy[k];
-                const float cmx = P.st.cmx[k];
-                if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
-                    flags |= kFlagNonFinite;  // also raised by the phase kernel
-                } else {
-                    chimax = fmaxf(chimax, cmx);
-                    // Sec. 5.2: the direction is kept, the stochastic broadening
-                    // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
-                    const double sigf = sqrt(fmax(s2_f, 0.0));
-                    const double a_eff = sp.a0 * S0;
-                    const double sigth =
-                        1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
-                    le = law_setup(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e);
-                    lt = law_setup(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w,
-                                   sp.n_th);
-                    {
-                        int ka = (int)floor(S0 * (double)sp.n_a);
-                        ka = min(max(ka, 0), sp.n_a - 1);
-                        atomicAdd(&ca[ka], 1u);
-                    }
-                    const double de = mu_f - sp.gamma0;
-                    acc[P_S1E] += de;
-                    acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
-                    acc[P_S1X] += thx_m;
-                    acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
-                    acc[P_S1Y] += thy_m;
-                    acc[P_S2Y] += thy_m * thy_m;
-                    acc[P_SAEFF] += a_eff;
-                    acc[P_SRAD] += 1.0 - mu_f / g0;
-                    acc[P_SSIGF] += sigf;
+        for (int64_t t0 = i0; t0 < i1; t0 += kMomTile) {
+            const int64_t t1 = t0 + kMomTile < i1 ? t0 + kMomTile : i1;
+            double acc[P_N];
+#pragma unroll
+            for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
+            float chimax = 0.0f;
+            // every lane runs every round (the wavefront deposit needs them all)
+            for (int64_t base = t0; base < t1; base += blockDim.x) {
+                const int64_t i = base + threadIdx.x;
+                LawLane le{-1, 0, -1, 0, 0.0f, 0.0f, 0.0f}, lt = le;
+                if (i < i1) {
+                    const int64_t k = sp.state_off + i;
+                    const double mu_f = P.st.mu[k], s2_f = P.st.s2[k], S0 = P.st.S0[k];
+                    const double g0 = P.st.g0[k];
+                    const double thx_m = 1e3 * P.st.thx[k], thy_m = 1e3 * P.st.thy[k];
+                    const float cmx = P.st.cmx[k];
+                    if (!(mu_f > 0.0) || !isfinite(mu_f) || !isfinite(s2_f)) {
+                        flags |= kFlagNonFinite;  // also raised by the phase kernel
+                    } else {
+                        chimax = fmaxf(chimax, cmx);
+                        // Sec. 5.2: the direction is kept, the stochastic broadening
+                        // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
+                        const double sigf = sqrt(fmax(s2_f, 0.0));
+                        const double a_eff = sp.a0 * S0;
+                        const double sigth =
+                            1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
+                        le = law_setup(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e);
+                        lt = law_setup(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w,
+                                       sp.n_th);
+                        {
+                            int ka = (int)floor(S0 * (double)sp.n_a);
+                            ka = min(max(ka, 0), sp.n_a - 1);
+                            atomicAdd(&ca[ka], 1u);
+                        }
+                        const double de = mu_f - sp.gamma0;
+                        acc[P_S1E] += de;
+                        acc[P_S2E] += fma(de, de, fmax(s2_f, 0.0));
+                        acc[P_S1X] += thx_m;
+                        acc[P_S2X] += fma(thx_m, thx_m, sigth * sigth);
+                        acc[P_S1Y] += thy_m;
+                        acc[P_S2Y] += thy_m * thy_m;
+                        acc[P_SAEFF] += a_eff;
+                        acc[P_SRAD] += 1.0 - mu_f / g0;
+                        acc[P_SSIGF] += sigf;
 
-                    if (so.samples != nullptr && i % so.rec_stride == 0 &&
-                        i / so.rec_stride < so.rec_n) {
-                        double *r = so.samples + (i / so.rec_stride) * 11;
-                        r[0] = mu_f;
-                        r[1] = s2_f;
-                        r[2] = thx_m;
-                        r[3] = thy_m;
-                        r[4] = sigth;
-                        r[5] = a_eff;
-                        r[6] = cmx;
-                        r[7] = g0;
-                        r[8] = 0.0;
-                        r[9] = 0.0;
-                        r[10] = 0.0;
+                        if (so.samples != nullptr && i % so.rec_stride == 0 &&
+                            i / so.rec_stride < so.rec_n) {
+                            double *r = so.samples + (i / so.rec_stride) * 11;
+                            r[0] = mu_f;
+                            r[1] = s2_f;
+                            r[2] = thx_m;
+                            r[3] = thy_m;
+                            r[4] = sigth;
+                            r[5] = a_eff;
+                            r[6] = cmx;
+                            r[7] = g0;
+                            r[8] = 0.0;
+                            r[9] = 0.0;
+                            r[10] = 0.0;
+                        }
                     }
                 }
+                wave_deposit(le, sp.e_w, hfe, Qe, ce);
+                wave_deposit(lt, sp.th_w, hft, Qt, ct);
             }
-            wave_deposit(le, sp.e_w, hfe, Qe, ce);
-            wave_deposit(lt, sp.th_w, hft, Qt, ct);
-        }
 
-        // ---- item reduction of moments (fixed order) ----
+            // ---- moment tile reduction (fixed order) ----
 #pragma unroll
-        for (int m = 0; m < P_N; ++m) {
-            const double v = wave_sum(acc[m]);
-            if (lane == 0) red[wid][m] = v;
+            for (int m = 0; m < P_N; ++m) {
+                const double v = wave_sum(acc[m]);
+                if (lane == 0) red[wid][m] = v;
+            }
+            const float wm = wave_max(chimax);
+            if (lane == 0) redmax[wid] = wm;
+            __syncthreads();
+            double *part = P.partials + (size_t)(sp.mtile0 + t0 / kMomTile) * kPartials;
+            if (threadIdx.x < P_N) {
+                double sum = 0.0;
+                for (int w = 0; w < kDepBlock / 64; ++w) sum += red[w][threadIdx.x];
+                part[threadIdx.x] = sum;
+            }
+            if (threadIdx.x == 0) {
+                float m = 0.0f;
+                for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
+                part[P_N] = m;
+            }
+            __syncthreads();  // red is rewritten by the next tile
         }
-        const float wm = wave_max(chimax);
-        if (lane == 0) redmax[wid] = wm;
         if (flags) atomicOr(&P.flags[s], flags);
-        __syncthreads();
-        double *part = P.partials + (size_t)item * kPartials;
-        if (threadIdx.x < P_N) {
-            double sum = 0.0;
-            for (int w = 0; w < kDepBlock / 64; ++w) sum += red[w][threadIdx.x];
-            part[threadIdx.x] = sum;
-        }
-        if (threadIdx.x == 0) {
-            float m = 0.0f;
-            for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
-            part[P_N] = m;
-        }
         unsigned long long *G = P.hist + sp.hist_off;
         flush_edges(Qe, ce, sp.n_e, G, wsum);
         flush_edges(Qt, ct, sp.n_th, G + nh_e, wsum);
@@ -455,20 +459,20 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
 }
 
 // ===========================================================================
-// Finalize: one block per shot, fixed-order reduction of its item partials
+// Finalize: one block per shot, fixed-order reduction of its moment tiles
 // ===========================================================================
 __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
     const int s = blockIdx.x;
     const ShotParams &sp = P.shots[s];
     const ShotOut &so = P.outs[s];
-    const int64_t nd = (sp.n_samples + kDepTile - 1) / kDepTile;
+    const int64_t nd = (sp.n_samples + kMomTile - 1) / kMomTile;
     __shared__ double sums[kPartials];
     __shared__ double tree[256];
     // each column: thread t sums items t, t + 256, ... then a fixed tree
     for (int m = 0; m < kPartials; ++m) {
         double acc = 0.0;
         for (int64_t b = threadIdx.x; b < nd; b += blockDim.x) {
-            const double v = P.partials[(size_t)(sp.ditem0 + b) * kPartials + m];
+            const double v = P.partials[(size_t)(sp.mtile0 + b) * kPartials + m];
             acc = m == P_N ? fmax(acc, v) : acc + v;
         }
         tree[threadIdx.x] = acc;
@@ -596,7 +600,7 @@ hipError_t launch_phase(const BatchParams &p, const float *env32, const double *
     const void *fn = select_phase(prec, rr, amp, p.any_mode != 0);
     if (!fn) return hipErrorInvalidValue;
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid, p.phase_cap);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     const float *e32 = env32;
@@ -620,7 +624,7 @@ hipError_t launch_phase_nodes(const BatchParams &p, const float *env32, const do
     if (prec == PREC_F32MIX) fn = node_ptr<PREC_F32MIX, true>();
     if (!fn) return hipErrorInvalidValue;
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid, p.phase_cap);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     const float *e32 = env32;
@@ -639,7 +643,7 @@ hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t 
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int grid = 0;
-    e = resident_grid(fn, kDepBlock, lds, p.n_ditems, &grid);
+    e = resident_grid(fn, kDepBlock, lds, p.n_ditems, &grid, p.dep_cap);
     if (e != hipSuccess) return e;
     deposit_kernel<<<grid, kDepBlock, lds, s>>>(p);
     return hipGetLastError();

@@ -61,6 +61,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Bins) == 4 * 4 + 8 * 4
     assert ctypes.sizeof(_lib.Outputs) == 8 * 8
     assert ctypes.sizeof(_lib.NodeGrid) == 4 * 2 + 8 * 2
+    assert ctypes.sizeof(_lib.Tuning) == 4 * 4 + 8 * 2
 
 
 def test_null_context_is_rejected_without_a_device():
@@ -70,4 +71,6 @@ def test_null_context_is_rejected_without_a_device():
     assert L.qs_forward_factorised(None, None, None, None, None, None, None,
                                    None) == _lib.QS_EINVAL
     assert L.qs_create(None, 0) == _lib.QS_EINVAL
+    assert L.qs_tune(None, None, None, None, None, None, None, None) == _lib.QS_EINVAL
+    assert L.qs_set_graphs(None, 1) == _lib.QS_EINVAL
     L.qs_destroy(None)
