@@ -23,6 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = "sample·phase-steps/s (fwd, fwd+adjoint), batched spectra/s; % FP32 VALU peak"
 UNIT = "sample·phase-steps/s"
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+# launch choices found by the tuner on this machine type, one line per class
+DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_2308_09348_amd", "tune_cache.txt")
 
 # Algorithmic floating-point operations per sample-step of the phase loop
 # (FMA = 2, each exp / sqrt / reciprocal = 1), counted from the method's
@@ -82,6 +84,9 @@ def parse():
                     help="steps of the plane-wave reconstruction leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--tune-cache", default=os.environ.get("QS_TUNE_CACHE", DEFAULT_TUNE_CACHE),
+                    help="launch-tuning cache file of the batched leg (read, else timed and "
+                         "appended)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -291,6 +296,8 @@ def main():
     n, N = params["n_samples"], params["n_steps"]
     ctx = qs.Context(0)
     dev = torch.device("cuda", 0)
+    # launch choices for this class (read from the cache, else timed there)
+    tuning = ctx.tune(params, cache_path=args.tune_cache)
     out = ctx.forward(params)  # allocates the outputs and the context scratch
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
@@ -328,6 +335,7 @@ def main():
                    "n_samples": n, "n_steps": N, "rr_model": params["rr_model"],
                    "amp_mode": params["amp_mode"], "precision": args.precision,
                    "chi_fp64": args.chi_fp64, "leg": "fwd"},
+        "tuning": tuning,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
                      "traffic": profiled_traffic() if args.precision == "fp32" else None,
@@ -337,10 +345,14 @@ def main():
                                                              params["amp_mode"])]},
     }
     if args.batched_steps > 0:
-        # batched leg: 4096 shots of uneven size in one launch
+        # batched leg: 4096 shots of uneven size in one launch, with the launch
+        # choices of the tuner (cached per device and launch class) and the
+        # launch replayed from a HIP graph
         shots = workloads.batched_shots()
         batch = ctx.prepare_batch(shots)
-        ctx.run_batch(batch)  # scratch allocation and warm-up
+        tuning = ctx.tune(batch, cache_path=args.tune_cache)
+        ctx.set_graphs(True)
+        ctx.run_batch(batch)  # scratch allocation, graph capture and warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.batched_steps):
@@ -358,7 +370,9 @@ def main():
             "n_shots": len(shots), "n_samples": n_tot, "n_steps": shots[0]["n_steps"],
             "steps": args.batched_steps, "ms_per_batch": 1e3 * dt,
             "spectra_per_s": len(shots) / dt,
-            "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt}
+            "sample_steps_per_s": n_tot * shots[0]["n_steps"] / dt,
+            "tuning": tuning, "hip_graph": True}
+        ctx.set_graphs(False)
     if args.factorised_steps > 0:
         line["factorised"] = factorised_leg(ctx, workloads, torch, args.factorised_steps)
     if args.adjoint_steps > 0:

@@ -450,23 +450,25 @@ typedef struct qs_tuning {
 /* Tune the forward launches of one class (batching of the high-repetition-
  * rate use in the abstract and the conclusions: many shots, each launch
  * sized to the machine).  The class is (n_steps, rr_model, amp_mode,
- * deposit, precision with its FP64 steps, histogram words n_e + n_th + n_a
- * + 4, floor(log2 n_samples), floor(log2 shots)); it is taken from num,
- * bins and one shot (laser, beam, num->n_samples).  The call times forward
- * passes of that shot on `stream` under each candidate (phase blocks per CU
- * in {all, 3, 2}, then deposit tile in {1024, 2048, 4096, 8192} x deposit
- * blocks per CU in {all, 4, 2}), keeps the fastest for later launches of the
- * class on this context and, when cache_path is not NULL, appends it to that
- * text file as one line keyed by the device (architecture and compute-unit
- * count) and the class.  A cache line for this device and class is used
- * instead of timing.  `out` (host, optional) receives the choice.  Blocks
- * until the trial passes end; allocates its own trial outputs.  Launches of
- * other classes keep the defaults (deposit tile 4096, all resident blocks).
- * Errors: QS_EINVAL (as qs_forward; a cache file that cannot be appended
- * to), QS_ENOMEM, QS_EDEVICE. */
-qs_status qs_tune(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
-                  const qs_numerics *num, const qs_bins *bins, const char *cache_path,
-                  qs_tuning *out, void *stream);
+ * deposit, precision with its FP64 steps, the largest histogram word count
+ * n_e + n_th + n_a + 4 of a shot, floor(log2 total samples), floor(log2
+ * n_shots)); it is taken from a batch given as to qs_forward_batched
+ * (n_shots >= 1 entries in lasers, beams, n_samples and bins; num->n_samples
+ * is ignored).  The call times forward launches of that batch on `stream`
+ * under each candidate (phase blocks per CU in {all, 3, 2}, then deposit
+ * tile in {1024, 2048, 4096, 8192} x deposit blocks per CU in {all, 4, 2}),
+ * keeps the fastest for later launches of the class on this context and,
+ * when cache_path is not NULL, appends it to that text file as one line
+ * keyed by the device (architecture and compute-unit count) and the class.
+ * A cache line for this device and class is used instead of timing.  `out`
+ * (host, optional) receives the choice.  Blocks until the trial launches
+ * end; allocates its own trial outputs.  Launches of other classes keep the
+ * defaults (deposit tile 4096, all resident blocks).
+ * Errors: QS_EINVAL (as qs_forward_batched; a cache file that cannot be
+ * appended to), QS_EUNSUPPORTED, QS_ENOMEM, QS_EDEVICE. */
+qs_status qs_tune(qs_ctx *ctx, int32_t n_shots, const qs_laser *lasers, const qs_beam *beams,
+                  const int64_t *n_samples, const qs_numerics *num, const qs_bins *bins,
+                  const char *cache_path, qs_tuning *out, void *stream);
 
 /* Enable (on != 0) or disable HIP graphs for qs_forward and
  * qs_forward_batched on this context: the device work of a launch after the

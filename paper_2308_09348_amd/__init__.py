@@ -410,18 +410,21 @@ class Context:
         torch.cuda.synchronize(dev)
         return out
 
-    def tune(self, params, cache_path=None, stream=None):
-        """Time the launch choices for the class of `params` (qs_tune) and keep
-        the fastest for later launches of that class on this context; with
-        cache_path, read the choice from / append it to that text file.
-        Returns the choice as a dict."""
+    def tune(self, shots, cache_path=None, stream=None):
+        """Time the launch choices for the launch class of `shots` (one
+        parameter dictionary, a list of them, or a prepared batch; qs_tune)
+        and keep the fastest for later launches of that class on this
+        context; with cache_path, read the choice from / append it to that
+        text file.  Returns the choice as a dict."""
         torch = _torch()
-        la, be, nu, bi = _lib.structs(params)
+        if isinstance(shots, dict):
+            shots = [shots]
+        b = shots if isinstance(shots, _Batch) else self.prepare_batch(shots)
         stream = stream or torch.cuda.current_stream(torch.device("cuda", self.device))
         t = _lib.Tuning()
         path = None if cache_path is None else os.fsencode(cache_path)
-        st = _lib.lib().qs_tune(self._ptr, ctypes.byref(la), ctypes.byref(be), ctypes.byref(nu),
-                                ctypes.byref(bi), path, ctypes.byref(t),
+        st = _lib.lib().qs_tune(self._ptr, b.n, b.lasers, b.beams, b.ns, ctypes.byref(b.nu),
+                                b.bins, path, ctypes.byref(t),
                                 ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())

@@ -191,9 +191,9 @@ def lib():
         L.qs_set_profiling.restype = ctypes.c_int
         L.qs_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.qs_last_timings.restype = ctypes.c_int
-        L.qs_tune.argtypes = [vp, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
-                              ctypes.POINTER(Numerics), ctypes.POINTER(Bins), ctypes.c_char_p,
-                              ctypes.POINTER(Tuning), vp]
+        L.qs_tune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Numerics),
+                              ctypes.POINTER(Bins), ctypes.c_char_p, ctypes.POINTER(Tuning), vp]
         L.qs_tune.restype = ctypes.c_int
         L.qs_set_graphs.argtypes = [vp, ctypes.c_int]
         L.qs_set_graphs.restype = ctypes.c_int

@@ -287,8 +287,9 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
 qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                       const qs_node_grid *G, const qs_outputs *O, hipStream_t s);
-qs_status tune_impl(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
-                    const qs_bins *H, const char *path, qs_tuning *out, hipStream_t s);
+qs_status tune_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                    const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                    const char *path, qs_tuning *out, hipStream_t s);
 
 }  // namespace
 
@@ -543,11 +544,15 @@ qs_status qs_radiation_derivs(qs_ctx *c, int32_t precision, int64_t n, const dou
     return QS_OK;
 }
 
-qs_status qs_tune(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
-                  const qs_bins *H, const char *cache_path, qs_tuning *out, void *stream) {
-    if (!c || !L || !B || !N || !H) return set_err(c, "null argument"), QS_EINVAL;
+qs_status qs_tune(qs_ctx *c, int32_t n_shots, const qs_laser *lasers, const qs_beam *beams,
+                  const int64_t *n_samples, const qs_numerics *N, const qs_bins *bins,
+                  const char *cache_path, qs_tuning *out, void *stream) {
+    if (!c || !lasers || !beams || !n_samples || !N || !bins)
+        return set_err(c, "null argument"), QS_EINVAL;
+    if (n_shots < 1 || n_shots > (1 << 20)) return set_err(c, "n_shots out of range"), QS_EINVAL;
     DeviceGuard guard(c->device);
-    return tune_impl(c, L, B, N, H, cache_path, out, reinterpret_cast<hipStream_t>(stream));
+    return tune_impl(c, n_shots, lasers, beams, n_samples, N, bins, cache_path, out,
+                     reinterpret_cast<hipStream_t>(stream));
 }
 
 qs_status qs_set_graphs(qs_ctx *c, int on) {
@@ -1355,17 +1360,27 @@ bool read_tune_cache(const char *path, const std::string &tag, const TuneKey &ke
 // the profiling events around the phase and deposit kernels; keeps the
 // fastest, installs it for launches of the same class and appends it to the
 // cache file.  Every candidate gives the same results (moment tiles are fixed).
-qs_status tune_impl(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_numerics *N,
-                    const qs_bins *H, const char *path, qs_tuning *out, hipStream_t s) {
+qs_status tune_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
+                    const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
+                    const char *path, qs_tuning *out, hipStream_t s) {
     qs_status st = validate_numerics(c, N);
     if (st != QS_OK) return st;
-    if ((st = validate_shot(c, L, B, H, N->n_samples)) != QS_OK) return st;
+    int max_nh = 0;
+    int64_t total = 0;
+    size_t nbuf = 0;
+    for (int k = 0; k < n_shots; ++k) {
+        if ((st = validate_shot(c, &L[k], &B[k], &H[k], n_samples[k])) != QS_OK) return st;
+        const int nh = H[k].n_e + 2 + H[k].n_th + 2 + H[k].n_a;
+        max_nh = std::max(max_nh, nh);
+        total += n_samples[k];
+        nbuf += (size_t)nh + QS_M_N;
+    }
     int prec = qs::PREC_F32;
     if (N->precision == QS_PREC_FP64)
         prec = qs::PREC_F64;
     else if (N->rr_model == QS_RR_QUANTUM && N->chi_fp64 > 0)
         prec = qs::PREC_F32MIX;
-    const TuneKey key = tune_key(N, prec, H->n_e + 2 + H->n_th + 2 + H->n_a, N->n_samples, 1);
+    const TuneKey key = tune_key(N, prec, max_nh, total, n_shots);
     const std::string tag = device_tag(c->device);
     qs_tuning res;
     std::memset(&res, 0, sizeof(res));
@@ -1386,20 +1401,25 @@ qs_status tune_impl(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_num
     // outputs of the trial passes
     double *buf = nullptr;
     int32_t *status = nullptr;
-    const size_t nbuf = (size_t)(H->n_e + 2) + (H->n_th + 2) + H->n_a + QS_M_N;
     hipError_t e = hipMalloc(&buf, nbuf * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&status, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&status, sizeof(int32_t) * n_shots);
     if (e != hipSuccess) {
         (void)hipFree(buf);
         return hip_fail(c, e, "tuning buffers");
     }
-    qs_outputs O;
-    std::memset(&O, 0, sizeof(O));
-    O.energy_hist = buf;
-    O.angle_hist = buf + H->n_e + 2;
-    O.a0eff_hist = O.angle_hist + H->n_th + 2;
-    O.moments = O.a0eff_hist + H->n_a;
-    O.status = status;
+    std::vector<qs_outputs> O(n_shots);
+    {
+        double *p = buf;
+        for (int k = 0; k < n_shots; ++k) {
+            std::memset(&O[k], 0, sizeof(qs_outputs));
+            O[k].energy_hist = p;
+            O[k].angle_hist = p + H[k].n_e + 2;
+            O[k].a0eff_hist = O[k].angle_hist + H[k].n_th + 2;
+            O[k].moments = O[k].a0eff_hist + H[k].n_a;
+            O[k].status = status + k;
+            p = O[k].moments + QS_M_N;
+        }
+    }
     const bool prof = c->profiling, graphs = c->graphs;
     struct Restore {
         qs_ctx *c;
@@ -1418,13 +1438,15 @@ qs_status tune_impl(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_num
     if ((st = qs_set_profiling(c, 1)) != QS_OK) return st;
     c->graphs = false;
 
-    // one warm-up pass, then the best of two timed passes
+    // one warm-up launch, then the best of `reps` timed launches (two, or one
+    // when a launch takes more than 100 ms)
+    int reps = 2;
     auto trial = [&](const TuneEntry &t, double &phase_ms, double &dep_ms) -> qs_status {
         c->tune_forced = true;
         c->forced = t;
         phase_ms = dep_ms = 1e30;
-        for (int r = 0; r < 3; ++r) {
-            qs_status q = forward_impl(c, 1, L, B, &N->n_samples, N, H, &O, nullptr, s);
+        for (int r = 0; r <= reps; ++r) {
+            qs_status q = forward_impl(c, n_shots, L, B, n_samples, N, H, O.data(), nullptr, s);
             if (q != QS_OK) return q;
             hipError_t he = hipEventSynchronize(c->ev[5]);
             float tp = 0.0f, td = 0.0f;
@@ -1434,6 +1456,8 @@ qs_status tune_impl(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_num
             if (r > 0) {
                 phase_ms = std::min(phase_ms, (double)tp);
                 dep_ms = std::min(dep_ms, (double)td);
+            } else if (tp + td > 100.0f) {
+                reps = 1;
             }
         }
         return QS_OK;

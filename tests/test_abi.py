@@ -71,6 +71,6 @@ def test_null_context_is_rejected_without_a_device():
     assert L.qs_forward_factorised(None, None, None, None, None, None, None,
                                    None) == _lib.QS_EINVAL
     assert L.qs_create(None, 0) == _lib.QS_EINVAL
-    assert L.qs_tune(None, None, None, None, None, None, None, None) == _lib.QS_EINVAL
+    assert L.qs_tune(None, 1, None, None, None, None, None, None, None, None) == _lib.QS_EINVAL
     assert L.qs_set_graphs(None, 1) == _lib.QS_EINVAL
     L.qs_destroy(None)

@@ -128,3 +128,26 @@ def test_deposit_tile_leaves_results_unchanged(qs, tmp_path, tile):
     assert re.match(r"qscatter-tune-1 \S+/\d+ ", cache.read_text())
     for c in (plain, probe, forced):
         c.close()
+
+
+def test_tuner_on_a_batch(qs, tmp_path):
+    """The class of a batch (shot count and total samples) is tuned as a
+    whole; the tuned batched launch, replayed from a graph, gives the bits of
+    the plain one."""
+    shots = [_case(n_samples=n, a0=a) for n, a in ((3000, 15.0), (20000, 50.0), (9000, 80.0),
+                                                   (1, 30.0))]
+    plain = qs.Context(0)
+    ref = [_np(o) for o in plain.forward_batched(shots)]
+    tuned = qs.Context(0)
+    cache = tmp_path / "tune.txt"
+    t = tuned.tune(shots, cache_path=str(cache))
+    assert not t["from_cache"] and t["dep_tile"] in (1024, 2048, 4096, 8192)
+    key = cache.read_text().split()
+    assert key[9] == "2"  # floor(log2 4 shots)
+    tuned.set_graphs(True)
+    for r in range(2):
+        got = [_np(o) for o in tuned.forward_batched(shots)]
+        for k in range(len(shots)):
+            _same(got[k], ref[k], f"tuned batch, launch {r}, shot {k}")
+    plain.close()
+    tuned.close()
