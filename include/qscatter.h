@@ -51,6 +51,10 @@ enum { QS_RR_CLASSICAL = 0, QS_RR_QUANTUM = 1 };
 enum { QS_AMP_A0EFF = 0, QS_AMP_LOCAL = 1 };
 enum { QS_DEP_POINT = 0, QS_DEP_CIC = 1, QS_DEP_GAUSS = 2 };
 enum { QS_PREC_FP32 = 0, QS_PREC_FP64 = 1 };
+/* qs_numerics.flags: QS_VALIDATE_FP64 shadows every shadow_stride-th sample
+ * of an FP32 pass with the FP64 integration and reports the differences in
+ * the moments QS_M_SHADOW_N .. QS_M_ERR_MEAN_G. */
+enum { QS_VALIDATE_FP64 = 1 };
 enum { QS_PROFILE_GAUSS = 0, QS_PROFILE_FLAT = 1 };
 /* Transverse laser modes, amplitude only (the wave's phase, Gouy phase and
  * curvature neglected as for eq. a0eff), scaled to a peak of 1 in the focal
@@ -117,6 +121,10 @@ typedef struct qs_numerics {
                                  FP64 when any of its samples has chi above
                                  this at the step start; <= 0 disables        */
     double c_theta;           /* pre-factor of the Sec. 5.2 divergence law    */
+    int32_t flags;            /* QS_VALIDATE_FP64 or 0                        */
+    int32_t shadow_stride;    /* with QS_VALIDATE_FP64: samples i with
+                                 i % shadow_stride == 0 are shadowed; 0 means
+                                 64; 1 .. 2^20                               */
 } qs_numerics;
 
 /* Histogram windows.  Energy and angle histograms have n bins plus
@@ -144,6 +152,15 @@ enum {
     QS_M_MAX_CHI,       /* largest chi met at a step start                      */
     QS_M_RAD_FRAC,      /* mean radiated energy fraction                        */
     QS_M_MEAN_SIGF,     /* mean beamlet energy spread sigma_f                   */
+    /* FP64 shadow of an FP32 pass (QS_VALIDATE_FP64; zero otherwise and for
+     * FP64 passes): over the shadowed samples, the final state of this pass
+     * (mu32, sig32) against the FP64 integration of the same samples
+     * (mu64, sig64), sig = sqrt(max(sig2, 0)). */
+    QS_M_SHADOW_N,      /* shadowed samples                                     */
+    QS_M_ERR_MU_MAX,    /* max |mu32 - mu64| / mu64                             */
+    QS_M_ERR_MU_MEAN,   /* mean (mu32 - mu64) / mu64 (signed)                   */
+    QS_M_ERR_SIG_MAX,   /* max |sig32 - sig64| / mu64                           */
+    QS_M_ERR_MEAN_G,    /* mean (mu32 - mu64): the FP32 bias of QS_M_MEAN_G     */
     QS_M_N = 16
 };
 

@@ -21,6 +21,9 @@ PROFILE = {"gauss": 0, "flat": 1}
 MODE = {"gauss": 0, "hg": 1, "lg": 2}
 
 M_N = 16
+# FP64 shadow of an FP32 pass (qs_numerics.flags) and its moment fields
+VALIDATE_FP64 = 1
+(M_SHADOW_N, M_ERR_MU_MAX, M_ERR_MU_MEAN, M_ERR_SIG_MAX, M_ERR_MEAN_G) = range(11, 16)
 S_N = 11
 (M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, M_MEAN_AEFF,
  M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF) = range(11)
@@ -49,7 +52,8 @@ class Numerics(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("rr_model", ctypes.c_int32),
                 ("amp_mode", ctypes.c_int32), ("deposit", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("kernel_sigma_bins", ctypes.c_double),
-                ("chi_fp64", ctypes.c_double), ("c_theta", ctypes.c_double)]
+                ("chi_fp64", ctypes.c_double), ("c_theta", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("shadow_stride", ctypes.c_int32)]
 
 
 class Bins(ctypes.Structure):
@@ -238,7 +242,9 @@ def structs(params):
                   deposit=_enum(DEPOSIT, params["deposit"]),
                   precision=_enum(PRECISION, params.get("precision", "fp32")),
                   kernel_sigma_bins=params["kernel_sigma_bins"],
-                  chi_fp64=params.get("chi_fp64", 0.0), c_theta=params["c_theta"])
+                  chi_fp64=params.get("chi_fp64", 0.0), c_theta=params["c_theta"],
+                  flags=VALIDATE_FP64 if params.get("validate_fp64") else 0,
+                  shadow_stride=int(params.get("shadow_stride", 0)))
     bi = Bins(n_e=params["n_e"], n_th=params["n_th"], n_a=params["n_a"], reserved0=0,
               e_lo=params["e_lo"], e_hi=params["e_hi"], th_lo_mrad=params["th_lo_mrad"],
               th_hi_mrad=params["th_hi_mrad"])

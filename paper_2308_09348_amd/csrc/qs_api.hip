@@ -242,6 +242,9 @@ qs_status validate_numerics(qs_ctx *c, const qs_numerics *N) {
         return set_err(c, "unknown deposit"), QS_EINVAL;
     if (N->precision != QS_PREC_FP32 && N->precision != QS_PREC_FP64)
         return set_err(c, "unknown precision"), QS_EINVAL;
+    if ((N->flags & ~QS_VALIDATE_FP64) != 0) return set_err(c, "unknown flags"), QS_EINVAL;
+    if (N->shadow_stride < 0 || N->shadow_stride > (1 << 20))
+        return set_err(c, "shadow_stride must be in [0, 2^20]"), QS_EINVAL;
     return QS_OK;
 }
 
@@ -763,6 +766,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         p.mode_inv_normf = (float)p.mode_inv_norm;
         if (p.mode != QS_MODE_GAUSS) bp.any_mode = 1;
         p.shot_word = N->shot + k;
+        p.draw_stride = 1;
         p.n_samples = n_samples[k];
         p.state_off = off;
         p.item0 = item;
@@ -812,14 +816,38 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         for (int k = 0; k < n_shots; ++k)
             if (L[k].mode != QS_MODE_GAUSS)
                 return set_err(c, "derivatives are for the Gaussian mode only"), QS_EUNSUPPORTED;
+    // FP64 shadow of an FP32 pass: a second view of the shot table (after the
+    // outputs) integrates every shadow_stride-th sample in FP64
+    const bool shadow = N && (N->flags & QS_VALIDATE_FP64) && N->precision == QS_PREC_FP32 &&
+                        !tape;
     Batch b;
-    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotOut), b)) != QS_OK)
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H,
+                            sizeof(qs::ShotOut) + (shadow ? sizeof(qs::ShotParams) : 0), b)) !=
+        QS_OK)
         return st;
     if (qs::deposit_lds_bytes(b.max_nh) > 160 * 1024)
         return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
     DeviceGuard guard(c->device);
     qs::BatchParams &bp = b.bp;
     qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(b.outs);
+    qs::ShotParams *sv = reinterpret_cast<qs::ShotParams *>(b.outs + sizeof(qs::ShotOut) * n_shots);
+    int64_t sh_total = 0, sh_items = 0;
+    if (shadow) {
+        const int stride = N->shadow_stride > 0 ? N->shadow_stride : 64;
+        for (int k = 0; k < n_shots; ++k) {
+            qs::ShotParams &p = b.sp[k];
+            const int64_t ns = (n_samples[k] + stride - 1) / stride;
+            p.shadow_stride = stride;
+            p.shadow_off = sh_total;
+            sv[k] = p;
+            sv[k].draw_stride = stride;
+            sv[k].n_samples = ns;
+            sv[k].state_off = sh_total;
+            sv[k].item0 = sh_items;
+            sh_total += ns;
+            sh_items += (ns + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
+        }
+    }
     for (int k = 0; k < n_shots; ++k) {
         const qs_outputs &o = O[k];
         so[k] = qs::ShotOut{};
@@ -837,15 +865,19 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     const size_t nenv = (size_t)2 * N->n_steps + 1;
     const size_t arr = ((size_t)b.total * 8 + 255) / 256 * 256;
     const size_t arrf = ((size_t)b.total * 4 + 255) / 256 * 256;
+    const size_t sarr = ((size_t)sh_total * 8 + 255) / 256 * 256;
+    const size_t sarrf = ((size_t)sh_total * 4 + 255) / 256 * 256;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;
-    const size_t accum_words = 1 + flag_words + (size_t)b.hist_words;
+    // work counters (phase, deposit, shadow phase, unused), flags, histograms
+    const size_t accum_words = 2 + flag_words + (size_t)b.hist_words;
     if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
     if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_mtiles * qs::kPartials,
                    "moment partials")) != QS_OK)
         return st;
-    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf, "sample states")) != QS_OK)
+    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf + 6 * sarr + sarrf,
+                   "sample states")) != QS_OK)
         return st;
     if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
         return st;
@@ -862,9 +894,19 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     bp.st.thx = reinterpret_cast<double *>(c->states + 4 * arr);
     bp.st.thy = reinterpret_cast<double *>(c->states + 5 * arr);
     bp.st.cmx = reinterpret_cast<float *>(c->states + 6 * arr);
+    if (shadow) {
+        unsigned char *base = c->states + 6 * arr + arrf;
+        bp.sst.mu = reinterpret_cast<double *>(base);
+        bp.sst.s2 = reinterpret_cast<double *>(base + sarr);
+        bp.sst.S0 = reinterpret_cast<double *>(base + 2 * sarr);
+        bp.sst.g0 = reinterpret_cast<double *>(base + 3 * sarr);
+        bp.sst.thx = reinterpret_cast<double *>(base + 4 * sarr);
+        bp.sst.thy = reinterpret_cast<double *>(base + 5 * sarr);
+        bp.sst.cmx = reinterpret_cast<float *>(base + 6 * sarr);
+    }
     bp.queue = reinterpret_cast<unsigned int *>(c->accum);
-    bp.flags = reinterpret_cast<int *>(c->accum + 1);
-    bp.hist = c->accum + 1 + flag_words;
+    bp.flags = reinterpret_cast<int *>(c->accum + 2);
+    bp.hist = c->accum + 2 + flag_words;
     bp.partials = c->partials;
     bp.tape = tape;
     bp.tape_n = b.total;
@@ -893,6 +935,18 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         } else if ((e = qs::launch_phase(bp, c->env32, c->env64, b.prec, N->rr_model,
                                          N->amp_mode, q)) != hipSuccess) {
             return hip_fail(c, e, "phase kernel");
+        }
+        if (shadow && sh_items > 0) {
+            // the shadowed samples again in FP64 (their own work counter)
+            qs::BatchParams bs = bp;
+            bs.shots = reinterpret_cast<const qs::ShotParams *>(
+                c->shot_tab + (sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots);
+            bs.n_items = sh_items;
+            bs.st = bp.sst;
+            bs.queue = bp.queue + 2;
+            if ((e = qs::launch_phase(bs, c->env32, c->env64, qs::PREC_F64, N->rr_model,
+                                      N->amp_mode, q)) != hipSuccess)
+                return hip_fail(c, e, "shadow phase kernel");
         }
         if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
         if ((e = qs::launch_deposit(bp, b.max_nh, q)) != hipSuccess)

@@ -42,8 +42,14 @@ enum {
     P_SAEFF,    // sum a0,eff
     P_SRAD,     // sum 1 - mu_f / gamma0_i
     P_SSIGF,    // sum sigma_f
+    P_SHN,      // FP64 shadow: samples compared
+    P_SHMU,     //   sum (mu32 - mu64) / mu64
+    P_SHG,      //   sum (mu32 - mu64)
     P_N
 };
+// after the sums, the maxima of a moment tile: chi, the shadow's relative
+// energy and spread differences
+constexpr int kPMaxChi = P_N, kPMaxEmu = P_N + 1, kPMaxEsig = P_N + 2;
 
 constexpr int kPhaseBlock = 256;  // one phase work item = kPhaseBlock samples of one shot
 constexpr int kDepBlock = 256;
@@ -51,7 +57,7 @@ constexpr int kDepTile = 4096;    // default deposit work item: kDepTile samples
 // Moment partial sums are kept per tile of kMomTile samples whatever the
 // deposit work item (a multiple of it), so the moments do not depend on it.
 constexpr int kMomTile = 1024;
-constexpr int kPartials = P_N + 1;  // moment sums + chi max per deposit item
+constexpr int kPartials = P_N + 3;  // moment sums and maxima of a moment tile
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
 
@@ -84,6 +90,11 @@ struct ShotParams {
     int64_t ditem0;      // its first deposit work item
     int64_t mtile0;      // its first moment tile (kMomTile samples each)
     int64_t hist_off;    // its first histogram word in the accumulators
+    // FP64 shadow: samples i with i % shadow_stride == 0 have the FP64 state
+    // shadow_off + i / shadow_stride (shadow_stride 0: none); a shot view
+    // with draw_stride > 1 integrates samples draw_stride i of the shot
+    int64_t shadow_off;
+    int32_t shadow_stride, draw_stride;
     // bins
     int32_t n_e, n_th, n_a, pad2;
     double e_lo, e_w, th_lo, th_w;
@@ -184,6 +195,7 @@ struct BatchParams {
     int64_t tape_n;         // samples over the batch (tape field stride)
     SampleState st;
     SampleState nst;        // plane-wave reconstruction: final states of the nodes
+    SampleState sst;        // FP64 shadow states of an FP32 pass
     // accumulators (device scratch, cleared before each launch)
     unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
     unsigned int *chimax_bits;     // [n_shots]

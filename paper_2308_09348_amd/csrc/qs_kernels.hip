@@ -98,7 +98,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             g0 = sp.g_node_lo + (double)m * sp.g_node_step;  // rounded twice, as defined
         }
     } else {
-        draw_sample<MODES>(sp, P.key0, P.key1, i, g0, thx, thy, pd, S0);
+        draw_sample<MODES>(sp, P.key0, P.key1, i * sp.draw_stride, g0, thx, thy, pd, S0);
     }
     const double a0S0 = sp.a0 * S0;
 
@@ -335,6 +335,7 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
     __shared__ int64_t slot;
     __shared__ double red[kDepBlock / 64][P_N];
     __shared__ float redmax[kDepBlock / 64];
+    __shared__ double redsh[kDepBlock / 64][2];
     __shared__ unsigned int wsum[kDepBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (;;) {
@@ -366,6 +367,7 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
 #pragma unroll
             for (int m = 0; m < P_N; ++m) acc[m] = 0.0;
             float chimax = 0.0f;
+            double emu = 0.0, esig = 0.0;  // FP64 shadow: largest differences
             // every lane runs every round (the wavefront deposit needs them all)
             for (int64_t base = t0; base < t1; base += blockDim.x) {
                 const int64_t i = base + threadIdx.x;
@@ -404,6 +406,20 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
                         acc[P_SAEFF] += a_eff;
                         acc[P_SRAD] += 1.0 - mu_f / g0;
                         acc[P_SSIGF] += sigf;
+                        if (sp.shadow_stride > 0 && i % sp.shadow_stride == 0) {
+                            // the same sample integrated in FP64
+                            const int64_t q = sp.shadow_off + i / sp.shadow_stride;
+                            const double m64 = P.sst.mu[q];
+                            const double s64 = sqrt(fmax(P.sst.s2[q], 0.0));
+                            if (m64 > 0.0) {
+                                const double d = mu_f - m64;
+                                acc[P_SHN] += 1.0;
+                                acc[P_SHMU] += d / m64;
+                                acc[P_SHG] += d;
+                                emu = fmax(emu, fabs(d) / m64);
+                                esig = fmax(esig, fabs(sigf - s64) / m64);
+                            }
+                        }
 
                         if (so.samples != nullptr && i % so.rec_stride == 0 &&
                             i / so.rec_stride < so.rec_n) {
@@ -433,7 +449,12 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
                 if (lane == 0) red[wid][m] = v;
             }
             const float wm = wave_max(chimax);
-            if (lane == 0) redmax[wid] = wm;
+            const double we = wave_max(emu), ws = wave_max(esig);
+            if (lane == 0) {
+                redmax[wid] = wm;
+                redsh[wid][0] = we;
+                redsh[wid][1] = ws;
+            }
             __syncthreads();
             double *part = P.partials + (size_t)(sp.mtile0 + t0 / kMomTile) * kPartials;
             if (threadIdx.x < P_N) {
@@ -443,8 +464,15 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
             }
             if (threadIdx.x == 0) {
                 float m = 0.0f;
-                for (int w = 0; w < kDepBlock / 64; ++w) m = fmaxf(m, redmax[w]);
-                part[P_N] = m;
+                double e0 = 0.0, e1 = 0.0;
+                for (int w = 0; w < kDepBlock / 64; ++w) {
+                    m = fmaxf(m, redmax[w]);
+                    e0 = fmax(e0, redsh[w][0]);
+                    e1 = fmax(e1, redsh[w][1]);
+                }
+                part[kPMaxChi] = m;
+                part[kPMaxEmu] = e0;
+                part[kPMaxEsig] = e1;
             }
             __syncthreads();  // red is rewritten by the next tile
         }
@@ -473,14 +501,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
         double acc = 0.0;
         for (int64_t b = threadIdx.x; b < nd; b += blockDim.x) {
             const double v = P.partials[(size_t)(sp.mtile0 + b) * kPartials + m];
-            acc = m == P_N ? fmax(acc, v) : acc + v;
+            acc = m >= P_N ? fmax(acc, v) : acc + v;
         }
         tree[threadIdx.x] = acc;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
             if (threadIdx.x < w) {
                 const double o = tree[threadIdx.x + w];
-                tree[threadIdx.x] = m == P_N ? fmax(tree[threadIdx.x], o) : tree[threadIdx.x] + o;
+                tree[threadIdx.x] = m >= P_N ? fmax(tree[threadIdx.x], o) : tree[threadIdx.x] + o;
             }
             __syncthreads();
         }
@@ -510,9 +538,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
             M[5] = sums[P_S1Y] / W;
             M[6] = sqrt(sums[P_S2Y] / W);
             M[7] = sums[P_SAEFF] / W;
-            M[8] = sums[P_N];
+            M[8] = sums[kPMaxChi];
             M[9] = sums[P_SRAD] / W;
             M[10] = sums[P_SSIGF] / W;
+            const double ns = sums[P_SHN];
+            if (ns > 0.0) {
+                M[11] = ns;
+                M[12] = sums[kPMaxEmu];
+                M[13] = sums[P_SHMU] / ns;
+                M[14] = sums[kPMaxEsig];
+                M[15] = sums[P_SHG] / ns;
+            }
         }
         const int fl = P.flags[s];
         *so.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);

@@ -57,7 +57,7 @@ def test_struct_layouts_match_header():
     # sizes follow from the header's field lists (8-byte aligned doubles)
     assert ctypes.sizeof(_lib.Laser) == 8 * 4 + 4 * 2 + 8 * 3 + 4 * 2
     assert ctypes.sizeof(_lib.Beam) == 8 * 5 + 4 * 2
-    assert ctypes.sizeof(_lib.Numerics) == 8 + 4 * 2 + 8 * 2 + 4 * 4 + 8 * 3
+    assert ctypes.sizeof(_lib.Numerics) == 8 + 4 * 2 + 8 * 2 + 4 * 4 + 8 * 3 + 4 * 2
     assert ctypes.sizeof(_lib.Bins) == 4 * 4 + 8 * 4
     assert ctypes.sizeof(_lib.Outputs) == 8 * 8
     assert ctypes.sizeof(_lib.NodeGrid) == 4 * 2 + 8 * 2

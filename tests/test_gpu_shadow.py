@@ -1,0 +1,80 @@
+"""FP64 shadow of an FP32 pass (QS_VALIDATE_FP64): every shadow_stride-th
+sample is integrated again in FP64 and the differences are reported in the
+moments QS_M_SHADOW_N .. QS_M_ERR_MEAN_G.  Checked against the FP64 pass's
+own per-sample records (the shadow runs the same FP64 integration of the same
+samples), and the rest of the output must be the FP32 pass's bits.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_09348_amd import _lib, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09348_amd as qs
+    ctx = qs.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def _run(ctx, p):
+    n = p["n_samples"]
+    return _np(ctx.forward(p, sample_stride=1, n_sample_records=n))
+
+
+@pytest.mark.parametrize("chi64,stride", [(0.0, 7), (0.1, 1), (0.1, 64)])
+def test_shadow_matches_the_fp64_pass(gpu, chi64, stride):
+    p = workloads.scaled(workloads.focused_3d(), n_samples=5037, n_steps=256, deposit="cic",
+                         chi_fp64=chi64)
+    plain = _run(gpu, p)
+    g = _run(gpu, dict(p, validate_fp64=True, shadow_stride=stride))
+    d = _run(gpu, dict(p, precision="fp64"))
+    # everything but the shadow fields is the FP32 pass
+    for k in ("energy_hist", "angle_hist", "a0eff_hist", "samples"):
+        assert np.array_equal(g[k], plain[k]), k
+    assert np.array_equal(g["moments"][:11], plain["moments"][:11])
+    assert not plain["moments"][11:].any()
+    m = g["moments"]
+    idx = np.arange(0, p["n_samples"], stride)
+    mu32, mu64 = g["samples"][idx, 0], d["samples"][idx, 0]
+    s32 = np.sqrt(np.maximum(g["samples"][idx, 1], 0.0))
+    s64 = np.sqrt(np.maximum(d["samples"][idx, 1], 0.0))
+    diff = mu32 - mu64
+    assert m[_lib.M_SHADOW_N] == len(idx)
+    assert m[_lib.M_ERR_MU_MAX] == np.max(np.abs(diff) / mu64)
+    assert m[_lib.M_ERR_SIG_MAX] == np.max(np.abs(s32 - s64) / mu64)
+    assert abs(m[_lib.M_ERR_MU_MEAN] - np.mean(diff / mu64)) <= 1e-12 * np.max(np.abs(diff / mu64))
+    assert abs(m[_lib.M_ERR_MEAN_G] - np.mean(diff)) <= 1e-12 * np.max(np.abs(diff))
+    # the FP32 pass is within its tolerance of the FP64 one, and not identical
+    assert 0 < m[_lib.M_ERR_MU_MAX] < 3e-6
+    assert m[_lib.M_ERR_SIG_MAX] < 3e-6
+
+
+def test_no_shadow_for_fp64_passes(gpu):
+    p = workloads.scaled(workloads.focused_3d(), n_samples=1000, n_steps=64, precision="fp64",
+                         validate_fp64=True, shadow_stride=3)
+    g = _run(gpu, p)
+    assert not g["moments"][11:].any()
+
+
+def test_shadow_in_a_batch_equals_single_shots(gpu):
+    base = workloads.scaled(workloads.focused_3d(), n_samples=3000, n_steps=128,
+                            validate_fp64=True, shadow_stride=5)
+    shots = [dict(base, n_samples=n, a0=a, shot=0) for n, a in ((3000, 30.0), (1, 50.0),
+                                                                 (777, 80.0))]
+    batch = [_np(o) for o in gpu.forward_batched(shots)]
+    for k, s in enumerate(shots):
+        single = _np(gpu.forward(dict(s, shot=k)))
+        for key in single:
+            assert np.array_equal(batch[k][key], single[key]), (k, key)
+    assert batch[1]["moments"][_lib.M_SHADOW_N] == 1
