@@ -344,6 +344,19 @@ def main():
                      "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
                                                              params["amp_mode"])]},
     }
+    # FP64 shadow of the same pass (untimed above): every 64th sample again in
+    # FP64, the FP32 pass's per-sample error against it
+    pv = dict(params, validate_fp64=True, shadow_stride=64)
+    ctx.forward(pv, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv = ctx.forward(pv)
+    torch.cuda.synchronize()
+    mv = sv["moments"].cpu().numpy()
+    line["fp64_shadow"] = {
+        "shadow_stride": 64, "samples": int(mv[11]), "ms_per_pass": 1e3 * (time.perf_counter() - t0),
+        "err_mu_max": float(mv[12]), "err_mu_mean": float(mv[13]), "err_sig_max": float(mv[14]),
+        "err_mean_gamma": float(mv[15])}
     if args.batched_steps > 0:
         # batched leg: 4096 shots of uneven size in one launch, with the launch
         # choices of the tuner (cached per device and launch class) and the
