@@ -1456,6 +1456,82 @@ int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
     return 0;
 }
 
+int qso_grad_outputs(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+                     double *angle_hist, double *jac_angle, double *moments, double *jac_moments) {
+    if (validate(p) || i_begin < 0 || i_end < i_begin || i_end > p->n_samples) return -1;
+    const Derived d = derive(p);
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int nt = p->n_th;
+    const int64_t total = i_end - i_begin;
+    const Params<Dual> P = seeded_params(p);
+    /* the sums of qso_forward, as dual numbers */
+    enum { S1E, S2E, S1X, S2X, S1Y, S2Y, SAEFF, SRAD, SSIGF, NSUM };
+    std::vector<std::vector<Dual>> ht(nthreads, std::vector<Dual>(nt + 2, Dual(0.0)));
+    std::vector<std::vector<Dual>> sums(nthreads, std::vector<Dual>(NSUM, Dual(0.0)));
+    std::vector<double> chimax(nthreads, 0.0);
+    std::vector<int> bad(nthreads, 0);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num();
+        const int nth = omp_get_num_threads();
+        const int64_t b = i_begin + total * t / nth, e = i_begin + total * (t + 1) / nth;
+        std::vector<Dual> &S = sums[t];
+        for (int64_t i = b; i < e; ++i) {
+            const SampleOut<Dual> o = run_sample<Dual>(p, d, P, i);
+            if (!std::isfinite(o.mu.v) || !std::isfinite(o.sig2.v)) { bad[t] = 1; continue; }
+            deposit<Dual>(o.thx, o.sigth, p->deposit, p->kernel_sigma_bins, p->th_lo_mrad,
+                          p->th_hi_mrad, nt, ht[t].data());
+            const Dual sigf = sqrt(fmax(o.sig2, Dual(0.0)));
+            const Dual de = o.mu - P.gamma0;
+            S[S1E] += de;
+            S[S2E] += de * de + fmax(o.sig2, Dual(0.0));
+            S[S1X] += o.thx;
+            S[S2X] += o.thx * o.thx + o.sigth * o.sigth;
+            S[S1Y] += o.thy;
+            S[S2Y] += o.thy * o.thy;
+            S[SAEFF] += P.a0 * o.aeff_ratio;
+            S[SRAD] += 1.0 - o.mu / o.gamma0;
+            S[SSIGF] += sigf;
+            chimax[t] = std::fmax(chimax[t], o.chimax);
+        }
+    }
+    for (int t = 1; t < nthreads; ++t) {
+        for (int k = 0; k < nt + 2; ++k) ht[0][k] += ht[t][k];
+        for (int m = 0; m < NSUM; ++m) sums[0][m] += sums[t][m];
+        chimax[0] = std::fmax(chimax[0], chimax[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) if (bad[t]) return -2;
+    for (int k = 0; k < nt + 2; ++k) {
+        if (angle_hist) angle_hist[k] = ht[0][k].v;
+        if (jac_angle)
+            for (int m = 0; m < kNP; ++m) jac_angle[k * kNP + m] = ht[0][k].d[m];
+    }
+    std::vector<Dual> M(QSO_M_N, Dual(0.0));
+    const double W = (double)total;
+    M[QSO_M_WEIGHT] = Dual(W);
+    if (total > 0) {
+        const std::vector<Dual> &S = sums[0];
+        const Dual m1 = S[S1E] / W;
+        M[QSO_M_MEAN_G] = P.gamma0 + m1;
+        M[QSO_M_STD_G] = sqrt(fmax(S[S2E] / W - m1 * m1, Dual(0.0)));
+        M[QSO_M_MEAN_THX] = S[S1X] / W;
+        M[QSO_M_RMS_THX] = sqrt(S[S2X] / W);
+        M[QSO_M_MEAN_THY] = S[S1Y] / W;
+        M[QSO_M_RMS_THY] = sqrt(S[S2Y] / W);
+        M[QSO_M_MEAN_AEFF] = S[SAEFF] / W;
+        M[QSO_M_MAX_CHI] = Dual(chimax[0]);
+        M[QSO_M_RAD_FRAC] = S[SRAD] / W;
+        M[QSO_M_MEAN_SIGF] = S[SSIGF] / W;
+    }
+    for (int k = 0; k < QSO_M_N; ++k) {
+        if (moments) moments[k] = M[k].v;
+        if (jac_moments)
+            for (int m = 0; m < kNP; ++m) jac_moments[k * kNP + m] = M[k].d[m];
+    }
+    return 0;
+}
+
 int qso_photon_cdf(double xi, double chi, double *phi, double *total) {
     if (!(chi > 0.0) || !(chi <= 1e3)) return -1;
     const PhotonRow R(chi);

@@ -173,6 +173,14 @@ int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gno
 int qso_sample_grad(const qso_problem *p, int64_t i, double *out);
 int qso_grad(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
              double *hist, double *jac);
+/* The other differentiable outputs over samples [i_begin, i_end): the angle
+ * histogram angle_hist[n_th + 2] and its Jacobian jac_angle[(n_th + 2) * 8],
+ * the moments moments[QSO_M_N] and their Jacobian jac_moments[QSO_M_N * 8]
+ * (rows of the weight, the largest chi and the unused fields are zero: the
+ * chi maximum has no derivative almost anywhere).  Dual numbers through the
+ * definitions of qso_forward (its values up to summation order). */
+int qso_grad_outputs(const qso_problem *p, int64_t i_begin, int64_t i_end, int nthreads,
+                     double *angle_hist, double *jac_angle, double *moments, double *jac_moments);
 
 /* Photon emission (Sec. 4): at every RK4 stage the electron's mean energy
  * and the instantaneous amplitude give the LCFA photon spectrum of

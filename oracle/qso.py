@@ -86,6 +86,9 @@ def lib():
         L.qso_sample_grad.restype = ctypes.c_int
         L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
         L.qso_grad.restype = ctypes.c_int
+        L.qso_grad_outputs.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp,
+                                       dp, dp]
+        L.qso_grad_outputs.restype = ctypes.c_int
         L.qso_photons.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int32,
                                   ctypes.c_double, ctypes.c_double, dp, dp]
         L.qso_photons.restype = ctypes.c_int
@@ -286,6 +289,25 @@ def grad(params, i_begin=0, i_end=None, nthreads=0):
     if rc == -2:
         raise FloatingPointError("non-finite state")
     return h, j
+
+
+def grad_outputs(params, i_begin=0, i_end=None, nthreads=0):
+    """Angle histogram [n_th + 2] with its Jacobian [n_th + 2, 8] and the
+    moments [16] with their Jacobian [16, 8], with respect to PARAM_NAMES."""
+    if i_end is None:
+        i_end = params["n_samples"]
+    p = problem(params)
+    ht = np.zeros(params["n_th"] + 2)
+    jt = np.zeros((params["n_th"] + 2, 8))
+    m = np.zeros(M_N)
+    jm = np.zeros((M_N, 8))
+    rc = lib().qso_grad_outputs(ctypes.byref(p), i_begin, i_end, nthreads, _dp(ht), _dp(jt),
+                                _dp(m), _dp(jm))
+    if rc == -1:
+        raise ValueError("invalid problem")
+    if rc == -2:
+        raise FloatingPointError("non-finite state")
+    return ht, jt, m, jm
 
 
 def photons(params, n_ph, ph_lo, ph_hi, i_begin=0, i_end=None, nthreads=0):

@@ -75,3 +75,52 @@ def test_plane_wave_map_derivatives(oracle):
     for k in (2, 3, 4, 5, 8):
         assert m[k] == 0.0
     assert np.all(s2[1:] == 0.0)
+
+
+# ---- the angle histogram and the moments ------------------------------------
+
+MOMENT_ROWS = [1, 2, 3, 4, 5, 6, 7, 9, 10]  # the differentiable moments
+
+
+def test_output_duals_carry_the_forward_values(oracle):
+    p = workloads.scaled(workloads.differentiation(), n_samples=120, n_steps=128, deposit="cic")
+    ht, _, m, jm = oracle.grad_outputs(p)
+    o = oracle.forward(p)
+    assert np.array_equal(ht, o["angle_hist"])
+    assert np.allclose(m, o["moments"], rtol=1e-12, atol=0)
+    # the weight and the largest chi carry no derivative
+    assert not jm[0].any() and not jm[8].any() and not jm[11:].any()
+
+
+@pytest.mark.parametrize("amp,dep", [("local", "gauss"), ("a0eff", "cic")])
+def test_angle_and_moment_jacobians_against_differences(oracle, amp, dep):
+    p = workloads.scaled(workloads.differentiation(), n_samples=150, n_steps=256, amp_mode=amp,
+                         deposit=dep)
+    _, jt, _, jm = oracle.grad_outputs(p)
+    ft = lambda q: oracle.forward(q)["angle_hist"]
+    fm = lambda q: oracle.forward(q)["moments"][MOMENT_ROWS]
+    for k, name in enumerate(NAMES):
+        fd = _richardson(ft, p, name)
+        scale = np.max(np.abs(jt[:, k]))
+        assert np.max(np.abs(fd - jt[:, k])) <= 2e-6 * scale + 1e-12, (name, scale)
+        assert abs(jt[:, k].sum()) <= 1e-9 * max(scale, 1e-300) * len(jt)
+        fd = _richardson(fm, p, name)
+        ref = jm[MOMENT_ROWS, k]
+        tol = 2e-6 * np.maximum(np.abs(ref), 1e-6 * np.abs(oracle.forward(p)["moments"][MOMENT_ROWS]))
+        assert np.all(np.abs(fd - ref) <= tol + 1e-15), (name, fd, ref)
+
+
+def test_moment_derivatives_in_closed_form(oracle):
+    """Angles scale with the divergence (theta = div n), a0,eff with a0
+    (a0,eff = a0 S0): the mean and rms of theta_y and the mean a0,eff are
+    homogeneous of degree one in them."""
+    p = workloads.scaled(workloads.differentiation(), n_samples=200, n_steps=64)
+    _, _, m, jm = oracle.grad_outputs(p)
+    div, a0 = p["div_mrad"], p["a0"]
+    k_div, k_a0 = NAMES.index("div_mrad"), NAMES.index("a0")
+    assert abs(jm[5, k_div] - m[5] / div) <= 1e-12 * abs(m[5] / div)
+    assert abs(jm[6, k_div] - m[6] / div) <= 1e-12 * m[6] / div
+    assert abs(jm[7, k_a0] - m[7] / a0) <= 1e-12 * m[7] / a0
+    for k in range(8):
+        if k != k_div:
+            assert jm[5, k] == 0.0 and jm[6, k] == 0.0
