@@ -249,17 +249,31 @@ enum {
 /* Adjoint inputs and outputs of one shot: device pointers, caller-allocated. */
 typedef struct qs_grad_outputs {
     const double *d_energy_hist; /* in: [n_e + 2] dL/dH for the energy histogram of
-                                    qs_forward (bins, underflow, overflow)        */
+                                    qs_forward (bins, underflow, overflow), or NULL */
     double *grad;                /* out: [QS_P_N] dL/dp                           */
     int32_t *status;             /* out: [1] qs_status of the device-side checks,
                                     or NULL                                       */
+    const double *d_angle_hist;  /* in: [n_th + 2] dL/dH for the angle histogram,
+                                    or NULL                                       */
+    const double *d_moments;     /* in: [QS_M_N] dL/dM for the moments, or NULL;
+                                    the weight, QS_M_MAX_CHI and the FP64-shadow
+                                    fields carry no derivative (their entries are
+                                    not read)                                     */
+    const double *moments;       /* in: [QS_M_N] the moments qs_forward returned for
+                                    the same arguments (needed with d_moments: the
+                                    derivatives of the std and rms moments depend
+                                    on their values)                              */
 } qs_grad_outputs;
 
-/* Adjoint of the energy histogram (the parameter-reconstruction use the
+/* Adjoint of the forward outputs (the parameter-reconstruction use the
  * abstract and the conclusions give for the method's speed): for
- * L = sum_k w_k H_k with w = d_energy_hist and H the energy histogram that
- * qs_forward returns for the same arguments, write dL/dp for the QS_P_*
- * parameters.  Each sample's trajectory (Sec. 2-4, as in qs_forward) is
+ * L = sum_k w_k H_k + sum_k u_k T_k + sum_m v_m M_m with w = d_energy_hist,
+ * u = d_angle_hist, v = d_moments (each optional, at least one given) and H,
+ * T, M the energy histogram, angle histogram and moments that qs_forward
+ * returns for the same arguments, write dL/dp for the QS_P_* parameters.
+ * The angle law's centre is the initial angle (a function of the divergence)
+ * and its width the Sec. 5.2 broadening, which depends on a0,eff and on the
+ * final energy state.  Each sample's trajectory (Sec. 2-4, as in qs_forward) is
  * integrated again together with its forward-mode tangents, i.e. the exact
  * derivatives of the discrete RK4 map, and contracted with the derivative of
  * the sample's deposited law at the bin edges (the smooth law, without the
@@ -269,7 +283,8 @@ typedef struct qs_grad_outputs {
  * in compensated FP32 with FP32 tangents.  num->deposit may be any of the
  * three kernels; n_samples and the RNG stream as in qs_forward, so the
  * derivative is that of the same Monte-Carlo estimate.
- * Errors: QS_EINVAL (as qs_forward; NULL d_energy_hist or grad),
+ * Errors: QS_EINVAL (as qs_forward; NULL grad; no upstream weights;
+ * d_moments without moments),
  * QS_ENOMEM, QS_EDEVICE. */
 qs_status qs_backward(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
                       const qs_numerics *num, const qs_bins *bins, const qs_grad_outputs *out,

@@ -13,8 +13,8 @@ import os
 
 from . import _lib
 
-__all__ = ["Context", "forward", "energy_histogram", "radiation_eval", "QScatterError",
-           "PARAM_NAMES"]
+__all__ = ["Context", "forward", "energy_histogram", "spectra", "radiation_eval",
+           "QScatterError", "PARAM_NAMES"]
 
 QScatterError = _lib.QScatterError
 PARAM_NAMES = _lib.PARAM_NAMES
@@ -251,26 +251,53 @@ class Context:
                 raise QScatterError(bad, "device status of a shot")
         return b.out
 
-    def backward(self, params, d_energy, stream=None, check=True, tape=None):
-        """Derivatives of L = sum_k d_energy[k] H_k (H: the energy histogram of
-        forward(params), n_e + 2 entries) with respect to PARAM_NAMES; returns
-        a float64 device tensor of 8.  With ``tape`` (recorded by
-        forward(params, tape=...)) the derivatives are read from it instead of
-        integrating the trajectories again."""
+    def _upstream(self, params, stream, d_energy, d_angle, d_moments, moments, keep):
+        """Device float64 copies of the upstream weights (None stays None)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        sizes = (params["n_e"] + 2, params["n_th"] + 2, _lib.M_N, _lib.M_N)
+        names = ("d_energy", "d_angle", "d_moments", "moments")
+        out = []
+        for t, n, name in zip((d_energy, d_angle, d_moments, moments), sizes, names):
+            if t is None:
+                out.append(None)
+                continue
+            d = t.to(device=dev, dtype=torch.float64).contiguous()
+            if d.numel() != n:
+                raise ValueError(f"{name} needs {n} entries")
+            if d.data_ptr() != t.data_ptr():
+                d.record_stream(stream)
+            keep.append(d)
+            out.append(d)
+        if out[2] is not None and out[3] is None:
+            raise ValueError("d_moments needs the forward moments")
+        if all(o is None for o in out[:3]):
+            raise ValueError("no upstream weights")
+        return out
+
+    def backward(self, params, d_energy=None, stream=None, check=True, tape=None, d_angle=None,
+                 d_moments=None, moments=None):
+        """Derivatives of L = d_energy . H + d_angle . T + d_moments . M (H, T, M:
+        the energy histogram, angle histogram and moments of forward(params);
+        each weight vector optional, ``moments`` = M is needed with d_moments)
+        with respect to PARAM_NAMES; returns a float64 device tensor of 8.  With
+        ``tape`` (recorded by forward(params, tape=...)) the energy-state
+        derivatives are read from it instead of integrating the trajectories
+        again."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         la, be, nu, bi = _lib.structs(params)
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        d = d_energy.to(device=dev, dtype=torch.float64).contiguous()
-        if d.numel() != params["n_e"] + 2:
-            raise ValueError("d_energy needs n_e + 2 entries")
-        if d.data_ptr() != d_energy.data_ptr():
-            d.record_stream(stream)
+        keep = []
+        de, dt, dm, mo = self._upstream(params, stream, d_energy, d_angle, d_moments, moments,
+                                        keep)
+        ptr = lambda t: None if t is None else t.data_ptr()
         grad = torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev)
         status = torch.empty(1, dtype=torch.int32, device=dev)
-        g = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grad.data_ptr(),
-                             status=status.data_ptr())
+        g = _lib.GradOutputs(d_energy_hist=ptr(de), grad=grad.data_ptr(),
+                             status=status.data_ptr(), d_angle_hist=ptr(dt), d_moments=ptr(dm),
+                             moments=ptr(mo))
         if tape is not None:
             _check_tape(tape, params["n_samples"])
             st = _lib.lib().qs_backward_tape(self._ptr, ctypes.byref(la), ctypes.byref(be),
@@ -290,14 +317,18 @@ class Context:
                 raise QScatterError(st, "device status")
         return grad
 
-    def backward_batched(self, shots, d_energy, stream=None, check=True, tape=None):
-        """Adjoint of forward_batched(shots): d_energy is a list of per-shot
-        upstream weights (n_e + 2 each); returns a list of gradient tensors.
-        ``tape``: as recorded by forward_batched(shots, tape=...)."""
+    def backward_batched(self, shots, d_energy=None, stream=None, check=True, tape=None,
+                         d_angle=None, d_moments=None, moments=None):
+        """Adjoint of forward_batched(shots): d_energy, d_angle, d_moments and
+        moments are lists of per-shot tensors (or None) as in backward();
+        returns a list of gradient tensors.  ``tape``: as recorded by
+        forward_batched(shots, tape=...)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = len(shots)
-        if n == 0 or len(d_energy) != n:
+        lists = [x if x is not None else [None] * n for x in (d_energy, d_angle, d_moments,
+                                                               moments)]
+        if n == 0 or any(len(x) != n for x in lists):
             raise ValueError("one upstream weight vector per shot")
         if stream is None:
             stream = torch.cuda.current_stream(dev)
@@ -306,17 +337,16 @@ class Context:
         outs, ns = (_lib.GradOutputs * n)(), (ctypes.c_int64 * n)()
         keep, grads = [], []
         status = torch.empty(n, dtype=torch.int32, device=dev)
+        ptr = lambda t: None if t is None else t.data_ptr()
         for k, p in enumerate(shots):
             la, be, _, bi = _lib.structs(p)
             lasers[k], beams[k], bins[k] = la, be, bi
             ns[k] = int(p["n_samples"])
-            d = d_energy[k].to(device=dev, dtype=torch.float64).contiguous()
-            if d.numel() != p["n_e"] + 2:
-                raise ValueError("d_energy needs n_e + 2 entries per shot")
-            keep.append(d)
+            de, dt, dm, mo = self._upstream(p, stream, *(x[k] for x in lists), keep)
             grads.append(torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev))
-            outs[k] = _lib.GradOutputs(d_energy_hist=d.data_ptr(), grad=grads[k].data_ptr(),
-                                       status=status[k:].data_ptr())
+            outs[k] = _lib.GradOutputs(d_energy_hist=ptr(de), grad=grads[k].data_ptr(),
+                                       status=status[k:].data_ptr(), d_angle_hist=ptr(dt),
+                                       d_moments=ptr(dm), moments=ptr(mo))
         if tape is not None:
             _check_tape(tape, sum(ns))
             st = _lib.lib().qs_backward_tape_batched(self._ptr, n, lasers, beams, ns,
@@ -329,9 +359,6 @@ class Context:
                                                 ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
-        for d, src in zip(keep, d_energy):
-            if d.data_ptr() != src.data_ptr():
-                d.record_stream(stream)
         if check:
             torch.cuda.synchronize(dev)
             bad = int(status.max().item())
@@ -556,3 +583,43 @@ def energy_histogram(theta, params, context=None, device=0):
     if not _fn_cache:
         _fn_cache.append(_energy_hist_fn())
     return _fn_cache[0].apply(theta, context or _ctx(device), params)
+
+
+def _spectra_fn():
+    torch = _torch()
+
+    class Spectra(torch.autograd.Function):
+        """(H, T, M)(theta): the energy histogram, the angle histogram and the
+        moments of one shot as functions of theta = the PARAM_NAMES values.
+        The forward records the derivative tape; the backward contracts it
+        with dL/dH, dL/dT and dL/dM on the device (the weight, the largest chi
+        and the FP64-shadow moments have no derivative)."""
+
+        @staticmethod
+        def forward(fctx, theta, qctx, params):
+            p = _with_theta(params, theta)
+            tape = qctx.new_tape(p["n_samples"])
+            out = qctx.forward(p, tape=tape)
+            fctx.qctx, fctx.p, fctx.tape, fctx.moments = qctx, p, tape, out["moments"]
+            fctx.theta_meta = (theta.dtype, theta.device)
+            return out["energy_hist"], out["angle_hist"], out["moments"]
+
+        @staticmethod
+        def backward(fctx, grad_h, grad_t, grad_m):
+            g = fctx.qctx.backward(fctx.p, grad_h, tape=fctx.tape, d_angle=grad_t,
+                                   d_moments=grad_m, moments=fctx.moments)
+            dtype, device = fctx.theta_meta
+            return g.to(device=device, dtype=dtype), None, None
+
+    return Spectra
+
+
+_spectra_cache = []
+
+
+def spectra(theta, params, context=None, device=0):
+    """Differentiable (energy histogram, angle histogram, moments): theta (8
+    values, PARAM_NAMES order) overrides those entries of ``params``."""
+    if not _spectra_cache:
+        _spectra_cache.append(_spectra_fn())
+    return _spectra_cache[0].apply(theta, context or _ctx(device), params)

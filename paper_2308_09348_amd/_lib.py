@@ -97,7 +97,8 @@ class PhotonOutputs(ctypes.Structure):
 
 class GradOutputs(ctypes.Structure):
     _fields_ = [("d_energy_hist", ctypes.c_void_p), ("grad", ctypes.c_void_p),
-                ("status", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("d_angle_hist", ctypes.c_void_p),
+                ("d_moments", ctypes.c_void_p), ("moments", ctypes.c_void_p)]
 
 
 # parameters of the adjoint, in the order of the QS_P_* enum

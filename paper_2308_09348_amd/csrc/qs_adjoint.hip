@@ -464,6 +464,88 @@ __device__ void law_sensitivity(double v, double s2, int dep, double ksig, doubl
     ls2 = ss * dse;
 }
 
+// Share of one sample in the angle-histogram and moment terms of L, as
+// derivatives along the eight parameters added to g.  The sample's energy
+// state (mu, sig2) and its derivatives come from the trajectory; the draw
+// gives the rest: theta = div n (derivative n in mrad per mrad), gamma0,i =
+// gamma0 + sigma_gamma n3, and a0,eff = a0 S0 with S0 at the collision point
+// (ln S0 derivatives of spatial_d; the divergence moves the collision point
+// by theta z / 2).  The angle law is N(theta_x, sig_th^2) with sig_th^2 =
+// C^2 a0,eff^2 max(sig2, 0) / mu^4 (Sec. 5.2), deposited like the energy law;
+// the moments are those of the finalize kernel:
+//   mean gamma = sum mu / W,   std^2 = sum (mu^2 + sig2^+) / W - mean^2,
+//   mean and rms of theta_x (rms with sig_th^2) and theta_y, mean a0,eff,
+//   mean 1 - mu / gamma0,i, mean sqrt(sig2^+);
+// the weight, the largest chi and the FP64-shadow fields carry no derivative.
+__device__ void observable_sensitivity(const BatchParams &P, const ShotParams &sp,
+                                       const ShotGrad &go, int64_t i, double mu, double s2,
+                                       const double *dmu, const double *ds2, double *g) {
+    if (!go.d_angle && !go.d_moments) return;
+    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
+    SampleCoords sc;
+    sample_coords(sp, P.key0, P.key1, i, sc);
+    const double *nrm = sc.n;
+    const double z = sc.z;
+    const double xc = fma(sc.thx, 0.5 * z, sc.x), yc = fma(sc.thy, 0.5 * z, sc.y);
+    const double zstar = fma(0.5, z, sp.z_delay);
+    const SpD<double> d0 = spatial_d(xc, yc, zstar, sp.inv_w0sq, sp.inv_zR, sqrt(sp.inv_w0sq));
+    const double aeff = sp.a0 * d0.S;
+    double da[kGradParams];
+    da[0] = d0.S;
+    da[1] = aeff * d0.Lw;
+    da[2] = aeff * d0.Lx;
+    da[3] = aeff * d0.Ly;
+    da[4] = aeff * kHalfC * d0.Lz;
+    da[5] = 0.0;
+    da[6] = 0.0;
+    da[7] = aeff * (0.5 * z) * fma(1e-3 * nrm[4], d0.Lx, 1e-3 * nrm[5] * d0.Ly);
+    const double thx = 1e3 * sc.thx, thy = 1e3 * sc.thy;
+    const double s2p = fmax(s2, 0.0), sigf = sqrt(s2p);
+    const double C = 1e3 * P.c_theta * 0.79788456080286535588;
+    const double q = C * C / (mu * mu * mu * mu);
+    const double sig_th = sqrt(q * aeff * aeff * s2p);
+    // dL = Lmu dmu + Ls2 dsig2^+ + Lx dtheta_x + Ly dtheta_y + Lq dsig_th^2
+    //      + La da0eff + Lg dgamma0,i
+    double Lmu = 0.0, Ls2 = 0.0, Lx = 0.0, Ly = 0.0, Lq = 0.0, La = 0.0, Lg = 0.0;
+    if (go.d_angle) {
+        double lv, ls;
+        law_sensitivity(thx, sig_th * sig_th, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w, sp.n_th,
+                        go.d_angle, lv, ls);
+        Lx += lv;
+        Lq += ls;
+    }
+    if (go.d_moments) {
+        const double *u = go.d_moments, *M = go.moments;
+        const double iW = 1.0 / (double)sp.n_samples;
+        Lmu += u[1] * iW;
+        if (M[2] > 0.0) {
+            Lmu += u[2] * (mu - M[1]) * iW / M[2];
+            Ls2 += u[2] * 0.5 * iW / M[2];
+        }
+        Lx += u[3] * iW;
+        if (M[4] > 0.0) {
+            Lx += u[4] * thx * iW / M[4];
+            Lq += u[4] * 0.5 * iW / M[4];
+        }
+        Ly += u[5] * iW;
+        if (M[6] > 0.0) Ly += u[6] * thy * iW / M[6];
+        La += u[7] * iW;
+        Lmu -= u[9] * iW / sc.g0;
+        Lg += u[9] * iW * mu / (sc.g0 * sc.g0);
+        if (sigf > 0.0) Ls2 += u[10] * iW * 0.5 / sigf;
+    }
+    const double a2 = aeff * aeff;
+#pragma unroll
+    for (int p = 0; p < kGradParams; ++p) {
+        const double ds2p = s2 > 0.0 ? ds2[p] : 0.0;
+        const double dq = q * fma(2.0 * aeff * s2p, da[p], fma(a2, ds2p, -4.0 * a2 * s2p * dmu[p] / mu));
+        const double dth_x = p == 7 ? nrm[4] : 0.0, dth_y = p == 7 ? nrm[5] : 0.0;
+        const double dg = p == 5 ? 1.0 : (p == 6 ? nrm[3] : 0.0);
+        g[p] += Lmu * dmu[p] + Ls2 * ds2p + Lx * dth_x + Ly * dth_y + Lq * dq + La * da[p] +
+                Lg * dg;
+    }
+}
+
 // Final state of one sample and its derivatives along the eight parameters
 // (order of the grad outputs: a0, W0, x offset, y offset, delay, gamma0,
 // sigma_gamma, divergence).
@@ -715,11 +797,15 @@ __global__ __launch_bounds__(kPhaseBlock) void tangent_kernel(BatchParams P,
                     t[(2 + kGradParams + p) * n] = o.ds2[p];
                 }
             } else if (!(flags & kFlagNonFinite)) {
-                double lv, ls;
-                law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
-                                P.gouts[s].d_energy, lv, ls);
+                const ShotGrad &go = P.gouts[s];
+                if (go.d_energy) {
+                    double lv, ls;
+                    law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                    go.d_energy, lv, ls);
 #pragma unroll
-                for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
+                    for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
+                }
+                observable_sensitivity(P, sp, go, i, o.mu, o.s2, o.dmu, o.ds2, g);
             }
             if (flags) atomicOr(&P.flags[s], flags);
         }
@@ -746,12 +832,21 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
             const double *t = P.tape + sp.state_off + i;
             const double mu = t[0], s2 = t[n];
             if (mu > 0.0 && isfinite(mu) && isfinite(s2)) {
-                double lv, ls;
-                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
-                                P.gouts[s].d_energy, lv, ls);
+                const ShotGrad &go = P.gouts[s];
+                double dm[kGradParams], ds[kGradParams];
 #pragma unroll
-                for (int p = 0; p < kGradParams; ++p)
-                    g[p] = fma(lv, t[(2 + p) * n], ls * t[(2 + kGradParams + p) * n]);
+                for (int p = 0; p < kGradParams; ++p) {
+                    dm[p] = t[(2 + p) * n];
+                    ds[p] = t[(2 + kGradParams + p) * n];
+                }
+                if (go.d_energy) {
+                    double lv, ls;
+                    law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                    go.d_energy, lv, ls);
+#pragma unroll
+                    for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, dm[p], ls * ds[p]);
+                }
+                observable_sensitivity(P, sp, go, i, mu, s2, dm, ds, g);
             } else {
                 atomicOr(&P.flags[s], kFlagNonFinite);
             }

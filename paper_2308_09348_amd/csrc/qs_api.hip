@@ -220,7 +220,11 @@ qs_status validate_outputs(qs_ctx *c, const qs_outputs *O) {
 
 qs_status validate_outputs(qs_ctx *c, const qs_grad_outputs *O) {
     if (!O) return set_err(c, "null argument"), QS_EINVAL;
-    if (!O->d_energy_hist || !O->grad) return set_err(c, "null gradient pointer"), QS_EINVAL;
+    if (!O->grad) return set_err(c, "null gradient pointer"), QS_EINVAL;
+    if (!O->d_energy_hist && !O->d_angle_hist && !O->d_moments)
+        return set_err(c, "no upstream weights"), QS_EINVAL;
+    if (O->d_moments && !O->moments)
+        return set_err(c, "d_moments needs the forward moments"), QS_EINVAL;
     return QS_OK;
 }
 
@@ -1049,6 +1053,9 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         so[k].d_energy = O[k].d_energy_hist;
         so[k].grad = O[k].grad;
         so[k].status = O[k].status;
+        so[k].d_angle = O[k].d_angle_hist;
+        so[k].d_moments = O[k].d_moments;
+        so[k].moments = O[k].moments;
     }
     const size_t nenv = (size_t)2 * N->n_steps + 1;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;

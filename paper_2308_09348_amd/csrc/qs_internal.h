@@ -158,9 +158,12 @@ struct ShotPhot {
 
 // Adjoint in/out pointers of one shot (device table).
 struct ShotGrad {
-    const double *d_energy;  // upstream weights dL/dH over the n_e + 2 energy bins
+    const double *d_energy;  // upstream weights dL/dH over the n_e + 2 energy bins, or null
     double *grad;            // 8 derivatives (order of the qs_grad_param enum)
     int32_t *status;         // optional
+    const double *d_angle;   // upstream weights over the n_th + 2 angle bins, or null
+    const double *d_moments; // upstream weights over the 16 moments, or null
+    const double *moments;   // the forward pass's moments (with d_moments)
 };
 
 constexpr int kGradParams = 8;

@@ -62,6 +62,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Outputs) == 8 * 8
     assert ctypes.sizeof(_lib.NodeGrid) == 4 * 2 + 8 * 2
     assert ctypes.sizeof(_lib.Tuning) == 4 * 4 + 8 * 2
+    assert ctypes.sizeof(_lib.GradOutputs) == 8 * 6
 
 
 def test_null_context_is_rejected_without_a_device():
