@@ -815,6 +815,9 @@ __global__ __launch_bounds__(kPhaseBlock) void tangent_kernel(BatchParams P,
 
 // The adjoint from a tape: contraction of the recorded derivatives with the
 // law sensitivities (memory-bound: 144 bytes a sample).
+// OBS: some shot also has angle-histogram or moment weights (the memory-bound
+// contraction of the energy terms alone keeps its small register budget).
+template <bool OBS>
 __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
@@ -846,7 +849,7 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
 #pragma unroll
                     for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, dm[p], ls * ds[p]);
                 }
-                observable_sensitivity(P, sp, go, i, mu, s2, dm, ds, g);
+                if (OBS) observable_sensitivity(P, sp, go, i, mu, s2, dm, ds, g);
             } else {
                 atomicOr(&P.flags[s], kFlagNonFinite);
             }
@@ -942,13 +945,15 @@ hipError_t launch_tangent(const BatchParams &p, const float *env32, const double
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
-hipError_t launch_contract(const BatchParams &p, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&contract_kernel);
+hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s) {
+    const void *fn = obs ? reinterpret_cast<const void *>(&contract_kernel<true>)
+                         : reinterpret_cast<const void *>(&contract_kernel<false>);
     int grid = 0;
     hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
     if (e != hipSuccess) return e;
-    contract_kernel<<<grid, kPhaseBlock, 0, s>>>(p);
-    return hipGetLastError();
+    BatchParams pc = p;
+    void *args[] = {&pc};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {

@@ -337,7 +337,7 @@ qs_status qs_create(qs_ctx **out, int device) {
             hipSuccess ||
         (e = hipMalloc(&c->rad64d, sizeof(double) * qs::kCells64 * 4 * qs::kDerivFuncs)) !=
             hipSuccess ||
-        (e = hipMalloc(&c->phtab, sizeof(double) * qs::kPhRows * (qs::kPhNZ + 1))) !=
+        (e = hipMalloc(&c->phtab, qs::kPhTabBytes)) !=
             hipSuccess ||
         (e = hipMalloc(&c->eval_flags, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&work, sizeof(double) * wd)) != hipSuccess ||
@@ -1089,7 +1089,9 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     if ((e = qs::launch_zero(c->accum, accum_words, s)) != hipSuccess)
         return hip_fail(c, e, "zero kernel");
     if (tape) {
-        if ((e = qs::launch_contract(bp, s)) != hipSuccess)
+        bool obs = false;
+        for (int k = 0; k < n_shots; ++k) obs = obs || O[k].d_angle_hist || O[k].d_moments;
+        if ((e = qs::launch_contract(bp, obs, s)) != hipSuccess)
             return hip_fail(c, e, "contraction kernel");
     } else if ((e = qs::launch_tangent(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode,
                                        false, s)) != hipSuccess) {

@@ -125,8 +125,12 @@ struct RadCell32 {
 // (t >= -2^kSB32): there g, chi g', chi^2 g'' and h are linear in chi to
 // 1e-12, and so is the cell's cubic.  Above the table the result is not used
 // (the caller reports the range error).
+// With ncell, *nq also receives that cell's entry of ncell (a per-cell cubic
+// of another function on the same cells).
 __device__ __forceinline__ void rad_lookup32(const float *__restrict__ tab, float chi,
-                                             RadCell32 &cell) {
+                                             RadCell32 &cell,
+                                             const float4 *__restrict__ ncell = nullptr,
+                                             float4 *nq = nullptr) {
     const float xc = fminf(fmaxf(chi, 0x1p-20f), 0x1.fffffep7f);
     const uint32_t b = __float_as_uint(xc);
     // cell 1 + (b - bits(2^kEMin)) >> (23 - SB): non-negative by the clamp
@@ -141,6 +145,7 @@ __device__ __forceinline__ void rad_lookup32(const float *__restrict__ tab, floa
     cell.q3 = T[3 * kCells32 + c];
     cell.tw = tw;
     cell.ts = ts;
+    if (ncell) *nq = ncell[c];
 }
 
 __device__ __forceinline__ void rad_cell_eval(const RadCell32 &cell, float chi, float &g,
@@ -226,6 +231,38 @@ __device__ __forceinline__ void coop_cell64(const double *__restrict__ tab, int 
         }
         wave_sync_lds();  // the upper halves overwrite the rows
     }
+}
+
+// Chi at coordinate t in [0, 1) of a table cell (SB: sub-cells per octave;
+// cell 0 is linear in chi below 2^kEMin), the four Chebyshev nodes of a cell
+// and the monomial coefficients l[0..3] of the Lagrange polynomial of node m
+// (a cubic through the node values v_m is sum_m v_m l_m(t)).
+__device__ __forceinline__ double cell_chi(int cell, double t, int sb) {
+    if (cell == 0) return t * 0x1p-20;
+    const int c = cell - 1;
+    const int e = kEMin + (c >> sb);
+    const int sub = c & ((1 << sb) - 1);
+    return ldexp(1.0 + ((double)sub + t) / (double)(1 << sb), e);
+}
+
+__device__ __forceinline__ double cheb_node(int m) {
+    return 0.5 * (1.0 - cospi((2.0 * m + 1.0) / 8.0));
+}
+
+__device__ __forceinline__ void cheb_basis(int m, double l[4]) {
+    double r[3];
+    int k = 0;
+    double den = 1.0;
+    for (int n = 0; n < 4; ++n)
+        if (n != m) {
+            r[k++] = cheb_node(n);
+            den *= cheb_node(m) - cheb_node(n);
+        }
+    // (t - r0)(t - r1)(t - r2) / den
+    l[3] = 1.0 / den;
+    l[2] = -(r[0] + r[1] + r[2]) / den;
+    l[1] = (r[0] * r[1] + r[0] * r[2] + r[1] * r[2]) / den;
+    l[0] = -(r[0] * r[1] * r[2]) / den;
 }
 
 template <class T>

@@ -133,6 +133,11 @@ constexpr double kPhU0 = kEMin * 0.69314718055994530942;
 constexpr int kPhRows = 100;  // u up to kPhU0 + 99 kPhDu: chi beyond 2^(kEMax+1)
 constexpr int kPhNZ = 1024;
 constexpr double kPhYMax = 80.0;
+// After the rows (in the same allocation): the photon number per unit of
+// the forward FP32 table's cells, a float cubic in the cell coordinate per
+// cell ([kCells32][4]), for the FP32 photon angular moments.
+constexpr size_t kPhCellOff = (size_t)kPhRows * (kPhNZ + 1);  // in doubles
+constexpr size_t kPhTabBytes = sizeof(double) * kPhCellOff + sizeof(float) * 4 * kCells32;
 // Emission grid of one shot: at most kPhNU rows (ln chi, global rows
 // r_lo .. r_lo + nu - 1) x kPhNV columns (ln mu), weights in fixed point.
 constexpr int kPhNU = 64, kPhNV = 64, kPhNodes = kPhNU * kPhNV;
@@ -225,7 +230,7 @@ hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, in
                                    const double *chi, double *out, int *flags, hipStream_t s);
 hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
                           int rr, int amp, bool tape, hipStream_t s);
-hipError_t launch_contract(const BatchParams &p, hipStream_t s);
+hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s);
 size_t photon_work_doubles();
 hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, hipStream_t s);
 hipError_t launch_photon(const BatchParams &p, const float *env32, const double *env64, int prec,

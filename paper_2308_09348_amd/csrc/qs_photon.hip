@@ -178,14 +178,44 @@ __device__ __forceinline__ float ph_total(const float *tot, float chi) {
     return fmaf(w0, tot[i], fmaf(w1, tot[i + 1], fmaf(w2, tot[i + 2], w3 * tot[i + 3])));
 }
 
+// Phi(1; chi) / chi in FP64 from the rows, as ph_total does in FP32.
+__device__ double ph_total64(const double *phtab, double chi) {
+    const double s = (log(chi) - kPhU0) * (1.0 / kPhDu);
+    if (!(s > 0.0)) return 7.85398163397448310 * (1.0 - 0.92376043070340122 * chi);
+    const int i = min(max((int)s - 1, 0), kPhRows - 4);
+    const double t = s - (double)i;
+    const double w[4] = {-(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0, t * (t - 2.0) * (t - 3.0) / 2.0,
+                         -t * (t - 1.0) * (t - 3.0) / 2.0, t * (t - 1.0) * (t - 2.0) / 6.0};
+    double v = 0.0;
+    for (int k = 0; k < 4; ++k)
+        v = fma(w[k], cbrt(kPhYMax) * phtab[(size_t)(i + k) * (kPhNZ + 1) + kPhNZ], v);
+    return v;
+}
+
+// The cubic in the cell coordinate of each FP32 radiation-table cell through
+// Phi(1; chi) / chi at the cell's four Chebyshev nodes (from the rows): the
+// FP32 photon kernel reads it with the cell it already holds for g and h.
+__global__ void ph_cell_kernel(const double *phtab, float *cells) {
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= kCells32) return;
+    double coef[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < 4; ++m) {
+        const double v = ph_total64(phtab, cell_chi(cell, cheb_node(m), kSB32));
+        double l[4];
+        cheb_basis(m, l);
+        for (int k = 0; k < 4; ++k) coef[k] = fma(v, l[k], coef[k]);
+    }
+    for (int k = 0; k < 4; ++k) cells[4 * cell + k] = (float)coef[k];
+}
+
 // One stage's share of the angular sums: weight c (the stage's quadrature
 // weight over h), amplitude a, mean energy mu, drift A; the emission angle is
 // theta_x + a/mu in x and theta_y in y, plus a 1/mu cone in each plane.
 template <class T>
 struct AngStep {
     T n, nx, ny, e, ex, ey;
-    __device__ __forceinline__ void add(T c, T a, T mu, T A, T thx, T thy, float tas,
-                                        const float *tot) {
+    // nf: Phi(1; chi) / chi at the stage's chi
+    __device__ __forceinline__ void add(T c, T a, T mu, T A, T thx, T thy, T nf) {
         const T aa = fabs(a);
         T imu;
         if constexpr (sizeof(T) == 4)
@@ -194,7 +224,7 @@ struct AngStep {
             imu = T(1) / mu;
         const T tx = fma(a, imu, thx), cone = imu * imu;
         const T x2 = fma(tx, tx, cone), y2 = fma(thy, thy, cone);
-        const T dn = aa > T(0) ? c * aa * (T)ph_total(tot, tas * (float)mu * (float)aa) : T(0);
+        const T dn = c * aa * nf;
         const T de = -c * A;
         n += dn;
         nx = fma(dn, x2, nx);
@@ -239,29 +269,45 @@ __device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi
 // reusing those cells; FP64: the global table at every stage.
 template <class T>
 struct FwdRad;
+// With ncell (FP32 angular moments) the cells also bring the photon-number
+// cubic of the same cell: num() gives Phi(1; chi) / chi of the last stage.
 template <>
 struct FwdRad<float> {
     const float *tab;
+    const float4 *ncell = nullptr;
     RadCell32 carry, mid;
-    __device__ __forceinline__ void init(float chi) { rad_lookup32(tab, chi, carry); }
+    float4 ncarry, nmid;
+    float nf = 0.0f;
+    __device__ __forceinline__ void init(float chi) { rad_lookup32(tab, chi, carry, ncell, &ncarry); }
+    __device__ __forceinline__ void number(const RadCell32 &c, const float4 &q, float chi) {
+        if (ncell) {
+            const float t = fmaf(chi, c.tw, c.ts);
+            nf = fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+        }
+    }
     __device__ __forceinline__ void s1(float chi, float *t) {
         rad_cell_eval(carry, chi, t[0], t[1], t[2], t[3]);
+        number(carry, ncarry, chi);
     }
     __device__ __forceinline__ void s2(float chi, float *t) {
-        rad_lookup32(tab, chi, mid);
+        rad_lookup32(tab, chi, mid, ncell, &nmid);
         rad_cell_eval(mid, chi, t[0], t[1], t[2], t[3]);
+        number(mid, nmid, chi);
     }
     __device__ __forceinline__ void s3(float chi, float *t) {
         rad_cell_eval(mid, chi, t[0], t[1], t[2], t[3]);
+        number(mid, nmid, chi);
     }
     __device__ __forceinline__ void s4(float chi, float *t) {
-        rad_lookup32(tab, chi, carry);
+        rad_lookup32(tab, chi, carry, ncell, &ncarry);
         rad_cell_eval(carry, chi, t[0], t[1], t[2], t[3]);
+        number(carry, ncarry, chi);
     }
 };
 template <>
 struct FwdRad<double> {
     const double *tab;
+    double nf = 0.0;  // unused: the FP64 pass takes the number from the rows
     __device__ __forceinline__ void init(double) {}
     __device__ __forceinline__ void ev(double chi, double *t) {
         double g, G1, G2, hq;
@@ -280,7 +326,7 @@ struct FwdRad<double> {
 // One stage: slopes and the drift A (the photon energy per unit phase is -A).
 template <class T, bool QUANTUM, int S>
 __device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph, FwdRad<T> &rad,
-                                             T &dmu, T &ds2, T &A, T &chi_hi) {
+                                             T &dmu, T &ds2, T &A, T &chi_hi, T &nf) {
     const T a2 = a * a;
     const T u = ph.K * a2;
     const T mu2 = mu * mu;
@@ -298,6 +344,7 @@ __device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph,
     if (S == 2) rad.s2(chi, t);
     if (S == 3) rad.s3(chi, t);
     if (S == 4) rad.s4(chi, t);
+    nf = (T)rad.nf;
     A = -u * mu2 * t[0];
     dmu = -u * fma(mu2, t[0], s2 * t[2]);
     ds2 = fma(T(-2) * u * mu * s2, t[1], ph.CD * aa * a2 * mu2 * mu2 * t[3]);
@@ -309,8 +356,12 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                                               const float *__restrict__ env32,
                                               const double *__restrict__ env64,
                                               const float *tab32, unsigned long long *grid,
-                                              const float *tot, PhotAcc &acc, double &loss) {
+                                              const float *tot, const float4 *ncell,
+                                              PhotAcc &acc, double &loss) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    const bool angles = pp.angles != nullptr;
+    // FP32 quantum passes take the photon number from the radiation cells
+    const bool cell_number = PREC != PREC_F64 && QUANTUM && angles;
     const T *env;
     FwdRad<T> rad;
     if constexpr (PREC == PREC_F64) {
@@ -319,6 +370,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     } else {
         env = env32;
         rad.tab = tab32;
+        if (cell_number) rad.ncell = ncell;
     }
     Phys<T> ph;
     ph.K = (T)P.K;
@@ -384,7 +436,6 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
             ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)mu), ph_ln(tas * aa),
                        tas * (float)mu * aa, pp, grid, acc);
     }
-    const bool angles = pp.angles != nullptr;
     const T tthx = (T)thx, tthy = (T)thy;
     T m4_prev = T(0);  // the previous step's stage-4 state, deposited with this step's stage 1
     for (int j = 0; j < N; ++j) {
@@ -411,20 +462,31 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
             }
         }
         T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
-        photon_stage<T, QUANTUM, 1>(mu, s2, a1, ph, rad, k1m, k1s, A1, chi_hi);
+        T n1 = T(0), n2 = T(0), n3 = T(0), n4 = T(0);
+        photon_stage<T, QUANTUM, 1>(mu, s2, a1, ph, rad, k1m, k1s, A1, chi_hi, n1);
         const T m2 = fma(hh, k1m, mu);
-        photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, ph, rad, k2m, k2s, A2, chi_hi);
+        photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, ph, rad, k2m, k2s, A2, chi_hi, n2);
         const T m3 = fma(hh, k2m, mu);
-        photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, ph, rad, k3m, k3s, A3, chi_hi);
+        photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, ph, rad, k3m, k3s, A3, chi_hi, n3);
         const T m4 = fma(h, k3m, mu);
-        photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, ph, rad, k4m, k4s, A4, chi_hi);
+        photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, ph, rad, k4m, k4s, A4, chi_hi, n4);
         acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
         if (angles) {
+            if (!cell_number) {  // from the rows
+                auto rows = [&](T m, T a) {
+                    const float aa = fabsf((float)a);
+                    return aa > 0.0f ? (T)ph_total(tot, tas * (float)m * aa) : T(0);
+                };
+                n1 = rows(mu, a1);
+                n2 = rows(m2, ah);
+                n3 = rows(m3, ah);
+                n4 = rows(m4, a4);
+            }
             AngStep<T> st{T(0), T(0), T(0), T(0), T(0), T(0)};
-            st.add(c16, a1, mu, A1, tthx, tthy, tas, tot);
-            st.add(c13, ah, m2, A2, tthx, tthy, tas, tot);
-            st.add(c13, ah, m3, A3, tthx, tthy, tas, tot);
-            st.add(c16, a4, m4, A4, tthx, tthy, tas, tot);
+            st.add(c16, a1, mu, A1, tthx, tthy, n1);
+            st.add(c13, ah, m2, A2, tthx, tthy, n2);
+            st.add(c13, ah, m3, A3, tthx, tthy, n3);
+            st.add(c16, a4, m4, A4, tthx, tthy, n4);
             acc.nn += st.n;
             acc.nx += st.nx;
             acc.ny += st.ny;
@@ -488,6 +550,8 @@ __global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     __shared__ unsigned long long grid[kPhNodes];
     __shared__ float tot[kPhRows];  // Phi(1; chi) / chi on the table rows
+    // ... and as a cubic on each FP32 radiation cell
+    __shared__ float4 ncell[kTab32 ? kCells32 : 1];
     __shared__ int64_t slot;
     __shared__ double red[kDepBlock / 64][kPhotPartials];
     for (int r = threadIdx.x; r < kPhRows; r += blockDim.x)
@@ -496,6 +560,8 @@ __global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
         for (int k = threadIdx.x; k < kCells32 * kCellVals / 4; k += blockDim.x) dst[k] = src[k];
+        const float4 *nsrc = reinterpret_cast<const float4 *>(P.phtab + kPhCellOff);
+        for (int k = threadIdx.x; k < kCells32; k += blockDim.x) ncell[k] = nsrc[k];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -514,7 +580,7 @@ __global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
         const int64_t i1 = i0 + kPhotTile < sp.n_samples ? i0 + kPhotTile : sp.n_samples;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
             photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, tot,
-                                                acc, loss);
+                                                ncell, acc, loss);
         if (acc.flags) atomicOr(&P.flags[s], acc.flags);
         const double v[kPhotPartials] = {acc.e_ph, loss, acc.soft, acc.nn, acc.nx,
                                          acc.ny, acc.ee, acc.ex, acc.ey};
@@ -666,6 +732,8 @@ hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, 
     ph_bessel_kernel<<<(5 * kPhNZ + 63) / 64, 64, 0, s>>>(k23, k13);
     ph_i13_kernel<<<1, 1, 0, s>>>(k13, i13);
     ph_row_kernel<<<(kPhRows + 63) / 64, 64, 0, s>>>(k23, k13, i13, phtab);
+    ph_cell_kernel<<<(kCells32 + 63) / 64, 64, 0, s>>>(
+        phtab, reinterpret_cast<float *>(phtab + kPhCellOff));
     return hipGetLastError();
 }
 

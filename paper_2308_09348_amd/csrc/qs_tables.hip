@@ -66,18 +66,6 @@ __global__ void rad_y_kernel(double *yf) {
     o[7] = Q3 * kDt;
 }
 
-__device__ __forceinline__ double cell_chi(int cell, double t, int sb) {
-    if (cell == 0) return t * 0x1p-20;
-    const int c = cell - 1;
-    const int e = kEMin + (c >> sb);
-    const int sub = c & ((1 << sb) - 1);
-    return ldexp(1.0 + ((double)sub + t) / (double)(1 << sb), e);
-}
-
-__device__ __forceinline__ double cheb_node(int m) {
-    return 0.5 * (1.0 - cospi((2.0 * m + 1.0) / 8.0));
-}
-
 // vals[node][6] at the four Chebyshev nodes of every cell, cells of the
 // FP32 table first, then those of the FP64 table.  The chi dependence of the
 // moments I_k (weight (y cosh t)^k) and J_k sits in y cosh t, which scales
@@ -134,29 +122,13 @@ __global__ void rad_coef_kernel(const double *vals, float *rad32, double *rad64,
                                 double *rad64d) {
     const int cell_all = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell_all >= kCells32 + kCells64) return;
-    double tn[4];
-    for (int m = 0; m < 4; ++m) tn[m] = cheb_node(m);
     double coef[kNodeVals][4] = {};
     for (int m = 0; m < 4; ++m) {
-        double r[3];
-        int k = 0;
-        double den = 1.0;
-        for (int n = 0; n < 4; ++n)
-            if (n != m) {
-                r[k++] = tn[n];
-                den *= tn[m] - tn[n];
-            }
-        // (t - r0)(t - r1)(t - r2) / den
-        const double l3 = 1.0 / den;
-        const double l2 = -(r[0] + r[1] + r[2]) / den;
-        const double l1 = (r[0] * r[1] + r[0] * r[2] + r[1] * r[2]) / den;
-        const double l0 = -(r[0] * r[1] * r[2]) / den;
+        double l[4];
+        cheb_basis(m, l);
         for (int f = 0; f < kNodeVals; ++f) {
             const double v = vals[kNodeVals * (4 * cell_all + m) + f];
-            coef[f][0] += v * l0;
-            coef[f][1] += v * l1;
-            coef[f][2] += v * l2;
-            coef[f][3] += v * l3;
+            for (int k = 0; k < 4; ++k) coef[f][k] += v * l[k];
         }
     }
     if (cell_all < kCells32) {
