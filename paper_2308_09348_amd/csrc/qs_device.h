@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <math.h>
 
 #include <type_traits>
@@ -686,18 +687,42 @@ __device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double
     return L;
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wavefront (DPP: shifts
+// within rows of 16 lanes, then the row ends broadcast to the rows after).
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
 // The laws of the 64 lanes of a wavefront, deposited together.  A law spans
 // anywhere from one bin to the whole window, so one lane per law would leave
 // most lanes idle behind the widest: instead the edges of all 64 laws are laid
 // end to end (law s takes edges ka - 1 .. kb, the first only to supply the
 // lower box end of edge ka) and the lanes take 64 consecutive positions at a
-// time, each finding its law by a binary search over the laws' offsets.
+// time; a lane finds its law from the marked starts of the block through a
+// prefix maximum, and reads the law from the wavefront's LDS rows.
 // Q[e] (u64) accumulates the quantised weight at or below edge e of the laws
 // that cover e; cnt[c] (u32) counts the samples whose weight is all at or
 // below edge c - 1 (a point in bin c - 1, or a law ending at edge c - 1), so
 // that edge e carries Q[e] + 2^32 sum_(c <= e) cnt[c] in total.
+//
+// Per-wavefront LDS rows of wave_deposit: the 64 laws (kind | ka << 2, t0,
+// sf, inv_s), their position offsets, and the start marks of a block of 64
+// positions (-1 between uses; set to -1 once before the first use).
+struct WaveLaws {
+    int4 *rec;
+    int *off;
+    int *mark;
+};
+
 __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
-                                             unsigned long long *Q, unsigned int *cnt) {
+                                             unsigned long long *Q, unsigned int *cnt,
+                                             const WaveLaws &WL) {
     const int lane = threadIdx.x & 63;
     if (L.kind == 0) atomicAdd(&cnt[L.ngp], 1u);
     if (L.kind > 0) atomicAdd(&cnt[L.kb + 1], 1u);
@@ -709,20 +734,31 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         if (lane >= o) incl += y;
     }
     const int off = incl - np;
-    const int total = __shfl(incl, 63, 64);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    WL.rec[lane] = make_int4(L.kind | (L.ka << 2), __float_as_int(L.t0), __float_as_int(L.sf),
+                             __float_as_int(L.inv_s));
+    WL.off[lane] = off;
     const float wf = (float)w, inv_w = (float)(1.0 / w);
     float cP = 0.0f, cPc = 0.0f;  // box ends of the previous block's last position
+    int carry = 0;                // owner of the previous block's last position
     for (int base = 0; base < total; base += 64) {
         const int p = base + lane;
-        int own = 0;  // the last lane whose offset is <= p
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (__shfl(off, own + step, 64) <= p) own += step;
-        const int kind = __shfl(L.kind, own, 64);
-        const int ka = __shfl(L.ka, own, 64);
-        const int rel = p - __shfl(off, own, 64) - 1;  // edge - ka
-        const float t0 = __shfl(L.t0, own, 64), sf = __shfl(L.sf, own, 64);
-        const float inv_s = __shfl(L.inv_s, own, 64);
+        // owner of position p: the last lane whose offset is <= p.  Lanes
+        // with positions mark their start if it falls in this block (starts
+        // are distinct); a prefix maximum carries each start to the positions
+        // after it, the previous block's last owner to those before the first
+        if (np > 0 && off >= base && off < base + 64) WL.mark[off - base] = lane;
+        wave_sync_lds();
+        const int m = WL.mark[lane];
+        WL.mark[lane] = -1;
+        const int own = max(wave_incl_max(m), carry);
+        carry = __builtin_amdgcn_readlane(own, 63);
+        const int4 r = WL.rec[own];
+        const int kind = r.x & 3, ka = r.x >> 2;
+        const int rel = p - WL.off[own] - 1;  // edge - ka
+        const float t0 = __int_as_float(r.y), sf = __int_as_float(r.z);
+        const float inv_s = __int_as_float(r.w);
+        wave_sync_lds();  // the marks and rows are rewritten after this block
         const bool live = p < total && rel >= 0;
         const float t = fmaf((float)rel, wf, t0);
         const bool upper = t > 0.0f;
@@ -733,8 +769,8 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
             lP = cP;
             lPc = cPc;
         }
-        cP = __shfl(up.P, 63, 64);
-        cPc = __shfl(up.Pc, 63, 64);
+        cP = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(up.P), 63));
+        cPc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(up.Pc), 63));
         if (live) {
             float F;
             if (kind == 3)
@@ -751,6 +787,7 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
             if (q) atomicAdd(&Q[ka + rel], q);
         }
     }
+    wave_sync_lds();  // the next call rewrites the rows
 }
 
 // ===========================================================================

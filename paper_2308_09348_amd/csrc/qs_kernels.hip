@@ -337,7 +337,11 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
     __shared__ float redmax[kDepBlock / 64];
     __shared__ double redsh[kDepBlock / 64][2];
     __shared__ unsigned int wsum[kDepBlock / 64];
+    __shared__ int4 wrec[kDepBlock];
+    __shared__ int woff[kDepBlock], wmark[kDepBlock];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const WaveLaws WL{wrec + 64 * wid, woff + 64 * wid, wmark + 64 * wid};
+    WL.mark[lane] = -1;
     for (;;) {
         const int64_t item = next_item(&P.queue[1], &slot);
         if (item >= P.n_ditems) break;
@@ -438,8 +442,8 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
                         }
                     }
                 }
-                wave_deposit(le, sp.e_w, hfe, Qe, ce);
-                wave_deposit(lt, sp.th_w, hft, Qt, ct);
+                wave_deposit(le, sp.e_w, hfe, Qe, ce, WL);
+                wave_deposit(lt, sp.th_w, hft, Qt, ct, WL);
             }
 
             // ---- moment tile reduction (fixed order) ----
