@@ -751,8 +751,13 @@ __device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t i
 // with its law sensitivities, summed per item.  TAPE = true: the forward pass
 // that also records the derivatives: final states for the deposit kernel and
 // the tape (mu, sig2 and their eight derivatives, structure of arrays).
+// The FP32 tape pass is latency-bound at two waves per SIMD: it is capped to
+// 168 VGPRs for three, which costs a few spills in the quantum local case and
+// still runs 7% faster; the FP64 tapes and the adjoints spill far more under
+// that cap and keep the compiler's allocation.
 template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
-__global__ __launch_bounds__(kPhaseBlock) void tangent_kernel(BatchParams P,
+__global__ __launch_bounds__(kPhaseBlock)
+__attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 1))) void tangent_kernel(BatchParams P,
                                                               const float *__restrict__ env32,
                                                               const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
