@@ -279,8 +279,11 @@ typedef struct qs_grad_outputs {
  * the sample's deposited law at the bin edges (the smooth law, without the
  * forward pass's 2^-32 quantisation and 6-sigma cut).  The quantum model
  * needs chi^3 g''' and chi h', tabulated on the device like g and h.
- * precision QS_PREC_FP64 integrates in FP64; QS_PREC_FP32 (and chi_fp64 > 0)
- * in compensated FP32 with FP32 tangents.  num->deposit may be any of the
+ * precision QS_PREC_FP64 integrates in FP64; QS_PREC_FP32 in compensated
+ * FP32 with FP32 tangents, and with chi_fp64 > 0 (quantum model) takes FP64
+ * steps where qs_forward does: the state advances by the forward pass's FP64
+ * step, the FP32 tangents by the step's linearisation at the state rounded to
+ * FP32.  num->deposit may be any of the
  * three kernels; n_samples and the RNG stream as in qs_forward, so the
  * derivative is that of the same Monte-Carlo estimate.
  * Errors: QS_EINVAL (as qs_forward; NULL grad; no upstream weights;

@@ -87,12 +87,16 @@ __device__ __forceinline__ void rad6_plain64(const double *__restrict__ tab, dou
         v[f] = fma(t, fma(t, fma(t, q[4 * f + 3], q[4 * f + 2]), q[4 * f + 1]), q[4 * f]);
 }
 
-__device__ __forceinline__ RadJ<double> radj_eval64(const double *__restrict__ tab, double chi) {
-    double v[kDerivFuncs];
-    rad6_plain64(tab, chi, v);
+__device__ __forceinline__ RadJ<double> radj_combine(const double v[kDerivFuncs]) {
     const double g = v[0], G1 = v[1], G2 = v[2], h = v[3], G3 = v[4], H1 = v[5];
     return RadJ<double>{g, fma(2.0, g, G1), fma(4.0, G1, fma(2.0, g, G2)), fma(6.0, G1 + G2, G3),
                         h, H1};
+}
+
+__device__ __forceinline__ RadJ<double> radj_eval64(const double *__restrict__ tab, double chi) {
+    double v[kDerivFuncs];
+    rad6_plain64(tab, chi, v);
+    return radj_combine(v);
 }
 
 // Where a stage takes its radiation functions from.  FP32: the LDS table,
@@ -125,6 +129,21 @@ struct RadSrc<double> {
     __device__ __forceinline__ RadJ<double> s2(double chi) { return radj_eval64(tab, chi); }
     __device__ __forceinline__ RadJ<double> s3(double chi) { return radj_eval64(tab, chi); }
     __device__ __forceinline__ RadJ<double> s4(double chi) { return radj_eval64(tab, chi); }
+};
+
+// FP32 derivative table looked up afresh at every stage (no cells carried:
+// the FP64 steps of the mixed loop keep their registers for the FP64 table).
+struct RadSrcFresh {
+    const float *tab;
+    __device__ __forceinline__ RadJ<float> ev(float chi) const {
+        RadCell6 c;
+        rad6_lookup32(tab, chi, c);
+        return rad6_cell_eval(c, chi);
+    }
+    __device__ __forceinline__ RadJ<float> s1(float chi) const { return ev(chi); }
+    __device__ __forceinline__ RadJ<float> s2(float chi) const { return ev(chi); }
+    __device__ __forceinline__ RadJ<float> s3(float chi) const { return ev(chi); }
+    __device__ __forceinline__ RadJ<float> s4(float chi) const { return ev(chi); }
 };
 
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -244,10 +263,14 @@ struct StepLin {
     T dmu, ds2;  // the state increment
 };
 
-template <class T, bool Q>
+template <class T, bool Q, class Src = RadSrc<T>>
 __device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T> &A1,
                                                     const StageAmp<T> &Ah, const StageAmp<T> &A4,
-                                                    T h, RadSrc<T> &rad, T &chi_hi) {
+                                                    T h, Src &rad, T &chi_hi) {
+    // The stage matrices M_s = K_s (I + c_s M_{s-1}) and the forcing chains
+    // e_s1 = c_s K_s e_{s-1,1}, e_sh = c_s K_s e_{s-1,h} (+ g_s) are summed
+    // with the RK4 weights as they are formed, so only the running sums and
+    // the latest stage stay live.
     const T hh = T(0.5) * h, h6 = h * T(1.0 / 6.0);
     StepLin<T, Q> L;
     // stage 1
@@ -259,7 +282,11 @@ __device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T
     } else {
         K1 = jac_classical(mu, A1);
     }
-    const Vec2<T> g1{K1.ma, K1.sa};
+    Mat2<T> M{K1.mm, K1.ms, K1.sm, K1.ss};
+    Mat2<T> SA = M;                  // M1 + 2 M2 + 2 M3 + M4
+    Vec2<T> e1{K1.ma, K1.sa};        // g1, e21, e31, e41
+    Vec2<T> S1 = e1;                 // g1 + 2 e21 + 2 e31 + e41
+    T Sm = K1.fm, Ss = K1.fs;        // k1 + 2 k2 + 2 k3 + k4
     // stage 2
     const T m2 = fma(hh, K1.fm, mu), s22 = fma(hh, K1.fs, s2);
     Jac<T> K2;
@@ -270,10 +297,15 @@ __device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T
     } else {
         K2 = jac_classical(m2, Ah);
     }
-    const Mat2<T> M1{K1.mm, K1.ms, K1.sm, K1.ss};
-    const Mat2<T> M2 = kism<T, Q>(K2, hh, M1);
-    const Vec2<T> e21 = skv<T, Q>(K2, hh, g1);
-    const Vec2<T> g2{K2.ma, K2.sa};
+    M = kism<T, Q>(K2, hh, M);
+    SA = Mat2<T>{fma(T(2), M.a, SA.a), fma(T(2), M.b, SA.b), fma(T(2), M.c, SA.c),
+                 fma(T(2), M.d, SA.d)};
+    e1 = skv<T, Q>(K2, hh, e1);
+    S1 = Vec2<T>{fma(T(2), e1.x, S1.x), fma(T(2), e1.y, S1.y)};
+    Vec2<T> eh{K2.ma, K2.sa};                        // g2, e3h, e4h
+    Vec2<T> Sh{T(2) * eh.x, T(2) * eh.y};           // 2 g2 + 2 e3h + e4h
+    Sm = fma(T(2), K2.fm, Sm);
+    Ss = fma(T(2), K2.fs, Ss);
     // stage 3
     const T m3 = fma(hh, K2.fm, mu), s23 = fma(hh, K2.fs, s2);
     Jac<T> K3;
@@ -284,11 +316,17 @@ __device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T
     } else {
         K3 = jac_classical(m3, Ah);
     }
-    const Mat2<T> M3 = kism<T, Q>(K3, hh, M2);
-    const Vec2<T> e31 = skv<T, Q>(K3, hh, e21);
-    Vec2<T> e3h = skv<T, Q>(K3, hh, g2);
-    e3h.x += K3.ma;
-    e3h.y += K3.sa;
+    M = kism<T, Q>(K3, hh, M);
+    SA = Mat2<T>{fma(T(2), M.a, SA.a), fma(T(2), M.b, SA.b), fma(T(2), M.c, SA.c),
+                 fma(T(2), M.d, SA.d)};
+    e1 = skv<T, Q>(K3, hh, e1);
+    S1 = Vec2<T>{fma(T(2), e1.x, S1.x), fma(T(2), e1.y, S1.y)};
+    eh = skv<T, Q>(K3, hh, eh);
+    eh.x += K3.ma;
+    eh.y += K3.sa;
+    Sh = Vec2<T>{fma(T(2), eh.x, Sh.x), fma(T(2), eh.y, Sh.y)};
+    Sm = fma(T(2), K3.fm, Sm);
+    Ss = fma(T(2), K3.fs, Ss);
     // stage 4
     const T m4 = fma(h, K3.fm, mu), s24 = fma(h, K3.fs, s2);
     Jac<T> K4;
@@ -299,22 +337,22 @@ __device__ __forceinline__ StepLin<T, Q> rk4_linear(T mu, T s2, const StageAmp<T
     } else {
         K4 = jac_classical(m4, A4);
     }
-    const Mat2<T> M4 = kism<T, Q>(K4, h, M3);
-    const Vec2<T> e41 = skv<T, Q>(K4, h, e31);
-    const Vec2<T> e4h = skv<T, Q>(K4, h, e3h);
+    M = kism<T, Q>(K4, h, M);
+    e1 = skv<T, Q>(K4, h, e1);
+    eh = skv<T, Q>(K4, h, eh);
     // assemble
-    L.A.a = fma(h6, M1.a + T(2) * (M2.a + M3.a) + M4.a, T(1));
-    L.A.b = h6 * (M1.b + T(2) * (M2.b + M3.b) + M4.b);
-    L.A.c = h6 * (M1.c + T(2) * (M2.c + M3.c) + M4.c);
-    L.A.d = fma(h6, M1.d + T(2) * (M2.d + M3.d) + M4.d, T(1));
-    L.P1.x = h6 * (g1.x + T(2) * (e21.x + e31.x) + e41.x);
-    L.P1.y = h6 * (g1.y + T(2) * (e21.y + e31.y) + e41.y);
-    L.Ph.x = h6 * (T(2) * (g2.x + e3h.x) + e4h.x);
-    L.Ph.y = h6 * (T(2) * (g2.y + e3h.y) + e4h.y);
+    L.A.a = fma(h6, SA.a + M.a, T(1));
+    L.A.b = h6 * (SA.b + M.b);
+    L.A.c = h6 * (SA.c + M.c);
+    L.A.d = fma(h6, SA.d + M.d, T(1));
+    L.P1.x = h6 * (S1.x + e1.x);
+    L.P1.y = h6 * (S1.y + e1.y);
+    L.Ph.x = h6 * (Sh.x + eh.x);
+    L.Ph.y = h6 * (Sh.y + eh.y);
     L.P4.x = h6 * K4.ma;
     L.P4.y = h6 * K4.sa;
-    L.dmu = h6 * (K1.fm + T(2) * (K2.fm + K3.fm) + K4.fm);
-    L.ds2 = h6 * (K1.fs + T(2) * (K2.fs + K3.fs) + K4.fs);
+    L.dmu = h6 * (Sm + K4.fm);
+    L.ds2 = h6 * (Ss + K4.fs);
     return L;
 }
 
@@ -389,6 +427,64 @@ struct AdjPath {
         da[6] = a * (hz + ell) * fma(dthx, d.Lx, dthy * d.Ly);
     }
 };
+
+// A sample's draw, its path in FP64 and the spatial factor at its collision
+// point with the log-derivatives.  The tangent loop recomputes this where it
+// needs it (FP64 steps, the chain to the parameters at the end) instead of
+// carrying it through the phase steps: the draw is a few hundred operations
+// against the thousands a step costs, and the registers go to the loop.
+struct AdjSample {
+    SampleCoords sc;
+    AdjPath<double> p;
+    SpD<double> d0;
+};
+
+// The sample index hidden from the optimiser, so that a recomputation is not
+// merged with an earlier one into values kept live in between.
+__device__ __forceinline__ int64_t opaque_index(int64_t i) {
+    asm volatile("" : "+v"(i));
+    return i;
+}
+
+__device__ __forceinline__ void adj_sample(const BatchParams &P, const ShotParams &sp, int64_t i,
+                                           AdjSample &s) {
+    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
+    sample_coords(sp, P.key0, P.key1, i, s.sc);
+    const double z = s.sc.z;
+    s.p.xc = fma(s.sc.thx, 0.5 * z, s.sc.x);
+    s.p.yc = fma(s.sc.thy, 0.5 * z, s.sc.y);
+    s.p.thx = s.sc.thx;
+    s.p.thy = s.sc.thy;
+    s.p.zstar = fma(0.5, z, sp.z_delay);
+    s.p.hz = 0.5 * z;
+    s.p.dthx = 1e-3 * s.sc.n[4];
+    s.p.dthy = 1e-3 * s.sc.n[5];
+    s.p.inv_w0sq = sp.inv_w0sq;
+    s.p.inv_zR = sp.inv_zR;
+    s.p.inv_w0 = sqrt(sp.inv_w0sq);
+    s.p.a0 = sp.a0;
+    s.p.zfac = kHalfC;
+    s.d0 = spatial_d(s.p.xc, s.p.yc, s.p.zstar, sp.inv_w0sq, sp.inv_zR, s.p.inv_w0);
+}
+
+template <class T>
+__device__ __forceinline__ AdjPath<T> adj_path_cast(const AdjPath<double> &p) {
+    AdjPath<T> r;
+    r.xc = (T)p.xc;
+    r.yc = (T)p.yc;
+    r.thx = (T)p.thx;
+    r.thy = (T)p.thy;
+    r.zstar = (T)p.zstar;
+    r.hz = (T)p.hz;
+    r.dthx = (T)p.dthx;
+    r.dthy = (T)p.dthy;
+    r.inv_w0sq = (T)p.inv_w0sq;
+    r.inv_zR = (T)p.inv_zR;
+    r.inv_w0 = (T)p.inv_w0;
+    r.a0 = (T)p.a0;
+    r.zfac = (T)p.zfac;
+    return r;
+}
 
 // Sensitivities of one sample's share of L = sum_k w_k H_k to the centre v
 // and the variance sig2 of its energy law.  Writing F for the law's CDF and
@@ -546,6 +642,101 @@ __device__ void observable_sensitivity(const BatchParams &P, const ShotParams &s
     }
 }
 
+// One step of the tangents of every direction: V' = A V + P1 d1 + Ph dh + P4 d4
+// (d1, dh, d4: the direction's amplitude derivatives at the three stage
+// points; the gamma0 direction GD has none).
+template <class T, bool QUANTUM, int ND, int GD>
+__device__ __forceinline__ void tangent_update(const StepLin<T, QUANTUM> &L, const T *da1,
+                                               const T *dah, const T *da4, T *vm, T *vs) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        T fm = T(0), fs = T(0);
+        if (d != GD) {
+            fm = fma(L.P1.x, da1[d], fma(L.Ph.x, dah[d], L.P4.x * da4[d]));
+            fs = fma(L.P1.y, da1[d], fma(L.Ph.y, dah[d], L.P4.y * da4[d]));
+        }
+        const T m0 = vm[d];
+        if (QUANTUM) {
+            const T s0 = vs[d];
+            vm[d] = fma(L.A.a, m0, fma(L.A.b, s0, fm));
+            vs[d] = fma(L.A.c, m0, fma(L.A.d, s0, fs));
+        } else {
+            vm[d] = fma(L.A.a, m0, fm);
+        }
+    }
+}
+
+// FP64 steps of the mixed-precision tangent loop, from step j on for as long
+// as some lane of the wavefront has chi above the threshold at a step start
+// (the rule of the forward pass).  The state advances by the forward pass's
+// FP64 step (FP64 amplitudes, the FP64 table read a wavefront at a time);
+// the tangents by the FP32 step linearisation at the state rounded to FP32,
+// with the FP32 amplitude derivatives and derivative table as in the FP32
+// steps (the linearisation is rounded to FP32 either way), its table cells
+// looked up at every stage.  A1 and da1 carry over to the step the segment
+// returns, the first not taken.
+template <bool LOCAL, int ND, int GD>
+__device__ __forceinline__ int tangent_fp64_segment(
+    const BatchParams &P, const AdjPath<double> &pd, double S0d, const AdjPath<float> &pf,
+    float S0f, const float *__restrict__ env32, const double *__restrict__ env64, double2 *stage,
+    const float *tab32, const Phys<float> &phf, int j, double &mu, double &s2, float *vm,
+    float *vs, float *da1, StageAmp<float> &A1, float &cmx, float &chi_hi, double &chd) {
+    const RadTabWave tabd(P.rad64, stage);
+    RadSrcFresh rad{tab32};
+    const Phys<double> phd{P.K, P.CD, P.two_over_aS};
+    const int N = P.n_steps;
+    const double h = P.h, psi0 = -P.psi_max, ell = P.ell_per_psi;
+    const float hf = (float)P.h, psi0f = (float)(-P.psi_max), ellf = (float)P.ell_per_psi;
+    auto amp64 = [&](double psi, double fc) {
+        if (LOCAL) {
+            const double e = psi * ell;
+            return pd.a0 * spatial(fma(pd.thx, e, pd.xc), fma(pd.thy, e, pd.yc), pd.zstar - e,
+                                   pd.inv_w0sq, pd.inv_zR) * fc;
+        }
+        return pd.a0 * S0d * fc;
+    };
+    auto amp32 = [&](float psi, float fc, float &a, float *da) {
+        if (LOCAL) {
+            pf.amp(psi * ellf, fc, a, da);
+        } else {
+            const float Sf = S0f * fc;
+            a = pf.a0 * Sf;
+            da[0] = Sf;
+            da[1] = 0.0f;
+        }
+    };
+    double a1 = amp64(fma((double)j, h, psi0), env64[2 * j]);
+    for (;;) {
+        // tangents: FP32 linearisation at the rounded state
+        const float psif = fmaf((float)j, hf, psi0f);
+        float ahf, a4f, dah[ND], da4[ND];
+        amp32(fmaf(0.5f, hf, psif), env32[2 * j + 1], ahf, dah);
+        amp32(psif + hf, env32[2 * j + 2], a4f, da4);
+        const StageAmp<float> Ah(ahf, phf), A4(a4f, phf);
+        const StepLin<float, true> L =
+            rk4_linear<float, true, RadSrcFresh>((float)mu, (float)s2, A1, Ah, A4, hf, rad, chi_hi);
+        tangent_update<float, true, ND, GD>(L, da1, dah, da4, vm, vs);
+        A1 = A4;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) da1[d] = da4[d];
+        // state: the forward pass's FP64 step
+        const double psi = fma((double)j, h, psi0);
+        const double ah = amp64(fma(0.5, h, psi), env64[2 * j + 1]);
+        const double a4 = amp64(psi + h, env64[2 * j + 2]);
+        double dm, ds;
+        rk4_increment<double, true, RadTabWave>(mu, s2, a1, ah, a4, h, phd, tabd, dm, ds, chd);
+        mu += dm;
+        s2 += ds;
+        a1 = a4;
+        ++j;
+        if (j >= N) break;
+        const double chi = phd.two_over_aS * mu * fabs(a1);
+        cmx = fmaxf(cmx, (float)chi);
+        if (!__any(chi > (double)P.chi_fp64)) break;
+    }
+    return j;
+}
+
 // Final state of one sample and its derivatives along the eight parameters
 // (order of the grad outputs: a0, W0, x offset, y offset, delay, gamma0,
 // sigma_gamma, divergence).
@@ -561,12 +752,16 @@ template <int PREC, bool QUANTUM, bool LOCAL>
 __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotParams &sp,
                                                int64_t i, const float *__restrict__ env32,
                                                const double *__restrict__ env64,
-                                               const float *tab32, SampleTangent &o,
-                                               int &flags) {
+                                               const float *tab32, double2 *stage,
+                                               SampleTangent &o, int &flags) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    // FP32 with FP64 steps where chi is above the threshold (quantum only;
+    // stage: the wavefront's staging rows for the FP64 table, every lane
+    // active)
+    constexpr bool MIX = PREC == PREC_F32MIX;
+    static_assert(!MIX || QUANTUM, "FP64 steps are a quantum-model option");
     constexpr int ND = LOCAL ? kDirLocal : kDirA0eff;
     constexpr int GD = LOCAL ? 5 : 1;  // the gamma0 direction: no amplitude forcing
-    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
     const int N = P.n_steps;
     RadSrc<T> rad;
     if constexpr (PREC == PREC_F64)
@@ -585,33 +780,11 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
     const float chi_top = (float)(1 << (kEMax + 1));
 
     // ---- sample and geometry (FP64) ----
-    SampleCoords sc;
-    sample_coords(sp, P.key0, P.key1, i, sc);
-    const double *nrm = sc.n;
-    const double x = sc.x, y = sc.y, z = sc.z;
-    const double g0 = sc.g0;
-    const double thx = sc.thx;
-    const double thy = sc.thy;
-    const double inv_w0 = sqrt(sp.inv_w0sq);
-    const double xc = fma(thx, 0.5 * z, x), yc = fma(thy, 0.5 * z, y);
-    const double zstar = fma(0.5, z, sp.z_delay);
-    const SpD<double> d0 = spatial_d(xc, yc, zstar, sp.inv_w0sq, sp.inv_zR, inv_w0);
-
-    AdjPath<T> pth;
-    pth.xc = (T)xc;
-    pth.yc = (T)yc;
-    pth.thx = (T)thx;
-    pth.thy = (T)thy;
-    pth.zstar = (T)zstar;
-    pth.hz = (T)(0.5 * z);
-    pth.dthx = (T)(1e-3 * nrm[4]);
-    pth.dthy = (T)(1e-3 * nrm[5]);
-    pth.inv_w0sq = (T)sp.inv_w0sq;
-    pth.inv_zR = (T)sp.inv_zR;
-    pth.inv_w0 = (T)inv_w0;
-    pth.a0 = (T)sp.a0;
-    pth.zfac = (T)kHalfC;
-    const T S0 = (T)d0.S;
+    AdjSample smp;
+    adj_sample(P, sp, i, smp);
+    const double g0 = smp.sc.g0;
+    AdjPath<T> pth = adj_path_cast<T>(smp.p);
+    const T S0 = (T)smp.d0.S;
     const T ell_per_psi = (T)P.ell_per_psi;
     const T h = (T)P.h;
     const T psi0 = (T)(-P.psi_max);
@@ -640,9 +813,33 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
     }
     StageAmp<T> A1(a1, ph);
     if (QUANTUM) rad.init(A1.chi_per_mu * mu);
-    for (int j = 0; j < N; ++j) {
+    double chd = 0.0;  // largest chi of the FP64 steps
+    for (int j = 0; j < N;) {
+        const T chi1 = A1.chi_per_mu * mu;
+        cmx = fmaxf(cmx, (float)chi1);
+        if constexpr (MIX) {
+            if (__any(chi1 > P.chi_fp64)) {
+                // FP64 steps while some lane of the wavefront has chi above
+                // the threshold; the FP32 pair takes the state back at the
+                // exit step (amplitude and derivatives carry over, the FP32
+                // cell is looked up again)
+                double mud = ((double)mu + (double)mu_lo) + g0_rest;
+                double s2d = (double)s2 + (double)s2_lo;
+                g0_rest = 0.0;  // now held by the state
+                AdjSample sd;
+                adj_sample(P, sp, opaque_index(i), sd);
+                j = tangent_fp64_segment<LOCAL, ND, GD>(P, sd.p, sd.d0.S, pth, S0, env32, env64,
+                                                        stage, tab32, ph, j, mud, s2d, vm, vs, da1,
+                                                        A1, cmx, chi_hi, chd);
+                mu = (float)mud;
+                mu_lo = (float)(mud - (double)mu);
+                s2 = (float)s2d;
+                s2_lo = (float)(s2d - (double)s2);
+                if (j < N) rad.init(A1.chi_per_mu * mu);
+                continue;
+            }
+        }
         const T psi = fma((T)j, h, psi0);
-        cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));
         T ah, a4, dah[ND], da4[ND];
         if (LOCAL) {
             pth.amp(fma(T(0.5), h, psi) * ell_per_psi, env[2 * j + 1], ah, dah);
@@ -657,22 +854,7 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
         }
         const StageAmp<T> Ah(ah, ph), A4(a4, ph);
         const StepLin<T, QUANTUM> L = rk4_linear<T, QUANTUM>(mu, s2, A1, Ah, A4, h, rad, chi_hi);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            T fm = T(0), fs = T(0);
-            if (d != GD) {
-                fm = fma(L.P1.x, da1[d], fma(L.Ph.x, dah[d], L.P4.x * da4[d]));
-                fs = fma(L.P1.y, da1[d], fma(L.Ph.y, dah[d], L.P4.y * da4[d]));
-            }
-            const T m0 = vm[d];
-            if (QUANTUM) {
-                const T s0 = vs[d];
-                vm[d] = fma(L.A.a, m0, fma(L.A.b, s0, fm));
-                vs[d] = fma(L.A.c, m0, fma(L.A.d, s0, fs));
-            } else {
-                vm[d] = fma(L.A.a, m0, fm);
-            }
-        }
+        tangent_update<T, QUANTUM, ND, GD>(L, da1, dah, da4, vm, vs);
         if constexpr (PREC == PREC_F64) {
             mu += L.dmu;
             s2 += L.ds2;
@@ -683,18 +865,27 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
         A1 = A4;
 #pragma unroll
         for (int d = 0; d < ND; ++d) da1[d] = da4[d];
+        ++j;
     }
+    if constexpr (MIX) chi_hi = fmax(chi_hi, (T)chd);
     o.mu = ((double)mu + (double)mu_lo) + g0_rest;
     o.s2 = (double)s2 + (double)s2_lo;
     o.cmx = fmaxf(cmx, (float)(A1.chi_per_mu * mu));  // the end of the last step
+    // the draw again for the chain (not carried through the loop)
+    AdjSample se;
+    adj_sample(P, sp, opaque_index(i), se);
+    const double *nrm = se.sc.n;
+    const SpD<double> &d0 = se.d0;
+    const double z = se.sc.z;
     o.S0 = d0.S;
-    o.g0 = g0;
-    o.thx = thx;
-    o.thy = thy;
+    o.g0 = se.sc.g0;
+    o.thx = se.sc.thx;
+    o.thy = se.sc.thy;
     if (QUANTUM && !((float)chi_hi < chi_top)) flags |= kFlagRange;
     if (!(o.mu > 0.0) || !isfinite(o.mu) || !isfinite(o.s2)) flags |= kFlagNonFinite;
 
     // ---- chain to the eight parameters ----
+    constexpr double kHalfC = 0.5 * 0.299792458;  // d z* / d delay [um/fs]
     const double dthx_dd = 1e-3 * nrm[4], dthy_dd = 1e-3 * nrm[5];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -751,19 +942,23 @@ __device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t i
 // with its law sensitivities, summed per item.  TAPE = true: the forward pass
 // that also records the derivatives: final states for the deposit kernel and
 // the tape (mu, sig2 and their eight derivatives, structure of arrays).
-// The FP32 tape pass is latency-bound at two waves per SIMD: it is capped to
-// 168 VGPRs for three, which costs a few spills in the quantum local case and
-// still runs 7% faster; the FP64 tapes and the adjoints spill far more under
-// that cap and keep the compiler's allocation.
+// Occupancy: the FP32 tape pass is latency-bound and fits 168 VGPRs, three
+// waves per SIMD; every other pass is held to 256 (two waves): the FP64 ones
+// would otherwise take a few registers more and run one wave per SIMD, and
+// the mixed ones are held to two by the FP64 table staging in LDS anyway.
+// Mixed precision (FP64 steps): every lane of a wavefront runs, lanes past a
+// shot's end repeat its last sample, for the wavefront's table reads.
 template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
 __global__ __launch_bounds__(kPhaseBlock)
-__attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 1))) void tangent_kernel(BatchParams P,
-                                                              const float *__restrict__ env32,
-                                                              const double *__restrict__ env64) {
+__attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void tangent_kernel(
+    BatchParams P, const float *__restrict__ env32, const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
+    constexpr bool kWave64 = PREC == PREC_F32MIX;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * 4 * kDerivFuncs : 4];
+    __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
+    double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
@@ -779,11 +974,16 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 1))) void ta
         double g[kGradParams];
 #pragma unroll
         for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
-        if (i < sp.n_samples) {
+        const bool live = i < sp.n_samples;
+        if (kWave64 || live) {
             int flags = 0;
             SampleTangent o;
-            tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, o, flags);
-            if (TAPE) {
+            tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, live ? i : sp.n_samples - 1, env32, env64,
+                                                 tab32, wstage, o, flags);
+            if (!live) {
+                // a lane past the shot's end: ran its last sample for the
+                // wavefront's table reads, stores and adds nothing
+            } else if (TAPE) {
                 const int64_t k = sp.state_off + i;
                 P.st.mu[k] = o.mu;
                 P.st.s2[k] = o.s2;
@@ -812,7 +1012,7 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 1))) void ta
                 }
                 observable_sensitivity(P, sp, go, i, o.mu, o.s2, o.dmu, o.ds2, g);
             }
-            if (flags) atomicOr(&P.flags[s], flags);
+            if (live && flags) atomicOr(&P.flags[s], flags);
         }
         if (!TAPE) grad_item_reduce(P, item, g, red);
     }
@@ -931,6 +1131,9 @@ static const void *select_tangent(int prec, int rr, int amp) {
                       : tangent_ptr<PREC_F64, true, false, TAPE>())
                  : (l ? tangent_ptr<PREC_F64, false, true, TAPE>()
                       : tangent_ptr<PREC_F64, false, false, TAPE>());
+    if (prec == PREC_F32MIX && q)  // FP64 steps are a quantum-model option
+        return l ? tangent_ptr<PREC_F32MIX, true, true, TAPE>()
+                 : tangent_ptr<PREC_F32MIX, true, false, TAPE>();
     return q ? (l ? tangent_ptr<PREC_F32, true, true, TAPE>()
                   : tangent_ptr<PREC_F32, true, false, TAPE>())
              : (l ? tangent_ptr<PREC_F32, false, true, TAPE>()

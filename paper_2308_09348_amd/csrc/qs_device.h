@@ -207,31 +207,40 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void coop_cell64(const double *__restrict__ tab, int c,
-                                            double2 *__restrict__ stage, double q[16]) {
+// The same for cells of 64 PASSES bytes (8 PASSES doubles, row after row):
+// PASSES rounds of the staged read above, one 64-byte part of every cell each.
+template <int PASSES>
+__device__ __forceinline__ void coop_rows64(const double *__restrict__ tab, int c,
+                                            double2 *__restrict__ stage, double *q) {
     const int lane = (int)(threadIdx.x & 63u);
     const int k = lane & 3;
     const double2 *cell[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int cr = __shfl(c, 16 * r + (lane >> 2), 64);
-        cell[r] = reinterpret_cast<const double2 *>(tab + (size_t)cr * kCellVals) + k;
+        cell[r] = reinterpret_cast<const double2 *>(tab + (size_t)cr * (8 * PASSES)) + k;
     }
     const double2 *row = stage + lane * kStageStride;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int part = 0; part < PASSES; ++part) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            stage[(16 * r + (lane >> 2)) * kStageStride + k] = cell[r][4 * half];
+            stage[(16 * r + (lane >> 2)) * kStageStride + k] = cell[r][4 * part];
         wave_sync_lds();
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const double2 v = row[m];
-            q[8 * half + 2 * m] = v.x;
-            q[8 * half + 2 * m + 1] = v.y;
+            q[8 * part + 2 * m] = v.x;
+            q[8 * part + 2 * m + 1] = v.y;
         }
-        wave_sync_lds();  // the upper halves overwrite the rows
+        wave_sync_lds();  // the next part overwrites the rows
     }
+}
+
+__device__ __forceinline__ void coop_cell64(const double *__restrict__ tab, int c,
+                                            double2 *__restrict__ stage, double q[16]) {
+    static_assert(kCellVals == 16, "a forward-table cell is two 64-byte parts");
+    coop_rows64<2>(tab, c, stage, q);
 }
 
 // Chi at coordinate t in [0, 1) of a table cell (SB: sub-cells per octave;
@@ -593,7 +602,12 @@ __device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slo
 // CDF is evaluated in FP32 on whichever side of v keeps it small (the tail),
 // so its error is a few ulps of the smaller tail mass.  For the box (x)
 // Gaussian law the CDF is a difference of Psi(x) = Int_-inf^x Phi(u/s) du at
-// the two box ends, and consecutive edges share one end.
+// the two box ends, and consecutive edges share one end.  Psi is of order s
+// while the difference is of order one bin, so for laws wider than 4 bins
+// that difference would lose log2(s / bin) bits in FP32; there the CDF is
+// the box average of Phi as a series in beta = bin / s instead,
+//   F = Phi(z) + beta^2/24 Phi''(z) + beta^4/1920 Phi''''(z),  z = t / s,
+// whose next term is below 2e-9 for beta <= 1/4.
 constexpr unsigned long long kOne = 1ull << 32;
 
 // erfc(a) for a >= 0 without branches, given ea2 = exp(-a^2): the
@@ -626,19 +640,28 @@ __device__ __forceinline__ float gauss_tail(float z) {
 struct PsiPair {
     float P, Pc;  // Psi(x) and Psi(x) - x
 };
-// Psi(x) = x Phi(x/s) + s phi(x/s) and Psi(x) - x = -x Phi(-x/s) + s phi(x/s),
-// each formed from the tail on its own side (no cancellation), without
-// branches: one exponential serves phi and the tail.
-__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s) {
+// Box (x) Gaussian law at a position: x = the upper box end of the edge for
+// a law up to 4 bins wide (Psi(x) = x Phi(x/s) + s phi(x/s) and Psi(x) - x =
+// -x Phi(-x/s) + s phi(x/s), each formed from the tail on its own side, no
+// cancellation), x = the edge itself for a wider one (F_wide: the series'
+// tail mass on the side of x).  One exponential serves phi and the tail.
+__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s, float beta2,
+                                            bool wide, float &F_wide) {
     const float zz = x * inv_s;
     const float e2 = __expf(-0.5f * zz * zz);  // relative error below 2e-6 out to 6 sigma
-    const float ph = s * 0.39894228040143267794f * e2;
+    const float phz = 0.39894228040143267794f * e2;
+    const float ph = s * phz;
     const float tail = 0.5f * erfc_pos(fabsf(zz) * 0.70710678118654752440f, e2);
     const float lo = fmaf(x, tail, ph);   // Psi(x) when x <= 0
     const float hi = fmaf(-x, tail, ph);  // Psi(x) - x when x > 0
     PsiPair r;
     r.P = zz <= 0.0f ? lo : hi + x;
     r.Pc = zz <= 0.0f ? lo - x : hi;
+    // tail + a phi(a) (beta^2/24 + beta^4/1920 (a^2 - 3)), a = |z|: both
+    // even-order terms have the sign of the tail mass on either side
+    const float a = fabsf(zz);
+    const float c = beta2 * fmaf(beta2 * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
+    F_wide = wide ? fmaf(a * phz, c, tail) : 0.0f;
     return r;
 }
 
@@ -762,8 +785,16 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         const bool live = p < total && rel >= 0;
         const float t = fmaf((float)rel, wf, t0);
         const bool upper = t > 0.0f;
+        // a box (x) Gaussian law wider than 4 bins takes the series (all its
+        // positions alike, so the box ends passed between lanes below are
+        // those of narrower laws only)
+        const bool wide = kind == 3 && sf >= 4.0f * wf;
         PsiPair up{0.0f, 0.0f};
-        if (kind == 3) up = psi_pair(t + hf, sf, inv_s);
+        float Fw = 0.0f;
+        if (kind == 3) {
+            const float beta = wf * inv_s;
+            up = psi_pair(wide ? t : t + hf, sf, inv_s, beta * beta, wide, Fw);
+        }
         float lP = __shfl_up(up.P, 1, 64), lPc = __shfl_up(up.Pc, 1, 64);
         if (lane == 0) {
             lP = cP;
@@ -774,7 +805,7 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         if (live) {
             float F;
             if (kind == 3)
-                F = upper ? (lPc - up.Pc) * inv_w : (up.P - lP) * inv_w;
+                F = wide ? Fw : (upper ? (lPc - up.Pc) * inv_w : (up.P - lP) * inv_w);
             else if (kind == 2)
                 F = gauss_tail(t * inv_s);
             else

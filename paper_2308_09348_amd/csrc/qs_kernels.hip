@@ -145,8 +145,9 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         const float a0f = sp.a0f;
         const float a0S0f = (float)a0S0;
         float mu = (float)g0, mu_lo = (float)(g0 - (double)mu), s2 = 0.0f, s2_lo = 0.0f;
-        // the part of g0 that the FP32 pair cannot hold, restored at the end
-        const double g0_rest = (g0 - (double)mu) - (double)mu_lo;
+        // the part of g0 that the FP32 pair cannot hold: restored at the end,
+        // or taken into the state by the first FP64 step
+        double g0_rest = (g0 - (double)mu) - (double)mu_lo;
         double chd = 0.0;
         float aS_prev = local ? a0f * pf.S(P.psi0f * P.ellf) : a0S0f;
         RadCell32 carry;
@@ -169,8 +170,9 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
                     // FP64 steps while any lane of the wavefront has chi above
                     // the threshold at the step start (uniform loop); the FP32
                     // state, amplitudes and cell are rebuilt at the exit step
-                    double mud = (double)mu + (double)mu_lo;
+                    double mud = ((double)mu + (double)mu_lo) + g0_rest;
                     double s2d = (double)s2 + (double)s2_lo;
+                    g0_rest = 0.0;
                     j = fp64_segment<QUANTUM>(P, sp, pd, local, a0S0, env64, j, stage, mud, s2d,
                                               cmx, chd);
                     mu = (float)mud;

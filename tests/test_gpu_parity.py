@@ -199,6 +199,22 @@ def test_promotion_at_high_chi(gpu, oracle):
     assert g["moments"][8] > 1.0  # the promoted steps were taken
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_wide_box_gaussian_laws(gpu, oracle, prec):
+    """Quantum-batch physics with the CIC deposit: samples that keep about 1 %
+    of their energy have angle laws hundreds of bins wide (width a0,eff
+    sigma_f / mu_f^2), deposited with the box-average series of the law's CDF;
+    every bin of both spectra within the parity bar."""
+    shot = workloads.quantum_batch(n_shots=4)[1]
+    p = dict(shot, a0=120.0, n_samples=2000, n_steps=512, deposit="cic", precision=prec)
+    g = _run(gpu, p)
+    o = oracle.forward(p)
+    _check_moments(g, o, p)
+    _check_bins(g["energy_hist"], o["energy_hist"])
+    _check_bins(g["angle_hist"], o["angle_hist"])
+    assert o["angle_hist"][:-2].min() > 0.5  # the tails are populated
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
 def test_small_and_ragged_sizes(gpu, oracle, n):
     p = workloads.scaled(workloads.focused_3d(), n_samples=n, n_steps=64)
