@@ -380,7 +380,9 @@ typedef struct qs_photon_outputs {
  * most 64 columns over the shot's energy range), which is contracted with
  * the tabulated LCFA number spectrum: about 1e-3 of the spectrum in L1.  The
  * emitted photon energy (energy[0]) is summed exactly per stage; in the
- * classical model it equals the electrons' energy loss (energy[1]).
+ * classical model it equals the electrons' energy loss (energy[1]).  With
+ * QS_PREC_FP32 and chi_fp64 > 0 (quantum model) the steps that qs_forward
+ * takes in FP64 are taken in FP64 here too, emission included.
  * Errors: QS_EINVAL (as qs_forward; photon bins out of range; NULL outputs),
  * QS_ENOMEM, QS_EDEVICE.  Device status QS_ERANGE: a stage left the grid. */
 qs_status qs_photons(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,

@@ -350,6 +350,113 @@ __device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph,
     ds2 = fma(T(-2) * u * mu * s2, t[1], ph.CD * aa * a2 * mu2 * mu2 * t[3]);
 }
 
+// Per-sample constants of the photon pass in precision T.
+template <class T>
+struct PhotCtx {
+    const T *env;
+    Path<T> pt;
+    Phys<T> ph;
+    T a0, a0S0, h, psi0, ell, thx, thy;
+    float inv_a0, tas;
+    bool local, mid, angles, cell_number;
+};
+
+// The state carried from step to step (mu_lo, s2_lo: the FP32 pairs' lower
+// parts, unused in FP64): the amplitude factors a0 S at psi_j (and psi_{j+1}
+// with the quadratic midpoint), the previous step's stage-4 energy.
+template <class T>
+struct PhotState {
+    T mu, mu_lo, s2, s2_lo, aS_prev, aS_next, m4_prev, chi_hi;
+};
+
+// Step j of the photon pass: the four RK4 stages with their emission, the
+// deposits of stage 1 with the previous step's stage 4 (same amplitude) and
+// of stages 2 and 3, the emitted energy and the Sec. 5.1 angular sums.
+template <class T, bool QUANTUM>
+__device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot &pp,
+                                            const float *tot, int j, PhotState<T> &st,
+                                            FwdRad<T> &rad, unsigned long long *grid,
+                                            PhotAcc &acc) {
+    const T h = c.h, hh = T(0.5) * h;
+    const T c16 = T(1.0 / 6.0), c13 = T(1.0 / 3.0);
+    const T psi = fma((T)j, h, c.psi0);
+    T aSh = c.a0S0, aS4 = c.a0S0;
+    if (c.mid) {
+        const T aS_far = c.a0 * c.pt.S(fma((T)(j + 2), h, c.psi0) * c.ell);
+        aS4 = st.aS_next;
+        aSh = fma(T(0.375), st.aS_prev, fma(T(0.75), aS4, T(-0.125) * aS_far));
+        st.aS_next = aS_far;
+    } else if (c.local) {
+        aSh = c.a0 * c.pt.S(fma(T(0.5), h, psi) * c.ell);
+        aS4 = c.a0 * c.pt.S((psi + h) * c.ell);
+    }
+    const T a1 = st.aS_prev * c.env[2 * j], ah = aSh * c.env[2 * j + 1], a4 = aS4 * c.env[2 * j + 2];
+    const T mu = st.mu, s2 = st.s2;
+    // stage 4 of the previous step with stage 1 of this one (same
+    // amplitude): one deposit at the geometric mean of the two energies
+    if (j > 0) {
+        const float aa = fabsf((float)a1);
+        if (aa > 0.0f) {
+            const float v = 0.5f * ph_ln((float)st.m4_prev * (float)mu);
+            ph_deposit((float)c13 * aa * c.inv_a0, v, ph_ln(c.tas * aa), c.tas * (float)mu * aa,
+                       pp, grid, acc);
+        }
+    }
+    T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
+    T n1 = T(0), n2 = T(0), n3 = T(0), n4 = T(0);
+    photon_stage<T, QUANTUM, 1>(mu, s2, a1, c.ph, rad, k1m, k1s, A1, st.chi_hi, n1);
+    const T m2 = fma(hh, k1m, mu);
+    photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, c.ph, rad, k2m, k2s, A2, st.chi_hi, n2);
+    const T m3 = fma(hh, k2m, mu);
+    photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, c.ph, rad, k3m, k3s, A3, st.chi_hi, n3);
+    const T m4 = fma(h, k3m, mu);
+    photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, c.ph, rad, k4m, k4s, A4, st.chi_hi, n4);
+    acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
+    if (c.angles) {
+        if (!c.cell_number) {  // from the rows
+            auto rows = [&](T m, T a) {
+                const float aa = fabsf((float)a);
+                return aa > 0.0f ? (T)ph_total(tot, c.tas * (float)m * aa) : T(0);
+            };
+            n1 = rows(mu, a1);
+            n2 = rows(m2, ah);
+            n3 = rows(m3, ah);
+            n4 = rows(m4, a4);
+        }
+        AngStep<T> an{T(0), T(0), T(0), T(0), T(0), T(0)};
+        an.add(c16, a1, mu, A1, c.thx, c.thy, n1);
+        an.add(c13, ah, m2, A2, c.thx, c.thy, n2);
+        an.add(c13, ah, m3, A3, c.thx, c.thy, n3);
+        an.add(c16, a4, m4, A4, c.thx, c.thy, n4);
+        acc.nn += an.n;
+        acc.nx += an.nx;
+        acc.ny += an.ny;
+        acc.ee += an.e;
+        acc.ex += an.ex;
+        acc.ey += an.ey;
+    }
+    {  // stages 2 and 3 (same amplitude)
+        const float aa = fabsf((float)ah);
+        if (aa > 0.0f) {
+            const float v = 0.5f * ph_ln((float)m2 * (float)m3);
+            ph_deposit(2.0f * (float)c13 * aa * c.inv_a0, v, ph_ln(c.tas * aa),
+                       c.tas * (float)m2 * aa, pp, grid, acc);
+        }
+    }
+    const T h6 = h * c16;
+    const T dm = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
+    const T ds = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
+    if constexpr (sizeof(T) == 8) {
+        st.mu += dm;
+        st.s2 += ds;
+    } else {
+        comp_add(st.mu, st.mu_lo, dm);
+        comp_add(st.s2, st.s2_lo, ds);
+    }
+    st.m4_prev = m4;
+    st.aS_prev = aS4;
+}
+
 template <int PREC, bool QUANTUM, bool LOCAL>
 __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotParams &sp,
                                               const ShotPhot &pp, int64_t i,
@@ -359,23 +466,10 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                                               const float *tot, const float4 *ncell,
                                               PhotAcc &acc, double &loss) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
+    // FP32 with FP64 steps where chi is above the threshold (quantum only)
+    constexpr bool MIX = PREC == PREC_F32MIX;
+    static_assert(!MIX || QUANTUM, "FP64 steps are a quantum-model option");
     const bool angles = pp.angles != nullptr;
-    // FP32 quantum passes take the photon number from the radiation cells
-    const bool cell_number = PREC != PREC_F64 && QUANTUM && angles;
-    const T *env;
-    FwdRad<T> rad;
-    if constexpr (PREC == PREC_F64) {
-        env = env64;
-        rad.tab = P.rad64;
-    } else {
-        env = env32;
-        rad.tab = tab32;
-        if (cell_number) rad.ncell = ncell;
-    }
-    Phys<T> ph;
-    ph.K = (T)P.K;
-    ph.CD = (T)P.CD;
-    ph.two_over_aS = (T)P.two_over_aS;
     const int N = P.n_steps;
     const bool local = LOCAL && !sp.plane_wave;
 
@@ -398,130 +492,139 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     pd.mn = sp.mode_n;
     pd.inv_norm = sp.mode_inv_norm;
     const double S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
-    Path<T> pt;
-    pt.xc = (T)pd.xc;
-    pt.yc = (T)pd.yc;
-    pt.thx = (T)thx;
-    pt.thy = (T)thy;
-    pt.zstar = (T)pd.zstar;
-    pt.inv_w0sq = (T)sp.inv_w0sq;
-    pt.inv_zR = (T)sp.inv_zR;
-    pt.mode = sp.mode;
-    pt.mm = sp.mode_m;
-    pt.mn = sp.mode_n;
-    pt.inv_norm = (T)sp.mode_inv_norm;
 
-    const T a0 = (T)sp.a0, a0S0 = (T)(sp.a0 * S0);
-    const float inv_a0 = sp.a0 > 0.0 ? (float)(1.0 / sp.a0) : 0.0f;
-    const float tas = (float)P.two_over_aS;
-    const T h = (T)P.h, hh = T(0.5) * h, psi0 = (T)(-P.psi_max), ell = (T)P.ell_per_psi;
-    const T c16 = T(1.0 / 6.0), c13 = T(1.0 / 3.0);
-    T mu = (T)g0, mu_lo = T(0), s2 = T(0), s2_lo = T(0);
-    double g0_rest = 0.0;
-    if constexpr (PREC != PREC_F64) {
-        mu_lo = (T)(g0 - (double)mu);
-        g0_rest = (g0 - (double)mu) - (double)mu_lo;
-    }
-    T chi_hi = T(0);
-    T aS_prev = local ? a0 * pt.S(psi0 * ell) : a0S0;
+    PhotCtx<T> c;
+    if constexpr (PREC == PREC_F64)
+        c.env = env64;
+    else
+        c.env = env32;
+    c.pt.xc = (T)pd.xc;
+    c.pt.yc = (T)pd.yc;
+    c.pt.thx = (T)thx;
+    c.pt.thy = (T)thy;
+    c.pt.zstar = (T)pd.zstar;
+    c.pt.inv_w0sq = (T)sp.inv_w0sq;
+    c.pt.inv_zR = (T)sp.inv_zR;
+    c.pt.mode = sp.mode;
+    c.pt.mm = sp.mode_m;
+    c.pt.mn = sp.mode_n;
+    c.pt.inv_norm = (T)sp.mode_inv_norm;
+    c.ph = Phys<T>{(T)P.K, (T)P.CD, (T)P.two_over_aS};
+    c.a0 = (T)sp.a0;
+    c.a0S0 = (T)(sp.a0 * S0);
+    c.h = (T)P.h;
+    c.psi0 = (T)(-P.psi_max);
+    c.ell = (T)P.ell_per_psi;
+    c.thx = (T)thx;
+    c.thy = (T)thy;
+    c.inv_a0 = sp.a0 > 0.0 ? (float)(1.0 / sp.a0) : 0.0f;
+    c.tas = (float)P.two_over_aS;
+    c.local = local;
     // FP32 with fine steps: one spatial factor a step, the midpoint from the
     // quadratic through three step points (as in the phase kernel)
-    const bool mid = PREC != PREC_F64 && local && sp.mid_interp;
-    T aS_next = mid ? a0 * pt.S((psi0 + h) * ell) : a0S0;
-    if (QUANTUM) rad.init(ph.two_over_aS * mu * fabs(aS_prev * env[0]));
+    c.mid = PREC != PREC_F64 && local && sp.mid_interp;
+    c.angles = angles;
+    // FP32 quantum passes take the photon number from the radiation cells
+    c.cell_number = PREC != PREC_F64 && QUANTUM && angles;
+
+    FwdRad<T> rad;
+    if constexpr (PREC == PREC_F64) {
+        rad.tab = P.rad64;
+    } else {
+        rad.tab = tab32;
+        if (c.cell_number) rad.ncell = ncell;
+    }
+    PhotState<T> st;
+    st.mu = (T)g0;
+    st.mu_lo = T(0);
+    st.s2 = T(0);
+    st.s2_lo = T(0);
+    st.chi_hi = T(0);
+    st.m4_prev = T(0);  // the previous step's stage-4 state, deposited with this step's stage 1
+    double g0_rest = 0.0;
+    if constexpr (PREC != PREC_F64) {
+        st.mu_lo = (T)(g0 - (double)st.mu);
+        g0_rest = (g0 - (double)st.mu) - (double)st.mu_lo;
+    }
+    st.aS_prev = local ? c.a0 * c.pt.S(c.psi0 * c.ell) : c.a0S0;
+    st.aS_next = c.mid ? c.a0 * c.pt.S((c.psi0 + c.h) * c.ell) : c.a0S0;
+    if (QUANTUM) rad.init(c.ph.two_over_aS * st.mu * fabs(st.aS_prev * c.env[0]));
     // the first stage of the first step deposits alone
     {
-        const float aa = fabsf((float)(aS_prev * env[0]));
+        const float aa = fabsf((float)(st.aS_prev * c.env[0]));
         if (aa > 0.0f)
-            ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)mu), ph_ln(tas * aa),
-                       tas * (float)mu * aa, pp, grid, acc);
+            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.mu), ph_ln(c.tas * aa),
+                       c.tas * (float)st.mu * aa, pp, grid, acc);
     }
-    const T tthx = (T)thx, tthy = (T)thy;
-    T m4_prev = T(0);  // the previous step's stage-4 state, deposited with this step's stage 1
-    for (int j = 0; j < N; ++j) {
-        const T psi = fma((T)j, h, psi0);
-        T aSh = a0S0, aS4 = a0S0;
-        if (mid) {
-            const T aS_far = a0 * pt.S(fma((T)(j + 2), h, psi0) * ell);
-            aS4 = aS_next;
-            aSh = fma(T(0.375), aS_prev, fma(T(0.75), aS4, T(-0.125) * aS_far));
-            aS_next = aS_far;
-        } else if (local) {
-            aSh = a0 * pt.S(fma(T(0.5), h, psi) * ell);
-            aS4 = a0 * pt.S((psi + h) * ell);
-        }
-        const T a1 = aS_prev * env[2 * j], ah = aSh * env[2 * j + 1], a4 = aS4 * env[2 * j + 2];
-        // stage 4 of the previous step with stage 1 of this one (same
-        // amplitude): one deposit at the geometric mean of the two energies
-        if (j > 0) {
-            const float aa = fabsf((float)a1);
-            if (aa > 0.0f) {
-                const float v = 0.5f * ph_ln((float)m4_prev * (float)mu);
-                ph_deposit((float)c13 * aa * inv_a0, v, ph_ln(tas * aa), tas * (float)mu * aa, pp,
-                           grid, acc);
+    double chd = 0.0;  // largest chi of the FP64 steps
+    for (int j = 0; j < N;) {
+        if constexpr (MIX) {
+            const float chi1 = c.ph.two_over_aS * st.mu * fabsf(st.aS_prev * env32[2 * j]);
+            if (__any(chi1 > P.chi_fp64)) {
+                // FP64 steps while some lane of the wavefront has chi above
+                // the threshold at a step start (the forward pass's rule);
+                // the FP32 pair, amplitudes and cell are rebuilt at the exit
+                PhotCtx<double> cd;
+                cd.env = env64;
+                cd.pt = pd;
+                cd.ph = Phys<double>{P.K, P.CD, P.two_over_aS};
+                cd.a0 = sp.a0;
+                cd.a0S0 = sp.a0 * S0;
+                cd.h = P.h;
+                cd.psi0 = -P.psi_max;
+                cd.ell = P.ell_per_psi;
+                cd.thx = thx;
+                cd.thy = thy;
+                cd.inv_a0 = c.inv_a0;
+                cd.tas = c.tas;
+                cd.local = local;
+                cd.mid = false;
+                cd.angles = angles;
+                cd.cell_number = false;
+                PhotState<double> sd;
+                sd.mu = ((double)st.mu + (double)st.mu_lo) + g0_rest;
+                g0_rest = 0.0;  // now held by the state
+                sd.s2 = (double)st.s2 + (double)st.s2_lo;
+                sd.mu_lo = sd.s2_lo = 0.0;
+                sd.aS_prev = local ? sp.a0 * pd.S(fma((double)j, P.h, -P.psi_max) * P.ell_per_psi)
+                                   : cd.a0S0;
+                sd.aS_next = 0.0;
+                sd.m4_prev = (double)st.m4_prev;
+                sd.chi_hi = 0.0;
+                FwdRad<double> radd;
+                radd.tab = P.rad64;
+                for (;;) {
+                    photon_step<double, QUANTUM>(cd, pp, tot, j, sd, radd, grid, acc);
+                    ++j;
+                    if (j >= N) break;
+                    const double chi = P.two_over_aS * sd.mu * fabs(sd.aS_prev * env64[2 * j]);
+                    if (!__any(chi > (double)P.chi_fp64)) break;
+                }
+                st.mu = (float)sd.mu;
+                st.mu_lo = (float)(sd.mu - (double)st.mu);
+                st.s2 = (float)sd.s2;
+                st.s2_lo = (float)(sd.s2 - (double)st.s2);
+                st.m4_prev = (float)sd.m4_prev;
+                chd = fmax(chd, sd.chi_hi);
+                if (local) {
+                    st.aS_prev = c.a0 * c.pt.S(fmaf((float)j, c.h, c.psi0) * c.ell);
+                    if (c.mid) st.aS_next = c.a0 * c.pt.S(fmaf((float)(j + 1), c.h, c.psi0) * c.ell);
+                }
+                if (j < N) rad.init(c.ph.two_over_aS * st.mu * fabsf(st.aS_prev * env32[2 * j]));
+                continue;
             }
         }
-        T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
-        T n1 = T(0), n2 = T(0), n3 = T(0), n4 = T(0);
-        photon_stage<T, QUANTUM, 1>(mu, s2, a1, ph, rad, k1m, k1s, A1, chi_hi, n1);
-        const T m2 = fma(hh, k1m, mu);
-        photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, ph, rad, k2m, k2s, A2, chi_hi, n2);
-        const T m3 = fma(hh, k2m, mu);
-        photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, ph, rad, k3m, k3s, A3, chi_hi, n3);
-        const T m4 = fma(h, k3m, mu);
-        photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, ph, rad, k4m, k4s, A4, chi_hi, n4);
-        acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
-        if (angles) {
-            if (!cell_number) {  // from the rows
-                auto rows = [&](T m, T a) {
-                    const float aa = fabsf((float)a);
-                    return aa > 0.0f ? (T)ph_total(tot, tas * (float)m * aa) : T(0);
-                };
-                n1 = rows(mu, a1);
-                n2 = rows(m2, ah);
-                n3 = rows(m3, ah);
-                n4 = rows(m4, a4);
-            }
-            AngStep<T> st{T(0), T(0), T(0), T(0), T(0), T(0)};
-            st.add(c16, a1, mu, A1, tthx, tthy, n1);
-            st.add(c13, ah, m2, A2, tthx, tthy, n2);
-            st.add(c13, ah, m3, A3, tthx, tthy, n3);
-            st.add(c16, a4, m4, A4, tthx, tthy, n4);
-            acc.nn += st.n;
-            acc.nx += st.nx;
-            acc.ny += st.ny;
-            acc.ee += st.e;
-            acc.ex += st.ex;
-            acc.ey += st.ey;
-        }
-        {  // stages 2 and 3 (same amplitude)
-            const float aa = fabsf((float)ah);
-            if (aa > 0.0f) {
-                const float v = 0.5f * ph_ln((float)m2 * (float)m3);
-                ph_deposit(2.0f * (float)c13 * aa * inv_a0, v, ph_ln(tas * aa),
-                           tas * (float)m2 * aa, pp, grid, acc);
-            }
-        }
-        const T h6 = h * c16;
-        const T dm = h6 * (k1m + T(2) * (k2m + k3m) + k4m);
-        const T ds = h6 * (k1s + T(2) * (k2s + k3s) + k4s);
-        if constexpr (PREC == PREC_F64) {
-            mu += dm;
-            s2 += ds;
-        } else {
-            comp_add(mu, mu_lo, dm);
-            comp_add(s2, s2_lo, ds);
-        }
-        m4_prev = m4;
-        aS_prev = aS4;
+        photon_step<T, QUANTUM>(c, pp, tot, j, st, rad, grid, acc);
+        ++j;
     }
     {  // the last stage 4 deposits alone
-        const float aa = fabsf((float)(aS_prev * env[2 * N]));
+        const float aa = fabsf((float)(st.aS_prev * c.env[2 * N]));
         if (aa > 0.0f)
-            ph_deposit((float)c16 * aa * inv_a0, ph_ln((float)m4_prev), ph_ln(tas * aa),
-                       tas * (float)m4_prev * aa, pp, grid, acc);
+            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.m4_prev), ph_ln(c.tas * aa),
+                       c.tas * (float)st.m4_prev * aa, pp, grid, acc);
     }
-    const double mu_f = ((double)mu + (double)mu_lo) + g0_rest;
+    const double mu_f = ((double)st.mu + (double)st.mu_lo) + g0_rest;
+    const double chi_hi = fmax((double)st.chi_hi, chd);
     if (QUANTUM && !((float)chi_hi < (float)(1 << (kEMax + 1)))) acc.flags |= kFlagRange;
     if (!(mu_f > 0.0) || !isfinite(mu_f)) {
         acc.flags |= kFlagNonFinite;
@@ -542,8 +645,11 @@ __device__ __forceinline__ int find_phot(const ShotPhot *ph, int n_shots, int64_
     return lo;
 }
 
+// The LDS (table, grid and photon-number cells, about 69 KB a block) allows
+// two blocks, two waves per SIMD: the registers are held to that (the FP64
+// and mixed-precision passes would otherwise take a few more and run one).
 template <int PREC, bool QUANTUM, bool LOCAL>
-__global__ __launch_bounds__(kDepBlock) void photon_kernel(BatchParams P,
+__global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(2))) void photon_kernel(BatchParams P,
                                                            const float *__restrict__ env32,
                                                            const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
@@ -749,6 +855,8 @@ hipError_t launch_photon(const BatchParams &p, const float *env32, const double 
     if (prec == PREC_F64)
         fn = q ? (l ? photon_ptr<PREC_F64, true, true>() : photon_ptr<PREC_F64, true, false>())
                : (l ? photon_ptr<PREC_F64, false, true>() : photon_ptr<PREC_F64, false, false>());
+    else if (prec == PREC_F32MIX && q)  // FP64 steps are a quantum-model option
+        fn = l ? photon_ptr<PREC_F32MIX, true, true>() : photon_ptr<PREC_F32MIX, true, false>();
     else
         fn = q ? (l ? photon_ptr<PREC_F32, true, true>() : photon_ptr<PREC_F32, true, false>())
                : (l ? photon_ptr<PREC_F32, false, true>() : photon_ptr<PREC_F32, false, false>());

@@ -161,3 +161,50 @@ def test_photon_angles_batched_and_empty(gpu):
     # asking for the moments leaves the spectrum unchanged
     h = gpu.photons(p)["photon_hist"].cpu().numpy()
     assert np.array_equal(h, gpu.photons(p, angles=True)["photon_hist"].cpu().numpy())
+
+
+# ---- FP64 steps where chi is above the threshold ------------------------------
+
+def _qb_case(precision="fp32", **kw):
+    """Quantum-batch physics (gamma0 = 2e4, a0 = 120, W0 = 2 um: chi up to
+    several), FP64 steps where chi > 0.1."""
+    shot = workloads.quantum_batch(n_shots=4)[1]
+    p = dict(shot, a0=120.0, n_samples=300, n_steps=512, precision=precision, n_ph=64)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("amp", ["local", "a0eff"])
+def test_mixed_precision_photons_vs_oracle(gpu, oracle, amp):
+    p = _qb_case(amp_mode=amp)
+    assert p["chi_fp64"] == 0.1
+    g = _np(gpu.photons(p, angles=True))
+    o = oracle.photons(p, p["n_ph"], p["ph_lo"], p["ph_hi"])
+    _check(g, o, p, 2e-5, "mixed-" + amp)
+    oa = oracle.photon_angles(p)
+    assert np.all(np.abs(g["angles"] - oa) <= 2e-5 * np.abs(oa)), (g["angles"], oa)
+
+
+def test_mixed_photons_promoted_everywhere_are_the_fp64_pass(gpu):
+    """A threshold below every chi runs every step in FP64 from the exact
+    initial energy: the FP64 pass's step arithmetic throughout (the state
+    returns through the FP32 pair only at the end, 2^-48 relative)."""
+    p = _qb_case(n_samples=1000)
+    m = _np(gpu.photons(dict(p, chi_fp64=1e-30), angles=True))
+    d = _np(gpu.photons(dict(p, precision="fp64"), angles=True))
+    assert np.allclose(m["photon_hist"], d["photon_hist"], rtol=1e-12,
+                       atol=1e-12 * d["photon_hist"].max())
+    assert np.allclose(m["energy"], d["energy"], rtol=1e-12, atol=0)
+    assert np.allclose(m["angles"], d["angles"], rtol=1e-12, atol=0)
+    f = _np(gpu.photons(dict(p, chi_fp64=0.0), angles=True))  # FP32 throughout
+    assert not np.array_equal(f["photon_hist"], d["photon_hist"])
+
+
+def test_mixed_photons_batched_equals_single(gpu):
+    shots = [_qb_case(n_samples=n, a0=a, shot=0) for n, a in ((700, 60.0), (1, 140.0),
+                                                              (2100, 110.0))]
+    batch = [_np(o) for o in gpu.photons_batched(shots, angles=True)]
+    for k, s in enumerate(shots):
+        single = _np(gpu.photons(dict(s, shot=k), angles=True))
+        for key in ("photon_hist", "energy", "angles", "status"):
+            assert np.array_equal(batch[k][key], single[key]), (k, key)
