@@ -1,7 +1,13 @@
-"""Build the HIP library libqscatter.so for gfx950, in-tree."""
+"""Build the HIP library libqscatter.so for gfx950, in-tree.
+
+Each source is compiled to an object of its own (in parallel, in a temporary
+directory) with the common flags plus its entry in SOURCE_FLAGS, then the
+objects are linked into the library."""
+import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -10,22 +16,39 @@ SOURCES = ["csrc/qs_kernels.hip", "csrc/qs_tables.hip", "csrc/qs_adjoint.hip", "
            "csrc/qs_factor.hip", "csrc/qs_api.hip"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # no packed FP32 instructions (hipcc would otherwise form them from float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
 
+# The tangent kernels' step loop runs about 7% faster under the instruction-
+# level-parallelism scheduling strategy than under the default occupancy one
+# (the same instructions in another order; measured on the differentiation
+# workload's tape pass).
+SOURCE_FLAGS = {
+    "csrc/qs_adjoint.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"],
+}
+
 
 def build(verbose=False, extra_flags=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + list(extra_flags) + [
-        "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc")]
-    cmd += [os.path.join(PKG, s) for s in SOURCES]
-    cmd += ["-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc")]
+    with tempfile.TemporaryDirectory(prefix="qs_build_") as tmp:
+        def compile_one(src):
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
+            cmd = ([hipcc] + HIPCC_FLAGS + SOURCE_FLAGS.get(src, []) + list(extra_flags) + inc +
+                   ["-c", os.path.join(PKG, src), "-o", obj])
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            return obj
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+            objs = list(ex.map(compile_one, SOURCES))
+        cmd = [hipcc, "-shared", "--offload-arch=gfx950", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

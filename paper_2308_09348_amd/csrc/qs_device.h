@@ -631,44 +631,11 @@ __device__ __forceinline__ float erfc_pos(float a, float ea2) {
     return t * ea2 * __expf(p);
 }
 
-// 0.5 erfc(|z| / sqrt2): the Gaussian tail beyond |z| standard deviations.
-__device__ __forceinline__ float gauss_tail(float z) {
-    const float a = fabsf(z) * 0.70710678118654752440f;
-    return 0.5f * erfc_pos(a, __expf(-a * a));
-}
-
-struct PsiPair {
-    float P, Pc;  // Psi(x) and Psi(x) - x
-};
-// Box (x) Gaussian law at a position: x = the upper box end of the edge for
-// a law up to 4 bins wide (Psi(x) = x Phi(x/s) + s phi(x/s) and Psi(x) - x =
-// -x Phi(-x/s) + s phi(x/s), each formed from the tail on its own side, no
-// cancellation), x = the edge itself for a wider one (F_wide: the series'
-// tail mass on the side of x).  One exponential serves phi and the tail.
-__device__ __forceinline__ PsiPair psi_pair(float x, float s, float inv_s, float beta2,
-                                            bool wide, float &F_wide) {
-    const float zz = x * inv_s;
-    const float e2 = __expf(-0.5f * zz * zz);  // relative error below 2e-6 out to 6 sigma
-    const float phz = 0.39894228040143267794f * e2;
-    const float ph = s * phz;
-    const float tail = 0.5f * erfc_pos(fabsf(zz) * 0.70710678118654752440f, e2);
-    const float lo = fmaf(x, tail, ph);   // Psi(x) when x <= 0
-    const float hi = fmaf(-x, tail, ph);  // Psi(x) - x when x > 0
-    PsiPair r;
-    r.P = zz <= 0.0f ? lo : hi + x;
-    r.Pc = zz <= 0.0f ? lo - x : hi;
-    // tail + a phi(a) (beta^2/24 + beta^4/1920 (a^2 - 3)), a = |z|: both
-    // even-order terms have the sign of the tail mass on either side
-    const float a = fabsf(zz);
-    const float c = beta2 * fmaf(beta2 * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
-    F_wide = wide ? fmaf(a * phz, c, tail) : 0.0f;
-    return r;
-}
-
 // One law of a lane, ready for the wavefront deposit: kind 1 box, 2 Gaussian,
-// 3 box (x) Gaussian over edges ka .. kb (t0 = edge ka - v); kind 0 when the
-// sample deposits as a point (NGP bin in `ngp`: 0 underflow, k + 1 for bin k,
-// n + 1 overflow), -1 when the lane has no sample.
+// 3 box (x) Gaussian, 4 box (x) Gaussian wider than 4 bins (the series), over
+// edges ka .. kb (t0 = edge ka - v; sf the width, for kind 4 beta^2 instead);
+// kind 0 when the sample deposits as a point (NGP bin in `ngp`: 0 underflow,
+// k + 1 for bin k, n + 1 overflow), -1 when the lane has no sample.
 struct LawLane {
     int kind, ka, kb, ngp;
     float t0, sf, inv_s;
@@ -701,6 +668,10 @@ __device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double
             L.t0 = (float)(fma((double)ka, w, lo) - v);
             L.sf = (float)se;
             L.inv_s = L.kind >= 2 ? (float)(1.0 / se) : 0.0f;
+            if (L.kind == 3 && se >= 4.0 * w) {
+                L.kind = 4;
+                L.sf = (float)((w / se) * (w / se));
+            }
         }
     }
     if (L.kind == 0) {
@@ -758,7 +729,7 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
     }
     const int off = incl - np;
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    WL.rec[lane] = make_int4(L.kind | (L.ka << 2), __float_as_int(L.t0), __float_as_int(L.sf),
+    WL.rec[lane] = make_int4(L.kind | (L.ka << 3), __float_as_int(L.t0), __float_as_int(L.sf),
                              __float_as_int(L.inv_s));
     WL.off[lane] = off;
     const float wf = (float)w, inv_w = (float)(1.0 / w);
@@ -777,7 +748,7 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         const int own = max(wave_incl_max(m), carry);
         carry = __builtin_amdgcn_readlane(own, 63);
         const int4 r = WL.rec[own];
-        const int kind = r.x & 3, ka = r.x >> 2;
+        const int kind = r.x & 7, ka = r.x >> 3;
         const int rel = p - WL.off[own] - 1;  // edge - ka
         const float t0 = __int_as_float(r.y), sf = __int_as_float(r.z);
         const float inv_s = __int_as_float(r.w);
@@ -785,31 +756,47 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         const bool live = p < total && rel >= 0;
         const float t = fmaf((float)rel, wf, t0);
         const bool upper = t > 0.0f;
-        // a box (x) Gaussian law wider than 4 bins takes the series (all its
-        // positions alike, so the box ends passed between lanes below are
-        // those of narrower laws only)
-        const bool wide = kind == 3 && sf >= 4.0f * wf;
-        PsiPair up{0.0f, 0.0f};
-        float Fw = 0.0f;
-        if (kind == 3) {
-            const float beta = wf * inv_s;
-            up = psi_pair(wide ? t : t + hf, sf, inv_s, beta * beta, wide, Fw);
+        // One Gaussian tail a position, without branches (one exponential
+        // serves phi and the tail): at the edge for the Gaussian law and the
+        // wide box (x) Gaussian (the series), at the upper box end x = t + b/2
+        // for the narrower box (x) Gaussian, whose CDF is a difference of
+        // Psi(x) = x Phi(x/s) + s phi(x/s) at the two box ends; Psi(x) and
+        // Psi(x) - x = -x Phi(-x/s) + s phi(x/s) are formed from the tail on
+        // the side of x (no cancellation) and consecutive edges share one end.
+        // All positions of a law are alike, so the box ends passed between
+        // lanes are those of narrow laws only.
+        const float x = kind == 3 ? t + hf : t;
+        const float zz = x * inv_s;
+        const float e2 = __expf(-0.5f * zz * zz);  // relative error below 2e-6 out to 6 sigma
+        const float phz = 0.39894228040143267794f * e2;
+        const float tail = 0.5f * erfc_pos(fabsf(zz) * 0.70710678118654752440f, e2);
+        float P = 0.0f, Pc = 0.0f, Fw = 0.0f;
+        if (__any(kind == 3)) {
+            const float ph = sf * phz;
+            const float lo = fmaf(x, tail, ph);   // Psi(x) when x <= 0
+            const float hi = fmaf(-x, tail, ph);  // Psi(x) - x when x > 0
+            P = zz <= 0.0f ? lo : hi + x;
+            Pc = zz <= 0.0f ? lo - x : hi;
         }
-        float lP = __shfl_up(up.P, 1, 64), lPc = __shfl_up(up.Pc, 1, 64);
+        if (__any(kind == 4)) {
+            // tail + a phi(a) (beta^2/24 + beta^4/1920 (a^2 - 3)), a = |z|
+            // (sf holds beta^2): both even-order terms have the sign of the
+            // tail mass on either side
+            const float a = fabsf(zz);
+            const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
+            Fw = fmaf(a * phz, c, tail);
+        }
+        float lP = __shfl_up(P, 1, 64), lPc = __shfl_up(Pc, 1, 64);
         if (lane == 0) {
             lP = cP;
             lPc = cPc;
         }
-        cP = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(up.P), 63));
-        cPc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(up.Pc), 63));
+        cP = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P), 63));
+        cPc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Pc), 63));
         if (live) {
-            float F;
-            if (kind == 3)
-                F = wide ? Fw : (upper ? (lPc - up.Pc) * inv_w : (up.P - lP) * inv_w);
-            else if (kind == 2)
-                F = gauss_tail(t * inv_s);
-            else
-                F = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
+            const float Fbox = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
+            const float Fpsi = upper ? (lPc - Pc) * inv_w : (P - lP) * inv_w;
+            float F = kind == 4 ? Fw : (kind == 3 ? Fpsi : (kind == 2 ? tail : Fbox));
             F = fminf(fmaxf(F, 0.0f), 1.0f);
             // below 1, 2^32 F rounds to at most 2^32 - 256: 32 bits
             const unsigned long long qf =
