@@ -322,10 +322,31 @@ struct FwdRad<double> {
     __device__ __forceinline__ void s3(double chi, double *t) { ev(chi, t); }
     __device__ __forceinline__ void s4(double chi, double *t) { ev(chi, t); }
 };
+// The same values from the FP64 table read a wavefront at a time
+// (RadTabWave; every lane of the wavefront active): the FP64 steps of
+// mixed-precision passes.
+struct FwdRadWave {
+    RadTabWave tw;
+    double nf = 0.0;  // unused: FP64 steps take the number from the rows
+    __device__ __forceinline__ FwdRadWave(const double *tab, double2 *stage) : tw(tab, stage) {}
+    __device__ __forceinline__ void init(double) {}
+    __device__ __forceinline__ void ev(double chi, double *t) {
+        double g, G1, G2, hq;
+        tw.eval(chi, g, G1, G2, hq);
+        t[0] = g;
+        t[1] = fma(2.0, g, G1);
+        t[2] = fma(0.5, G2, fma(2.0, G1, g));
+        t[3] = hq;
+    }
+    __device__ __forceinline__ void s1(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s2(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s3(double chi, double *t) { ev(chi, t); }
+    __device__ __forceinline__ void s4(double chi, double *t) { ev(chi, t); }
+};
 
 // One stage: slopes and the drift A (the photon energy per unit phase is -A).
-template <class T, bool QUANTUM, int S>
-__device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph, FwdRad<T> &rad,
+template <class T, bool QUANTUM, int S, class R = FwdRad<T>>
+__device__ __forceinline__ void photon_stage(T mu, T s2, T a, const Phys<T> &ph, R &rad,
                                              T &dmu, T &ds2, T &A, T &chi_hi, T &nf) {
     const T a2 = a * a;
     const T u = ph.K * a2;
@@ -359,6 +380,7 @@ struct PhotCtx {
     T a0, a0S0, h, psi0, ell, thx, thy;
     float inv_a0, tas;
     bool local, mid, angles, cell_number;
+    bool live;  // the lane's sample is real (else it runs for the wavefront's table reads only)
 };
 
 // The state carried from step to step (mu_lo, s2_lo: the FP32 pairs' lower
@@ -372,11 +394,10 @@ struct PhotState {
 // Step j of the photon pass: the four RK4 stages with their emission, the
 // deposits of stage 1 with the previous step's stage 4 (same amplitude) and
 // of stages 2 and 3, the emitted energy and the Sec. 5.1 angular sums.
-template <class T, bool QUANTUM>
+template <class T, bool QUANTUM, class R = FwdRad<T>>
 __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot &pp,
-                                            const float *tot, int j, PhotState<T> &st,
-                                            FwdRad<T> &rad, unsigned long long *grid,
-                                            PhotAcc &acc) {
+                                            const float *tot, int j, PhotState<T> &st, R &rad,
+                                            unsigned long long *grid, PhotAcc &acc) {
     const T h = c.h, hh = T(0.5) * h;
     const T c16 = T(1.0 / 6.0), c13 = T(1.0 / 3.0);
     const T psi = fma((T)j, h, c.psi0);
@@ -394,7 +415,7 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
     const T mu = st.mu, s2 = st.s2;
     // stage 4 of the previous step with stage 1 of this one (same
     // amplitude): one deposit at the geometric mean of the two energies
-    if (j > 0) {
+    if (j > 0 && c.live) {
         const float aa = fabsf((float)a1);
         if (aa > 0.0f) {
             const float v = 0.5f * ph_ln((float)st.m4_prev * (float)mu);
@@ -404,15 +425,15 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
     }
     T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
     T n1 = T(0), n2 = T(0), n3 = T(0), n4 = T(0);
-    photon_stage<T, QUANTUM, 1>(mu, s2, a1, c.ph, rad, k1m, k1s, A1, st.chi_hi, n1);
+    photon_stage<T, QUANTUM, 1, R>(mu, s2, a1, c.ph, rad, k1m, k1s, A1, st.chi_hi, n1);
     const T m2 = fma(hh, k1m, mu);
-    photon_stage<T, QUANTUM, 2>(m2, fma(hh, k1s, s2), ah, c.ph, rad, k2m, k2s, A2, st.chi_hi, n2);
+    photon_stage<T, QUANTUM, 2, R>(m2, fma(hh, k1s, s2), ah, c.ph, rad, k2m, k2s, A2, st.chi_hi, n2);
     const T m3 = fma(hh, k2m, mu);
-    photon_stage<T, QUANTUM, 3>(m3, fma(hh, k2s, s2), ah, c.ph, rad, k3m, k3s, A3, st.chi_hi, n3);
+    photon_stage<T, QUANTUM, 3, R>(m3, fma(hh, k2s, s2), ah, c.ph, rad, k3m, k3s, A3, st.chi_hi, n3);
     const T m4 = fma(h, k3m, mu);
-    photon_stage<T, QUANTUM, 4>(m4, fma(h, k3s, s2), a4, c.ph, rad, k4m, k4s, A4, st.chi_hi, n4);
-    acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
-    if (c.angles) {
+    photon_stage<T, QUANTUM, 4, R>(m4, fma(h, k3s, s2), a4, c.ph, rad, k4m, k4s, A4, st.chi_hi, n4);
+    if (c.live) acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
+    if (c.angles && c.live) {
         if (!c.cell_number) {  // from the rows
             auto rows = [&](T m, T a) {
                 const float aa = fabsf((float)a);
@@ -435,7 +456,7 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
         acc.ex += an.ex;
         acc.ey += an.ey;
     }
-    {  // stages 2 and 3 (same amplitude)
+    if (c.live) {  // stages 2 and 3 (same amplitude)
         const float aa = fabsf((float)ah);
         if (aa > 0.0f) {
             const float v = 0.5f * ph_ln((float)m2 * (float)m3);
@@ -464,9 +485,12 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                                               const double *__restrict__ env64,
                                               const float *tab32, unsigned long long *grid,
                                               const float *tot, const float4 *ncell,
-                                              PhotAcc &acc, double &loss) {
+                                              double2 *stage, bool live, PhotAcc &acc,
+                                              double &loss) {
     using T = typename std::conditional<PREC == PREC_F64, double, float>::type;
-    // FP32 with FP64 steps where chi is above the threshold (quantum only)
+    // FP32 with FP64 steps where chi is above the threshold (quantum only;
+    // every lane of the wavefront runs, live says whether the lane's sample
+    // is real and deposits, stage holds the wavefront's FP64 table rows)
     constexpr bool MIX = PREC == PREC_F32MIX;
     static_assert(!MIX || QUANTUM, "FP64 steps are a quantum-model option");
     const bool angles = pp.angles != nullptr;
@@ -526,6 +550,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     c.angles = angles;
     // FP32 quantum passes take the photon number from the radiation cells
     c.cell_number = PREC != PREC_F64 && QUANTUM && angles;
+    c.live = MIX ? live : true;
 
     FwdRad<T> rad;
     if constexpr (PREC == PREC_F64) {
@@ -550,7 +575,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     st.aS_next = c.mid ? c.a0 * c.pt.S((c.psi0 + c.h) * c.ell) : c.a0S0;
     if (QUANTUM) rad.init(c.ph.two_over_aS * st.mu * fabs(st.aS_prev * c.env[0]));
     // the first stage of the first step deposits alone
-    {
+    if (c.live) {
         const float aa = fabsf((float)(st.aS_prev * c.env[0]));
         if (aa > 0.0f)
             ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.mu), ph_ln(c.tas * aa),
@@ -581,6 +606,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                 cd.mid = false;
                 cd.angles = angles;
                 cd.cell_number = false;
+                cd.live = c.live;
                 PhotState<double> sd;
                 sd.mu = ((double)st.mu + (double)st.mu_lo) + g0_rest;
                 g0_rest = 0.0;  // now held by the state
@@ -591,10 +617,9 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                 sd.aS_next = 0.0;
                 sd.m4_prev = (double)st.m4_prev;
                 sd.chi_hi = 0.0;
-                FwdRad<double> radd;
-                radd.tab = P.rad64;
+                FwdRadWave radd(P.rad64, stage);
                 for (;;) {
-                    photon_step<double, QUANTUM>(cd, pp, tot, j, sd, radd, grid, acc);
+                    photon_step<double, QUANTUM, FwdRadWave>(cd, pp, tot, j, sd, radd, grid, acc);
                     ++j;
                     if (j >= N) break;
                     const double chi = P.two_over_aS * sd.mu * fabs(sd.aS_prev * env64[2 * j]);
@@ -617,6 +642,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
         photon_step<T, QUANTUM>(c, pp, tot, j, st, rad, grid, acc);
         ++j;
     }
+    if (!c.live) return;
     {  // the last stage 4 deposits alone
         const float aa = fabsf((float)(st.aS_prev * c.env[2 * N]));
         if (aa > 0.0f)
@@ -645,13 +671,24 @@ __device__ __forceinline__ int find_phot(const ShotPhot *ph, int n_shots, int64_
     return lo;
 }
 
-// The LDS (table, grid and photon-number cells, about 69 KB a block) allows
-// two blocks, two waves per SIMD: the registers are held to that (the FP64
-// and mixed-precision passes would otherwise take a few more and run one).
+// Block size of the photon kernel: mixed-precision passes read the FP64 table
+// a wavefront at a time and stage it in LDS (5 KB a wavefront), which beside
+// the table, grid and photon-number cells (about 69 KB) fits one block of 512
+// a CU; the others run blocks of 256, two a CU.  Either way two waves per
+// SIMD, and the registers are held to that (the FP64 and mixed-precision
+// passes would otherwise take a few more and run one).
+template <int PREC>
+constexpr int phot_block() {
+    return PREC == PREC_F32MIX ? 2 * kDepBlock : kDepBlock;
+}
+
 template <int PREC, bool QUANTUM, bool LOCAL>
-__global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(2))) void photon_kernel(BatchParams P,
-                                                           const float *__restrict__ env32,
-                                                           const double *__restrict__ env64) {
+__global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per_eu(2))) void photon_kernel(
+    BatchParams P, const float *__restrict__ env32, const double *__restrict__ env64) {
+    constexpr int kBlock = phot_block<PREC>();
+    // mixed precision: every lane of a wavefront runs (lanes past an item's
+    // end repeat its last sample without depositing), for the table reads
+    constexpr bool kWave64 = PREC == PREC_F32MIX;
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     __shared__ unsigned long long grid[kPhNodes];
@@ -659,7 +696,9 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(2))) 
     // ... and as a cubic on each FP32 radiation cell
     __shared__ float4 ncell[kTab32 ? kCells32 : 1];
     __shared__ int64_t slot;
-    __shared__ double red[kDepBlock / 64][kPhotPartials];
+    __shared__ double red[kBlock / 64][kPhotPartials];
+    __shared__ double2 stage[kWave64 ? (kBlock / 64) * kStageChunks : 1];
+    double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     for (int r = threadIdx.x; r < kPhRows; r += blockDim.x)
         tot[r] = (float)(cbrt(kPhYMax) * P.phtab[(size_t)r * (kPhNZ + 1) + kPhNZ]);
     if (kTab32) {
@@ -684,9 +723,19 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(2))) 
         double loss = 0.0;
         const int64_t i0 = (item - pp.pitem0) * kPhotTile;
         const int64_t i1 = i0 + kPhotTile < sp.n_samples ? i0 + kPhotTile : sp.n_samples;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-            photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, tot,
-                                                ncell, acc, loss);
+        if (kWave64) {
+            for (int64_t b = i0; b < i1; b += kBlock) {
+                const int64_t i = b + threadIdx.x;
+                const bool live = i < i1;
+                photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, live ? i : i1 - 1, env32, env64,
+                                                    tab32, grid, tot, ncell, wstage, live, acc,
+                                                    loss);
+            }
+        } else {
+            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+                photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, i, env32, env64, tab32, grid, tot,
+                                                    ncell, wstage, true, acc, loss);
+        }
         if (acc.flags) atomicOr(&P.flags[s], acc.flags);
         const double v[kPhotPartials] = {acc.e_ph, loss, acc.soft, acc.nn, acc.nx,
                                          acc.ny, acc.ee, acc.ex, acc.ey};
@@ -698,7 +747,7 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(2))) 
         __syncthreads();
         if (threadIdx.x < kPhotPartials) {
             double sum = 0.0;
-            for (int w = 0; w < kDepBlock / 64; ++w) sum += red[w][threadIdx.x];
+            for (int w = 0; w < kBlock / 64; ++w) sum += red[w][threadIdx.x];
             P.partials[(size_t)item * kPhotPartials + threadIdx.x] = sum;
         }
         for (int k = threadIdx.x; k < nodes; k += blockDim.x) {
@@ -860,14 +909,15 @@ hipError_t launch_photon(const BatchParams &p, const float *env32, const double 
     else
         fn = q ? (l ? photon_ptr<PREC_F32, true, true>() : photon_ptr<PREC_F32, true, false>())
                : (l ? photon_ptr<PREC_F32, false, true>() : photon_ptr<PREC_F32, false, false>());
+    const int block = prec == PREC_F32MIX && q ? phot_block<PREC_F32MIX>() : kDepBlock;
     int grid = 0;
-    hipError_t e = resident_grid(fn, kDepBlock, 0, p.n_pitems, &grid);
+    hipError_t e = resident_grid(fn, block, 0, p.n_pitems, &grid);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     const float *e32 = env32;
     const double *e64 = env64;
     void *args[] = {&pc, &e32, &e64};
-    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kDepBlock), args, 0, s);
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, 0, s);
 }
 
 hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t s) {
