@@ -139,7 +139,7 @@ typedef struct qs_bins {
     double th_lo_mrad, th_hi_mrad; /* angle window, hi > lo                     */
 } qs_bins;
 
-/* Moments written to qs_outputs.moments (16 doubles). */
+/* Moments written to qs_outputs.moments (QS_M_N doubles). */
 enum {
     QS_M_WEIGHT = 0,    /* number of samples                                    */
     QS_M_MEAN_G,        /* mean final Lorentz factor                            */
@@ -161,7 +161,15 @@ enum {
     QS_M_ERR_MU_MEAN,   /* mean (mu32 - mu64) / mu64 (signed)                   */
     QS_M_ERR_SIG_MAX,   /* max |sig32 - sig64| / mu64                           */
     QS_M_ERR_MEAN_G,    /* mean (mu32 - mu64): the FP32 bias of QS_M_MEAN_G     */
-    QS_M_N = 16
+    /* ... and the spectra: D_k = sum over the shadowed samples of the bin-k
+     * mass of the law deposited from (mu32, sig32) minus that from (mu64,
+     * sig64) (both CDFs exact in FP64, so D is the trajectories' part of the
+     * FP32 error); per shadowed sample, i.e. as a fraction of the weight: */
+    QS_M_ERR_E_L1,      /* sum_k |D_k| / n over the energy bins (+ under/over)  */
+    QS_M_ERR_E_MAX,     /* max_k |D_k| / n, energy                              */
+    QS_M_ERR_T_L1,      /* the same for the angle histogram                     */
+    QS_M_ERR_T_MAX,
+    QS_M_N = 20
 };
 
 /* Per-sample record (QS_S_N doubles) for diagnostics and parity checks. */

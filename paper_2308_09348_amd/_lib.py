@@ -20,10 +20,11 @@ PRECISION = {"fp32": 0, "fp64": 1}
 PROFILE = {"gauss": 0, "flat": 1}
 MODE = {"gauss": 0, "hg": 1, "lg": 2}
 
-M_N = 16
+M_N = 20
 # FP64 shadow of an FP32 pass (qs_numerics.flags) and its moment fields
 VALIDATE_FP64 = 1
 (M_SHADOW_N, M_ERR_MU_MAX, M_ERR_MU_MEAN, M_ERR_SIG_MAX, M_ERR_MEAN_G) = range(11, 16)
+(M_ERR_E_L1, M_ERR_E_MAX, M_ERR_T_L1, M_ERR_T_MAX) = range(16, 20)
 S_N = 11
 (M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, M_MEAN_AEFF,
  M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF) = range(11)

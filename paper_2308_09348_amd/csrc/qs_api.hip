@@ -835,7 +835,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     qs::BatchParams &bp = b.bp;
     qs::ShotOut *so = reinterpret_cast<qs::ShotOut *>(b.outs);
     qs::ShotParams *sv = reinterpret_cast<qs::ShotParams *>(b.outs + sizeof(qs::ShotOut) * n_shots);
-    int64_t sh_total = 0, sh_items = 0;
+    static_assert(qs::kMoments == QS_M_N, "moment count");
+    int64_t sh_total = 0, sh_items = 0, shd_words = 0;
     if (shadow) {
         const int stride = N->shadow_stride > 0 ? N->shadow_stride : 64;
         for (int k = 0; k < n_shots; ++k) {
@@ -843,6 +844,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
             const int64_t ns = (n_samples[k] + stride - 1) / stride;
             p.shadow_stride = stride;
             p.shadow_off = sh_total;
+            p.shd_off = shd_words;
+            shd_words += (int64_t)H[k].n_e + 2 + H[k].n_th + 2;
             sv[k] = p;
             sv[k].draw_stride = stride;
             sv[k].n_samples = ns;
@@ -872,8 +875,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     const size_t sarr = ((size_t)sh_total * 8 + 255) / 256 * 256;
     const size_t sarrf = ((size_t)sh_total * 4 + 255) / 256 * 256;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;
-    // work counters (phase, deposit, shadow phase, unused), flags, histograms
-    const size_t accum_words = 2 + flag_words + (size_t)b.hist_words;
+    // work counters (phase, deposit, shadow phase, unused), flags, histograms,
+    // FP64-shadow law differences
+    const size_t accum_words = 2 + flag_words + (size_t)b.hist_words + (size_t)shd_words;
     if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
     if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
@@ -911,6 +915,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     bp.queue = reinterpret_cast<unsigned int *>(c->accum);
     bp.flags = reinterpret_cast<int *>(c->accum + 2);
     bp.hist = c->accum + 2 + flag_words;
+    bp.shdiff = shadow ? bp.hist + b.hist_words : nullptr;
     bp.partials = c->partials;
     bp.tape = tape;
     bp.tape_n = b.total;

@@ -58,6 +58,7 @@ constexpr int kDepTile = 4096;    // default deposit work item: kDepTile samples
 // deposit work item (a multiple of it), so the moments do not depend on it.
 constexpr int kMomTile = 1024;
 constexpr int kPartials = P_N + 3;  // moment sums and maxima of a moment tile
+constexpr int kMoments = 20;        // moments a shot returns (QS_M_N)
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
 
@@ -94,6 +95,7 @@ struct ShotParams {
     // shadow_off + i / shadow_stride (shadow_stride 0: none); a shot view
     // with draw_stride > 1 integrates samples draw_stride i of the shot
     int64_t shadow_off;
+    int64_t shd_off;     // its per-bin FP32 - FP64 law differences [n_e + 2 | n_th + 2]
     int32_t shadow_stride, draw_stride;
     // bins
     int32_t n_e, n_th, n_a, pad2;
@@ -206,6 +208,8 @@ struct BatchParams {
     SampleState sst;        // FP64 shadow states of an FP32 pass
     // accumulators (device scratch, cleared before each launch)
     unsigned long long *hist;      // per shot: [n_e + 2 | n_th + 2 | n_a] in 32.32 fixed point
+    unsigned long long *shdiff;    // FP64 shadow, per shot: sum over the shadowed samples of
+                                   // (FP32-state law - FP64-state law) bin masses, signed, 2^-40
     unsigned int *chimax_bits;     // [n_shots]
     int *flags;                    // [n_shots]
     unsigned int *queue;           // [2]: phase and deposit work counters

@@ -332,6 +332,52 @@ __device__ void flush_edges(const unsigned long long *Q, const unsigned int *cnt
     }
 }
 
+// FP64 shadow, histogram level: the bin masses of a sample's law (its own law
+// convolved with the deposit kernel, as deposited) from its FP32 state minus
+// those from its FP64 state, added to D[n + 2] (bins, underflow n, overflow
+// n + 1) in signed fixed point of 2^-40 (the differences are small: units of
+// 2^-32 would round most of them away; a word holds up to 2^23 whole masses).  Both laws' CDFs are evaluated exactly
+// in FP64, so the difference is that of the two trajectories alone.  Only the
+// CDF difference at each edge matters: edge j adds it to the mass below
+// (bin j - 1, or the underflow) and subtracts it from the mass above (bin j,
+// or the overflow); edges beyond 9 standard deviations of both laws add
+// nothing at FP64 precision.
+__device__ double law_cdf64(double t, double s, int dep, double ksig, double w) {
+    const double r = 0.70710678118654752440;
+    if (dep == 2) {  // GAUSS: N(0, s^2 + (ksig bins)^2)
+        const double se = sqrt(fma(s, s, (ksig * w) * (ksig * w)));
+        return 0.5 * erfc(-t * r / se);
+    }
+    if (dep == 1) {  // CIC: box one bin wide (x) N(0, s^2)
+        const double h = 0.5 * w;
+        if (!(s > 0.0)) return fmin(fmax((t + h) / w, 0.0), 1.0);
+        auto psi = [&](double x) {  // Int_-inf^x Phi(u / s) du
+            return x * 0.5 * erfc(-x * r / s) + s * 0.39894228040143267794 * exp(-0.5 * (x / s) * (x / s));
+        };
+        return fmin(fmax((psi(t + h) - psi(t - h)) / w, 0.0), 1.0);
+    }
+    if (!(s > 0.0)) return t > 0.0 ? 1.0 : 0.0;  // POINT: a value on an edge goes up
+    return 0.5 * erfc(-t * r / s);
+}
+
+__device__ void shadow_law_diff(double v32, double s32, double v64, double s64, int dep,
+                                double ksig, double lo, double w, int n,
+                                unsigned long long *D) {
+    double reach = 9.0 * fmax(s32, s64) + w;
+    if (dep == 2) reach += 9.0 * ksig * w;
+    const double a = fmin(v32, v64) - reach, b = fmax(v32, v64) + reach;
+    const int ja = (int)fmin(fmax(ceil((a - lo) / w), 0.0), (double)n + 1.0);
+    const int jb = (int)fmin(fmax(floor((b - lo) / w), -1.0), (double)n);
+    for (int j = ja; j <= jb; ++j) {
+        const double e = fma((double)j, w, lo);
+        const double d = law_cdf64(e - v32, s32, dep, ksig, w) - law_cdf64(e - v64, s64, dep, ksig, w);
+        const long long q = llrint(d * 1099511627776.0);
+        if (q == 0) continue;
+        atomicAdd(&D[j == 0 ? n : j - 1], (unsigned long long)q);
+        atomicAdd(&D[j == n ? n + 1 : j], (unsigned long long)(-q));
+    }
+}
+
 __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t slot;
@@ -424,6 +470,14 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
                                 acc[P_SHG] += d;
                                 emu = fmax(emu, fabs(d) / m64);
                                 esig = fmax(esig, fabs(sigf - s64) / m64);
+                                // the two states' laws, bin by bin (energy, angle)
+                                const double sth64 = 1e3 * P.c_theta * 0.79788456080286535588 *
+                                                     a_eff * s64 / (m64 * m64);
+                                unsigned long long *D = P.shdiff + sp.shd_off;
+                                shadow_law_diff(mu_f, sigf, m64, s64, P.deposit, P.ksig_bins,
+                                                sp.e_lo, sp.e_w, sp.n_e, D);
+                                shadow_law_diff(thx_m, sigth, thx_m, sth64, P.deposit, P.ksig_bins,
+                                                sp.th_lo, sp.th_w, sp.n_th, D + sp.n_e + 2);
                             }
                         }
 
@@ -530,9 +584,37 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
     for (int k = threadIdx.x; k < sp.n_a; k += blockDim.x)
         so.a0eff_hist[k] = (double)H[nh_e + nh_t + k] * scale;
     __syncthreads();
+    // FP64 shadow, histogram level: L1 and largest bin of the summed law
+    // differences, energy then angle, per shadowed sample
+    __shared__ double shd[4];
+    if (sp.shadow_stride > 0 && sums[P_SHN] > 0.0) {
+        const unsigned long long *D = P.shdiff + sp.shd_off;
+        for (int h = 0; h < 2; ++h) {
+            const int n0 = h == 0 ? 0 : nh_e, n1 = h == 0 ? nh_e : nh_e + nh_t;
+            double l1 = 0.0, mx = 0.0;
+            for (int k = n0 + threadIdx.x; k < n1; k += blockDim.x) {
+                const double v = fabs((double)(long long)D[k]) * (1.0 / 1099511627776.0);
+                l1 += v;
+                mx = fmax(mx, v);
+            }
+            for (int part = 0; part < 2; ++part) {
+                tree[threadIdx.x] = part == 0 ? l1 : mx;
+                __syncthreads();
+                for (int w = 128; w > 0; w >>= 1) {
+                    if (threadIdx.x < w) {
+                        const double o = tree[threadIdx.x + w];
+                        tree[threadIdx.x] = part == 0 ? tree[threadIdx.x] + o : fmax(tree[threadIdx.x], o);
+                    }
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) shd[2 * h + part] = tree[0] / sums[P_SHN];
+                __syncthreads();
+            }
+        }
+    }
     if (threadIdx.x == 0) {
         double *M = so.moments;
-        for (int m = 0; m < 16; ++m) M[m] = 0.0;
+        for (int m = 0; m < kMoments; ++m) M[m] = 0.0;
         const double W = (double)sp.n_samples;
         M[0] = W;
         if (sp.n_samples > 0) {
@@ -554,6 +636,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
                 M[13] = sums[P_SHMU] / ns;
                 M[14] = sums[kPMaxEsig];
                 M[15] = sums[P_SHG] / ns;
+                for (int q = 0; q < 4; ++q) M[16 + q] = shd[q];
             }
         }
         const int fl = P.flags[s];

@@ -78,3 +78,46 @@ def test_shadow_in_a_batch_equals_single_shots(gpu):
         for key in single:
             assert np.array_equal(batch[k][key], single[key]), (k, key)
     assert batch[1]["moments"][_lib.M_SHADOW_N] == 1
+
+
+@pytest.mark.parametrize("deposit", ["cic", "gauss", "point"])
+def test_shadow_spectrum_errors(gpu, oracle, deposit):
+    """The histogram-level shadow fields: D_k = sum over the shadowed samples
+    of the law deposited from the FP32 state minus that from the FP64 state
+    (the FP64 pass's records give the latter), through the oracle's deposit;
+    L1 and largest bin per shadowed sample, energy and angle.  Bars: the
+    device quantises each edge's CDF difference to 2^-40 (at most 2^-40 per
+    bin and shadowed sample), and the oracle's law stops at 6 standard
+    deviations (the device's difference runs to 9: 2e-9 of a law's mass,
+    times the relative shift of the two laws)."""
+    stride = 7
+    p = workloads.scaled(workloads.focused_3d(), n_samples=5037, n_steps=256, deposit=deposit)
+    n = p["n_samples"]
+    g = _run(gpu, dict(p, validate_fp64=True, shadow_stride=stride))
+    d = _run(gpu, dict(p, precision="fp64"))
+    idx = np.arange(0, n, stride)
+    r32, r64 = g["samples"][idx], d["samples"][idx]
+    De = np.zeros(p["n_e"] + 2)
+    Dt = np.zeros(p["n_th"] + 2)
+    for a, b in zip(r32, r64):
+        De += oracle.deposit(a[0], np.sqrt(max(a[1], 0.0)), deposit, p["kernel_sigma_bins"],
+                             p["e_lo"], p["e_hi"], p["n_e"])
+        De -= oracle.deposit(b[0], np.sqrt(max(b[1], 0.0)), deposit, p["kernel_sigma_bins"],
+                             p["e_lo"], p["e_hi"], p["n_e"])
+        Dt += oracle.deposit(a[2], a[4], deposit, p["kernel_sigma_bins"], p["th_lo_mrad"],
+                             p["th_hi_mrad"], p["n_th"])
+        Dt -= oracle.deposit(b[2], b[4], deposit, p["kernel_sigma_bins"], p["th_lo_mrad"],
+                             p["th_hi_mrad"], p["n_th"])
+    ns = len(idx)
+    m = g["moments"]
+    want = [np.abs(De).sum() / ns, np.abs(De).max() / ns, np.abs(Dt).sum() / ns,
+            np.abs(Dt).max() / ns]
+    got = [m[_lib.M_ERR_E_L1], m[_lib.M_ERR_E_MAX], m[_lib.M_ERR_T_L1], m[_lib.M_ERR_T_MAX]]
+    print(deposit, "want", want, "got", got)
+    # the FP32 pass differs from the FP64 one, and the fields say by how much
+    assert want[0] > 0 and got[0] > 0
+    # quantisation: at most 2^-40 a bin and shadowed sample (L1: times the bins)
+    for w_, g_, nb in zip(want, got, (p["n_e"] + 2, 1, p["n_th"] + 2, 1)):
+        assert abs(g_ - w_) <= 1e-6 * w_ + nb * 2.0 ** -40, (deposit, want, got)
+    # an FP32 pass without the shadow leaves them zero
+    assert not _run(gpu, p)["moments"][11:].any()
