@@ -356,7 +356,9 @@ def main():
     line["fp64_shadow"] = {
         "shadow_stride": 64, "samples": int(mv[11]), "ms_per_pass": 1e3 * (time.perf_counter() - t0),
         "err_mu_max": float(mv[12]), "err_mu_mean": float(mv[13]), "err_sig_max": float(mv[14]),
-        "err_mean_gamma": float(mv[15])}
+        "err_mean_gamma": float(mv[15]), "err_energy_hist_l1": float(mv[16]),
+        "err_energy_hist_max_bin": float(mv[17]), "err_angle_hist_l1": float(mv[18]),
+        "err_angle_hist_max_bin": float(mv[19])}
     if args.batched_steps > 0:
         # batched leg: 4096 shots of uneven size in one launch, with the launch
         # choices of the tuner (cached per device and launch class) and the
