@@ -849,6 +849,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
             sv[k] = p;
             sv[k].draw_stride = stride;
             sv[k].n_samples = ns;
+            sv[k].src_off = p.state_off;
             sv[k].state_off = sh_total;
             sv[k].item0 = sh_items;
             sh_total += ns;
@@ -956,6 +957,11 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
             if ((e = qs::launch_phase(bs, c->env32, c->env64, qs::PREC_F64, N->rr_model,
                                       N->amp_mode, q)) != hipSuccess)
                 return hip_fail(c, e, "shadow phase kernel");
+            // the two states' laws of every shadowed sample, bin by bin
+            qs::BatchParams bd = bp;
+            bd.shots = bs.shots;
+            if ((e = qs::launch_shadow_diff(bd, sh_items, b.max_nh, q)) != hipSuccess)
+                return hip_fail(c, e, "shadow difference kernel");
         }
         if ((e = mark(3)) != hipSuccess) return hip_fail(c, e, "event record");
         if ((e = qs::launch_deposit(bp, b.max_nh, q)) != hipSuccess)

@@ -96,6 +96,7 @@ struct ShotParams {
     // with draw_stride > 1 integrates samples draw_stride i of the shot
     int64_t shadow_off;
     int64_t shd_off;     // its per-bin FP32 - FP64 law differences [n_e + 2 | n_th + 2]
+    int64_t src_off;     // shadow view: the FP32 state of the shot's sample 0
     int32_t shadow_stride, draw_stride;
     // bins
     int32_t n_e, n_th, n_a, pad2;
@@ -228,6 +229,8 @@ hipError_t launch_phase(const BatchParams &p, const float *env32, const double *
 size_t deposit_lds_bytes(int max_hist_words);
 hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t s);
 hipError_t launch_finalize(const BatchParams &p, hipStream_t s);
+hipError_t launch_shadow_diff(const BatchParams &p, int64_t n_items, int max_hist_words,
+                              hipStream_t s);
 hipError_t launch_radiation_eval(const float *rad32, const double *rad64, int prec, int64_t n,
                                  const double *chi, double *out, int *flags, hipStream_t s);
 hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, int prec, int64_t n,

@@ -360,7 +360,7 @@ __device__ double law_cdf64(double t, double s, int dep, double ksig, double w) 
     return 0.5 * erfc(-t * r / s);
 }
 
-__device__ void shadow_law_diff(double v32, double s32, double v64, double s64, int dep,
+__device__ __forceinline__ void shadow_law_diff(double v32, double s32, double v64, double s64, int dep,
                                 double ksig, double lo, double w, int n,
                                 unsigned long long *D) {
     double reach = 9.0 * fmax(s32, s64) + w;
@@ -375,6 +375,45 @@ __device__ void shadow_law_diff(double v32, double s32, double v64, double s64, 
         if (q == 0) continue;
         atomicAdd(&D[j == 0 ? n : j - 1], (unsigned long long)q);
         atomicAdd(&D[j == n ? n + 1 : j], (unsigned long long)(-q));
+    }
+}
+
+// One lane per shadowed sample, over the work items of the shadow view
+// (P.shots; an item lies within one shot; the FP32 state of shadowed sample q
+// is src_off + q draw_stride, its FP64 state state_off + q in P.sst): the law
+// differences summed per item in LDS, then added to the shot's words.  A
+// kernel of its own keeps the FP64 CDFs off the deposit's register budget.
+__global__ __launch_bounds__(kPhaseBlock) void shadow_diff_kernel(BatchParams P, int64_t n_items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long *D = reinterpret_cast<unsigned long long *>(smem);
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+        const ShotParams &sv = P.shots[s];
+        const int nd = sv.n_e + 2 + sv.n_th + 2;
+        for (int k = threadIdx.x; k < nd; k += blockDim.x) D[k] = 0ull;
+        __syncthreads();
+        const int64_t q = (item - sv.item0) * kPhaseBlock + threadIdx.x;
+        if (q < sv.n_samples) {
+            const int64_t k32 = sv.src_off + q * sv.draw_stride, k64 = sv.state_off + q;
+            const double mu_f = P.st.mu[k32], s2_f = P.st.s2[k32];
+            const double m64 = P.sst.mu[k64];
+            if (mu_f > 0.0 && isfinite(mu_f) && isfinite(s2_f) && m64 > 0.0) {
+                const double thx_m = 1e3 * P.st.thx[k32];
+                const double sigf = sqrt(fmax(s2_f, 0.0)), s64 = sqrt(fmax(P.sst.s2[k64], 0.0));
+                // Sec. 5.2 broadening of either state, as deposited
+                const double c = 1e3 * P.c_theta * 0.79788456080286535588 * sv.a0 * P.st.S0[k32];
+                const double sth32 = c * sigf / (mu_f * mu_f), sth64 = c * s64 / (m64 * m64);
+                shadow_law_diff(mu_f, sigf, m64, s64, P.deposit, P.ksig_bins, sv.e_lo, sv.e_w,
+                                sv.n_e, D);
+                shadow_law_diff(thx_m, sth32, thx_m, sth64, P.deposit, P.ksig_bins, sv.th_lo,
+                                sv.th_w, sv.n_th, D + sv.n_e + 2);
+            }
+        }
+        __syncthreads();
+        unsigned long long *G = P.shdiff + sv.shd_off;
+        for (int k = threadIdx.x; k < nd; k += blockDim.x)
+            if (D[k]) atomicAdd(&G[k], D[k]);
+        __syncthreads();  // the next item clears D
     }
 }
 
@@ -470,14 +509,6 @@ __global__ __launch_bounds__(kDepBlock) void deposit_kernel(BatchParams P) {
                                 acc[P_SHG] += d;
                                 emu = fmax(emu, fabs(d) / m64);
                                 esig = fmax(esig, fabs(sigf - s64) / m64);
-                                // the two states' laws, bin by bin (energy, angle)
-                                const double sth64 = 1e3 * P.c_theta * 0.79788456080286535588 *
-                                                     a_eff * s64 / (m64 * m64);
-                                unsigned long long *D = P.shdiff + sp.shd_off;
-                                shadow_law_diff(mu_f, sigf, m64, s64, P.deposit, P.ksig_bins,
-                                                sp.e_lo, sp.e_w, sp.n_e, D);
-                                shadow_law_diff(thx_m, sigth, thx_m, sth64, P.deposit, P.ksig_bins,
-                                                sp.th_lo, sp.th_w, sp.n_th, D + sp.n_e + 2);
                             }
                         }
 
@@ -771,6 +802,14 @@ hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t 
     e = resident_grid(fn, kDepBlock, lds, p.n_ditems, &grid, p.dep_cap);
     if (e != hipSuccess) return e;
     deposit_kernel<<<grid, kDepBlock, lds, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow_diff(const BatchParams &p, int64_t n_items, int max_hist_words,
+                              hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const int grid = (int)(n_items < 2048 ? n_items : 2048);
+    shadow_diff_kernel<<<grid, kPhaseBlock, (size_t)max_hist_words * 8, s>>>(p, n_items);
     return hipGetLastError();
 }
 
