@@ -131,21 +131,6 @@ struct RadSrc<double> {
     __device__ __forceinline__ RadJ<double> s4(double chi) { return radj_eval64(tab, chi); }
 };
 
-// FP32 derivative table looked up afresh at every stage (no cells carried:
-// the FP64 steps of the mixed loop keep their registers for the FP64 table).
-struct RadSrcFresh {
-    const float *tab;
-    __device__ __forceinline__ RadJ<float> ev(float chi) const {
-        RadCell6 c;
-        rad6_lookup32(tab, chi, c);
-        return rad6_cell_eval(c, chi);
-    }
-    __device__ __forceinline__ RadJ<float> s1(float chi) const { return ev(chi); }
-    __device__ __forceinline__ RadJ<float> s2(float chi) const { return ev(chi); }
-    __device__ __forceinline__ RadJ<float> s3(float chi) const { return ev(chi); }
-    __device__ __forceinline__ RadJ<float> s4(float chi) const { return ev(chi); }
-};
-
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
@@ -672,17 +657,16 @@ __device__ __forceinline__ void tangent_update(const StepLin<T, QUANTUM> &L, con
 // FP64 step (FP64 amplitudes, the FP64 table read a wavefront at a time);
 // the tangents by the FP32 step linearisation at the state rounded to FP32,
 // with the FP32 amplitude derivatives and derivative table as in the FP32
-// steps (the linearisation is rounded to FP32 either way), its table cells
-// looked up at every stage.  A1 and da1 carry over to the step the segment
-// returns, the first not taken.
+// steps (the linearisation is rounded to FP32 either way), with the FP32
+// loop's table cells carried from stage to stage as there.  A1, da1 and those
+// cells carry over to the step the segment returns, the first not taken.
 template <bool LOCAL, int ND, int GD>
 __device__ __forceinline__ int tangent_fp64_segment(
     const BatchParams &P, const AdjPath<double> &pd, double S0d, const AdjPath<float> &pf,
     float S0f, const float *__restrict__ env32, const double *__restrict__ env64, double2 *stage,
-    const float *tab32, const Phys<float> &phf, int j, double &mu, double &s2, float *vm,
+    RadSrc<float> &rad, const Phys<float> &phf, int j, double &mu, double &s2, float *vm,
     float *vs, float *da1, StageAmp<float> &A1, float &cmx, float &chi_hi, double &chd) {
     const RadTabWave tabd(P.rad64, stage);
-    RadSrcFresh rad{tab32};
     const Phys<double> phd{P.K, P.CD, P.two_over_aS};
     const int N = P.n_steps;
     const double h = P.h, psi0 = -P.psi_max, ell = P.ell_per_psi;
@@ -714,7 +698,7 @@ __device__ __forceinline__ int tangent_fp64_segment(
         amp32(psif + hf, env32[2 * j + 2], a4f, da4);
         const StageAmp<float> Ah(ahf, phf), A4(a4f, phf);
         const StepLin<float, true> L =
-            rk4_linear<float, true, RadSrcFresh>((float)mu, (float)s2, A1, Ah, A4, hf, rad, chi_hi);
+            rk4_linear<float, true>((float)mu, (float)s2, A1, Ah, A4, hf, rad, chi_hi);
         tangent_update<float, true, ND, GD>(L, da1, dah, da4, vm, vs);
         A1 = A4;
 #pragma unroll
@@ -821,21 +805,19 @@ __device__ __forceinline__ void tangent_sample(const BatchParams &P, const ShotP
             if (__any(chi1 > P.chi_fp64)) {
                 // FP64 steps while some lane of the wavefront has chi above
                 // the threshold; the FP32 pair takes the state back at the
-                // exit step (amplitude and derivatives carry over, the FP32
-                // cell is looked up again)
+                // exit step (amplitude, derivatives and cells carry over)
                 double mud = ((double)mu + (double)mu_lo) + g0_rest;
                 double s2d = (double)s2 + (double)s2_lo;
                 g0_rest = 0.0;  // now held by the state
                 AdjSample sd;
                 adj_sample(P, sp, opaque_index(i), sd);
                 j = tangent_fp64_segment<LOCAL, ND, GD>(P, sd.p, sd.d0.S, pth, S0, env32, env64,
-                                                        stage, tab32, ph, j, mud, s2d, vm, vs, da1,
+                                                        stage, rad, ph, j, mud, s2d, vm, vs, da1,
                                                         A1, cmx, chi_hi, chd);
                 mu = (float)mud;
                 mu_lo = (float)(mud - (double)mu);
                 s2 = (float)s2d;
                 s2_lo = (float)(s2d - (double)s2);
-                if (j < N) rad.init(A1.chi_per_mu * mu);
                 continue;
             }
         }
