@@ -42,7 +42,7 @@ typedef enum qs_status {
     QS_ENOMEM = 2,        /* device allocation failed                          */
     QS_EDEVICE = 3,       /* a HIP runtime call failed                         */
     QS_ENONFINITE = 4,    /* a sample reached a non-finite state (device-side) */
-    QS_EUNSUPPORTED = 5,  /* valid but not supported by this build             */
+    QS_EUNSUPPORTED = 5,  /* valid but not supported by this library           */
     QS_ERANGE = 6         /* chi left the tabulated range [0, 256) (device)    */
 } qs_status;
 
