@@ -1,0 +1,115 @@
+"""The batched workloads at their full sizes, in the launch configuration the
+benchmark times (launch choices from the committed tuner cache, the forward
+launch replayed from a HIP graph), checked on sampled outputs the oracle can
+compute one by one, and through properties that hold at any size:
+
+  - 4096 shots, samples log-uniform in [2^12, 2^18], 512 steps: every shot's
+    histograms carry exactly its samples, status clean; sampled final states
+    of shots across the batch against the oracle's (FP32 bars);
+  - 256 shots x 2^18 samples x 2048 steps with FP64 steps where chi > 0.1:
+    the same for the spectra pass, and sampled entries of the derivative tape
+    against the oracle's per-sample derivatives (FP32 tangent bars).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2308_09348_amd import _lib, workloads
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma", "div_mrad"]
+SCALE = {"a0": 1.0, "w0_um": 3.0, "x_off_um": 3.0, "y_off_um": 3.0, "delay_fs": 30.0,
+         "gamma0": 1.0, "sigma_gamma": 1.0, "div_mrad": 1.0}
+CACHE = os.path.join(os.path.dirname(_lib.__file__), "tune_cache.txt")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09348_amd as qs
+    ctx = qs.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _with_records(ctx, batch, picks, n_rec):
+    """Ask the prepared batch for n_rec evenly spaced sample records of the
+    picked shots; returns the record strides."""
+    import torch
+    strides = {}
+    for k, n in picks:
+        stride = max(n // n_rec, 1)
+        o = batch.out[k]
+        o["samples"] = torch.empty((n_rec, _lib.S_N), dtype=torch.float64,
+                                   device=torch.device("cuda", ctx.device))
+        batch.outs[k].samples = o["samples"].data_ptr()
+        batch.outs[k].sample_stride = stride
+        batch.outs[k].n_sample_records = n_rec
+        strides[k] = stride
+    return strides
+
+
+def _check_records(oracle, shot, rec, stride, n_rec, mu_tol):
+    idx = list(range(0, n_rec * stride, stride))
+    ref = oracle.samples(shot, idx)
+    assert np.allclose(rec[:, 0], ref[:, oracle.S_MU], rtol=mu_tol, atol=0), shot["shot"]
+    assert np.allclose(rec[:, 1], ref[:, oracle.S_SIG2], rtol=3e-5,
+                       atol=3e-5 * max(ref[:, oracle.S_SIG2].max(), 1.0)), shot["shot"]
+    assert np.array_equal(rec[:, 7], ref[:, oracle.S_GAMMA0]) or \
+        np.allclose(rec[:, 7], ref[:, oracle.S_GAMMA0], rtol=1e-15, atol=0)
+
+
+def test_batched_shots_full_size(gpu, oracle):
+    shots = workloads.batched_shots()
+    batch = gpu.prepare_batch(shots)
+    gpu.tune(batch, cache_path=CACHE)
+    gpu.set_graphs(True)
+    n_rec = 8
+    picks = [(k, shots[k]["n_samples"]) for k in (0, 517, 1400, 2047, 3333, 4095)]
+    strides = _with_records(gpu, batch, picks, n_rec)
+    outs = gpu.run_batch(batch)
+    hist_sums = np.array([o["energy_hist"].sum().item() for o in outs])
+    assert np.array_equal(hist_sums, np.array([s["n_samples"] for s in shots], dtype=float))
+    for k, _ in picks:
+        rec = outs[k]["samples"].cpu().numpy()
+        _check_records(oracle, shots[k], rec, strides[k], n_rec, 3e-6)
+    gpu.set_graphs(False)
+
+
+def test_quantum_batch_full_size(gpu, oracle):
+    import torch
+    shots = workloads.quantum_batch()
+    batch = gpu.prepare_batch(shots)
+    gpu.tune(batch, cache_path=CACHE)
+    n_rec = 6
+    picks = [(k, shots[k]["n_samples"]) for k in (0, 101, 255)]
+    strides = _with_records(gpu, batch, picks, n_rec)
+    outs = gpu.run_batch(batch)
+    for k, o in enumerate(outs):
+        assert o["energy_hist"].sum().item() == shots[k]["n_samples"], k
+    assert max(o["moments"][_lib.M_MAX_CHI].item() for o in outs) > 1.0  # FP64 steps taken
+    for k, _ in picks:
+        rec = outs[k]["samples"].cpu().numpy()
+        _check_records(oracle, shots[k], rec, strides[k], n_rec, 3e-6)
+    # the derivative tape of the whole batch, sampled
+    total = sum(s["n_samples"] for s in shots)
+    tape = gpu.new_tape(total)
+    gpu.run_batch(gpu.prepare_batch(shots), tape=tape)
+    off = {k: sum(s["n_samples"] for s in shots[:k]) for k, _ in picks}
+    for k, n in picks:
+        for i in (0, n // 3, n - 1):
+            t = tape[:, off[k] + i].cpu().numpy()
+            m, s2 = oracle.sample_grad(shots[k], i)
+            assert abs(t[0] - m[0]) <= 3e-6 * abs(m[0]), (k, i)
+            assert abs(t[1] - s2[0]) <= 3e-5 * abs(s2[0]) + 1e-6 * m[0] ** 2, (k, i)
+            for q, name in enumerate(NAMES):
+                fl = 1e-6 * abs(m[0]) / SCALE[name]
+                assert abs(t[2 + q] - m[1 + q]) <= 1e-4 * abs(m[1 + q]) + fl, (k, i, name)
+                assert abs(t[10 + q] - s2[1 + q]) <= 1e-4 * abs(s2[1 + q]) + fl * abs(m[0]), \
+                    (k, i, name)
+    del tape
+    torch.cuda.empty_cache()
