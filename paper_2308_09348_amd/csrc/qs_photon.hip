@@ -218,10 +218,15 @@ struct AngStep {
     __device__ __forceinline__ void add(T c, T a, T mu, T A, T thx, T thy, T nf) {
         const T aa = fabs(a);
         T imu;
-        if constexpr (sizeof(T) == 4)
+        if constexpr (sizeof(T) == 4) {
             imu = __builtin_amdgcn_rcpf(mu);  // about one ulp
-        else
-            imu = T(1) / mu;
+        } else {
+            // the hardware reciprocal refined by two Newton steps (each
+            // squares the relative error): FP64 rounding for mu >= 1
+            imu = __builtin_amdgcn_rcp(mu);
+            imu = fma(fma(-mu, imu, 1.0), imu, imu);
+            imu = fma(fma(-mu, imu, 1.0), imu, imu);
+        }
         const T tx = fma(a, imu, thx), cone = imu * imu;
         const T x2 = fma(tx, tx, cone), y2 = fma(thy, thy, cone);
         const T dn = c * aa * nf;
