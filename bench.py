@@ -178,7 +178,7 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
             "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
 
-def quantum_batch_leg(ctx, workloads, torch, steps):
+def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
     """256 shots of 2^18 samples x 2048 steps, quantum (FP64 steps where
     chi > 0.1): per step the electron spectra, the derivative tape and per-shot
     gradients of a Neyman chi^2 loss against per-shot Poisson targets, and the
@@ -187,6 +187,9 @@ def quantum_batch_leg(ctx, workloads, torch, steps):
     total = sum(p["n_samples"] for p in shots)
     N = shots[0]["n_steps"]
     batch = ctx.prepare_batch(shots)
+    # launch choices of the spectra pass from the tuner cache (tuned once
+    # if the class is not there)
+    tuning = ctx.tune(batch, cache_path=tune_cache) if tune_cache else None
     tape = ctx.new_tape(total)
     n_tot = 1e6
     ref = ctx.run_batch(batch)
@@ -236,7 +239,8 @@ def quantum_batch_leg(ctx, workloads, torch, steps):
             "n_shots": len(shots), "n_samples": total, "n_steps": N, "steps": steps,
             "ms_per_step": 1e3 * dt,
             "ms_parts": {k: 1e3 * v / steps for k, v in parts.items()},
-            "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt}
+            "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt,
+            "tuning": tuning}
 
 
 def factorised_leg(ctx, workloads, torch, steps):
@@ -393,7 +397,8 @@ def main():
     if args.adjoint_steps > 0:
         line["adjoint"] = adjoint_leg(ctx, qs, workloads, torch, args.adjoint_steps)
     if args.quantum_batch_steps > 0:
-        line["quantum_batch"] = quantum_batch_leg(ctx, workloads, torch, args.quantum_batch_steps)
+        line["quantum_batch"] = quantum_batch_leg(ctx, workloads, torch, args.quantum_batch_steps,
+                                                  args.tune_cache)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
