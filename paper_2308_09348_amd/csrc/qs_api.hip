@@ -979,6 +979,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
             double psi_max, h, omega_tau;
             const void *env32, *env64, *accum;
             int64_t accum_words;
+            // the FP64 shadow's launches take these by value
+            int64_t sh_items, sh_total;
+            int32_t shadow;
             int32_t n_steps, envelope, prec, rr, amp, max_nh;
         } sig;
         std::memset(&sig, 0, sizeof(sig));
@@ -990,6 +993,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         sig.env64 = c->env64;
         sig.accum = c->accum;
         sig.accum_words = (int64_t)accum_words;
+        sig.sh_items = sh_items;
+        sig.sh_total = sh_total;
+        sig.shadow = shadow ? 1 : 0;
         sig.n_steps = N->n_steps;
         sig.envelope = L[0].envelope;
         sig.prec = b.prec;
