@@ -216,6 +216,33 @@ qs_status qs_forward(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
                      const qs_numerics *num, const qs_bins *bins,
                      const qs_outputs *out, void *stream);
 
+/* Largest n_samples of qs_forward_noalloc. */
+#define QS_NOALLOC_MAX_SAMPLES (1 << 20)
+
+/* qs_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same pass, kernels and results (bit for bit) as qs_forward, with every
+ * piece of device scratch -- the per-sample final states, the envelope
+ * tables, the accumulators, the moment partials and the device shot table --
+ * taken from one static device array of about 55 MiB that each GPU the library
+ * runs on holds until the process ends (its address is looked up by
+ * qs_create, which also makes the call's pinned staging block and event).
+ * The call itself allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine, and it never captures a HIP graph.  Limits: one shot of at
+ * most QS_NOALLOC_MAX_SAMPLES samples; every other size as qs_forward (steps
+ * up to 65536, bins up to 4096 each).  The caller still owns and passes the
+ * outputs.  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind (the accumulators are cleared by a kernel at the start of
+ * each call): calls that overlap on one GPU -- on different streams, or from
+ * different contexts on the same device -- race and give wrong results;
+ * order them on one stream.
+ * Errors: as qs_forward; QS_EINVAL for n_samples above
+ * QS_NOALLOC_MAX_SAMPLES; QS_EUNSUPPORTED for QS_VALIDATE_FP64 (the FP64
+ * shadow needs scratch of its own). */
+qs_status qs_forward_noalloc(qs_ctx *ctx, const qs_laser *laser, const qs_beam *beam,
+                             const qs_numerics *num, const qs_bins *bins,
+                             const qs_outputs *out, void *stream);
+
 /* Many shots in one launch (the high-repetition-rate use of the abstract and
  * the conclusions): shot k uses lasers[k], beams[k], bins[k], outs[k] and
  * n_samples[k] samples, and the shared numerics (num->n_samples is ignored;

@@ -64,13 +64,15 @@ class Context:
                            device=torch.device("cuda", self.device))
 
     def forward(self, params, sample_stride=0, n_sample_records=0, stream=None, out=None,
-                check=True, tape=None):
+                check=True, tape=None, noalloc=False):
         """Enqueue one forward pass; returns a dict of device tensors.
 
         ``out`` may hold preallocated tensors (same keys as the result) to
         avoid allocation.  With ``check`` the stream is synchronised and the
         device status word raised as an error.  With ``tape`` (from new_tape)
-        the pass also records the per-sample parameter derivatives there."""
+        the pass also records the per-sample parameter derivatives there.
+        With ``noalloc`` the pass runs through qs_forward_noalloc (the
+        library allocates nothing; at most NOALLOC_MAX_SAMPLES samples)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         la, be, nu, bi = _lib.structs(params)
@@ -100,9 +102,9 @@ class Context:
                                             ctypes.c_void_p(tape.data_ptr()),
                                             ctypes.c_void_p(stream.cuda_stream))
         else:
-            st = _lib.lib().qs_forward(self._ptr, ctypes.byref(la), ctypes.byref(be),
-                                       ctypes.byref(nu), ctypes.byref(bi), ctypes.byref(o),
-                                       ctypes.c_void_p(stream.cuda_stream))
+            fn = _lib.lib().qs_forward_noalloc if noalloc else _lib.lib().qs_forward
+            st = fn(self._ptr, ctypes.byref(la), ctypes.byref(be), ctypes.byref(nu),
+                    ctypes.byref(bi), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
         if st != _lib.QS_OK:
             raise QScatterError(st, self.last_error())
         if check:

@@ -26,6 +26,7 @@ VALIDATE_FP64 = 1
 (M_SHADOW_N, M_ERR_MU_MAX, M_ERR_MU_MEAN, M_ERR_SIG_MAX, M_ERR_MEAN_G) = range(11, 16)
 (M_ERR_E_L1, M_ERR_E_MAX, M_ERR_T_L1, M_ERR_T_MAX) = range(16, 20)
 S_N = 11
+NOALLOC_MAX_SAMPLES = 1 << 20  # QS_NOALLOC_MAX_SAMPLES
 (M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, M_MEAN_AEFF,
  M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF) = range(11)
 (S_MU, S_SIG2, S_THX, S_THY, S_SIGTH, S_AEFF, S_CHIMAX, S_GAMMA0, S_X, S_Y, S_Z) = range(11)
@@ -109,7 +110,7 @@ PARAM_NAMES = ("a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sig
 TAPE_FIELDS = 2 + 2 * len(PARAM_NAMES)  # mu, sig2, d mu / dp, d sig2 / dp
 T_MU, T_SIG2, T_DMU, T_DSIG2 = 0, 1, 2, 2 + len(PARAM_NAMES)
 
-EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_batched",
+EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_noalloc", "qs_forward_batched",
            "qs_forward_factorised", "qs_forward_factorised_batched", "qs_backward",
            "qs_backward_batched", "qs_forward_tape", "qs_forward_tape_batched",
            "qs_backward_tape", "qs_backward_tape_batched", "qs_photons", "qs_photons_batched",
@@ -145,6 +146,8 @@ def lib():
                                  ctypes.POINTER(Numerics), ctypes.POINTER(Bins),
                                  ctypes.POINTER(Outputs), vp]
         L.qs_forward.restype = ctypes.c_int
+        L.qs_forward_noalloc.argtypes = L.qs_forward.argtypes
+        L.qs_forward_noalloc.restype = ctypes.c_int
         L.qs_forward_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser),
                                          ctypes.POINTER(Beam), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(Numerics), ctypes.POINTER(Bins),

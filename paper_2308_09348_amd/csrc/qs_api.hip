@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -75,8 +76,43 @@ struct qs_ctx {
     bool graphs = false;
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graph_cache;
+    // qs_forward_noalloc: the device address of this device's `scratch` array
+    // and a pinned staging block for its shot table, both set up by qs_create
+    unsigned char *na_scratch = nullptr;
+    unsigned char *na_stage = nullptr;
+    hipEvent_t na_done = nullptr;  // the last copy out of na_stage
+    bool na_pending = false;
     char last_error[512] = {0};
 };
+
+// ---- scratch of qs_forward_noalloc -----------------------------------------
+// The entry point for callers that cannot allocate takes all of its device
+// scratch from one file-scope array (each GPU holds its own copy from the
+// library's load until the process ends).  Layout, each part 256-byte aligned:
+// the per-sample final states (6 double arrays and 1 float array of
+// QS_NOALLOC_MAX_SAMPLES), the FP64 and FP32 envelope tables (2 n_steps + 1
+// points at the largest n_steps), the accumulators (work counters, the status
+// flags, the histogram words of the largest bins), the moment partials (one
+// row per 1024-sample tile) and the device copy of the shot table.
+namespace na {
+constexpr size_t r256(size_t n) { return (n + 255) / 256 * 256; }
+constexpr size_t kSamples = QS_NOALLOC_MAX_SAMPLES;
+constexpr size_t kEnvPoints = 2 * 65536 + 1;
+constexpr size_t kAccumWords = 2 + 1 + 3 * 4096 + 4;
+constexpr size_t kPartWords = (kSamples + qs::kMomTile - 1) / qs::kMomTile * qs::kPartials;
+constexpr size_t kArr = r256(kSamples * 8), kArrf = r256(kSamples * 4);
+constexpr size_t kStatesOff = 0;
+constexpr size_t kEnv64Off = kStatesOff + 6 * kArr + kArrf;
+constexpr size_t kEnv32Off = kEnv64Off + r256(kEnvPoints * 8);
+constexpr size_t kAccumOff = kEnv32Off + r256(kEnvPoints * 4);
+constexpr size_t kPartOff = kAccumOff + r256(kAccumWords * 8);
+constexpr size_t kTabOff = kPartOff + r256(kPartWords * 8);
+constexpr size_t kTabBytes = r256(sizeof(qs::ShotParams) + sizeof(qs::ShotOut));
+constexpr size_t kBytes = kTabOff + kTabBytes;
+static_assert(kBytes < ((size_t)56 << 20), "the no-allocation scratch stays under 56 MiB");
+}  // namespace na
+
+static __device__ __align__(256) unsigned char scratch[na::kBytes];
 
 namespace {
 
@@ -94,6 +130,25 @@ qs_status hip_fail(qs_ctx *c, hipError_t e, const char *where) {
     if (c)
         std::snprintf(c->last_error, sizeof(c->last_error), "%s: %s", where, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? QS_ENOMEM : QS_EDEVICE;
+}
+
+// Device address of `scratch` on each device: looked up once per device, by
+// the first qs_create on it, with that device current.  In host code the
+// array's name is only a host-side stand-in; kernels get this address.
+std::mutex g_scratch_mutex;
+std::vector<unsigned char *> g_scratch_addr;
+
+hipError_t scratch_address(int device, unsigned char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if ((size_t)device >= g_scratch_addr.size()) g_scratch_addr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
 }
 
 class DeviceGuard {
@@ -284,7 +339,7 @@ qs_status grow_pinned(qs_ctx *c, size_t n) {
 
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                       const qs_outputs *O, double *tape, hipStream_t s);
+                       const qs_outputs *O, double *tape, hipStream_t s, bool noalloc = false);
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                         const qs_grad_outputs *O, const double *tape, hipStream_t s);
@@ -357,6 +412,16 @@ qs_status qs_create(qs_ctx **out, int device) {
         qs_destroy(c);
         return st;
     }
+    // set-up of qs_forward_noalloc: this device's scratch address, the
+    // staging block of its shot table and the event that guards it
+    if ((e = scratch_address(device, &c->na_scratch)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&c->na_stage), na::kTabBytes,
+                           hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->na_done, hipEventDisableTiming)) != hipSuccess) {
+        qs_status st = hip_fail(c, e, "no-allocation scratch set-up");
+        qs_destroy(c);
+        return st;
+    }
     *out = c;
     return QS_OK;
 }
@@ -379,6 +444,8 @@ void qs_destroy(qs_ctx *c) {
         (void)hipFree(c->shot_tab);
         if (c->stage) (void)hipHostFree(c->stage);
         if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+        if (c->na_stage) (void)hipHostFree(c->na_stage);
+        if (c->na_done) (void)hipEventDestroy(c->na_done);
         (void)hipFree(c->eval_flags);
         for (hipEvent_t &e : c->ev)
             if (e) (void)hipEventDestroy(e);
@@ -397,6 +464,22 @@ qs_status qs_forward(qs_ctx *c, const qs_laser *L, const qs_beam *B, const qs_nu
     if (!N) return set_err(c, "null argument"), QS_EINVAL;
     const int64_t n = N->n_samples;
     return forward_impl(c, 1, L, B, &n, N, H, O, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+qs_status qs_forward_noalloc(qs_ctx *c, const qs_laser *L, const qs_beam *B,
+                             const qs_numerics *N, const qs_bins *H, const qs_outputs *O,
+                             void *stream) {
+    if (!c) return QS_EINVAL;
+    if (!N) return set_err(c, "null argument"), QS_EINVAL;
+    if (N->n_samples > (int64_t)QS_NOALLOC_MAX_SAMPLES)
+        return set_err(c, "qs_forward_noalloc: n_samples above QS_NOALLOC_MAX_SAMPLES"),
+               QS_EINVAL;
+    if (N->flags & QS_VALIDATE_FP64)
+        return set_err(c, "qs_forward_noalloc: no FP64 shadow (QS_VALIDATE_FP64)"),
+               QS_EUNSUPPORTED;
+    const int64_t n = N->n_samples;
+    return forward_impl(c, 1, L, B, &n, N, H, O, nullptr, reinterpret_cast<hipStream_t>(stream),
+                        true);
 }
 
 qs_status qs_forward_batched(qs_ctx *c, int32_t n_shots, const qs_laser *lasers,
@@ -625,6 +708,7 @@ struct Batch {
     int64_t total = 0;    // samples over all shots
     int64_t hist_words = 0;
     size_t tab_bytes = 0;
+    unsigned char *stage = nullptr;  // pinned staging buffer of the shot table
     qs::ShotParams *sp = nullptr;  // in the staging buffer
     unsigned char *outs = nullptr;  // in the staging buffer, after the ShotParams
 };
@@ -661,7 +745,7 @@ const TuneEntry *find_tune(const qs_ctx *c, const TuneKey &k) {
 
 qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        size_t out_size, Batch &b) {
+                        size_t out_size, Batch &b, bool noalloc = false) {
     qs_status st = validate_numerics(c, N);
     if (st != QS_OK) return st;
     for (int k = 0; k < n_shots; ++k) {
@@ -717,14 +801,29 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
 
     // ---- per-shot table in pinned staging memory ----
     b.tab_bytes = ((sizeof(qs::ShotParams) + out_size) * n_shots + 255) / 256 * 256;
-    if (c->stage_pending) {
-        hipError_t e = hipEventSynchronize(c->stage_done);  // previous copy out of staging
-        if (e != hipSuccess) return hip_fail(c, e, "staging event");
-        c->stage_pending = false;
+    unsigned char *stage = nullptr;
+    if (noalloc) {
+        // the fixed staging block of qs_forward_noalloc
+        if (b.tab_bytes > na::kTabBytes)
+            return set_err(c, "shot table exceeds the no-allocation staging block"), QS_EINVAL;
+        if (c->na_pending) {
+            hipError_t e = hipEventSynchronize(c->na_done);  // previous copy out of it
+            if (e != hipSuccess) return hip_fail(c, e, "staging event");
+            c->na_pending = false;
+        }
+        stage = c->na_stage;
+    } else {
+        if (c->stage_pending) {
+            hipError_t e = hipEventSynchronize(c->stage_done);  // previous copy out of staging
+            if (e != hipSuccess) return hip_fail(c, e, "staging event");
+            c->stage_pending = false;
+        }
+        if ((st = grow_pinned(c, b.tab_bytes)) != QS_OK) return st;
+        stage = c->stage;
     }
-    if ((st = grow_pinned(c, b.tab_bytes)) != QS_OK) return st;
-    b.sp = reinterpret_cast<qs::ShotParams *>(c->stage);
-    b.outs = c->stage + sizeof(qs::ShotParams) * n_shots;
+    b.stage = stage;
+    b.sp = reinterpret_cast<qs::ShotParams *>(stage);
+    b.outs = stage + sizeof(qs::ShotParams) * n_shots;
     int64_t item = 0, ditem = 0, mtile = 0, off = 0, hoff = 0;
     for (int k = 0; k < n_shots; ++k) {
         const qs_laser &l = L[k];
@@ -810,9 +909,19 @@ qs_status upload_batch(qs_ctx *c, const Batch &b, hipStream_t s) {
     return QS_OK;
 }
 
+// The same for qs_forward_noalloc: its staging block to the shot table in
+// the device scratch, guarded by its own event (both made by qs_create).
+qs_status upload_batch_noalloc(qs_ctx *c, const Batch &b, unsigned char *dst, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, c->na_stage, b.tab_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "shot table copy");
+    if ((e = hipEventRecord(c->na_done, s)) != hipSuccess) return hip_fail(c, e, "event record");
+    c->na_pending = true;
+    return QS_OK;
+}
+
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                       const qs_outputs *O, double *tape, hipStream_t s) {
+                       const qs_outputs *O, double *tape, hipStream_t s, bool noalloc) {
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
@@ -826,8 +935,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
                         !tape;
     Batch b;
     if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H,
-                            sizeof(qs::ShotOut) + (shadow ? sizeof(qs::ShotParams) : 0), b)) !=
-        QS_OK)
+                            sizeof(qs::ShotOut) + (shadow ? sizeof(qs::ShotParams) : 0), b,
+                            noalloc)) != QS_OK)
         return st;
     if (qs::deposit_lds_bytes(b.max_nh) > 160 * 1024)
         return set_err(c, "histograms exceed the LDS budget"), QS_EINVAL;
@@ -879,32 +988,61 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     // work counters (phase, deposit, shadow phase, unused), flags, histograms,
     // FP64-shadow law differences
     const size_t accum_words = 2 + flag_words + (size_t)b.hist_words + (size_t)shd_words;
-    if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
-    if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
-    if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK) return st;
-    if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_mtiles * qs::kPartials,
-                   "moment partials")) != QS_OK)
-        return st;
-    if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf + 6 * sarr + sarrf,
-                   "sample states")) != QS_OK)
-        return st;
-    if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
-        return st;
-    bp.shots = reinterpret_cast<const qs::ShotParams *>(c->shot_tab);
-    bp.outs = reinterpret_cast<const qs::ShotOut *>(c->shot_tab + sizeof(qs::ShotParams) * n_shots);
+    float *env32 = nullptr;
+    double *env64 = nullptr;
+    unsigned long long *accum = nullptr;
+    double *partials = nullptr;
+    unsigned char *states = nullptr, *shot_tab = nullptr;
+    if (noalloc) {
+        // one shot, no shadow, no tape: every part fits its slot of `scratch`
+        // (the sizes were validated; these checks keep the carve honest)
+        if (n_shots != 1 || shadow || tape || (size_t)b.total > na::kSamples ||
+            nenv > na::kEnvPoints || accum_words > na::kAccumWords ||
+            (size_t)bp.n_mtiles * qs::kPartials > na::kPartWords || b.tab_bytes > na::kTabBytes ||
+            arr > na::kArr || arrf > na::kArrf)
+            return set_err(c, "qs_forward_noalloc: the call exceeds the static scratch"), QS_EINVAL;
+        unsigned char *base = c->na_scratch;
+        env64 = reinterpret_cast<double *>(base + na::kEnv64Off);
+        env32 = reinterpret_cast<float *>(base + na::kEnv32Off);
+        accum = reinterpret_cast<unsigned long long *>(base + na::kAccumOff);
+        partials = reinterpret_cast<double *>(base + na::kPartOff);
+        states = base + na::kStatesOff;
+        shot_tab = base + na::kTabOff;
+    } else {
+        if ((st = grow(c, &c->env32, &c->env32_cap, nenv, "envelope table")) != QS_OK) return st;
+        if ((st = grow(c, &c->env64, &c->env64_cap, nenv, "envelope table")) != QS_OK) return st;
+        if ((st = grow(c, &c->accum, &c->accum_cap, accum_words, "accumulators")) != QS_OK)
+            return st;
+        if ((st = grow(c, &c->partials, &c->part_cap, (size_t)bp.n_mtiles * qs::kPartials,
+                       "moment partials")) != QS_OK)
+            return st;
+        if ((st = grow(c, &c->states, &c->states_cap, 6 * arr + arrf + 6 * sarr + sarrf,
+                       "sample states")) != QS_OK)
+            return st;
+        if ((st = grow(c, &c->shot_tab, &c->shot_tab_cap, b.tab_bytes, "shot table")) != QS_OK)
+            return st;
+        env32 = c->env32;
+        env64 = c->env64;
+        accum = c->accum;
+        partials = c->partials;
+        states = c->states;
+        shot_tab = c->shot_tab;
+    }
+    bp.shots = reinterpret_cast<const qs::ShotParams *>(shot_tab);
+    bp.outs = reinterpret_cast<const qs::ShotOut *>(shot_tab + sizeof(qs::ShotParams) * n_shots);
     bp.rad32 = c->rad32;
     bp.rad64 = c->rad64;
     bp.rad32d = c->rad32d;
     bp.rad64d = c->rad64d;
-    bp.st.mu = reinterpret_cast<double *>(c->states);
-    bp.st.s2 = reinterpret_cast<double *>(c->states + arr);
-    bp.st.S0 = reinterpret_cast<double *>(c->states + 2 * arr);
-    bp.st.g0 = reinterpret_cast<double *>(c->states + 3 * arr);
-    bp.st.thx = reinterpret_cast<double *>(c->states + 4 * arr);
-    bp.st.thy = reinterpret_cast<double *>(c->states + 5 * arr);
-    bp.st.cmx = reinterpret_cast<float *>(c->states + 6 * arr);
+    bp.st.mu = reinterpret_cast<double *>(states);
+    bp.st.s2 = reinterpret_cast<double *>(states + arr);
+    bp.st.S0 = reinterpret_cast<double *>(states + 2 * arr);
+    bp.st.g0 = reinterpret_cast<double *>(states + 3 * arr);
+    bp.st.thx = reinterpret_cast<double *>(states + 4 * arr);
+    bp.st.thy = reinterpret_cast<double *>(states + 5 * arr);
+    bp.st.cmx = reinterpret_cast<float *>(states + 6 * arr);
     if (shadow) {
-        unsigned char *base = c->states + 6 * arr + arrf;
+        unsigned char *base = states + 6 * arr + arrf;
         bp.sst.mu = reinterpret_cast<double *>(base);
         bp.sst.s2 = reinterpret_cast<double *>(base + sarr);
         bp.sst.S0 = reinterpret_cast<double *>(base + 2 * sarr);
@@ -913,17 +1051,18 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         bp.sst.thy = reinterpret_cast<double *>(base + 5 * sarr);
         bp.sst.cmx = reinterpret_cast<float *>(base + 6 * sarr);
     }
-    bp.queue = reinterpret_cast<unsigned int *>(c->accum);
-    bp.flags = reinterpret_cast<int *>(c->accum + 2);
-    bp.hist = c->accum + 2 + flag_words;
+    bp.queue = reinterpret_cast<unsigned int *>(accum);
+    bp.flags = reinterpret_cast<int *>(accum + 2);
+    bp.hist = accum + 2 + flag_words;
     bp.shdiff = shadow ? bp.hist + b.hist_words : nullptr;
-    bp.partials = c->partials;
+    bp.partials = partials;
     bp.tape = tape;
     bp.tape_n = b.total;
 
     // ---- enqueue ----
-    const bool prof = c->profiling;
-    if ((st = upload_batch(c, b, s)) != QS_OK) return st;
+    const bool prof = c->profiling && !noalloc;
+    if ((st = noalloc ? upload_batch_noalloc(c, b, shot_tab, s) : upload_batch(c, b, s)) != QS_OK)
+        return st;
     // the device work after the shot-table copy: envelope, clear, phase (or
     // tangent), deposit, finalize; with events between them when profiling
     auto enqueue = [&](hipStream_t q, bool marks) -> qs_status {
@@ -931,18 +1070,18 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         auto mark = [&](int k) { return marks ? hipEventRecord(c->ev[k], q) : hipSuccess; };
         if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
         if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau,
-                                     c->env32, c->env64, q)) != hipSuccess)
+                                     env32, env64, q)) != hipSuccess)
             return hip_fail(c, e, "envelope kernel");
         if ((e = mark(1)) != hipSuccess) return hip_fail(c, e, "event record");
-        if ((e = qs::launch_zero(c->accum, accum_words, q)) != hipSuccess)
+        if ((e = qs::launch_zero(accum, accum_words, q)) != hipSuccess)
             return hip_fail(c, e, "zero kernel");
         if ((e = mark(2)) != hipSuccess) return hip_fail(c, e, "event record");
         if (tape) {
             // the forward pass that also records the parameter derivatives
-            if ((e = qs::launch_tangent(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode,
+            if ((e = qs::launch_tangent(bp, env32, env64, b.prec, N->rr_model, N->amp_mode,
                                         true, q)) != hipSuccess)
                 return hip_fail(c, e, "tangent kernel");
-        } else if ((e = qs::launch_phase(bp, c->env32, c->env64, b.prec, N->rr_model,
+        } else if ((e = qs::launch_phase(bp, env32, env64, b.prec, N->rr_model,
                                          N->amp_mode, q)) != hipSuccess) {
             return hip_fail(c, e, "phase kernel");
         }
@@ -950,11 +1089,11 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
             // the shadowed samples again in FP64 (their own work counter)
             qs::BatchParams bs = bp;
             bs.shots = reinterpret_cast<const qs::ShotParams *>(
-                c->shot_tab + (sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots);
+                shot_tab + (sizeof(qs::ShotParams) + sizeof(qs::ShotOut)) * n_shots);
             bs.n_items = sh_items;
             bs.st = bp.sst;
             bs.queue = bp.queue + 2;
-            if ((e = qs::launch_phase(bs, c->env32, c->env64, qs::PREC_F64, N->rr_model,
+            if ((e = qs::launch_phase(bs, env32, env64, qs::PREC_F64, N->rr_model,
                                       N->amp_mode, q)) != hipSuccess)
                 return hip_fail(c, e, "shadow phase kernel");
             // the two states' laws of every shadowed sample, bin by bin
@@ -971,7 +1110,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
         return QS_OK;
     };
-    if (c->graphs && !prof && !tape) {
+    if (c->graphs && !prof && !tape && !noalloc) {
         // everything the captured launches depend on besides the device shot
         // table (copied before every replay) and the tables built at creation
         struct Sig {
@@ -989,9 +1128,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         sig.psi_max = b.psi_max;
         sig.h = b.h;
         sig.omega_tau = b.omega_tau;
-        sig.env32 = c->env32;
-        sig.env64 = c->env64;
-        sig.accum = c->accum;
+        sig.env32 = env32;
+        sig.env64 = env64;
+        sig.accum = accum;
         sig.accum_words = (int64_t)accum_words;
         sig.sh_items = sh_items;
         sig.sh_total = sh_total;
