@@ -7,15 +7,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libqso.so")
 
 
-def build(verbose=False):
-    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
-           "-ffp-contract=off", "-Wall", "-Wextra",
-           os.path.join(HERE, "qso.cpp"), "-o", LIB + ".tmp"]
+FLAGS = ["-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+         "-Wextra"]
+
+
+def build(verbose=False, source=None, lib=None, extra_flags=()):
+    """Compile qso.cpp (or `source`, a copy of it) into oracle/libqso.so (or
+    `lib`)."""
+    source = source or os.path.join(HERE, "qso.cpp")
+    lib = lib or LIB
+    cmd = ["g++"] + FLAGS + ["-I" + HERE] + list(extra_flags) + [source, "-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -60,54 +60,60 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from oracle import build as _b  # noqa: F401  (local build script)
             _b.build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        pp = ctypes.POINTER(Problem)
-        L.qso_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
-        L.qso_philox4x32_10.restype = None
-        L.qso_normals.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, dp]
-        L.qso_normals.restype = None
-        L.qso_gh_quadrature.argtypes = [ctypes.c_double, dp, dp]
-        L.qso_gh_quadrature.restype = None
-        L.qso_radiation.argtypes = [ctypes.c_double, dp]
-        L.qso_radiation.restype = None
-        L.qso_rhs.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
-        L.qso_rhs.restype = ctypes.c_int
-        L.qso_envelope_carrier.argtypes = [pp, ctypes.c_double]
-        L.qso_envelope_carrier.restype = ctypes.c_double
-        L.qso_derived.argtypes = [pp, dp]
-        L.qso_derived.restype = ctypes.c_int
-        L.qso_sample.argtypes = [pp, ctypes.c_int64, dp]
-        L.qso_sample.restype = ctypes.c_int
-        L.qso_forward.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                                  dp, dp, dp, dp]
-        L.qso_forward.restype = ctypes.c_int
-        L.qso_sample_grad.argtypes = [pp, ctypes.c_int64, dp]
-        L.qso_sample_grad.restype = ctypes.c_int
-        L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
-        L.qso_grad.restype = ctypes.c_int
-        L.qso_grad_outputs.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp,
-                                       dp, dp]
-        L.qso_grad_outputs.restype = ctypes.c_int
-        L.qso_photons.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int32,
-                                  ctypes.c_double, ctypes.c_double, dp, dp]
-        L.qso_photons.restype = ctypes.c_int
-        L.qso_photon_cdf.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
-        L.qso_photon_cdf.restype = ctypes.c_int
-        L.qso_deposit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                  ctypes.c_int32, dp]
-        L.qso_deposit.restype = ctypes.c_int
-        L.qso_factorised.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                     ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp, dp, dp]
-        L.qso_factorised.restype = ctypes.c_int
-        L.qso_factorised_samples.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp]
-        L.qso_factorised_samples.restype = ctypes.c_int
-        L.qso_photon_angles.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
-        L.qso_photon_angles.restype = ctypes.c_int
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path):
+    """A ctypes handle on an oracle library built from qso.cpp at `path`
+    (the tests also load copies built with a planted mistake)."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(Problem)
+    L.qso_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+    L.qso_philox4x32_10.restype = None
+    L.qso_normals.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, dp]
+    L.qso_normals.restype = None
+    L.qso_gh_quadrature.argtypes = [ctypes.c_double, dp, dp]
+    L.qso_gh_quadrature.restype = None
+    L.qso_radiation.argtypes = [ctypes.c_double, dp]
+    L.qso_radiation.restype = None
+    L.qso_rhs.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    L.qso_rhs.restype = ctypes.c_int
+    L.qso_envelope_carrier.argtypes = [pp, ctypes.c_double]
+    L.qso_envelope_carrier.restype = ctypes.c_double
+    L.qso_derived.argtypes = [pp, dp]
+    L.qso_derived.restype = ctypes.c_int
+    L.qso_sample.argtypes = [pp, ctypes.c_int64, dp]
+    L.qso_sample.restype = ctypes.c_int
+    L.qso_forward.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                              dp, dp, dp, dp]
+    L.qso_forward.restype = ctypes.c_int
+    L.qso_sample_grad.argtypes = [pp, ctypes.c_int64, dp]
+    L.qso_sample_grad.restype = ctypes.c_int
+    L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
+    L.qso_grad.restype = ctypes.c_int
+    L.qso_grad_outputs.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp,
+                                   dp, dp]
+    L.qso_grad_outputs.restype = ctypes.c_int
+    L.qso_photons.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int32,
+                              ctypes.c_double, ctypes.c_double, dp, dp]
+    L.qso_photons.restype = ctypes.c_int
+    L.qso_photon_cdf.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+    L.qso_photon_cdf.restype = ctypes.c_int
+    L.qso_deposit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int32, dp]
+    L.qso_deposit.restype = ctypes.c_int
+    L.qso_factorised.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+    L.qso_factorised.restype = ctypes.c_int
+    L.qso_factorised_samples.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp]
+    L.qso_factorised_samples.restype = ctypes.c_int
+    L.qso_photon_angles.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
+    L.qso_photon_angles.restype = ctypes.c_int
+    return L
 
 
 def _dp(a):
