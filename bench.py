@@ -294,8 +294,9 @@ def main():
         sys.exit(2)
     import torch
     import paper_2308_09348_amd as qs
-    from paper_2308_09348_amd import workloads
+    from paper_2308_09348_amd import _lib, workloads
 
+    build_id = _lib.check_build()  # the library was built from these sources
     params = dict(workloads.focused_3d(), precision=args.precision, chi_fp64=args.chi_fp64)
     n, N = params["n_samples"], params["n_steps"]
     ctx = qs.Context(0)
@@ -339,6 +340,7 @@ def main():
                    "n_samples": n, "n_steps": N, "rr_model": params["rr_model"],
                    "amp_mode": params["amp_mode"], "precision": args.precision,
                    "chi_fp64": args.chi_fp64, "leg": "fwd"},
+        "build_id": build_id,
         "tuning": tuning,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,

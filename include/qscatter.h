@@ -563,6 +563,11 @@ const char *qs_last_error(qs_ctx *ctx);
 /* QS_ABI_VERSION of the built library. */
 int qs_abi_version(void);
 
+/* Build provenance: the SHA-256 (64 hex digits) of the sources, headers and
+ * compiler flags the library was built from, or "unknown" for a build that
+ * did not stamp it.  Static string; never NULL. */
+const char *qs_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

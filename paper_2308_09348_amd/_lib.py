@@ -117,7 +117,7 @@ EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_noalloc", "qs_fo
            "qs_photon_cdf", "qs_radiation_eval",
            "qs_radiation_derivs", "qs_sync_status",
            "qs_set_profiling", "qs_last_timings", "qs_tune", "qs_set_graphs", "qs_strerror",
-           "qs_last_error", "qs_abi_version"]
+           "qs_last_error", "qs_abi_version", "qs_build_id"]
 
 _lib = None
 
@@ -212,8 +212,26 @@ def lib():
         L.qs_last_error.restype = ctypes.c_char_p
         L.qs_abi_version.argtypes = []
         L.qs_abi_version.restype = ctypes.c_int
+        L.qs_build_id.argtypes = []
+        L.qs_build_id.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+def build_id():
+    """The source hash stamped into the loaded library (qs_build_id)."""
+    return lib().qs_build_id().decode()
+
+
+def check_build():
+    """Raise unless the loaded library was built from the sources now checked
+    out (its stamped hash against build.source_id()); returns the hash."""
+    from . import build as _build
+    want, have = _build.source_id(), build_id()
+    if have != want:
+        raise RuntimeError(f"{LIB_PATH} was built from other sources (build id {have[:16]}, "
+                           f"sources {want[:16]}): rebuild it")
+    return have
 
 
 def _enum(table, v):

@@ -4,6 +4,7 @@ Each source is compiled to an object of its own (in parallel, in a temporary
 directory) with the common flags plus its entry in SOURCE_FLAGS, then the
 objects are linked into the library."""
 import concurrent.futures
+import hashlib
 import os
 import subprocess
 import sys
@@ -31,13 +32,33 @@ SOURCE_FLAGS = {
 }
 
 
+def source_id(extra_flags=()):
+    """SHA-256 (hex) of everything the library is built from: each source
+    and header under csrc/, the C-ABI header and the compiler flags.  The
+    build stamps it into the library (qs_build_id), so a loaded library can
+    be matched against the checked-out sources."""
+    h = hashlib.sha256()
+    csrc = os.path.join(PKG, "csrc")
+    files = sorted(os.path.join("csrc", f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".h")))
+    for rel in files + [os.path.join("..", "include", "qscatter.h")]:
+        h.update(rel.encode() + b"\0")
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    flags = HIPCC_FLAGS + sorted(f"{k}:{' '.join(v)}" for k, v in SOURCE_FLAGS.items())
+    h.update(" ".join(flags + list(extra_flags)).encode())
+    return h.hexdigest()
+
+
 def build(verbose=False, extra_flags=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc")]
+    stamp = ['-DQS_BUILD_ID="' + source_id(extra_flags) + '"']
     with tempfile.TemporaryDirectory(prefix="qs_build_") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             cmd = ([hipcc] + HIPCC_FLAGS + SOURCE_FLAGS.get(src, []) + list(extra_flags) + inc +
+                   (stamp if src == "csrc/qs_api.hip" else []) +
                    ["-c", os.path.join(PKG, src), "-o", obj])
             if verbose:
                 print(" ".join(cmd), flush=True)

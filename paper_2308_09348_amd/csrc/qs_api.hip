@@ -359,6 +359,13 @@ extern "C" {
 
 int qs_abi_version(void) { return QS_ABI_VERSION; }
 
+// SHA-256 of the sources and flags this library was built from, stamped by
+// the build script.
+#ifndef QS_BUILD_ID
+#define QS_BUILD_ID "unknown"
+#endif
+const char *qs_build_id(void) { return QS_BUILD_ID; }
+
 const char *qs_strerror(qs_status s) {
     switch (s) {
         case QS_OK: return "ok";

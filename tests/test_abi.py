@@ -52,17 +52,43 @@ def test_abi_version_and_strerror():
     assert L.qs_strerror(99) == b"unknown status"
 
 
-def test_struct_layouts_match_header():
+# binding struct -> C struct name in the header
+STRUCTS = {"Laser": "qs_laser", "Beam": "qs_beam", "Numerics": "qs_numerics", "Bins": "qs_bins",
+           "Outputs": "qs_outputs", "NodeGrid": "qs_node_grid", "Tuning": "qs_tuning",
+           "GradOutputs": "qs_grad_outputs", "PhotonBins": "qs_photon_bins",
+           "PhotonOutputs": "qs_photon_outputs"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every binding struct has the size, field names and field offsets that
+    a C compiler gives the header's struct (gcc on the host)."""
+    import shutil
+    import subprocess
     from paper_2308_09348_amd import _lib
-    # sizes follow from the header's field lists (8-byte aligned doubles)
-    assert ctypes.sizeof(_lib.Laser) == 8 * 4 + 4 * 2 + 8 * 3 + 4 * 2
-    assert ctypes.sizeof(_lib.Beam) == 8 * 5 + 4 * 2
-    assert ctypes.sizeof(_lib.Numerics) == 8 + 4 * 2 + 8 * 2 + 4 * 4 + 8 * 3 + 4 * 2
-    assert ctypes.sizeof(_lib.Bins) == 4 * 4 + 8 * 4
-    assert ctypes.sizeof(_lib.Outputs) == 8 * 8
-    assert ctypes.sizeof(_lib.NodeGrid) == 4 * 2 + 8 * 2
-    assert ctypes.sizeof(_lib.Tuning) == 4 * 4 + 8 * 2
-    assert ctypes.sizeof(_lib.GradOutputs) == 8 * 6
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "qscatter.h"',
+             "int main(void) {"]
+    for py, c in STRUCTS.items():
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for name, _ in getattr(_lib, py)._fields_:
+            lines.append(f'  printf("{py} {name} %zu\\n", offsetof({c}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        py, name, v = line.split()
+        got[(py, name)] = int(v)
+    for py in STRUCTS:
+        cls = getattr(_lib, py)
+        assert ctypes.sizeof(cls) == got[(py, "size")], py
+        for name, _ in cls._fields_:
+            assert getattr(cls, name).offset == got[(py, name)], (py, name)
 
 
 def test_null_context_is_rejected_without_a_device():
@@ -75,3 +101,10 @@ def test_null_context_is_rejected_without_a_device():
     assert L.qs_tune(None, 1, None, None, None, None, None, None, None, None) == _lib.QS_EINVAL
     assert L.qs_set_graphs(None, 1) == _lib.QS_EINVAL
     L.qs_destroy(None)
+
+
+def test_library_was_built_from_these_sources():
+    from paper_2308_09348_amd import _lib
+    _lib_path()
+    bid = _lib.check_build()
+    assert len(bid) == 64 and int(bid, 16) >= 0

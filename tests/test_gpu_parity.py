@@ -31,6 +31,11 @@ def gpu():
     ctx.close()
 
 
+def test_loaded_library_matches_the_sources(gpu):
+    from paper_2308_09348_amd import _lib
+    assert len(_lib.check_build()) == 64
+
+
 def _run(ctx, params, **kw):
     out = ctx.forward(params, **kw)
     return {k: v.cpu().numpy() for k, v in out.items()}
