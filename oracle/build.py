@@ -24,6 +24,21 @@ def build(verbose=False, source=None, lib=None, extra_flags=()):
     return lib
 
 
+SAN_LIB = os.path.join(HERE, "libqso_san.so")
+# AddressSanitizer and UndefinedBehaviorSanitizer, any report fatal: the
+# sanitized oracle runs the CPU pins with the ASan runtime preloaded
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized(verbose=False):
+    """The oracle built under ASan + UBSan into oracle/libqso_san.so."""
+    return build(verbose=verbose, lib=SAN_LIB, extra_flags=SAN_FLAGS)
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

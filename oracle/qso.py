@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqso.so")
+# QSO_LIB selects another build of the same source (the sanitized one)
+LIB_PATH = os.environ.get("QSO_LIB") or os.path.join(HERE, "libqso.so")
 
 ENVELOPE = {"gauss": 0, "sin2": 1}
 RR_MODEL = {"classical": 0, "quantum": 1}
