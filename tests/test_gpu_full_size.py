@@ -7,9 +7,19 @@ compute one by one, and through properties that hold at any size:
     histograms carry exactly its samples, status clean; sampled final states
     of shots across the batch against the oracle's (FP32 bars);
   - 256 shots x 2^18 samples x 2048 steps with FP64 steps where chi > 0.1
-    (untuned, as the benchmark runs it): the same for the spectra pass, and
-    sampled entries of the derivative tape against the oracle's per-sample
-    derivatives (FP32 tangent bars).
+    (launch choices of the spectra pass from a copy of the committed cache,
+    as the benchmark reads them): the same for the spectra pass, and sampled
+    entries of the derivative tape against the oracle's per-sample
+    derivatives (FP32 tangent bars);
+  - the focused single shot (2^22 samples x 1024 steps, quantum, local
+    amplitude, CIC, FP32; launch choices from the cache as the benchmark
+    times it) element by element against the oracle run over all 2^22
+    samples: every energy and angle bin at |G - O| <= 1e-4 O + 1e-7 sum(O),
+    every moment at 1e-5, the a0,eff histogram bin for bin (both sides
+    compute the spatial factor in FP64 and agree to 1e-13, so a sample
+    decides its bin alike unless it lies within 1e-13 of an edge: at most one
+    sample per bin is allowed to differ; about 2e-4 such samples are expected
+    at this size).
 """
 import os
 import shutil
@@ -84,10 +94,13 @@ def test_batched_shots_full_size(gpu, oracle, tmp_path):
     gpu.set_graphs(False)
 
 
-def test_quantum_batch_full_size(gpu, oracle):
+def test_quantum_batch_full_size(gpu, oracle, tmp_path):
     import torch
     shots = workloads.quantum_batch()
     batch = gpu.prepare_batch(shots)
+    cache = tmp_path / "tune_cache.txt"
+    shutil.copy(CACHE, cache)
+    assert gpu.tune(batch, cache_path=str(cache))["from_cache"]
     n_rec = 6
     picks = [(k, shots[k]["n_samples"]) for k in (0, 101, 255)]
     strides = _with_records(gpu, batch, picks, n_rec)
@@ -116,3 +129,36 @@ def test_quantum_batch_full_size(gpu, oracle):
                     (k, i, name)
     del tape
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_focused_full_size_elementwise(gpu, oracle, tmp_path):
+    p = workloads.focused_3d()
+    n = p["n_samples"]
+    cache = tmp_path / "tune_cache.txt"
+    shutil.copy(CACHE, cache)
+    assert gpu.tune(p, cache_path=str(cache))["from_cache"]
+    print(f"full size: focused workload {n} samples x {p['n_steps']} steps on the GPU",
+          flush=True)
+    g = {k: v.cpu().numpy() for k, v in gpu.forward(p).items()}
+    print("full size: the oracle over every sample (all host threads)", flush=True)
+    o = oracle.forward(p)
+    assert g["status"][0] == 0
+    for k in ("energy_hist", "angle_hist"):
+        oh, gh = o[k], g[k]
+        assert gh.sum() == float(n) and abs(oh.sum() - n) < 1e-6 * n, k
+        tol = 1e-4 * np.abs(oh) + 1e-7 * oh.sum()
+        bad = np.abs(gh - oh) > tol
+        worst = np.max(np.abs(gh - oh) / tol)
+        print(f"full size: {k} worst bin at {worst:.3f} of the bar", flush=True)
+        assert not bad.any(), (k, np.nonzero(bad)[0][:10], gh[bad][:5], oh[bad][:5])
+    assert g["a0eff_hist"].sum() == o["a0eff_hist"].sum() == float(n)
+    assert np.max(np.abs(g["a0eff_hist"] - o["a0eff_hist"])) <= 1.0
+    gm, om = g["moments"], o["moments"]
+    assert gm[0] == om[0] == n
+    for k in (1, 2, 3, 4, 5, 6, 7, 9, 10):
+        scale = abs(om[k])
+        if k in (3, 5):  # mean angles: near zero, compare against the rms
+            scale = max(scale, om[k + 1])
+        assert abs(gm[k] - om[k]) <= 1e-5 * scale, (k, gm[k], om[k])
+    assert abs(gm[8] - om[8]) <= 1e-5 * om[8]
