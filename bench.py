@@ -26,13 +26,15 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # launch choices found by the tuner on this machine type, one line per class
 DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_2308_09348_amd", "tune_cache.txt")
 
-# Algorithmic floating-point operations per sample-step of the phase loop
-# (FMA = 2, each exp / sqrt / reciprocal = 1), counted from the method's
-# arithmetic: RK4 over (mu, sig2), four evaluations of the moment right-hand
-# side, the spatial factor at the two new stage phases.  The breakdown is in
-# the design notes.
-ALG_FLOPS = {("quantum", "local"): 270, ("quantum", "a0eff"): 229,
-             ("classical", "local"): 79, ("classical", "a0eff"): 31}
+# Algorithmic floating-point operations per sample-step of the phase loop:
+# the oracle's own operation tally (oracle/flop_table.py writes the table; it
+# is read here as data).
+FLOP_TABLE = os.path.join(ROOT, "oracle", "flop_table.json")
+
+
+def alg_flops(rr, amp):
+    with open(FLOP_TABLE) as f:
+        return float(json.load(f)["modes"][f"{rr}/{amp}"]["per_sample_step"])
 
 
 PROFILE = os.path.join(ROOT, "profiles", "phase_kernel_focused_2p22.md")
@@ -49,9 +51,10 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per phase-kernel launch from the committed rocprofv3 byte
-    counters, or None when the kernel source changed since they were taken."""
+def profile_values():
+    """The machine-readable block of the committed phase-kernel profile
+    (rocprofv3 average duration, HBM traffic, hardware-counted FP32 FLOPs per
+    sample-step), or {} when the kernel source changed since it was taken."""
     try:
         kv = {}
         for line in open(PROFILE):
@@ -59,10 +62,10 @@ def profiled_traffic():
             if len(parts) == 2:
                 kv[parts[0]] = parts[1]
         if kv.get("kernel_source_sha256") != kernel_source_sha256():
-            return None
-        return float(kv["phase_kernel_traffic_bytes"])
-    except (OSError, KeyError, ValueError):
-        return None
+            return {}
+        return {k: float(v) for k, v in kv.items() if k != "kernel_source_sha256"}
+    except (OSError, ValueError):
+        return {}
 
 
 def parse():
@@ -327,8 +330,11 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     value = n * N / (wall / args.steps)
     phase_avg_ms = sum(phase_ms) / len(phase_ms)
-    flops_launch = ALG_FLOPS[(params["rr_model"], params["amp_mode"])] * n * N
+    flops_step = alg_flops(params["rr_model"], params["amp_mode"])
+    flops_launch = flops_step * n * N
     achieved = flops_launch / (phase_avg_ms * 1e-3) / 1e12
+    prof = profile_values() if args.precision == "fp32" and args.chi_fp64 <= 0 else {}
+    peak = FP32_VALU_PEAK_TFLOPS
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -342,13 +348,24 @@ def main():
                    "chi_fp64": args.chi_fp64, "leg": "fwd"},
         "build_id": build_id,
         "tuning": tuning,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                     "traffic": profiled_traffic() if args.precision == "fp32" else None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": prof.get("phase_kernel_traffic_bytes"),
                      "kernel": "phase_kernel",
                      "kernel_avg_ms": phase_avg_ms,
-                     "alg_flops_per_sample_step": ALG_FLOPS[(params["rr_model"],
-                                                             params["amp_mode"])]},
+                     "alg_flops_per_sample_step": flops_step,
+                     "alg_flops_source": "oracle/flop_table.json (the oracle's operation tally)",
+                     # the same FLOPs over the committed rocprofv3 average of the kernel
+                     "kernel_avg_ms_rocprof": prof.get("phase_kernel_avg_ms"),
+                     "frac_rocprof": (flops_launch / (prof["phase_kernel_avg_ms"] * 1e-3) / 1e12
+                                      / peak if "phase_kernel_avg_ms" in prof else None),
+                     # FP32 operations the hardware counted (rocprofv3 VALU classes, FMA = 2)
+                     "hw_flops_per_sample_step": prof.get("hw_flops_per_sample_step"),
+                     "frac_hw": (prof["hw_flops_per_sample_step"] * n * N /
+                                 (phase_avg_ms * 1e-3) / 1e12 / peak
+                                 if "hw_flops_per_sample_step" in prof else None),
+                     # the algorithmic FLOPs over the whole pass (every kernel of a step)
+                     "frac_whole_pass": flops_launch / (ms_per_step * 1e-3) / 1e12 / peak},
     }
     # FP64 shadow of the same pass (untimed above): every 64th sample again in
     # FP64, the FP32 pass's per-sample error against it

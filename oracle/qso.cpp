@@ -92,6 +92,43 @@ inline Dual fmin(const Dual &a, const Dual &b) { return a.v <= b.v ? a : b; }
 using std::exp; using std::log; using std::sqrt; using std::fabs; using std::erfc;
 using std::fmax; using std::fmin;
 
+/* ---- operation counting ------------------------------------------------ */
+/* A value that counts the floating-point operations performed on it (per
+ * thread): the per-sample path instantiated with it gives the method's own
+ * operation tally.  Each add, subtract, multiply, divide counts one; each
+ * exp, log, sqrt or erfc counts one transcendental; sign changes, absolute
+ * values, maxima and comparisons count nothing.  Arithmetic on plain doubles
+ * (quantities shared by every sample, such as the envelope at a phase) is not
+ * counted. */
+struct OpCount { double add, mul, div, trans; };
+thread_local OpCount g_ops = {0.0, 0.0, 0.0, 0.0};
+struct Counted {
+    double v;
+    Counted(double x = 0.0) : v(x) {}
+};
+inline double val(const Counted &x) { return x.v; }
+inline Counted operator+(const Counted &a, const Counted &b) { g_ops.add += 1; return Counted(a.v + b.v); }
+inline Counted operator-(const Counted &a, const Counted &b) { g_ops.add += 1; return Counted(a.v - b.v); }
+inline Counted operator-(const Counted &a) { return Counted(-a.v); }
+inline Counted operator*(const Counted &a, const Counted &b) { g_ops.mul += 1; return Counted(a.v * b.v); }
+inline Counted operator/(const Counted &a, const Counted &b) { g_ops.div += 1; return Counted(a.v / b.v); }
+inline Counted operator+(const Counted &a, double b) { g_ops.add += 1; return Counted(a.v + b); }
+inline Counted operator+(double a, const Counted &b) { g_ops.add += 1; return Counted(a + b.v); }
+inline Counted operator-(const Counted &a, double b) { g_ops.add += 1; return Counted(a.v - b); }
+inline Counted operator-(double a, const Counted &b) { g_ops.add += 1; return Counted(a - b.v); }
+inline Counted operator*(const Counted &a, double b) { g_ops.mul += 1; return Counted(a.v * b); }
+inline Counted operator*(double a, const Counted &b) { g_ops.mul += 1; return Counted(a * b.v); }
+inline Counted operator/(const Counted &a, double b) { g_ops.div += 1; return Counted(a.v / b); }
+inline Counted operator/(double a, const Counted &b) { g_ops.div += 1; return Counted(a / b.v); }
+inline Counted &operator+=(Counted &a, const Counted &b) { a = a + b; return a; }
+inline Counted exp(const Counted &a) { g_ops.trans += 1; return Counted(std::exp(a.v)); }
+inline Counted log(const Counted &a) { g_ops.trans += 1; return Counted(std::log(a.v)); }
+inline Counted sqrt(const Counted &a) { g_ops.trans += 1; return Counted(std::sqrt(a.v)); }
+inline Counted erfc(const Counted &a) { g_ops.trans += 1; return Counted(std::erfc(a.v)); }
+inline Counted fabs(const Counted &a) { return Counted(std::fabs(a.v)); }
+inline Counted fmax(const Counted &a, const Counted &b) { return Counted(std::fmax(a.v, b.v)); }
+inline Counted fmin(const Counted &a, const Counted &b) { return Counted(std::fmin(a.v, b.v)); }
+
 /* ---- Philox4x32-10 ----------------------------------------------------- */
 /* Counter-based generator of Salmon et al. (SC'11): ten rounds of two
  * 32x32->64 multiplies with the key bumped by the Weyl constants between
@@ -1405,6 +1442,50 @@ static Params<Dual> seeded_params(const qso_problem *p) {
     P.div_mrad.d[7] = 1.0;
     finish_params(p, P);
     return P;
+}
+
+int qso_flop_tally(const qso_problem *p, int64_t i_begin, int64_t i_end, int32_t n_steps_b,
+                   double *out) {
+    if (validate(p) || i_begin < 0 || i_end <= i_begin || i_end > p->n_samples ||
+        n_steps_b <= p->n_steps)
+        return -1;
+    if (p->rr_model == QSO_RR_QUANTUM) table();
+    qso_problem pb = *p;
+    pb.n_steps = n_steps_b;
+    const Derived da = derive(p), db = derive(&pb);
+    Params<Counted> P = params<Counted>(p);
+    finish_params(p, P);
+    OpCount tot = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = i_begin; i < i_end; ++i) {
+        /* the same sample at two step counts: the difference is the work of
+         * n_steps_b - n_steps phase steps (set-up and deposit cancel) */
+        g_ops = OpCount{0.0, 0.0, 0.0, 0.0};
+        (void)run_sample<Counted>(p, da, P, i);
+        const OpCount a = g_ops;
+        g_ops = OpCount{0.0, 0.0, 0.0, 0.0};
+        (void)run_sample<Counted>(&pb, db, P, i);
+        const OpCount b = g_ops;
+        tot.add += b.add - a.add;
+        tot.mul += b.mul - a.mul;
+        tot.div += b.div - a.div;
+        tot.trans += b.trans - a.trans;
+    }
+    const double steps = (double)(i_end - i_begin) * (double)(n_steps_b - p->n_steps);
+    out[0] = tot.add / steps;
+    out[1] = tot.mul / steps;
+    out[2] = tot.div / steps;
+    out[3] = tot.trans / steps;
+    out[4] = (tot.add + tot.mul + tot.div + tot.trans) / steps;
+    /* one amplitude evaluation (spatial factor along the path, times a0 and
+     * the envelope), on the first sample at the window centre */
+    {
+        const SampleIn<Counted> smp = make_sample<Counted>(p, P, i_begin);
+        const Geometry<Counted> gmt = geometry<Counted>(p, P, smp);
+        g_ops = OpCount{0.0, 0.0, 0.0, 0.0};
+        (void)amplitude<Counted>(p, da, P, smp, gmt, 0.0);
+        out[5] = g_ops.add + g_ops.mul + g_ops.div + g_ops.trans;
+    }
+    return 0;
 }
 
 int qso_sample_grad(const qso_problem *p, int64_t i, double *out) {

@@ -163,6 +163,17 @@ int qso_photon_angles(const qso_problem *p, int64_t i_begin, int64_t i_end, int 
 int qso_factorised_samples(const qso_problem *p, int32_t n_anodes, int32_t n_gnodes,
                            int64_t n_idx, const int64_t *idx, int nthreads, double *recs);
 
+/* The method's operation tally: the per-sample path instantiated with a
+ * value type that counts its operations, each sample of [i_begin, i_end) run
+ * at p->n_steps and at n_steps_b > p->n_steps steps; the difference per
+ * sample-step: out[0] adds and subtracts, out[1] multiplies, out[2] divides,
+ * out[3] transcendentals (exp, log, sqrt, erfc), out[4] their total; out[5]
+ * the operations of one amplitude evaluation (spatial factor at a phase,
+ * times a0 and the envelope).  Only per-sample arithmetic counts (the
+ * envelope at each phase is shared by all samples). */
+int qso_flop_tally(const qso_problem *p, int64_t i_begin, int64_t i_end, int32_t n_steps_b,
+                   double *out);
+
 /* Derivatives with respect to the eight parameters, in this order:
  * (a0, w0_um, x_off_um, y_off_um, delay_fs, gamma0, sigma_gamma, div_mrad).
  * qso_sample_grad: out[0] = mu_f, out[1..8] = d mu_f / d p, out[9] = sig2_f,

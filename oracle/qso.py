@@ -90,6 +90,8 @@ def load(path):
     L.qso_forward.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                               dp, dp, dp, dp]
     L.qso_forward.restype = ctypes.c_int
+    L.qso_flop_tally.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, dp]
+    L.qso_flop_tally.restype = ctypes.c_int
     L.qso_sample_grad.argtypes = [pp, ctypes.c_int64, dp]
     L.qso_sample_grad.restype = ctypes.c_int
     L.qso_grad.argtypes = [pp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
@@ -270,6 +272,20 @@ def factorised_samples(params, n_anodes, n_gnodes, indices, nthreads=0):
 
 PARAM_NAMES = ["a0", "w0_um", "x_off_um", "y_off_um", "delay_fs", "gamma0", "sigma_gamma",
                "div_mrad"]
+
+
+def flop_tally(params, n_tally=16, steps_b=None):
+    """The oracle's operation count per sample-step of the phase loop on the
+    first n_tally samples of a workload: dict of adds, muls, divs,
+    transcendentals and total (the per-sample path run with an
+    operation-counting value type at n_steps and steps_b steps), and
+    "amplitude": the operations of one amplitude evaluation."""
+    out = np.zeros(6)
+    p = problem(params)
+    steps_b = steps_b or 2 * params["n_steps"]
+    if lib().qso_flop_tally(ctypes.byref(p), 0, n_tally, steps_b, _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return dict(zip(["add", "mul", "div", "trans", "total", "amplitude"], out.tolist()))
 
 
 def sample_grad(params, i):
