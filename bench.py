@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--quantum-batch-steps", type=int, default=1,
                     help="timed steps of the quantum batch with gradients and photon spectra "
                          "(0: skip)")
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="timed passes of the focused workload with FP64 steps where chi > 0.1 "
+                         "(0: skip)")
     ap.add_argument("--factorised-steps", type=int, default=10,
                     help="steps of the plane-wave reconstruction leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -181,17 +184,30 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
             "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak
+
+
+def mixed_peak(fp64_share):
+    """The VALU ceiling of a pass that takes the given share of its phase
+    steps in FP64 (at half the FP32 rate) and the rest in FP32."""
+    return 1.0 / (fp64_share / FP64_VALU_PEAK_TFLOPS + (1.0 - fp64_share) / FP32_VALU_PEAK_TFLOPS)
+
+
 def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
     """256 shots of 2^18 samples x 2048 steps, quantum (FP64 steps where
-    chi > 0.1): per step the electron spectra, the derivative tape and per-shot
-    gradients of a Neyman chi^2 loss against per-shot Poisson targets, and the
-    photon spectra -- all shots in one launch per stage."""
+    chi > 0.1).  One training step: the forward pass that records the
+    derivative tape (it deposits the electron spectra too), per-shot Neyman
+    chi^2 losses against Poisson targets and their upstream weights, the
+    adjoint from the tape, and the photon spectra with angular moments -- all
+    shots in one launch per stage.  The plain forward pass of the batch (the
+    spectra alone) is timed beside it for its roofline and its share of FP64
+    steps."""
     shots = workloads.quantum_batch()
     total = sum(p["n_samples"] for p in shots)
     N = shots[0]["n_steps"]
     batch = ctx.prepare_batch(shots)
-    # launch choices of the spectra pass from the tuner cache (tuned once
-    # if the class is not there)
+    # launch choices of the forward pass from the tuner cache (tuned once if
+    # the class is not there)
     tuning = ctx.tune(batch, cache_path=tune_cache) if tune_cache else None
     tape = ctx.new_tape(total)
     n_tot = 1e6
@@ -199,14 +215,14 @@ def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
     rng = np.random.Generator(np.random.PCG64(5))
     targets = [torch.tensor(rng.poisson(n_tot * o["energy_hist"].cpu().numpy() / p["n_samples"])
                             .astype(np.float64), device="cuda") for o, p in zip(ref, shots)]
+    share = float(np.mean([o["moments"][20].item() for o in ref]))
     parts = {}
 
     def step():
         t = [time.perf_counter()]
-        outs = ctx.run_batch(batch, check=False)
+        tout = ctx.run_batch(batch, check=False, tape=tape)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        tout = ctx.run_batch(batch, check=False, tape=tape)
         ws = []
         for o, p, tg in zip(tout, shots, targets):
             r = n_tot * o["energy_hist"] / p["n_samples"] - tg
@@ -217,9 +233,9 @@ def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
         phot = ctx.photons_batched(shots, check=False, angles=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        for k, name in enumerate(("spectra", "gradients", "photons")):
+        for k, name in enumerate(("tape_forward", "adjoint", "photons")):
             parts[name] = parts.get(name, 0.0) + t[k + 1] - t[k]
-        return outs, grads, phot
+        return tout, grads, phot
 
     step()  # warm-up
     parts.clear()
@@ -235,14 +251,34 @@ def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
     g = torch.stack(grads).cpu().numpy()
     if not np.all(np.isfinite(g)):
         raise RuntimeError("non-finite gradient in the quantum batch leg")
+    # the plain forward pass of the batch: its phase kernel against the
+    # mixed FP32/FP64 ceiling
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.run_batch(batch, check=False)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t1
+    phase_ms = ctx.last_timings()["phase"]
+    ctx.set_profiling(False)
+    flops = alg_flops("quantum", "local") * total * N
+    peak = mixed_peak(share)
+    achieved = flops / (phase_ms * 1e-3) / 1e12
     return {"workload": "256 shots: gamma0 N(2e4, 600^2), a0 U[50,150], W0 2um, no offsets, "
                         "2^18 samples x 2048 steps, quantum with FP64 steps where chi > 0.1, "
-                        "local amplitude; electron spectra, per-shot gradients (tape), "
-                        "256-bin photon spectra with photon angular moments",
+                        "local amplitude; one training step: electron spectra with the derivative "
+                        "tape, per-shot gradients of chi^2 losses, 256-bin photon spectra with "
+                        "photon angular moments",
             "n_shots": len(shots), "n_samples": total, "n_steps": N, "steps": steps,
             "ms_per_step": 1e3 * dt,
             "ms_parts": {k: 1e3 * v / steps for k, v in parts.items()},
             "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt,
+            "fp64_step_share": share,
+            "forward_ms": 1e3 * fwd_s,
+            "roofline": {"bound": "alu", "kernel": "phase_kernel (FP32 with FP64 steps)",
+                         "kernel_avg_ms": phase_ms, "achieved": achieved, "peak": peak,
+                         "unit": "TFLOP/s", "frac": achieved / peak,
+                         "peak_rule": "time-weighted: FP64 steps at 78.6, FP32 at 157.3 TFLOP/s"},
             "tuning": tuning}
 
 
@@ -367,6 +403,30 @@ def main():
                      # the algorithmic FLOPs over the whole pass (every kernel of a step)
                      "frac_whole_pass": flops_launch / (ms_per_step * 1e-3) / 1e12 / peak},
     }
+    # the same workload with FP64 steps where chi > 0.1 (the stability rule):
+    # its phase kernel against the mixed FP32/FP64 ceiling
+    if args.chi_fp64 <= 0 and args.precision == "fp32" and args.mixed_steps > 0:
+        pm = dict(params, chi_fp64=0.1)
+        om = ctx.forward(pm)
+        share = float(om["moments"][20].item())
+        ctx.set_profiling(True)
+        mixed_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            ctx.forward(pm, out=om, stream=stream, check=False)
+            mixed_ms.append(ctx.last_timings()["phase"])
+        torch.cuda.synchronize()
+        wall_m = (time.perf_counter() - t0) / args.mixed_steps
+        ctx.set_profiling(False)
+        k_ms = sum(mixed_ms) / len(mixed_ms)
+        pk = mixed_peak(share)
+        ach = flops_launch / (k_ms * 1e-3) / 1e12
+        line["fwd_chi_fp64_0p1"] = {
+            "chi_fp64": 0.1, "fp64_step_share": share, "ms_per_step": 1e3 * wall_m,
+            "sample_steps_per_s": n * N / wall_m, "kernel_avg_ms": k_ms,
+            "roofline": {"achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+                         "peak_rule": "time-weighted: FP64 steps at 78.6, FP32 at 157.3 TFLOP/s"}}
     # FP64 shadow of the same pass (untimed above): every 64th sample again in
     # FP64, the FP32 pass's per-sample error against it
     pv = dict(params, validate_fp64=True, shadow_stride=64)

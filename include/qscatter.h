@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define QS_ABI_VERSION 1
+#define QS_ABI_VERSION 2
 
 typedef enum qs_status {
     QS_OK = 0,
@@ -169,7 +169,14 @@ enum {
     QS_M_ERR_E_MAX,     /* max_k |D_k| / n, energy                              */
     QS_M_ERR_T_L1,      /* the same for the angle histogram                     */
     QS_M_ERR_T_MAX,
-    QS_M_N = 20
+    /* Precision of the phase steps (R21 of the FP64 promotion rule): the share
+     * of the pass's wavefront phase steps taken in FP64 -- 1 for QS_PREC_FP64,
+     * 0 for FP32 without chi_fp64, the promoted share otherwise (promoted
+     * wave-steps over ceil(n_samples / 64) x n_steps).  qs_forward and
+     * qs_forward_batched count it; the derivative-tape and plane-wave
+     * reconstruction passes report -1 (not counted). */
+    QS_M_FP64_STEPS,
+    QS_M_N = 21
 };
 
 /* Per-sample record (QS_S_N doubles) for diagnostics and parity checks. */

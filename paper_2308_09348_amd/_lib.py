@@ -20,7 +20,9 @@ PRECISION = {"fp32": 0, "fp64": 1}
 PROFILE = {"gauss": 0, "flat": 1}
 MODE = {"gauss": 0, "hg": 1, "lg": 2}
 
-M_N = 20
+M_N = 21
+# share of the pass's wavefront phase steps taken in FP64 (-1: not counted)
+M_FP64_STEPS = 20
 # FP64 shadow of an FP32 pass (qs_numerics.flags) and its moment fields
 VALIDATE_FP64 = 1
 (M_SHADOW_N, M_ERR_MU_MAX, M_ERR_MU_MEAN, M_ERR_SIG_MAX, M_ERR_MEAN_G) = range(11, 16)

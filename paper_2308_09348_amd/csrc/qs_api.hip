@@ -98,7 +98,7 @@ namespace na {
 constexpr size_t r256(size_t n) { return (n + 255) / 256 * 256; }
 constexpr size_t kSamples = QS_NOALLOC_MAX_SAMPLES;
 constexpr size_t kEnvPoints = 2 * 65536 + 1;
-constexpr size_t kAccumWords = 2 + 1 + 3 * 4096 + 4;
+constexpr size_t kAccumWords = 2 + 1 + 3 * 4096 + 4 + 1;
 constexpr size_t kPartWords = (kSamples + qs::kMomTile - 1) / qs::kMomTile * qs::kPartials;
 constexpr size_t kArr = r256(kSamples * 8), kArrf = r256(kSamples * 4);
 constexpr size_t kStatesOff = 0;
@@ -993,8 +993,10 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     const size_t sarrf = ((size_t)sh_total * 4 + 255) / 256 * 256;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;
     // work counters (phase, deposit, shadow phase, unused), flags, histograms,
-    // FP64-shadow law differences
-    const size_t accum_words = 2 + flag_words + (size_t)b.hist_words + (size_t)shd_words;
+    // FP64-shadow law differences, FP64 wave-steps per shot (forward passes)
+    const size_t count_words = tape ? 0 : (size_t)n_shots;
+    const size_t accum_words =
+        2 + flag_words + (size_t)b.hist_words + (size_t)shd_words + count_words;
     float *env32 = nullptr;
     double *env64 = nullptr;
     unsigned long long *accum = nullptr;
@@ -1062,6 +1064,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     bp.flags = reinterpret_cast<int *>(accum + 2);
     bp.hist = accum + 2 + flag_words;
     bp.shdiff = shadow ? bp.hist + b.hist_words : nullptr;
+    bp.fp64_steps = count_words ? bp.hist + b.hist_words + shd_words : nullptr;
+    bp.prec = b.prec;
     bp.partials = partials;
     bp.tape = tape;
     bp.tape_n = b.total;

@@ -58,7 +58,7 @@ constexpr int kDepTile = 4096;    // default deposit work item: kDepTile samples
 // deposit work item (a multiple of it), so the moments do not depend on it.
 constexpr int kMomTile = 1024;
 constexpr int kPartials = P_N + 3;  // moment sums and maxima of a moment tile
-constexpr int kMoments = 20;        // moments a shot returns (QS_M_N)
+constexpr int kMoments = 21;        // moments a shot returns (QS_M_N)
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
 
@@ -187,7 +187,7 @@ struct BatchParams {
     int32_t dep_tile;   // samples of one deposit work item (a tuning choice)
     int32_t phase_cap;  // resident phase blocks per CU at most (0: all that fit)
     int32_t dep_cap;    // resident deposit blocks per CU at most (0: all that fit)
-    int32_t pad1;
+    int32_t prec;       // the pass's precision (Prec)
     uint32_t key0, key1;
     double ksig_bins, c_theta;
     int64_t n_items, n_ditems, n_mtiles;
@@ -214,6 +214,8 @@ struct BatchParams {
     unsigned int *chimax_bits;     // [n_shots]
     int *flags;                    // [n_shots]
     unsigned int *queue;           // [2]: phase and deposit work counters
+    unsigned long long *fp64_steps;  // [n_shots]: wavefront phase steps taken in FP64 by
+                                     // the forward pass's FP32 loop (null: not counted)
     double *partials;              // [n_mtiles][kPartials]; adjoint: [n_items][kGradParams]
 };
 

@@ -75,7 +75,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
                                              const float *__restrict__ env32,
                                              const double *__restrict__ env64,
                                              const float *tab32, double2 *stage, bool live,
-                                             int &flags) {
+                                             int &flags, int &nprom) {
     const RadTabWave tabd(P.rad64, stage);
     const RadTab<float> tabf{tab32};
     const Phys<float> phf{P.Kf, P.CDf, P.two_over_aSf};
@@ -173,8 +173,10 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
                     double mud = ((double)mu + (double)mu_lo) + g0_rest;
                     double s2d = (double)s2 + (double)s2_lo;
                     g0_rest = 0.0;
+                    const int j0 = j;
                     j = fp64_segment<QUANTUM>(P, sp, pd, local, a0S0, env64, j, stage, mud, s2d,
                                               cmx, chd);
+                    nprom += j - j0;  // wave-uniform
                     mu = (float)mud;
                     mu_lo = (float)(mud - (double)mu);
                     s2 = (float)s2d;
@@ -269,10 +271,17 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
         const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
         const bool live = i < sp.n_samples;
         if (kWave64 || live) {
-            int flags = 0;
+            int flags = 0, nprom = 0;
             phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(
-                P, sp, live ? i : sp.n_samples - 1, env32, env64, tab32, wstage, live, flags);
+                P, sp, live ? i : sp.n_samples - 1, env32, env64, tab32, wstage, live, flags,
+                nprom);
             if (flags) atomicOr(&P.flags[s], flags);
+            if (PREC == PREC_F32MIX && P.fp64_steps != nullptr) {
+                // FP64 wave-steps of the wavefronts that hold a sample of the shot
+                const bool count = __any(live);
+                if (count && nprom > 0 && (threadIdx.x & 63) == 0)
+                    atomicAdd(&P.fp64_steps[s], (unsigned long long)nprom);
+            }
         }
     }
 }
@@ -673,6 +682,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchParams P) {
                 for (int q = 0; q < 4; ++q) M[16 + q] = shd[q];
             }
         }
+        // share of the wavefront phase steps taken in FP64
+        if (P.fp64_steps == nullptr)
+            M[20] = -1.0;
+        else if (P.prec == PREC_F64)
+            M[20] = 1.0;
+        else
+            M[20] = (double)P.fp64_steps[s] /
+                    ((double)((sp.n_samples + 63) / 64) * (double)P.n_steps);
         const int fl = P.flags[s];
         *so.status = (fl & kFlagNonFinite) ? 4 : ((fl & kFlagRange) ? 6 : 0);
     }

@@ -204,6 +204,26 @@ def test_promotion_at_high_chi(gpu, oracle):
     assert g["moments"][8] > 1.0  # the promoted steps were taken
 
 
+def test_fp64_step_share(gpu):
+    """The moment QS_M_FP64_STEPS: 1 for the FP64 pass, 0 for FP32 without the
+    threshold, 1 when the threshold lies below every chi (each wavefront takes
+    every step in FP64), strictly between at quantum-batch physics, -1 for the
+    derivative-tape pass (not counted)."""
+    from paper_2308_09348_amd import _lib
+    p = workloads.scaled(workloads.focused_3d(), n_samples=3037, n_steps=256)
+    m = lambda q: _run(gpu, q)["moments"][_lib.M_FP64_STEPS]
+    assert m(dict(p, precision="fp64")) == 1.0
+    assert m(dict(p, precision="fp32", chi_fp64=0.0)) == 0.0
+    assert m(dict(p, precision="fp32", chi_fp64=1e-30)) == 1.0
+    shot = workloads.quantum_batch(n_shots=4)[1]
+    q = dict(shot, a0=120.0, n_samples=2037, n_steps=512)
+    share = m(q)
+    assert 0.0 < share < 1.0, share
+    tape = gpu.new_tape(q["n_samples"])
+    out = gpu.forward(q, tape=tape)
+    assert out["moments"][_lib.M_FP64_STEPS].item() == -1.0
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_wide_box_gaussian_laws(gpu, oracle, prec):
     """Quantum-batch physics with the CIC deposit: samples that keep about 1 %

@@ -43,7 +43,9 @@ def test_shadow_matches_the_fp64_pass(gpu, chi64, stride):
     for k in ("energy_hist", "angle_hist", "a0eff_hist", "samples"):
         assert np.array_equal(g[k], plain[k]), k
     assert np.array_equal(g["moments"][:11], plain["moments"][:11])
-    assert not plain["moments"][11:].any()
+    assert not plain["moments"][11:_lib.M_FP64_STEPS].any()
+    # the shadow's FP64 launch counts no FP32-loop steps: the share is the pass's
+    assert g["moments"][_lib.M_FP64_STEPS] == plain["moments"][_lib.M_FP64_STEPS]
     m = g["moments"]
     idx = np.arange(0, p["n_samples"], stride)
     mu32, mu64 = g["samples"][idx, 0], d["samples"][idx, 0]
@@ -64,7 +66,8 @@ def test_no_shadow_for_fp64_passes(gpu):
     p = workloads.scaled(workloads.focused_3d(), n_samples=1000, n_steps=64, precision="fp64",
                          validate_fp64=True, shadow_stride=3)
     g = _run(gpu, p)
-    assert not g["moments"][11:].any()
+    assert not g["moments"][11:_lib.M_FP64_STEPS].any()
+    assert g["moments"][_lib.M_FP64_STEPS] == 1.0
 
 
 def test_shadow_in_a_batch_equals_single_shots(gpu):
@@ -120,4 +123,4 @@ def test_shadow_spectrum_errors(gpu, oracle, deposit):
     for w_, g_, nb in zip(want, got, (p["n_e"] + 2, 1, p["n_th"] + 2, 1)):
         assert abs(g_ - w_) <= 1e-6 * w_ + nb * 2.0 ** -40, (deposit, want, got)
     # an FP32 pass without the shadow leaves them zero
-    assert not _run(gpu, p)["moments"][11:].any()
+    assert not _run(gpu, p)["moments"][11:_lib.M_FP64_STEPS].any()
