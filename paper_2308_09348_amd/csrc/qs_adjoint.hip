@@ -940,6 +940,10 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
     __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
+    // FP64 steps where chi is high: the lanes take the item's samples in
+    // order of their chi scale, as the forward pass does (chi_order)
+    __shared__ float okey[kWave64 ? kPhaseBlock : 1];
+    __shared__ unsigned short oidx[kWave64 ? kPhaseBlock : 1];
     double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
@@ -952,7 +956,13 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
         if (item >= P.n_items) break;
         const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
         const ShotParams &sp = P.shots[s];
-        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        const int64_t base = (item - sp.item0) * kPhaseBlock;
+        int off = threadIdx.x;
+        if constexpr (kWave64) {
+            chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            off = oidx[threadIdx.x];
+        }
+        const int64_t i = base + off;
         double g[kGradParams];
 #pragma unroll
         for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
@@ -995,6 +1005,22 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
                 observable_sensitivity(P, sp, go, i, o.mu, o.s2, o.dmu, o.ds2, g);
             }
             if (live && flags) atomicOr(&P.flags[s], flags);
+        }
+        if constexpr (kWave64 && !TAPE) {
+            // the lanes held the item's samples in chi order: hand each
+            // sample's terms to the lane of its index (through the FP64 table
+            // staging, idle between items), so that the item's sum is formed
+            // in sample order, as the contraction of a tape forms it
+            static_assert(sizeof(stage) >= sizeof(double) * kPhaseBlock * kGradParams,
+                          "the staging area holds the item's terms");
+            double *gx = reinterpret_cast<double *>(stage);
+            __syncthreads();  // every wavefront is past its table reads
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) gx[off * kGradParams + p] = g[p];
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) g[p] = gx[threadIdx.x * kGradParams + p];
+            __syncthreads();  // before the next item's table reads
         }
         if (!TAPE) grad_item_reduce(P, item, g, red);
     }

@@ -463,6 +463,46 @@ __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0,
     S0 = sp.plane_wave ? 1.0 : pd.S(0.0);
 }
 
+// Order in which the lanes of a block take the G consecutive samples of a
+// group (from `base`) in passes with FP64 steps where chi exceeds a
+// threshold.  A wavefront steps in FP64 when any of its lanes needs it, so its
+// lanes should hold samples of similar chi: they take the samples in
+// increasing order of S0 gamma0, the chi scale of a sample at its collision
+// point.  The order is stable (ties by index), so every launch of a group
+// forms the same wavefronts.  s_idx[r] receives the group offset of rank r;
+// offsets at or past `end` (no sample) rank last.  B threads take part.
+template <int G, int B>
+__device__ __forceinline__ void chi_order(const ShotParams &sp, uint32_t key0, uint32_t key1,
+                                          int64_t base, int64_t end, float *s_key,
+                                          unsigned short *s_idx) {
+    static_assert(G % B == 0 && G <= 65536, "group of whole rounds, 16-bit offsets");
+    __syncthreads();  // the previous group's order is no longer read
+    for (int q = threadIdx.x; q < G; q += B) {
+        float key = __builtin_inff();
+        const int64_t i = base + q;
+        if (i < end) {
+            // (the Gaussian focus's factor also orders samples of a higher mode:
+            // any order gives the same results up to the FP64-step choice)
+            double g0, thx, thy, S0;
+            Path<double, false> pd{};
+            draw_sample<false>(sp, key0, key1, i * sp.draw_stride, g0, thx, thy, pd, S0);
+            key = (float)(S0 * g0);
+        }
+        s_key[q] = key;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < G; q += B) {
+        const float k = s_key[q];
+        int rank = 0;
+        for (int j = 0; j < G; ++j) {
+            const float kj = s_key[j];
+            rank += (kj < k || (kj == k && j < q)) ? 1 : 0;
+        }
+        s_idx[rank] = (unsigned short)q;
+    }
+    __syncthreads();
+}
+
 // One RK4 step of (mu, sig2) from psi_j with amplitudes a1 = a(psi_j),
 // ah = a(psi_j + h/2), a4 = a(psi_j + h); returns the increments.
 template <class T, bool QUANTUM, class Tab = RadTab<T>>

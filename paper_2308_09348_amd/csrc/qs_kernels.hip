@@ -256,6 +256,11 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
+    // FP64 steps where chi is high: the lanes take the item's samples in
+    // order of their chi scale (chi_order), so that wavefronts step alike
+    constexpr bool kOrder = PREC == PREC_F32MIX && !NODES;
+    __shared__ float okey[kOrder ? kPhaseBlock : 1];
+    __shared__ unsigned short oidx[kOrder ? kPhaseBlock : 1];
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
@@ -268,7 +273,13 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
         if (item >= P.n_items) break;
         const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
         const ShotParams &sp = P.shots[s];
-        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+        const int64_t base = (item - sp.item0) * kPhaseBlock;
+        int off = threadIdx.x;
+        if constexpr (kOrder) {
+            chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            off = oidx[threadIdx.x];
+        }
+        const int64_t i = base + off;
         const bool live = i < sp.n_samples;
         if (kWave64 || live) {
             int flags = 0, nprom = 0;

@@ -703,6 +703,10 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
     __shared__ int64_t slot;
     __shared__ double red[kBlock / 64][kPhotPartials];
     __shared__ double2 stage[kWave64 ? (kBlock / 64) * kStageChunks : 1];
+    // FP64 steps where chi is high: the lanes take the item's samples in
+    // order of their chi scale (chi_order over the whole item)
+    __shared__ float okey[kWave64 ? kPhotTile : 1];
+    __shared__ unsigned short oidx[kWave64 ? kPhotTile : 1];
     double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     for (int r = threadIdx.x; r < kPhRows; r += blockDim.x)
         tot[r] = (float)(cbrt(kPhYMax) * P.phtab[(size_t)r * (kPhNZ + 1) + kPhNZ]);
@@ -728,9 +732,10 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
         double loss = 0.0;
         const int64_t i0 = (item - pp.pitem0) * kPhotTile;
         const int64_t i1 = i0 + kPhotTile < sp.n_samples ? i0 + kPhotTile : sp.n_samples;
-        if (kWave64) {
-            for (int64_t b = i0; b < i1; b += kBlock) {
-                const int64_t i = b + threadIdx.x;
+        if constexpr (kWave64) {
+            chi_order<kPhotTile, kBlock>(sp, P.key0, P.key1, i0, i1, okey, oidx);
+            for (int64_t b = 0; b < i1 - i0; b += kBlock) {
+                const int64_t i = i0 + oidx[b + threadIdx.x];
                 const bool live = i < i1;
                 photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, live ? i : i1 - 1, env32, env64,
                                                     tab32, grid, tot, ncell, wstage, live, acc,
