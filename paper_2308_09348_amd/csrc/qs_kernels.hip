@@ -245,7 +245,8 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
 }
 
 template <int PREC, bool QUANTUM, bool LOCAL, bool NODES = false, bool MODES = false>
-__global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
+__global__ __launch_bounds__(kPhaseBlock)
+__attribute__((amdgpu_waves_per_eu((PREC == PREC_F32 && QUANTUM) ? 4 : 1))) void phase_kernel(BatchParams P,
                                                             const float *__restrict__ env32,
                                                             const double *__restrict__ env64) {
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kPhaseBlock) void phase_kernel(BatchParams P,
     __shared__ int64_t slot;
     // FP64 steps where chi is high: the lanes take the item's samples in
     // order of their chi scale (chi_order), so that wavefronts step alike
-    constexpr bool kOrder = PREC == PREC_F32MIX && !NODES;
+    constexpr bool kOrder = PREC != PREC_F64 && QUANTUM && !NODES;
     __shared__ float okey[kOrder ? kPhaseBlock : 1];
     __shared__ unsigned short oidx[kOrder ? kPhaseBlock : 1];
     if (kTab32) {
