@@ -88,8 +88,11 @@ def parse():
                          "(0: skip)")
     ap.add_argument("--factorised-steps", type=int, default=10,
                     help="steps of the plane-wave reconstruction leg (0 = skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=4.0,
+                    help="target wall time of one run of the CPU-oracle sample (median of 3)")
+    ap.add_argument("--cpu-other-seconds", type=float, default=3.0,
+                    help="target wall time of one run of each other workload's CPU-oracle "
+                         "sample (median of 3; 0 skips them)")
     ap.add_argument("--tune-cache", default=os.environ.get("QS_TUNE_CACHE", DEFAULT_TUNE_CACHE),
                     help="launch-tuning cache file of the batched leg (read, else timed and "
                          "appended)")
@@ -99,30 +102,125 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(params, target_s):
-    """The FP64 oracle on a bounded prefix of the same workload, all host
-    cores; sample-steps per second."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _median_time(fn, reps=3):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def _oracle():
     from oracle import build as obuild, qso
     if not os.path.exists(qso.LIB_PATH):
         obuild.build()
+    return qso
+
+
+def _prefix(run, n_max, target_s, start):
+    """Grow a sample prefix until one run of it takes about target_s."""
+    n = start
+    while True:
+        t0 = time.perf_counter()
+        run(n)
+        dt = time.perf_counter() - t0
+        if dt > 0.25 * target_s or n >= n_max:
+            break
+        n = min(n * 4, n_max)
+    return int(max(1, min(n_max, n * target_s / max(dt, 1e-3))))
+
+
+def cpu_baseline(params, target_s):
+    """The FP64 oracle on a bounded prefix of the focused workload, all host
+    threads; sample-steps per second, median of 3 runs."""
+    qso = _oracle()
     threads = min(os.cpu_count() or 1, 64)
     qso.forward(dict(params, n_samples=threads), 0, threads, threads)  # builds the g/h table
-    n = 4 * threads
-    while True:  # grow the prefix until it takes a tenth of the target
-        t0 = time.perf_counter()
-        qso.forward(dict(params, n_samples=n), 0, n, threads)
-        dt = time.perf_counter() - t0
-        if dt > 0.1 * target_s or n >= params["n_samples"]:
-            break
-        n = min(n * 4, params["n_samples"])
-    n = int(max(n, min(params["n_samples"], n * target_s / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    qso.forward(dict(params, n_samples=n), 0, n, threads)
-    dt = time.perf_counter() - t0
+    run = lambda n: qso.forward(dict(params, n_samples=n), 0, n, threads)
+    n = _prefix(run, params["n_samples"], target_s, 4 * threads)
+    dt = _median_time(lambda: run(n))
     return {"value": n * params["n_steps"] / dt, "unit": UNIT, "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"first {n} of {params['n_samples']} samples x {params['n_steps']} steps "
-                      f"({dt:.1f} s wall, FP64, {threads} threads)"}
+                      f"(median of 3 runs, {dt:.2f} s each, FP64, {threads} threads)"}
+
+
+def cpu_baselines(workloads, target_s):
+    """The oracle on bounded samples of the other workloads (median of 3 runs
+    each, all host threads): the 1D plane wave in full, the 4096-shot batch
+    (its first 64 shots, a prefix of each), the differentiation workload
+    (forward and the dual-number gradient of the energy histogram) and the
+    quantum batch (its first 16 shots: forward, gradient and photon spectrum
+    with angular moments, a prefix of each); sample-steps per second of the
+    work done, and the time the whole workload would take at that rate."""
+    qso = _oracle()
+    threads = min(os.cpu_count() or 1, 64)
+    out = {"cores": threads, "cpu": cpu_model(), "nproc": os.cpu_count(), "kind": "oracle"}
+    p1 = workloads.plane_wave_1d()
+    dt = _median_time(lambda: qso.forward(p1, 0, p1["n_samples"], threads))
+    out["plane_wave_1d"] = {"value": p1["n_samples"] * p1["n_steps"] / dt, "unit": UNIT,
+                            "sample": f"all {p1['n_samples']} samples x {p1['n_steps']} steps",
+                            "s": dt}
+    shots = workloads.batched_shots()[:64]
+    total_b = sum(s["n_samples"] for s in workloads.batched_shots())
+    qso.forward(dict(shots[0], n_samples=threads), 0, threads, threads)
+
+    def run_b(n):
+        for s in shots:
+            m = min(n, s["n_samples"])
+            qso.forward(dict(s, n_samples=m), 0, m, threads)
+    n = _prefix(run_b, 1 << 18, target_s, threads)
+    dt = _median_time(lambda: run_b(n))
+    work = sum(min(n, s["n_samples"]) for s in shots) * shots[0]["n_steps"]
+    rate = work / dt
+    out["batched"] = {"value": rate, "unit": UNIT,
+                      "sample": f"first 64 of 4096 shots, first {n} samples of each x "
+                                f"{shots[0]['n_steps']} steps",
+                      "extrapolated_batch_s": total_b * shots[0]["n_steps"] / rate,
+                      "extrapolated_spectra_per_s": 4096 / (total_b * shots[0]["n_steps"] / rate)}
+    pd = workloads.differentiation_eval()
+
+    def run_d(n):
+        q = dict(pd, n_samples=n)
+        qso.forward(q, 0, n, threads)
+        qso.grad(q, 0, n, threads)
+    n = _prefix(run_d, pd["n_samples"], target_s, threads)
+    dt = _median_time(lambda: run_d(n))
+    out["differentiation"] = {
+        "value": n * pd["n_steps"] / dt, "unit": "sample·phase-steps/s (fwd+adjoint)",
+        "sample": f"first {n} of {pd['n_samples']} samples x {pd['n_steps']} steps: forward "
+                  "and the dual-number gradient",
+        "extrapolated_step_s": pd["n_samples"] * pd["n_steps"] / (n * pd["n_steps"] / dt)}
+    qshots = workloads.quantum_batch()[:16]
+    qtotal = sum(s["n_samples"] for s in workloads.quantum_batch())
+
+    def run_q(n):
+        for s in qshots:
+            q = dict(s, n_samples=n)
+            qso.forward(q, 0, n, threads)
+            qso.grad(q, 0, n, threads)
+            qso.photons(q, q["n_ph"], q["ph_lo"], q["ph_hi"], 0, n, threads)
+            qso.photon_angles(q, 0, n, threads)
+    n = _prefix(run_q, 1 << 18, target_s, threads)
+    dt = _median_time(lambda: run_q(n))
+    rate = 16 * n * qshots[0]["n_steps"] / dt
+    out["quantum_batch"] = {
+        "value": rate, "unit": "sample·phase-steps/s (spectra, gradients, photons)",
+        "sample": f"first 16 of 256 shots, first {n} samples of each x {qshots[0]['n_steps']} "
+                  "steps: forward, dual-number gradient, photon spectrum and angular moments",
+        "extrapolated_step_s": qtotal * qshots[0]["n_steps"] / rate}
+    return out
 
 
 def adjoint_leg(ctx, qs, workloads, torch, steps):
@@ -488,6 +586,8 @@ def main():
         line["copy_probe_bytes"] = nb
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
+        if args.cpu_other_seconds > 0:
+            line["cpu_baselines"] = cpu_baselines(workloads, args.cpu_other_seconds)
     print(json.dumps(line), flush=True)
     ctx.close()
 
