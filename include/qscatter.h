@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define QS_ABI_VERSION 2
+#define QS_ABI_VERSION 3
 
 typedef enum qs_status {
     QS_OK = 0,
@@ -52,8 +52,10 @@ enum { QS_AMP_A0EFF = 0, QS_AMP_LOCAL = 1 };
 enum { QS_DEP_POINT = 0, QS_DEP_CIC = 1, QS_DEP_GAUSS = 2 };
 enum { QS_PREC_FP32 = 0, QS_PREC_FP64 = 1 };
 /* qs_numerics.flags: QS_VALIDATE_FP64 shadows every shadow_stride-th sample
- * of an FP32 pass with the FP64 integration and reports the differences in
- * the moments QS_M_SHADOW_N .. QS_M_ERR_MEAN_G. */
+ * of an FP32 pass with the FP64 integration and reports the differences: in
+ * the moments QS_M_SHADOW_N .. QS_M_ERR_T_MAX (qs_forward), in
+ * qs_photon_outputs.errors (qs_photons) and in qs_grad_outputs.errors
+ * (qs_backward). */
 enum { QS_VALIDATE_FP64 = 1 };
 enum { QS_PROFILE_GAUSS = 0, QS_PROFILE_FLAT = 1 };
 /* Transverse laser modes, amplitude only (the wave's phase, Gouy phase and
@@ -305,7 +307,23 @@ typedef struct qs_grad_outputs {
                                     the same arguments (needed with d_moments: the
                                     derivatives of the std and rms moments depend
                                     on their values)                              */
+    double *errors;              /* out: optional [QS_GE_N] FP64-shadow report, or
+                                    NULL; zero-filled unless an FP32 pass runs with
+                                    QS_VALIDATE_FP64                              */
 } qs_grad_outputs;
+
+/* FP64 shadow of an FP32 adjoint (QS_VALIDATE_FP64): the gradient of the
+ * view that holds every shadow_stride-th sample (the same upstream weights
+ * and forward moments; the view's weight is its own sample count) is taken
+ * twice, at the pass's precision (FP32, with its chi_fp64 rule) and in FP64,
+ * both by integrating the trajectories with their tangents, and
+ * qs_grad_outputs.errors receives: */
+enum {
+    QS_GE_SHADOW_N = 0,            /* samples in the view                          */
+    QS_GE_DIFF = 1,                /* + p: dL/dp of the view, FP32 minus FP64     */
+    QS_GE_REF = 1 + QS_P_N,        /* + p: dL/dp of the view in FP64 (the scale)   */
+    QS_GE_N = 1 + 2 * QS_P_N
+};
 
 /* Adjoint of the forward outputs (the parameter-reconstruction use the
  * abstract and the conclusions give for the method's speed): for
@@ -411,7 +429,29 @@ typedef struct qs_photon_outputs {
                             plane, within a 1/mu cone per plane; each stage's
                             photons weigh by their number (the paper's
                             N_gamma/N_e weighting) or by their energy        */
+    double *errors;      /* optional [QS_PE_N] FP64-shadow report, or NULL;
+                            zero-filled unless an FP32 pass runs with
+                            QS_VALIDATE_FP64                                  */
 } qs_photon_outputs;
+
+/* FP64 shadow of an FP32 photon pass (QS_VALIDATE_FP64): the view that holds
+ * every shadow_stride-th sample is integrated twice, at the pass's precision
+ * (FP32, with its chi_fp64 rule) and in FP64, on the same emission grid, and
+ * qs_photon_outputs.errors receives (X32, X64: the view's outputs): */
+enum {
+    QS_PE_SHADOW_N = 0,  /* samples in the view                                 */
+    QS_PE_HIST_L1,       /* sum_k |H32_k - H64_k| / sum_k H64_k, over the n_ph + 2
+                            bins of photon_hist                                 */
+    QS_PE_HIST_MAX,      /* max_k |H32_k - H64_k| / sum_k H64_k                  */
+    QS_PE_ENERGY,        /* (E32 - E64) / E64 of the emitted energy (energy[0])  */
+    QS_PE_LOSS,          /* the same for the electrons' energy loss (energy[1])  */
+    QS_PE_ANGLES,        /* + j, j < 6: (A32_j - A64_j) / A64_j of angles[j] (0
+                            without angles or where A64_j is 0)                */
+    QS_PE_REF_PHOTONS = QS_PE_ANGLES + 6, /* the scales: sum_k H64_k,          */
+    QS_PE_REF_ENERGY,    /* E64,                                                */
+    QS_PE_REF_LOSS,      /* and the FP64 energy loss of the view                */
+    QS_PE_N
+};
 
 /* The approximate photon spectrum of Sec. 4: along each sample's trajectory
  * (integrated as in qs_forward) every phase pairs the mean energy with the

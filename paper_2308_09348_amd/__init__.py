@@ -278,14 +278,15 @@ class Context:
         return out
 
     def backward(self, params, d_energy=None, stream=None, check=True, tape=None, d_angle=None,
-                 d_moments=None, moments=None):
+                 d_moments=None, moments=None, errors=False):
         """Derivatives of L = d_energy . H + d_angle . T + d_moments . M (H, T, M:
         the energy histogram, angle histogram and moments of forward(params);
         each weight vector optional, ``moments`` = M is needed with d_moments)
         with respect to PARAM_NAMES; returns a float64 device tensor of 8.  With
         ``tape`` (recorded by forward(params, tape=...)) the energy-state
         derivatives are read from it instead of integrating the trajectories
-        again."""
+        again.  With ``errors`` returns (gradient, report): the FP64-shadow
+        report [GE_N] (zeros unless params["validate_fp64"] on an FP32 pass)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         la, be, nu, bi = _lib.structs(params)
@@ -297,9 +298,10 @@ class Context:
         ptr = lambda t: None if t is None else t.data_ptr()
         grad = torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev)
         status = torch.empty(1, dtype=torch.int32, device=dev)
+        err = torch.empty(_lib.GE_N, dtype=torch.float64, device=dev) if errors else None
         g = _lib.GradOutputs(d_energy_hist=ptr(de), grad=grad.data_ptr(),
                              status=status.data_ptr(), d_angle_hist=ptr(dt), d_moments=ptr(dm),
-                             moments=ptr(mo))
+                             moments=ptr(mo), errors=ptr(err))
         if tape is not None:
             _check_tape(tape, params["n_samples"])
             st = _lib.lib().qs_backward_tape(self._ptr, ctypes.byref(la), ctypes.byref(be),
@@ -317,13 +319,14 @@ class Context:
                                            ctypes.c_void_p(stream.cuda_stream))
             if st != _lib.QS_OK:
                 raise QScatterError(st, "device status")
-        return grad
+        return (grad, err) if errors else grad
 
     def backward_batched(self, shots, d_energy=None, stream=None, check=True, tape=None,
-                         d_angle=None, d_moments=None, moments=None):
+                         d_angle=None, d_moments=None, moments=None, errors=False):
         """Adjoint of forward_batched(shots): d_energy, d_angle, d_moments and
         moments are lists of per-shot tensors (or None) as in backward();
-        returns a list of gradient tensors.  ``tape``: as recorded by
+        returns a list of gradient tensors (with ``errors``: and a list of
+        FP64-shadow reports, as in backward()).  ``tape``: as recorded by
         forward_batched(shots, tape=...)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
@@ -339,6 +342,8 @@ class Context:
         outs, ns = (_lib.GradOutputs * n)(), (ctypes.c_int64 * n)()
         keep, grads = [], []
         status = torch.empty(n, dtype=torch.int32, device=dev)
+        errs = [torch.empty(_lib.GE_N, dtype=torch.float64, device=dev) if errors else None
+                for _ in range(n)]
         ptr = lambda t: None if t is None else t.data_ptr()
         for k, p in enumerate(shots):
             la, be, _, bi = _lib.structs(p)
@@ -348,7 +353,7 @@ class Context:
             grads.append(torch.empty(len(PARAM_NAMES), dtype=torch.float64, device=dev))
             outs[k] = _lib.GradOutputs(d_energy_hist=ptr(de), grad=grads[k].data_ptr(),
                                        status=status[k:].data_ptr(), d_angle_hist=ptr(dt),
-                                       d_moments=ptr(dm), moments=ptr(mo))
+                                       d_moments=ptr(dm), moments=ptr(mo), errors=ptr(errs[k]))
         if tape is not None:
             _check_tape(tape, sum(ns))
             st = _lib.lib().qs_backward_tape_batched(self._ptr, n, lasers, beams, ns,
@@ -366,14 +371,16 @@ class Context:
             bad = int(status.max().item())
             if bad != _lib.QS_OK:
                 raise QScatterError(bad, "device status of a shot")
-        return grads
+        return (grads, errs) if errors else grads
 
     def photons(self, params, stream=None, check=True, angles=False):
         """Photon spectrum of one shot (Sec. 4): returns {"photon_hist": [n_ph + 2]
         expected photon number per bin, "energy": [emitted photon energy,
         electron energy loss], "status"}; bins from photon_bins(params).  With
         ``angles`` also "angles" [6]: photon number and its rms theta_x,
-        theta_y (mrad), photon energy and its rms theta_x, theta_y (Sec. 5.1)."""
+        theta_y (mrad), photon energy and its rms theta_x, theta_y (Sec. 5.1).
+        With params["validate_fp64"] also "errors" [PE_N]: the FP64-shadow
+        report (zeros for an FP64 pass)."""
         return self.photons_batched([params], stream=stream, check=check, single=True,
                                     angles=angles)[0]
 
@@ -388,6 +395,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(dev)
         _, _, nu, _ = _lib.structs(shots[0])
+        report = bool(shots[0].get("validate_fp64", False))
         lasers, beams = (_lib.Laser * n)(), (_lib.Beam * n)()
         pbins, pouts, ns = (_lib.PhotonBins * n)(), (_lib.PhotonOutputs * n)(), (ctypes.c_int64 * n)()
         outs = []
@@ -401,11 +409,14 @@ class Context:
                  "status": torch.empty(1, dtype=torch.int32, device=dev)}
             if angles:
                 o["angles"] = torch.empty(6, dtype=torch.float64, device=dev)
+            if report:
+                o["errors"] = torch.empty(_lib.PE_N, dtype=torch.float64, device=dev)
             outs.append(o)
             pouts[k] = _lib.PhotonOutputs(photon_hist=o["photon_hist"].data_ptr(),
                                           energy=o["energy"].data_ptr(),
                                           status=o["status"].data_ptr(),
-                                          angles=o["angles"].data_ptr() if angles else None)
+                                          angles=o["angles"].data_ptr() if angles else None,
+                                          errors=o["errors"].data_ptr() if report else None)
         if single:
             st = _lib.lib().qs_photons(self._ptr, ctypes.byref(lasers[0]), ctypes.byref(beams[0]),
                                        ctypes.byref(nu), ctypes.byref(pbins[0]),

@@ -28,6 +28,11 @@ VALIDATE_FP64 = 1
 (M_SHADOW_N, M_ERR_MU_MAX, M_ERR_MU_MEAN, M_ERR_SIG_MAX, M_ERR_MEAN_G) = range(11, 16)
 (M_ERR_E_L1, M_ERR_E_MAX, M_ERR_T_L1, M_ERR_T_MAX) = range(16, 20)
 S_N = 11
+# FP64-shadow reports of the photon and adjoint passes (QS_PE_*, QS_GE_*)
+(PE_SHADOW_N, PE_HIST_L1, PE_HIST_MAX, PE_ENERGY, PE_LOSS, PE_ANGLES) = range(6)
+PE_REF_PHOTONS, PE_REF_ENERGY, PE_REF_LOSS = PE_ANGLES + 6, PE_ANGLES + 7, PE_ANGLES + 8
+PE_N = PE_ANGLES + 9
+GE_SHADOW_N, GE_DIFF, GE_REF, GE_N = 0, 1, 9, 17
 NOALLOC_MAX_SAMPLES = 1 << 20  # QS_NOALLOC_MAX_SAMPLES
 (M_WEIGHT, M_MEAN_G, M_STD_G, M_MEAN_THX, M_RMS_THX, M_MEAN_THY, M_RMS_THY, M_MEAN_AEFF,
  M_MAX_CHI, M_RAD_FRAC, M_MEAN_SIGF) = range(11)
@@ -96,13 +101,15 @@ class PhotonBins(ctypes.Structure):
 
 class PhotonOutputs(ctypes.Structure):
     _fields_ = [("photon_hist", ctypes.c_void_p), ("energy", ctypes.c_void_p),
-                ("status", ctypes.c_void_p), ("angles", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("angles", ctypes.c_void_p),
+                ("errors", ctypes.c_void_p)]
 
 
 class GradOutputs(ctypes.Structure):
     _fields_ = [("d_energy_hist", ctypes.c_void_p), ("grad", ctypes.c_void_p),
                 ("status", ctypes.c_void_p), ("d_angle_hist", ctypes.c_void_p),
-                ("d_moments", ctypes.c_void_p), ("moments", ctypes.c_void_p)]
+                ("d_moments", ctypes.c_void_p), ("moments", ctypes.c_void_p),
+                ("errors", ctypes.c_void_p)]
 
 
 # parameters of the adjoint, in the order of the QS_P_* enum

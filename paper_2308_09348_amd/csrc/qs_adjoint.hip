@@ -1097,6 +1097,26 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(BatchParams P) {
     }
 }
 
+// FP64-shadow report of each shot: the batch is the FP64 view pass, the FP32
+// view pass's gradients sit span doubles before its own (span 0: zeros).
+__global__ __launch_bounds__(256) void grad_shadow_kernel(BatchParams P, int64_t span) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.n_shots) return;
+    const ShotGrad &so = P.gouts[s];
+    double *o = so.errors;
+    if (!o) return;
+    if (span == 0) {
+        for (int q = 0; q < 1 + 2 * kGradParams; ++q) o[q] = 0.0;
+        return;
+    }
+    o[0] = (double)P.shots[s].n_samples;
+    for (int p = 0; p < kGradParams; ++p) {
+        const double g64 = so.grad[p], g32 = so.grad[p - span];
+        o[1 + p] = g32 - g64;
+        o[1 + kGradParams + p] = g64;
+    }
+}
+
 __global__ void rad_derivs_kernel(const float *rad32d, const double *rad64d, int prec, int64_t n,
                                   const double *chi, double *out, int *flags) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1174,6 +1194,11 @@ hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s) {
 
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {
     grad_finalize_kernel<<<p.n_shots, 256, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_shadow(const BatchParams &p, int64_t span, hipStream_t s) {
+    grad_shadow_kernel<<<(p.n_shots + 255) / 256, 256, 0, s>>>(p, span);
     return hipGetLastError();
 }
 

@@ -53,6 +53,8 @@ struct qs_ctx {
     size_t accum_cap = 0;
     double *partials = nullptr;
     size_t part_cap = 0;
+    double *shadow = nullptr;  // outputs of the FP64-shadow view passes (photons, adjoint)
+    size_t shadow_cap = 0;
     unsigned char *states = nullptr;  // per-sample final states (SampleState arrays)
     size_t states_cap = 0;
     // per-shot tables: pinned staging on the host, a device copy
@@ -337,15 +339,25 @@ qs_status grow_pinned(qs_ctx *c, size_t n) {
     return QS_OK;
 }
 
+// A view pass of the FP64 shadow: every stride-th sample of each shot (the
+// n_samples of the call are the view's); the FP64 view pass (report) writes
+// the error report, its outputs sitting `span` doubles after the FP32 view's.
+struct View {
+    int32_t stride;
+    int64_t span;
+    bool report;
+};
+
 qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                        const qs_outputs *O, double *tape, hipStream_t s, bool noalloc = false);
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        const qs_grad_outputs *O, const double *tape, hipStream_t s);
+                        const qs_grad_outputs *O, const double *tape, hipStream_t s,
+                        const View *view = nullptr);
 qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_photon_bins *PB,
-                       const qs_photon_outputs *PO, hipStream_t s);
+                       const qs_photon_outputs *PO, hipStream_t s, const View *view = nullptr);
 qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                       const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
                       const qs_node_grid *G, const qs_outputs *O, hipStream_t s);
@@ -447,6 +459,7 @@ void qs_destroy(qs_ctx *c) {
         (void)hipFree(c->env64);
         (void)hipFree(c->accum);
         (void)hipFree(c->partials);
+        (void)hipFree(c->shadow);
         (void)hipFree(c->states);
         (void)hipFree(c->shot_tab);
         if (c->stage) (void)hipHostFree(c->stage);
@@ -752,7 +765,8 @@ const TuneEntry *find_tune(const qs_ctx *c, const TuneKey &k) {
 
 qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        size_t out_size, Batch &b, bool noalloc = false) {
+                        size_t out_size, Batch &b, bool noalloc = false,
+                        int32_t draw_stride = 1) {
     qs_status st = validate_numerics(c, N);
     if (st != QS_OK) return st;
     for (int k = 0; k < n_shots; ++k) {
@@ -876,7 +890,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         p.mode_inv_normf = (float)p.mode_inv_norm;
         if (p.mode != QS_MODE_GAUSS) bp.any_mode = 1;
         p.shot_word = N->shot + k;
-        p.draw_stride = 1;
+        p.draw_stride = draw_stride;
         p.n_samples = n_samples[k];
         p.state_off = off;
         p.item0 = item;
@@ -1202,7 +1216,8 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
 
 qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                         const int64_t *n_samples, const qs_numerics *N, const qs_bins *H,
-                        const qs_grad_outputs *O, const double *tape, hipStream_t s) {
+                        const qs_grad_outputs *O, const double *tape, hipStream_t s,
+                        const View *view) {
     qs_status st;
     for (int k = 0; k < n_shots; ++k)
         if ((st = validate_outputs(c, &O[k])) != QS_OK) return st;
@@ -1210,8 +1225,14 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         for (int k = 0; k < n_shots; ++k)
             if (L[k].mode != QS_MODE_GAUSS)
                 return set_err(c, "derivatives are for the Gaussian mode only"), QS_EUNSUPPORTED;
+    bool want_err = false;
+    for (int k = 0; k < n_shots; ++k) want_err = want_err || O[k].errors;
+    // FP64 shadow of an FP32 adjoint: two view passes after this one
+    const bool shadow = !view && want_err && N && (N->flags & QS_VALIDATE_FP64) &&
+                        N->precision == QS_PREC_FP32;
     Batch b;
-    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotGrad), b)) != QS_OK)
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H, sizeof(qs::ShotGrad), b, false,
+                            view ? view->stride : 1)) != QS_OK)
         return st;
     DeviceGuard guard(c->device);
     qs::BatchParams &bp = b.bp;
@@ -1223,6 +1244,7 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         so[k].d_angle = O[k].d_angle_hist;
         so[k].d_moments = O[k].d_moments;
         so[k].moments = O[k].moments;
+        so[k].errors = shadow ? nullptr : O[k].errors;
     }
     const size_t nenv = (size_t)2 * N->n_steps + 1;
     const size_t flag_words = ((size_t)n_shots + 1) / 2;
@@ -1266,13 +1288,46 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     }
     if ((e = qs::launch_grad_finalize(bp, s)) != hipSuccess)
         return hip_fail(c, e, "gradient finalize kernel");
+    if (view ? view->report : want_err && !shadow) {
+        // the report of the view passes, or zeros
+        if ((e = qs::launch_grad_shadow(bp, view ? view->span : 0, s)) != hipSuccess)
+            return hip_fail(c, e, "shadow report kernel");
+    }
+    if (shadow) {
+        // the view of every stride-th sample, recomputed (no tape) at this
+        // pass's precision and then in FP64, with the same upstream weights
+        const int32_t stride = N->shadow_stride > 0 ? N->shadow_stride : 64;
+        const int64_t span = (int64_t)n_shots * qs::kGradParams;
+        if ((st = grow(c, &c->shadow, &c->shadow_cap, (size_t)(2 * span), "shadow outputs")) !=
+            QS_OK)
+            return st;
+        std::vector<int64_t> nv(n_shots);
+        std::vector<qs_grad_outputs> v32(O, O + n_shots), v64(O, O + n_shots);
+        for (int k = 0; k < n_shots; ++k) {
+            nv[k] = (n_samples[k] + stride - 1) / stride;
+            v32[k].grad = c->shadow + (size_t)k * qs::kGradParams;
+            v64[k].grad = v32[k].grad + span;
+            v32[k].status = v64[k].status = nullptr;
+            v32[k].errors = nullptr;
+        }
+        qs_numerics vn = *N;
+        vn.flags = 0;
+        const View v32v{stride, 0, false}, v64v{stride, span, true};
+        if ((st = backward_impl(c, n_shots, L, B, nv.data(), &vn, H, v32.data(), nullptr, s,
+                                &v32v)) != QS_OK)
+            return st;
+        vn.precision = QS_PREC_FP64;
+        if ((st = backward_impl(c, n_shots, L, B, nv.data(), &vn, H, v64.data(), nullptr, s,
+                                &v64v)) != QS_OK)
+            return st;
+    }
     c->last_error[0] = 0;
     return QS_OK;
 }
 
 qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam *B,
                        const int64_t *n_samples, const qs_numerics *N, const qs_photon_bins *PB,
-                       const qs_photon_outputs *PO, hipStream_t s) {
+                       const qs_photon_outputs *PO, hipStream_t s, const View *view) {
     for (int k = 0; k < n_shots; ++k) {
         const qs_photon_bins &b = PB[k];
         if (b.n_ph < 1 || b.n_ph > 4096 || !fin(b.ph_lo) || !fin(b.ph_hi) || !(b.ph_lo >= 0.0) ||
@@ -1288,10 +1343,15 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     // the electron histograms are not used: placeholder windows
     std::vector<qs_bins> H(n_shots);
     for (qs_bins &h : H) h = qs_bins{1, 1, 1, 0, 0.0, 1.0, 0.0, 1.0};
+    bool want_err = false;
+    for (int k = 0; k < n_shots; ++k) want_err = want_err || PO[k].errors;
+    // FP64 shadow of an FP32 pass: two view passes after this one
+    const bool shadow = !view && want_err && (N->flags & QS_VALIDATE_FP64) &&
+                        N->precision == QS_PREC_FP32;
     Batch b;
     qs_status st;
-    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H.data(), sizeof(qs::ShotPhot), b)) !=
-        QS_OK)
+    if ((st = prepare_batch(c, n_shots, L, B, n_samples, N, H.data(), sizeof(qs::ShotPhot), b,
+                            false, view ? view->stride : 1)) != QS_OK)
         return st;
     DeviceGuard guard(c->device);
     qs::BatchParams &bp = b.bp;
@@ -1339,6 +1399,7 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         p.energy = PO[k].energy;
         p.status = PO[k].status;
         p.angles = PO[k].angles;
+        p.errors = shadow ? nullptr : PO[k].errors;
         p.pitem0 = pitem;
         p.grid_off = (int64_t)k * qs::kPhNodes;
         pitem += (n_samples[k] + qs::kPhotTile - 1) / qs::kPhotTile;
@@ -1380,6 +1441,45 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     const double c_ph = kAlpha * aS / (2.0 * std::sqrt(3.0) * kPi);
     if ((e = qs::launch_photon_finalize(bp, c_ph, s)) != hipSuccess)
         return hip_fail(c, e, "photon finalize kernel");
+    if (view ? view->report : want_err && !shadow) {
+        // the report of the view passes, or zeros
+        if ((e = qs::launch_photon_shadow(bp, view ? view->span : 0, s)) != hipSuccess)
+            return hip_fail(c, e, "shadow report kernel");
+    }
+    if (shadow) {
+        // the view of every stride-th sample at this pass's precision and
+        // then in FP64, on the same emission grids (they depend on the beam
+        // and laser only); per shot: histogram, energies, angles
+        const int32_t stride = N->shadow_stride > 0 ? N->shadow_stride : 64;
+        int64_t span = 0;
+        for (int k = 0; k < n_shots; ++k) span += PB[k].n_ph + 2 + 2 + 6;
+        if ((st = grow(c, &c->shadow, &c->shadow_cap, (size_t)(2 * span), "shadow outputs")) !=
+            QS_OK)
+            return st;
+        std::vector<int64_t> nv(n_shots);
+        std::vector<qs_photon_outputs> v32(n_shots), v64(n_shots);
+        int64_t o = 0;
+        for (int k = 0; k < n_shots; ++k) {
+            nv[k] = (n_samples[k] + stride - 1) / stride;
+            const int64_t nh = PB[k].n_ph + 2;
+            double *a = c->shadow + o, *d = a + span;
+            v32[k] = qs_photon_outputs{a, a + nh, nullptr, PO[k].angles ? a + nh + 2 : nullptr,
+                                       nullptr};
+            v64[k] = qs_photon_outputs{d, d + nh, nullptr, PO[k].angles ? d + nh + 2 : nullptr,
+                                       PO[k].errors};
+            o += nh + 8;
+        }
+        qs_numerics vn = *N;
+        vn.flags = 0;
+        const View v32v{stride, 0, false}, v64v{stride, span, true};
+        if ((st = photons_impl(c, n_shots, L, B, nv.data(), &vn, PB, v32.data(), s, &v32v)) !=
+            QS_OK)
+            return st;
+        vn.precision = QS_PREC_FP64;
+        if ((st = photons_impl(c, n_shots, L, B, nv.data(), &vn, PB, v64.data(), s, &v64v)) !=
+            QS_OK)
+            return st;
+    }
     c->last_error[0] = 0;
     return QS_OK;
 }

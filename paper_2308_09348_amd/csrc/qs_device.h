@@ -47,12 +47,15 @@ struct SampleCoords {
     double n[6];
 };
 
+// Sample i of a shot table entry: sample i draw_stride of the shot (a view
+// with draw_stride > 1 holds every draw_stride-th sample).
 __device__ __forceinline__ void sample_coords(const ShotParams &sp, uint32_t k0, uint32_t k1,
                                               int64_t i, SampleCoords &sc) {
     uint32_t r[8];
+    const uint32_t ctr0 = (uint32_t)(i * (int64_t)sp.draw_stride);
 #pragma unroll
     for (uint32_t k = 0; k < 2; ++k) {
-        uint32_t c[4] = {(uint32_t)i, (uint32_t)sp.shot_word, k, 0u};
+        uint32_t c[4] = {ctr0, (uint32_t)sp.shot_word, k, 0u};
         philox4x32_10(c, k0, k1);
         r[4 * k + 0] = c[0];
         r[4 * k + 1] = c[1];
@@ -485,7 +488,7 @@ __device__ __forceinline__ void chi_order(const ShotParams &sp, uint32_t key0, u
             // any order gives the same results up to the FP64-step choice)
             double g0, thx, thy, S0;
             Path<double, false> pd{};
-            draw_sample<false>(sp, key0, key1, i * sp.draw_stride, g0, thx, thy, pd, S0);
+            draw_sample<false>(sp, key0, key1, i, g0, thx, thy, pd, S0);
             key = (float)(S0 * g0);
         }
         s_key[q] = key;

@@ -162,6 +162,7 @@ struct ShotPhot {
     double *angles;              // optional [6]: Sec. 5.1 photon angular moments
     int64_t pitem0;              // first photon work item
     int64_t grid_off;            // its grid in the accumulators (kPhNodes words)
+    double *errors;              // optional [14]: FP64-shadow report of the shot
 };
 
 // Adjoint in/out pointers of one shot (device table).
@@ -170,8 +171,9 @@ struct ShotGrad {
     double *grad;            // 8 derivatives (order of the qs_grad_param enum)
     int32_t *status;         // optional
     const double *d_angle;   // upstream weights over the n_th + 2 angle bins, or null
-    const double *d_moments; // upstream weights over the 16 moments, or null
+    const double *d_moments; // upstream weights over the kMoments moments, or null
     const double *moments;   // the forward pass's moments (with d_moments)
+    double *errors;          // optional [17]: FP64-shadow report of the shot
 };
 
 constexpr int kGradParams = 8;
@@ -245,9 +247,15 @@ hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, 
 hipError_t launch_photon(const BatchParams &p, const float *env32, const double *env64, int prec,
                          int rr, int amp, hipStream_t s);
 hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t s);
+// FP64-shadow report of a photon pass: the batch is the FP64 view pass, whose
+// outputs sit `span` doubles after those of the FP32 view pass; span 0 writes
+// zeros (no shadow).  One block per shot with errors.
+hipError_t launch_photon_shadow(const BatchParams &p, int64_t span, hipStream_t s);
 hipError_t launch_photon_cdf(const double *phtab, int64_t n, const double *chi, const double *xi,
                              double *out, hipStream_t s);
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s);
+// The same for an adjoint pass (gradients `span` doubles apart).
+hipError_t launch_grad_shadow(const BatchParams &p, int64_t span, hipStream_t s);
 // plane-wave reconstruction (qs_factor.hip): the node pass is the phase
 // kernel in node mode on the node view of the shot table; the interpolation
 // pass writes sample states for the deposit and finalize kernels

@@ -98,7 +98,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
             g0 = sp.g_node_lo + (double)m * sp.g_node_step;  // rounded twice, as defined
         }
     } else {
-        draw_sample<MODES>(sp, P.key0, P.key1, i * sp.draw_stride, g0, thx, thy, pd, S0);
+        draw_sample<MODES>(sp, P.key0, P.key1, i, g0, thx, thy, pd, S0);
     }
     const double a0S0 = sp.a0 * S0;
 

@@ -886,6 +886,60 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
     }
 }
 
+// FP64-shadow report of one shot.  The batch is the FP64 view pass; the FP32
+// view pass wrote the same layout span doubles earlier (span 0: no shadow,
+// zeros).  Relative differences are signed, against the FP64 value.
+__device__ __forceinline__ double rel_diff(double a, double b) {
+    return b != 0.0 ? (a - b) / b : 0.0;
+}
+
+__global__ __launch_bounds__(256) void photon_shadow_kernel(BatchParams P, int64_t span) {
+    const ShotPhot &pp = P.phot[blockIdx.x];
+    double *o = pp.errors;
+    if (!o) return;
+    const int tid = threadIdx.x;
+    constexpr int kOut = 14;  // QS_PE_N
+    if (span == 0) {
+        if (tid < kOut) o[tid] = 0.0;
+        return;
+    }
+    const double *h64 = pp.hist, *h32 = pp.hist - span;
+    double l1 = 0.0, mx = 0.0, tot = 0.0;
+    for (int k = tid; k < pp.n_ph + 2; k += blockDim.x) {
+        const double d = fabs(h32[k] - h64[k]);
+        l1 += d;
+        mx = fmax(mx, d);
+        tot += h64[k];
+    }
+    __shared__ double r_l1[256], r_mx[256], r_tot[256];
+    r_l1[tid] = l1;
+    r_mx[tid] = mx;
+    r_tot[tid] = tot;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            r_l1[tid] += r_l1[tid + w];
+            r_mx[tid] = fmax(r_mx[tid], r_mx[tid + w]);
+            r_tot[tid] += r_tot[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double T = r_tot[0];
+        o[0] = (double)P.shots[blockIdx.x].n_samples;
+        o[1] = T > 0.0 ? r_l1[0] / T : 0.0;
+        o[2] = T > 0.0 ? r_mx[0] / T : 0.0;
+        const double *e64 = pp.energy, *e32 = pp.energy - span;
+        o[3] = rel_diff(e32[0], e64[0]);
+        o[4] = rel_diff(e32[1], e64[1]);
+        for (int j = 0; j < 6; ++j)
+            o[5 + j] = pp.angles ? rel_diff(pp.angles[j - span], pp.angles[j]) : 0.0;
+        o[11] = T;
+        o[12] = e64[0];
+        o[13] = e64[1];
+    }
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
@@ -932,6 +986,11 @@ hipError_t launch_photon(const BatchParams &p, const float *env32, const double 
 
 hipError_t launch_photon_finalize(const BatchParams &p, double c_ph, hipStream_t s) {
     photon_finalize_kernel<<<p.n_shots, 256, 0, s>>>(p, c_ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_photon_shadow(const BatchParams &p, int64_t span, hipStream_t s) {
+    photon_shadow_kernel<<<p.n_shots, 256, 0, s>>>(p, span);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ def test_binding_covers_the_exports():
 def test_abi_version_and_strerror():
     from paper_2308_09348_amd import _lib
     L = _lib.lib()
-    assert L.qs_abi_version() == 2
+    assert L.qs_abi_version() == 3
     assert L.qs_strerror(0) == b"ok"
     assert L.qs_strerror(1) == b"invalid argument"
     assert L.qs_strerror(99) == b"unknown status"

@@ -203,7 +203,26 @@ def test_derivative_tables(gpu, oracle):
     f64 = gpu.radiation_eval(t, "fp64").cpu().numpy()
     assert np.array_equal(d64[:, :4], f64)
     d32 = gpu.radiation_derivs(t, "fp32").cpu().numpy()
-    assert np.all(np.abs(d32 - d64) <= 1e-5 * np.abs(d64).max(axis=0) + 2e-6 * np.abs(d64))
+    # The FP32 table holds the combinations the step's Jacobian uses:
+    # g, E1 = 2g + G1, E2 = 2g + 4 G1 + G2, h, E3 = 6 G1 + 6 G2 + G3, H1
+    # (G1 = chi dg/dchi, G2 = chi^2 d2g/dchi2, G3 = chi^3 d3g/dchi3, H1 = chi
+    # dh/dchi).  Each is a cubic per cell fitted to the FP64 values and
+    # evaluated in FP32: within 2e-6 of its own size and of its largest size
+    # over chi.
+    def combos(d):
+        g, G1, G2, h, G3, H1 = d.T
+        return np.stack([g, 2 * g + G1, 2 * g + 4 * G1 + G2, h, 6 * (G1 + G2) + G3, H1], axis=1)
+    c32, c64 = combos(d32), combos(d64)
+    tol_c = 2e-6 * np.abs(c64) + 2e-6 * np.abs(c64).max(axis=0)
+    assert np.all(np.abs(c32 - c64) <= tol_c)
+    # the single functions are undone from them by subtraction (in FP64):
+    # their errors are the combinations' errors carried through it
+    e_g, e_E1, e_E2, e_h, e_E3, e_H1 = tol_c.T
+    e_G1 = e_E1 + 2 * e_g
+    e_G2 = e_E2 + 2 * e_g + 4 * e_G1
+    e_G3 = e_E3 + 6 * (e_G1 + e_G2)
+    bound = np.stack([e_g, e_G1, e_G2, e_h, e_G3, e_H1], axis=1)
+    assert np.all(np.abs(d32 - d64) <= bound)
     du = 1.0 / 64.0
 
     def rad(c):

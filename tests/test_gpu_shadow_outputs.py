@@ -1,0 +1,232 @@
+"""FP64 shadow of the photon and adjoint passes (QS_VALIDATE_FP64): the view
+of every shadow_stride-th sample is run at the pass's precision and in FP64,
+and the differences go to qs_photon_outputs.errors and qs_grad_outputs.errors.
+
+With stride 1 the view is the whole shot, so each report must be exactly the
+difference of a plain FP32 pass and an FP64 pass (the view passes are those
+passes); with a larger stride the report's FP64 scales must be the oracle's
+sums over the strided samples (which pins the view to the right samples).
+
+Bars of the FP32 arithmetic against FP64, per output; each is the output's
+parity bar against the oracle, which the FP32 arithmetic alone must meet:
+  photon spectrum: L1 and largest bin, over the view's photon number, <= 1e-4
+  (the per-bin spectrum bar);
+  emitted energy, electron energy loss, angular moments: <= 2e-5 relative
+  (the FP32 photon energy bar);
+  gradient: max_p |dL/dp32 - dL/dp64| <= 1e-4 max_p |dL/dp64| (the norm-wise
+  gradient bar).
+"""
+import numpy as np
+import pytest
+
+from paper_2308_09348_amd import _lib, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09348_amd as qs
+    ctx = qs.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def _photon_case(n_samples=1500, **kw):
+    p = workloads.scaled(workloads.focused_3d(), n_samples=n_samples, n_steps=256)
+    p.update(rr_model="quantum", amp_mode="local", n_ph=64, ph_lo=0.0, ph_hi=1.2 * p["gamma0"])
+    p.update(kw)
+    return p
+
+
+def _rel(a, b):
+    return np.where(b != 0.0, (a - b) / np.where(b != 0.0, b, 1.0), 0.0)
+
+
+def _photon_bars(e):
+    assert 0.0 < e[_lib.PE_HIST_L1] <= 1e-4, e
+    assert e[_lib.PE_HIST_MAX] <= 1e-4, e
+    assert abs(e[_lib.PE_ENERGY]) <= 2e-5 and abs(e[_lib.PE_LOSS]) <= 2e-5, e
+    assert np.all(np.abs(e[_lib.PE_ANGLES:_lib.PE_ANGLES + 6]) <= 2e-5), e
+
+
+@pytest.mark.parametrize("chi64", [0.0, 0.1])
+def test_photon_report_at_stride_one_is_the_two_passes(gpu, chi64):
+    p = _photon_case(chi_fp64=chi64)
+    print(f"photon shadow, stride 1, chi_fp64={chi64}", flush=True)
+    g = _np(gpu.photons(dict(p, validate_fp64=True, shadow_stride=1), angles=True))
+    plain = _np(gpu.photons(p, angles=True))
+    d = _np(gpu.photons(dict(p, precision="fp64"), angles=True))
+    # the pass's own outputs are the plain FP32 pass's bits
+    for k in ("photon_hist", "energy", "angles"):
+        assert np.array_equal(g[k], plain[k]), k
+    e = g["errors"]
+    h32, h64 = plain["photon_hist"], d["photon_hist"]
+    T = e[_lib.PE_REF_PHOTONS]
+    print("report", e.tolist())
+    assert e[_lib.PE_SHADOW_N] == p["n_samples"]
+    assert abs(T - h64.sum()) <= 1e-13 * h64.sum()
+    assert abs(e[_lib.PE_HIST_L1] - np.abs(h32 - h64).sum() / T) <= 1e-12 * e[_lib.PE_HIST_L1]
+    assert e[_lib.PE_HIST_MAX] == np.abs(h32 - h64).max() / T
+    assert e[_lib.PE_ENERGY] == _rel(plain["energy"][0], d["energy"][0])
+    assert e[_lib.PE_LOSS] == _rel(plain["energy"][1], d["energy"][1])
+    assert np.array_equal(e[_lib.PE_ANGLES:_lib.PE_ANGLES + 6], _rel(plain["angles"], d["angles"]))
+    assert e[_lib.PE_REF_ENERGY] == d["energy"][0] and e[_lib.PE_REF_LOSS] == d["energy"][1]
+    _photon_bars(e)
+
+
+def test_photon_report_of_a_strided_view(gpu, oracle):
+    stride = 7
+    p = _photon_case(n_samples=600)
+    print("photon shadow, stride 7", flush=True)
+    g = _np(gpu.photons(dict(p, validate_fp64=True, shadow_stride=stride)))
+    e = g["errors"]
+    idx = range(0, p["n_samples"], stride)
+    H, E = np.zeros(p["n_ph"] + 2), np.zeros(2)
+    for i in idx:
+        h, en = oracle.photons(p, p["n_ph"], p["ph_lo"], p["ph_hi"], i, i + 1, nthreads=1)
+        H += h
+        E += en
+    print("report", e.tolist(), "oracle", E.tolist(), H.sum())
+    assert e[_lib.PE_SHADOW_N] == len(idx)
+    # exact sums on both sides (the photon parity bar of FP64 passes)
+    assert abs(e[_lib.PE_REF_ENERGY] - E[0]) <= 1e-10 * E[0]
+    assert abs(e[_lib.PE_REF_LOSS] - E[1]) <= 1e-10 * E[1]
+    # the grid's spectrum: within its L1 bar of the oracle's
+    assert abs(e[_lib.PE_REF_PHOTONS] - H.sum()) <= 2e-3 * H.sum()
+    assert np.all(e[_lib.PE_ANGLES:_lib.PE_ANGLES + 6] == 0.0)  # angles not asked for
+    _photon_bars(e)
+
+
+def test_photon_report_is_zero_without_a_shadow(gpu):
+    p = _photon_case(n_samples=300)
+    # an FP64 pass has nothing to shadow
+    g = _np(gpu.photons(dict(p, precision="fp64", validate_fp64=True), angles=True))
+    assert not g["errors"].any()
+
+
+def test_photon_report_batched_equals_single(gpu):
+    base = _photon_case(validate_fp64=True, shadow_stride=5)
+    shots = [dict(base, n_samples=n, a0=a) for n, a in ((1500, 30.0), (1, 50.0), (777, 80.0))]
+    print("photon shadow, batch of 3", flush=True)
+    batch = [_np(o) for o in gpu.photons_batched(shots, angles=True)]
+    for k, s in enumerate(shots):
+        single = _np(gpu.photons(dict(s, shot=k), angles=True))
+        for key in single:
+            assert np.array_equal(batch[k][key], single[key]), (k, key)
+    assert batch[1]["errors"][_lib.PE_SHADOW_N] == 1
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+
+def _grad_case(n_samples=400, **kw):
+    p = workloads.scaled(workloads.differentiation(), n_samples=n_samples, n_steps=256)
+    p.update(rr_model="quantum", amp_mode="local", deposit="gauss")
+    p.update(kw)
+    return p
+
+
+def _weights(n_e, seed=11):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(size=n_e + 2)
+
+
+def _backward(ctx, p, w, **kw):
+    import torch
+    out = ctx.backward(p, torch.tensor(w, dtype=torch.float64, device="cuda"), **kw)
+    if isinstance(out, tuple):
+        return tuple(x.cpu().numpy() for x in out)
+    return out.cpu().numpy()
+
+
+def _grad_bar(e):
+    d = e[_lib.GE_DIFF:_lib.GE_DIFF + 8]
+    r = e[_lib.GE_REF:_lib.GE_REF + 8]
+    print("grad report: max |diff| / max |ref|", np.abs(d).max() / np.abs(r).max())
+    assert np.abs(d).max() > 0.0
+    assert np.abs(d).max() <= 1e-4 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("chi64", [0.0, 0.1])
+def test_grad_report_at_stride_one_is_the_two_passes(gpu, chi64):
+    p = _grad_case(chi_fp64=chi64)
+    w = _weights(p["n_e"])
+    print(f"adjoint shadow, stride 1, chi_fp64={chi64}", flush=True)
+    g, e = _backward(gpu, dict(p, validate_fp64=True, shadow_stride=1), w, errors=True)
+    g32 = _backward(gpu, p, w)
+    g64 = _backward(gpu, dict(p, precision="fp64"), w)
+    assert np.array_equal(g, g32)
+    assert e[_lib.GE_SHADOW_N] == p["n_samples"]
+    assert np.array_equal(e[_lib.GE_DIFF:_lib.GE_DIFF + 8], g32 - g64)
+    assert np.array_equal(e[_lib.GE_REF:_lib.GE_REF + 8], g64)
+    _grad_bar(e)
+
+
+def test_grad_report_of_a_tape_adjoint(gpu):
+    """A tape adjoint's view passes recompute the trajectories: the report
+    is the recomputing adjoint's, and the tape's gradient is that adjoint's
+    FP32 gradient bit for bit."""
+    p = _grad_case(chi_fp64=0.1)
+    w = _weights(p["n_e"])
+    print("adjoint shadow of a tape", flush=True)
+    tape = gpu.new_tape(p["n_samples"])
+    gpu.forward(p, tape=tape)
+    v = dict(p, validate_fp64=True, shadow_stride=1)
+    g, e = _backward(gpu, v, w, tape=tape, errors=True)
+    g_rec, e_rec = _backward(gpu, v, w, errors=True)
+    assert np.array_equal(g, g_rec)
+    assert np.array_equal(e, e_rec)
+    _grad_bar(e)
+
+
+def test_grad_report_of_a_strided_view(gpu, oracle):
+    stride = 7
+    p = _grad_case()
+    w = _weights(p["n_e"])
+    print("adjoint shadow, stride 7", flush=True)
+    _, e = _backward(gpu, dict(p, validate_fp64=True, shadow_stride=stride), w, errors=True)
+    idx = range(0, p["n_samples"], stride)
+    og, scale = np.zeros(8), np.zeros(8)
+    for i in idx:
+        _, jac = oracle.grad(p, i, i + 1, nthreads=1)
+        og += w @ jac
+        scale += np.abs(w) @ np.abs(jac)
+    ref = e[_lib.GE_REF:_lib.GE_REF + 8]
+    g32 = ref + e[_lib.GE_DIFF:_lib.GE_DIFF + 8]
+    print("ref", ref.tolist(), "oracle", og.tolist())
+    assert e[_lib.GE_SHADOW_N] == len(idx)
+    # the FP64 and FP32 adjoint parity bars against the oracle
+    assert np.all(np.abs(ref - og) <= 1e-9 * scale + 1e-300)
+    assert np.all(np.abs(g32 - og) <= 1e-5 * scale + 1e-300)
+    _grad_bar(e)
+
+
+def test_grad_report_is_zero_without_a_shadow(gpu):
+    p = _grad_case(n_samples=100)
+    w = _weights(p["n_e"])
+    _, e = _backward(gpu, p, w, errors=True)
+    assert not e.any()
+    _, e = _backward(gpu, dict(p, precision="fp64", validate_fp64=True), w, errors=True)
+    assert not e.any()
+
+
+def test_grad_report_batched_equals_single(gpu):
+    import torch
+    base = _grad_case(validate_fp64=True, shadow_stride=3)
+    shots = [dict(base, n_samples=n, a0=a) for n, a in ((400, 30.0), (1, 50.0), (257, 80.0))]
+    ws = [torch.tensor(_weights(s["n_e"], seed=k), dtype=torch.float64, device="cuda")
+          for k, s in enumerate(shots)]
+    print("adjoint shadow, batch of 3", flush=True)
+    grads, errs = gpu.backward_batched(shots, ws, errors=True)
+    for k, s in enumerate(shots):
+        g, e = gpu.backward(dict(s, shot=k), ws[k], errors=True)
+        assert torch.equal(grads[k], g) and torch.equal(errs[k], e), k
+    assert errs[1][_lib.GE_SHADOW_N].item() == 1
