@@ -423,6 +423,11 @@ def factorised_leg(ctx, workloads, torch, steps):
             "mean_gamma_rel_diff": float(abs(mf[1] - md[1]) / md[1])}
 
 
+def note(msg):
+    """A progress line on stderr as each leg ends (stdout holds the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -463,6 +468,7 @@ def main():
 
     ms_per_step = 1e3 * wall / args.steps
     value = n * N / (wall / args.steps)
+    note(f"forward: {ms_per_step:.3f} ms per pass")
     phase_avg_ms = sum(phase_ms) / len(phase_ms)
     flops_step = alg_flops(params["rr_model"], params["amp_mode"])
     flops_launch = flops_step * n * N
@@ -520,6 +526,7 @@ def main():
         k_ms = sum(mixed_ms) / len(mixed_ms)
         pk = mixed_peak(share)
         ach = flops_launch / (k_ms * 1e-3) / 1e12
+        note(f"forward at chi_fp64 = 0.1: {1e3 * wall_m:.3f} ms per pass")
         line["fwd_chi_fp64_0p1"] = {
             "chi_fp64": 0.1, "fp64_step_share": share, "ms_per_step": 1e3 * wall_m,
             "sample_steps_per_s": n * N / wall_m, "kernel_avg_ms": k_ms,
@@ -559,6 +566,7 @@ def main():
         if bad != 0:
             raise RuntimeError(f"device status {bad} in the batched leg")
         n_tot = sum(p["n_samples"] for p in shots)
+        note(f"batched: {1e3 * dt:.1f} ms per batch")
         line["batched"] = {
             "workload": "4096 shots, samples log-uniform in [2^12, 2^18], a0 U[5,100], "
                         "W0 U[2,6]um, offsets N(0,2^2)um, delay N(0,15^2)fs, gamma0 "
@@ -571,11 +579,14 @@ def main():
         ctx.set_graphs(False)
     if args.factorised_steps > 0:
         line["factorised"] = factorised_leg(ctx, workloads, torch, args.factorised_steps)
+        note("factorised leg done")
     if args.adjoint_steps > 0:
         line["adjoint"] = adjoint_leg(ctx, qs, workloads, torch, args.adjoint_steps)
+        note("adjoint leg done")
     if args.quantum_batch_steps > 0:
         line["quantum_batch"] = quantum_batch_leg(ctx, workloads, torch, args.quantum_batch_steps,
                                                   args.tune_cache)
+        note(f"quantum batch: {line['quantum_batch']['ms_per_step']:.0f} ms per step")
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
@@ -586,8 +597,10 @@ def main():
         line["copy_probe_bytes"] = nb
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
+        note("CPU baseline of the forward workload done")
         if args.cpu_other_seconds > 0:
             line["cpu_baselines"] = cpu_baselines(workloads, args.cpu_other_seconds)
+            note("CPU baselines of the other workloads done")
     print(json.dumps(line), flush=True)
     ctx.close()
 

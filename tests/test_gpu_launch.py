@@ -151,3 +151,24 @@ def test_tuner_on_a_batch(qs, tmp_path):
             _same(got[k], ref[k], f"tuned batch, launch {r}, shot {k}")
     plain.close()
     tuned.close()
+
+
+def test_graph_replays_follow_the_shadow_stride(qs):
+    """The FP64-shadow launches of a captured batch take their item count from
+    shadow_stride: a new stride that leaves every buffer size unchanged
+    (16384 and 6400 samples, stride 64 then 63) must be captured anew, not
+    replayed with the old count."""
+    eager = qs.Context(0)
+    graph = qs.Context(0)
+    graph.set_graphs(True)
+    base = [_case(n_samples=n, a0=a, shot=0, validate_fp64=True)
+            for n, a in ((16384, 30.0), (6400, 45.0))]
+    for stride in (64, 63, 64):
+        shots = [dict(s, shadow_stride=stride) for s in base]
+        ref = [_np(o) for o in eager.forward_batched(shots)]
+        for r in range(2):
+            got = [_np(o) for o in graph.forward_batched(shots)]
+            for k in range(len(shots)):
+                _same(got[k], ref[k], f"stride {stride} replay {r} shot {k}")
+    eager.close()
+    graph.close()

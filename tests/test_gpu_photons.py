@@ -208,3 +208,19 @@ def test_mixed_photons_batched_equals_single(gpu):
         single = _np(gpu.photons(dict(s, shot=k), angles=True))
         for key in ("photon_hist", "energy", "angles", "status"):
             assert np.array_equal(batch[k][key], single[key]), (k, key)
+
+
+@pytest.mark.parametrize("k", [0, 255])
+def test_photon_spectrum_of_quantum_batch_shots(gpu, oracle, k):
+    """Shots of the quantum batch at their own numerics -- 2048 steps, 256
+    photon bins, FP64 steps where chi > 0.1 -- on a 512-sample prefix (the
+    counter-based draw makes a prefix the same samples as in the full shot),
+    against the oracle at the emission grid's bars."""
+    p = dict(workloads.quantum_batch()[k], n_samples=512)
+    assert p["n_steps"] == 2048 and p["n_ph"] == 256 and p["chi_fp64"] == 0.1
+    print(f"photons: quantum batch shot {k}, 512 samples", flush=True)
+    g = _np(gpu.photons(p, angles=True))
+    o = oracle.photons(p, p["n_ph"], p["ph_lo"], p["ph_hi"])
+    _check(g, o, p, 2e-5, f"quantum-batch-{k}")
+    oa = oracle.photon_angles(p)
+    assert np.all(np.abs(g["angles"] - oa) <= 2e-5 * np.abs(oa)), (g["angles"], oa)
