@@ -928,8 +928,9 @@ __device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t i
 // waves per SIMD; every other pass is held to 256 (two waves): the FP64 ones
 // would otherwise take a few registers more and run one wave per SIMD, and
 // the mixed ones are held to two by the FP64 table staging in LDS anyway.
-// Mixed precision (FP64 steps): every lane of a wavefront runs, lanes past a
-// shot's end repeat its last sample, for the wavefront's table reads.
+// Mixed precision (FP64 steps): the work items are groups of kGradGroup
+// samples taken in rounds in order of their chi scale; every lane of a
+// wavefront runs, lanes past the group's end repeat its last sample.
 template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
 __global__ __launch_bounds__(kPhaseBlock)
 __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void tangent_kernel(
@@ -940,10 +941,10 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
     __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
-    // FP64 steps where chi is high: the lanes take the item's samples in
-    // order of their chi scale, as the forward pass does (chi_order)
-    __shared__ float okey[kWave64 ? kPhaseBlock : 1];
-    __shared__ unsigned short oidx[kWave64 ? kPhaseBlock : 1];
+    // FP64 steps where chi is high: the group's samples in order of their chi
+    // scale, as the forward pass orders its items (chi_order)
+    __shared__ float okey[kWave64 ? kGradGroup : 1];
+    __shared__ unsigned short oidx[kWave64 ? kGradGroup : 1];
     double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
@@ -951,76 +952,73 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
         for (int k = threadIdx.x; k < kCells32 * kDerivFuncs; k += blockDim.x) dst[k] = src[k];
         __syncthreads();
     }
+    // one sample: the tape entries and final state (TAPE), else its terms
+    // of the gradient added to g
+    auto one = [&](const ShotParams &sp, int s, int64_t i, bool live, double *g) {
+        int flags = 0;
+        SampleTangent o;
+        tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, i, env32, env64, tab32, wstage, o, flags);
+        if (!live) return;  // ran for the wavefront's table reads only
+        if (TAPE) {
+            const int64_t k = sp.state_off + i;
+            P.st.mu[k] = o.mu;
+            P.st.s2[k] = o.s2;
+            P.st.S0[k] = o.S0;
+            P.st.g0[k] = o.g0;
+            P.st.thx[k] = o.thx;
+            P.st.thy[k] = o.thy;
+            P.st.cmx[k] = o.cmx;
+            double *tp = P.tape + k;
+            const int64_t n = P.tape_n;
+            tp[0] = o.mu;
+            tp[n] = o.s2;
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) {
+                tp[(2 + p) * n] = o.dmu[p];
+                tp[(2 + kGradParams + p) * n] = o.ds2[p];
+            }
+        } else if (!(flags & kFlagNonFinite)) {
+            const ShotGrad &go = P.gouts[s];
+            double gi[kGradParams];
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) gi[p] = 0.0;
+            if (go.d_energy) {
+                double lv, ls;
+                law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                go.d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) gi[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
+            }
+            observable_sensitivity(P, sp, go, i, o.mu, o.s2, o.dmu, o.ds2, gi);
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) g[p] += gi[p];
+        }
+        if (flags) atomicOr(&P.flags[s], flags);
+    };
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
-        if (item >= P.n_items) break;
-        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
-        const ShotParams &sp = P.shots[s];
-        const int64_t base = (item - sp.item0) * kPhaseBlock;
-        int off = threadIdx.x;
-        if constexpr (kWave64) {
-            chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
-            off = oidx[threadIdx.x];
-        }
-        const int64_t i = base + off;
         double g[kGradParams];
 #pragma unroll
         for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
-        const bool live = i < sp.n_samples;
-        if (kWave64 || live) {
-            int flags = 0;
-            SampleTangent o;
-            tangent_sample<PREC, QUANTUM, LOCAL>(P, sp, live ? i : sp.n_samples - 1, env32, env64,
-                                                 tab32, wstage, o, flags);
-            if (!live) {
-                // a lane past the shot's end: ran its last sample for the
-                // wavefront's table reads, stores and adds nothing
-            } else if (TAPE) {
-                const int64_t k = sp.state_off + i;
-                P.st.mu[k] = o.mu;
-                P.st.s2[k] = o.s2;
-                P.st.S0[k] = o.S0;
-                P.st.g0[k] = o.g0;
-                P.st.thx[k] = o.thx;
-                P.st.thy[k] = o.thy;
-                P.st.cmx[k] = o.cmx;
-                double *t = P.tape + k;
-                const int64_t n = P.tape_n;
-                t[0] = o.mu;
-                t[n] = o.s2;
-#pragma unroll
-                for (int p = 0; p < kGradParams; ++p) {
-                    t[(2 + p) * n] = o.dmu[p];
-                    t[(2 + kGradParams + p) * n] = o.ds2[p];
-                }
-            } else if (!(flags & kFlagNonFinite)) {
-                const ShotGrad &go = P.gouts[s];
-                if (go.d_energy) {
-                    double lv, ls;
-                    law_sensitivity(o.mu, o.s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
-                                    go.d_energy, lv, ls);
-#pragma unroll
-                    for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, o.dmu[p], ls * o.ds2[p]);
-                }
-                observable_sensitivity(P, sp, go, i, o.mu, o.s2, o.dmu, o.ds2, g);
+        if constexpr (kWave64) {
+            if (item >= P.n_gitems) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_group_shot(P.shots, P.n_shots, item));
+            const ShotParams &sp = P.shots[s];
+            const int64_t base = (item - sp.gitem0) * kGradGroup;
+            const int cnt = (int)min((int64_t)kGradGroup, sp.n_samples - base);
+            chi_order<kGradGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            for (int r = 0; r * kPhaseBlock < cnt; ++r) {
+                const int rank = r * kPhaseBlock + (int)threadIdx.x;
+                if (r * kPhaseBlock + (int)(threadIdx.x & ~63u) >= cnt) continue;  // whole wavefront
+                const bool live = rank < cnt;
+                one(sp, s, base + oidx[live ? rank : cnt - 1], live, g);
             }
-            if (live && flags) atomicOr(&P.flags[s], flags);
-        }
-        if constexpr (kWave64 && !TAPE) {
-            // the lanes held the item's samples in chi order: hand each
-            // sample's terms to the lane of its index (through the FP64 table
-            // staging, idle between items), so that the item's sum is formed
-            // in sample order, as the contraction of a tape forms it
-            static_assert(sizeof(stage) >= sizeof(double) * kPhaseBlock * kGradParams,
-                          "the staging area holds the item's terms");
-            double *gx = reinterpret_cast<double *>(stage);
-            __syncthreads();  // every wavefront is past its table reads
-#pragma unroll
-            for (int p = 0; p < kGradParams; ++p) gx[off * kGradParams + p] = g[p];
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < kGradParams; ++p) g[p] = gx[threadIdx.x * kGradParams + p];
-            __syncthreads();  // before the next item's table reads
+        } else {
+            if (item >= P.n_items) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+            const ShotParams &sp = P.shots[s];
+            const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+            if (i < sp.n_samples) one(sp, s, i, true, g);
         }
         if (!TAPE) grad_item_reduce(P, item, g, red);
     }
@@ -1030,42 +1028,65 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
 // law sensitivities (memory-bound: 144 bytes a sample).
 // OBS: some shot also has angle-histogram or moment weights (the memory-bound
 // contraction of the energy terms alone keeps its small register budget).
-template <bool OBS>
+// GROUPED: the tape of a pass with FP64 steps, summed over the groups of its
+// tangent pass in the same order (rounds in chi order, each lane adding its
+// samples' terms round by round, then the block reduction), so that the
+// result equals the recomputing adjoint's bit for bit.
+template <bool OBS, bool GROUPED>
 __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
+    __shared__ float okey[GROUPED ? kGradGroup : 1];
+    __shared__ unsigned short oidx[GROUPED ? kGradGroup : 1];
+    auto one = [&](const ShotParams &sp, int s, int64_t i, double *g) {
+        const int64_t n = P.tape_n;
+        const double *t = P.tape + sp.state_off + i;
+        const double mu = t[0], s2 = t[n];
+        if (mu > 0.0 && isfinite(mu) && isfinite(s2)) {
+            const ShotGrad &go = P.gouts[s];
+            double dm[kGradParams], ds[kGradParams], gi[kGradParams];
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) {
+                dm[p] = t[(2 + p) * n];
+                ds[p] = t[(2 + kGradParams + p) * n];
+                gi[p] = 0.0;
+            }
+            if (go.d_energy) {
+                double lv, ls;
+                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
+                                go.d_energy, lv, ls);
+#pragma unroll
+                for (int p = 0; p < kGradParams; ++p) gi[p] = fma(lv, dm[p], ls * ds[p]);
+            }
+            if (OBS) observable_sensitivity(P, sp, go, i, mu, s2, dm, ds, gi);
+#pragma unroll
+            for (int p = 0; p < kGradParams; ++p) g[p] += gi[p];
+        } else {
+            atomicOr(&P.flags[s], kFlagNonFinite);
+        }
+    };
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
-        if (item >= P.n_items) break;
-        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
-        const ShotParams &sp = P.shots[s];
-        const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
         double g[kGradParams];
 #pragma unroll
         for (int p = 0; p < kGradParams; ++p) g[p] = 0.0;
-        if (i < sp.n_samples) {
-            const int64_t n = P.tape_n;
-            const double *t = P.tape + sp.state_off + i;
-            const double mu = t[0], s2 = t[n];
-            if (mu > 0.0 && isfinite(mu) && isfinite(s2)) {
-                const ShotGrad &go = P.gouts[s];
-                double dm[kGradParams], ds[kGradParams];
-#pragma unroll
-                for (int p = 0; p < kGradParams; ++p) {
-                    dm[p] = t[(2 + p) * n];
-                    ds[p] = t[(2 + kGradParams + p) * n];
-                }
-                if (go.d_energy) {
-                    double lv, ls;
-                    law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
-                                    go.d_energy, lv, ls);
-#pragma unroll
-                    for (int p = 0; p < kGradParams; ++p) g[p] = fma(lv, dm[p], ls * ds[p]);
-                }
-                if (OBS) observable_sensitivity(P, sp, go, i, mu, s2, dm, ds, g);
-            } else {
-                atomicOr(&P.flags[s], kFlagNonFinite);
+        if constexpr (GROUPED) {
+            if (item >= P.n_gitems) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_group_shot(P.shots, P.n_shots, item));
+            const ShotParams &sp = P.shots[s];
+            const int64_t base = (item - sp.gitem0) * kGradGroup;
+            const int cnt = (int)min((int64_t)kGradGroup, sp.n_samples - base);
+            chi_order<kGradGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            for (int r = 0; r * kPhaseBlock < cnt; ++r) {
+                const int rank = r * kPhaseBlock + (int)threadIdx.x;
+                if (rank < cnt) one(sp, s, base + oidx[rank], g);
             }
+        } else {
+            if (item >= P.n_items) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+            const ShotParams &sp = P.shots[s];
+            const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+            if (i < sp.n_samples) one(sp, s, i, g);
         }
         grad_item_reduce(P, item, g, red);
     }
@@ -1076,12 +1097,16 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(BatchParams P) {
     const int s = blockIdx.x;
     const ShotParams &sp = P.shots[s];
     const ShotGrad &so = P.gouts[s];
-    const int64_t ni = (sp.n_samples + kPhaseBlock - 1) / kPhaseBlock;
+    // partials per group with FP64 steps, else per phase item
+    const bool grouped = P.prec == PREC_F32MIX;
+    const int64_t ni = grouped ? (sp.n_samples + kGradGroup - 1) / kGradGroup
+                               : (sp.n_samples + kPhaseBlock - 1) / kPhaseBlock;
+    const int64_t first = grouped ? sp.gitem0 : sp.item0;
     __shared__ double tree[256];
     for (int p = 0; p < kGradParams; ++p) {
         double acc = 0.0;
         for (int64_t b = threadIdx.x; b < ni; b += blockDim.x)
-            acc += P.partials[(size_t)(sp.item0 + b) * kGradParams + p];
+            acc += P.partials[(size_t)(first + b) * kGradParams + p];
         tree[threadIdx.x] = acc;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -1171,8 +1196,9 @@ static const void *select_tangent(int prec, int rr, int amp) {
 hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
                           int rr, int amp, bool tape, hipStream_t s) {
     const void *fn = tape ? select_tangent<true>(prec, rr, amp) : select_tangent<false>(prec, rr, amp);
+    const bool grouped = prec == PREC_F32MIX && rr == 1;
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, grouped ? p.n_gitems : p.n_items, &grid);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     const float *e32 = env32;
@@ -1182,10 +1208,15 @@ hipError_t launch_tangent(const BatchParams &p, const float *env32, const double
 }
 
 hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s) {
-    const void *fn = obs ? reinterpret_cast<const void *>(&contract_kernel<true>)
-                         : reinterpret_cast<const void *>(&contract_kernel<false>);
+    // a tape of a pass with FP64 steps is summed over that pass's groups
+    const bool grouped = p.prec == PREC_F32MIX;
+    const void *fn =
+        grouped ? (obs ? reinterpret_cast<const void *>(&contract_kernel<true, true>)
+                       : reinterpret_cast<const void *>(&contract_kernel<false, true>))
+                : (obs ? reinterpret_cast<const void *>(&contract_kernel<true, false>)
+                       : reinterpret_cast<const void *>(&contract_kernel<false, false>));
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid);
+    hipError_t e = resident_grid(fn, kPhaseBlock, 0, grouped ? p.n_gitems : p.n_items, &grid);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     void *args[] = {&pc};

@@ -845,7 +845,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
     b.stage = stage;
     b.sp = reinterpret_cast<qs::ShotParams *>(stage);
     b.outs = stage + sizeof(qs::ShotParams) * n_shots;
-    int64_t item = 0, ditem = 0, mtile = 0, off = 0, hoff = 0;
+    int64_t item = 0, ditem = 0, mtile = 0, gitem = 0, off = 0, hoff = 0;
     for (int k = 0; k < n_shots; ++k) {
         const qs_laser &l = L[k];
         const qs_beam &bm = B[k];
@@ -896,6 +896,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         p.item0 = item;
         p.ditem0 = ditem;
         p.mtile0 = mtile;
+        p.gitem0 = gitem;
         p.hist_off = hoff;
         p.n_e = hb.n_e;
         p.n_th = hb.n_th;
@@ -908,11 +909,14 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         item += (n_samples[k] + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
         ditem += (n_samples[k] + bp.dep_tile - 1) / bp.dep_tile;
         mtile += (n_samples[k] + qs::kMomTile - 1) / qs::kMomTile;
+        gitem += (n_samples[k] + qs::kGradGroup - 1) / qs::kGradGroup;
         hoff += hb.n_e + 2 + hb.n_th + 2 + hb.n_a;
     }
     bp.n_items = item;
     bp.n_ditems = ditem;
     bp.n_mtiles = mtile;
+    bp.n_gitems = gitem;
+    bp.prec = b.prec;
     b.hist_words = hoff;
     return QS_OK;
 }

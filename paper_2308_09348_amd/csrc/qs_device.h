@@ -625,6 +625,19 @@ __device__ __forceinline__ int find_shot(const ShotParams *shots, int n_shots, i
     return lo;
 }
 
+// The shot of a group of the mixed-precision derivative passes.
+__device__ __forceinline__ int find_group_shot(const ShotParams *shots, int n_shots, int64_t grp) {
+    int lo = 0, hi = n_shots - 1;  // largest s whose first group is <= grp
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (shots[mid].gitem0 <= grp)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ int64_t next_item(unsigned int *counter, int64_t *slot) {
     if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1u);
     __syncthreads();

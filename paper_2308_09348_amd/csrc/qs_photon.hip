@@ -696,7 +696,14 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
     constexpr bool kWave64 = PREC == PREC_F32MIX;
     constexpr bool kTab32 = QUANTUM && PREC != PREC_F64;
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
-    __shared__ unsigned long long grid[kPhNodes];
+    // mixed precision: two copies of the grid, the even lanes of a wavefront
+    // depositing into one and the odd lanes into the other (the lanes hold
+    // samples of similar chi, so neighbours often hit the same node; the copy
+    // is offset by 32 banks), summed when the grid is flushed
+    constexpr int kRep = kWave64 ? 2 : 1;
+    constexpr int kRepStride = kPhNodes + 16;
+    __shared__ unsigned long long grid[(kRep - 1) * kRepStride + kPhNodes];
+    unsigned long long *lgrid = grid + (kRep > 1 ? (threadIdx.x & 1) * kRepStride : 0);
     __shared__ float tot[kPhRows];  // Phi(1; chi) / chi on the table rows
     // ... and as a cubic on each FP32 radiation cell
     __shared__ float4 ncell[kTab32 ? kCells32 : 1];
@@ -726,7 +733,8 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
         const ShotParams &sp = P.shots[s];
         const ShotPhot &pp = P.phot[s];
         const int nodes = pp.nu * pp.nv;
-        for (int k = threadIdx.x; k < nodes; k += blockDim.x) grid[k] = 0ull;
+        for (int r = 0; r < kRep; ++r)
+            for (int k = threadIdx.x; k < nodes; k += blockDim.x) grid[r * kRepStride + k] = 0ull;
         __syncthreads();
         PhotAcc acc{0.0, 0.0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double loss = 0.0;
@@ -738,7 +746,7 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
                 const int64_t i = i0 + oidx[b + threadIdx.x];
                 const bool live = i < i1;
                 photon_sample<PREC, QUANTUM, LOCAL>(P, sp, pp, live ? i : i1 - 1, env32, env64,
-                                                    tab32, grid, tot, ncell, wstage, live, acc,
+                                                    tab32, lgrid, tot, ncell, wstage, live, acc,
                                                     loss);
             }
         } else {
@@ -761,7 +769,8 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
             P.partials[(size_t)item * kPhotPartials + threadIdx.x] = sum;
         }
         for (int k = threadIdx.x; k < nodes; k += blockDim.x) {
-            const unsigned long long w = grid[k];
+            unsigned long long w = grid[k];
+            for (int r = 1; r < kRep; ++r) w += grid[r * kRepStride + k];
             if (w) atomicAdd(&P.pgrid[pp.grid_off + k], w);
         }
         __syncthreads();  // the next item clears the grid
