@@ -928,7 +928,7 @@ __device__ __forceinline__ void grad_item_reduce(const BatchParams &P, int64_t i
 // waves per SIMD; every other pass is held to 256 (two waves): the FP64 ones
 // would otherwise take a few registers more and run one wave per SIMD, and
 // the mixed ones are held to two by the FP64 table staging in LDS anyway.
-// Mixed precision (FP64 steps): the work items are groups of kGradGroup
+// Mixed precision (FP64 steps): the work items are groups of kChiGroup
 // samples taken in rounds in order of their chi scale; every lane of a
 // wavefront runs, lanes past the group's end repeat its last sample.
 template <int PREC, bool QUANTUM, bool LOCAL, bool TAPE>
@@ -943,8 +943,8 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
     __shared__ double red[kPhaseBlock / 64][kGradParams];
     // FP64 steps where chi is high: the group's samples in order of their chi
     // scale, as the forward pass orders its items (chi_order)
-    __shared__ float okey[kWave64 ? kGradGroup : 1];
-    __shared__ unsigned short oidx[kWave64 ? kGradGroup : 1];
+    __shared__ float okey[kWave64 ? kChiGroup : 1];
+    __shared__ unsigned short oidx[kWave64 ? kChiGroup : 1];
     double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32d);
@@ -1004,9 +1004,9 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
             if (item >= P.n_gitems) break;
             const int s = __builtin_amdgcn_readfirstlane(find_group_shot(P.shots, P.n_shots, item));
             const ShotParams &sp = P.shots[s];
-            const int64_t base = (item - sp.gitem0) * kGradGroup;
-            const int cnt = (int)min((int64_t)kGradGroup, sp.n_samples - base);
-            chi_order<kGradGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            const int64_t base = (item - sp.gitem0) * kChiGroup;
+            const int cnt = (int)min((int64_t)kChiGroup, sp.n_samples - base);
+            chi_order<kChiGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
             for (int r = 0; r * kPhaseBlock < cnt; ++r) {
                 const int rank = r * kPhaseBlock + (int)threadIdx.x;
                 if (r * kPhaseBlock + (int)(threadIdx.x & ~63u) >= cnt) continue;  // whole wavefront
@@ -1036,8 +1036,8 @@ template <bool OBS, bool GROUPED>
 __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
-    __shared__ float okey[GROUPED ? kGradGroup : 1];
-    __shared__ unsigned short oidx[GROUPED ? kGradGroup : 1];
+    __shared__ float okey[GROUPED ? kChiGroup : 1];
+    __shared__ unsigned short oidx[GROUPED ? kChiGroup : 1];
     auto one = [&](const ShotParams &sp, int s, int64_t i, double *g) {
         const int64_t n = P.tape_n;
         const double *t = P.tape + sp.state_off + i;
@@ -1074,9 +1074,9 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
             if (item >= P.n_gitems) break;
             const int s = __builtin_amdgcn_readfirstlane(find_group_shot(P.shots, P.n_shots, item));
             const ShotParams &sp = P.shots[s];
-            const int64_t base = (item - sp.gitem0) * kGradGroup;
-            const int cnt = (int)min((int64_t)kGradGroup, sp.n_samples - base);
-            chi_order<kGradGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            const int64_t base = (item - sp.gitem0) * kChiGroup;
+            const int cnt = (int)min((int64_t)kChiGroup, sp.n_samples - base);
+            chi_order<kChiGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
             for (int r = 0; r * kPhaseBlock < cnt; ++r) {
                 const int rank = r * kPhaseBlock + (int)threadIdx.x;
                 if (rank < cnt) one(sp, s, base + oidx[rank], g);
@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(BatchParams P) {
     const ShotGrad &so = P.gouts[s];
     // partials per group with FP64 steps, else per phase item
     const bool grouped = P.prec == PREC_F32MIX;
-    const int64_t ni = grouped ? (sp.n_samples + kGradGroup - 1) / kGradGroup
+    const int64_t ni = grouped ? (sp.n_samples + kChiGroup - 1) / kChiGroup
                                : (sp.n_samples + kPhaseBlock - 1) / kPhaseBlock;
     const int64_t first = grouped ? sp.gitem0 : sp.item0;
     __shared__ double tree[256];

@@ -909,7 +909,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         item += (n_samples[k] + qs::kPhaseBlock - 1) / qs::kPhaseBlock;
         ditem += (n_samples[k] + bp.dep_tile - 1) / bp.dep_tile;
         mtile += (n_samples[k] + qs::kMomTile - 1) / qs::kMomTile;
-        gitem += (n_samples[k] + qs::kGradGroup - 1) / qs::kGradGroup;
+        gitem += (n_samples[k] + qs::kChiGroup - 1) / qs::kChiGroup;
         hoff += hb.n_e + 2 + hb.n_th + 2 + hb.n_a;
     }
     bp.n_items = item;

@@ -58,12 +58,12 @@ constexpr int kDepTile = 4096;    // default deposit work item: kDepTile samples
 // deposit work item (a multiple of it), so the moments do not depend on it.
 constexpr int kMomTile = 1024;
 constexpr int kPartials = P_N + 3;  // moment sums and maxima of a moment tile
-// Derivative passes with FP64 steps (tape forward, adjoint, contraction): a
-// work item is a group of up to kGradGroup samples of one shot, which the
-// block takes in rounds of kPhaseBlock in order of their chi scale, so that
-// wavefronts hold samples of similar chi over a wider pool than one phase
-// item; the gradient partials are per group.
-constexpr int kGradGroup = 2048;
+// Passes with FP64 steps (forward, tape forward, adjoint, and the
+// contraction of their tapes): a work item is a group of up to kChiGroup
+// samples of one shot, which the block takes in rounds of kPhaseBlock in
+// order of their chi scale, so that wavefronts hold samples of similar chi
+// over a wider pool than one phase item; gradient partials are per group.
+constexpr int kChiGroup = 2048;
 constexpr int kMoments = 21;        // moments a shot returns (QS_M_N)
 
 enum Prec { PREC_F32 = 0, PREC_F32MIX = 1, PREC_F64 = 2 };
@@ -96,7 +96,7 @@ struct ShotParams {
     int64_t item0;       // its first phase work item
     int64_t ditem0;      // its first deposit work item
     int64_t mtile0;      // its first moment tile (kMomTile samples each)
-    int64_t gitem0;      // its first group (kGradGroup samples) of the mixed derivative passes
+    int64_t gitem0;      // its first group (kChiGroup samples) of the passes with FP64 steps
     int64_t hist_off;    // its first histogram word in the accumulators
     // FP64 shadow: samples i with i % shadow_stride == 0 have the FP64 state
     // shadow_off + i / shadow_stride (shadow_stride 0: none); a shot view
@@ -200,7 +200,7 @@ struct BatchParams {
     uint32_t key0, key1;
     double ksig_bins, c_theta;
     int64_t n_items, n_ditems, n_mtiles;
-    int64_t n_gitems;   // groups of the mixed-precision derivative passes
+    int64_t n_gitems;   // groups of the passes with FP64 steps
     const ShotParams *shots;
     const ShotOut *outs;
     const float *rad32;   // [kCells32 * 16]

@@ -257,11 +257,15 @@ __attribute__((amdgpu_waves_per_eu((PREC == PREC_F32 && QUANTUM) ? 4 : 1))) void
     __shared__ __align__(16) float tab32[kTab32 ? kCells32 * kCellVals : 4];
     __shared__ double2 stage[kWave64 ? (kPhaseBlock / 64) * kStageChunks : 1];
     __shared__ int64_t slot;
-    // FP64 steps where chi is high: the lanes take the item's samples in
-    // order of their chi scale (chi_order), so that wavefronts step alike
+    // FP32 passes: the lanes take the item's samples in order of their chi
+    // scale (chi_order), so that neighbouring lanes read nearby table cells;
+    // with FP64 steps the work items are groups of kChiGroup samples taken in
+    // rounds in that order, so that wavefronts step alike
     constexpr bool kOrder = PREC != PREC_F64 && QUANTUM && !NODES;
-    __shared__ float okey[kOrder ? kPhaseBlock : 1];
-    __shared__ unsigned short oidx[kOrder ? kPhaseBlock : 1];
+    constexpr bool kGroup = PREC == PREC_F32MIX && QUANTUM && !NODES;
+    constexpr int kOrderN = kGroup ? kChiGroup : kPhaseBlock;
+    __shared__ float okey[kOrder ? kOrderN : 1];
+    __shared__ unsigned short oidx[kOrder ? kOrderN : 1];
     if (kTab32) {
         const float4 *src = reinterpret_cast<const float4 *>(P.rad32);
         float4 *dst = reinterpret_cast<float4 *>(tab32);
@@ -269,31 +273,49 @@ __attribute__((amdgpu_waves_per_eu((PREC == PREC_F32 && QUANTUM) ? 4 : 1))) void
         __syncthreads();
     }
     double2 *wstage = stage + (kWave64 ? (threadIdx.x >> 6) * kStageChunks : 0);
+    // one sample (a lane that is not live runs the sample for the
+    // wavefront's table reads and stores nothing)
+    auto one = [&](const ShotParams &sp, int s, int64_t i, bool live) {
+        int flags = 0, nprom = 0;
+        phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(P, sp, i, env32, env64, tab32, wstage,
+                                                         live, flags, nprom);
+        if (flags) atomicOr(&P.flags[s], flags);
+        if (PREC == PREC_F32MIX && P.fp64_steps != nullptr) {
+            // FP64 wave-steps of the wavefronts that hold a sample of the shot
+            const bool count = __any(live);
+            if (count && nprom > 0 && (threadIdx.x & 63) == 0)
+                atomicAdd(&P.fp64_steps[s], (unsigned long long)nprom);
+        }
+    };
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
-        if (item >= P.n_items) break;
-        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
-        const ShotParams &sp = P.shots[s];
-        const int64_t base = (item - sp.item0) * kPhaseBlock;
-        int off = threadIdx.x;
-        if constexpr (kOrder) {
-            chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
-            off = oidx[threadIdx.x];
-        }
-        const int64_t i = base + off;
-        const bool live = i < sp.n_samples;
-        if (kWave64 || live) {
-            int flags = 0, nprom = 0;
-            phase_sample<PREC, QUANTUM, LOCAL, NODES, MODES>(
-                P, sp, live ? i : sp.n_samples - 1, env32, env64, tab32, wstage, live, flags,
-                nprom);
-            if (flags) atomicOr(&P.flags[s], flags);
-            if (PREC == PREC_F32MIX && P.fp64_steps != nullptr) {
-                // FP64 wave-steps of the wavefronts that hold a sample of the shot
-                const bool count = __any(live);
-                if (count && nprom > 0 && (threadIdx.x & 63) == 0)
-                    atomicAdd(&P.fp64_steps[s], (unsigned long long)nprom);
+        if constexpr (kGroup) {
+            if (item >= P.n_gitems) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_group_shot(P.shots, P.n_shots, item));
+            const ShotParams &sp = P.shots[s];
+            const int64_t base = (item - sp.gitem0) * kChiGroup;
+            const int cnt = (int)min((int64_t)kChiGroup, sp.n_samples - base);
+            chi_order<kChiGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
+            for (int r = 0; r * kPhaseBlock < cnt; ++r) {
+                const int rank = r * kPhaseBlock + (int)threadIdx.x;
+                if (r * kPhaseBlock + (int)(threadIdx.x & ~63u) >= cnt) continue;  // whole wavefront
+                const bool live = rank < cnt;
+                one(sp, s, base + oidx[live ? rank : cnt - 1], live);
             }
+        } else {
+            if (item >= P.n_items) break;
+            const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+            const ShotParams &sp = P.shots[s];
+            const int64_t base = (item - sp.item0) * kPhaseBlock;
+            int off = threadIdx.x;
+            if constexpr (kOrder) {
+                chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey,
+                                                    oidx);
+                off = oidx[threadIdx.x];
+            }
+            const int64_t i = base + off;
+            const bool live = i < sp.n_samples;
+            if (kWave64 || live) one(sp, s, live ? i : sp.n_samples - 1, live);
         }
     }
 }
@@ -787,8 +809,11 @@ hipError_t launch_phase(const BatchParams &p, const float *env32, const double *
                         int rr, int amp, hipStream_t s) {
     const void *fn = select_phase(prec, rr, amp, p.any_mode != 0);
     if (!fn) return hipErrorInvalidValue;
+    // FP64 steps: work items are groups of kChiGroup samples
+    const bool grouped = prec == PREC_F32MIX && rr == 1;
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, p.n_items, &grid, p.phase_cap);
+    hipError_t e =
+        resident_grid(fn, kPhaseBlock, 0, grouped ? p.n_gitems : p.n_items, &grid, p.phase_cap);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     const float *e32 = env32;
