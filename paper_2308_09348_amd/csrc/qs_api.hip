@@ -1375,11 +1375,20 @@ qs_status photons_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         const double mu_max = g0 + 6.5 * sg;
         const double mu_lo = std::max(g0 - 6.5 * sg, 1.01);
         const double mu_min = std::max(0.5 * mu_lo / (1.0 + bp.K * mu_lo * a0 * a0 * I2), 1.0);
+        // columns uniform in sqrt(mu), the energy range inside columns
+        // 1 .. nv - 2 (the outer two stay empty, so the contraction's
+        // deconvolution of the deposit needs no column beyond them); the
+        // lowest column at no less than half the range's lowest sqrt(mu)
         p.nv = qs::kPhNV;
-        p.v_lo = std::log(mu_min) - 0.01;
-        p.dv = (std::log(mu_max) + 0.01 - p.v_lo) / (p.nv - 1);
-        p.v_lof = (float)p.v_lo;
-        p.inv_dv = (float)(1.0 / p.dv);
+        const double t_min = std::sqrt(mu_min), t_max = std::sqrt(mu_max);
+        p.dt = (t_max - t_min) / (p.nv - 3);
+        p.t_lo = t_min - p.dt;
+        if (p.t_lo < 0.5 * t_min) {
+            p.t_lo = 0.5 * t_min;
+            p.dt = (t_max - p.t_lo) / (p.nv - 2);
+        }
+        p.t_lof = (float)p.t_lo;
+        p.inv_dt = (float)(1.0 / p.dt);
         // chi range: the largest chi possible above; below, stages whose
         // photons all fall in the lowest bin (y > 27 beyond 40 chi mu)
         const double width = (PB[k].ph_hi - PB[k].ph_lo) / PB[k].n_ph;

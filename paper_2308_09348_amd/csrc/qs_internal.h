@@ -149,7 +149,8 @@ constexpr double kPhYMax = 80.0;
 constexpr size_t kPhCellOff = (size_t)kPhRows * (kPhNZ + 1);  // in doubles
 constexpr size_t kPhTabBytes = sizeof(double) * kPhCellOff + sizeof(float) * 4 * kCells32;
 // Emission grid of one shot: at most kPhNU rows (ln chi, global rows
-// r_lo .. r_lo + nu - 1) x kPhNV columns (ln mu), weights in fixed point.
+// r_lo .. r_lo + nu - 1) x kPhNV columns (t = sqrt(mu), uniform), weights
+// in fixed point.
 constexpr int kPhNU = 64, kPhNV = 64, kPhNodes = kPhNU * kPhNV;
 constexpr int kPhotTile = 2048;          // one photon work item = kPhotTile samples
 // photon energy, electron loss, soft weight; then the Sec. 5.1 angular sums:
@@ -160,8 +161,8 @@ constexpr double kPhScale = 16777216.0;  // 2^24: unit of the grid weights
 
 struct ShotPhot {
     int32_t r_lo, nu, nv, n_ph;  // first global row, rows, columns, photon bins
-    double v_lo, dv;             // ln mu at column 0, column width
-    float v_lof, inv_dv;         // the same for the FP32 deposit: v_lo, 1 / dv
+    double t_lo, dt;             // sqrt(mu) at column 0, column width
+    float t_lof, inv_dt;         // the same for the FP32 deposit: t_lo, 1 / dt
     double ph_lo, ph_w;          // photon-energy bins [m c^2]
     double *hist;                // [n_ph + 2]
     double *energy;              // [2]: photon energy, electron energy loss

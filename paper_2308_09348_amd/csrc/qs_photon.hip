@@ -12,21 +12,44 @@ namespace qs {
 // Phi(e_k/mu; chi)] / chi to photon-energy bin k, Phi(xi; chi) = Int_0^xi F.
 // Evaluating Phi at every bin edge for every stage would cost the bin count
 // per stage, so each stage instead deposits its weight c (chi / mu) =
-// c 2|a| / a_S, bilinearly, into an emission grid over (ln chi, ln mu) kept
-// in LDS in fixed point (order-independent sums); a finalize kernel then
-// evaluates Phi / chi once per grid node and bin edge.  The grid spacing
-// (0.2 in ln chi, at most ~0.05 in ln mu for the shot's energy range) sets the
-// accuracy, about 1e-3 of the spectrum in L1.  Stages whose chi lies below
-// the grid emit photons below the first bin (the host sizes the grid so): they
-// add only their photon number, (5 pi / 2) chi (1 - 8 chi / (5 sqrt3)) per
-// unit C_ph c / mu, to the lowest bin.  The emitted photon energy itself,
-// c h (-A) summed over the stages (A: the drift), is accumulated exactly.
+// c 2|a| / a_S, bilinearly, into an emission grid over (u, t) = (ln chi,
+// sqrt(mu)) kept in LDS in fixed point (order-independent sums); a finalize
+// kernel then evaluates Phi / chi once per grid node and bin edge.
+//
+// Bilinear deposit followed by evaluation at the nodes is the bin content f
+// integrated against the emission density smoothed by a tent of one node
+// spacing in each direction: to second order, f + (du^2/12) f_uu + (dt^2/12)
+// f_tt.  The contraction removes that term by weighting the nodes with the
+// deposit convolved with [-1/12, 7/6, -1/12] along each axis (the inverse of
+// the tent's [1/12, 5/6, 1/12] node average to second order), leaving an
+// error of fourth order in the spacings.  The emission density in t is set
+// by the beam's energy spread near the initial energy, where t = sqrt(mu)
+// gives finer columns than ln mu over the same range.  The host keeps the
+// outer columns empty and the row above the largest chi; the row below the
+// grid's first is a table row too, so the convolution needs no node the
+// table lacks.
+//
+// Stages whose chi lies below the grid emit photons below the first bin (the
+// host sizes the grid so): they add only their photon number, (5 pi / 2) chi
+// (1 - 8 chi / (5 sqrt3)) per unit C_ph c / mu, to the lowest bin.  The
+// emitted photon energy itself, c h (-A) summed over the stages (A: the
+// drift), is accumulated exactly.
 // ===========================================================================
 __device__ __forceinline__ double ph_dz() { return cbrt(kPhYMax) / kPhNZ; }
 __device__ __forceinline__ float ph_ln(float x) {
     return __builtin_amdgcn_logf(x) * 0.69314718055994530942f;
 }
 __device__ __forceinline__ float ph_ln(double x) { return (float)log(x); }
+// Grid coordinates need a few 1e-7 relative: the hardware square root (1 ulp).
+__device__ __forceinline__ float ph_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// ln of the geometric mean of two stage energies from their product.  Like
+// the deposit below, evaluated without contracting a product into a later
+// sum, so that every instantiation of the photon step (FP64 pass, FP64
+// steps of the mixed pass) places a deposit at the same grid coordinates.
+__device__ __forceinline__ float ph_half_ln(float pm) {
+#pragma clang fp contract(off)
+    return 0.5f * ph_ln(pm);
+}
 
 // K_{2/3} and K_{1/3} at the 5 Gauss-Legendre nodes of every z interval.
 __constant__ double kGLx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0,
@@ -151,8 +174,8 @@ __global__ void ph_cdf_kernel(const double *phtab, int64_t n, const double *chi,
 }
 
 // Deposit of emission weight D (in units of 2 a0 / a_S per unit h) at
-// v = ln mu, u = ln chi = la + v (la = ln(2 |a| / a_S)), bilinear in (u, v);
-// below the grid only the photon number is kept.
+// u = ln chi = la + lm (la = ln(2 |a| / a_S), lm = ln mu) and t = sqrt(mu),
+// bilinear in (u, t); below the grid only the photon number is kept.
 struct PhotAcc {
     double e_ph, soft;
     int flags;
@@ -243,15 +266,16 @@ struct AngStep {
 // Weights in units of 2^-24 (kPhScale): D <= 2/3, so every node weight is
 // below 2^24 and its FP32 product is within half a unit of the exact one
 // before rounding to an integer; the grid words sum them in any order alike.
-__device__ __forceinline__ void ph_deposit(float D, float v, float la, float chi,
+__device__ __forceinline__ void ph_deposit(float D, float lm, float t, float la, float chi,
                                            const ShotPhot &sp, unsigned long long *grid,
                                            PhotAcc &acc) {
-    const float ru = (la + v - (float)(kPhU0 + sp.r_lo * kPhDu)) * (float)(1.0 / kPhDu);
+#pragma clang fp contract(off)
+    const float ru = (la + lm - (float)(kPhU0 + sp.r_lo * kPhDu)) * (float)(1.0 / kPhDu);
     if (ru < 0.0f) {  // below the grid: photon number only
         acc.soft += (double)D * (1.0 - 0.92376043070340122 * (double)chi);
         return;
     }
-    float fu = ru, fv = (v - sp.v_lof) * sp.inv_dv;
+    float fu = ru, fv = (t - sp.t_lof) * sp.inv_dt;
     if (!(fu <= (float)(sp.nu - 1)) || !(fv >= 0.0f) || !(fv <= (float)(sp.nv - 1))) {
         acc.flags |= kFlagRange;
         fu = fminf(fmaxf(fu, 0.0f), (float)(sp.nu - 1));
@@ -423,9 +447,9 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
     if (j > 0 && c.live) {
         const float aa = fabsf((float)a1);
         if (aa > 0.0f) {
-            const float v = 0.5f * ph_ln((float)st.m4_prev * (float)mu);
-            ph_deposit((float)c13 * aa * c.inv_a0, v, ph_ln(c.tas * aa), c.tas * (float)mu * aa,
-                       pp, grid, acc);
+            const float pm = (float)st.m4_prev * (float)mu;
+            ph_deposit((float)c13 * aa * c.inv_a0, ph_half_ln(pm), ph_sqrt(ph_sqrt(pm)),
+                       ph_ln(c.tas * aa), c.tas * (float)mu * aa, pp, grid, acc);
         }
     }
     T k1m, k1s, A1, k2m, k2s, A2, k3m, k3s, A3, k4m, k4s, A4;
@@ -464,9 +488,9 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
     if (c.live) {  // stages 2 and 3 (same amplitude)
         const float aa = fabsf((float)ah);
         if (aa > 0.0f) {
-            const float v = 0.5f * ph_ln((float)m2 * (float)m3);
-            ph_deposit(2.0f * (float)c13 * aa * c.inv_a0, v, ph_ln(c.tas * aa),
-                       c.tas * (float)m2 * aa, pp, grid, acc);
+            const float pm = (float)m2 * (float)m3;
+            ph_deposit(2.0f * (float)c13 * aa * c.inv_a0, ph_half_ln(pm), ph_sqrt(ph_sqrt(pm)),
+                       ph_ln(c.tas * aa), c.tas * (float)m2 * aa, pp, grid, acc);
         }
     }
     const T h6 = h * c16;
@@ -583,8 +607,8 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     if (c.live) {
         const float aa = fabsf((float)(st.aS_prev * c.env[0]));
         if (aa > 0.0f)
-            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.mu), ph_ln(c.tas * aa),
-                       c.tas * (float)st.mu * aa, pp, grid, acc);
+            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.mu), ph_sqrt((float)st.mu),
+                       ph_ln(c.tas * aa), c.tas * (float)st.mu * aa, pp, grid, acc);
     }
     double chd = 0.0;  // largest chi of the FP64 steps
     for (int j = 0; j < N;) {
@@ -651,7 +675,8 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
     {  // the last stage 4 deposits alone
         const float aa = fabsf((float)(st.aS_prev * c.env[2 * N]));
         if (aa > 0.0f)
-            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.m4_prev), ph_ln(c.tas * aa),
+            ph_deposit((1.0f / 6.0f) * aa * c.inv_a0, ph_ln((float)st.m4_prev),
+                       ph_sqrt((float)st.m4_prev), ph_ln(c.tas * aa),
                        c.tas * (float)st.m4_prev * aa, pp, grid, acc);
     }
     const double mu_f = ((double)st.mu + (double)st.mu_lo) + g0_rest;
@@ -789,8 +814,10 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
     const ShotPhot &pp = P.phot[s];
     __shared__ double tree[256];
     __shared__ double sums[kPhotPartials];
-    __shared__ double nzw[kPhNodes + 2];   // weights of the non-zero nodes, then S_k
-    __shared__ unsigned short nzi[kPhNodes];
+    // weights of the non-zero nodes (the grid and a row above and below),
+    // then S_k
+    __shared__ double nzw[kPhNodes + 2 * kPhNV + 2];
+    __shared__ unsigned short nzi[kPhNodes + 2 * kPhNV];
     __shared__ int cnt[257];
     const int tid = threadIdx.x;
     const int64_t ni = (sp.n_samples + kPhotTile - 1) / kPhotTile;
@@ -807,14 +834,37 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
         if (tid == 0) sums[m] = tree[0];
         __syncthreads();
     }
-    // compact the non-zero nodes in index order
-    const int nodes = pp.nu * pp.nv;
+    // node weights: the grid convolved with [-1/12, 7/6, -1/12] along each
+    // axis (the deposit's tent deconvolved to second order), over the grid's
+    // rows and the table rows just below and above it; columns beyond the
+    // grid's are left out (the host keeps its outer columns empty); the
+    // non-zero nodes compacted in index order
+    const int nv = pp.nv, nu = pp.nu;
+    const int nodes = (nu + 2) * nv;  // extended row e = grid row e - 1
     const unsigned long long *G = P.pgrid + pp.grid_off;
-    constexpr int kPer = kPhNodes / 256;
+    auto node_weight = [&](int k) -> double {
+        const int e = k / nv, m = k - e * nv;
+        const int r = pp.r_lo + e - 1;
+        if (r < 0 || r >= kPhRows) return 0.0;
+        double acc = 0.0;
+        for (int a = -1; a <= 1; ++a) {
+            const int n = e - 1 + a;
+            if (n < 0 || n >= nu) continue;
+            double row = 0.0;
+            for (int b = -1; b <= 1; ++b) {
+                const int mm = m + b;
+                if (mm < 0 || mm >= nv) continue;
+                row += (b == 0 ? 7.0 / 6.0 : -1.0 / 12.0) * (double)G[n * nv + mm];
+            }
+            acc += (a == 0 ? 7.0 / 6.0 : -1.0 / 12.0) * row;
+        }
+        return acc;
+    };
+    const int kPer = (nodes + 255) / 256;
     int mine = 0;
     for (int q = 0; q < kPer; ++q) {
         const int k = tid * kPer + q;
-        if (k < nodes && G[k]) ++mine;
+        if (k < nodes && node_weight(k) != 0.0) ++mine;
     }
     cnt[tid + 1] = mine;
     if (tid == 0) cnt[0] = 0;
@@ -825,9 +875,11 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
     int pos = cnt[tid];
     for (int q = 0; q < kPer; ++q) {
         const int k = tid * kPer + q;
-        if (k < nodes && G[k]) {
+        if (k >= nodes) break;
+        const double w = node_weight(k);
+        if (w != 0.0) {
             nzi[pos] = (unsigned short)k;
-            nzw[pos] = (double)G[k];
+            nzw[pos] = w;
             ++pos;
         }
     }
@@ -840,10 +892,11 @@ __global__ __launch_bounds__(256) void photon_finalize_kernel(BatchParams P, dou
     for (int q = 0; q < kPhMaxEdgesPerThread; ++q) S[q] = 0.0;
     for (int z = 0; z < nnz; ++z) {
         const int k = nzi[z];
-        const int n = k / pp.nv, m = k - n * pp.nv;
-        const int r = pp.r_lo + n;
+        const int e = k / nv, m = k - e * nv;
+        const int r = pp.r_lo + e - 1;
         const double chi = exp(kPhU0 + r * kPhDu);
-        const double inv_mu = exp(-(pp.v_lo + m * pp.dv));
+        const double t = pp.t_lo + m * pp.dt;
+        const double inv_mu = 1.0 / (t * t);
         const double w = nzw[z];
         for (int q = 0; q < kPhMaxEdgesPerThread; ++q) {
             const int e = tid + 256 * q;
