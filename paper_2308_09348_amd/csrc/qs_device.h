@@ -751,24 +751,82 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 
 // The laws of the 64 lanes of a wavefront, deposited together.  A law spans
 // anywhere from one bin to the whole window, so one lane per law would leave
-// most lanes idle behind the widest: instead the edges of all 64 laws are laid
-// end to end (law s takes edges ka - 1 .. kb, the first only to supply the
-// lower box end of edge ka) and the lanes take 64 consecutive positions at a
-// time; a lane finds its law from the marked starts of the block through a
-// prefix maximum, and reads the law from the wavefront's LDS rows.
+// most lanes idle behind the widest: instead the work of all 64 laws is laid
+// end to end and the lanes take 64 consecutive pieces at a time; a lane finds
+// its law from the marked starts of the block through a prefix maximum, and
+// reads the law from the wavefront's LDS rows.  Two passes:
+//  - positions (the box, the narrow box (x) Gaussian, Gaussians whose edges
+//    lie more than a quarter standard deviation apart): one piece per edge,
+//    law s taking edges ka - 1 .. kb (the first only to supply the lower box
+//    end of edge ka), each edge's CDF evaluated on its own;
+//  - runs (the wide box (x) Gaussian series and Gaussians with edges at most a
+//    quarter standard deviation apart): one piece per run of up to kRunLen
+//    consecutive edges on one side of the law's centre, starting at the run's
+//    edge farthest from the centre.  The tail there is evaluated as in the
+//    position pass; towards the centre the run adds the integral of the
+//    Gaussian density phi over each edge interval by Boole's rule on four
+//    subintervals of h = dz / 4 (dz: edge spacing in standard deviations, at
+//    most 1/4), phi following the lattice by phi(a - h) = phi(a) e^(a h - h^2/2)
+//    (the exponential once an edge, then multiplied by e^(-h^2) down the
+//    subintervals).  Boole's rule errs by 8/945 h^7 phi^(6), below 1e-5 of an
+//    interval's mass out to 6.4 standard deviations (its sixth derivative is
+//    He6(a) phi), and the recurrence by a few ulps an edge: a few 1e-6 of the
+//    tail at most, against the 1e-4 a bin of the spectrum may err.
 // Q[e] (u64) accumulates the quantised weight at or below edge e of the laws
 // that cover e; cnt[c] (u32) counts the samples whose weight is all at or
 // below edge c - 1 (a point in bin c - 1, or a law ending at edge c - 1), so
 // that edge e carries Q[e] + 2^32 sum_(c <= e) cnt[c] in total.
 //
-// Per-wavefront LDS rows of wave_deposit: the 64 laws (kind | ka << 2, t0,
-// sf, inv_s), their position offsets, and the start marks of a block of 64
-// positions (-1 between uses; set to -1 once before the first use).
+// Per-wavefront LDS rows of wave_deposit: the 64 laws (kind | ka << 3, t0,
+// sf, inv_s), their run shape (edges, edges below the centre), the piece
+// offsets, and the start marks of a block of 64 pieces (-1 between uses; set
+// to -1 once before the first use).
 struct WaveLaws {
     int4 *rec;
+    int2 *ext;
     int *off;
     int *mark;
 };
+
+constexpr int kRunLen = 8;  // edges a run
+
+// Owner of piece p of a block (base .. base + 63): the last lane whose first
+// piece is <= p.  Lanes with pieces mark their start if it falls in the block
+// (starts are distinct); a prefix maximum carries each start to the pieces
+// after it, the previous block's last owner (carry) to those before the first.
+__device__ __forceinline__ int piece_owner(bool has, int off, int base, int carry,
+                                           const WaveLaws &WL) {
+    const int lane = threadIdx.x & 63;
+    if (has && off >= base && off < base + 64) WL.mark[off - base] = lane;
+    wave_sync_lds();
+    const int m = WL.mark[lane];
+    WL.mark[lane] = -1;
+    return max(wave_incl_max(m), carry);
+}
+
+// Exclusive scan of n over the wavefront; *total receives the sum.
+__device__ __forceinline__ int wave_excl_scan(int n, int *total) {
+    const int lane = threadIdx.x & 63;
+    int incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    *total = __builtin_amdgcn_readlane(incl, 63);
+    return incl - n;
+}
+
+// Quantised weight of a CDF value at edge e (F: the tail mass on the side of
+// the edge away from the law's centre), added to Q[e].
+__device__ __forceinline__ void add_edge(unsigned long long *Q, int e, float F, bool upper) {
+    F = fminf(fmaxf(F, 0.0f), 1.0f);
+    // below 1, 2^32 F rounds to at most 2^32 - 256: 32 bits
+    const unsigned long long qf =
+        F >= 1.0f ? kOne : (unsigned long long)(uint32_t)rintf(F * 4294967296.0f);
+    const unsigned long long q = upper ? kOne - qf : qf;
+    if (q) atomicAdd(&Q[e], q);
+}
 
 __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
                                              unsigned long long *Q, unsigned int *cnt,
@@ -776,32 +834,31 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
     const int lane = threadIdx.x & 63;
     if (L.kind == 0) atomicAdd(&cnt[L.ngp], 1u);
     if (L.kind > 0) atomicAdd(&cnt[L.kb + 1], 1u);
-    const int np = L.kind > 0 ? L.kb - L.ka + 2 : 0;
-    int incl = np;  // inclusive scan of the position counts over the lanes
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
+    const float wf = (float)w, inv_w = (float)(1.0 / w);
+    // runs: the wide box (x) Gaussian, and Gaussians with dz <= 1/4
+    const bool run = L.kind == 4 || (L.kind == 2 && wf * L.inv_s <= 0.25f);
+    const int ne = L.kind > 0 ? L.kb - L.ka + 1 : 0;  // edges of the law
+    // edges at or below the centre (t <= 0, as the position pass decides it)
+    int nl = 0;
+    if (run) {
+        nl = min(max((int)floorf(-L.t0 * inv_w) + 1, 0), ne);
+        if (nl > 0 && fmaf((float)(nl - 1), wf, L.t0) > 0.0f) --nl;
+        if (nl < ne && fmaf((float)nl, wf, L.t0) <= 0.0f) ++nl;
     }
-    const int off = incl - np;
-    const int total = __builtin_amdgcn_readlane(incl, 63);
     WL.rec[lane] = make_int4(L.kind | (L.ka << 3), __float_as_int(L.t0), __float_as_int(L.sf),
                              __float_as_int(L.inv_s));
+    WL.ext[lane] = make_int2(ne, nl);
+
+    // ---- position pass ----
+    const int np = L.kind > 0 && !run ? ne + 1 : 0;
+    int total;
+    int off = wave_excl_scan(np, &total);
     WL.off[lane] = off;
-    const float wf = (float)w, inv_w = (float)(1.0 / w);
     float cP = 0.0f, cPc = 0.0f;  // box ends of the previous block's last position
     int carry = 0;                // owner of the previous block's last position
     for (int base = 0; base < total; base += 64) {
         const int p = base + lane;
-        // owner of position p: the last lane whose offset is <= p.  Lanes
-        // with positions mark their start if it falls in this block (starts
-        // are distinct); a prefix maximum carries each start to the positions
-        // after it, the previous block's last owner to those before the first
-        if (np > 0 && off >= base && off < base + 64) WL.mark[off - base] = lane;
-        wave_sync_lds();
-        const int m = WL.mark[lane];
-        WL.mark[lane] = -1;
-        const int own = max(wave_incl_max(m), carry);
+        const int own = piece_owner(np > 0, off, base, carry, WL);
         carry = __builtin_amdgcn_readlane(own, 63);
         const int4 r = WL.rec[own];
         const int kind = r.x & 7, ka = r.x >> 3;
@@ -813,34 +870,25 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         const float t = fmaf((float)rel, wf, t0);
         const bool upper = t > 0.0f;
         // One Gaussian tail a position, without branches (one exponential
-        // serves phi and the tail): at the edge for the Gaussian law and the
-        // wide box (x) Gaussian (the series), at the upper box end x = t + b/2
-        // for the narrower box (x) Gaussian, whose CDF is a difference of
-        // Psi(x) = x Phi(x/s) + s phi(x/s) at the two box ends; Psi(x) and
-        // Psi(x) - x = -x Phi(-x/s) + s phi(x/s) are formed from the tail on
-        // the side of x (no cancellation) and consecutive edges share one end.
-        // All positions of a law are alike, so the box ends passed between
-        // lanes are those of narrow laws only.
+        // serves phi and the tail): at the edge for the Gaussian law, at the
+        // upper box end x = t + b/2 for the narrow box (x) Gaussian, whose CDF
+        // is a difference of Psi(x) = x Phi(x/s) + s phi(x/s) at the two box
+        // ends; Psi(x) and Psi(x) - x = -x Phi(-x/s) + s phi(x/s) are formed
+        // from the tail on the side of x (no cancellation) and consecutive
+        // edges share one end.  All positions of a law are alike, so the box
+        // ends passed between lanes are those of narrow laws only.
         const float x = kind == 3 ? t + hf : t;
         const float zz = x * inv_s;
         const float e2 = __expf(-0.5f * zz * zz);  // relative error below 2e-6 out to 6 sigma
         const float phz = 0.39894228040143267794f * e2;
         const float tail = 0.5f * erfc_pos(fabsf(zz) * 0.70710678118654752440f, e2);
-        float P = 0.0f, Pc = 0.0f, Fw = 0.0f;
+        float P = 0.0f, Pc = 0.0f;
         if (__any(kind == 3)) {
             const float ph = sf * phz;
             const float lo = fmaf(x, tail, ph);   // Psi(x) when x <= 0
             const float hi = fmaf(-x, tail, ph);  // Psi(x) - x when x > 0
             P = zz <= 0.0f ? lo : hi + x;
             Pc = zz <= 0.0f ? lo - x : hi;
-        }
-        if (__any(kind == 4)) {
-            // tail + a phi(a) (beta^2/24 + beta^4/1920 (a^2 - 3)), a = |z|
-            // (sf holds beta^2): both even-order terms have the sign of the
-            // tail mass on either side
-            const float a = fabsf(zz);
-            const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
-            Fw = fmaf(a * phz, c, tail);
         }
         float lP = __shfl_up(P, 1, 64), lPc = __shfl_up(Pc, 1, 64);
         if (lane == 0) {
@@ -852,13 +900,67 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         if (live) {
             const float Fbox = upper ? 0.5f - t * inv_w : fmaf(t, inv_w, 0.5f);
             const float Fpsi = upper ? (lPc - Pc) * inv_w : (P - lP) * inv_w;
-            float F = kind == 4 ? Fw : (kind == 3 ? Fpsi : (kind == 2 ? tail : Fbox));
-            F = fminf(fmaxf(F, 0.0f), 1.0f);
-            // below 1, 2^32 F rounds to at most 2^32 - 256: 32 bits
-            const unsigned long long qf =
-                F >= 1.0f ? kOne : (unsigned long long)(uint32_t)rintf(F * 4294967296.0f);
-            const unsigned long long q = upper ? kOne - qf : qf;
-            if (q) atomicAdd(&Q[ka + rel], q);
+            const float F = kind == 3 ? Fpsi : (kind == 2 ? tail : Fbox);
+            add_edge(Q, ka + rel, F, upper);
+        }
+    }
+    wave_sync_lds();  // the offsets are rewritten below
+
+    // ---- run pass ----
+    const int rl = run ? (nl + kRunLen - 1) / kRunLen : 0;
+    const int nr = run ? rl + (ne - nl + kRunLen - 1) / kRunLen : 0;
+    off = wave_excl_scan(nr, &total);
+    WL.off[lane] = off;
+    carry = 0;
+    for (int base = 0; base < total; base += 64) {
+        const int p = base + lane;
+        const int own = piece_owner(nr > 0, off, base, carry, WL);
+        carry = __builtin_amdgcn_readlane(own, 63);
+        const int4 r = WL.rec[own];
+        const int2 x2 = WL.ext[own];
+        const int j = p - WL.off[own];  // run of the law
+        wave_sync_lds();
+        const int kind = r.x & 7, ka = r.x >> 3;
+        const float t0 = __int_as_float(r.y), sf = __int_as_float(r.z);
+        const float inv_s = __int_as_float(r.w);
+        const int n_e = x2.x, n_l = x2.y, r_l = (n_l + kRunLen - 1) / kRunLen;
+        const bool upper = j >= r_l;
+        // first edge (farthest from the centre) and length of the run
+        const int rel0 = upper ? n_e - 1 - (j - r_l) * kRunLen : j * kRunLen;
+        const int len = p < total ? (upper ? min(kRunLen, n_e - n_l - (j - r_l) * kRunLen)
+                                           : min(kRunLen, n_l - j * kRunLen))
+                                  : 0;
+        const int step = upper ? -1 : 1;
+        const float hs = 0.25f * wf * inv_s;  // Boole subinterval (a quarter edge)
+        const float q = __expf(-hs * hs);
+        const float cb = hs * (2.0f / 45.0f);
+        // the tail at the run's first edge
+        float a = fabsf(fmaf((float)rel0, wf, t0) * inv_s);
+        const float e2 = __expf(-0.5f * a * a);
+        float ph = 0.39894228040143267794f * e2;
+        float T = 0.5f * erfc_pos(a * 0.70710678118654752440f, e2);
+        for (int k = 0; k < kRunLen; ++k) {
+            if (k < len) {
+                if (k > 0) {
+                    // from the previous edge (a) one edge towards the centre
+                    float rho = __expf(fmaf(a, hs, -0.5f * hs * hs));
+                    const float p1 = ph * rho;
+                    rho *= q;
+                    const float p2 = p1 * rho;
+                    rho *= q;
+                    const float p3 = p2 * rho;
+                    rho *= q;
+                    const float p4 = p3 * rho;
+                    T = fmaf(cb, fmaf(7.0f, ph + p4, fmaf(32.0f, p1 + p3, 12.0f * p2)), T);
+                    ph = p4;
+                    a = fabsf(fmaf((float)(rel0 + step * k), wf, t0) * inv_s);
+                }
+                // wide box (x) Gaussian: the series' even terms beside the tail
+                // (sf holds beta^2), with the sign of the tail on either side
+                const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
+                const float F = kind == 4 ? fmaf(a * ph, c, T) : T;
+                add_edge(Q, ka + rel0 + step * k, F, upper);
+            }
         }
     }
     wave_sync_lds();  // the next call rewrites the rows

@@ -471,9 +471,10 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     __shared__ double redsh[kDepBlock / 64][2];
     __shared__ unsigned int wsum[kDepBlock / 64];
     __shared__ int4 wrec[kDepBlock];
+    __shared__ int2 wext[kDepBlock];
     __shared__ int woff[kDepBlock], wmark[kDepBlock];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const WaveLaws WL{wrec + 64 * wid, woff + 64 * wid, wmark + 64 * wid};
+    const WaveLaws WL{wrec + 64 * wid, wext + 64 * wid, woff + 64 * wid, wmark + 64 * wid};
     WL.mark[lane] = -1;
     for (;;) {
         const int64_t item = next_item(&P.queue[1], &slot);
