@@ -38,6 +38,8 @@ struct GraphEntry {
 constexpr size_t kMaxGraphs = 8;
 }  // namespace
 
+constexpr int kStageSlots = 4;  // pinned staging blocks of the shot tables
+
 struct qs_ctx {
     int device = -1;
     float *rad32 = nullptr;
@@ -57,13 +59,17 @@ struct qs_ctx {
     size_t shadow_cap = 0;
     unsigned char *states = nullptr;  // per-sample final states (SampleState arrays)
     size_t states_cap = 0;
-    // per-shot tables: pinned staging on the host, a device copy
-    unsigned char *stage = nullptr;
-    size_t stage_cap = 0;
+    // per-shot tables: pinned staging on the host, a device copy.  Calls
+    // take the staging blocks in turn, so the host can stage a call while
+    // the copies of the kStageSlots - 1 calls before it still wait on the
+    // stream; a block is reused once its own copy has run.
+    unsigned char *stage[kStageSlots] = {};
+    size_t stage_cap[kStageSlots] = {};
+    hipEvent_t stage_done[kStageSlots] = {};  // the last copy out of each block
+    bool stage_pending[kStageSlots] = {};
+    int stage_next = 0;
     unsigned char *shot_tab = nullptr;
     size_t shot_tab_cap = 0;
-    hipEvent_t stage_done = nullptr;  // the last copy out of the staging buffer
-    bool stage_pending = false;
     int *eval_flags = nullptr;
     // kernel timing
     bool profiling = false;
@@ -325,17 +331,19 @@ qs_status grow(qs_ctx *c, T **p, size_t *cap, size_t n, const char *what) {
     return QS_OK;
 }
 
-qs_status grow_pinned(qs_ctx *c, size_t n) {
-    if (c->stage_cap >= n) return QS_OK;
-    if (c->stage) {
-        if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
-        (void)hipHostFree(c->stage);
+qs_status grow_pinned(qs_ctx *c, int slot, size_t n) {
+    if (c->stage_cap[slot] >= n) return QS_OK;
+    if (c->stage[slot]) {
+        if (c->stage_pending[slot]) (void)hipEventSynchronize(c->stage_done[slot]);
+        c->stage_pending[slot] = false;
+        (void)hipHostFree(c->stage[slot]);
     }
-    c->stage = nullptr;
-    c->stage_cap = 0;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->stage), n, hipHostMallocDefault);
+    c->stage[slot] = nullptr;
+    c->stage_cap[slot] = 0;
+    hipError_t e =
+        hipHostMalloc(reinterpret_cast<void **>(&c->stage[slot]), n, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(c, e, "pinned staging");
-    c->stage_cap = n;
+    c->stage_cap[slot] = n;
     return QS_OK;
 }
 
@@ -462,8 +470,10 @@ void qs_destroy(qs_ctx *c) {
         (void)hipFree(c->shadow);
         (void)hipFree(c->states);
         (void)hipFree(c->shot_tab);
-        if (c->stage) (void)hipHostFree(c->stage);
-        if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+        for (int k = 0; k < kStageSlots; ++k) {
+            if (c->stage[k]) (void)hipHostFree(c->stage[k]);
+            if (c->stage_done[k]) (void)hipEventDestroy(c->stage_done[k]);
+        }
         if (c->na_stage) (void)hipHostFree(c->na_stage);
         if (c->na_done) (void)hipEventDestroy(c->na_done);
         (void)hipFree(c->eval_flags);
@@ -729,6 +739,7 @@ struct Batch {
     int64_t hist_words = 0;
     size_t tab_bytes = 0;
     unsigned char *stage = nullptr;  // pinned staging buffer of the shot table
+    int slot = 0;                    // its block in the context's ring
     qs::ShotParams *sp = nullptr;  // in the staging buffer
     unsigned char *outs = nullptr;  // in the staging buffer, after the ShotParams
 };
@@ -834,13 +845,16 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         }
         stage = c->na_stage;
     } else {
-        if (c->stage_pending) {
-            hipError_t e = hipEventSynchronize(c->stage_done);  // previous copy out of staging
+        const int slot = c->stage_next;
+        if (c->stage_pending[slot]) {
+            // the copy out of this block, kStageSlots calls ago
+            hipError_t e = hipEventSynchronize(c->stage_done[slot]);
             if (e != hipSuccess) return hip_fail(c, e, "staging event");
-            c->stage_pending = false;
+            c->stage_pending[slot] = false;
         }
-        if ((st = grow_pinned(c, b.tab_bytes)) != QS_OK) return st;
-        stage = c->stage;
+        if ((st = grow_pinned(c, slot, b.tab_bytes)) != QS_OK) return st;
+        stage = c->stage[slot];
+        b.slot = slot;
     }
     b.stage = stage;
     b.sp = reinterpret_cast<qs::ShotParams *>(stage);
@@ -872,7 +886,12 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         p.plane_wave = plane_wave ? 1 : 0;
         {
             // the quadratic midpoint of the spatial factor is used only when one
-            // phase step moves a sample much less than the focal scales
+            // phase step moves a sample much less than the focal scales: its
+            // error is S''' d^3 / 16 for a step of length d, and the third
+            // derivative of the Gaussian focus's factor along the axis is at
+            // most about 135 / zR^3 of its peak, so below 3e-3 of the scale the
+            // midpoint amplitude is within 2.3e-7 of the peak (about four FP32
+            // roundings of it, a few 1e-7 of the energy loss at most)
             const double step_um = b.h * bp.ell_per_psi;
             // (a mode of order k varies on W0 / sqrt(1 + k))
             const int order = l.mode == QS_MODE_HG   ? std::max(l.mode_m, l.mode_n)
@@ -881,7 +900,7 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
             const double scale = plane_wave ? 0.0
                                             : std::fmax(p.inv_zR, 6.0 * p.div_rad / l.w0_um) *
                                                   std::sqrt(1.0 + order);
-            p.mid_interp = step_um * scale < 1e-3 ? 1 : 0;
+            p.mid_interp = step_um * scale < 3e-3 ? 1 : 0;
         }
         p.mode = plane_wave ? QS_MODE_GAUSS : l.mode;
         p.mode_m = l.mode_m;
@@ -923,14 +942,17 @@ qs_status prepare_batch(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
 
 // Copy the staged shot table to the device and record the staging event.
 qs_status upload_batch(qs_ctx *c, const Batch &b, hipStream_t s) {
-    if (!c->stage_done) {
-        hipError_t e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+    const int slot = b.slot;
+    if (!c->stage_done[slot]) {
+        hipError_t e = hipEventCreateWithFlags(&c->stage_done[slot], hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(c, e, "event create");
     }
-    hipError_t e = hipMemcpyAsync(c->shot_tab, c->stage, b.tab_bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(c->shot_tab, b.stage, b.tab_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "shot table copy");
-    if ((e = hipEventRecord(c->stage_done, s)) != hipSuccess) return hip_fail(c, e, "event record");
-    c->stage_pending = true;
+    if ((e = hipEventRecord(c->stage_done[slot], s)) != hipSuccess)
+        return hip_fail(c, e, "event record");
+    c->stage_pending[slot] = true;
+    c->stage_next = (slot + 1) % kStageSlots;
     return QS_OK;
 }
 
