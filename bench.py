@@ -373,6 +373,9 @@ def quantum_batch_leg(ctx, workloads, torch, steps, tune_cache=None):
             "sample_steps_per_s": total * N / dt, "spectra_per_s": len(shots) / dt,
             "fp64_step_share": share,
             "forward_ms": 1e3 * fwd_s,
+            # the batched forward pass with its adjoint (the tape-recording
+            # forward and the adjoint from the tape) over the plain batched forward
+            "fwd_adjoint_over_fwd": (parts["tape_forward"] + parts["adjoint"]) / steps / fwd_s,
             "roofline": {"bound": "alu", "kernel": "phase_kernel (FP32 with FP64 steps)",
                          "kernel_avg_ms": phase_ms, "achieved": achieved, "peak": peak,
                          "unit": "TFLOP/s", "frac": achieved / peak,
