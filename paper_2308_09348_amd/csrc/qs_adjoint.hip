@@ -519,6 +519,30 @@ __device__ void law_sensitivity(double v, double s2, int dep, double ksig, doubl
     const int jb = (int)fmin(fmax(floor((v + reach - lo) / wb), -1.0), (double)n);
     const double inv_se = mode >= 2 ? 1.0 / se : 0.0;
     double sv = 0.0, ss = 0.0;
+    if (mode == 2) {
+        // the Gaussian density along the edges by multiplications:
+        // phi(z + dz) = phi(z) r, r = exp(-z dz - dz^2 / 2), and r itself
+        // advances by exp(-dz^2) (exact in the arithmetic; FP64 rounding adds
+        // an ulp or two an edge)
+        const double dz = wb * inv_se;
+        const double q = exp(-dz * dz);
+        double z = (fma((double)ja, wb, lo) - v) * inv_se;
+        double f = phi_pdf(z) * inv_se;
+        double r = exp(fma(-z, dz, -0.5 * dz * dz));
+        for (int j = ja; j <= jb; ++j) {
+            const double wl = j == 0 ? W[n] : W[j - 1];
+            const double wr = j == n ? W[n + 1] : W[j];
+            const double c = wl - wr;
+            sv = fma(c, f, sv);
+            ss = fma(c, -z * f, ss);
+            f *= r;
+            r *= q;
+            z += dz;
+        }
+        lv = -sv;
+        ls2 = ss * dse;
+        return;
+    }
     for (int j = ja; j <= jb; ++j) {
         const double wl = j == 0 ? W[n] : W[j - 1];
         const double wr = j == n ? W[n + 1] : W[j];
