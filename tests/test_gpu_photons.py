@@ -214,12 +214,13 @@ def test_mixed_photons_batched_equals_single(gpu):
             assert np.array_equal(batch[k][key], single[key]), (k, key)
 
 
-@pytest.mark.parametrize("k", [0, 255])
+@pytest.mark.parametrize("k", [0, 37, 51, 255])
 def test_photon_spectrum_of_quantum_batch_shots(gpu, oracle, k):
     """Shots of the quantum batch at their own numerics -- 2048 steps, 256
     photon bins, FP64 steps where chi > 0.1 -- on a 512-sample prefix (the
     counter-based draw makes a prefix the same samples as in the full shot),
-    against the oracle at the spectrum bar."""
+    against the oracle at the spectrum bar; shots 51 and 37 carry the batch's
+    smallest and largest a0 (50.6 and 149.9)."""
     p = dict(workloads.quantum_batch()[k], n_samples=512)
     assert p["n_steps"] == 2048 and p["n_ph"] == 256 and p["chi_fp64"] == 0.1
     print(f"photons: quantum batch shot {k}, 512 samples", flush=True)
@@ -228,3 +229,25 @@ def test_photon_spectrum_of_quantum_batch_shots(gpu, oracle, k):
     _check(g, o, p, 2e-5, f"quantum-batch-{k}")
     oa = oracle.photon_angles(p)
     assert np.all(np.abs(g["angles"] - oa) <= 2e-5 * np.abs(oa)), (g["angles"], oa)
+
+
+@pytest.mark.parametrize("k", [0, 37, 51, 255])
+def test_photon_number_of_full_quantum_batch_shots(gpu, k):
+    """Whole shots of the quantum batch (2^18 samples x 2048 steps, FP64 steps
+    where chi > 0.1), where the oracle cannot follow every stage: the
+    spectrum's photon number (every bin with the under- and overflow: the
+    emission grid, its contraction and the soft stages below it) against the
+    photon number summed stage by stage along the same trajectories (the
+    number weight of the angular moments, Phi(1; chi)/chi at each stage), a
+    relation that holds at any size.  The grid's deconvolution keeps a column
+    sum, and Phi(1; chi)/chi is smooth in ln chi, so the two agree far inside
+    the FP32 bar of the number (2e-5); the status is clean."""
+    p = workloads.quantum_batch()[k]
+    assert p["n_samples"] == 1 << 18 and p["n_steps"] == 2048
+    print(f"photons: quantum batch shot {k}, full size", flush=True)
+    g = _np(gpu.photons(p, angles=True))
+    n_spec = g["photon_hist"].sum()
+    n_stage = g["angles"][0]
+    print("photon number: spectrum", n_spec, "stages", n_stage, "rel", n_spec / n_stage - 1)
+    assert int(g["status"][0]) == 0
+    assert n_stage > 0 and abs(n_spec - n_stage) <= 2e-5 * n_stage
