@@ -767,11 +767,15 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 //    Gaussian density phi over each edge interval by Boole's rule on four
 //    subintervals of h = dz / 4 (dz: edge spacing in standard deviations, at
 //    most 1/4), phi following the lattice by phi(a - h) = phi(a) e^(a h - h^2/2)
-//    (the exponential once an edge, then multiplied by e^(-h^2) down the
-//    subintervals).  Boole's rule errs by 8/945 h^7 phi^(6), below 1e-5 of an
-//    interval's mass out to 6.4 standard deviations (its sixth derivative is
-//    He6(a) phi), and the recurrence by a few ulps an edge: a few 1e-6 of the
-//    tail at most, against the 1e-4 a bin of the spectrum may err.
+//    (one exponential a run: the ratio itself shrinks by e^(-h^2) from one
+//    subinterval to the next and by e^(-4 h^2) from one edge to the next).
+//    Boole's rule errs by 8/945 h^7 phi^(6), below 1e-5 of an interval's mass
+//    out to 6.4 standard deviations (its sixth derivative is He6(a) phi), and
+//    the products' roundings grow with the square of the edges walked: over
+//    a run an interval's mass carries at most about 1e-5 relative error in
+//    all (an FP32 emulation of nine-edge runs with dz in [0.02, 0.25] starting
+//    out to 6.2 standard deviations finds 1.0e-5), against the 1e-4 a bin may
+//    err.
 // Q[e] (u64) accumulates the quantised weight at or below edge e of the laws
 // that cover e; cnt[c] (u32) counts the samples whose weight is all at or
 // below edge c - 1 (a point in bin c - 1, or a law ending at edge c - 1), so
@@ -788,7 +792,11 @@ struct WaveLaws {
     int *mark;
 };
 
-constexpr int kRunLen = 8;  // edges a run
+// Edges a run.  Consecutive lanes of one law walk runs whose edges lie kRunLen
+// words of 8 bytes apart: with eight, every second lane's atomic falls on the
+// same 4-byte LDS bank (16 banks on); with nine they spread over the banks
+// (the deposit's bank-conflict cycles drop by three quarters).
+constexpr int kRunLen = 9;
 
 // Owner of piece p of a block (base .. base + 63): the last lane whose first
 // piece is <= p.  Lanes with pieces mark their start if it falls in the block
@@ -826,6 +834,16 @@ __device__ __forceinline__ void add_edge(unsigned long long *Q, int e, float F, 
         F >= 1.0f ? kOne : (unsigned long long)(uint32_t)rintf(F * 4294967296.0f);
     const unsigned long long q = upper ? kOne - qf : qf;
     if (q) atomicAdd(&Q[e], q);
+}
+
+// The same for an edge of a run, whose tail mass F is at most about one half:
+// 2^32 F fits 32 bits, and the weight on the upper side, 2^32 - 2^32 F, has
+// its high word set only when 2^32 F rounds to zero.
+__device__ __forceinline__ void add_run_edge(unsigned long long *Qe, float F, bool upper) {
+    const uint32_t qf = (uint32_t)rintf(fminf(fmaxf(F, 0.0f), 0x1.fffffep-1f) * 4294967296.0f);
+    const uint32_t lo = upper ? 0u - qf : qf;
+    const uint32_t hi = upper && qf == 0u ? 1u : 0u;
+    atomicAdd(Qe, ((unsigned long long)hi << 32) | lo);
 }
 
 __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
@@ -931,35 +949,41 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
                                            : min(kRunLen, n_l - j * kRunLen))
                                   : 0;
         const int step = upper ? -1 : 1;
-        const float hs = 0.25f * wf * inv_s;  // Boole subinterval (a quarter edge)
-        const float q = __expf(-hs * hs);
+        const float da = wf * inv_s;    // edge spacing in standard deviations
+        const float hs = 0.25f * da;    // Boole subinterval (a quarter edge)
+        const float q = __expf(-hs * hs), q4 = __expf(-4.0f * hs * hs);
         const float cb = hs * (2.0f / 45.0f);
         // the tail at the run's first edge
         float a = fabsf(fmaf((float)rel0, wf, t0) * inv_s);
         const float e2 = __expf(-0.5f * a * a);
         float ph = 0.39894228040143267794f * e2;
         float T = 0.5f * erfc_pos(a * 0.70710678118654752440f, e2);
+        // phi(a - hs) / phi(a) at the current edge a; the ratio of the next
+        // subinterval is e^(-hs^2) times this one's, of the next edge e^(-4 hs^2)
+        float rho = __expf(fmaf(a, hs, -0.5f * hs * hs));
+        unsigned long long *qe = Q + (ka + rel0);
         for (int k = 0; k < kRunLen; ++k) {
             if (k < len) {
                 if (k > 0) {
                     // from the previous edge (a) one edge towards the centre
-                    float rho = __expf(fmaf(a, hs, -0.5f * hs * hs));
-                    const float p1 = ph * rho;
-                    rho *= q;
-                    const float p2 = p1 * rho;
-                    rho *= q;
-                    const float p3 = p2 * rho;
-                    rho *= q;
-                    const float p4 = p3 * rho;
+                    float r = rho;
+                    const float p1 = ph * r;
+                    r *= q;
+                    const float p2 = p1 * r;
+                    r *= q;
+                    const float p3 = p2 * r;
+                    r *= q;
+                    const float p4 = p3 * r;
+                    rho *= q4;
                     T = fmaf(cb, fmaf(7.0f, ph + p4, fmaf(32.0f, p1 + p3, 12.0f * p2)), T);
                     ph = p4;
-                    a = fabsf(fmaf((float)(rel0 + step * k), wf, t0) * inv_s);
+                    a -= da;
                 }
                 // wide box (x) Gaussian: the series' even terms beside the tail
                 // (sf holds beta^2), with the sign of the tail on either side
                 const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
                 const float F = kind == 4 ? fmaf(a * ph, c, T) : T;
-                add_edge(Q, ka + rel0 + step * k, F, upper);
+                add_run_edge(qe + step * k, F, upper);
             }
         }
     }
