@@ -259,11 +259,19 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
         return (time.perf_counter() - t0) / steps
 
     res = {}
-    dt = timed(lambda: res.update(zip(("loss", "g", "w"), step())))
+    fwd = lambda: ctx.forward(p, out=out, check=False)
+    # the step and the plain forward pass timed in alternating rounds, so that
+    # both see the same clock state of the device (kernel durations drift by
+    # several percent over a few seconds of load)
+    fn_step = lambda: res.update(zip(("loss", "g", "w"), step()))
+    dts, fwds = [], []
+    for _ in range(4):
+        dts.append(timed(fn_step))
+        fwds.append(timed(fwd))
+    dt, t_fwd = float(np.mean(dts)), float(np.mean(fwds))
     if int(out["status"].item()) != 0:
         raise RuntimeError("device status in the adjoint leg")
     w = res["w"]
-    t_fwd = timed(lambda: ctx.forward(p, out=out, check=False))
     t_tape = timed(lambda: ctx.forward(p, out=out, tape=tape, check=False))
     t_contract = timed(lambda: ctx.backward(p, w, tape=tape, check=False))
     t_recompute = timed(lambda: ctx.backward(p, w, check=False))
@@ -277,7 +285,8 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
             "fwd_ms": 1e3 * t_fwd, "fwd_tape_ms": 1e3 * t_tape,
             "adjoint_from_tape_ms": 1e3 * t_contract,
             "adjoint_recompute_ms": 1e3 * t_recompute,
-            "step_over_fwd": dt / t_fwd,
+            "step_over_fwd": dt / t_fwd, "rounds": len(dts),
+            "step_over_fwd_by_round": [a / b for a, b in zip(dts, fwds)],
             "sample_steps_per_s": n * N / dt, "loss": float(res["loss"]),
             "grad": dict(zip(qs.PARAM_NAMES, [float(x) for x in g]))}
 
