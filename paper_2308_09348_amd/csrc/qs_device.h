@@ -474,7 +474,32 @@ __device__ __forceinline__ void draw_sample(const ShotParams &sp, uint32_t key0,
 // point.  The order is stable (ties by index), so every launch of a group
 // forms the same wavefronts.  s_idx[r] receives the group offset of rank r;
 // offsets at or past `end` (no sample) rank last.  B threads take part.
-template <int G, int B>
+// An FP32 estimate of that key, for passes whose results do not depend on the
+// order (no FP64 steps): the first counter block's normals by Box-Muller in
+// FP32, the collision point without the divergence's shift (below 1e-2 um).
+__device__ __forceinline__ float chi_key32(const ShotParams &sp, uint32_t k0, uint32_t k1,
+                                           int64_t i) {
+    uint32_t c[4] = {(uint32_t)(i * (int64_t)sp.draw_stride), (uint32_t)sp.shot_word, 0u, 0u};
+    philox4x32_10(c, k0, k1);
+    float u[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) u[m] = ((float)(c[m] >> 8) + 0.5f) * 0x1p-24f;
+    const float R0 = __builtin_sqrtf(-2.0f * __logf(u[0])), R1 = __builtin_sqrtf(-2.0f * __logf(u[2]));
+    float s0, c0, s1, c1;
+    __sincosf(6.28318530717958648f * u[1], &s0, &c0);
+    __sincosf(6.28318530717958648f * u[3], &s1, &c1);
+    const bool flat_r = (sp.profile & kFlatR) != 0;
+    const float sr = (float)sp.sigma_r, rad = flat_r ? sr * __builtin_sqrtf(u[0]) : sr * R0;
+    const float x = fmaf(rad, c0, (float)sp.x_off), y = fmaf(rad, s0, (float)sp.y_off);
+    const float z = (float)sp.sigma_z * ((sp.profile & kFlatZ) ? u[2] - 0.5f : R1 * c1);
+    const float g0 = fmaf((float)sp.sigma_gamma, R1 * s1, (float)sp.gamma0);
+    if (sp.plane_wave) return g0;
+    return g0 * spatial(x, y, fmaf(0.5f, z, (float)sp.z_delay), sp.inv_w0sqf, sp.inv_zRf);
+}
+
+// FAST: the FP32 key (passes without FP64 steps, where any order gives the same
+// results); else the FP64 one.
+template <int G, int B, bool FAST = false>
 __device__ __forceinline__ void chi_order(const ShotParams &sp, uint32_t key0, uint32_t key1,
                                           int64_t base, int64_t end, float *s_key,
                                           unsigned short *s_idx) {
@@ -484,12 +509,17 @@ __device__ __forceinline__ void chi_order(const ShotParams &sp, uint32_t key0, u
         float key = __builtin_inff();
         const int64_t i = base + q;
         if (i < end) {
-            // (the Gaussian focus's factor also orders samples of a higher mode:
-            // any order gives the same results up to the FP64-step choice)
-            double g0, thx, thy, S0;
-            Path<double, false> pd{};
-            draw_sample<false>(sp, key0, key1, i, g0, thx, thy, pd, S0);
-            key = (float)(S0 * g0);
+            if constexpr (FAST) {
+                key = chi_key32(sp, key0, key1, i);
+            } else {
+                // (the Gaussian focus's factor also orders samples of a higher
+                // mode: any order gives the same results up to the FP64-step
+                // choice)
+                double g0, thx, thy, S0;
+                Path<double, false> pd{};
+                draw_sample<false>(sp, key0, key1, i, g0, thx, thy, pd, S0);
+                key = (float)(S0 * g0);
+            }
         }
         s_key[q] = key;
     }
@@ -589,7 +619,10 @@ __device__ __forceinline__ void rk4_q32(float mu, float s2, AmpQ &A1, float ah, 
     rad_cell_eval(carry, c4, g, G1, G2, hq);
     float k4m, k4s;
     rhs_q32(m4, s24, A1, g, G1, G2, hq, k4m, k4s);
-    chi_hi = fmaxf(chi_hi, fmaxf(fmaxf(c1, c2), fmaxf(c3, c4)));
+    // the range check takes the chi of the table reads: stages 1 and 3
+    // evaluate the cells of stages 4 and 2 at a chi a hair away (the state
+    // moved by less than one step's increment)
+    chi_hi = fmaxf(chi_hi, fmaxf(c2, c4));
     const float h6 = h * (1.0f / 6.0f);
     dmu = h6 * (k1m + 2.0f * (k2m + k3m) + k4m);
     ds2 = h6 * (k1s + 2.0f * (k2s + k3s) + k4s);
@@ -618,6 +651,28 @@ __device__ __forceinline__ int find_shot(const ShotParams *shots, int n_shots, i
         const int mid = (lo + hi + 1) >> 1;
         const int64_t first = deposit ? shots[mid].ditem0 : shots[mid].item0;
         if (first <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The same from shot s0 on, for a block that took an item of shot s0 before
+// (a block takes items in increasing order, so the shot is s0 or a later one,
+// mostly within a few): a doubling search forward from s0, then bisection.
+__device__ __forceinline__ int find_shot_from(const ShotParams *shots, int n_shots, int64_t item,
+                                              bool deposit, int s0) {
+    auto first = [&](int s) { return deposit ? shots[s].ditem0 : shots[s].item0; };
+    int lo = s0, step = 1;  // first(lo) <= item throughout
+    while (lo + step < n_shots && first(lo + step) <= item) {
+        lo += step;
+        step <<= 1;
+    }
+    int hi = min(lo + step, n_shots) - 1;  // first(hi + 1) > item, or hi the last shot
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= item)
             lo = mid;
         else
             hi = mid - 1;
@@ -766,16 +821,20 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 //    position pass; towards the centre the run adds the integral of the
 //    Gaussian density phi over each edge interval by Boole's rule on four
 //    subintervals of h = dz / 4 (dz: edge spacing in standard deviations, at
-//    most 1/4), phi following the lattice by phi(a - h) = phi(a) e^(a h - h^2/2)
-//    (one exponential a run: the ratio itself shrinks by e^(-h^2) from one
-//    subinterval to the next and by e^(-4 h^2) from one edge to the next).
-//    Boole's rule errs by 8/945 h^7 phi^(6), below 1e-5 of an interval's mass
-//    out to 6.4 standard deviations (its sixth derivative is He6(a) phi), and
-//    the products' roundings grow with the square of the edges walked: over
-//    a run an interval's mass carries at most about 1e-5 relative error in
-//    all (an FP32 emulation of nine-edge runs with dz in [0.02, 0.25] starting
-//    out to 6.2 standard deviations finds 1.0e-5), against the 1e-4 a bin may
-//    err.
+//    most 1/4), or by Simpson's on two of h = dz / 2 when every run of the
+//    wavefront has dz <= 1/10, phi following the lattice by
+//    phi(a - h) = phi(a) e^(a h - h^2/2) (one exponential a run: the ratio
+//    itself shrinks by e^(-h^2) from one subinterval to the next).  Boole's
+//    rule errs by 8/945 h^7 phi^(6), below 1e-5 of an interval's mass out to
+//    6.4 standard deviations (its sixth derivative is He6(a) phi); Simpson's
+//    by h^5/90 phi^(4), below 1e-5 of it out to 4 and below 4e-5 out to 6
+//    standard deviations at dz <= 1/10, where the masses are below 1e-9 of a
+//    sample; the products' roundings grow with the square of the edges
+//    walked.  An FP32 emulation of nine-edge runs starting out to 6.2
+//    standard deviations finds at most 1.0e-5 relative error in an
+//    interval's mass with Boole's rule (dz in [0.02, 0.25]), and 1.2e-5 with
+//    Simpson's (dz in [0.02, 0.125]) for runs starting within 4, against the
+//    1e-4 a bin may err.
 // Q[e] (u64) accumulates the quantised weight at or below edge e of the laws
 // that cover e; cnt[c] (u32) counts the samples whose weight is all at or
 // below edge c - 1 (a point in bin c - 1, or a law ending at edge c - 1), so
@@ -844,6 +903,53 @@ __device__ __forceinline__ void add_run_edge(unsigned long long *Qe, float F, bo
     const uint32_t lo = upper ? 0u - qf : qf;
     const uint32_t hi = upper && qf == 0u ? 1u : 0u;
     atomicAdd(Qe, ((unsigned long long)hi << 32) | lo);
+}
+
+// The edges of one run from the tail inwards (see wave_deposit): a0, ph0 and
+// T0 are the distance from the centre, the density and the tail mass at the
+// run's first edge; each step adds the density's integral over one edge
+// interval, by Simpson's rule on two subintervals (SIMP) or Boole's on four,
+// the density following the lattice by phi(a - h) = phi(a) e^(a h - h^2/2): the
+// ratio itself shrinks by e^(-h^2) from one subinterval to the next.
+template <bool SIMP>
+__device__ __forceinline__ void walk_run(unsigned long long *qe, int step, int len, int kind,
+                                         float sf, float da, float a0, float ph0, float T0,
+                                         bool upper) {
+    constexpr int kSub = SIMP ? 2 : 4;
+    const float hs = da * (1.0f / kSub);
+    const float q = __expf(-hs * hs), qn = __expf(-(float)kSub * hs * hs);
+    const float cb = hs * (SIMP ? 1.0f / 3.0f : 2.0f / 45.0f);
+    float a = a0, ph = ph0, T = T0;
+    float rho = __expf(fmaf(a, hs, -0.5f * hs * hs));  // phi(a - hs) / phi(a)
+    for (int k = 0; k < kRunLen; ++k) {
+        if (k < len) {
+            if (k > 0) {
+                // from the previous edge (a) one edge towards the centre
+                float r = rho;
+                const float p1 = ph * r;
+                r *= q;
+                const float p2 = p1 * r;
+                if constexpr (SIMP) {
+                    T = fmaf(cb, fmaf(4.0f, p1, ph + p2), T);
+                    ph = p2;
+                } else {
+                    r *= q;
+                    const float p3 = p2 * r;
+                    r *= q;
+                    const float p4 = p3 * r;
+                    T = fmaf(cb, fmaf(7.0f, ph + p4, fmaf(32.0f, p1 + p3, 12.0f * p2)), T);
+                    ph = p4;
+                }
+                rho *= qn;
+                a -= da;
+            }
+            // wide box (x) Gaussian: the series' even terms beside the tail
+            // (sf holds beta^2), with the sign of the tail on either side
+            const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
+            const float F = kind == 4 ? fmaf(a * ph, c, T) : T;
+            add_run_edge(qe + step * k, F, upper);
+        }
+    }
 }
 
 __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
@@ -949,43 +1055,21 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
                                            : min(kRunLen, n_l - j * kRunLen))
                                   : 0;
         const int step = upper ? -1 : 1;
-        const float da = wf * inv_s;    // edge spacing in standard deviations
-        const float hs = 0.25f * da;    // Boole subinterval (a quarter edge)
-        const float q = __expf(-hs * hs), q4 = __expf(-4.0f * hs * hs);
-        const float cb = hs * (2.0f / 45.0f);
+        const float da = wf * inv_s;  // edge spacing in standard deviations
         // the tail at the run's first edge
-        float a = fabsf(fmaf((float)rel0, wf, t0) * inv_s);
-        const float e2 = __expf(-0.5f * a * a);
-        float ph = 0.39894228040143267794f * e2;
-        float T = 0.5f * erfc_pos(a * 0.70710678118654752440f, e2);
-        // phi(a - hs) / phi(a) at the current edge a; the ratio of the next
-        // subinterval is e^(-hs^2) times this one's, of the next edge e^(-4 hs^2)
-        float rho = __expf(fmaf(a, hs, -0.5f * hs * hs));
+        const float a0 = fabsf(fmaf((float)rel0, wf, t0) * inv_s);
+        const float e2 = __expf(-0.5f * a0 * a0);
+        const float ph0 = 0.39894228040143267794f * e2;
+        const float T0 = 0.5f * erfc_pos(a0 * 0.70710678118654752440f, e2);
         unsigned long long *qe = Q + (ka + rel0);
-        for (int k = 0; k < kRunLen; ++k) {
-            if (k < len) {
-                if (k > 0) {
-                    // from the previous edge (a) one edge towards the centre
-                    float r = rho;
-                    const float p1 = ph * r;
-                    r *= q;
-                    const float p2 = p1 * r;
-                    r *= q;
-                    const float p3 = p2 * r;
-                    r *= q;
-                    const float p4 = p3 * r;
-                    rho *= q4;
-                    T = fmaf(cb, fmaf(7.0f, ph + p4, fmaf(32.0f, p1 + p3, 12.0f * p2)), T);
-                    ph = p4;
-                    a -= da;
-                }
-                // wide box (x) Gaussian: the series' even terms beside the tail
-                // (sf holds beta^2), with the sign of the tail on either side
-                const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
-                const float F = kind == 4 ? fmaf(a * ph, c, T) : T;
-                add_run_edge(qe + step * k, F, upper);
-            }
-        }
+        // Simpson's rule on half edges where the laws of all the wavefront's
+        // runs have edges at most a tenth of a standard deviation apart (its
+        // error then stays within 1e-5 of an interval's mass out to four
+        // standard deviations), Boole's on quarter edges otherwise
+        if (__all(!(p < total) || da <= 0.1f))
+            walk_run<true>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
+        else
+            walk_run<false>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
     }
     wave_sync_lds();  // the next call rewrites the rows
 }

@@ -104,7 +104,7 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
 
     double mu_f, s2_f;
     float cmx = 0.0f;     // largest chi at a step start for this sample
-    float chi_hi = 0.0f;  // largest chi at any stage (range check)
+    float chi_hi = 0.0f;  // largest chi of the table reads (range check)
     if (PREC == PREC_F64) {
         double mu = g0, s2 = 0.0, chd = 0.0;
         double aS_prev = local ? sp.a0 * pd.S(-P.psi_max * P.ell_per_psi) : a0S0;
@@ -287,6 +287,7 @@ __attribute__((amdgpu_waves_per_eu((PREC == PREC_F32 && QUANTUM) ? 4 : 1))) void
                 atomicAdd(&P.fp64_steps[s], (unsigned long long)nprom);
         }
     };
+    int s_prev = 0;  // the shot of the block's previous item
     for (;;) {
         const int64_t item = next_item(&P.queue[0], &slot);
         if constexpr (kGroup) {
@@ -304,13 +305,15 @@ __attribute__((amdgpu_waves_per_eu((PREC == PREC_F32 && QUANTUM) ? 4 : 1))) void
             }
         } else {
             if (item >= P.n_items) break;
-            const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
+            const int s = __builtin_amdgcn_readfirstlane(
+                find_shot_from(P.shots, P.n_shots, item, false, s_prev));
+            s_prev = s;
             const ShotParams &sp = P.shots[s];
             const int64_t base = (item - sp.item0) * kPhaseBlock;
             int off = threadIdx.x;
             if constexpr (kOrder) {
-                chi_order<kPhaseBlock, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey,
-                                                    oidx);
+                chi_order<kPhaseBlock, kPhaseBlock, true>(sp, P.key0, P.key1, base, sp.n_samples,
+                                                          okey, oidx);
                 off = oidx[threadIdx.x];
             }
             const int64_t i = base + off;
@@ -476,10 +479,13 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const WaveLaws WL{wrec + 64 * wid, wext + 64 * wid, woff + 64 * wid, wmark + 64 * wid};
     WL.mark[lane] = -1;
+    int s_prev = 0;  // the shot of the block's previous item
     for (;;) {
         const int64_t item = next_item(&P.queue[1], &slot);
         if (item >= P.n_ditems) break;
-        const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, true));
+        const int s = __builtin_amdgcn_readfirstlane(
+            find_shot_from(P.shots, P.n_shots, item, true, s_prev));
+        s_prev = s;
         const ShotParams &sp = P.shots[s];
         const ShotOut &so = P.outs[s];
         const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2;
