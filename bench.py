@@ -265,9 +265,11 @@ def adjoint_leg(ctx, qs, workloads, torch, steps):
     # several percent over a few seconds of load)
     fn_step = lambda: res.update(zip(("loss", "g", "w"), step()))
     dts, fwds = [], []
-    for _ in range(4):
-        dts.append(timed(fn_step))
-        fwds.append(timed(fwd))
+    for r in range(5):  # the first round warms the device up and is not kept
+        dt_r, fwd_r = timed(fn_step), timed(fwd)
+        if r > 0:
+            dts.append(dt_r)
+            fwds.append(fwd_r)
     dt, t_fwd = float(np.mean(dts)), float(np.mean(fwds))
     if int(out["status"].item()) != 0:
         raise RuntimeError("device status in the adjoint leg")

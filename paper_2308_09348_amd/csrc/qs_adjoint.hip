@@ -1058,10 +1058,23 @@ __attribute__((amdgpu_waves_per_eu((TAPE && PREC == PREC_F32) ? 3 : 2))) void ta
 // result equals the recomputing adjoint's bit for bit.
 template <bool OBS, bool GROUPED>
 __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
+    // the energy-histogram weights of the block's current shot (n_e + 2
+    // words), read from LDS by every edge of every sample's law
+    extern __shared__ double wsh[];
     __shared__ int64_t slot;
     __shared__ double red[kPhaseBlock / 64][kGradParams];
     __shared__ float okey[GROUPED ? kChiGroup : 1];
     __shared__ unsigned short oidx[GROUPED ? kChiGroup : 1];
+    int s_w = -1;  // the shot whose weights wsh holds (block-uniform)
+    auto load_w = [&](int s, const ShotParams &sp) {
+        if (s == s_w) return;
+        // the previous item's reads ended at its reduction's barrier
+        const double *W = P.gouts[s].d_energy;
+        if (W)
+            for (int k = threadIdx.x; k < sp.n_e + 2; k += blockDim.x) wsh[k] = W[k];
+        __syncthreads();
+        s_w = s;
+    };
     auto one = [&](const ShotParams &sp, int s, int64_t i, double *g) {
         const int64_t n = P.tape_n;
         const double *t = P.tape + sp.state_off + i;
@@ -1077,8 +1090,8 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
             }
             if (go.d_energy) {
                 double lv, ls;
-                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e,
-                                go.d_energy, lv, ls);
+                law_sensitivity(mu, s2, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e, wsh,
+                                lv, ls);
 #pragma unroll
                 for (int p = 0; p < kGradParams; ++p) gi[p] = fma(lv, dm[p], ls * ds[p]);
             }
@@ -1100,6 +1113,7 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
             const ShotParams &sp = P.shots[s];
             const int64_t base = (item - sp.gitem0) * kChiGroup;
             const int cnt = (int)min((int64_t)kChiGroup, sp.n_samples - base);
+            load_w(s, sp);
             chi_order<kChiGroup, kPhaseBlock>(sp, P.key0, P.key1, base, sp.n_samples, okey, oidx);
             for (int r = 0; r * kPhaseBlock < cnt; ++r) {
                 const int rank = r * kPhaseBlock + (int)threadIdx.x;
@@ -1110,6 +1124,7 @@ __global__ __launch_bounds__(kPhaseBlock) void contract_kernel(BatchParams P) {
             const int s = __builtin_amdgcn_readfirstlane(find_shot(P.shots, P.n_shots, item, false));
             const ShotParams &sp = P.shots[s];
             const int64_t i = (item - sp.item0) * kPhaseBlock + threadIdx.x;
+            load_w(s, sp);
             if (i < sp.n_samples) one(sp, s, i, g);
         }
         grad_item_reduce(P, item, g, red);
@@ -1231,7 +1246,7 @@ hipError_t launch_tangent(const BatchParams &p, const float *env32, const double
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
 }
 
-hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s) {
+hipError_t launch_contract(const BatchParams &p, bool obs, int max_ne, hipStream_t s) {
     // a tape of a pass with FP64 steps is summed over that pass's groups
     const bool grouped = p.prec == PREC_F32MIX;
     const void *fn =
@@ -1239,12 +1254,13 @@ hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s) {
                        : reinterpret_cast<const void *>(&contract_kernel<false, true>))
                 : (obs ? reinterpret_cast<const void *>(&contract_kernel<true, false>)
                        : reinterpret_cast<const void *>(&contract_kernel<false, false>));
+    const size_t lds = (size_t)(max_ne + 2) * sizeof(double);  // at most 32 KB (n_e <= 4096)
     int grid = 0;
-    hipError_t e = resident_grid(fn, kPhaseBlock, 0, grouped ? p.n_gitems : p.n_items, &grid);
+    hipError_t e = resident_grid(fn, kPhaseBlock, lds, grouped ? p.n_gitems : p.n_items, &grid);
     if (e != hipSuccess) return e;
     BatchParams pc = p;
     void *args[] = {&pc};
-    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, 0, s);
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kPhaseBlock), args, lds, s);
 }
 
 hipError_t launch_grad_finalize(const BatchParams &p, hipStream_t s) {

@@ -1305,8 +1305,12 @@ qs_status backward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_
         return hip_fail(c, e, "zero kernel");
     if (tape) {
         bool obs = false;
-        for (int k = 0; k < n_shots; ++k) obs = obs || O[k].d_angle_hist || O[k].d_moments;
-        if ((e = qs::launch_contract(bp, obs, s)) != hipSuccess)
+        int max_ne = 1;
+        for (int k = 0; k < n_shots; ++k) {
+            obs = obs || O[k].d_angle_hist || O[k].d_moments;
+            max_ne = std::max(max_ne, H[k].n_e);
+        }
+        if ((e = qs::launch_contract(bp, obs, max_ne, s)) != hipSuccess)
             return hip_fail(c, e, "contraction kernel");
     } else if ((e = qs::launch_tangent(bp, c->env32, c->env64, b.prec, N->rr_model, N->amp_mode,
                                        false, s)) != hipSuccess) {

@@ -251,7 +251,7 @@ hipError_t launch_radiation_derivs(const float *rad32d, const double *rad64d, in
                                    const double *chi, double *out, int *flags, hipStream_t s);
 hipError_t launch_tangent(const BatchParams &p, const float *env32, const double *env64, int prec,
                           int rr, int amp, bool tape, hipStream_t s);
-hipError_t launch_contract(const BatchParams &p, bool obs, hipStream_t s);
+hipError_t launch_contract(const BatchParams &p, bool obs, int max_ne, hipStream_t s);
 size_t photon_work_doubles();
 hipError_t build_photon_table(double *phtab, double *work, size_t work_doubles, hipStream_t s);
 hipError_t launch_photon(const BatchParams &p, const float *env32, const double *env64, int prec,
