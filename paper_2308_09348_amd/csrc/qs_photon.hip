@@ -410,7 +410,22 @@ struct PhotCtx {
     float inv_a0, tas;
     bool local, mid, angles, cell_number;
     bool live;  // the lane's sample is real (else it runs for the wavefront's table reads only)
+    const float4 *ncell = nullptr;  // photon-number cubics of the FP32 cells (FP64 steps of mixed passes)
 };
+
+// Phi(1; chi) / chi from the photon-number cubic of the FP32 radiation-table
+// cell of chi (the index map of rad_lookup32; below the first octave its cubic
+// extrapolated down to chi = 0).
+__device__ __forceinline__ float ph_number32(const float4 *ncell, float chi) {
+    const float xc = fminf(fmaxf(chi, 0x1p-20f), 0x1.fffffep7f);
+    const uint32_t b = __float_as_uint(xc);
+    const uint32_t c = ((b - ((uint32_t)(127 + kEMin) << 23)) >> (23 - kSB32)) + 1u;
+    const float tw = __uint_as_float((uint32_t)(254 + kSB32 - (int)(b >> 23)) << 23);
+    const float ts = -__uint_as_float(b & ~((1u << (23 - kSB32)) - 1)) * tw;
+    const float4 q = ncell[c];
+    const float t = fmaf(chi, tw, ts);
+    return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+}
 
 // The state carried from step to step (mu_lo, s2_lo: the FP32 pairs' lower
 // parts, unused in FP64): the amplitude factors a0 S at psi_j (and psi_{j+1}
@@ -423,7 +438,10 @@ struct PhotState {
 // Step j of the photon pass: the four RK4 stages with their emission, the
 // deposits of stage 1 with the previous step's stage 4 (same amplitude) and
 // of stages 2 and 3, the emitted energy and the Sec. 5.1 angular sums.
-template <class T, bool QUANTUM, class R = FwdRad<T>>
+// ANG32: the angular sums' terms in FP32 with the photon number from the FP32
+// cells' cubics (the FP64 steps of a mixed-precision pass, whose angular
+// moments are held to the FP32 pass's bar; the FP64 pass takes them in FP64).
+template <class T, bool QUANTUM, class R = FwdRad<T>, bool ANG32 = false>
 __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot &pp,
                                             const float *tot, int j, PhotState<T> &st, R &rad,
                                             unsigned long long *grid, PhotAcc &acc) {
@@ -462,7 +480,26 @@ __device__ __forceinline__ void photon_step(const PhotCtx<T> &c, const ShotPhot 
     const T m4 = fma(h, k3m, mu);
     photon_stage<T, QUANTUM, 4, R>(m4, fma(h, k3s, s2), a4, c.ph, rad, k4m, k4s, A4, st.chi_hi, n4);
     if (c.live) acc.e_ph += (double)(h * -(c16 * (A1 + A4) + c13 * (A2 + A3)));
-    if (c.angles && c.live) {
+    if constexpr (ANG32) {
+        if (c.angles && c.live) {
+            auto num = [&](T m, T a) {
+                const float aa = fabsf((float)a);
+                return aa > 0.0f ? ph_number32(c.ncell, c.tas * (float)m * aa) : 0.0f;
+            };
+            const float thx = (float)c.thx, thy = (float)c.thy;
+            AngStep<float> an{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            an.add((float)c16, (float)a1, (float)mu, (float)A1, thx, thy, num(mu, a1));
+            an.add((float)c13, (float)ah, (float)m2, (float)A2, thx, thy, num(m2, ah));
+            an.add((float)c13, (float)ah, (float)m3, (float)A3, thx, thy, num(m3, ah));
+            an.add((float)c16, (float)a4, (float)m4, (float)A4, thx, thy, num(m4, a4));
+            acc.nn += an.n;
+            acc.nx += an.nx;
+            acc.ny += an.ny;
+            acc.ee += an.e;
+            acc.ex += an.ex;
+            acc.ey += an.ey;
+        }
+    } else if (c.angles && c.live) {
         if (!c.cell_number) {  // from the rows
             auto rows = [&](T m, T a) {
                 const float aa = fabsf((float)a);
@@ -635,6 +672,7 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                 cd.mid = false;
                 cd.angles = angles;
                 cd.cell_number = false;
+                cd.ncell = ncell;
                 cd.live = c.live;
                 PhotState<double> sd;
                 sd.mu = ((double)st.mu + (double)st.mu_lo) + g0_rest;
@@ -648,7 +686,8 @@ __device__ __forceinline__ void photon_sample(const BatchParams &P, const ShotPa
                 sd.chi_hi = 0.0;
                 FwdRadWave radd(P.rad64, stage);
                 for (;;) {
-                    photon_step<double, QUANTUM, FwdRadWave>(cd, pp, tot, j, sd, radd, grid, acc);
+                    photon_step<double, QUANTUM, FwdRadWave, true>(cd, pp, tot, j, sd, radd, grid,
+                                                                   acc);
                     ++j;
                     if (j >= N) break;
                     const double chi = P.two_over_aS * sd.mu * fabs(sd.aS_prev * env64[2 * j]);

@@ -188,7 +188,11 @@ def test_mixed_precision_photons_vs_oracle(gpu, oracle, amp):
 def test_mixed_photons_promoted_everywhere_are_the_fp64_pass(gpu):
     """A threshold below every chi runs every step in FP64 from the exact
     initial energy: the FP64 pass's step arithmetic throughout (the state
-    returns through the FP32 pair only at the end, 2^-48 relative)."""
+    returns through the FP32 pair only at the end, 2^-48 relative), so the
+    spectrum and the energy are the FP64 pass's.  The angular moments' terms
+    are taken in FP32 in the FP64 steps of a mixed pass (summed in FP64; the
+    moments are held to the FP32 pass's bar against the oracle): within 2e-6
+    of the FP64 pass's."""
     p = _qb_case(n_samples=1000)
     m = _np(gpu.photons(dict(p, chi_fp64=1e-30), angles=True))
     d = _np(gpu.photons(dict(p, precision="fp64"), angles=True))
@@ -199,7 +203,9 @@ def test_mixed_photons_promoted_everywhere_are_the_fp64_pass(gpu):
     assert np.allclose(m["photon_hist"], d["photon_hist"], rtol=1e-12,
                        atol=1e-12 * d["photon_hist"].max())
     assert np.allclose(m["energy"], d["energy"], rtol=1e-12, atol=0)
-    assert np.allclose(m["angles"], d["angles"], rtol=1e-12, atol=0)
+    print("promoted vs fp64: largest relative angle-moment difference",
+          np.max(np.abs(m["angles"] - d["angles"]) / np.abs(d["angles"])))
+    assert np.allclose(m["angles"], d["angles"], rtol=2e-6, atol=0)
     f = _np(gpu.photons(dict(p, chi_fp64=0.0), angles=True))  # FP32 throughout
     assert not np.array_equal(f["photon_hist"], d["photon_hist"])
 
