@@ -162,6 +162,10 @@ __device__ __forceinline__ void phase_sample(const BatchParams &P, const ShotPar
         // derivative of S, far below FP32 rounding)
         float aS_next = local ? a0f * pf.S((P.psi0f + P.hf) * P.ellf) : a0S0f;
         int j = 0;
+        // two steps an iteration: the loop's bookkeeping and the moves of the
+        // carried values at its back edge are halved (FP32 quantum pass 3%
+        // faster; four steps no faster, with spills)
+#pragma clang loop unroll_count(2)
         while (j < N) {
             if (PREC == PREC_F32MIX) {
                 const float chi1 = amp1.cpm * mu;
