@@ -240,6 +240,23 @@ def test_wide_box_gaussian_laws(gpu, oracle, prec):
     assert o["angle_hist"][:-2].min() > 0.5  # the tails are populated
 
 
+@pytest.mark.parametrize("ksig", [4.5, 9.0, 11.0, 20.0])
+def test_gauss_runs_on_both_sides_of_the_rule_bound(gpu, oracle, ksig):
+    """GAUSS deposits with kernels of ksig bins: every law is at least ksig
+    bins wide, so its edges are at most 1/ksig of its width apart and its
+    edges are walked in runs, by Boole's rule on quarter edges where some law
+    of the wavefront has them more than a tenth of its width apart (ksig 4.5
+    and 9) and by Simpson's on half edges where none has (ksig 11 and 20):
+    every bin of both spectra within the parity bar on either side."""
+    p = workloads.scaled(workloads.focused_3d(), n_samples=3000, n_steps=256,
+                         deposit="gauss", kernel_sigma_bins=ksig)
+    g = _run(gpu, p)
+    o = oracle.forward(p)
+    _check_moments(g, o, p)
+    _check_bins(g["energy_hist"], o["energy_hist"])
+    _check_bins(g["angle_hist"], o["angle_hist"])
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
 def test_small_and_ragged_sizes(gpu, oracle, n):
     p = workloads.scaled(workloads.focused_3d(), n_samples=n, n_steps=64)
