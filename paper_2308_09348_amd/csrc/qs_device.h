@@ -897,12 +897,20 @@ __device__ __forceinline__ void add_edge(unsigned long long *Q, int e, float F, 
 
 // The same for an edge of a run, whose tail mass F is at most about one half:
 // 2^32 F fits 32 bits, and the weight on the upper side, 2^32 - 2^32 F, has
-// its high word set only when 2^32 F rounds to zero.
+// its high word set only when 2^32 F rounds to zero.  SPLIT: the upper side's
+// tails go to an array of their own (Qe points into it) as they are, the
+// 2^32 of each upper edge counted once a law at its first upper edge.
+template <bool SPLIT>
 __device__ __forceinline__ void add_run_edge(unsigned long long *Qe, float F, bool upper) {
-    const uint32_t qf = (uint32_t)rintf(fminf(fmaxf(F, 0.0f), 0x1.fffffep-1f) * 4294967296.0f);
-    const uint32_t lo = upper ? 0u - qf : qf;
-    const uint32_t hi = upper && qf == 0u ? 1u : 0u;
-    atomicAdd(Qe, ((unsigned long long)hi << 32) | lo);
+    const uint32_t qf =
+        (uint32_t)rintf(__builtin_amdgcn_fmed3f(F, 0.0f, 0x1.fffffep-1f) * 4294967296.0f);
+    if constexpr (SPLIT) {
+        atomicAdd(Qe, (unsigned long long)qf);
+    } else {
+        const uint32_t lo = upper ? 0u - qf : qf;
+        const uint32_t hi = upper && qf == 0u ? 1u : 0u;
+        atomicAdd(Qe, ((unsigned long long)hi << 32) | lo);
+    }
 }
 
 // The edges of one run from the tail inwards (see wave_deposit): a0, ph0 and
@@ -911,7 +919,7 @@ __device__ __forceinline__ void add_run_edge(unsigned long long *Qe, float F, bo
 // interval, by Simpson's rule on two subintervals (SIMP) or Boole's on four,
 // the density following the lattice by phi(a - h) = phi(a) e^(a h - h^2/2): the
 // ratio itself shrinks by e^(-h^2) from one subinterval to the next.
-template <bool SIMP>
+template <bool SIMP, bool SPLIT>
 __device__ __forceinline__ void walk_run(unsigned long long *qe, int step, int len, int kind,
                                          float sf, float da, float a0, float ph0, float T0,
                                          bool upper) {
@@ -947,17 +955,19 @@ __device__ __forceinline__ void walk_run(unsigned long long *qe, int step, int l
             // (sf holds beta^2), with the sign of the tail on either side
             const float c = sf * fmaf(sf * (1.0f / 1920.0f), fmaf(a, a, -3.0f), 1.0f / 24.0f);
             const float F = kind == 4 ? fmaf(a * ph, c, T) : T;
-            add_run_edge(qe + step * k, F, upper);
+            add_run_edge<SPLIT>(qe + step * k, F, upper);
         }
     }
 }
 
+// SPLIT: the runs' upper-side tails go to QU (see add_run_edge), and a law
+// walked in runs counts its sample at its first upper edge instead of past
+// its last edge: edge e carries Q[e] - QU[e] + 2^32 sum_(c <= e) cnt[c].
+template <bool SPLIT>
 __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float hf,
-                                             unsigned long long *Q, unsigned int *cnt,
-                                             const WaveLaws &WL) {
+                                             unsigned long long *Q, unsigned long long *QU,
+                                             unsigned int *cnt, const WaveLaws &WL) {
     const int lane = threadIdx.x & 63;
-    if (L.kind == 0) atomicAdd(&cnt[L.ngp], 1u);
-    if (L.kind > 0) atomicAdd(&cnt[L.kb + 1], 1u);
     const float wf = (float)w, inv_w = (float)(1.0 / w);
     // runs: the wide box (x) Gaussian, and Gaussians with dz <= 1/4
     const bool run = L.kind == 4 || (L.kind == 2 && wf * L.inv_s <= 0.25f);
@@ -969,6 +979,8 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         if (nl > 0 && fmaf((float)(nl - 1), wf, L.t0) > 0.0f) --nl;
         if (nl < ne && fmaf((float)nl, wf, L.t0) <= 0.0f) ++nl;
     }
+    if (L.kind == 0) atomicAdd(&cnt[L.ngp], 1u);
+    if (L.kind > 0) atomicAdd(&cnt[SPLIT && run ? L.ka + nl : L.kb + 1], 1u);
     WL.rec[lane] = make_int4(L.kind | (L.ka << 3), __float_as_int(L.t0), __float_as_int(L.sf),
                              __float_as_int(L.inv_s));
     WL.ext[lane] = make_int2(ne, nl);
@@ -1061,15 +1073,15 @@ __device__ __forceinline__ void wave_deposit(const LawLane &L, double w, float h
         const float e2 = __expf(-0.5f * a0 * a0);
         const float ph0 = 0.39894228040143267794f * e2;
         const float T0 = 0.5f * erfc_pos(a0 * 0.70710678118654752440f, e2);
-        unsigned long long *qe = Q + (ka + rel0);
+        unsigned long long *qe = (SPLIT && upper ? QU : Q) + (ka + rel0);
         // Simpson's rule on half edges where the laws of all the wavefront's
         // runs have edges at most a tenth of a standard deviation apart (its
         // error then stays within 1e-5 of an interval's mass out to four
         // standard deviations), Boole's on quarter edges otherwise
         if (__all(!(p < total) || da <= 0.1f))
-            walk_run<true>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
+            walk_run<true, SPLIT>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
         else
-            walk_run<false>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
+            walk_run<false, SPLIT>(qe, step, len, kind, sf, da, a0, ph0, T0, upper);
     }
     wave_sync_lds();  // the next call rewrites the rows
 }

@@ -354,12 +354,15 @@ __device__ __forceinline__ unsigned int block_scan(unsigned int v, unsigned int 
 }
 
 // Bin masses of one histogram of n bins from the edge accumulators of a tile
-// (see wave_deposit): edge e carries T(e) = Q[e] + 2^32 C(e), C(e) =
+// (see wave_deposit): edge e carries T(e) = Q[e] (- QU[e]) + 2^32 C(e), C(e) =
 // sum_(c <= e) cnt[c]; bin b gets T(b+1) - T(b), the underflow T(0), the
 // overflow 2^32 S - T(n) with S = sum of all cnt (every sample counts once).
 // Added to the global words G[0 .. n+1] (bins, underflow, overflow).
-__device__ void flush_edges(const unsigned long long *Q, const unsigned int *cnt, int n,
-                            unsigned long long *G, unsigned int *wsum) {
+template <bool SPLIT>
+__device__ void flush_edges(const unsigned long long *Q, const unsigned long long *QU,
+                            const unsigned int *cnt, int n, unsigned long long *G,
+                            unsigned int *wsum) {
+    auto q = [&](int e) { return SPLIT ? Q[e] - QU[e] : Q[e]; };
     const int m = (n + 2 + kDepBlock - 1) / kDepBlock;  // cnt entries a thread
     const int c0 = threadIdx.x * m, c1 = min(c0 + m, n + 2);
     unsigned int local = 0;
@@ -367,10 +370,10 @@ __device__ void flush_edges(const unsigned long long *Q, const unsigned int *cnt
     unsigned int S;
     unsigned int C = block_scan(local, wsum, &S);
     const unsigned long long one = kOne;
-    unsigned long long prev = c0 >= 1 && c0 <= n + 1 ? Q[c0 - 1] + one * C : 0ull;
+    unsigned long long prev = c0 >= 1 && c0 <= n + 1 ? q(c0 - 1) + one * C : 0ull;
     for (int e = c0; e < c1 && e <= n; ++e) {
         C += cnt[e];
-        const unsigned long long T = Q[e] + one * C;
+        const unsigned long long T = q(e) + one * C;
         const long long mass = (long long)(e == 0 ? T : T - prev);
         const int bin = e == 0 ? n : e - 1;
         if (mass > 0) atomicAdd(&G[bin], (unsigned long long)mass);
@@ -469,6 +472,9 @@ __global__ __launch_bounds__(kPhaseBlock) void shadow_diff_kernel(BatchParams P,
 
 // Held to 128 VGPRs (four waves per SIMD; it takes 131 otherwise, which
 // leaves three): one spilled register, a quarter less time.
+// SPLIT: the runs' upper-side tails in arrays of their own (16 bytes an edge
+// instead of 8; histograms of up to 64 KB of LDS words take it).
+template <bool SPLIT>
 __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) void deposit_kernel(
     BatchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -493,14 +499,18 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         const ShotParams &sp = P.shots[s];
         const ShotOut &so = P.outs[s];
         const int nh_e = sp.n_e + 2, nh_t = sp.n_th + 2;
-        // LDS: edge weights Qe [n_e + 1], Qt [n_th + 1] (u64); counters
-        // ce [n_e + 2], ct [n_th + 2], ca [n_a] (u32)
+        // LDS: edge weights Qe [n_e + 1], Qt [n_th + 1] (u64; SPLIT: and the
+        // upper tails QeU [n_e + 1], QtU [n_th + 1]); counters ce [n_e + 2],
+        // ct [n_th + 2], ca [n_a] (u32)
         unsigned long long *Qe = reinterpret_cast<unsigned long long *>(smem);
         unsigned long long *Qt = Qe + sp.n_e + 1;
-        unsigned int *ce = reinterpret_cast<unsigned int *>(Qt + sp.n_th + 1);
+        unsigned long long *QeU = Qt + sp.n_th + 1;
+        unsigned long long *QtU = QeU + (SPLIT ? sp.n_e + 1 : 0);
+        unsigned int *ce =
+            reinterpret_cast<unsigned int *>(SPLIT ? QtU + sp.n_th + 1 : QeU);
         unsigned int *ct = ce + nh_e;
         unsigned int *ca = ct + nh_t;
-        const int nq = sp.n_e + 1 + sp.n_th + 1, nc = nh_e + nh_t + sp.n_a;
+        const int nq = (SPLIT ? 2 : 1) * (sp.n_e + 1 + sp.n_th + 1), nc = nh_e + nh_t + sp.n_a;
         for (int k = threadIdx.x; k < nq; k += blockDim.x) Qe[k] = 0ull;
         for (int k = threadIdx.x; k < nc; k += blockDim.x) ce[k] = 0u;
         __syncthreads();
@@ -586,8 +596,8 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
                         }
                     }
                 }
-                wave_deposit(le, sp.e_w, hfe, Qe, ce, WL);
-                wave_deposit(lt, sp.th_w, hft, Qt, ct, WL);
+                wave_deposit<SPLIT>(le, sp.e_w, hfe, Qe, QeU, ce, WL);
+                wave_deposit<SPLIT>(lt, sp.th_w, hft, Qt, QtU, ct, WL);
             }
 
             // ---- moment tile reduction (fixed order) ----
@@ -626,8 +636,8 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         }
         if (flags) atomicOr(&P.flags[s], flags);
         unsigned long long *G = P.hist + sp.hist_off;
-        flush_edges(Qe, ce, sp.n_e, G, wsum);
-        flush_edges(Qt, ct, sp.n_th, G + nh_e, wsum);
+        flush_edges<SPLIT>(Qe, QeU, ce, sp.n_e, G, wsum);
+        flush_edges<SPLIT>(Qt, QtU, ct, sp.n_th, G + nh_e, wsum);
         for (int k = threadIdx.x; k < sp.n_a; k += blockDim.x)
             if (ca[k]) atomicAdd(&G[nh_e + nh_t + k], kOne * ca[k]);
         __syncthreads();  // the next item clears the LDS words
@@ -858,19 +868,23 @@ hipError_t launch_phase_nodes(const BatchParams &p, const float *env32, const do
 }
 
 // edge weights (u64, one per edge) and counters (u32, one per bin and two
-// more) of the deposit kernel: at most 12 bytes a histogram word
+// more) of the deposit kernel: at most 12 bytes a histogram word (20 with the
+// runs' upper tails apart)
 size_t deposit_lds_bytes(int max_hist_words) { return (size_t)max_hist_words * 12; }
 
 hipError_t launch_deposit(const BatchParams &p, int max_hist_words, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&deposit_kernel);
-    const size_t lds = deposit_lds_bytes(max_hist_words);
+    const bool split = (size_t)max_hist_words * 20 <= 64 * 1024;
+    const void *fn = split ? reinterpret_cast<const void *>(&deposit_kernel<true>)
+                           : reinterpret_cast<const void *>(&deposit_kernel<false>);
+    const size_t lds = (size_t)max_hist_words * (split ? 20 : 12);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int grid = 0;
     e = resident_grid(fn, kDepBlock, lds, p.n_ditems, &grid, p.dep_cap);
     if (e != hipSuccess) return e;
-    deposit_kernel<<<grid, kDepBlock, lds, s>>>(p);
-    return hipGetLastError();
+    BatchParams pc = p;
+    void *args[] = {&pc};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kDepBlock), args, lds, s);
 }
 
 hipError_t launch_shadow_diff(const BatchParams &p, int64_t n_items, int max_hist_words,
