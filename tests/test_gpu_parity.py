@@ -257,6 +257,19 @@ def test_gauss_runs_on_both_sides_of_the_rule_bound(gpu, oracle, ksig):
     _check_bins(g["angle_hist"], o["angle_hist"])
 
 
+def test_fine_histograms_keep_the_single_edge_array(gpu, oracle):
+    """4096 energy and 4096 angle bins: the deposit's LDS words exceed what the
+    split upper-tail arrays may take, so the runs add their upper tails as
+    2^32 - 2^32 F into the one edge array; every bin within the bar."""
+    p = workloads.scaled(workloads.focused_3d(), n_samples=2000, n_steps=128,
+                         n_e=4096, n_th=4096, n_a=64)
+    g = _run(gpu, p)
+    o = oracle.forward(p)
+    _check_moments(g, o, p)
+    _check_bins(g["energy_hist"], o["energy_hist"])
+    _check_bins(g["angle_hist"], o["angle_hist"])
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
 def test_small_and_ragged_sizes(gpu, oracle, n):
     p = workloads.scaled(workloads.focused_3d(), n_samples=n, n_steps=64)
