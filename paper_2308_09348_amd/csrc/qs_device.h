@@ -752,8 +752,11 @@ struct LawLane {
     float t0, sf, inv_s;
 };
 
+// (inv_w: 1 / w; the window and bin decisions take the product, which
+// differs from the quotient by an ulp at most: a value within 1e-16 of an
+// edge may fall on either side)
 __device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double ksig, double lo,
-                                             double w, int n) {
+                                             double w, double inv_w, int n) {
     LawLane L{0, 0, -1, 0, 0.0f, 0.0f, 0.0f};
     const double half = 0.5 * w;
     double se = s;
@@ -769,8 +772,10 @@ __device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double
     if (L.kind != 0) {
         const double reach =
             L.kind == 1 ? half : (L.kind == 2 ? 6.0 * se : 6.0 * se + half);
-        const int ka = max((int)fmin(fmax(ceil((v - reach - lo) / w), -1.0), (double)n + 1.0), 0);
-        const int kb = min((int)fmin(fmax(floor((v + reach - lo) / w), -1.0), (double)n + 1.0), n);
+        const int ka =
+            max((int)fmin(fmax(ceil((v - reach - lo) * inv_w), -1.0), (double)n + 1.0), 0);
+        const int kb =
+            min((int)fmin(fmax(floor((v + reach - lo) * inv_w), -1.0), (double)n + 1.0), n);
         if (ka > kb) {
             L.kind = 0;  // the whole law lies inside one bin (or outside)
         } else {
@@ -778,15 +783,16 @@ __device__ __forceinline__ LawLane law_setup(double v, double s, int dep, double
             L.kb = kb;
             L.t0 = (float)(fma((double)ka, w, lo) - v);
             L.sf = (float)se;
-            L.inv_s = L.kind >= 2 ? (float)(1.0 / se) : 0.0f;
+            L.inv_s = L.kind >= 2 ? __builtin_amdgcn_rcpf((float)se) : 0.0f;  // about one ulp
             if (L.kind == 3 && se >= 4.0 * w) {
                 L.kind = 4;
-                L.sf = (float)((w / se) * (w / se));
+                const float beta = (float)w * L.inv_s;
+                L.sf = beta * beta;
             }
         }
     }
     if (L.kind == 0) {
-        const double x = (v - lo) / w;  // bin floor(x); v on an edge goes up
+        const double x = (v - lo) * inv_w;  // bin floor(x); v on an edge goes up
         L.ngp = !(x >= 0.0) ? 0 : (x >= (double)n ? n + 1 : (int)x + 1);
     }
     return L;

@@ -519,6 +519,7 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         const int64_t i0 = (item - sp.ditem0) * P.dep_tile;
         const int64_t i1 = i0 + P.dep_tile < sp.n_samples ? i0 + P.dep_tile : sp.n_samples;
         const float hfe = (float)(0.5 * sp.e_w), hft = (float)(0.5 * sp.th_w);
+        const double inv_we = 1.0 / sp.e_w, inv_wt = 1.0 / sp.th_w;
         for (int64_t t0 = i0; t0 < i1; t0 += kMomTile) {
             const int64_t t1 = t0 + kMomTile < i1 ? t0 + kMomTile : i1;
             double acc[P_N];
@@ -544,11 +545,20 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
                         // c_theta sqrt(2/pi) a0,eff sigma_f / gamma_f^2 acts in x
                         const double sigf = sqrt(fmax(s2_f, 0.0));
                         const double a_eff = sp.a0 * S0;
+                        // 1 / mu_f^2 and 1 / g0 by the hardware reciprocal
+                        // and two Newton steps (FP64 rounding)
+                        const double mu2 = mu_f * mu_f;
+                        double imu2 = __builtin_amdgcn_rcp(mu2), ig0 = __builtin_amdgcn_rcp(g0);
+                        imu2 = fma(fma(-mu2, imu2, 1.0), imu2, imu2);
+                        imu2 = fma(fma(-mu2, imu2, 1.0), imu2, imu2);
+                        ig0 = fma(fma(-g0, ig0, 1.0), ig0, ig0);
+                        ig0 = fma(fma(-g0, ig0, 1.0), ig0, ig0);
                         const double sigth =
-                            1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf / (mu_f * mu_f);
-                        le = law_setup(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, sp.n_e);
+                            1e3 * P.c_theta * 0.79788456080286535588 * a_eff * sigf * imu2;
+                        le = law_setup(mu_f, sigf, P.deposit, P.ksig_bins, sp.e_lo, sp.e_w, inv_we,
+                                       sp.n_e);
                         lt = law_setup(thx_m, sigth, P.deposit, P.ksig_bins, sp.th_lo, sp.th_w,
-                                       sp.n_th);
+                                       inv_wt, sp.n_th);
                         {
                             int ka = (int)floor(S0 * (double)sp.n_a);
                             ka = min(max(ka, 0), sp.n_a - 1);
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(kDepBlock) __attribute__((amdgpu_waves_per_eu(4))) 
                         acc[P_S1Y] += thy_m;
                         acc[P_S2Y] += thy_m * thy_m;
                         acc[P_SAEFF] += a_eff;
-                        acc[P_SRAD] += 1.0 - mu_f / g0;
+                        acc[P_SRAD] += fma(-mu_f, ig0, 1.0);
                         acc[P_SSIGF] += sigf;
                         if (sp.shadow_stride > 0 && i % sp.shadow_stride == 0) {
                             // the same sample integrated in FP64
