@@ -552,6 +552,15 @@ qs_status qs_set_profiling(qs_ctx *ctx, int on);
  * profiled call yet), QS_EDEVICE. */
 qs_status qs_last_timings(qs_ctx *ctx, double *ms);
 
+/* Sums of the kernel durations that qs_last_timings reports, over the last
+ * min(n, 64) calls enqueued with profiling on since it was switched on (n of
+ * them): ms[0..4] as there (host array of 5), *n_calls the number of calls
+ * summed.  The events of up to 64 calls are kept, so calls can be enqueued
+ * back to back and read once at the end.  Waits for each summed call's last
+ * event.  Errors: QS_EINVAL (profiling off or no profiled call yet),
+ * QS_EDEVICE. */
+qs_status qs_timings_sum(qs_ctx *ctx, int32_t *n_calls, double *ms);
+
 /* Launch choices for a class of forward launches (qs_tune).  None of them
  * changes a result bit: moment partial sums are kept per tile of 1024
  * samples whatever the deposit tile. */

@@ -493,6 +493,17 @@ class Context:
             raise QScatterError(st, self.last_error())
         return dict(zip(["envelope", "clear", "phase", "deposit", "finalize"], list(ms)))
 
+    def timings_sum(self):
+        """(calls, sums) of the kernel durations [ms] that last_timings reports,
+        over the last min(n, 64) of the n profiled forwards since profiling was
+        switched on; read once after many back-to-back calls."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int32(0)
+        st = _lib.lib().qs_timings_sum(self._ptr, ctypes.byref(n), ms)
+        if st != _lib.QS_OK:
+            raise QScatterError(st, self.last_error())
+        return n.value, dict(zip(["envelope", "clear", "phase", "deposit", "finalize"], list(ms)))
+
     def radiation_eval(self, chi, precision="fp32"):
         """{g, chi g', chi^2 g'', h} of the device tables at chi (1-D float64 tensor)."""
         torch = _torch()

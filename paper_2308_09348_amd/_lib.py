@@ -125,7 +125,7 @@ EXPORTS = ["qs_create", "qs_destroy", "qs_forward", "qs_forward_noalloc", "qs_fo
            "qs_backward_tape", "qs_backward_tape_batched", "qs_photons", "qs_photons_batched",
            "qs_photon_cdf", "qs_radiation_eval",
            "qs_radiation_derivs", "qs_sync_status",
-           "qs_set_profiling", "qs_last_timings", "qs_tune", "qs_set_graphs", "qs_strerror",
+           "qs_set_profiling", "qs_last_timings", "qs_timings_sum", "qs_tune", "qs_set_graphs", "qs_strerror",
            "qs_last_error", "qs_abi_version", "qs_build_id"]
 
 _lib = None
@@ -209,6 +209,9 @@ def lib():
         L.qs_set_profiling.restype = ctypes.c_int
         L.qs_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.qs_last_timings.restype = ctypes.c_int
+        L.qs_timings_sum.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.qs_timings_sum.restype = ctypes.c_int
         L.qs_tune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Laser), ctypes.POINTER(Beam),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Numerics),
                               ctypes.POINTER(Bins), ctypes.c_char_p, ctypes.POINTER(Tuning), vp]

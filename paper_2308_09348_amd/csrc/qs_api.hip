@@ -39,6 +39,7 @@ constexpr size_t kMaxGraphs = 8;
 }  // namespace
 
 constexpr int kStageSlots = 4;  // pinned staging blocks of the shot tables
+constexpr int kTimingRing = 64;  // event sets of profiled calls kept for qs_timings_sum
 
 struct qs_ctx {
     int device = -1;
@@ -71,10 +72,14 @@ struct qs_ctx {
     unsigned char *shot_tab = nullptr;
     size_t shot_tab_cap = 0;
     int *eval_flags = nullptr;
-    // kernel timing
+    // kernel timing: a ring of event sets, one set per profiled call, so
+    // that many calls can be enqueued before any of them is read
     bool profiling = false;
     bool profiled_call = false;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[kTimingRing][6] = {};
+    int ev_next = 0;   // the set the next profiled call records into
+    int ev_last = 0;   // the set of the last profiled call
+    int ev_count = 0;  // profiled calls since profiling was switched on
     // launch tuning (qs_tune): choices by launch class, and a forced choice
     // while tuning
     std::vector<TuneEntry> tunes;
@@ -477,8 +482,9 @@ void qs_destroy(qs_ctx *c) {
         if (c->na_stage) (void)hipHostFree(c->na_stage);
         if (c->na_done) (void)hipEventDestroy(c->na_done);
         (void)hipFree(c->eval_flags);
-        for (hipEvent_t &e : c->ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto &set : c->ev)
+            for (hipEvent_t &e : set)
+                if (e) (void)hipEventDestroy(e);
         for (GraphEntry &g : c->graph_cache) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -684,14 +690,37 @@ qs_status qs_set_graphs(qs_ctx *c, int on) {
 qs_status qs_set_profiling(qs_ctx *c, int on) {
     if (!c) return QS_EINVAL;
     DeviceGuard guard(c->device);
-    if (on && !c->ev[0]) {
-        for (hipEvent_t &ev : c->ev) {
-            hipError_t e = hipEventCreate(&ev);
-            if (e != hipSuccess) return hip_fail(c, e, "event create");
-        }
+    if (on && !c->ev[kTimingRing - 1][5]) {
+        for (auto &set : c->ev)
+            for (hipEvent_t &ev : set) {
+                if (ev) continue;
+                hipError_t e = hipEventCreate(&ev);
+                if (e != hipSuccess) return hip_fail(c, e, "event create");
+            }
     }
     c->profiling = on != 0;
     c->profiled_call = false;
+    c->ev_count = 0;
+    return QS_OK;
+}
+
+// a profiled call has been enqueued into the set c->ev[c->ev_next]
+static void advance_timing_ring(qs_ctx *c) {
+    c->ev_last = c->ev_next;
+    c->ev_next = (c->ev_next + 1) % kTimingRing;
+    c->ev_count = std::min(c->ev_count + 1, kTimingRing);
+}
+
+// kernel durations of one event set, after its last event
+static qs_status read_timing_set(qs_ctx *c, int set, double *ms) {
+    hipError_t e = hipEventSynchronize(c->ev[set][5]);
+    if (e != hipSuccess) return hip_fail(c, e, "event synchronize");
+    for (int k = 0; k < 5; ++k) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, c->ev[set][k], c->ev[set][k + 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "event elapsed");
+        ms[k] = t;
+    }
     return QS_OK;
 }
 
@@ -700,14 +729,23 @@ qs_status qs_last_timings(qs_ctx *c, double *ms) {
     if (!c->profiling || !c->profiled_call)
         return set_err(c, "no profiled call"), QS_EINVAL;
     DeviceGuard guard(c->device);
-    hipError_t e = hipEventSynchronize(c->ev[5]);
-    if (e != hipSuccess) return hip_fail(c, e, "event synchronize");
-    for (int k = 0; k < 5; ++k) {
-        float t = 0.0f;
-        e = hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]);
-        if (e != hipSuccess) return hip_fail(c, e, "event elapsed");
-        ms[k] = t;
+    return read_timing_set(c, c->ev_last, ms);
+}
+
+qs_status qs_timings_sum(qs_ctx *c, int32_t *n_calls, double *ms) {
+    if (!c || !n_calls || !ms) return QS_EINVAL;
+    if (!c->profiling || c->ev_count == 0)
+        return set_err(c, "no profiled call"), QS_EINVAL;
+    DeviceGuard guard(c->device);
+    for (int k = 0; k < 5; ++k) ms[k] = 0.0;
+    for (int i = 0; i < c->ev_count; ++i) {
+        const int set = (c->ev_last - i + kTimingRing) % kTimingRing;
+        double one[5];
+        const qs_status st = read_timing_set(c, set, one);
+        if (st != QS_OK) return st;
+        for (int k = 0; k < 5; ++k) ms[k] += one[k];
     }
+    *n_calls = c->ev_count;
     return QS_OK;
 }
 
@@ -1118,7 +1156,9 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
     // tangent), deposit, finalize; with events between them when profiling
     auto enqueue = [&](hipStream_t q, bool marks) -> qs_status {
         hipError_t e;
-        auto mark = [&](int k) { return marks ? hipEventRecord(c->ev[k], q) : hipSuccess; };
+        auto mark = [&](int k) {
+            return marks ? hipEventRecord(c->ev[c->ev_next][k], q) : hipSuccess;
+        };
         if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
         if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau,
                                      env32, env64, q)) != hipSuccess)
@@ -1235,6 +1275,7 @@ qs_status forward_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_b
         return QS_OK;
     }
     if ((st = enqueue(s, prof)) != QS_OK) return st;
+    if (prof) advance_timing_ring(c);
     c->profiled_call = prof;
     c->last_error[0] = 0;
     return QS_OK;
@@ -1643,7 +1684,9 @@ qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_be
     // ---- enqueue ----
     hipError_t e;
     const bool prof = c->profiling;
-    auto mark = [&](int k) { return prof ? hipEventRecord(c->ev[k], s) : hipSuccess; };
+    auto mark = [&](int k) {
+        return prof ? hipEventRecord(c->ev[c->ev_next][k], s) : hipSuccess;
+    };
     if ((st = upload_batch(c, b, s)) != QS_OK) return st;
     if ((e = mark(0)) != hipSuccess) return hip_fail(c, e, "event record");
     if ((e = qs::launch_envelope(b.psi_max, b.h, N->n_steps, L[0].envelope, b.omega_tau, c->env32,
@@ -1666,6 +1709,7 @@ qs_status factor_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_be
     if ((e = qs::launch_node_outputs(bp, s)) != hipSuccess)
         return hip_fail(c, e, "node output kernel");
     if ((e = mark(5)) != hipSuccess) return hip_fail(c, e, "event record");
+    if (prof) advance_timing_ring(c);
     c->profiled_call = prof;
     c->last_error[0] = 0;
     return QS_OK;
@@ -1817,11 +1861,9 @@ qs_status tune_impl(qs_ctx *c, int32_t n_shots, const qs_laser *L, const qs_beam
         for (int r = 0; r <= reps; ++r) {
             qs_status q = forward_impl(c, n_shots, L, B, n_samples, N, H, O.data(), nullptr, s);
             if (q != QS_OK) return q;
-            hipError_t he = hipEventSynchronize(c->ev[5]);
-            float tp = 0.0f, td = 0.0f;
-            if (he == hipSuccess) he = hipEventElapsedTime(&tp, c->ev[2], c->ev[3]);
-            if (he == hipSuccess) he = hipEventElapsedTime(&td, c->ev[3], c->ev[4]);
-            if (he != hipSuccess) return hip_fail(c, he, "tuning events");
+            double t5[5];
+            if ((q = read_timing_set(c, c->ev_last, t5)) != QS_OK) return q;
+            const double tp = t5[2], td = t5[3];
             if (r > 0) {
                 phase_ms = std::min(phase_ms, (double)tp);
                 dep_ms = std::min(dep_ms, (double)td);

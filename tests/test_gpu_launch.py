@@ -172,3 +172,44 @@ def test_graph_replays_follow_the_shadow_stride(qs):
                 _same(got[k], ref[k], f"stride {stride} replay {r} shot {k}")
     eager.close()
     graph.close()
+
+
+def test_profiled_calls_are_kept_for_the_sum(qs):
+    """Kernel events are kept per profiled call (a ring of 64 sets): the sum
+    over calls enqueued back to back equals the per-call durations read one
+    by one, only the last 64 calls are summed, and profiled launches are
+    never graph replays."""
+    ctx = qs.Context(0)
+    p = _case(n_samples=4000, n_steps=64)
+    out = ctx.forward(p)
+    with pytest.raises(qs.QScatterError):
+        ctx.timings_sum()  # profiling off
+    ctx.set_profiling(True)
+    with pytest.raises(qs.QScatterError):
+        ctx.timings_sum()  # no profiled call yet
+    each = []
+    for _ in range(3):
+        ctx.forward(p, out=out, check=False)
+        each.append(ctx.last_timings())
+    n, tot = ctx.timings_sum()
+    assert n == 3
+    for k in tot:
+        assert tot[k] == pytest.approx(sum(t[k] for t in each), rel=1e-12, abs=1e-9)
+    assert tot["phase"] > 0 and tot["deposit"] > 0
+    # back to back, read once: the ring keeps the last 64
+    for _ in range(70):
+        ctx.forward(p, out=out, check=False)
+    n, tot = ctx.timings_sum()
+    assert n == 64 and tot["phase"] > 0
+    last = ctx.last_timings()
+    assert 0 < last["phase"] <= tot["phase"]
+    # switching profiling on again starts a new count
+    ctx.set_profiling(True)
+    ctx.forward(p, out=out, check=False)
+    assert ctx.timings_sum()[0] == 1
+    # profiled launches are not captured into graphs: they stay eager and count
+    ctx.set_graphs(True)
+    ctx.forward(p, out=out, check=False)
+    ctx.forward(p, out=out, check=False)
+    assert ctx.timings_sum()[0] == 3
+    ctx.close()
