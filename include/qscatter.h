@@ -539,8 +539,9 @@ qs_status qs_sync_status(qs_ctx *ctx, const int32_t *status, void *stream);
 
 /* Enable (on != 0) or disable event timing of the kernels that qs_forward
  * enqueues on this context.  Events are recorded on the caller's stream
- * between the launches, so they bracket each kernel.  Errors: QS_EINVAL,
- * QS_EDEVICE. */
+ * between the launches, so they bracket each kernel.  Every call (also one
+ * that leaves profiling on) starts a new count for qs_timings_sum.  Errors:
+ * QS_EINVAL, QS_EDEVICE. */
 qs_status qs_set_profiling(qs_ctx *ctx, int on);
 
 /* Durations in milliseconds of the kernels of the last qs_forward enqueued
