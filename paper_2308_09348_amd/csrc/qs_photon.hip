@@ -263,6 +263,12 @@ struct AngStep {
     }
 };
 
+// LDS row stride of the emission grid: one word more than a row, so that
+// nodes of one column in neighbouring rows fall in different LDS banks (the
+// lanes of a wavefront deposit at similar energies in neighbouring rows)
+constexpr int kPhLdsRow = kPhNV + 1;
+constexpr int kPhLdsNodes = kPhNU * kPhLdsRow;
+
 // Weights in units of 2^-24 (kPhScale): D <= 2/3, so every node weight is
 // below 2^24 and its FP32 product is within half a unit of the exact one
 // before rounding to an integer; the grid words sum them in any order alike.
@@ -285,11 +291,11 @@ __device__ __forceinline__ void ph_deposit(float D, float lm, float t, float la,
     const float du = fu - (float)n, dv = fv - (float)m;
     const float q = D * (float)kPhScale;
     const float qu = q * du, ql = q - qu;  // the two rows' shares
-    unsigned long long *g = grid + n * sp.nv + m;
+    unsigned long long *g = grid + n * kPhLdsRow + m;
     atomicAdd(g, (unsigned long long)(unsigned int)rintf(ql - ql * dv));
     atomicAdd(g + 1, (unsigned long long)(unsigned int)rintf(ql * dv));
-    atomicAdd(g + sp.nv, (unsigned long long)(unsigned int)rintf(qu - qu * dv));
-    atomicAdd(g + sp.nv + 1, (unsigned long long)(unsigned int)rintf(qu * dv));
+    atomicAdd(g + kPhLdsRow, (unsigned long long)(unsigned int)rintf(qu - qu * dv));
+    atomicAdd(g + kPhLdsRow + 1, (unsigned long long)(unsigned int)rintf(qu * dv));
 }
 
 // Radiation functions per stage in the forward table's combinations
@@ -765,8 +771,8 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
     // samples of similar chi, so neighbours often hit the same node; the copy
     // is offset by 32 banks), summed when the grid is flushed
     constexpr int kRep = kWave64 ? 2 : 1;
-    constexpr int kRepStride = kPhNodes + 16;
-    __shared__ unsigned long long grid[(kRep - 1) * kRepStride + kPhNodes];
+    constexpr int kRepStride = kPhLdsNodes + 16;
+    __shared__ unsigned long long grid[(kRep - 1) * kRepStride + kPhLdsNodes];
     unsigned long long *lgrid = grid + (kRep > 1 ? (threadIdx.x & 1) * kRepStride : 0);
     __shared__ float tot[kPhRows];  // Phi(1; chi) / chi on the table rows
     // ... and as a cubic on each FP32 radiation cell
@@ -796,9 +802,9 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
         const int s = __builtin_amdgcn_readfirstlane(find_phot(P.phot, P.n_shots, item));
         const ShotParams &sp = P.shots[s];
         const ShotPhot &pp = P.phot[s];
-        const int nodes = pp.nu * pp.nv;
+        const int nodes = pp.nu * pp.nv, lnodes = pp.nu * kPhLdsRow;
         for (int r = 0; r < kRep; ++r)
-            for (int k = threadIdx.x; k < nodes; k += blockDim.x) grid[r * kRepStride + k] = 0ull;
+            for (int k = threadIdx.x; k < lnodes; k += blockDim.x) grid[r * kRepStride + k] = 0ull;
         __syncthreads();
         PhotAcc acc{0.0, 0.0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double loss = 0.0;
@@ -833,8 +839,9 @@ __global__ __launch_bounds__(phot_block<PREC>()) __attribute__((amdgpu_waves_per
             P.partials[(size_t)item * kPhotPartials + threadIdx.x] = sum;
         }
         for (int k = threadIdx.x; k < nodes; k += blockDim.x) {
-            unsigned long long w = grid[k];
-            for (int r = 1; r < kRep; ++r) w += grid[r * kRepStride + k];
+            const int l = (k / pp.nv) * kPhLdsRow + k % pp.nv;
+            unsigned long long w = grid[l];
+            for (int r = 1; r < kRep; ++r) w += grid[r * kRepStride + l];
             if (w) atomicAdd(&P.pgrid[pp.grid_off + k], w);
         }
         __syncthreads();  // the next item clears the grid
